@@ -1,0 +1,236 @@
+"""FP64 CPU oracle for the compact-kernel MPM step (CK-MPM, arXiv 2412.10399).
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the benchmark's
+CPU-baseline leg may import this package; the product path (the HIP library and
+its Python binding) never touches it, and the two share no code.
+
+Two independent implementations live here:
+  * `ckmpm_oracle.cpp` (loaded through ctypes below): plain FP64 loops following
+    the paper's step order, used at every size;
+  * `bruteforce.py`: a numpy transcription at the level of the definitions
+    (weights of every node of both grids, LAPACK SVD), used on tiny scenes to pin
+    the C++ oracle.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ckmpm_oracle.cpp")
+_LIB = os.path.join(_HERE, "libckmpm_oracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the C++ oracle with g++ (FP64, no fast-math, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["g++", "-std=c++17", "-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+               "-fno-fast-math", "-Wall", "-o", tmp, _SRC]
+        subprocess.check_call(cmd, cwd=_HERE)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class OraConfig(ctypes.Structure):
+    _fields_ = [("n_cells", ctypes.c_int32 * 3), ("dx", ctypes.c_double), ("origin", ctypes.c_double * 3),
+                ("gravity", ctypes.c_double * 3), ("bc_band", ctypes.c_int32), ("transfer", ctypes.c_int32)]
+
+
+class OraMaterial(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int32), ("E", ctypes.c_double), ("nu", ctypes.c_double),
+                ("rho", ctypes.c_double), ("vol0", ctypes.c_double), ("friction_deg", ctypes.c_double)]
+
+
+class OraOutputs(ctypes.Structure):
+    _fields_ = [("grid_m", ctypes.c_void_p), ("grid_p", ctypes.c_void_p), ("grid_v", ctypes.c_void_p),
+                ("diag", ctypes.c_void_p)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.ora_K1.restype = ctypes.c_double
+        L.ora_K1.argtypes = [ctypes.c_double]
+        L.ora_dK1.restype = ctypes.c_double
+        L.ora_dK1.argtypes = [ctypes.c_double]
+        L.ora_d2K1.restype = ctypes.c_double
+        L.ora_d2K1.argtypes = [ctypes.c_double]
+        L.ora_stencil.argtypes = [ctypes.POINTER(OraConfig), dp, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.ora_moment_matrix.argtypes = [ctypes.POINTER(OraConfig), dp, dp]
+        L.ora_svd3.argtypes = [dp, dp, dp, dp]
+        L.ora_kirchhoff.argtypes = [ctypes.POINTER(OraMaterial), ctypes.c_double, dp, dp]
+        L.ora_energy_density.restype = ctypes.c_double
+        L.ora_energy_density.argtypes = [ctypes.POINTER(OraMaterial), ctypes.c_double, dp]
+        L.ora_dp_return_map.argtypes = [ctypes.POINTER(OraMaterial), ctypes.c_double, dp]
+        L.ora_cell_keys.argtypes = [ctypes.POINTER(OraConfig), ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                    ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]
+        L.ora_stable_sort.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
+        L.ora_step.restype = ctypes.c_int
+        L.ora_step.argtypes = [ctypes.POINTER(OraConfig), ctypes.POINTER(OraMaterial), ctypes.c_int32,
+                               ctypes.c_int64, dp, dp, dp, dp, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                               ctypes.POINTER(OraOutputs)]
+        L.ora_num_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _dptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def config(n_cells, dx, origin=(0.0, 0.0, 0.0), gravity=(0.0, 0.0, 0.0), bc_band=0, transfer=0) -> OraConfig:
+    c = OraConfig()
+    for a in range(3):
+        c.n_cells[a] = int(n_cells[a])
+        c.origin[a] = float(origin[a])
+        c.gravity[a] = float(gravity[a])
+    c.dx = float(dx)
+    c.bc_band = int(bc_band)
+    c.transfer = int(transfer)
+    return c
+
+
+def material(model, E, nu, rho, vol0, friction_deg=30.0) -> OraMaterial:
+    m = OraMaterial()
+    m.model, m.E, m.nu, m.rho, m.vol0, m.friction_deg = int(model), E, nu, rho, vol0, friction_deg
+    return m
+
+
+def scene_config(sc, transfer=0) -> OraConfig:
+    return config(sc.n_cells, sc.dx, sc.origin, sc.gravity, sc.bc_band, transfer)
+
+
+def scene_materials(sc):
+    arr = (OraMaterial * len(sc.materials))()
+    for i, m in enumerate(sc.materials):
+        arr[i] = material(m.model, m.E, m.nu, m.rho, m.vol0, m.friction_deg)
+    return arr
+
+
+def K1(x: float) -> float:
+    return lib().ora_K1(float(x))
+
+
+def dK1(x: float) -> float:
+    return lib().ora_dK1(float(x))
+
+
+def d2K1(x: float) -> float:
+    return lib().ora_d2K1(float(x))
+
+
+def stencil(cfg: OraConfig, xp):
+    xp = np.ascontiguousarray(xp, dtype=np.float64)
+    nodes = np.zeros((2, 8, 3), np.int32)
+    w = np.zeros((2, 8), np.float64)
+    d = np.zeros((2, 8, 3), np.float64)
+    lib().ora_stencil(ctypes.byref(cfg), _dptr(xp), nodes.ctypes.data, w.ctypes.data, d.ctypes.data)
+    return nodes, w, d
+
+
+def moment_matrix(cfg: OraConfig, xp) -> np.ndarray:
+    xp = np.ascontiguousarray(xp, dtype=np.float64)
+    D = np.zeros((3, 3), np.float64)
+    lib().ora_moment_matrix(ctypes.byref(cfg), _dptr(xp), _dptr(D))
+    return D
+
+
+def svd3(F):
+    F = np.ascontiguousarray(F, dtype=np.float64)
+    U = np.zeros((3, 3))
+    S = np.zeros(3)
+    V = np.zeros((3, 3))
+    lib().ora_svd3(_dptr(F), _dptr(U), _dptr(S), _dptr(V))
+    return U, S, V
+
+
+def kirchhoff(mat: OraMaterial, F, logE: Optional[float] = None) -> np.ndarray:
+    F = np.ascontiguousarray(F, dtype=np.float64)
+    tau = np.zeros((3, 3))
+    lib().ora_kirchhoff(ctypes.byref(mat), float("nan") if logE is None else float(logE), _dptr(F), _dptr(tau))
+    return tau
+
+
+def energy_density(mat: OraMaterial, F, logE: Optional[float] = None) -> float:
+    F = np.ascontiguousarray(F, dtype=np.float64)
+    return lib().ora_energy_density(ctypes.byref(mat), float("nan") if logE is None else float(logE), _dptr(F))
+
+
+def dp_return_map(mat: OraMaterial, F, logE: Optional[float] = None) -> np.ndarray:
+    F = np.array(F, dtype=np.float64, order="C")
+    lib().ora_dp_return_map(ctypes.byref(mat), float("nan") if logE is None else float(logE), _dptr(F))
+    return F
+
+
+def cell_keys(cfg: OraConfig, x_soa: np.ndarray):
+    """Keys of FP32 positions given as a (3, N) array (one plane per axis)."""
+    x_soa = np.ascontiguousarray(x_soa, dtype=np.float32)
+    n = x_soa.shape[1]
+    keys = np.zeros(n, np.uint32)
+    bad = ctypes.c_int32(0)
+    lib().ora_cell_keys(ctypes.byref(cfg), n, x_soa.ctypes.data, n, keys.ctypes.data, ctypes.byref(bad))
+    return keys, bad.value
+
+
+def stable_sort(keys: np.ndarray) -> np.ndarray:
+    keys = np.ascontiguousarray(keys, dtype=np.uint32)
+    perm = np.zeros(keys.shape[0], np.uint32)
+    lib().ora_stable_sort(keys.shape[0], keys.ctypes.data, perm.ctypes.data)
+    return perm
+
+
+class State:
+    """FP64 particle state (array of structures)."""
+
+    def __init__(self, x, v, B, F, mat=None, logE=None):
+        self.x = np.array(x, dtype=np.float64, order="C").reshape(-1, 3)
+        self.v = np.array(v, dtype=np.float64, order="C").reshape(-1, 3)
+        self.B = np.array(B, dtype=np.float64, order="C").reshape(-1, 3, 3)
+        self.F = np.array(F, dtype=np.float64, order="C").reshape(-1, 3, 3)
+        self.mat = None if mat is None else np.ascontiguousarray(mat, dtype=np.uint8)
+        self.logE = None if logE is None else np.ascontiguousarray(logE, dtype=np.float64)
+
+    @classmethod
+    def from_scene(cls, sc):
+        return cls(sc.x, sc.v, sc.B, sc.F, sc.mat, sc.logE)
+
+    def copy(self):
+        return State(self.x, self.v, self.B, self.F, self.mat, self.logE)
+
+    @property
+    def n(self):
+        return self.x.shape[0]
+
+
+def step(cfg: OraConfig, mats, st: State, dt: float, grids: bool = False):
+    """Advance `st` in place by one step.  Returns (status, diag[32], grids-or-None);
+    grids = dict(m=[2, ny+1, ... ], p=..., v=...) indexed [g][iz][iy][ix](,3)."""
+    n = st.n
+    dims = (cfg.n_cells[2] + 1, cfg.n_cells[1] + 1, cfg.n_cells[0] + 1)
+    out = OraOutputs()
+    diag = np.zeros(32)
+    out.diag = diag.ctypes.data
+    g = None
+    if grids:
+        g = dict(m=np.zeros((2,) + dims), p=np.zeros((2,) + dims + (3,)), v=np.zeros((2,) + dims + (3,)))
+        out.grid_m, out.grid_p, out.grid_v = g["m"].ctypes.data, g["p"].ctypes.data, g["v"].ctypes.data
+    mat_ptr = None if st.mat is None else st.mat.ctypes.data
+    loge_ptr = None if st.logE is None else st.logE.ctypes.data
+    status = lib().ora_step(ctypes.byref(cfg), mats, len(mats), n, _dptr(st.x), _dptr(st.v), _dptr(st.B),
+                            _dptr(st.F), mat_ptr, loge_ptr, float(dt), ctypes.byref(out))
+    return status, diag, g
+
+
+def num_threads() -> int:
+    return lib().ora_num_threads()

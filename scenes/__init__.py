@@ -1,0 +1,178 @@
+"""Seeded synthetic scenes for the compact-kernel MPM step.
+
+This module only *generates inputs*: particle positions, velocities, affine
+matrices, deformation gradients and material tags, plus the plain scene
+parameters (grid size, spacing, time step, material constants).  It holds none
+of the method's arithmetic (no kernel weights, no transfers, no stress), so the
+FP64 oracle and the HIP path can both consume its output without sharing any
+computation.
+
+Sampling follows the paper's workloads: solids seeded at 8 particles per cell
+(section 6.1 uses 8 ppc; section 6.2 samples solids uniformly in 256^3-class
+grids).  The paper's meshes are not available, so every scene is a box (or a
+sphere) filled by stratified jitter: each dx^3 region is split into 2x2x2
+sub-cells and one particle is drawn uniformly inside each sub-cell, with numpy's
+PCG64 generator and a fixed seed.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional
+
+import numpy as np
+
+FIXED_COROTATED = 0
+DRUCKER_PRAGER = 1
+
+
+@dataclasses.dataclass
+class Material:
+    model: int
+    E: float
+    nu: float
+    rho: float
+    vol0: float
+    friction_deg: float = 30.0
+
+
+@dataclasses.dataclass
+class Scene:
+    name: str
+    n_cells: tuple
+    dx: float
+    origin: tuple
+    gravity: tuple
+    bc_band: int
+    dt: float
+    steps: int
+    materials: List[Material]
+    x: np.ndarray            # (N, 3) float32, world positions
+    v: np.ndarray            # (N, 3) float32
+    B: np.ndarray            # (N, 3, 3) float32, APIC affine matrix
+    F: np.ndarray            # (N, 3, 3) float32, deformation gradient
+    mat: np.ndarray          # (N,) uint8 material index
+    logE: Optional[np.ndarray] = None   # (N,) float32, optional per-particle log Young's modulus
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[0])
+
+    def copy(self) -> "Scene":
+        return dataclasses.replace(
+            self, x=self.x.copy(), v=self.v.copy(), B=self.B.copy(), F=self.F.copy(),
+            mat=self.mat.copy(), logE=None if self.logE is None else self.logE.copy())
+
+
+def stratified_box(rng: np.random.Generator, lo, ncell, dx) -> np.ndarray:
+    """Positions filling an axis-aligned box of ncell = (cx, cy, cz) dx-cells whose
+    lower corner is `lo`: 2x2x2 sub-cells per cell, one uniform sample in each.
+    Particle order is x fastest, then y, then z (sub-cells inside each cell)."""
+    cx, cy, cz = (int(c) for c in ncell)
+    iz, iy, ix = np.meshgrid(np.arange(cz), np.arange(cy), np.arange(cx), indexing="ij")
+    cells = np.stack([ix.ravel(), iy.ravel(), iz.ravel()], axis=1).astype(np.float64)
+    sub = np.array([[a, b, c] for c in (0, 1) for b in (0, 1) for a in (0, 1)], dtype=np.float64)
+    pts = (cells[:, None, :] + (sub[None, :, :] + rng.random((cells.shape[0], 8, 3))) * 0.5)
+    want = np.floor(pts.reshape(-1, 3))
+    lo = np.asarray(lo, dtype=np.float64)
+    out = (pts.reshape(-1, 3) * dx + lo).astype(np.float32)
+    # rounding to FP32 may push a sample onto its cell's upper face: step it back inside
+    over = np.floor((out.astype(np.float64) - lo) / dx) > want
+    out[over] = np.nextafter(out[over], np.float32(-np.inf))
+    return out
+
+
+def _rest_state(n: int):
+    v = np.zeros((n, 3), np.float32)
+    B = np.zeros((n, 3, 3), np.float32)
+    F = np.tile(np.eye(3, dtype=np.float32), (n, 1, 1))
+    return v, B, F
+
+
+def cube_elastic(seed: int = 0) -> Scene:
+    """A 16^3-cell elastic cube (32,768 particles) centred at (0.5, 0.6, 0.5) on a
+    32^3 grid over the unit box, falling at 1 m/s: fixed-corotated, rho=1000,
+    E=1e4, nu=0.3, gravity -9.8, sticky walls, dt=1e-4, 100 steps."""
+    dx = 1.0 / 32
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = stratified_box(rng, (0.25, 0.35, 0.25), (16, 16, 16), dx)
+    v, B, F = _rest_state(x.shape[0])
+    v[:, 1] = -1.0
+    mats = [Material(FIXED_COROTATED, 1e4, 0.3, 1000.0, dx ** 3 / 8)]
+    return Scene("cube_elastic_32k", (32, 32, 32), dx, (0.0, 0.0, 0.0), (0.0, -9.8, 0.0), 2,
+                 1e-4, 100, mats, x, v, B, F, np.zeros(x.shape[0], np.uint8))
+
+
+def cube_elastic_perturbed(seed: int = 1, floor_cells: Optional[float] = None) -> Scene:
+    """The elastic cube with seeded perturbations so that stress, the affine
+    term and plasticity-free rotation all take part: v += 0.1 N(0,1),
+    F = I + 0.01 N(0,1).  With `floor_cells` the cube's bottom face is placed at
+    that height (in cells) so its lowest particles reach the sticky wall band."""
+    sc = cube_elastic(0)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = sc.n
+    sc.v = (sc.v + 0.1 * rng.standard_normal((n, 3))).astype(np.float32)
+    sc.F = (np.eye(3)[None] + 0.01 * rng.standard_normal((n, 3, 3))).astype(np.float32)
+    sc.name = "cube_elastic_perturbed"
+    if floor_cells is not None:
+        shift = floor_cells * sc.dx - 0.35
+        sc.x = (sc.x.astype(np.float64) + np.array([0.0, shift, 0.0])).astype(np.float32)
+        sc.name = "cube_elastic_perturbed_floor"
+    return sc
+
+
+def sand_column(seed: int = 2, scale: int = 1) -> Scene:
+    """Drucker-Prager sand column resting on the sticky floor of a 256^3 grid
+    (dx = 1/256): cells [96,160) x [2,130) x [96,160), 8 ppc, 4,194,304 particles,
+    friction angle 30 deg, E=3.5e5, nu=0.3, rho=1600, dt=2e-5.
+
+    `scale` > 1 shrinks the column footprint by that factor per axis (same grid,
+    same material) to give CPU-sized versions of the same workload."""
+    n = 256
+    dx = 1.0 / n
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ext = (64 // scale, 128 // scale, 64 // scale)
+    lo_cells = (128 - ext[0] // 2, 2, 128 - ext[2] // 2)
+    x = stratified_box(rng, tuple(c * dx for c in lo_cells), ext, dx)
+    v, B, F = _rest_state(x.shape[0])
+    mats = [Material(DRUCKER_PRAGER, 3.5e5, 0.3, 1600.0, dx ** 3 / 8, 30.0)]
+    return Scene("sand_column_%d" % x.shape[0], (n, n, n), dx, (0.0, 0.0, 0.0), (0.0, -9.8, 0.0), 2,
+                 2e-5, 500, mats, x, v, B, F, np.zeros(x.shape[0], np.uint8))
+
+
+def random_blob(seed: int, n_cells=(8, 8, 8), lo_cells=(2.5, 2.5, 2.5), ext_cells=(3, 3, 3),
+                model: int = FIXED_COROTATED, v_scale=0.5, B_scale=2.0, F_scale=0.05,
+                gravity=(0.0, 0.0, 0.0), bc_band: int = 0, dt: float = 1e-3,
+                E: float = 1e4, nu: float = 0.3, rho: float = 1000.0,
+                dx: Optional[float] = None, ppc_sub: int = 2) -> Scene:
+    """Small random scene for transfer identities and brute-force checks:
+    stratified particles in a box of `ext_cells` cells starting at `lo_cells`,
+    random v, B and F = I + F_scale N(0,1).  dx defaults to 1/n_cells[0]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    dx = (1.0 / n_cells[0]) if dx is None else dx
+    x = stratified_box(rng, tuple(c * dx for c in lo_cells), ext_cells, dx)
+    n = x.shape[0]
+    v = (v_scale * rng.standard_normal((n, 3))).astype(np.float32)
+    B = (B_scale * dx * rng.standard_normal((n, 3, 3))).astype(np.float32)
+    F = (np.eye(3)[None] + F_scale * rng.standard_normal((n, 3, 3))).astype(np.float32)
+    mats = [Material(model, E, nu, rho, dx ** 3 / 8, 30.0)]
+    return Scene("random_blob_s%d" % seed, tuple(n_cells), dx, (0.0, 0.0, 0.0), tuple(gravity), bc_band,
+                 dt, 1, mats, x, v, B, F, np.zeros(n, np.uint8))
+
+
+def sphere(rng: np.random.Generator, centre, radius, dx) -> np.ndarray:
+    """Stratified samples of a ball: the stratified lattice of its bounding box,
+    kept where the sample lies inside the ball."""
+    ncell = int(math.ceil(2 * radius / dx)) + 1
+    lo = np.asarray(centre, np.float64) - ncell * dx / 2
+    pts = stratified_box(rng, lo, (ncell, ncell, ncell), dx).astype(np.float64)
+    keep = np.sum((pts - np.asarray(centre)) ** 2, axis=1) < radius * radius
+    return pts[keep].astype(np.float32)
+
+
+PRESETS = {
+    "cube_elastic": cube_elastic,
+    "cube_elastic_perturbed": lambda: cube_elastic_perturbed(1),
+    "cube_elastic_floor": lambda: cube_elastic_perturbed(1, floor_cells=2.5),
+    "sand_column": sand_column,
+}
