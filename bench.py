@@ -1,0 +1,173 @@
+#!/usr/bin/env python3
+"""Throughput of the compact-kernel MPM step on one MI355X.
+
+Workload: the 4,194,304-particle Drucker-Prager sand column on a 256^3 grid
+(dx = 1/256, dt = 2e-5; synthetic stratified sampling, see scenes/), the
+configuration the particle-steps/s metric is quoted on.  W warm-up steps (the
+first steps of the trajectory, also the parity window), then K timed steps with
+every kernel of the step included (keys, block activation, sort, P2G, grid
+update, G2P).  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line with the metric, the roofline of the dominant kernel
+(algorithmic bytes per launch over its mean duration, timed with HIP events on
+the launch stream) and the FP64 CPU checker timed on a bounded sample of the same
+workload on this host.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PARTICLE_BYTES = {"p2g": 96, "g2p": 144}            # algorithmic particle bytes per kernel
+GRID_BLOCK_BYTES = {"p2g": 2048, "g2p": 1536, "grid_update": 3584}
+STEP_PARTICLE_BYTES = 240
+STEP_GRID_BLOCK_BYTES = 9 * 1024
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sand_column_4M.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2412_10399_amd", "csrc", f) for f in ("ck_transfer.hip", "ck_common.hpp")]
+KERNEL_SYMBOL = {"p2g": "k_p2g", "g2p": "k_g2p", "grid_update": "k_grid_update"}
+
+
+def source_digest():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, n_launch_units):
+    """HBM bytes per launch from committed rocprofv3 counter runs, scaled by the
+    copy-kernel calibration; None when the kernel sources changed since."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_digest") != source_digest() or kernel not in t.get("kernels", {}):
+        return None
+    k = t["kernels"][kernel]
+    return (k["fetch_kib"] * t["fetch_scale"] + k["write_kib"] * t["write_scale"]) * 1024.0
+
+
+def cpu_baseline(sc, max_seconds=30.0):
+    import oracle
+    st = oracle.State.from_scene(sc)
+    cfg, mats = oracle.scene_config(sc), oracle.scene_materials(sc)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        status, _, _ = oracle.step(cfg, mats, st, sc.dt)
+        if status != 0:
+            break
+        steps += 1
+        if time.perf_counter() - t0 > max_seconds / 2 or steps >= 10:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": sc.n * steps / dt, "unit": "particle-steps/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "%d step(s) of the same %d-particle sand column from its initial state, FP64, %.1f s" %
+                      (steps, sc.n, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=490)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (calibrates HBM counters under rocprofv3)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs the step on a single MI355X; "
+              "multi-GPU sharding is a design note only (--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import scenes
+    from paper_2412_10399_amd import ckmpm
+
+    torch.cuda.set_device(0)
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    sc = scenes.sand_column()
+    ctx = ckmpm.Context(ckmpm.scene_config(sc), ckmpm.scene_materials(sc))
+    parts = ckmpm.particles_from_scene(sc, "cuda:0")
+    stream = torch.cuda.current_stream()
+    h = ctx.h
+
+    ckmpm.check(ckmpm.mpm_step(h, parts.c, sc.dt, args.warmup, stream), "warmup")
+    ckmpm.check(ckmpm.mpm_sync(h, stream), "warmup status")
+
+    ckmpm.check(ckmpm.mpm_profile_enable(h, True))
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    ckmpm.check(ckmpm.mpm_step(h, parts.c, sc.dt, args.steps, stream), "timed steps")
+    stop.record(stream)
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(stop)
+    status = ckmpm.mpm_sync(h, stream)
+    ckmpm.check(status, "timed status")
+    s, phase_ms, phase_n = ckmpm.mpm_profile_read(h)
+    ckmpm.check(s)
+    s, stats = ckmpm.mpm_get_stats(h, stream)
+    ckmpm.check(s)
+
+    ms_per_step = total_ms / max(args.steps, 1)
+    value = sc.n * args.steps / (total_ms / 1e3)
+    avg = {name: (phase_ms[i] / phase_n[i] if phase_n[i] else 0.0) for i, name in enumerate(ckmpm.PHASES)}
+    ngb = int(stats.n_grid_blocks)
+    dominant = max(("p2g", "g2p", "grid_update"), key=lambda k: avg[k])
+    alg_bytes = PARTICLE_BYTES.get(dominant, 0) * sc.n + GRID_BLOCK_BYTES[dominant] * ngb
+    achieved = alg_bytes / (avg[dominant] * 1e-3) / 1e9
+    traffic = measured_traffic(dominant, sc.n)
+    step_bytes = STEP_PARTICLE_BYTES * sc.n + STEP_GRID_BLOCK_BYTES * ngb
+    result = {
+        "metric": "particle-steps/s at 4M particles",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "sand_column_drucker_prager", "particles": sc.n, "grid": "256^3", "dx": sc.dx,
+                   "dt": sc.dt, "ppc": 8, "active_grid_blocks": ngb,
+                   "particle_blocks": int(stats.n_particle_blocks)},
+        "roofline": {"bound": "hbm", "kernel": KERNEL_SYMBOL[dominant], "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "alg_bytes_per_launch": alg_bytes,
+                     "mean_launch_ms": avg[dominant]},
+        "step_roofline": {"alg_bytes_per_step": step_bytes,
+                          "achieved_GBs": step_bytes / (ms_per_step * 1e-3) / 1e9,
+                          "frac": step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "phases_ms": avg,
+    }
+    ctx.close()
+    del parts
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(scenes.sand_column())
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

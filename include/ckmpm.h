@@ -1,0 +1,166 @@
+/*
+ * ckmpm.h - C ABI of the MI355X compact-kernel MPM step.
+ *
+ * One explicit MLS-MPM / APIC time step of CK-MPM (Liu, Wang, Li: "CK-MPM: A
+ * Compact-Kernel Material Point Method", arXiv 2412.10399):
+ *   - the C^2 compact kernel K1(x) = 1 - |x| + sin(2 pi |x|)/(2 pi) of section 4.1,
+ *     applied as a tensor product on two staggered grids G- and G+ placed a quarter
+ *     cell either side of the (unstored) grid G0 (section 4.2);
+ *   - particle-to-grid transfer of mass and APIC affine momentum with the MLS stress
+ *     force (sections 4.3-4.5): each particle touches the 2x2x2 nodes of its cell on
+ *     each grid, 16 nodes in all;
+ *   - grid velocity update with gravity and sticky walls (section 3.2, section 4.3);
+ *   - grid-to-particle gather of velocity and the affine matrix B, update of the
+ *     deformation gradient, plasticity return mapping and advection (section 3.2,
+ *     sections 4.3-4.5).
+ *
+ * Every entry point is plain C: integers, doubles and pointers.  Particle arrays
+ * and stream handles belong to the caller; device memory for the sparse grid, the
+ * page table, sort scratch and the status word belongs to the library and is
+ * allocated once in mpm_create.  Steps never allocate.  No entry point aborts or
+ * prints; failures are reported through mpm_status.
+ *
+ * Conventions
+ *   - world position of node i (integer triple, 0..n_cells per axis) of grid G_k,
+ *     k = -1 (G-) or +1 (G+):   origin + (i + k/4) * dx;
+ *   - a particle is valid while (x - origin)/dx lies in [1/4, n_cells - 1/4) on every
+ *     axis (all 16 nodes of its stencil then exist);
+ *   - particle state is structure-of-arrays FP32: one allocation of 24 planes of
+ *     `stride` floats each, plane order x0 x1 x2 | v0 v1 v2 | B00 B01 B02 B10 .. B22 |
+ *     H00 H01 .. H22 (matrices row-major), element p of plane q at base[q*stride + p].
+ *     The deformation gradient is stored as H = F - I: an FP32 F near the identity
+ *     resolves strains only to about 6e-8, H keeps them to FP32 relative precision;
+ *   - streams are hipStream_t values passed as void* (NULL = the null stream).
+ */
+#ifndef CKMPM_H
+#define CKMPM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CKMPM_ABI_VERSION 1
+#define MPM_STATE_PLANES 24
+
+typedef struct mpm_ctx mpm_ctx; /* opaque, owned by the library */
+
+typedef enum {
+    MPM_OK = 0,
+    MPM_E_INVALID = 1,   /* bad argument or configuration (detected on the host)          */
+    MPM_E_OOM = 2,       /* device allocation failed in mpm_create                          */
+    MPM_E_DOMAIN = 3,    /* a particle left the valid domain (device-detected)               */
+    MPM_E_CAPACITY = 4,  /* block pool or per-block particle capacity exceeded (device)      */
+    MPM_E_NONFINITE = 5, /* a NaN/Inf appeared in v, B or F (device-detected)                */
+    MPM_E_HIP = 6,       /* a HIP runtime call failed                                        */
+    MPM_E_STALE = 7      /* positions changed after the library computed their cell keys      */
+} mpm_status;
+
+enum { MPM_FIXED_COROTATED = 0, MPM_DRUCKER_PRAGER = 1 };
+enum { MPM_BC_NONE = 0, MPM_BC_STICKY = 1 };
+enum { MPM_TRANSFER_MLS = 0 };
+
+typedef struct {
+    int32_t n_cells[3];    /* cells per axis; nodes per axis and grid = n_cells + 1                */
+    double dx;             /* cell size; must be a power of two (exact cell keys)                   */
+    double origin[3];      /* world position of G0 node (0,0,0)                                     */
+    double gravity[3];     /* acceleration added in the grid update                                 */
+    int32_t bc;            /* MPM_BC_NONE or MPM_BC_STICKY                                          */
+    int32_t bc_band;       /* sticky: zero v~ at nodes closer than bc_band cells to a box face      */
+    int64_t max_particles; /* capacity of every per-particle scratch array                          */
+    int64_t max_blocks;    /* capacity of the grid block pool (blocks of 4x4x4 nodes, both grids)   */
+    int32_t transfer;      /* MPM_TRANSFER_MLS                                                      */
+    int32_t flags;         /* reserved, must be 0                                                   */
+} mpm_config;
+
+typedef struct {
+    int32_t model;         /* MPM_FIXED_COROTATED or MPM_DRUCKER_PRAGER                             */
+    float E, nu, rho;      /* Young's modulus, Poisson ratio (0 <= nu < 0.5), density               */
+    float vol0;            /* initial particle volume V_p^0 (particle mass = rho * vol0)             */
+    float friction_deg;    /* Drucker-Prager friction angle in degrees                              */
+} mpm_material;
+
+typedef struct {
+    int64_t n;             /* live particles                                                         */
+    int64_t stride;        /* elements per state plane, n <= stride                                  */
+    float *state[2];       /* ping-pong buffers (device), 24 planes each, see above                  */
+    uint32_t *id[2];       /* optional particle ids (device), permuted with the state; may be NULL   */
+    uint8_t *mat[2];       /* optional material index per particle (device), permuted with the state;
+                              NULL means material 0 for every particle                               */
+    int32_t current;       /* 0 or 1: buffer holding the current state; the library flips it in
+                              mpm_g2p and mpm_step, at enqueue time                                   */
+    int32_t reserved;
+} mpm_particles;
+
+typedef struct {
+    int64_t n_particle_blocks; /* 4x4x4-cell blocks holding particles in the last p2g              */
+    int64_t n_grid_blocks;     /* grid blocks touched (both grids) in the last p2g                 */
+    int64_t max_block_particles;
+    uint32_t status_bits;      /* raw device status word (not cleared)                             */
+    uint32_t reserved;
+} mpm_stats;
+
+/* Create a context.  Validates the configuration on the host (n_cells >= 4, dx a power
+ * of two, capacities > 0, 0 < n_mat <= 8, materials with E > 0, 0 <= nu < 0.5, rho > 0,
+ * vol0 > 0) and returns MPM_E_INVALID before touching the GPU if any check fails.
+ * Allocates every device buffer on the current HIP device; MPM_E_OOM if that fails. */
+mpm_status mpm_create(const mpm_config *cfg, const mpm_material *mats, int32_t n_mat, mpm_ctx **out);
+
+/* Free every buffer of the context (synchronises the device first).  NULL is accepted. */
+mpm_status mpm_destroy(mpm_ctx *ctx);
+
+/* Sort + activation + P2G (sections 4.3-4.5): computes the particles' cell keys (unless
+ * the previous mpm_g2p produced them for this buffer), sorts particles stably by
+ * (4^3-cell block, cell), activates the grid blocks the 16-node stencils touch, clears
+ * them and scatters mass and momentum m v + (m B - dt V0 tau) D^-1 (x_i - x_p) to both
+ * grids.  Reads the current buffer only.  Enqueued on `stream`; asynchronous. */
+mpm_status mpm_p2g(mpm_ctx *ctx, const mpm_particles *p, double dt, void *stream);
+
+/* Grid update (section 4.3): v~ = p/m + dt g on nodes with m > 0, zero elsewhere and
+ * on sticky wall nodes.  Overwrites the momentum channels of the pool with v~. */
+mpm_status mpm_grid_update(mpm_ctx *ctx, double dt, void *stream);
+
+/* G2P (sections 4.3-4.5): v_p = 1/2 sum w v~, B_p = 1/2 sum w v~ (x_i - x_p)^T,
+ * F <- (I + dt B_p D_p^-1) F (applied to H = F - I), Drucker-Prager return mapping,
+ * x <- x + dt v_p.  Writes
+ * the new state into the other buffer in sorted order (ids and materials permuted
+ * alongside), computes the next cell keys, and flips p->current. */
+mpm_status mpm_g2p(mpm_ctx *ctx, mpm_particles *p, double dt, void *stream);
+
+/* nsteps x (p2g, grid_update, g2p), enqueued back to back without host syncs. */
+mpm_status mpm_step(mpm_ctx *ctx, mpm_particles *p, double dt, int32_t nsteps, void *stream);
+
+/* Wait for `stream`, then return (and clear) the device status word as a status code:
+ * NONFINITE before DOMAIN before CAPACITY before STALE. */
+mpm_status mpm_sync(mpm_ctx *ctx, void *stream);
+
+/* Export the grid as dense arrays (device pointers): m[2][nz+1][ny+1][nx+1] and
+ * vec[2][nz+1][ny+1][nx+1][3], grid 0 = G-, 1 = G+.  After mpm_p2g vec holds momentum,
+ * after mpm_grid_update it holds v~.  Nodes outside active blocks are written as 0.
+ * Either pointer may be NULL.  For tests and diagnostics. */
+mpm_status mpm_grid_read(mpm_ctx *ctx, float *m, float *vec, void *stream);
+
+/* Cell keys of the current buffer (computed from positions) and the stable sorting
+ * permutation: keys[p] = block * 64 + cell as defined in mpm_p2g, perm[j] = index of the
+ * j-th particle in key order (ties in index order).  Device output arrays of n. */
+mpm_status mpm_sort_keys(mpm_ctx *ctx, const mpm_particles *p, uint32_t *keys, uint32_t *perm, void *stream);
+
+/* Forget cached cell keys: call after changing particle positions in place. */
+mpm_status mpm_invalidate(mpm_ctx *ctx);
+
+/* Synchronous statistics of the last p2g (blocks, largest block). */
+mpm_status mpm_get_stats(mpm_ctx *ctx, mpm_stats *out, void *stream);
+
+/* Per-phase timing with HIP events on the launch stream: enable, read totals (ms) and
+ * launch counts of the phases {sort+activate, p2g, grid update, g2p} since enabling. */
+mpm_status mpm_profile_enable(mpm_ctx *ctx, int32_t enable);
+mpm_status mpm_profile_read(mpm_ctx *ctx, double *total_ms, int64_t *count, int32_t n_phases);
+
+const char *mpm_status_string(mpm_status s);
+int32_t mpm_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CKMPM_H */

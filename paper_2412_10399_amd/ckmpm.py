@@ -1,0 +1,312 @@
+"""Thin ctypes binding of libckmpm.so (the C ABI declared in include/ckmpm.h).
+
+Functions carry the C names and only marshal arguments: every step of the MPM
+path runs in the HIP library.  PyTorch tensors provide device memory
+(`data_ptr()`) and streams (`torch.cuda.Stream.cuda_stream`).  If the library is
+not built this module raises on first use; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libckmpm.so")
+_lib = None
+
+MPM_OK, MPM_E_INVALID, MPM_E_OOM, MPM_E_DOMAIN, MPM_E_CAPACITY, MPM_E_NONFINITE, MPM_E_HIP, MPM_E_STALE = range(8)
+MPM_FIXED_COROTATED, MPM_DRUCKER_PRAGER = 0, 1
+MPM_BC_NONE, MPM_BC_STICKY = 0, 1
+MPM_TRANSFER_MLS = 0
+MPM_STATE_PLANES = 24
+PHASES = ("sort", "p2g", "grid_update", "g2p")
+
+# plane offsets inside one state buffer
+X0, V0, B0, F0 = 0, 3, 6, 15
+
+
+class CkMpmError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        super().__init__("%s: %s (%d)" % (what, status_string(status), status))
+        self.status = status
+
+
+class mpm_config(ctypes.Structure):
+    _fields_ = [("n_cells", ctypes.c_int32 * 3), ("dx", ctypes.c_double), ("origin", ctypes.c_double * 3),
+                ("gravity", ctypes.c_double * 3), ("bc", ctypes.c_int32), ("bc_band", ctypes.c_int32),
+                ("max_particles", ctypes.c_int64), ("max_blocks", ctypes.c_int64), ("transfer", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
+
+
+class mpm_material(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int32), ("E", ctypes.c_float), ("nu", ctypes.c_float), ("rho", ctypes.c_float),
+                ("vol0", ctypes.c_float), ("friction_deg", ctypes.c_float)]
+
+
+class mpm_particles(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("stride", ctypes.c_int64), ("state", ctypes.c_void_p * 2),
+                ("id", ctypes.c_void_p * 2), ("mat", ctypes.c_void_p * 2), ("current", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class mpm_stats(ctypes.Structure):
+    _fields_ = [("n_particle_blocks", ctypes.c_int64), ("n_grid_blocks", ctypes.c_int64),
+                ("max_block_particles", ctypes.c_int64), ("status_bits", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+EXPORTS = ("mpm_create", "mpm_destroy", "mpm_p2g", "mpm_grid_update", "mpm_g2p", "mpm_step", "mpm_sync",
+           "mpm_grid_read", "mpm_sort_keys", "mpm_invalidate", "mpm_get_stats", "mpm_profile_enable",
+           "mpm_profile_read", "mpm_status_string", "mpm_abi_version")
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError("libckmpm.so is not built (expected at %s); run __graft_entry__.build()" % _LIB_PATH)
+        L = ctypes.CDLL(_LIB_PATH)
+        vp, st = ctypes.c_void_p, ctypes.c_int
+        L.mpm_create.argtypes = [ctypes.POINTER(mpm_config), ctypes.POINTER(mpm_material), ctypes.c_int32,
+                                 ctypes.POINTER(vp)]
+        L.mpm_destroy.argtypes = [vp]
+        L.mpm_p2g.argtypes = [vp, ctypes.POINTER(mpm_particles), ctypes.c_double, vp]
+        L.mpm_grid_update.argtypes = [vp, ctypes.c_double, vp]
+        L.mpm_g2p.argtypes = [vp, ctypes.POINTER(mpm_particles), ctypes.c_double, vp]
+        L.mpm_step.argtypes = [vp, ctypes.POINTER(mpm_particles), ctypes.c_double, ctypes.c_int32, vp]
+        L.mpm_sync.argtypes = [vp, vp]
+        L.mpm_grid_read.argtypes = [vp, vp, vp, vp]
+        L.mpm_sort_keys.argtypes = [vp, ctypes.POINTER(mpm_particles), vp, vp, vp]
+        L.mpm_invalidate.argtypes = [vp]
+        L.mpm_get_stats.argtypes = [vp, ctypes.POINTER(mpm_stats), vp]
+        L.mpm_profile_enable.argtypes = [vp, ctypes.c_int32]
+        L.mpm_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.c_int32]
+        L.mpm_status_string.argtypes = [st]
+        L.mpm_status_string.restype = ctypes.c_char_p
+        L.mpm_abi_version.restype = ctypes.c_int32
+        for name in EXPORTS:
+            if name not in ("mpm_status_string", "mpm_abi_version"):
+                getattr(L, name).restype = st
+        _lib = L
+    return _lib
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+# ----------------------------------------------------------------- C ABI mirror
+def mpm_create(cfg: mpm_config, mats: Sequence[mpm_material]):
+    arr = (mpm_material * len(mats))(*mats)
+    h = ctypes.c_void_p()
+    s = lib().mpm_create(ctypes.byref(cfg), arr, len(mats), ctypes.byref(h))
+    return s, h
+
+
+def mpm_destroy(ctx) -> int:
+    return lib().mpm_destroy(ctx)
+
+
+def mpm_p2g(ctx, parts: mpm_particles, dt: float, stream=None) -> int:
+    return lib().mpm_p2g(ctx, ctypes.byref(parts), float(dt), _stream(stream))
+
+
+def mpm_grid_update(ctx, dt: float, stream=None) -> int:
+    return lib().mpm_grid_update(ctx, float(dt), _stream(stream))
+
+
+def mpm_g2p(ctx, parts: mpm_particles, dt: float, stream=None) -> int:
+    return lib().mpm_g2p(ctx, ctypes.byref(parts), float(dt), _stream(stream))
+
+
+def mpm_step(ctx, parts: mpm_particles, dt: float, nsteps: int, stream=None) -> int:
+    return lib().mpm_step(ctx, ctypes.byref(parts), float(dt), int(nsteps), _stream(stream))
+
+
+def mpm_sync(ctx, stream=None) -> int:
+    return lib().mpm_sync(ctx, _stream(stream))
+
+
+def mpm_grid_read(ctx, m_ptr: Optional[int], vec_ptr: Optional[int], stream=None) -> int:
+    return lib().mpm_grid_read(ctx, m_ptr, vec_ptr, _stream(stream))
+
+
+def mpm_sort_keys(ctx, parts: mpm_particles, keys_ptr: Optional[int], perm_ptr: Optional[int], stream=None) -> int:
+    return lib().mpm_sort_keys(ctx, ctypes.byref(parts), keys_ptr, perm_ptr, _stream(stream))
+
+
+def mpm_invalidate(ctx) -> int:
+    return lib().mpm_invalidate(ctx)
+
+
+def mpm_get_stats(ctx, stream=None):
+    out = mpm_stats()
+    s = lib().mpm_get_stats(ctx, ctypes.byref(out), _stream(stream))
+    return s, out
+
+
+def mpm_profile_enable(ctx, enable: bool) -> int:
+    return lib().mpm_profile_enable(ctx, 1 if enable else 0)
+
+
+def mpm_profile_read(ctx, n_phases: int = 4):
+    ms = (ctypes.c_double * n_phases)()
+    cnt = (ctypes.c_int64 * n_phases)()
+    s = lib().mpm_profile_read(ctx, ms, cnt, n_phases)
+    return s, list(ms), list(cnt)
+
+
+def mpm_status_string(status: int) -> str:
+    return lib().mpm_status_string(int(status)).decode()
+
+
+def mpm_abi_version() -> int:
+    return lib().mpm_abi_version()
+
+
+def status_string(status: int) -> str:
+    try:
+        return mpm_status_string(status)
+    except Exception:  # library missing: still format the error
+        return "status"
+
+
+def check(status: int, what: str = "ckmpm") -> None:
+    if status != MPM_OK:
+        raise CkMpmError(status, what)
+
+
+# --------------------------------------------------------- struct construction
+def make_config(n_cells, dx, origin=(0.0, 0.0, 0.0), gravity=(0.0, 0.0, 0.0), bc_band=0, max_particles=1,
+                max_blocks=1024, bc=None) -> mpm_config:
+    c = mpm_config()
+    for a in range(3):
+        c.n_cells[a] = int(n_cells[a])
+        c.origin[a] = float(origin[a])
+        c.gravity[a] = float(gravity[a])
+    c.dx = float(dx)
+    c.bc = (MPM_BC_STICKY if bc_band > 0 else MPM_BC_NONE) if bc is None else int(bc)
+    c.bc_band = int(bc_band)
+    c.max_particles = int(max_particles)
+    c.max_blocks = int(max_blocks)
+    c.transfer = MPM_TRANSFER_MLS
+    c.flags = 0
+    return c
+
+
+def make_material(model, E, nu, rho, vol0, friction_deg=30.0) -> mpm_material:
+    m = mpm_material()
+    m.model, m.E, m.nu, m.rho, m.vol0, m.friction_deg = int(model), E, nu, rho, vol0, friction_deg
+    return m
+
+
+class Particles:
+    """Device particle storage: two ping-pong buffers of 24 FP32 planes, ids and
+    optional material indices, as torch tensors on a GPU."""
+
+    def __init__(self, n: int, stride: Optional[int] = None, device="cuda", with_mat: bool = False):
+        import torch
+        self.n = int(n)
+        self.stride = int(stride if stride is not None else max(n, 1))
+        self.state = torch.zeros((2, MPM_STATE_PLANES, self.stride), dtype=torch.float32, device=device)
+        self.ids = torch.zeros((2, self.stride), dtype=torch.int32, device=device)
+        self.mats = torch.zeros((2, self.stride), dtype=torch.uint8, device=device) if with_mat else None
+        self.c = mpm_particles()
+        self.c.n = self.n
+        self.c.stride = self.stride
+        for b in range(2):
+            self.c.state[b] = self.state[b].data_ptr()
+            self.c.id[b] = self.ids[b].data_ptr()
+            self.c.mat[b] = self.mats[b].data_ptr() if with_mat else None
+        self.c.current = 0
+
+    @property
+    def current(self) -> int:
+        return int(self.c.current)
+
+    def load(self, x, v, B, F, ids=None, mat=None):
+        """Host arrays (N,3), (N,3), (N,3,3), (N,3,3) into the current buffer.  The
+        deformation gradient is stored as H = F - I (formed in FP64, then rounded)."""
+        import numpy as np
+        import torch
+        n = self.n
+        planes = np.zeros((MPM_STATE_PLANES, n), np.float32)
+        planes[X0:X0 + 3] = np.asarray(x, np.float32).reshape(n, 3).T
+        planes[V0:V0 + 3] = np.asarray(v, np.float32).reshape(n, 3).T
+        planes[B0:B0 + 9] = np.asarray(B, np.float32).reshape(n, 9).T
+        H = np.asarray(F, np.float64).reshape(n, 3, 3) - np.eye(3)[None]
+        planes[F0:F0 + 9] = H.reshape(n, 9).T.astype(np.float32)
+        cur = self.current
+        self.state[cur, :, :n].copy_(torch.from_numpy(planes))
+        idv = np.arange(n, dtype=np.int32) if ids is None else np.asarray(ids, np.int32)
+        self.ids[cur, :n].copy_(torch.from_numpy(idv))
+        if self.mats is not None:
+            mv = np.zeros(n, np.uint8) if mat is None else np.asarray(mat, np.uint8)
+            self.mats[cur, :n].copy_(torch.from_numpy(mv))
+
+    def read(self):
+        """Current buffer to host in storage (sorted) order: dict(x, v, B, H, F, id[, mat]);
+        H = F - I as stored (FP32), F = I + H formed in FP64."""
+        import numpy as np
+        cur = self.current
+        n = self.n
+        pl = self.state[cur, :, :n].cpu().numpy()
+        H = pl[F0:F0 + 9].T.reshape(n, 3, 3).copy()
+        out = dict(x=pl[X0:X0 + 3].T.copy(), v=pl[V0:V0 + 3].T.copy(), B=pl[B0:B0 + 9].T.reshape(n, 3, 3).copy(),
+                   H=H, F=H.astype(np.float64) + np.eye(3)[None], id=self.ids[cur, :n].cpu().numpy().copy())
+        if self.mats is not None:
+            out["mat"] = self.mats[cur, :n].cpu().numpy().copy()
+        return out
+
+    def read_by_id(self):
+        """Current state reordered so that row k holds particle id k."""
+        d = self.read()
+        order = d["id"].argsort(kind="stable")
+        return {k: v[order] for k, v in d.items()}
+
+
+class Context:
+    """RAII holder for an mpm_ctx handle."""
+
+    def __init__(self, cfg: mpm_config, mats: Sequence[mpm_material]):
+        s, h = mpm_create(cfg, mats)
+        check(s, "mpm_create")
+        self.h = h
+        self.cfg = cfg
+
+    def close(self):
+        if self.h is not None and self.h.value:
+            mpm_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def scene_config(sc, max_particles=None, max_blocks=None) -> mpm_config:
+    """mpm_config for a scene from the `scenes` package."""
+    n = sc.n if max_particles is None else max_particles
+    if max_blocks is None:
+        nb = 1
+        for a in range(3):
+            nb *= sc.n_cells[a] // 4 + 1
+        max_blocks = min(nb, max(1024, 4 * (n // 64 + 1) + 4096))
+    return make_config(sc.n_cells, sc.dx, sc.origin, sc.gravity, sc.bc_band, max(n, 1), max_blocks)
+
+
+def scene_materials(sc):
+    return [make_material(m.model, m.E, m.nu, m.rho, m.vol0, m.friction_deg) for m in sc.materials]
+
+
+def particles_from_scene(sc, device="cuda") -> Particles:
+    p = Particles(sc.n, device=device, with_mat=len(sc.materials) > 1)
+    p.load(sc.x, sc.v, sc.B, sc.F, mat=sc.mat)
+    return p

@@ -1,0 +1,436 @@
+// C ABI of the compact-kernel MPM library (declared in include/ckmpm.h): context
+// creation and validation, launch sequencing of the step's kernels, status
+// reporting and per-phase event timing.  No allocation happens after mpm_create.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/ckmpm.h"
+#include "ck_common.hpp"
+
+using namespace ck;
+
+namespace {
+
+constexpr int kPhases = 4;          // sort+activate, p2g, grid update, g2p
+constexpr int kEventRing = 512;     // steps recorded before the ring is folded into the totals
+
+}  // namespace
+
+struct mpm_ctx {
+    mpm_config cfg;
+    std::vector<mpm_material> mats;
+    DevCtx d;
+    int device = 0;
+    const float *next_ready = nullptr;   // buffer whose keys and next-epoch stamps are in place
+    long long next_n = -1;
+    const float *p2g_done = nullptr;     // buffer the last p2g ran on
+    unsigned int *host_counters = nullptr;
+    // profiling
+    bool prof = false;
+    std::vector<hipEvent_t> ev;          // kEventRing x (kPhases + 1)
+    int ev_used = 0;
+    hipStream_t ev_stream = nullptr;
+    double totals[kPhases] = {0, 0, 0, 0};
+    long long counts[kPhases] = {0, 0, 0, 0};
+    std::vector<void *> allocs;
+};
+
+namespace {
+
+bool is_pow2(double v) {
+    if (!(v > 0.0) || !std::isfinite(v)) return false;
+    int e;
+    return std::frexp(v, &e) == 0.5;
+}
+
+mpm_status hip_ok(hipError_t e) { return e == hipSuccess ? MPM_OK : MPM_E_HIP; }
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+        else prev = -1;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+mpm_status validate_config(const mpm_config *c, const mpm_material *m, int32_t n_mat) {
+    if (!c || !m) return MPM_E_INVALID;
+    if (n_mat < 1 || n_mat > kMaxMaterials) return MPM_E_INVALID;
+    long long nbv = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (c->n_cells[a] < 4 || c->n_cells[a] > (1 << 16)) return MPM_E_INVALID;
+        nbv *= (c->n_cells[a] / 4 + 1);
+        if (!std::isfinite(c->origin[a]) || !std::isfinite(c->gravity[a])) return MPM_E_INVALID;
+    }
+    if (nbv >= (1ll << 26)) return MPM_E_INVALID;               // key = block * 64 + cell fits in 32 bits
+    if (!is_pow2(c->dx)) return MPM_E_INVALID;
+    if (c->max_particles < 1 || c->max_particles >= (1ll << kIndexBits)) return MPM_E_INVALID;
+    if (c->max_blocks < 1 || c->max_blocks >= (1ll << 26)) return MPM_E_INVALID;
+    if (c->bc != MPM_BC_NONE && c->bc != MPM_BC_STICKY) return MPM_E_INVALID;
+    if (c->bc_band < 0) return MPM_E_INVALID;
+    if (c->transfer != MPM_TRANSFER_MLS || c->flags != 0) return MPM_E_INVALID;
+    for (int i = 0; i < n_mat; ++i) {
+        const mpm_material &q = m[i];
+        if (q.model != MPM_FIXED_COROTATED && q.model != MPM_DRUCKER_PRAGER) return MPM_E_INVALID;
+        if (!(q.E > 0) || !(q.nu >= 0 && q.nu < 0.5f) || !(q.rho > 0) || !(q.vol0 > 0)) return MPM_E_INVALID;
+        if (!std::isfinite(q.E) || !std::isfinite(q.rho) || !std::isfinite(q.vol0)) return MPM_E_INVALID;
+        if (q.model == MPM_DRUCKER_PRAGER && !(q.friction_deg >= 0 && q.friction_deg < 90)) return MPM_E_INVALID;
+    }
+    return MPM_OK;
+}
+
+mpm_status validate_particles(const mpm_ctx *ctx, const mpm_particles *p) {
+    if (!ctx || !p) return MPM_E_INVALID;
+    if (p->n < 0 || p->n > ctx->cfg.max_particles || p->n > p->stride) return MPM_E_INVALID;
+    if (p->current != 0 && p->current != 1) return MPM_E_INVALID;
+    if (p->n > 0 && !p->state[p->current]) return MPM_E_INVALID;
+    if ((reinterpret_cast<uintptr_t>(p->state[p->current]) & 3u) != 0) return MPM_E_INVALID;
+    return MPM_OK;
+}
+
+void fill_geometry(const mpm_config &c, Geometry &g) {
+    for (int a = 0; a < 3; ++a) {
+        g.origin[a] = c.origin[a];
+        g.n[a] = c.n_cells[a];
+        g.NB[a] = c.n_cells[a] / 4 + 1;
+    }
+    g.inv_dx = 1.0 / c.dx;
+    g.dx = (float)c.dx;
+    g.inv_dx_f = (float)(1.0 / c.dx);
+    // a node i of grid G_k (k = -1, +1) sits at (i + k/4) cells; it is inside the
+    // sticky walls when band <= i + k/4 <= n - band on every axis
+    for (int gi = 0; gi < 2; ++gi) {
+        const double k = gi == 0 ? -0.25 : 0.25;
+        if (c.bc == MPM_BC_STICKY && c.bc_band > 0) {
+            g.stick_lo[gi] = (int)std::ceil(c.bc_band - k);
+            for (int a = 0; a < 3; ++a) g.stick_hi[gi][a] = (int)std::floor(c.n_cells[a] - c.bc_band - k);
+        } else {
+            g.stick_lo[gi] = -(1 << 30);
+            for (int a = 0; a < 3; ++a) g.stick_hi[gi][a] = 1 << 30;
+        }
+    }
+}
+
+DevMaterial dev_material(const mpm_material &m) {
+    DevMaterial r;
+    r.model = m.model;
+    r.mass = m.rho * m.vol0;
+    r.vol0 = m.vol0;
+    const double E = m.E, nu = m.nu;
+    const double mu = E / (2.0 * (1.0 + nu)), lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    r.mu = (float)mu;
+    r.lambda = (float)lam;
+    const double sphi = std::sin(m.friction_deg * 3.14159265358979323846 / 180.0);
+    const double alpha = std::sqrt(2.0 / 3.0) * 2.0 * sphi / (3.0 - sphi);
+    r.dp_coef = (float)((3.0 * lam + 2.0 * mu) / (2.0 * mu) * alpha);
+    return r;
+}
+
+template <typename T>
+mpm_status dalloc(mpm_ctx *ctx, T **ptr, size_t count) {
+    void *p = nullptr;
+    if (hipMalloc(&p, count * sizeof(T) + 256) != hipSuccess) return MPM_E_OOM;
+    ctx->allocs.push_back(p);
+    *ptr = static_cast<T *>(p);
+    return MPM_OK;
+}
+
+PartArgs part_args(const mpm_particles *p, bool with_out) {
+    PartArgs a;
+    const int cur = p->current;
+    a.in = p->state[cur];
+    a.out = with_out ? p->state[cur ^ 1] : nullptr;
+    a.stride = p->stride;
+    a.n = (int)p->n;
+    a.id_in = (p->id[0] && p->id[1]) ? p->id[cur] : nullptr;
+    a.id_out = (with_out && p->id[0] && p->id[1]) ? p->id[cur ^ 1] : nullptr;
+    a.mat_in = (p->mat[0] && p->mat[1]) ? p->mat[cur] : nullptr;
+    a.mat_out = (with_out && p->mat[0] && p->mat[1]) ? p->mat[cur ^ 1] : nullptr;
+    return a;
+}
+
+mpm_status last_error() { return hipGetLastError() == hipSuccess ? MPM_OK : MPM_E_HIP; }
+
+void fold_events(mpm_ctx *ctx) {
+    if (ctx->ev_used == 0) return;
+    (void)hipStreamSynchronize(ctx->ev_stream);
+    for (int s = 0; s < ctx->ev_used; ++s) {
+        for (int ph = 0; ph < kPhases; ++ph) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, ctx->ev[s * (kPhases + 1) + ph], ctx->ev[s * (kPhases + 1) + ph + 1]) == hipSuccess) {
+                ctx->totals[ph] += ms;
+                ctx->counts[ph] += 1;
+            }
+        }
+    }
+    ctx->ev_used = 0;
+}
+
+hipEvent_t *event_slot(mpm_ctx *ctx, hipStream_t s) {
+    if (!ctx->prof) return nullptr;
+    if (ctx->ev_used == kEventRing || (ctx->ev_used > 0 && s != ctx->ev_stream)) fold_events(ctx);
+    ctx->ev_stream = s;
+    return &ctx->ev[ctx->ev_used * (kPhases + 1)];
+}
+
+// sort + activation + P2G; ev (optional) receives phase boundaries 0, 1, 2
+mpm_status enqueue_p2g(mpm_ctx *ctx, const mpm_particles *p, double dt, hipStream_t s, hipEvent_t *ev, bool physics) {
+    const PartArgs pa = part_args(p, false);
+    if (ev) (void)hipEventRecord(ev[0], s);
+    if (!(ctx->next_ready == pa.in && ctx->next_n == pa.n)) launch_flag_keys(ctx->d, pa, 1, s);
+    launch_compact(ctx->d, s);
+    launch_bucket(ctx->d, pa.n, s);
+    if (ev) (void)hipEventRecord(ev[1], s);
+    launch_p2g(ctx->d, pa, (float)dt, physics, s);
+    if (ev) (void)hipEventRecord(ev[2], s);
+    ctx->next_ready = nullptr;
+    ctx->p2g_done = pa.in;
+    return last_error();
+}
+
+mpm_status enqueue_update(mpm_ctx *ctx, double dt, hipStream_t s) {
+    float g[3] = {(float)ctx->cfg.gravity[0], (float)ctx->cfg.gravity[1], (float)ctx->cfg.gravity[2]};
+    launch_grid_update(ctx->d, (float)dt, g, s);
+    return last_error();
+}
+
+mpm_status enqueue_g2p(mpm_ctx *ctx, mpm_particles *p, double dt, hipStream_t s) {
+    if (ctx->p2g_done != p->state[p->current]) return MPM_E_INVALID;
+    if (!p->state[p->current ^ 1]) return MPM_E_INVALID;
+    if ((p->id[0] == nullptr) != (p->id[1] == nullptr)) return MPM_E_INVALID;
+    if ((p->mat[0] == nullptr) != (p->mat[1] == nullptr)) return MPM_E_INVALID;
+    const PartArgs pa = part_args(p, true);
+    launch_g2p(ctx->d, pa, (float)dt, s);
+    p->current ^= 1;
+    ctx->next_ready = pa.out;
+    ctx->next_n = pa.n;
+    ctx->p2g_done = nullptr;
+    return last_error();
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t mpm_abi_version(void) { return CKMPM_ABI_VERSION; }
+
+const char *mpm_status_string(mpm_status s) {
+    switch (s) {
+        case MPM_OK: return "ok";
+        case MPM_E_INVALID: return "invalid argument or configuration";
+        case MPM_E_OOM: return "device allocation failed";
+        case MPM_E_DOMAIN: return "particle outside the valid domain";
+        case MPM_E_CAPACITY: return "grid block pool or per-block particle capacity exceeded";
+        case MPM_E_NONFINITE: return "non-finite particle state";
+        case MPM_E_HIP: return "HIP runtime error";
+        case MPM_E_STALE: return "particle positions changed after their cell keys were computed";
+    }
+    return "unknown status";
+}
+
+mpm_status mpm_create(const mpm_config *cfg, const mpm_material *mats, int32_t n_mat, mpm_ctx **out) {
+    if (!out) return MPM_E_INVALID;
+    *out = nullptr;
+    const mpm_status v = validate_config(cfg, mats, n_mat);
+    if (v != MPM_OK) return v;
+    mpm_ctx *ctx = new (std::nothrow) mpm_ctx();
+    if (!ctx) return MPM_E_OOM;
+    ctx->cfg = *cfg;
+    ctx->mats.assign(mats, mats + n_mat);
+    if (hipGetDevice(&ctx->device) != hipSuccess) {
+        delete ctx;
+        return MPM_E_HIP;
+    }
+    DevCtx &d = ctx->d;
+    std::memset(&d, 0, sizeof d);
+    fill_geometry(*cfg, d.geo);
+    for (int i = 0; i < n_mat; ++i) d.mats[i] = dev_material(mats[i]);
+    d.n_mat = n_mat;
+    d.max_blocks = (int)cfg->max_blocks;
+    d.nbv = (long long)d.geo.NB[0] * d.geo.NB[1] * d.geo.NB[2];
+    const size_t np = (size_t)cfg->max_particles, nb = (size_t)cfg->max_blocks, nv = (size_t)d.nbv;
+    const size_t nchunks = (nv + kCompactChunk - 1) / kCompactChunk;
+    mpm_status st = MPM_OK;
+    if (st == MPM_OK) st = dalloc(ctx, &d.key, np);
+    if (st == MPM_OK) st = dalloc(ctx, &d.slot, np);
+    if (st == MPM_OK) st = dalloc(ctx, &d.u, np);
+    if (st == MPM_OK) st = dalloc(ctx, &d.perm, np);
+    if (st == MPM_OK) st = dalloc(ctx, &d.pflag, 2 * nv);
+    if (st == MPM_OK) st = dalloc(ctx, &d.gflag, 2 * nv);
+    if (st == MPM_OK) st = dalloc(ctx, &d.page, nv);
+    if (st == MPM_OK) st = dalloc(ctx, &d.prank, nv);
+    if (st == MPM_OK) st = dalloc(ctx, &d.plist, nb);
+    if (st == MPM_OK) st = dalloc(ctx, &d.pstart, nb + 1);
+    if (st == MPM_OK) st = dalloc(ctx, &d.bcount, nb);
+    if (st == MPM_OK) st = dalloc(ctx, &d.glist, nb);
+    if (st == MPM_OK) st = dalloc(ctx, &d.chunk_p, nchunks);
+    if (st == MPM_OK) st = dalloc(ctx, &d.chunk_g, nchunks);
+    if (st == MPM_OK) st = dalloc(ctx, &d.pool, nb * kBlockFloats);
+    if (st == MPM_OK) st = dalloc(ctx, &d.counters, (size_t)C_COUNT);
+    if (st == MPM_OK && hipHostMalloc((void **)&ctx->host_counters, C_COUNT * sizeof(unsigned int), hipHostMallocDefault) != hipSuccess)
+        st = MPM_E_OOM;
+    if (st == MPM_OK) {
+        bool ok = hipMemset(d.pflag, 0, 2 * nv * sizeof(int)) == hipSuccess &&
+                  hipMemset(d.gflag, 0, 2 * nv * sizeof(int)) == hipSuccess &&
+                  hipMemset(d.page, 0xff, nv * sizeof(int)) == hipSuccess &&
+                  hipMemset(d.prank, 0xff, nv * sizeof(int)) == hipSuccess &&
+                  hipMemset(d.pstart, 0, (nb + 1) * sizeof(int)) == hipSuccess &&
+                  hipMemset(d.counters, 0, C_COUNT * sizeof(unsigned int)) == hipSuccess &&
+                  hipDeviceSynchronize() == hipSuccess;
+        if (!ok) st = MPM_E_HIP;
+    }
+    if (st != MPM_OK) {
+        mpm_destroy(ctx);
+        return st;
+    }
+    *out = ctx;
+    return MPM_OK;
+}
+
+mpm_status mpm_destroy(mpm_ctx *ctx) {
+    if (!ctx) return MPM_OK;
+    DeviceGuard g(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (void *p : ctx->allocs) (void)hipFree(p);
+    for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+    if (ctx->host_counters) (void)hipHostFree(ctx->host_counters);
+    delete ctx;
+    return MPM_OK;
+}
+
+mpm_status mpm_p2g(mpm_ctx *ctx, const mpm_particles *p, double dt, void *stream) {
+    const mpm_status v = validate_particles(ctx, p);
+    if (v != MPM_OK) return v;
+    if (!std::isfinite(dt) || dt < 0) return MPM_E_INVALID;
+    DeviceGuard g(ctx->device);
+    return enqueue_p2g(ctx, p, dt, (hipStream_t)stream, nullptr, true);
+}
+
+mpm_status mpm_grid_update(mpm_ctx *ctx, double dt, void *stream) {
+    if (!ctx || !std::isfinite(dt) || dt < 0) return MPM_E_INVALID;
+    DeviceGuard g(ctx->device);
+    return enqueue_update(ctx, dt, (hipStream_t)stream);
+}
+
+mpm_status mpm_g2p(mpm_ctx *ctx, mpm_particles *p, double dt, void *stream) {
+    const mpm_status v = validate_particles(ctx, p);
+    if (v != MPM_OK) return v;
+    if (!std::isfinite(dt) || dt < 0) return MPM_E_INVALID;
+    DeviceGuard g(ctx->device);
+    return enqueue_g2p(ctx, p, dt, (hipStream_t)stream);
+}
+
+mpm_status mpm_step(mpm_ctx *ctx, mpm_particles *p, double dt, int32_t nsteps, void *stream) {
+    const mpm_status v = validate_particles(ctx, p);
+    if (v != MPM_OK) return v;
+    if (!std::isfinite(dt) || dt < 0 || nsteps < 0) return MPM_E_INVALID;
+    if (!p->state[p->current ^ 1]) return MPM_E_INVALID;
+    DeviceGuard g(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    for (int k = 0; k < nsteps; ++k) {
+        hipEvent_t *ev = event_slot(ctx, s);
+        mpm_status st = enqueue_p2g(ctx, p, dt, s, ev, true);
+        if (st == MPM_OK) st = enqueue_update(ctx, dt, s);
+        if (st == MPM_OK && ev) (void)hipEventRecord(ev[3], s);
+        if (st == MPM_OK) st = enqueue_g2p(ctx, p, dt, s);
+        if (st == MPM_OK && ev) {
+            (void)hipEventRecord(ev[4], s);
+            ctx->ev_used += 1;
+        }
+        if (st != MPM_OK) return st;
+    }
+    return MPM_OK;
+}
+
+mpm_status mpm_sync(mpm_ctx *ctx, void *stream) {
+    if (!ctx) return MPM_E_INVALID;
+    DeviceGuard g(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    if (hipStreamSynchronize(s) != hipSuccess) return MPM_E_HIP;
+    unsigned int bits = 0;
+    if (hipMemcpy(&bits, ctx->d.counters + C_STATUS, sizeof bits, hipMemcpyDeviceToHost) != hipSuccess) return MPM_E_HIP;
+    const unsigned int zero = 0;
+    if (hipMemcpy(ctx->d.counters + C_STATUS, &zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess) return MPM_E_HIP;
+    if (bits & ST_NONFINITE) return MPM_E_NONFINITE;
+    if (bits & ST_DOMAIN) return MPM_E_DOMAIN;
+    if (bits & ST_CAPACITY) return MPM_E_CAPACITY;
+    if (bits & ST_STALE) return MPM_E_STALE;
+    return MPM_OK;
+}
+
+mpm_status mpm_grid_read(mpm_ctx *ctx, float *m, float *vec, void *stream) {
+    if (!ctx) return MPM_E_INVALID;
+    DeviceGuard g(ctx->device);
+    launch_grid_export(ctx->d, m, vec, (hipStream_t)stream);
+    return last_error();
+}
+
+mpm_status mpm_sort_keys(mpm_ctx *ctx, const mpm_particles *p, uint32_t *keys, uint32_t *perm, void *stream) {
+    const mpm_status v = validate_particles(ctx, p);
+    if (v != MPM_OK) return v;
+    DeviceGuard g(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    ctx->next_ready = nullptr;   // always recompute the keys from the positions
+    mpm_status st = enqueue_p2g(ctx, p, 0.0, s, nullptr, false);
+    if (st != MPM_OK) return st;
+    launch_copy_keys(ctx->d, keys, perm, (int)p->n, s);
+    ctx->p2g_done = nullptr;
+    return last_error();
+}
+
+mpm_status mpm_invalidate(mpm_ctx *ctx) {
+    if (!ctx) return MPM_E_INVALID;
+    ctx->next_ready = nullptr;
+    ctx->p2g_done = nullptr;
+    return MPM_OK;
+}
+
+mpm_status mpm_get_stats(mpm_ctx *ctx, mpm_stats *out, void *stream) {
+    if (!ctx || !out) return MPM_E_INVALID;
+    DeviceGuard g(ctx->device);
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return MPM_E_HIP;
+    if (hipMemcpy(ctx->host_counters, ctx->d.counters, C_COUNT * sizeof(unsigned int), hipMemcpyDeviceToHost) != hipSuccess)
+        return MPM_E_HIP;
+    out->n_particle_blocks = ctx->host_counters[C_NPB];
+    out->n_grid_blocks = ctx->host_counters[C_NGB];
+    out->max_block_particles = ctx->host_counters[C_MAXPB];
+    out->status_bits = ctx->host_counters[C_STATUS];
+    out->reserved = 0;
+    return MPM_OK;
+}
+
+mpm_status mpm_profile_enable(mpm_ctx *ctx, int32_t enable) {
+    if (!ctx) return MPM_E_INVALID;
+    DeviceGuard g(ctx->device);
+    if (enable && ctx->ev.empty()) {
+        ctx->ev.resize((size_t)kEventRing * (kPhases + 1));
+        for (auto &e : ctx->ev)
+            if (hipEventCreate(&e) != hipSuccess) return MPM_E_HIP;
+    }
+    if (!enable) fold_events(ctx);
+    ctx->prof = enable != 0;
+    for (int i = 0; i < kPhases; ++i) {
+        ctx->totals[i] = 0;
+        ctx->counts[i] = 0;
+    }
+    ctx->ev_used = 0;
+    return MPM_OK;
+}
+
+mpm_status mpm_profile_read(mpm_ctx *ctx, double *total_ms, int64_t *count, int32_t n_phases) {
+    if (!ctx || n_phases < 0) return MPM_E_INVALID;
+    DeviceGuard g(ctx->device);
+    fold_events(ctx);
+    for (int i = 0; i < n_phases && i < kPhases; ++i) {
+        if (total_ms) total_ms[i] = ctx->totals[i];
+        if (count) count[i] = ctx->counts[i];
+    }
+    return MPM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,421 @@
+// Shared definitions of the HIP implementation of the compact-kernel MPM step:
+// device-side context, particle arguments, and the per-particle FP32 math
+// (compact-kernel stencil, moment matrix, constitutive models).  Product code;
+// it has no relation to the CPU checker and includes nothing from it.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ck {
+
+constexpr int kThreads = 256;           // threads per workgroup of the particle kernels
+constexpr int kBlockFloats = 512;       // one pool block: [grid 2][channel 4][64 nodes] floats
+constexpr int kMaxMaterials = 8;
+constexpr int kMaxBlockParticles = 2048;  // particles one 4^3-cell block may hold (32 per cell on average)
+constexpr int kTileMinus = 125;         // G- nodes [4B, 4B+4]^3 touched by the particles of block B
+constexpr int kTilePlus = 216;          // G+ nodes [4B-1, 4B+4]^3
+constexpr int kTileNodes = kTileMinus + kTilePlus;
+constexpr int kCompactChunk = 1024;     // virtual blocks per workgroup in the block compaction
+constexpr int kIndexBits = 26;          // particle index bits in the packed (cell, index) sort word
+
+enum StatusBits : uint32_t {
+    ST_DOMAIN = 1u,
+    ST_CAPACITY = 2u,
+    ST_NONFINITE = 4u,
+    ST_STALE = 8u,
+};
+
+enum Counter : int {
+    C_NPB = 0,      // particle blocks this step
+    C_NGB = 1,      // grid blocks this step
+    C_STATUS = 2,   // status bits
+    C_EPOCH = 3,    // current activation epoch
+    C_MAXPB = 4,    // largest particle count of a block
+    C_TOTAL = 5,    // particles placed by the sort
+    C_COUNT = 8
+};
+
+struct DevMaterial {
+    int model;      // 0 fixed corotated, 1 Drucker-Prager
+    float mass;     // rho * vol0
+    float vol0;
+    float mu, lambda;
+    float dp_coef;  // (3 lambda + 2 mu) / (2 mu) * alpha,  alpha = sqrt(2/3) 2 sin(phi) / (3 - sin(phi))
+};
+
+struct Geometry {
+    double origin[3];
+    double inv_dx;
+    float dx, inv_dx_f;
+    int n[3];              // cells per axis
+    int NB[3];             // virtual blocks per axis (n/4 + 1)
+    int stick_lo[2];       // per grid: a node is inside the walls when lo <= i <= hi on every axis
+    int stick_hi[2][3];
+};
+
+struct DevCtx {
+    Geometry geo;
+    DevMaterial mats[kMaxMaterials];
+    int n_mat;
+    int max_blocks;
+    long long nbv;         // number of virtual blocks
+    uint32_t *key;         // per particle: block * 64 + cell of the current buffer
+    uint32_t *slot;        // per particle: rank inside its block (arbitrary order)
+    uint32_t *u;           // block-bucketed particle indices (arbitrary order inside a block)
+    uint32_t *perm;        // exact stable sort order
+    int *pflag, *gflag;    // [2][nbv] epoch stamps ("holds particles" / "grid block touched"),
+                           // double-buffered by epoch parity so that stamping the next step
+                           // never disturbs readers of the current one
+    int *page;             // per virtual block: physical pool block
+    int *prank;            // per virtual block: rank among the particle blocks
+    int *plist;            // particle blocks in increasing virtual id
+    int *pstart;           // first sorted position of each particle block (+1 sentinel)
+    int *bcount;           // particles per particle block
+    int *glist;            // virtual id of each physical pool block
+    int *chunk_p, *chunk_g;
+    float *pool;           // max_blocks * 512 floats
+    unsigned int *counters;
+};
+
+struct PartArgs {
+    const float *in;       // 24 planes
+    float *out;            // 24 planes
+    long long stride;
+    int n;
+    const uint32_t *id_in;
+    uint32_t *id_out;
+    const uint8_t *mat_in;
+    uint8_t *mat_out;
+};
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ void set_status(unsigned int *counters, uint32_t bits) {
+    atomicOr(&counters[C_STATUS], bits);
+}
+
+__device__ __forceinline__ int vblock_id(const Geometry &g, int bx, int by, int bz) {
+    return (bz * g.NB[1] + by) * g.NB[0] + bx;
+}
+
+// Stamp array of a given epoch (double buffer indexed by the epoch's parity).
+__device__ __forceinline__ int *stamps(int *base, long long nbv, int epoch) { return base + (epoch & 1) * nbv; }
+
+// Cell of a position on grid G- (particle keys) and the fractional coordinates on
+// both grids.  The integer part is taken in FP64 from the FP32 position so that it
+// is exact and identical to any FP64 evaluation of floor((x - origin)/dx + 1/4).
+struct CellCoord {
+    int c[3];       // G- cell: nodes c, c+1 of G- carry the particle
+    int bp[3];      // G+ base node: nodes bp, bp+1 of G+ carry the particle (bp = c or c-1)
+    float xm[3];    // fractional position inside the G- cell, in [0, 1)
+    float xp[3];    // fractional position inside the G+ cell, in [0, 1)
+};
+
+__device__ __forceinline__ bool cell_coord(const Geometry &g, const float x[3], CellCoord &cc) {
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double X = ((double)x[a] - g.origin[a]) * g.inv_dx;
+        ok = ok && (X >= 0.25) && (X < (double)g.n[a] - 0.25);
+        const double Xm = X + 0.25;
+        const double fl = floor(Xm);
+        cc.c[a] = (int)fl;
+        const double fm = Xm - fl;
+        cc.xm[a] = (float)fm;
+        if (fm >= 0.5) {
+            cc.bp[a] = cc.c[a];
+            cc.xp[a] = (float)(fm - 0.5);
+        } else {
+            cc.bp[a] = cc.c[a] - 1;
+            cc.xp[a] = (float)(fm + 0.5);
+        }
+    }
+    return ok;
+}
+
+__device__ __forceinline__ uint32_t cell_key(const Geometry &g, const CellCoord &cc) {
+    const int vb = vblock_id(g, cc.c[0] >> 2, cc.c[1] >> 2, cc.c[2] >> 2);
+    return ((uint32_t)vb << 6) | (uint32_t)((cc.c[2] & 3) * 16 + (cc.c[1] & 3) * 4 + (cc.c[0] & 3));
+}
+
+// Per-axis compact-kernel weights (section 4.1 kernel on the two staggered grids).
+// On a grid whose cell holds the particle at fractional coordinate xi, the two nodes
+// sit at distances xi and 1 - xi (cell units), so their weights are
+//   K1(xi) = 1 - xi + s   and   K1(1 - xi) = xi - s,   s = sin(2 pi xi)/(2 pi).
+// The G- coordinate is the G+ one shifted by half a cell, so its sine is the
+// negative of the G+ sine; one sine per axis serves both grids, and the dual-grid
+// cancellations (zero first moment of the pair) then hold exactly in FP32
+// whatever the accuracy of the sine.
+struct Weights {
+    float wm[3][2], wp[3][2];   // G-, G+ weights per axis and node offset
+    float sp[3];                // s on G+ (s on G- is -sp)
+};
+
+__device__ __forceinline__ void axis_weights(const CellCoord &cc, Weights &w) {
+    constexpr float kInv2Pi = 0.15915494309189535f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float s = sinpif(2.0f * cc.xp[a]) * kInv2Pi;
+        w.sp[a] = s;
+        w.wp[a][0] = 1.0f - cc.xp[a] + s;
+        w.wp[a][1] = cc.xp[a] - s;
+        w.wm[a][0] = 1.0f - cc.xm[a] - s;
+        w.wm[a][1] = cc.xm[a] + s;
+    }
+}
+
+// Moment matrix D_p / dx^2 of section 4.4 and its inverse.  Per axis the two
+// weights of grid k have first moment -s_k and second moment
+// xi_k (1 - xi_k) - s_k (1 - 2 xi_k) (cell units); the tensor-product kernel makes
+// D separable: D_aa = 1/2 sum_k m2_k,a and D_ab = 1/2 sum_k s_k,a s_k,b = sp_a sp_b.
+__device__ __forceinline__ void moment_inverse(const CellCoord &cc, const Weights &w, float Di[9]) {
+    float d[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float s = w.sp[a];
+        const float m2p = cc.xp[a] * (1.0f - cc.xp[a]) - s * (1.0f - 2.0f * cc.xp[a]);
+        const float m2m = cc.xm[a] * (1.0f - cc.xm[a]) + s * (1.0f - 2.0f * cc.xm[a]);
+        d[a] = 0.5f * (m2p + m2m);
+    }
+    const float o01 = w.sp[0] * w.sp[1], o02 = w.sp[0] * w.sp[2], o12 = w.sp[1] * w.sp[2];
+    // symmetric inverse by cofactors (D is SPD with condition number below 2)
+    const float c00 = d[1] * d[2] - o12 * o12;
+    const float c01 = o02 * o12 - o01 * d[2];
+    const float c02 = o01 * o12 - o02 * d[1];
+    const float c11 = d[0] * d[2] - o02 * o02;
+    const float c12 = o01 * o02 - d[0] * o12;
+    const float c22 = d[0] * d[1] - o01 * o01;
+    const float inv_det = 1.0f / (d[0] * c00 + o01 * c01 + o02 * c02);
+    Di[0] = c00 * inv_det; Di[1] = c01 * inv_det; Di[2] = c02 * inv_det;
+    Di[3] = c01 * inv_det; Di[4] = c11 * inv_det; Di[5] = c12 * inv_det;
+    Di[6] = c02 * inv_det; Di[7] = c12 * inv_det; Di[8] = c22 * inv_det;
+}
+
+// ------------------------------------------------------ constitutive models
+// Particle state stores the deformation gradient as H = F - I.  Solids stay close
+// to the identity, and an FP32 F near I resolves strains only to about 6e-8
+// absolute; H keeps them to FP32 relative precision, and every quantity below is
+// formed from H without subtracting numbers close to one.
+//
+// Both models are isotropic, so everything follows from the eigen-decomposition
+// F^T F = V diag(sigma^2) V^T, taken of the small symmetric matrix
+//   E = F^T F - I = H + H^T + H^T H  =  V diag(e) V^T,
+// so that sigma_i^2 = 1 + e_i, sigma_i - 1 = e_i / (1 + sqrt(1 + e_i)) and
+// log sigma_i = log1p(e_i)/2 are all resolved relative to the strain itself.  With
+// W = F V = V + H V (columns w_i = F v_i, |w_i| = sigma_i) no explicit U is needed:
+//   F = sum_i w_i v_i^T,  U = W diag(1/sigma),  R = W diag(1/sigma) V^T.
+// det F < 0 is handled as in the rotation-variant SVD: the smallest singular value
+// takes the sign.
+
+struct Eig3 {
+    float e[3];     // eigenvalues of F^T F - I, decreasing
+    float V[9];     // eigenvectors (columns), row-major storage V[3*row + col]
+};
+
+// Cyclic Jacobi eigen-decomposition of a symmetric 3x3 matrix (Golub & Van Loan,
+// symmetric Schur rotations), fixed number of sweeps.
+__device__ __forceinline__ void jacobi_rotate(float A[3][3], float V[9], int p, int q) {
+    const float apq = A[p][q];
+    const float d = A[q][q] - A[p][p];
+    const float den = fabsf(d) + sqrtf(d * d + 4.0f * apq * apq);
+    const float t = (den > 0.0f) ? (2.0f * apq * (d >= 0.0f ? 1.0f : -1.0f)) / den : 0.0f;
+    const float c = rsqrtf(1.0f + t * t);
+    const float s = t * c;
+    A[p][p] -= t * apq;
+    A[q][q] += t * apq;
+    A[p][q] = A[q][p] = 0.0f;
+    const int r = 3 - p - q;
+    const float arp = A[r][p], arq = A[r][q];
+    A[r][p] = A[p][r] = c * arp - s * arq;
+    A[r][q] = A[q][r] = s * arp + c * arq;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const float vp = V[3 * i + p], vq = V[3 * i + q];
+        V[3 * i + p] = c * vp - s * vq;
+        V[3 * i + q] = s * vp + c * vq;
+    }
+}
+
+__device__ __forceinline__ void strain_eig(const float H[9], Eig3 &r) {
+    float A[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = i; j < 3; ++j) {
+            float v = H[3 * i + j] + H[3 * j + i];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) v += H[3 * k + i] * H[3 * k + j];
+            A[i][j] = A[j][i] = v;
+        }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) r.V[i] = (i % 4 == 0) ? 1.0f : 0.0f;
+#pragma unroll
+    for (int sweep = 0; sweep < 5; ++sweep) {
+        jacobi_rotate(A, r.V, 0, 1);
+        jacobi_rotate(A, r.V, 0, 2);
+        jacobi_rotate(A, r.V, 1, 2);
+    }
+    float e0 = A[0][0], e1 = A[1][1], e2 = A[2][2];
+    // sort decreasing, swapping eigenvector columns alongside
+    auto swapcol = [&](int i, int j) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float t = r.V[3 * k + i];
+            r.V[3 * k + i] = r.V[3 * k + j];
+            r.V[3 * k + j] = t;
+        }
+    };
+    if (e0 < e1) { const float t = e0; e0 = e1; e1 = t; swapcol(0, 1); }
+    if (e1 < e2) { const float t = e1; e1 = e2; e2 = t; swapcol(1, 2); }
+    if (e0 < e1) { const float t = e0; e0 = e1; e1 = t; swapcol(0, 1); }
+    r.e[0] = e0; r.e[1] = e1; r.e[2] = e2;
+}
+
+// det F - 1 = det(I + H) - 1 = tr H + ((tr H)^2 - tr(H^2))/2 + det H.
+__device__ __forceinline__ float det_minus_one(const float H[9]) {
+    const float tr = H[0] + H[4] + H[8];
+    const float trH2 = H[0] * H[0] + H[4] * H[4] + H[8] * H[8] + 2.0f * (H[1] * H[3] + H[2] * H[6] + H[5] * H[7]);
+    const float detH = H[0] * (H[4] * H[8] - H[5] * H[7]) - H[1] * (H[3] * H[8] - H[5] * H[6]) + H[2] * (H[3] * H[7] - H[4] * H[6]);
+    return tr + 0.5f * (tr * tr - trH2) + detH;
+}
+
+// W = F V = V + H V
+__device__ __forceinline__ void mat_W(const float H[9], const float V[9], float W[9]) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            W[3 * i + j] = V[3 * i + j] + (H[3 * i] * V[j] + H[3 * i + 1] * V[3 + j] + H[3 * i + 2] * V[6 + j]);
+}
+
+constexpr float kSigmaFloor2 = 1e-8f;   // Drucker-Prager: singular values clamped at 1e-4 before logs
+
+// Kirchhoff stress tau = P F^T (symmetric, stored as 6 values: 00 11 22 01 02 12).
+// Fixed corotated (Stomakhin et al. 2012):  tau = 2 mu (F - R) F^T + lambda (J - 1) J I
+//   with (F - R) F^T = W diag((sigma - 1)/sigma) W^T.
+// Drucker-Prager elastic part (Hencky St. Venant-Kirchhoff, Klar et al. 2016):
+//   tau = U diag(2 mu eps + lambda tr eps) U^T = W diag((2 mu eps + lambda tr eps)/sigma^2) W^T.
+__device__ __forceinline__ void kirchhoff(const DevMaterial &m, const float H[9], float tau[6]) {
+    Eig3 ev;
+    strain_eig(H, ev);
+    float W[9];
+    mat_W(H, ev.V, W);
+    const float jm1 = det_minus_one(H);
+    const bool inverted = (1.0f + jm1) < 0.0f;
+    float coef[3];
+    float iso = 0.0f;
+    if (m.model == 0) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const float s2 = fmaxf(1.0f + ev.e[i], 0.0f);
+            const float s = sqrtf(s2);
+            float sm1 = ev.e[i] / (1.0f + s);   // sigma - 1
+            float sig = s;
+            if (i == 2 && inverted) {
+                sig = -s;
+                sm1 = -s - 1.0f;
+            }
+            const float sg = (fabsf(sig) < 1e-12f) ? (sig < 0.0f ? -1e-12f : 1e-12f) : sig;
+            coef[i] = 2.0f * m.mu * sm1 / sg;
+        }
+        iso = m.lambda * jm1 * (1.0f + jm1);
+    } else {
+        float eps[3];
+        float tr = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const float e = (i == 2 && inverted) ? (kSigmaFloor2 - 1.0f) : fmaxf(ev.e[i], kSigmaFloor2 - 1.0f);
+            eps[i] = 0.5f * log1pf(e);
+            tr += eps[i];
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const float s2 = fmaxf(1.0f + ev.e[i], 1e-30f);
+            coef[i] = (2.0f * m.mu * eps[i] + m.lambda * tr) / s2;
+        }
+    }
+    // tau = sum_i coef_i w_i w_i^T + iso I
+    float t00 = iso, t11 = iso, t22 = iso, t01 = 0.0f, t02 = 0.0f, t12 = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const float a = W[i], b = W[3 + i], c = W[6 + i];
+        t00 += coef[i] * a * a;
+        t11 += coef[i] * b * b;
+        t22 += coef[i] * c * c;
+        t01 += coef[i] * a * b;
+        t02 += coef[i] * a * c;
+        t12 += coef[i] * b * c;
+    }
+    tau[0] = t00; tau[1] = t11; tau[2] = t22; tau[3] = t01; tau[4] = t02; tau[5] = t12;
+}
+
+// Drucker-Prager return mapping (Klar et al. 2016) on the trial elastic F = I + H,
+// in place on H.  eps = log sigma, eps_hat = eps - tr(eps)/3:
+//   tr eps > 0 or |eps_hat| = 0      -> sigma' = 1 (cone tip: stress free)
+//   dgamma = |eps_hat| + c tr(eps) <= 0 -> unchanged (inside the cone)
+//   otherwise                          -> eps' = eps - dgamma eps_hat / |eps_hat|
+// and F' = sum_i (sigma'_i / sigma_i) w_i v_i^T, i.e.
+//   H' = H + sum_i expm1(eps'_i - log sigma_i) w_i v_i^T.
+__device__ __forceinline__ void dp_return_map(const DevMaterial &m, float H[9]) {
+    Eig3 ev;
+    strain_eig(H, ev);
+    const float jm1 = det_minus_one(H);
+    const bool inverted = (1.0f + jm1) < 0.0f;
+    float eps[3], lns[3];
+    float tr = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const float e = (i == 2 && inverted) ? (kSigmaFloor2 - 1.0f) : fmaxf(ev.e[i], kSigmaFloor2 - 1.0f);
+        eps[i] = 0.5f * log1pf(e);
+        lns[i] = 0.5f * log1pf(fmaxf(ev.e[i], -1.0f + 1e-30f));
+        tr += eps[i];
+    }
+    float dev[3];
+    float dn2 = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        dev[i] = eps[i] - tr * (1.0f / 3.0f);
+        dn2 += dev[i] * dev[i];
+    }
+    const float dn = sqrtf(dn2);
+    float target[3];
+    if (tr > 0.0f || dn == 0.0f) {
+        target[0] = target[1] = target[2] = 0.0f;
+    } else {
+        const float dgamma = dn + m.dp_coef * tr;
+        if (dgamma <= 0.0f) return;
+        const float k = dgamma / dn;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) target[i] = eps[i] - k * dev[i];
+    }
+    float W[9];
+    mat_W(H, ev.V, W);
+    float r[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) r[i] = expm1f(target[i] - lns[i]);
+    if (inverted) {
+        // sigma_3 carries the sign: sigma'_3 / sigma_3 = -exp(target_3) / |sigma_3|
+        r[2] = -expf(target[2] - lns[2]) - 1.0f;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            H[3 * i + j] += r[0] * W[3 * i] * ev.V[3 * j] + r[1] * W[3 * i + 1] * ev.V[3 * j + 1] +
+                            r[2] * W[3 * i + 2] * ev.V[3 * j + 2];
+}
+
+// ------------------------------------------------------------ launchers
+struct Ctx;  // host context (ck_api.hip)
+
+void launch_flag_keys(const DevCtx &d, const PartArgs &pa, int epoch_offset, hipStream_t s);
+void launch_clear_flags(const DevCtx &d, hipStream_t s);
+void launch_compact(const DevCtx &d, hipStream_t s);
+void launch_bucket(const DevCtx &d, int n, hipStream_t s);
+void launch_p2g(const DevCtx &d, const PartArgs &pa, float dt, bool physics, hipStream_t s);
+void launch_grid_update(const DevCtx &d, float dt, const float gravity[3], hipStream_t s);
+void launch_g2p(const DevCtx &d, const PartArgs &pa, float dt, hipStream_t s);
+void launch_grid_export(const DevCtx &d, float *m, float *vec, hipStream_t s);
+void launch_copy_keys(const DevCtx &d, uint32_t *keys, uint32_t *perm, int n, hipStream_t s);
+
+}  // namespace ck

@@ -1,0 +1,342 @@
+// Cell keys, grid-block activation and the bucketing half of the particle sort.
+//
+// The particles are sorted stably by key = (4^3-cell block) * 64 + (cell in block),
+// the G- cell being floor((x - origin)/dx + 1/4) per axis.  A stable sort by key is
+// the same as a sort by (key, index), which we build in two exact stages:
+//   1. bucket by block: blocks holding particles are enumerated in increasing
+//      virtual id (compaction of per-block epoch stamps), every particle takes a slot
+//      in its block's bucket with one wave-aggregated atomic, and a scan of the
+//      bucket sizes gives each block its range of sorted positions;
+//   2. inside each block (in the P2G workgroup, in LDS): order by (cell, index).
+// Atomics only decide where a particle waits inside its bucket, never its final
+// position, so the resulting permutation is deterministic and exact.
+#include "ck_common.hpp"
+
+namespace ck {
+
+namespace {
+
+__device__ __forceinline__ int wave_lane() { return __lane_id(); }
+
+// Stamp the virtual blocks a particle needs: its own block (it holds particles) and
+// every block containing one of its 16 stencil nodes (G- nodes c..c+1 and G+ nodes
+// bp..bp+1 on each axis, so at most two blocks per axis).
+__device__ __forceinline__ void stamp_blocks(const DevCtx &d, const CellCoord &cc, int epoch) {
+    const Geometry &g = d.geo;
+    int *pf = stamps(d.pflag, d.nbv, epoch);
+    int *gf = stamps(d.gflag, d.nbv, epoch);
+    pf[vblock_id(g, cc.c[0] >> 2, cc.c[1] >> 2, cc.c[2] >> 2)] = epoch;
+    int lo[3], hi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = min(cc.c[a], cc.bp[a]) >> 2;
+        hi[a] = (cc.c[a] + 1) >> 2;
+    }
+    for (int bz = lo[2]; bz <= hi[2]; ++bz)
+        for (int by = lo[1]; by <= hi[1]; ++by)
+            for (int bx = lo[0]; bx <= hi[0]; ++bx) gf[vblock_id(g, bx, by, bz)] = epoch;
+}
+
+__global__ void __launch_bounds__(kThreads) k_flag_keys(DevCtx d, PartArgs pa, int epoch_offset) {
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= pa.n) return;
+    const int epoch = (int)d.counters[C_EPOCH] + epoch_offset;
+    const float x[3] = {pa.in[i], pa.in[pa.stride + i], pa.in[2 * pa.stride + i]};
+    CellCoord cc;
+    if (!cell_coord(d.geo, x, cc)) {
+        d.key[i] = 0xffffffffu;
+        set_status(d.counters, ST_DOMAIN);
+        return;
+    }
+    d.key[i] = cell_key(d.geo, cc);
+    stamp_blocks(d, cc, epoch);
+}
+
+__global__ void k_clear_flags(DevCtx d) {
+    for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < 2 * d.nbv; v += (long long)gridDim.x * blockDim.x) {
+        d.pflag[v] = 0;
+        d.gflag[v] = 0;
+    }
+}
+
+// Workgroup-wide sum of two counters (256 threads).
+__device__ __forceinline__ void wg_sum2(int &a, int &b, int *sh) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_down(a, off);
+        b += __shfl_down(b, off);
+    }
+    const int w = threadIdx.x >> 6;
+    if (wave_lane() == 0) {
+        sh[2 * w] = a;
+        sh[2 * w + 1] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int sa = 0, sb = 0;
+        for (int k = 0; k < kThreads / 64; ++k) {
+            sa += sh[2 * k];
+            sb += sh[2 * k + 1];
+        }
+        sh[2 * (kThreads / 64)] = sa;
+        sh[2 * (kThreads / 64) + 1] = sb;
+    }
+    __syncthreads();
+    a = sh[2 * (kThreads / 64)];
+    b = sh[2 * (kThreads / 64) + 1];
+}
+
+constexpr int kPerThread = kCompactChunk / kThreads;   // 4 virtual blocks per thread
+
+__global__ void __launch_bounds__(kThreads) k_compact_count(DevCtx d) {
+    __shared__ int sh[16];
+    const int E = (int)d.counters[C_EPOCH] + 1;
+    const int *pf = stamps(d.pflag, d.nbv, E);
+    const int *gf = stamps(d.gflag, d.nbv, E);
+    const long long base = (long long)blockIdx.x * kCompactChunk + threadIdx.x * kPerThread;
+    int cp = 0, cg = 0;
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+        const long long v = base + k;
+        if (v < d.nbv) {
+            cp += (pf[v] == E);
+            cg += (gf[v] == E);
+        }
+    }
+    wg_sum2(cp, cg, sh);
+    if (threadIdx.x == 0) {
+        d.chunk_p[blockIdx.x] = cp;
+        d.chunk_g[blockIdx.x] = cg;
+    }
+}
+
+// Exclusive scan of `n` ints in place by one workgroup of 1024 threads; returns the total.
+template <int T>
+__device__ int wg_scan_inplace(int *data, int n, int *sh) {
+    const int per = (n + T - 1) / T;
+    const int beg = min(n, threadIdx.x * per), end = min(n, beg + per);
+    int local = 0;
+    for (int i = beg; i < end; ++i) local += data[i];
+    // inclusive scan of the per-thread sums across the workgroup
+    int v = local;
+    const int lane = wave_lane();
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(v, off);
+        if (lane >= off) v += t;
+    }
+    const int w = threadIdx.x >> 6;
+    if (lane == 63) sh[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int k = 0; k < T / 64; ++k) {
+            const int t = sh[k];
+            sh[k] = acc;
+            acc += t;
+        }
+        sh[T / 64] = acc;
+    }
+    __syncthreads();
+    int run = sh[w] + v - local;
+    for (int i = beg; i < end; ++i) {
+        const int t = data[i];
+        data[i] = run;
+        run += t;
+    }
+    const int total = sh[T / 64];
+    __syncthreads();
+    return total;
+}
+
+__global__ void __launch_bounds__(1024) k_compact_scan(DevCtx d, int nchunks) {
+    __shared__ int sh[32];
+    const int np = wg_scan_inplace<1024>(d.chunk_p, nchunks, sh);
+    const int ng = wg_scan_inplace<1024>(d.chunk_g, nchunks, sh);
+    if (threadIdx.x == 0) {
+        if (ng > d.max_blocks || np > d.max_blocks) set_status(d.counters, ST_CAPACITY);
+        d.counters[C_NPB] = (unsigned)min(np, d.max_blocks);
+        d.counters[C_NGB] = (unsigned)min(ng, d.max_blocks);
+        d.counters[C_EPOCH] += 1u;
+        d.counters[C_MAXPB] = 0u;
+        d.counters[C_TOTAL] = 0u;
+    }
+}
+
+// Workgroup exclusive scan of one int per thread (256 threads); returns the total.
+__device__ __forceinline__ int wg_excl_scan(int x, int &excl, int *sh) {
+    int v = x;
+    const int lane = wave_lane();
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(v, off);
+        if (lane >= off) v += t;
+    }
+    const int w = threadIdx.x >> 6;
+    if (lane == 63) sh[w] = v;
+    __syncthreads();
+    int pre = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < kThreads / 64; ++k) {
+        const int t = sh[k];
+        pre += (k < w) ? t : 0;
+        tot += t;
+    }
+    excl = pre + v - x;
+    __syncthreads();
+    return tot;
+}
+
+__global__ void __launch_bounds__(kThreads) k_compact_emit(DevCtx d) {
+    __shared__ int sh[8];
+    __shared__ int emitted[kCompactChunk];
+    __shared__ int n_emitted;
+    const int E = (int)d.counters[C_EPOCH];
+    const int *pf = stamps(d.pflag, d.nbv, E);
+    const int *gf = stamps(d.gflag, d.nbv, E);
+    const long long base = (long long)blockIdx.x * kCompactChunk + threadIdx.x * kPerThread;
+    int fp[kPerThread], fg[kPerThread];
+    int cp = 0, cg = 0;
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+        const long long v = base + k;
+        fp[k] = (v < d.nbv) && (pf[v] == E);
+        fg[k] = (v < d.nbv) && (gf[v] == E);
+        cp += fp[k];
+        cg += fg[k];
+    }
+    int ep, eg;
+    wg_excl_scan(cp, ep, sh);
+    const int gtot = wg_excl_scan(cg, eg, sh);
+    const int offp = d.chunk_p[blockIdx.x] + ep;
+    const int offg = d.chunk_g[blockIdx.x] + eg;
+    int rp = offp, rg = offg;
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+        const int v = (int)(base + k);
+        if (fp[k]) {
+            if (rp < d.max_blocks) {
+                d.plist[rp] = v;
+                d.prank[v] = rp;
+                d.bcount[rp] = 0;
+            } else {
+                d.prank[v] = -1;
+            }
+            ++rp;
+        }
+        if (fg[k]) {
+            if (rg < d.max_blocks) {
+                d.glist[rg] = v;
+                d.page[v] = rg;
+                emitted[rg - d.chunk_g[blockIdx.x]] = rg;
+            } else {
+                d.page[v] = -1;
+                emitted[rg - d.chunk_g[blockIdx.x]] = -1;
+            }
+            ++rg;
+        }
+    }
+    if (threadIdx.x == 0) n_emitted = gtot;
+    __syncthreads();
+    // zero the pool blocks handed out by this chunk (a float4 per thread and step)
+    const int nb = n_emitted;
+    for (int t = threadIdx.x; t < nb * (kBlockFloats / 4); t += kThreads) {
+        const int b = emitted[t / (kBlockFloats / 4)];
+        if (b >= 0) reinterpret_cast<float4 *>(d.pool + (size_t)b * kBlockFloats)[t % (kBlockFloats / 4)] = make_float4(0, 0, 0, 0);
+    }
+}
+
+// Slot of each particle in its block's bucket: one atomic per distinct block in the
+// wave (particles arrive nearly sorted, so a wave usually spans one or two blocks).
+__global__ void __launch_bounds__(kThreads) k_bucket_count(DevCtx d, int n) {
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    const bool live = i < n;
+    const int E = (int)d.counters[C_EPOCH];
+    int r = -1;
+    if (live) {
+        const uint32_t k = d.key[i];
+        if (k != 0xffffffffu) {
+            // a key whose block was not stamped this step cannot be placed
+            if (stamps(d.pflag, d.nbv, E)[k >> 6] == E) r = d.prank[k >> 6];
+            else set_status(d.counters, ST_STALE);
+        }
+    }
+    const bool act = r >= 0;
+    uint64_t remaining = __ballot(act);
+    const int lane = wave_lane();
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    while (remaining) {
+        const int leader = __ffsll((unsigned long long)remaining) - 1;
+        const int rl = __shfl(r, leader);
+        const uint64_t same = __ballot(act && r == rl);
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&d.bcount[rl], __popcll(same));
+        base = __shfl(base, leader);
+        if (act && r == rl) d.slot[i] = (uint32_t)(base + __popcll(same & below));
+        remaining &= ~same;
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_bucket_scan(DevCtx d) {
+    __shared__ int sh[32];
+    __shared__ int smax[16];
+    const int np = (int)d.counters[C_NPB];
+    // largest bucket
+    int mx = 0;
+    for (int r = threadIdx.x; r < np; r += 1024) mx = max(mx, d.bcount[r]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_down(mx, off));
+    if (wave_lane() == 0) smax[threadIdx.x >> 6] = mx;
+    // exclusive scan of the bucket sizes into pstart
+    for (int r = threadIdx.x; r < np; r += 1024) d.pstart[r] = d.bcount[r];
+    __syncthreads();
+    const int total = wg_scan_inplace<1024>(d.pstart, np, sh);
+    if (threadIdx.x == 0) {
+        int m = 0;
+        for (int k = 0; k < 16; ++k) m = max(m, smax[k]);
+        d.pstart[np] = total;
+        d.counters[C_MAXPB] = (unsigned)m;
+        d.counters[C_TOTAL] = (unsigned)total;
+        if (m > kMaxBlockParticles) set_status(d.counters, ST_CAPACITY);
+    }
+}
+
+__global__ void __launch_bounds__(kThreads) k_bucket_scatter(DevCtx d, int n) {
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t k = d.key[i];
+    if (k == 0xffffffffu) return;
+    const int E = (int)d.counters[C_EPOCH];
+    if (stamps(d.pflag, d.nbv, E)[k >> 6] != E) return;
+    const int r = d.prank[k >> 6];
+    if (r < 0) return;
+    const int pos = d.pstart[r] + (int)d.slot[i];
+    if (pos < 0 || pos >= n) return;
+    d.u[pos] = (uint32_t)i;
+}
+
+}  // namespace
+
+void launch_flag_keys(const DevCtx &d, const PartArgs &pa, int epoch_offset, hipStream_t s) {
+    if (pa.n <= 0) return;
+    hipLaunchKernelGGL(k_flag_keys, dim3((pa.n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, d, pa, epoch_offset);
+}
+
+void launch_clear_flags(const DevCtx &d, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear_flags, dim3(1024), dim3(256), 0, s, d);
+}
+
+void launch_compact(const DevCtx &d, hipStream_t s) {
+    const int nchunks = (int)((d.nbv + kCompactChunk - 1) / kCompactChunk);
+    hipLaunchKernelGGL(k_compact_count, dim3(nchunks), dim3(kThreads), 0, s, d);
+    hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, s, d, nchunks);
+    hipLaunchKernelGGL(k_compact_emit, dim3(nchunks), dim3(kThreads), 0, s, d);
+}
+
+void launch_bucket(const DevCtx &d, int n, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_bucket_count, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, d, n);
+    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, d);
+    if (n > 0) hipLaunchKernelGGL(k_bucket_scatter, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, d, n);
+}
+
+}  // namespace ck
