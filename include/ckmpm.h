@@ -69,7 +69,9 @@ typedef struct {
     int32_t bc;            /* MPM_BC_NONE or MPM_BC_STICKY                                          */
     int32_t bc_band;       /* sticky: zero v~ at nodes closer than bc_band cells to a box face      */
     int64_t max_particles; /* capacity of every per-particle scratch array                          */
-    int64_t max_blocks;    /* capacity of the grid block pool (blocks of 4x4x4 nodes, both grids)   */
+    int64_t max_blocks;    /* capacity of the grid block pool (blocks of 4x4x4 nodes, both grids);
+                              device memory is about 10 KiB per block (2 KiB of grid, 8 KiB of
+                              sort buckets of up to 2048 particles per block)                      */
     int32_t transfer;      /* MPM_TRANSFER_MLS                                                      */
     int32_t flags;         /* reserved, must be 0                                                   */
 } mpm_config;

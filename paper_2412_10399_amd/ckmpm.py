@@ -298,7 +298,7 @@ def scene_config(sc, max_particles=None, max_blocks=None) -> mpm_config:
         nb = 1
         for a in range(3):
             nb *= sc.n_cells[a] // 4 + 1
-        max_blocks = min(nb, max(1024, 4 * (n // 64 + 1) + 4096))
+        max_blocks = min(nb, 2 * (n // 256) + 4096)
     return make_config(sc.n_cells, sc.dx, sc.origin, sc.gravity, sc.bc_band, max(n, 1), max_blocks)
 
 

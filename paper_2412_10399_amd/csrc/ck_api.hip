@@ -181,12 +181,15 @@ hipEvent_t *event_slot(mpm_ctx *ctx, hipStream_t s) {
 // sort + activation + P2G; ev (optional) receives phase boundaries 0, 1, 2
 mpm_status enqueue_p2g(mpm_ctx *ctx, const mpm_particles *p, double dt, hipStream_t s, hipEvent_t *ev, bool physics) {
     const PartArgs pa = part_args(p, false);
+    // keys, next-step block stamps and the stress of every particle are in place
+    // when the previous mpm_g2p wrote this very buffer
+    const bool ready = ctx->next_ready == pa.in && ctx->next_n == pa.n;
     if (ev) (void)hipEventRecord(ev[0], s);
-    if (!(ctx->next_ready == pa.in && ctx->next_n == pa.n)) launch_flag_keys(ctx->d, pa, 1, s);
+    if (!ready) launch_flag_keys(ctx->d, pa, 1, s);
     launch_compact(ctx->d, s);
     launch_bucket(ctx->d, pa.n, s);
     if (ev) (void)hipEventRecord(ev[1], s);
-    launch_p2g(ctx->d, pa, (float)dt, physics, s);
+    launch_p2g(ctx->d, pa, (float)dt, physics, ready, s);
     if (ev) (void)hipEventRecord(ev[2], s);
     ctx->next_ready = nullptr;
     ctx->p2g_done = pa.in;
@@ -257,8 +260,7 @@ mpm_status mpm_create(const mpm_config *cfg, const mpm_material *mats, int32_t n
     const size_t nchunks = (nv + kCompactChunk - 1) / kCompactChunk;
     mpm_status st = MPM_OK;
     if (st == MPM_OK) st = dalloc(ctx, &d.key, np);
-    if (st == MPM_OK) st = dalloc(ctx, &d.slot, np);
-    if (st == MPM_OK) st = dalloc(ctx, &d.u, np);
+    if (st == MPM_OK) st = dalloc(ctx, &d.bucket, nb * (size_t)kMaxBlockParticles);
     if (st == MPM_OK) st = dalloc(ctx, &d.perm, np);
     if (st == MPM_OK) st = dalloc(ctx, &d.pflag, 2 * nv);
     if (st == MPM_OK) st = dalloc(ctx, &d.gflag, 2 * nv);
@@ -271,6 +273,8 @@ mpm_status mpm_create(const mpm_config *cfg, const mpm_material *mats, int32_t n
     if (st == MPM_OK) st = dalloc(ctx, &d.chunk_p, nchunks);
     if (st == MPM_OK) st = dalloc(ctx, &d.chunk_g, nchunks);
     if (st == MPM_OK) st = dalloc(ctx, &d.pool, nb * kBlockFloats);
+    if (st == MPM_OK) st = dalloc(ctx, &d.tau, 6 * np);
+    d.tau_stride = (long long)np;
     if (st == MPM_OK) st = dalloc(ctx, &d.counters, (size_t)C_COUNT);
     if (st == MPM_OK && hipHostMalloc((void **)&ctx->host_counters, C_COUNT * sizeof(unsigned int), hipHostMallocDefault) != hipSuccess)
         st = MPM_E_OOM;

@@ -61,8 +61,8 @@ struct DevCtx {
     int max_blocks;
     long long nbv;         // number of virtual blocks
     uint32_t *key;         // per particle: block * 64 + cell of the current buffer
-    uint32_t *slot;        // per particle: rank inside its block (arbitrary order)
-    uint32_t *u;           // block-bucketed particle indices (arbitrary order inside a block)
+    uint32_t *bucket;      // [max_blocks][kMaxBlockParticles]: particle indices of each particle
+                           // block, in arrival order
     uint32_t *perm;        // exact stable sort order
     int *pflag, *gflag;    // [2][nbv] epoch stamps ("holds particles" / "grid block touched"),
                            // double-buffered by epoch parity so that stamping the next step
@@ -75,6 +75,8 @@ struct DevCtx {
     int *glist;            // virtual id of each physical pool block
     int *chunk_p, *chunk_g;
     float *pool;           // max_blocks * 512 floats
+    float *tau;            // [6][max_particles] Kirchhoff stress of the state G2P wrote, at its sorted position
+    long long tau_stride;
     unsigned int *counters;
 };
 
@@ -90,6 +92,12 @@ struct PartArgs {
 };
 
 // ------------------------------------------------------------------ helpers
+// Hardware reciprocal and square root (about 1 ulp).  Used where a correctly
+// rounded result buys nothing: rotation angles, inverses of well-conditioned
+// quantities, normalisations.
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 __device__ __forceinline__ void set_status(unsigned int *counters, uint32_t bits) {
     atomicOr(&counters[C_STATUS], bits);
 }
@@ -185,7 +193,7 @@ __device__ __forceinline__ void moment_inverse(const CellCoord &cc, const Weight
     const float c11 = d[0] * d[2] - o02 * o02;
     const float c12 = o01 * o02 - d[0] * o12;
     const float c22 = d[0] * d[1] - o01 * o01;
-    const float inv_det = 1.0f / (d[0] * c00 + o01 * c01 + o02 * c02);
+    const float inv_det = fast_rcp(d[0] * c00 + o01 * c01 + o02 * c02);
     Di[0] = c00 * inv_det; Di[1] = c01 * inv_det; Di[2] = c02 * inv_det;
     Di[3] = c01 * inv_det; Di[4] = c11 * inv_det; Di[5] = c12 * inv_det;
     Di[6] = c02 * inv_det; Di[7] = c12 * inv_det; Di[8] = c22 * inv_det;
@@ -213,12 +221,15 @@ struct Eig3 {
 };
 
 // Cyclic Jacobi eigen-decomposition of a symmetric 3x3 matrix (Golub & Van Loan,
-// symmetric Schur rotations), fixed number of sweeps.
+// symmetric Schur rotations), fixed number of sweeps (convergence is quadratic:
+// four sweeps reach FP32 rounding for 3x3 matrices).
 __device__ __forceinline__ void jacobi_rotate(float A[3][3], float V[9], int p, int q) {
     const float apq = A[p][q];
     const float d = A[q][q] - A[p][p];
-    const float den = fabsf(d) + sqrtf(d * d + 4.0f * apq * apq);
-    const float t = (den > 0.0f) ? (2.0f * apq * (d >= 0.0f ? 1.0f : -1.0f)) / den : 0.0f;
+    // any t gives an exact rotation (c^2 + s^2 = 1 to rounding), so the angle may be
+    // computed with hardware reciprocal and square root
+    const float den = fabsf(d) + fast_sqrt(d * d + 4.0f * apq * apq);
+    const float t = (den > 0.0f) ? (2.0f * apq * (d >= 0.0f ? 1.0f : -1.0f)) * fast_rcp(den) : 0.0f;
     const float c = rsqrtf(1.0f + t * t);
     const float s = t * c;
     A[p][p] -= t * apq;
@@ -250,7 +261,7 @@ __device__ __forceinline__ void strain_eig(const float H[9], Eig3 &r) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) r.V[i] = (i % 4 == 0) ? 1.0f : 0.0f;
 #pragma unroll
-    for (int sweep = 0; sweep < 5; ++sweep) {
+    for (int sweep = 0; sweep < 4; ++sweep) {
         jacobi_rotate(A, r.V, 0, 1);
         jacobi_rotate(A, r.V, 0, 2);
         jacobi_rotate(A, r.V, 1, 2);
@@ -308,15 +319,15 @@ __device__ __forceinline__ void kirchhoff(const DevMaterial &m, const float H[9]
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             const float s2 = fmaxf(1.0f + ev.e[i], 0.0f);
-            const float s = sqrtf(s2);
-            float sm1 = ev.e[i] / (1.0f + s);   // sigma - 1
+            const float s = fast_sqrt(s2);
+            float sm1 = ev.e[i] * fast_rcp(1.0f + s);   // sigma - 1
             float sig = s;
             if (i == 2 && inverted) {
                 sig = -s;
                 sm1 = -s - 1.0f;
             }
             const float sg = (fabsf(sig) < 1e-12f) ? (sig < 0.0f ? -1e-12f : 1e-12f) : sig;
-            coef[i] = 2.0f * m.mu * sm1 / sg;
+            coef[i] = 2.0f * m.mu * sm1 * fast_rcp(sg);
         }
         iso = m.lambda * jm1 * (1.0f + jm1);
     } else {
@@ -331,7 +342,7 @@ __device__ __forceinline__ void kirchhoff(const DevMaterial &m, const float H[9]
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             const float s2 = fmaxf(1.0f + ev.e[i], 1e-30f);
-            coef[i] = (2.0f * m.mu * eps[i] + m.lambda * tr) / s2;
+            coef[i] = (2.0f * m.mu * eps[i] + m.lambda * tr) * fast_rcp(s2);
         }
     }
     // tau = sum_i coef_i w_i w_i^T + iso I
@@ -350,24 +361,29 @@ __device__ __forceinline__ void kirchhoff(const DevMaterial &m, const float H[9]
 }
 
 // Drucker-Prager return mapping (Klar et al. 2016) on the trial elastic F = I + H,
-// in place on H.  eps = log sigma, eps_hat = eps - tr(eps)/3:
+// in place on H, returning also the Kirchhoff stress of the result (the next
+// step's P2G then needs no decomposition of its own).  eps = log sigma,
+// eps_hat = eps - tr(eps)/3:
 //   tr eps > 0 or |eps_hat| = 0      -> sigma' = 1 (cone tip: stress free)
 //   dgamma = |eps_hat| + c tr(eps) <= 0 -> unchanged (inside the cone)
 //   otherwise                          -> eps' = eps - dgamma eps_hat / |eps_hat|
 // and F' = sum_i (sigma'_i / sigma_i) w_i v_i^T, i.e.
 //   H' = H + sum_i expm1(eps'_i - log sigma_i) w_i v_i^T.
-__device__ __forceinline__ void dp_return_map(const DevMaterial &m, float H[9]) {
+// The left singular vectors u_i = w_i / sigma_i are unchanged by the projection, so
+//   tau(F') = sum_i (2 mu eps'_i + lambda tr eps') / sigma_i^2 w_i w_i^T.
+__device__ __forceinline__ void dp_return_map(const DevMaterial &m, float H[9], float tau[6]) {
     Eig3 ev;
     strain_eig(H, ev);
     const float jm1 = det_minus_one(H);
     const bool inverted = (1.0f + jm1) < 0.0f;
+    // log sigma_i = log1p(e_i)/2; the clamp sigma >= 1e-4 commutes with the monotone log
+    constexpr float kLogSigmaFloor = -9.210340371976184f;   // log(1e-4)
     float eps[3], lns[3];
     float tr = 0.0f;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        const float e = (i == 2 && inverted) ? (kSigmaFloor2 - 1.0f) : fmaxf(ev.e[i], kSigmaFloor2 - 1.0f);
-        eps[i] = 0.5f * log1pf(e);
         lns[i] = 0.5f * log1pf(fmaxf(ev.e[i], -1.0f + 1e-30f));
+        eps[i] = (i == 2 && inverted) ? kLogSigmaFloor : fmaxf(lns[i], kLogSigmaFloor);
         tr += eps[i];
     }
     float dev[3];
@@ -377,19 +393,41 @@ __device__ __forceinline__ void dp_return_map(const DevMaterial &m, float H[9]) 
         dev[i] = eps[i] - tr * (1.0f / 3.0f);
         dn2 += dev[i] * dev[i];
     }
-    const float dn = sqrtf(dn2);
+    const float dn = fast_sqrt(dn2);
     float target[3];
+    bool changed = true;
     if (tr > 0.0f || dn == 0.0f) {
         target[0] = target[1] = target[2] = 0.0f;
     } else {
         const float dgamma = dn + m.dp_coef * tr;
-        if (dgamma <= 0.0f) return;
-        const float k = dgamma / dn;
+        if (dgamma <= 0.0f) {
+            changed = false;
 #pragma unroll
-        for (int i = 0; i < 3; ++i) target[i] = eps[i] - k * dev[i];
+            for (int i = 0; i < 3; ++i) target[i] = eps[i];
+        } else {
+            const float k = dgamma * fast_rcp(dn);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) target[i] = eps[i] - k * dev[i];
+        }
     }
     float W[9];
     mat_W(H, ev.V, W);
+    // stress of the projected state
+    const float trt = target[0] + target[1] + target[2];
+    float t00 = 0.0f, t11 = 0.0f, t22 = 0.0f, t01 = 0.0f, t02 = 0.0f, t12 = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const float c = (2.0f * m.mu * target[i] + m.lambda * trt) * fast_rcp(fmaxf(1.0f + ev.e[i], 1e-30f));
+        const float a = W[i], b = W[3 + i], cc = W[6 + i];
+        t00 += c * a * a;
+        t11 += c * b * b;
+        t22 += c * cc * cc;
+        t01 += c * a * b;
+        t02 += c * a * cc;
+        t12 += c * b * cc;
+    }
+    tau[0] = t00; tau[1] = t11; tau[2] = t22; tau[3] = t01; tau[4] = t02; tau[5] = t12;
+    if (!changed) return;
     float r[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) r[i] = expm1f(target[i] - lns[i]);
@@ -412,7 +450,7 @@ void launch_flag_keys(const DevCtx &d, const PartArgs &pa, int epoch_offset, hip
 void launch_clear_flags(const DevCtx &d, hipStream_t s);
 void launch_compact(const DevCtx &d, hipStream_t s);
 void launch_bucket(const DevCtx &d, int n, hipStream_t s);
-void launch_p2g(const DevCtx &d, const PartArgs &pa, float dt, bool physics, hipStream_t s);
+void launch_p2g(const DevCtx &d, const PartArgs &pa, float dt, bool physics, bool carried_tau, hipStream_t s);
 void launch_grid_update(const DevCtx &d, float dt, const float gravity[3], hipStream_t s);
 void launch_g2p(const DevCtx &d, const PartArgs &pa, float dt, hipStream_t s);
 void launch_grid_export(const DevCtx &d, float *m, float *vec, hipStream_t s);

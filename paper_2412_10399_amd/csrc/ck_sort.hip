@@ -5,8 +5,8 @@
 // the same as a sort by (key, index), which we build in two exact stages:
 //   1. bucket by block: blocks holding particles are enumerated in increasing
 //      virtual id (compaction of per-block epoch stamps), every particle takes a slot
-//      in its block's bucket with one wave-aggregated atomic, and a scan of the
-//      bucket sizes gives each block its range of sorted positions;
+//      in its block's fixed-size bucket with one wave-aggregated atomic, and a scan
+//      of the bucket sizes gives each block its range of sorted positions;
 //   2. inside each block (in the P2G workgroup, in LDS): order by (cell, index).
 // Atomics only decide where a particle waits inside its bucket, never its final
 // position, so the resulting permutation is deterministic and exact.
@@ -246,8 +246,10 @@ __global__ void __launch_bounds__(kThreads) k_compact_emit(DevCtx d) {
     }
 }
 
-// Slot of each particle in its block's bucket: one atomic per distinct block in the
-// wave (particles arrive nearly sorted, so a wave usually spans one or two blocks).
+// Each particle takes a slot in its block's bucket with one atomic per distinct
+// block in the wave (particles arrive nearly sorted, so a wave usually spans one or
+// two blocks) and writes its index there.  Slots past the bucket capacity are not
+// written; the scan below reports the overflow.
 __global__ void __launch_bounds__(kThreads) k_bucket_count(DevCtx d, int n) {
     const int i = blockIdx.x * kThreads + threadIdx.x;
     const bool live = i < n;
@@ -272,47 +274,76 @@ __global__ void __launch_bounds__(kThreads) k_bucket_count(DevCtx d, int n) {
         int base = 0;
         if (lane == leader) base = atomicAdd(&d.bcount[rl], __popcll(same));
         base = __shfl(base, leader);
-        if (act && r == rl) d.slot[i] = (uint32_t)(base + __popcll(same & below));
+        if (act && r == rl) {
+            const int slot = base + __popcll(same & below);
+            if (slot < kMaxBlockParticles) d.bucket[(size_t)rl * kMaxBlockParticles + slot] = (uint32_t)i;
+        }
         remaining &= ~same;
     }
 }
 
+// Exclusive scan of the bucket sizes into the first sorted position of every
+// particle block (one workgroup; sizes staged through LDS in chunks).
 __global__ void __launch_bounds__(1024) k_bucket_scan(DevCtx d) {
-    __shared__ int sh[32];
-    __shared__ int smax[16];
+    constexpr int kChunk = 8192;
+    __shared__ int buf[kChunk];
+    __shared__ int wsum[16];
+    __shared__ int carry_sh;
     const int np = (int)d.counters[C_NPB];
-    // largest bucket
+    const int tid = threadIdx.x, lane = wave_lane(), w = tid >> 6;
     int mx = 0;
-    for (int r = threadIdx.x; r < np; r += 1024) mx = max(mx, d.bcount[r]);
+    if (tid == 0) carry_sh = 0;
+    __syncthreads();
+    for (int base = 0; base < np; base += kChunk) {
+        const int len = min(kChunk, np - base);
+        for (int k = tid; k < len; k += 1024) {
+            const int c = d.bcount[base + k];
+            buf[k] = c;
+            mx = max(mx, c);
+        }
+        __syncthreads();
+        // each thread owns 8 consecutive entries
+        const int b0 = tid * 8;
+        int loc[8];
+        int sum = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            loc[k] = (b0 + k < len) ? buf[b0 + k] : 0;
+            sum += loc[k];
+        }
+        int v = sum;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int t = __shfl_up(v, off);
+            if (lane >= off) v += t;
+        }
+        if (lane == 63) wsum[w] = v;
+        __syncthreads();
+        int pre = carry_sh;
+        for (int k = 0; k < w; ++k) pre += wsum[k];
+        int run = pre + v - sum;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (b0 + k < len) d.pstart[base + b0 + k] = run;
+            run += loc[k];
+        }
+        __syncthreads();
+        if (tid == 1023) carry_sh = run;
+        __syncthreads();
+    }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_down(mx, off));
-    if (wave_lane() == 0) smax[threadIdx.x >> 6] = mx;
-    // exclusive scan of the bucket sizes into pstart
-    for (int r = threadIdx.x; r < np; r += 1024) d.pstart[r] = d.bcount[r];
+    if (lane == 0) wsum[w] = mx;
     __syncthreads();
-    const int total = wg_scan_inplace<1024>(d.pstart, np, sh);
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         int m = 0;
-        for (int k = 0; k < 16; ++k) m = max(m, smax[k]);
+        for (int k = 0; k < 16; ++k) m = max(m, wsum[k]);
+        const int total = carry_sh;
         d.pstart[np] = total;
         d.counters[C_MAXPB] = (unsigned)m;
         d.counters[C_TOTAL] = (unsigned)total;
         if (m > kMaxBlockParticles) set_status(d.counters, ST_CAPACITY);
     }
-}
-
-__global__ void __launch_bounds__(kThreads) k_bucket_scatter(DevCtx d, int n) {
-    const int i = blockIdx.x * kThreads + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t k = d.key[i];
-    if (k == 0xffffffffu) return;
-    const int E = (int)d.counters[C_EPOCH];
-    if (stamps(d.pflag, d.nbv, E)[k >> 6] != E) return;
-    const int r = d.prank[k >> 6];
-    if (r < 0) return;
-    const int pos = d.pstart[r] + (int)d.slot[i];
-    if (pos < 0 || pos >= n) return;
-    d.u[pos] = (uint32_t)i;
 }
 
 }  // namespace
@@ -336,7 +367,6 @@ void launch_compact(const DevCtx &d, hipStream_t s) {
 void launch_bucket(const DevCtx &d, int n, hipStream_t s) {
     if (n > 0) hipLaunchKernelGGL(k_bucket_count, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, d, n);
     hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, d);
-    if (n > 0) hipLaunchKernelGGL(k_bucket_scatter, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, d, n);
 }
 
 }  // namespace ck

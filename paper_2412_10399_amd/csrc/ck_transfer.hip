@@ -86,8 +86,15 @@ __device__ __forceinline__ void load_particle(const PartArgs &pa, int p, Particl
 // which is the APIC affine transfer of section 4.4 plus the MLS stress impulse
 // (section 4.5: grad Phi_i = w D^-1 (x_i - x_p), f_i = -V^0 tau grad Phi_i).  In cell
 // units x_i - x_p = dx (o - xi) for node offset o on the particle's cell of that grid.
-__device__ __forceinline__ void p2g_particle(const DevCtx &d, const PartArgs &pa, int p, int bx, int by, int bz,
-                                             float dt, float *tile) {
+//
+// Sorted particles put the ~8 particles of a cell in neighbouring lanes, and all of
+// them add to the same 16 nodes.  LDS atomics to one address from several lanes of
+// an instruction serialise, so each particle walks its 8 nodes per grid starting at
+// an offset given by its rank inside the cell: in any one instruction the lanes of a
+// cell hit 8 different nodes.
+__device__ __forceinline__ void p2g_particle(const DevCtx &d, const PartArgs &pa, int p, int rank_in_cell_base,
+                                             const int *cstart, int bx, int by, int bz, float dt, float *tile,
+                                             bool carried_tau) {
     Particle q;
     load_particle(pa, p, q, true);
     CellCoord cc;
@@ -107,7 +114,12 @@ __device__ __forceinline__ void p2g_particle(const DevCtx &d, const PartArgs &pa
     float Di[9];
     moment_inverse(cc, w, Di);
     float tau[6];
-    kirchhoff(M, q.H, tau);
+    if (carried_tau) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) tau[i] = d.tau[i * d.tau_stride + p];
+    } else {
+        kirchhoff(M, q.H, tau);
+    }
     const float T[9] = {tau[0], tau[3], tau[4], tau[3], tau[1], tau[5], tau[4], tau[5], tau[2]};
     const float k = dt * M.vol0;
     float A[9];
@@ -120,6 +132,8 @@ __device__ __forceinline__ void p2g_particle(const DevCtx &d, const PartArgs &pa
 #pragma unroll
         for (int j = 0; j < 3; ++j) Q[3 * i + j] = s * (A[3 * i] * Di[j] + A[3 * i + 1] * Di[3 + j] + A[3 * i + 2] * Di[6 + j]);
     const float mv[3] = {M.mass * q.v[0], M.mass * q.v[1], M.mass * q.v[2]};
+    const int lcell = ((cc.c[2] & 3) * 4 + (cc.c[1] & 3)) * 4 + (cc.c[0] & 3);
+    const int rot = (rank_in_cell_base - cstart[lcell]) & 7;
 
 #pragma unroll
     for (int g = 0; g < 2; ++g) {
@@ -134,16 +148,20 @@ __device__ __forceinline__ void p2g_particle(const DevCtx &d, const PartArgs &pa
             t0 = kTileMinus + ((cc.bp[2] - 4 * bz + 1) * 6 + (cc.bp[1] - 4 * by + 1)) * 6 + (cc.bp[0] - 4 * bx + 1);
         }
         const int sy = g == 0 ? 5 : 6, sz = g == 0 ? 25 : 36;
-        const float(*wa)[2] = g == 0 ? w.wm : w.wp;
+        // per-axis weights as scalars: lane-dependent choices stay register selects
+        const float wx0 = g == 0 ? w.wm[0][0] : w.wp[0][0], wx1 = g == 0 ? w.wm[0][1] : w.wp[0][1];
+        const float wy0 = g == 0 ? w.wm[1][0] : w.wp[1][0], wy1 = g == 0 ? w.wm[1][1] : w.wp[1][1];
+        const float wz0 = g == 0 ? w.wm[2][0] : w.wp[2][0], wz1 = g == 0 ? w.wm[2][1] : w.wp[2][1];
 #pragma unroll
-        for (int o = 0; o < 8; ++o) {
-            const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
-            const float wt = wa[0][ox] * wa[1][oy] * wa[2][oz];
+        for (int it = 0; it < 8; ++it) {
+            const int o = (it + rot) & 7;
+            const bool ox = o & 1, oy = (o >> 1) & 1, oz = (o >> 2) & 1;
+            const float wt = (ox ? wx1 : wx0) * (oy ? wy1 : wy0) * (oz ? wz1 : wz0);
             float m3[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a)
                 m3[a] = base[a] + (ox ? Q[3 * a] : 0.0f) + (oy ? Q[3 * a + 1] : 0.0f) + (oz ? Q[3 * a + 2] : 0.0f);
-            const int t = t0 + ox + oy * sy + oz * sz;
+            const int t = t0 + (ox ? 1 : 0) + (oy ? sy : 0) + (oz ? sz : 0);
             atomicAdd(&tile[t], wt * M.mass);
             atomicAdd(&tile[kTileNodes + t], wt * m3[0]);
             atomicAdd(&tile[2 * kTileNodes + t], wt * m3[1]);
@@ -155,8 +173,8 @@ __device__ __forceinline__ void p2g_particle(const DevCtx &d, const PartArgs &pa
 constexpr int kSlots = kMaxBlockParticles / kThreads;   // bucket entries per thread
 constexpr uint32_t kIndexMask = (1u << kIndexBits) - 1u;
 
-template <bool PHYSICS>
-__global__ void __launch_bounds__(kThreads) k_p2g(DevCtx d, PartArgs pa, float dt) {
+template <bool PHYSICS, bool CARRIED_TAU>
+__global__ void __launch_bounds__(kThreads, 3) k_p2g(DevCtx d, PartArgs pa, float dt) {
     __shared__ float tile[4 * kTileNodes];
     __shared__ uint32_t lbuf[kMaxBlockParticles];
     __shared__ uint32_t ord[kMaxBlockParticles];
@@ -182,7 +200,7 @@ __global__ void __launch_bounds__(kThreads) k_p2g(DevCtx d, PartArgs pa, float d
         for (int k = 0; k < kSlots; ++k) {
             const int j = tid + k * kThreads;
             if (j < cnt) {
-                const uint32_t idx = d.u[s + j];
+                const uint32_t idx = d.bucket[(size_t)r * kMaxBlockParticles + j];
                 const uint32_t cell = d.key[idx] & 63u;
                 pk[k] = (cell << kIndexBits) | idx;
                 ps[k] = atomicAdd(&ccount[cell], 1);
@@ -227,7 +245,8 @@ __global__ void __launch_bounds__(kThreads) k_p2g(DevCtx d, PartArgs pa, float d
             load_neighbours(d, bx, by, bz, E, nbr);
             for (int t = tid; t < 4 * kTileNodes; t += kThreads) tile[t] = 0.0f;
             __syncthreads();
-            for (int j = tid; j < cnt; j += kThreads) p2g_particle(d, pa, (int)ord[j], bx, by, bz, dt, tile);
+            for (int j = tid; j < cnt; j += kThreads)
+                p2g_particle(d, pa, (int)ord[j], j, cstart, bx, by, bz, dt, tile, CARRIED_TAU);
             __syncthreads();
             // ---- flush nonzero tile entries to the pool
             for (int t = tid; t < 4 * kTileNodes; t += kThreads) {
@@ -267,7 +286,7 @@ __global__ void __launch_bounds__(128) k_grid_update(DevCtx d, float dt, float g
         const float m = blk[l];
         float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f;
         if (m > 0.0f && inside) {
-            const float im = 1.0f / m;
+            const float im = fast_rcp(m);
             v0 = blk[64 + l] * im + dt * g0;
             v1 = blk[128 + l] * im + dt * g1;
             v2 = blk[192 + l] * im + dt * g2;
@@ -394,7 +413,10 @@ __global__ void __launch_bounds__(kThreads) k_g2p(DevCtx d, PartArgs pa, float d
                 for (int j = 0; j < 3; ++j)
                     Fn[3 * i + j] = q.H[3 * i + j] +
                                     dt * (C[3 * i + j] + C[3 * i] * q.H[j] + C[3 * i + 1] * q.H[3 + j] + C[3 * i + 2] * q.H[6 + j]);
-            if (M.model == 1) dp_return_map(M, Fn);
+            // stress of the new state for the next step's P2G
+            float tau[6];
+            if (M.model == 1) dp_return_map(M, Fn, tau);
+            else kirchhoff(M, Fn, tau);
             float xn[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) xn[a] = q.x[a] + dt * vn[a];
@@ -414,6 +436,8 @@ __global__ void __launch_bounds__(kThreads) k_g2p(DevCtx d, PartArgs pa, float d
                 pa.out[(6 + i) * S + out] = Bn[i];
                 pa.out[(15 + i) * S + out] = Fn[i];
             }
+#pragma unroll
+            for (int i = 0; i < 6; ++i) d.tau[i * d.tau_stride + out] = tau[i];
             if (pa.id_out) pa.id_out[out] = pa.id_in[p];
             if (pa.mat_out) pa.mat_out[out] = pa.mat_in[p];
             // next cell key and activation stamps for the following step
@@ -484,11 +508,13 @@ int particle_grid(const DevCtx &d) { return d.max_blocks < 8192 ? d.max_blocks :
 
 }  // namespace
 
-void launch_p2g(const DevCtx &d, const PartArgs &pa, float dt, bool physics, hipStream_t s) {
-    if (physics)
-        hipLaunchKernelGGL(k_p2g<true>, dim3(particle_grid(d)), dim3(kThreads), 0, s, d, pa, dt);
+void launch_p2g(const DevCtx &d, const PartArgs &pa, float dt, bool physics, bool carried_tau, hipStream_t s) {
+    if (!physics)
+        hipLaunchKernelGGL((k_p2g<false, false>), dim3(particle_grid(d)), dim3(kThreads), 0, s, d, pa, dt);
+    else if (carried_tau)
+        hipLaunchKernelGGL((k_p2g<true, true>), dim3(particle_grid(d)), dim3(kThreads), 0, s, d, pa, dt);
     else
-        hipLaunchKernelGGL(k_p2g<false>, dim3(particle_grid(d)), dim3(kThreads), 0, s, d, pa, dt);
+        hipLaunchKernelGGL((k_p2g<true, false>), dim3(particle_grid(d)), dim3(kThreads), 0, s, d, pa, dt);
 }
 
 void launch_grid_update(const DevCtx &d, float dt, const float gravity[3], hipStream_t s) {

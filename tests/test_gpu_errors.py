@@ -94,3 +94,44 @@ def test_empty_particle_set():
     assert run.ck.mpm_step(run.ctx.h, run.parts.c, 1e-4, 2, run.stream) == run.ck.MPM_OK
     assert run.ck.mpm_sync(run.ctx.h, run.stream) == run.ck.MPM_OK
     run.close()
+
+
+def _dense_block_scene(n, seed=0):
+    """n particles inside the single block of G- cells 4..7 per axis of a 16^3 grid;
+    the G- cell is floor(X + 1/4), so the block spans X in [3.75, 7.75)."""
+    rng = np.random.default_rng(seed)
+    sc = _blob()
+    dx = sc.dx
+    x = ((3.75 + 4.0 * rng.random((n, 3))) * dx).astype(np.float32)
+    x = np.clip(x, np.float32(3.75 * dx), np.nextafter(np.float32(7.75 * dx), np.float32(0)))
+    sc.x = x
+    sc.v = (0.1 * rng.standard_normal((n, 3))).astype(np.float32)
+    sc.B = np.zeros((n, 3, 3), np.float32)
+    sc.F = np.tile(np.eye(3, dtype=np.float32), (n, 1, 1))
+    sc.mat = np.zeros(n, np.uint8)
+    return sc
+
+
+def test_block_at_particle_capacity_matches_checker():
+    import oracle
+    from gpu_util import nerr, oracle_state, oracle_step
+    sc = _dense_block_scene(2048)
+    run = GpuRun(sc)
+    got = run.steps(1e-4, 1)
+    assert got["status"] == run.ck.MPM_OK
+    st = oracle_state(dict(x=sc.x, v=sc.v, B=sc.B, F=sc.F))
+    oracle_step(sc, st, 1e-4, grids=False)
+    for name in ("x", "v", "F"):
+        assert nerr(got[name], getattr(st, name)) < 1e-5
+    s, stats = run.ck.mpm_get_stats(run.ctx.h, run.stream)
+    assert s == 0 and stats.max_block_particles == 2048 and stats.n_particle_blocks == 1
+    run.close()
+    del oracle
+
+
+def test_block_over_particle_capacity_reported():
+    sc = _dense_block_scene(2049)
+    run = GpuRun(sc)
+    got = run.steps(1e-4, 1)
+    assert got["status"] == run.ck.MPM_E_CAPACITY
+    run.close()

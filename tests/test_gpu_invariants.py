@@ -58,7 +58,10 @@ def test_affine_field_reproduced():
     Bexp = np.einsum("ab,pbc->pac", A, D)
     eB = nerr(got["B"], Bexp)
     log("affine reproduction on the GPU: v %.2e  B %.2e" % (nerr(got["v"], vexp), eB))
-    assert eB < 5e-6
+    # FP32 node velocities of size |v| ~ 1 carry ~1e-7 |v| absolute error, while B
+    # resolves velocity differences of size |A| dx (dx = 1/32) weighted by D ~ 0.1 dx^2:
+    # the relative error of B is of order 1e-7 |v| / (0.1 |A| dx) ~ 3e-5 here.
+    assert eB < 1e-4
     run.close()
 
 
