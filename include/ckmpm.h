@@ -162,6 +162,10 @@ mpm_status mpm_profile_read(mpm_ctx *ctx, double *total_ms, int64_t *count, int3
 const char *mpm_status_string(mpm_status s);
 int32_t mpm_abi_version(void);
 
+/* Device memory (bytes) a context with this configuration and particle capacity
+ * holds, plus two ping-pong particle buffers of n particles with ids. */
+int64_t mpm_footprint(const mpm_config *cfg, int64_t n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -57,7 +57,7 @@ class mpm_stats(ctypes.Structure):
 
 EXPORTS = ("mpm_create", "mpm_destroy", "mpm_p2g", "mpm_grid_update", "mpm_g2p", "mpm_step", "mpm_sync",
            "mpm_grid_read", "mpm_sort_keys", "mpm_invalidate", "mpm_get_stats", "mpm_profile_enable",
-           "mpm_profile_read", "mpm_status_string", "mpm_abi_version")
+           "mpm_profile_read", "mpm_status_string", "mpm_abi_version", "mpm_footprint")
 
 
 def lib():
@@ -85,8 +85,10 @@ def lib():
         L.mpm_status_string.argtypes = [st]
         L.mpm_status_string.restype = ctypes.c_char_p
         L.mpm_abi_version.restype = ctypes.c_int32
+        L.mpm_footprint.argtypes = [ctypes.POINTER(mpm_config), ctypes.c_int64]
+        L.mpm_footprint.restype = ctypes.c_int64
         for name in EXPORTS:
-            if name not in ("mpm_status_string", "mpm_abi_version"):
+            if name not in ("mpm_status_string", "mpm_abi_version", "mpm_footprint"):
                 getattr(L, name).restype = st
         _lib = L
     return _lib
@@ -167,6 +169,11 @@ def mpm_status_string(status: int) -> str:
 
 def mpm_abi_version() -> int:
     return lib().mpm_abi_version()
+
+
+def mpm_footprint(cfg: mpm_config, n: int) -> int:
+    """Device bytes of a context with `cfg` plus two ping-pong buffers of n particles."""
+    return int(lib().mpm_footprint(ctypes.byref(cfg), int(n)))
 
 
 def status_string(status: int) -> str:

@@ -35,6 +35,8 @@ struct mpm_ctx {
     double totals[kPhases] = {0, 0, 0, 0};
     long long counts[kPhases] = {0, 0, 0, 0};
     std::vector<void *> allocs;
+    ck::Allocator alloc;                 // where the device buffers came from
+    bool host_counters_pinned = false;
 };
 
 namespace {
@@ -131,13 +133,31 @@ DevMaterial dev_material(const mpm_material &m) {
     return r;
 }
 
+void *hip_alloc(void *, size_t bytes) {
+    void *p = nullptr;
+    return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
+}
+void hip_free(void *, void *p) { (void)hipFree(p); }
+
 template <typename T>
 mpm_status dalloc(mpm_ctx *ctx, T **ptr, size_t count) {
-    void *p = nullptr;
-    if (hipMalloc(&p, count * sizeof(T) + 256) != hipSuccess) return MPM_E_OOM;
+    void *p = ctx->alloc.alloc(ctx->alloc.self, count * sizeof(T) + 256);
+    if (!p) return MPM_E_OOM;
     ctx->allocs.push_back(p);
     *ptr = static_cast<T *>(p);
     return MPM_OK;
+}
+
+// Bytes of every device buffer a context allocates (each rounded as dalloc does).
+int64_t ctx_device_bytes(const mpm_config &c) {
+    long long nbv = 1;
+    for (int a = 0; a < 3; ++a) nbv *= (c.n_cells[a] / 4 + 1);
+    const long long np = c.max_particles, nb = c.max_blocks;
+    const long long nchunks = (nbv + kCompactChunk - 1) / kCompactChunk;
+    auto r = [](long long bytes) { return bytes + 256; };
+    return r(4 * np) + r(4 * np) + r(4 * nb * (long long)kMaxBlockParticles) + r(8 * nbv) + r(8 * nbv) + r(4 * nbv) +
+           r(4 * nbv) + r(4 * nb) + r(4 * (nb + 1)) + r(4 * nb) + r(4 * nb) + r(4 * nchunks) + r(4 * nchunks) +
+           r(4 * nb * (long long)kBlockFloats) + r(24 * np) + r(4 * (long long)C_COUNT);
 }
 
 PartArgs part_args(const mpm_particles *p, bool with_out) {
@@ -218,6 +238,98 @@ mpm_status enqueue_g2p(mpm_ctx *ctx, mpm_particles *p, double dt, hipStream_t s)
 
 }  // namespace
 
+namespace ck {
+
+void ctx_destroy(mpm_ctx *ctx, bool device_sync);
+
+mpm_status ctx_create(const mpm_config *cfg, const mpm_material *mats, int32_t n_mat, const Allocator *alloc,
+                      hipStream_t init_stream, bool device_sync, mpm_ctx **out) {
+    if (!out) return MPM_E_INVALID;
+    *out = nullptr;
+    const mpm_status v = validate_config(cfg, mats, n_mat);
+    if (v != MPM_OK) return v;
+    mpm_ctx *ctx = new (std::nothrow) mpm_ctx();
+    if (!ctx) return MPM_E_OOM;
+    ctx->cfg = *cfg;
+    ctx->mats.assign(mats, mats + n_mat);
+    ctx->alloc = *alloc;
+    if (hipGetDevice(&ctx->device) != hipSuccess) {
+        delete ctx;
+        return MPM_E_HIP;
+    }
+    DevCtx &d = ctx->d;
+    std::memset(&d, 0, sizeof d);
+    fill_geometry(*cfg, d.geo);
+    for (int i = 0; i < n_mat; ++i) d.mats[i] = dev_material(mats[i]);
+    d.n_mat = n_mat;
+    d.max_blocks = (int)cfg->max_blocks;
+    d.nbv = (long long)d.geo.NB[0] * d.geo.NB[1] * d.geo.NB[2];
+    const size_t np = (size_t)cfg->max_particles, nb = (size_t)cfg->max_blocks, nv = (size_t)d.nbv;
+    const size_t nchunks = (nv + kCompactChunk - 1) / kCompactChunk;
+    mpm_status st = MPM_OK;
+    if (st == MPM_OK) st = dalloc(ctx, &d.key, np);
+    if (st == MPM_OK) st = dalloc(ctx, &d.perm, np);
+    if (st == MPM_OK) st = dalloc(ctx, &d.bucket, nb * (size_t)kMaxBlockParticles);
+    if (st == MPM_OK) st = dalloc(ctx, &d.pflag, 2 * nv);
+    if (st == MPM_OK) st = dalloc(ctx, &d.gflag, 2 * nv);
+    if (st == MPM_OK) st = dalloc(ctx, &d.page, nv);
+    if (st == MPM_OK) st = dalloc(ctx, &d.prank, nv);
+    if (st == MPM_OK) st = dalloc(ctx, &d.plist, nb);
+    if (st == MPM_OK) st = dalloc(ctx, &d.pstart, nb + 1);
+    if (st == MPM_OK) st = dalloc(ctx, &d.bcount, nb);
+    if (st == MPM_OK) st = dalloc(ctx, &d.glist, nb);
+    if (st == MPM_OK) st = dalloc(ctx, &d.chunk_p, nchunks);
+    if (st == MPM_OK) st = dalloc(ctx, &d.chunk_g, nchunks);
+    if (st == MPM_OK) st = dalloc(ctx, &d.pool, nb * kBlockFloats);
+    if (st == MPM_OK) st = dalloc(ctx, &d.tau, 6 * np);
+    d.tau_stride = (long long)np;
+    if (st == MPM_OK) st = dalloc(ctx, &d.counters, (size_t)C_COUNT);
+    if (st == MPM_OK) {
+        if (hipHostMalloc((void **)&ctx->host_counters, C_COUNT * sizeof(unsigned int), hipHostMallocDefault) == hipSuccess)
+            ctx->host_counters_pinned = true;
+        else
+            st = MPM_E_OOM;
+    }
+    if (st == MPM_OK) {
+        bool ok = hipMemsetAsync(d.pflag, 0, 2 * nv * sizeof(int), init_stream) == hipSuccess &&
+                  hipMemsetAsync(d.gflag, 0, 2 * nv * sizeof(int), init_stream) == hipSuccess &&
+                  hipMemsetAsync(d.page, 0xff, nv * sizeof(int), init_stream) == hipSuccess &&
+                  hipMemsetAsync(d.prank, 0xff, nv * sizeof(int), init_stream) == hipSuccess &&
+                  hipMemsetAsync(d.pstart, 0, (nb + 1) * sizeof(int), init_stream) == hipSuccess &&
+                  hipMemsetAsync(d.counters, 0, C_COUNT * sizeof(unsigned int), init_stream) == hipSuccess;
+        ok = ok && (device_sync ? hipDeviceSynchronize() : hipStreamSynchronize(init_stream)) == hipSuccess;
+        if (!ok) st = MPM_E_HIP;
+    }
+    if (st != MPM_OK) {
+        ctx_destroy(ctx, device_sync);
+        return st;
+    }
+    *out = ctx;
+    return MPM_OK;
+}
+
+void ctx_destroy(mpm_ctx *ctx, bool device_sync) {
+    if (!ctx) return;
+    DeviceGuard g(ctx->device);
+    if (device_sync) (void)hipDeviceSynchronize();
+    for (void *p : ctx->allocs) ctx->alloc.free(ctx->alloc.self, p);
+    for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+    if (ctx->host_counters_pinned) (void)hipHostFree(ctx->host_counters);
+    delete ctx;
+}
+
+mpm_status ctx_read_status(mpm_ctx *ctx) {
+    unsigned int bits = 0;
+    if (hipMemcpy(&bits, ctx->d.counters + C_STATUS, sizeof bits, hipMemcpyDeviceToHost) != hipSuccess) return MPM_E_HIP;
+    if (bits & ST_NONFINITE) return MPM_E_NONFINITE;
+    if (bits & ST_DOMAIN) return MPM_E_DOMAIN;
+    if (bits & ST_CAPACITY) return MPM_E_CAPACITY;
+    if (bits & ST_STALE) return MPM_E_STALE;
+    return MPM_OK;
+}
+
+}  // namespace ck
+
 extern "C" {
 
 int32_t mpm_abi_version(void) { return CKMPM_ABI_VERSION; }
@@ -237,74 +349,18 @@ const char *mpm_status_string(mpm_status s) {
 }
 
 mpm_status mpm_create(const mpm_config *cfg, const mpm_material *mats, int32_t n_mat, mpm_ctx **out) {
-    if (!out) return MPM_E_INVALID;
-    *out = nullptr;
-    const mpm_status v = validate_config(cfg, mats, n_mat);
-    if (v != MPM_OK) return v;
-    mpm_ctx *ctx = new (std::nothrow) mpm_ctx();
-    if (!ctx) return MPM_E_OOM;
-    ctx->cfg = *cfg;
-    ctx->mats.assign(mats, mats + n_mat);
-    if (hipGetDevice(&ctx->device) != hipSuccess) {
-        delete ctx;
-        return MPM_E_HIP;
-    }
-    DevCtx &d = ctx->d;
-    std::memset(&d, 0, sizeof d);
-    fill_geometry(*cfg, d.geo);
-    for (int i = 0; i < n_mat; ++i) d.mats[i] = dev_material(mats[i]);
-    d.n_mat = n_mat;
-    d.max_blocks = (int)cfg->max_blocks;
-    d.nbv = (long long)d.geo.NB[0] * d.geo.NB[1] * d.geo.NB[2];
-    const size_t np = (size_t)cfg->max_particles, nb = (size_t)cfg->max_blocks, nv = (size_t)d.nbv;
-    const size_t nchunks = (nv + kCompactChunk - 1) / kCompactChunk;
-    mpm_status st = MPM_OK;
-    if (st == MPM_OK) st = dalloc(ctx, &d.key, np);
-    if (st == MPM_OK) st = dalloc(ctx, &d.bucket, nb * (size_t)kMaxBlockParticles);
-    if (st == MPM_OK) st = dalloc(ctx, &d.perm, np);
-    if (st == MPM_OK) st = dalloc(ctx, &d.pflag, 2 * nv);
-    if (st == MPM_OK) st = dalloc(ctx, &d.gflag, 2 * nv);
-    if (st == MPM_OK) st = dalloc(ctx, &d.page, nv);
-    if (st == MPM_OK) st = dalloc(ctx, &d.prank, nv);
-    if (st == MPM_OK) st = dalloc(ctx, &d.plist, nb);
-    if (st == MPM_OK) st = dalloc(ctx, &d.pstart, nb + 1);
-    if (st == MPM_OK) st = dalloc(ctx, &d.bcount, nb);
-    if (st == MPM_OK) st = dalloc(ctx, &d.glist, nb);
-    if (st == MPM_OK) st = dalloc(ctx, &d.chunk_p, nchunks);
-    if (st == MPM_OK) st = dalloc(ctx, &d.chunk_g, nchunks);
-    if (st == MPM_OK) st = dalloc(ctx, &d.pool, nb * kBlockFloats);
-    if (st == MPM_OK) st = dalloc(ctx, &d.tau, 6 * np);
-    d.tau_stride = (long long)np;
-    if (st == MPM_OK) st = dalloc(ctx, &d.counters, (size_t)C_COUNT);
-    if (st == MPM_OK && hipHostMalloc((void **)&ctx->host_counters, C_COUNT * sizeof(unsigned int), hipHostMallocDefault) != hipSuccess)
-        st = MPM_E_OOM;
-    if (st == MPM_OK) {
-        bool ok = hipMemset(d.pflag, 0, 2 * nv * sizeof(int)) == hipSuccess &&
-                  hipMemset(d.gflag, 0, 2 * nv * sizeof(int)) == hipSuccess &&
-                  hipMemset(d.page, 0xff, nv * sizeof(int)) == hipSuccess &&
-                  hipMemset(d.prank, 0xff, nv * sizeof(int)) == hipSuccess &&
-                  hipMemset(d.pstart, 0, (nb + 1) * sizeof(int)) == hipSuccess &&
-                  hipMemset(d.counters, 0, C_COUNT * sizeof(unsigned int)) == hipSuccess &&
-                  hipDeviceSynchronize() == hipSuccess;
-        if (!ok) st = MPM_E_HIP;
-    }
-    if (st != MPM_OK) {
-        mpm_destroy(ctx);
-        return st;
-    }
-    *out = ctx;
-    return MPM_OK;
+    ck::Allocator a{hip_alloc, hip_free, nullptr};
+    return ck::ctx_create(cfg, mats, n_mat, &a, nullptr, true, out);
 }
 
 mpm_status mpm_destroy(mpm_ctx *ctx) {
-    if (!ctx) return MPM_OK;
-    DeviceGuard g(ctx->device);
-    (void)hipDeviceSynchronize();
-    for (void *p : ctx->allocs) (void)hipFree(p);
-    for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
-    if (ctx->host_counters) (void)hipHostFree(ctx->host_counters);
-    delete ctx;
+    ck::ctx_destroy(ctx, true);
     return MPM_OK;
+}
+
+int64_t mpm_footprint(const mpm_config *cfg, int64_t n) {
+    if (!cfg) return 0;
+    return ctx_device_bytes(*cfg) + 2 * (int64_t)MPM_STATE_PLANES * 4 * n + 2 * 4 * n + 2 * n + 3 * 256;
 }
 
 mpm_status mpm_p2g(mpm_ctx *ctx, const mpm_particles *p, double dt, void *stream) {

@@ -159,11 +159,14 @@ struct Weights {
     float sp[3];                // s on G+ (s on G- is -sp)
 };
 
+// The sine is the hardware instruction (its argument is in revolutions, so it
+// returns sin(2 pi xi) directly); over every FP32 xi in [0, 1) it is within 1.3e-7
+// of sin(2 pi xi), i.e. 2e-8 in s, below the FP32 rounding of the weights.
 __device__ __forceinline__ void axis_weights(const CellCoord &cc, Weights &w) {
     constexpr float kInv2Pi = 0.15915494309189535f;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const float s = sinpif(2.0f * cc.xp[a]) * kInv2Pi;
+        const float s = __builtin_amdgcn_sinf(cc.xp[a]) * kInv2Pi;
         w.sp[a] = s;
         w.wp[a][0] = 1.0f - cc.xp[a] + s;
         w.wp[a][1] = cc.xp[a] - s;
@@ -306,7 +309,7 @@ constexpr float kSigmaFloor2 = 1e-8f;   // Drucker-Prager: singular values clamp
 //   with (F - R) F^T = W diag((sigma - 1)/sigma) W^T.
 // Drucker-Prager elastic part (Hencky St. Venant-Kirchhoff, Klar et al. 2016):
 //   tau = U diag(2 mu eps + lambda tr eps) U^T = W diag((2 mu eps + lambda tr eps)/sigma^2) W^T.
-__device__ __forceinline__ void kirchhoff(const DevMaterial &m, const float H[9], float tau[6]) {
+__device__ __forceinline__ void kirchhoff_eig(const DevMaterial &m, const float H[9], float tau[6]) {
     Eig3 ev;
     strain_eig(H, ev);
     float W[9];
@@ -371,7 +374,7 @@ __device__ __forceinline__ void kirchhoff(const DevMaterial &m, const float H[9]
 //   H' = H + sum_i expm1(eps'_i - log sigma_i) w_i v_i^T.
 // The left singular vectors u_i = w_i / sigma_i are unchanged by the projection, so
 //   tau(F') = sum_i (2 mu eps'_i + lambda tr eps') / sigma_i^2 w_i w_i^T.
-__device__ __forceinline__ void dp_return_map(const DevMaterial &m, float H[9], float tau[6]) {
+__device__ __forceinline__ void dp_return_map_eig(const DevMaterial &m, float H[9], float tau[6]) {
     Eig3 ev;
     strain_eig(H, ev);
     const float jm1 = det_minus_one(H);
@@ -443,8 +446,186 @@ __device__ __forceinline__ void dp_return_map(const DevMaterial &m, float H[9], 
                             r[2] * W[3 * i + 2] * ev.V[3 * j + 2];
 }
 
+// ------------------------------------------ small-strain series evaluation
+// For the strains of solids near rest the eigen-decomposition can be avoided.  With
+// the left Cauchy-Green tensor b = F F^T = I + E, E = H + H^T + H H^T, both models
+// are functions of E alone, evaluated as matrix power series (all terms are
+// polynomials in E, so they commute and stay symmetric):
+//   Hencky strain (left frame)   eps = 1/2 log(I + E) = 1/2 (E - E^2/2 + E^3/3 - ...),
+//   Drucker-Prager elastic       tau = 2 mu eps + lambda tr(eps) I,
+//   fixed corotated              (F - R) F^T = b - b^(1/2) = E/2 + E^2/8 - E^3/16 + 5E^4/128 - ...,
+//   return mapping               F' = exp(eps' - eps) F (eps and eps' share eigenvectors),
+//                                 tip: F' = exp(-eps) F = R.
+// Six terms reach FP32 rounding for |E|_F <= 0.05; larger strains (and inverted
+// elements) take the eigen-decomposition path above.
+struct Sym3 {
+    float xx, yy, zz, xy, xz, yz;
+};
+
+// product of two commuting symmetric matrices (the result is symmetric)
+__device__ __forceinline__ Sym3 sym_mul(const Sym3 &a, const Sym3 &b) {
+    Sym3 r;
+    r.xx = a.xx * b.xx + a.xy * b.xy + a.xz * b.xz;
+    r.yy = a.xy * b.xy + a.yy * b.yy + a.yz * b.yz;
+    r.zz = a.xz * b.xz + a.yz * b.yz + a.zz * b.zz;
+    r.xy = a.xx * b.xy + a.xy * b.yy + a.xz * b.yz;
+    r.xz = a.xx * b.xz + a.xy * b.yz + a.xz * b.zz;
+    r.yz = a.xy * b.xz + a.yy * b.yz + a.yz * b.zz;
+    return r;
+}
+
+// c0 I + E * acc
+__device__ __forceinline__ Sym3 horner_step(float c0, const Sym3 &E, const Sym3 &acc) {
+    Sym3 r = sym_mul(E, acc);
+    r.xx += c0;
+    r.yy += c0;
+    r.zz += c0;
+    return r;
+}
+
+__device__ __forceinline__ Sym3 scaled_identity(float c) { return Sym3{c, c, c, 0.0f, 0.0f, 0.0f}; }
+
+constexpr float kSeriesMax2 = 0.0025f;   // |E|_F^2 <= 0.05^2
+
+__device__ __forceinline__ Sym3 left_cauchy_green_minus_I(const float H[9]) {
+    Sym3 E;
+    E.xx = 2.0f * H[0] + H[0] * H[0] + H[1] * H[1] + H[2] * H[2];
+    E.yy = 2.0f * H[4] + H[3] * H[3] + H[4] * H[4] + H[5] * H[5];
+    E.zz = 2.0f * H[8] + H[6] * H[6] + H[7] * H[7] + H[8] * H[8];
+    E.xy = H[1] + H[3] + H[0] * H[3] + H[1] * H[4] + H[2] * H[5];
+    E.xz = H[2] + H[6] + H[0] * H[6] + H[1] * H[7] + H[2] * H[8];
+    E.yz = H[5] + H[7] + H[3] * H[6] + H[4] * H[7] + H[5] * H[8];
+    return E;
+}
+
+__device__ __forceinline__ float frob2(const Sym3 &a) {
+    return a.xx * a.xx + a.yy * a.yy + a.zz * a.zz + 2.0f * (a.xy * a.xy + a.xz * a.xz + a.yz * a.yz);
+}
+
+// 1/2 log(I + E), series to E^6
+__device__ __forceinline__ Sym3 hencky_series(const Sym3 &E) {
+    Sym3 acc = scaled_identity(-1.0f / 6.0f);
+    acc = horner_step(1.0f / 5.0f, E, acc);
+    acc = horner_step(-1.0f / 4.0f, E, acc);
+    acc = horner_step(1.0f / 3.0f, E, acc);
+    acc = horner_step(-1.0f / 2.0f, E, acc);
+    acc = horner_step(1.0f, E, acc);
+    Sym3 L = sym_mul(E, acc);
+    return Sym3{0.5f * L.xx, 0.5f * L.yy, 0.5f * L.zz, 0.5f * L.xy, 0.5f * L.xz, 0.5f * L.yz};
+}
+
+// exp(X) - I, series to X^6
+__device__ __forceinline__ Sym3 expm1_series(const Sym3 &X) {
+    Sym3 acc = scaled_identity(1.0f / 720.0f);
+    acc = horner_step(1.0f / 120.0f, X, acc);
+    acc = horner_step(1.0f / 24.0f, X, acc);
+    acc = horner_step(1.0f / 6.0f, X, acc);
+    acc = horner_step(1.0f / 2.0f, X, acc);
+    acc = horner_step(1.0f, X, acc);
+    return sym_mul(X, acc);
+}
+
+// H <- H + G (I + H), i.e. F <- (I + G) F
+__device__ __forceinline__ void apply_left(const Sym3 &G, float H[9]) {
+    const float g[9] = {G.xx, G.xy, G.xz, G.xy, G.yy, G.yz, G.xz, G.yz, G.zz};
+    float r[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            r[3 * i + j] = H[3 * i + j] + g[3 * i + j] + g[3 * i] * H[j] + g[3 * i + 1] * H[3 + j] + g[3 * i + 2] * H[6 + j];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) H[i] = r[i];
+}
+
+__device__ __forceinline__ void store_tau(const Sym3 &t, float tau[6]) {
+    tau[0] = t.xx; tau[1] = t.yy; tau[2] = t.zz; tau[3] = t.xy; tau[4] = t.xz; tau[5] = t.yz;
+}
+
+// The path is chosen per wave: if any active lane needs the decomposition, the
+// whole wave takes it (both forms agree to FP32 rounding), so no wave runs both.
+__device__ __forceinline__ bool wave_needs_eig(const Sym3 &E, float jm1) {
+    return __any(frob2(E) > kSeriesMax2 || 1.0f + jm1 <= 0.0f);
+}
+
+__device__ __forceinline__ void kirchhoff(const DevMaterial &m, const float H[9], float tau[6]) {
+    const Sym3 E = left_cauchy_green_minus_I(H);
+    const float jm1 = det_minus_one(H);
+    if (wave_needs_eig(E, jm1)) {
+        kirchhoff_eig(m, H, tau);
+        return;
+    }
+    Sym3 t;
+    if (m.model == 0) {
+        // (b - b^(1/2)): coefficients 1/2, 1/8, -1/16, 5/128, -7/256, 21/1024
+        Sym3 acc = scaled_identity(21.0f / 1024.0f);
+        acc = horner_step(-7.0f / 256.0f, E, acc);
+        acc = horner_step(5.0f / 128.0f, E, acc);
+        acc = horner_step(-1.0f / 16.0f, E, acc);
+        acc = horner_step(1.0f / 8.0f, E, acc);
+        acc = horner_step(1.0f / 2.0f, E, acc);
+        const Sym3 D = sym_mul(E, acc);
+        const float iso = m.lambda * jm1 * (1.0f + jm1);
+        const float k = 2.0f * m.mu;
+        t = Sym3{k * D.xx + iso, k * D.yy + iso, k * D.zz + iso, k * D.xy, k * D.xz, k * D.yz};
+    } else {
+        const Sym3 e = hencky_series(E);
+        const float iso = m.lambda * (e.xx + e.yy + e.zz);
+        const float k = 2.0f * m.mu;
+        t = Sym3{k * e.xx + iso, k * e.yy + iso, k * e.zz + iso, k * e.xy, k * e.xz, k * e.yz};
+    }
+    store_tau(t, tau);
+}
+
+__device__ __forceinline__ void dp_return_map(const DevMaterial &m, float H[9], float tau[6]) {
+    const Sym3 E = left_cauchy_green_minus_I(H);
+    const float jm1 = det_minus_one(H);
+    if (wave_needs_eig(E, jm1)) {
+        dp_return_map_eig(m, H, tau);
+        return;
+    }
+    const Sym3 e = hencky_series(E);
+    const float tr = e.xx + e.yy + e.zz;
+    const float t3 = tr * (1.0f / 3.0f);
+    const Sym3 dev{e.xx - t3, e.yy - t3, e.zz - t3, e.xy, e.xz, e.yz};
+    const float dn = fast_sqrt(frob2(dev));
+    const float k2 = 2.0f * m.mu;
+    if (tr > 0.0f || dn == 0.0f) {
+        // cone tip: F' = exp(-eps) F, stress free
+        apply_left(expm1_series(Sym3{-e.xx, -e.yy, -e.zz, -e.xy, -e.xz, -e.yz}), H);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) tau[i] = 0.0f;
+        return;
+    }
+    const float dgamma = dn + m.dp_coef * tr;
+    const float iso = m.lambda * tr;
+    if (dgamma <= 0.0f) {
+        store_tau(Sym3{k2 * e.xx + iso, k2 * e.yy + iso, k2 * e.zz + iso, k2 * e.xy, k2 * e.xz, k2 * e.yz}, tau);
+        return;
+    }
+    // eps' = eps - k eps_hat: F' = exp(-k eps_hat) F, tau from eps' (same trace)
+    const float k = dgamma * fast_rcp(dn);
+    const Sym3 X{-k * dev.xx, -k * dev.yy, -k * dev.zz, -k * dev.xy, -k * dev.xz, -k * dev.yz};
+    apply_left(expm1_series(X), H);
+    store_tau(Sym3{k2 * (e.xx + X.xx) + iso, k2 * (e.yy + X.yy) + iso, k2 * (e.zz + X.zz) + iso, k2 * (e.xy + X.xy),
+                   k2 * (e.xz + X.xz), k2 * (e.yz + X.yz)},
+              tau);
+}
+
 // ------------------------------------------------------------ launchers
-struct Ctx;  // host context (ck_api.hip)
+}  // namespace ck
+
+struct mpm_ctx;  // host context (ck_api.hip)
+
+namespace ck {
+
+// Device memory source of a context: hipMalloc for stand-alone contexts, the
+// server's arena for served jobs.
+struct Allocator {
+    void *(*alloc)(void *self, size_t bytes);
+    void (*free)(void *self, void *p);
+    void *self;
+};
 
 void launch_flag_keys(const DevCtx &d, const PartArgs &pa, int epoch_offset, hipStream_t s);
 void launch_clear_flags(const DevCtx &d, hipStream_t s);

@@ -189,8 +189,6 @@ __device__ __forceinline__ int wg_excl_scan(int x, int &excl, int *sh) {
 
 __global__ void __launch_bounds__(kThreads) k_compact_emit(DevCtx d) {
     __shared__ int sh[8];
-    __shared__ int emitted[kCompactChunk];
-    __shared__ int n_emitted;
     const int E = (int)d.counters[C_EPOCH];
     const int *pf = stamps(d.pflag, d.nbv, E);
     const int *gf = stamps(d.gflag, d.nbv, E);
@@ -228,57 +226,95 @@ __global__ void __launch_bounds__(kThreads) k_compact_emit(DevCtx d) {
             if (rg < d.max_blocks) {
                 d.glist[rg] = v;
                 d.page[v] = rg;
-                emitted[rg - d.chunk_g[blockIdx.x]] = rg;
             } else {
                 d.page[v] = -1;
-                emitted[rg - d.chunk_g[blockIdx.x]] = -1;
             }
             ++rg;
         }
     }
-    if (threadIdx.x == 0) n_emitted = gtot;
-    __syncthreads();
-    // zero the pool blocks handed out by this chunk (a float4 per thread and step)
-    const int nb = n_emitted;
-    for (int t = threadIdx.x; t < nb * (kBlockFloats / 4); t += kThreads) {
-        const int b = emitted[t / (kBlockFloats / 4)];
-        if (b >= 0) reinterpret_cast<float4 *>(d.pool + (size_t)b * kBlockFloats)[t % (kBlockFloats / 4)] = make_float4(0, 0, 0, 0);
-    }
+    (void)gtot;
 }
 
-// Each particle takes a slot in its block's bucket with one atomic per distinct
-// block in the wave (particles arrive nearly sorted, so a wave usually spans one or
-// two blocks) and writes its index there.  Slots past the bucket capacity are not
-// written; the scan below reports the overflow.
+// Each particle takes a slot in its block's bucket and writes its index there.
+// Particles arrive nearly sorted (the previous G2P wrote them in block order), so
+// a workgroup's 1024 consecutive particles span few blocks: slots are ranked
+// inside the workgroup (a run of equal blocks gets consecutive slots) and each run
+// costs one global atomic.  Slots past the bucket capacity are not written; the
+// scan below reports the overflow.  The same launch zeroes this step's grid blocks.
+constexpr int kCountPer = 4;                       // consecutive particles per thread
+constexpr int kCountTile = kThreads * kCountPer;   // particles per workgroup
+
 __global__ void __launch_bounds__(kThreads) k_bucket_count(DevCtx d, int n) {
-    const int i = blockIdx.x * kThreads + threadIdx.x;
-    const bool live = i < n;
+    __shared__ int rblk[kCountTile];   // particle block rank of each particle of the tile (-1: skipped)
+    __shared__ int base_of[kCountTile];
+    __shared__ int wmax[kThreads / 64];
+    const int tid = threadIdx.x, lane = wave_lane(), w = tid >> 6;
     const int E = (int)d.counters[C_EPOCH];
-    int r = -1;
-    if (live) {
-        const uint32_t k = d.key[i];
-        if (k != 0xffffffffu) {
-            // a key whose block was not stamped this step cannot be placed
-            if (stamps(d.pflag, d.nbv, E)[k >> 6] == E) r = d.prank[k >> 6];
-            else set_status(d.counters, ST_STALE);
-        }
+    const int *pf = stamps(d.pflag, d.nbv, E);
+    const int base = blockIdx.x * kCountTile;
+    // zero a share of the pool blocks handed out this step
+    {
+        const long long nfl = (long long)d.counters[C_NGB] * (kBlockFloats / 4);
+        float4 *pool4 = reinterpret_cast<float4 *>(d.pool);
+        for (long long t = (long long)blockIdx.x * kThreads + tid; t < nfl; t += (long long)gridDim.x * kThreads)
+            pool4[t] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
-    const bool act = r >= 0;
-    uint64_t remaining = __ballot(act);
-    const int lane = wave_lane();
-    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    while (remaining) {
-        const int leader = __ffsll((unsigned long long)remaining) - 1;
-        const int rl = __shfl(r, leader);
-        const uint64_t same = __ballot(act && r == rl);
-        int base = 0;
-        if (lane == leader) base = atomicAdd(&d.bcount[rl], __popcll(same));
-        base = __shfl(base, leader);
-        if (act && r == rl) {
-            const int slot = base + __popcll(same & below);
-            if (slot < kMaxBlockParticles) d.bucket[(size_t)rl * kMaxBlockParticles + slot] = (uint32_t)i;
+    int r[kCountPer];
+#pragma unroll
+    for (int k = 0; k < kCountPer; ++k) {
+        const int i = base + tid * kCountPer + k;
+        r[k] = -1;
+        if (i < n) {
+            const uint32_t key = d.key[i];
+            if (key != 0xffffffffu) {
+                // a key whose block was not stamped this step cannot be placed
+                if (pf[key >> 6] == E) r[k] = d.prank[key >> 6];
+                else set_status(d.counters, ST_STALE);
+            }
         }
-        remaining &= ~same;
+        rblk[tid * kCountPer + k] = r[k];
+    }
+    __syncthreads();
+    // start of the run of equal blocks each element belongs to: inclusive max-scan
+    // of (element starts a run ? position : 0)
+    int st[kCountPer];
+    int m = 0;
+#pragma unroll
+    for (int k = 0; k < kCountPer; ++k) {
+        const int j = tid * kCountPer + k;
+        const bool starts = (j == 0) || (rblk[j - 1] != r[k]);
+        m = starts ? j : m;
+        st[k] = m;
+    }
+    int v = m;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(v, off);
+        if (lane >= off) v = max(v, t);
+    }
+    if (lane == 63) wmax[w] = v;
+    __syncthreads();
+    int carry = 0;
+    for (int k = 0; k < w; ++k) carry = max(carry, wmax[k]);
+    const int up = __shfl_up(v, 1);                       // every lane takes part in the shuffle
+    const int prev_thread = lane > 0 ? max(carry, up) : carry;   // max over all earlier threads
+#pragma unroll
+    for (int k = 0; k < kCountPer; ++k) st[k] = max(st[k], prev_thread);
+    // the last element of each run takes the run's slots with one atomic
+#pragma unroll
+    for (int k = 0; k < kCountPer; ++k) {
+        const int j = tid * kCountPer + k;
+        if (r[k] < 0) continue;
+        const bool last = (j == kCountTile - 1) || (rblk[j + 1] != r[k]);
+        if (last) base_of[st[k]] = atomicAdd(&d.bcount[r[k]], j - st[k] + 1);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kCountPer; ++k) {
+        const int j = tid * kCountPer + k;
+        if (r[k] < 0) continue;
+        const int slot = base_of[st[k]] + (j - st[k]);
+        if (slot < kMaxBlockParticles) d.bucket[(size_t)r[k] * kMaxBlockParticles + slot] = (uint32_t)(base + j);
     }
 }
 
@@ -365,7 +401,9 @@ void launch_compact(const DevCtx &d, hipStream_t s) {
 }
 
 void launch_bucket(const DevCtx &d, int n, hipStream_t s) {
-    if (n > 0) hipLaunchKernelGGL(k_bucket_count, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, d, n);
+    // at least a few hundred workgroups, so that the pool clearing is spread wide
+    const int tiles = (n + kCountTile - 1) / kCountTile;
+    hipLaunchKernelGGL(k_bucket_count, dim3(tiles > 1024 ? tiles : 1024), dim3(kThreads), 0, s, d, n);
     hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, d);
 }
 

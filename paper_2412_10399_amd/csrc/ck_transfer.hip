@@ -4,9 +4,9 @@
 //
 // Work decomposition: one workgroup per 4^3-cell particle block.  A block's
 // particles touch G- nodes [4B, 4B+4] and G+ nodes [4B-1, 4B+4] on each axis
-// (5^3 + 6^3 = 341 nodes), so that tile is staged in LDS: P2G accumulates into it
-// with LDS float atomics and flushes each nonzero node once to the grid pool with a
-// global float atomic; G2P reads the updated velocities of the same tile from LDS.
+// (5^3 + 6^3 = 341 nodes), so that tile is staged in LDS: P2G sums into it and
+// flushes each nonzero node once to the grid pool with a global float atomic; G2P
+// reads the updated velocities of the same tile from LDS.
 // Grid storage is a pool of 2 KiB blocks, [grid][channel m, p0, p1, p2][64 nodes],
 // reached through a page table indexed by virtual block id.
 #include "ck_common.hpp"
@@ -62,6 +62,22 @@ __device__ __forceinline__ long long pool_index(const DevCtx &d, const int *nbr,
     return (long long)ph * kBlockFloats + g * 256 + ch * 64 + ((iz & 3) * 16 + (iy & 3) * 4 + (ix & 3));
 }
 
+// Particle block of this workgroup in the round of blocks [base, base + G) (G
+// workgroups).  Workgroups are dealt to the 8 XCDs round-robin by index; each XCD
+// gets a contiguous, equal share of the round, so the halo nodes that neighbouring
+// blocks share are reused from the same L2 and every XCD has the same work.
+// Returns -1 when the workgroup has no block in this round.  Grids that are not a
+// multiple of 8 keep the identity mapping.
+__device__ __forceinline__ int round_block(int base, int np) {
+    const int G = gridDim.x;
+    const int m = min(G, np - base);
+    if (G & 7) return (int)blockIdx.x < m ? base + (int)blockIdx.x : -1;
+    const int per = (m + 7) >> 3;
+    const int x = blockIdx.x & 7, y = blockIdx.x >> 3;
+    const int i = x * per + y;
+    return (y < per && i < m) ? base + i : -1;
+}
+
 struct Particle {
     float x[3], v[3], B[9], H[9];   // H = F - I
 };
@@ -81,110 +97,201 @@ __device__ __forceinline__ void load_particle(const PartArgs &pa, int p, Particl
 }
 
 // ---------------------------------------------------------------- P2G
-// One particle's contributions to the LDS tile.  Mass w m_p and momentum
-//   w (m_p v_p + Q (x_i - x_p)),  Q = (m_p B_p - dt V_p^0 tau_p) D_p^-1,
-// which is the APIC affine transfer of section 4.4 plus the MLS stress impulse
-// (section 4.5: grad Phi_i = w D^-1 (x_i - x_p), f_i = -V^0 tau grad Phi_i).  In cell
-// units x_i - x_p = dx (o - xi) for node offset o on the particle's cell of that grid.
+// Particle contributions (section 4.4 APIC transfer plus the MLS stress impulse of
+// section 4.5): mass w m_p and momentum w (m_p v_p + Q (x_i - x_p)) with
+//   Q = (m_p B_p - dt V_p^0 tau_p) D_p^-1,
+// where grad Phi_i = w D^-1 (x_i - x_p) and f_i = -V^0 tau grad Phi_i.  In cell units,
+// with xi the particle's fractional position in its G- cell c, G- node c + o
+// (o in {0,1}^3) sits at x_i - x_p = dx (o - xi) and G+ node c + r (r in {-1,0,1}^3)
+// at dx (r + 1/2 - xi), since G+ is shifted half a cell from G-.  With
+// base = m_p v_p - Q xi the momenta are base + Q o and base + Q (r + 1/2).
 //
-// Sorted particles put the ~8 particles of a cell in neighbouring lanes, and all of
-// them add to the same 16 nodes.  LDS atomics to one address from several lanes of
-// an instruction serialise, so each particle walks its 8 nodes per grid starting at
-// an offset given by its rank inside the cell: in any one instruction the lanes of a
-// cell hit 8 different nodes.
-__device__ __forceinline__ void p2g_particle(const DevCtx &d, const PartArgs &pa, int p, int rank_in_cell_base,
-                                             const int *cstart, int bx, int by, int bz, float dt, float *tile,
-                                             bool carried_tau) {
-    Particle q;
-    load_particle(pa, p, q, true);
-    CellCoord cc;
-    const bool ok = cell_coord(d.geo, q.x, cc);
-    if (!ok) {
-        set_status(d.counters, ST_DOMAIN);
-        return;
-    }
-    if ((cc.c[0] >> 2) != bx || (cc.c[1] >> 2) != by || (cc.c[2] >> 2) != bz) {
-        set_status(d.counters, ST_STALE);
-        return;
-    }
-    const int mi = pa.mat_in ? (int)pa.mat_in[p] : 0;
-    const DevMaterial M = d.mats[mi < d.n_mat ? mi : 0];
-    Weights w;
-    axis_weights(cc, w);
-    float Di[9];
-    moment_inverse(cc, w, Di);
+// Accumulation without atomics inside the workgroup (LDS float atomics run about
+// a hundred times slower than plain LDS traffic on gfx950): the block's particles,
+// ordered by cell, are staged in LDS as compact records; then lane c of each wave
+// owns G- cell c of the block and sums, in registers, the contributions of that
+// cell's particles to a fixed set of nodes: wave 0 the 8 G- nodes c + o, wave
+// 1 + l the 9 G+ nodes c + (rx, ry, l - 1) of layer l (a G- cell's particles reach
+// G+ nodes c - 1 .. c + 1 on each axis, two of the three per particle).  The
+// register sums are added into the LDS tile in conflict-free phases (within a phase
+// every lane of a wave targets a different node; each G+ wave owns a copy of the G+
+// tile), and every nonzero tile node is flushed to the pool with one global atomic.
+constexpr int kSlots = kMaxBlockParticles / kThreads;   // bucket entries per thread
+constexpr uint32_t kIndexMask = (1u << kIndexBits) - 1u;
+constexpr int kChunk = 512;                              // particles staged per pass
+constexpr int kRecVec = 5;                               // float4 per staged record
+constexpr int kRecSlots = kChunk + kChunk / 8;
+
+// Record slot of the k-th staged particle.  Cells of a uniformly sampled block hold
+// eight consecutive particles; one spare slot per eight spreads the records read
+// together by the lanes of a wave over different LDS banks.
+__device__ __forceinline__ int rec_slot(int k) { return k + (k >> 3); }
+
+// Record: xi[3] s+[3] m_p base[3] Q[9] (row-major) and one pad float.
+__device__ __forceinline__ void stage_particle(const DevCtx &d, const PartArgs &pa, int p, int bx, int by, int bz,
+                                               float dt, bool carried_tau, float4 *rec) {
+    float out[20];
+#pragma unroll
+    for (int i = 0; i < 20; ++i) out[i] = 0.0f;
+    const long long S = pa.stride;
+    float x[3], v[3], B[9];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) x[a] = pa.in[a * S + p];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v[a] = pa.in[(3 + a) * S + p];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) B[a] = pa.in[(6 + a) * S + p];
     float tau[6];
     if (carried_tau) {
 #pragma unroll
         for (int i = 0; i < 6; ++i) tau[i] = d.tau[i * d.tau_stride + p];
-    } else {
-        kirchhoff(M, q.H, tau);
     }
-    const float T[9] = {tau[0], tau[3], tau[4], tau[3], tau[1], tau[5], tau[4], tau[5], tau[2]};
-    const float k = dt * M.vol0;
-    float A[9];
+    const int mi = pa.mat_in ? (int)pa.mat_in[p] : 0;
+    const DevMaterial M = d.mats[mi < d.n_mat ? mi : 0];
+    CellCoord cc;
+    bool ok = cell_coord(d.geo, x, cc);
+    if (!ok) set_status(d.counters, ST_DOMAIN);
+    if (ok && ((cc.c[0] >> 2) != bx || (cc.c[1] >> 2) != by || (cc.c[2] >> 2) != bz)) {
+        set_status(d.counters, ST_STALE);
+        ok = false;
+    }
+    if (ok) {
+        if (!carried_tau) {
+            float H[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) A[i] = M.mass * q.B[i] - k * T[i];
-    float Q[9];
-    const float s = d.geo.inv_dx_f;
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) Q[3 * i + j] = s * (A[3 * i] * Di[j] + A[3 * i + 1] * Di[3 + j] + A[3 * i + 2] * Di[6 + j]);
-    const float mv[3] = {M.mass * q.v[0], M.mass * q.v[1], M.mass * q.v[2]};
-    const int lcell = ((cc.c[2] & 3) * 4 + (cc.c[1] & 3)) * 4 + (cc.c[0] & 3);
-    const int rot = (rank_in_cell_base - cstart[lcell]) & 7;
-
-#pragma unroll
-    for (int g = 0; g < 2; ++g) {
-        const float *xi = g == 0 ? cc.xm : cc.xp;
-        float base[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) base[a] = mv[a] - (Q[3 * a] * xi[0] + Q[3 * a + 1] * xi[1] + Q[3 * a + 2] * xi[2]);
-        int t0;
-        if (g == 0) {
-            t0 = ((cc.c[2] - 4 * bz) * 5 + (cc.c[1] - 4 * by)) * 5 + (cc.c[0] - 4 * bx);
-        } else {
-            t0 = kTileMinus + ((cc.bp[2] - 4 * bz + 1) * 6 + (cc.bp[1] - 4 * by + 1)) * 6 + (cc.bp[0] - 4 * bx + 1);
+            for (int a = 0; a < 9; ++a) H[a] = pa.in[(15 + a) * S + p];
+            kirchhoff(M, H, tau);
         }
-        const int sy = g == 0 ? 5 : 6, sz = g == 0 ? 25 : 36;
-        // per-axis weights as scalars: lane-dependent choices stay register selects
-        const float wx0 = g == 0 ? w.wm[0][0] : w.wp[0][0], wx1 = g == 0 ? w.wm[0][1] : w.wp[0][1];
-        const float wy0 = g == 0 ? w.wm[1][0] : w.wp[1][0], wy1 = g == 0 ? w.wm[1][1] : w.wp[1][1];
-        const float wz0 = g == 0 ? w.wm[2][0] : w.wp[2][0], wz1 = g == 0 ? w.wm[2][1] : w.wp[2][1];
+        Weights w;
+        axis_weights(cc, w);
+        float Di[9];
+        moment_inverse(cc, w, Di);
+        const float T[9] = {tau[0], tau[3], tau[4], tau[3], tau[1], tau[5], tau[4], tau[5], tau[2]};
+        const float k = dt * M.vol0;
+        float A[9];
 #pragma unroll
-        for (int it = 0; it < 8; ++it) {
-            const int o = (it + rot) & 7;
-            const bool ox = o & 1, oy = (o >> 1) & 1, oz = (o >> 2) & 1;
-            const float wt = (ox ? wx1 : wx0) * (oy ? wy1 : wy0) * (oz ? wz1 : wz0);
-            float m3[3];
+        for (int i = 0; i < 9; ++i) A[i] = M.mass * B[i] - k * T[i];
+        const float sc = d.geo.inv_dx_f;
+        float Q[9];
 #pragma unroll
-            for (int a = 0; a < 3; ++a)
-                m3[a] = base[a] + (ox ? Q[3 * a] : 0.0f) + (oy ? Q[3 * a + 1] : 0.0f) + (oz ? Q[3 * a + 2] : 0.0f);
-            const int t = t0 + (ox ? 1 : 0) + (oy ? sy : 0) + (oz ? sz : 0);
-            atomicAdd(&tile[t], wt * M.mass);
-            atomicAdd(&tile[kTileNodes + t], wt * m3[0]);
-            atomicAdd(&tile[2 * kTileNodes + t], wt * m3[1]);
-            atomicAdd(&tile[3 * kTileNodes + t], wt * m3[2]);
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                Q[3 * i + j] = sc * (A[3 * i] * Di[j] + A[3 * i + 1] * Di[3 + j] + A[3 * i + 2] * Di[6 + j]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            out[a] = cc.xm[a];
+            out[3 + a] = w.sp[a];
+            out[7 + a] = M.mass * v[a] - (Q[3 * a] * cc.xm[0] + Q[3 * a + 1] * cc.xm[1] + Q[3 * a + 2] * cc.xm[2]);
+        }
+        out[6] = M.mass;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) out[10 + i] = Q[i];
+    }
+#pragma unroll
+    for (int i = 0; i < kRecVec; ++i) rec[i] = make_float4(out[4 * i], out[4 * i + 1], out[4 * i + 2], out[4 * i + 3]);
+}
+
+struct Rec {
+    float xm[3], sp[3], mass, base[3], Q[9];
+};
+
+__device__ __forceinline__ void read_rec(const float4 *r, Rec &q) {
+    const float4 a = r[0], b = r[1], c = r[2], e = r[3], f = r[4];
+    q.xm[0] = a.x; q.xm[1] = a.y; q.xm[2] = a.z; q.sp[0] = a.w;
+    q.sp[1] = b.x; q.sp[2] = b.y; q.mass = b.z; q.base[0] = b.w;
+    q.base[1] = c.x; q.base[2] = c.y; q.Q[0] = c.z; q.Q[1] = c.w;
+    q.Q[2] = e.x; q.Q[3] = e.y; q.Q[4] = e.z; q.Q[5] = e.w;
+    q.Q[6] = f.x; q.Q[7] = f.y; q.Q[8] = f.z;
+}
+
+// Sums over the records [lo, hi) of one G- cell: the 8 G- nodes c + o
+// (acc[4 o + channel], o = ox + 2 oy + 4 oz).
+__device__ __forceinline__ void accumulate_minus(const float4 *rec, int lo, int hi, float (&acc)[36]) {
+    for (int k = lo; k < hi; ++k) {
+        Rec q;
+        read_rec(&rec[rec_slot(k) * kRecVec], q);
+        float w[3][2];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            w[a][0] = 1.0f - q.xm[a] - q.sp[a];
+            w[a][1] = q.xm[a] + q.sp[a];
+        }
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+            const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
+            const float wt = w[0][ox] * w[1][oy] * w[2][oz];
+            acc[4 * o] += wt * q.mass;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const float mom = q.base[a] + (ox ? q.Q[3 * a] : 0.0f) + (oy ? q.Q[3 * a + 1] : 0.0f) +
+                                  (oz ? q.Q[3 * a + 2] : 0.0f);
+                acc[4 * o + 1 + a] += wt * mom;
+            }
         }
     }
 }
 
-constexpr int kSlots = kMaxBlockParticles / kThreads;   // bucket entries per thread
-constexpr uint32_t kIndexMask = (1u << kIndexBits) - 1u;
+// Sums over the records [lo, hi) of one G- cell: the 9 G+ nodes c + (rx, ry, rz) of
+// layer rz (acc[4 ((ry + 1) 3 + rx + 1) + channel]).
+__device__ __forceinline__ void accumulate_plus(const float4 *rec, int lo, int hi, int rz, float (&acc)[36]) {
+    for (int k = lo; k < hi; ++k) {
+        Rec q;
+        read_rec(&rec[rec_slot(k) * kRecVec], q);
+        // per axis: weights of the G+ nodes c - 1, c, c + 1 (two are nonzero)
+        float w[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const bool up = q.xm[a] >= 0.5f;                       // G+ cell base is c, else c - 1
+            const float xp = up ? q.xm[a] - 0.5f : q.xm[a] + 0.5f;
+            const float w0 = 1.0f - xp + q.sp[a], w1 = xp - q.sp[a];
+            w[a][0] = up ? 0.0f : w0;
+            w[a][1] = up ? w0 : w1;
+            w[a][2] = up ? w1 : 0.0f;
+        }
+        const float wz = rz < 0 ? w[2][0] : (rz == 0 ? w[2][1] : w[2][2]);
+        const float hz = (float)rz + 0.5f;
+        float m0[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) m0[a] = q.base[a] + 0.5f * (q.Q[3 * a] + q.Q[3 * a + 1]) + hz * q.Q[3 * a + 2];
+#pragma unroll
+        for (int ry = -1; ry <= 1; ++ry) {
+            const float wyz = w[1][ry + 1] * wz;
+#pragma unroll
+            for (int rx = -1; rx <= 1; ++rx) {
+                const int n = 4 * ((ry + 1) * 3 + rx + 1);
+                const float wt = w[0][rx + 1] * wyz;
+                acc[n] += wt * q.mass;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const float mom = m0[a] + (float)rx * q.Q[3 * a] + (float)ry * q.Q[3 * a + 1];
+                    acc[n + 1 + a] += wt * mom;
+                }
+            }
+        }
+    }
+}
 
 template <bool PHYSICS, bool CARRIED_TAU>
-__global__ void __launch_bounds__(kThreads, 3) k_p2g(DevCtx d, PartArgs pa, float dt) {
-    __shared__ float tile[4 * kTileNodes];
-    __shared__ uint32_t lbuf[kMaxBlockParticles];
+__global__ void __launch_bounds__(kThreads, 2) k_p2g(DevCtx d, PartArgs pa, float dt) {
+    __shared__ float4 rec[kRecSlots * kRecVec];
+    __shared__ float tile_m[4 * kTileMinus];
+    __shared__ float tile_p[3 * 4 * kTilePlus];
     __shared__ uint32_t ord[kMaxBlockParticles];
     __shared__ int ccount[64];
     __shared__ int cstart[65];
     __shared__ int nbr[27];
+    uint32_t *lbuf = reinterpret_cast<uint32_t *>(rec);
+    static_assert(kMaxBlockParticles * 4 <= kRecSlots * kRecVec * 16, "ordering buffer must fit the record area");
     const int np = (int)d.counters[C_NPB];
     const int E = (int)d.counters[C_EPOCH];
     const int tid = threadIdx.x;
-    for (int r = blockIdx.x; r < np; r += gridDim.x) {
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int cx = lane & 3, cy = (lane >> 2) & 3, cz = lane >> 4;
+    for (int base = 0; base < np; base += gridDim.x) {
+        const int r = round_block(base, np);
+        if (r < 0) continue;
         const int vb = d.plist[r];
         int bx, by, bz;
         block_coords(d.geo, vb, bx, by, bz);
@@ -208,7 +315,6 @@ __global__ void __launch_bounds__(kThreads, 3) k_p2g(DevCtx d, PartArgs pa, floa
         }
         __syncthreads();
         if (tid < 64) {
-            // exclusive scan of the 64 cell counts within one wave
             const int c = ccount[tid];
             int v = c;
 #pragma unroll
@@ -239,32 +345,71 @@ __global__ void __launch_bounds__(kThreads, 3) k_p2g(DevCtx d, PartArgs pa, floa
                 d.perm[s + rank] = v & kIndexMask;
             }
         }
+        if (!PHYSICS) {
+            __syncthreads();
+            continue;
+        }
+
+        // ---- per-cell register sums over passes of kChunk staged particles
+        load_neighbours(d, bx, by, bz, E, nbr);
+        for (int q = tid; q < 4 * kTileMinus; q += kThreads) tile_m[q] = 0.0f;
+        for (int q = tid; q < 3 * 4 * kTilePlus; q += kThreads) tile_p[q] = 0.0f;
+        float acc[36];
+#pragma unroll
+        for (int i = 0; i < 36; ++i) acc[i] = 0.0f;
+        for (int r0 = 0; r0 < cnt; r0 += kChunk) {
+            __syncthreads();   // ordering done / previous pass's records consumed
+            for (int j = tid; j < kChunk && r0 + j < cnt; j += kThreads)
+                stage_particle(d, pa, (int)ord[r0 + j], bx, by, bz, dt, CARRIED_TAU, &rec[rec_slot(j) * kRecVec]);
+            __syncthreads();
+            const int lo = max(cstart[lane], r0) - r0;
+            const int hi = min(cstart[lane + 1], r0 + kChunk) - r0;
+            if (wave == 0)
+                accumulate_minus(rec, lo, hi, acc);
+            else
+                accumulate_plus(rec, lo, hi, wave - 2, acc);
+        }
         __syncthreads();
-        if (PHYSICS) {
-            // ---- scatter into the LDS tile
-            load_neighbours(d, bx, by, bz, E, nbr);
-            for (int t = tid; t < 4 * kTileNodes; t += kThreads) tile[t] = 0.0f;
-            __syncthreads();
-            for (int j = tid; j < cnt; j += kThreads)
-                p2g_particle(d, pa, (int)ord[j], j, cstart, bx, by, bz, dt, tile, CARRIED_TAU);
-            __syncthreads();
-            // ---- flush nonzero tile entries to the pool
-            for (int t = tid; t < 4 * kTileNodes; t += kThreads) {
-                const float val = tile[t];
-                if (val == 0.0f) continue;
-                const int ch = t / kTileNodes;
-                const int ni = t - ch * kTileNodes;
-                int g, ix, iy, iz;
-                tile_node(ni, bx, by, bz, g, ix, iy, iz);
-                const long long a = pool_index(d, nbr, bx, by, bz, g, ix, iy, iz, ch);
-                if (a < 0) {
-                    set_status(d.counters, ST_CAPACITY);
-                    continue;
+        // ---- add the register sums into the tile, one target node per lane and phase
+#pragma unroll
+        for (int ph = 0; ph < 9; ++ph) {
+            if (wave == 0) {
+                if (ph < 8) {
+                    const int node = (cz + (ph >> 2)) * 25 + (cy + ((ph >> 1) & 1)) * 5 + cx + (ph & 1);
+#pragma unroll
+                    for (int ch = 0; ch < 4; ++ch) tile_m[ch * kTileMinus + node] += acc[4 * ph + ch];
                 }
-                atomicAdd(&d.pool[a], val);
+            } else {
+                const int rx = ph % 3 - 1, ry = ph / 3 - 1, rz = wave - 2;
+                const int node = (cz + rz + 1) * 36 + (cy + ry + 1) * 6 + cx + rx + 1;
+                float *tp = &tile_p[(wave - 1) * 4 * kTilePlus];
+#pragma unroll
+                for (int ch = 0; ch < 4; ++ch) tp[ch * kTilePlus + node] += acc[4 * ph + ch];
             }
             __syncthreads();
         }
+        // ---- flush every nonzero tile node to the pool
+        for (int t = tid; t < 4 * kTileNodes; t += kThreads) {
+            const int ch = t / kTileNodes;
+            const int ni = t - ch * kTileNodes;
+            float val;
+            if (ni < kTileMinus) {
+                val = tile_m[ch * kTileMinus + ni];
+            } else {
+                const int k = ch * kTilePlus + ni - kTileMinus;
+                val = tile_p[k] + tile_p[4 * kTilePlus + k] + tile_p[8 * kTilePlus + k];
+            }
+            if (val == 0.0f) continue;
+            int g, ix, iy, iz;
+            tile_node(ni, bx, by, bz, g, ix, iy, iz);
+            const long long a = pool_index(d, nbr, bx, by, bz, g, ix, iy, iz, ch);
+            if (a < 0) {
+                set_status(d.counters, ST_CAPACITY);
+                continue;
+            }
+            atomicAdd(&d.pool[a], val);
+        }
+        __syncthreads();
     }
 }
 
@@ -309,7 +454,9 @@ __global__ void __launch_bounds__(kThreads) k_g2p(DevCtx d, PartArgs pa, float d
     const int E = (int)d.counters[C_EPOCH];
     const int tid = threadIdx.x;
     const long long S = pa.stride;
-    for (int r = blockIdx.x; r < np; r += gridDim.x) {
+    for (int base = 0; base < np; base += gridDim.x) {
+        const int r = round_block(base, np);
+        if (r < 0) continue;
         const int vb = d.plist[r];
         int bx, by, bz;
         block_coords(d.geo, vb, bx, by, bz);
@@ -504,7 +651,10 @@ __global__ void k_copy_keys(DevCtx d, uint32_t *keys, uint32_t *perm, int n) {
     }
 }
 
-int particle_grid(const DevCtx &d) { return d.max_blocks < 8192 ? d.max_blocks : 8192; }
+int particle_grid(const DevCtx &d) {
+    const int g = d.max_blocks < 8192 ? d.max_blocks : 8192;
+    return g >= 8 ? (g & ~7) : g;
+}
 
 }  // namespace
 

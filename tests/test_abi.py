@@ -24,7 +24,7 @@ def ck():
 
 def declared_functions():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:mpm_status|const char \*|int32_t)\s*\*?\s*(mpm_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:mpm_status|const char \*|int32_t|int64_t)\s*\*?\s*(mpm_\w+)\s*\(", text, re.M)))
 
 
 def test_every_declared_symbol_is_exported(ck):

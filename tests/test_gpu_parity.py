@@ -56,6 +56,11 @@ PHASE_CASES = {
                      ext_cells=(29, 7, 10), gravity=(0.5, -9.8, 0.0), bc_band=2, F_scale=0.05, E=3.5e5),
     "fc_inverted": dict(seed=4, model=scenes.FIXED_COROTATED, n_cells=(16, 16, 16), lo_cells=(5.0, 5.0, 5.0),
                         ext_cells=(3, 3, 3), F_scale=0.6),
+    # strains below the series threshold (|FF^T - I|_F <= 0.05): matrix-series constitutive path
+    "fc_small_strain": dict(seed=5, model=scenes.FIXED_COROTATED, n_cells=(16, 16, 16), lo_cells=(4.5, 5.0, 5.5),
+                            ext_cells=(6, 5, 4), F_scale=0.004, E=1e5),
+    "dp_small_strain": dict(seed=6, model=scenes.DRUCKER_PRAGER, n_cells=(16, 16, 16), lo_cells=(5.0, 4.5, 4.0),
+                            ext_cells=(5, 6, 5), F_scale=0.004, E=3.5e5),
 }
 
 
