@@ -155,7 +155,7 @@ int64_t ctx_device_bytes(const mpm_config &c) {
     const long long np = c.max_particles, nb = c.max_blocks;
     const long long nchunks = (nbv + kCompactChunk - 1) / kCompactChunk;
     auto r = [](long long bytes) { return bytes + 256; };
-    return r(4 * np) + r(4 * np) + r(4 * nb * (long long)kMaxBlockParticles) + r(8 * nbv) + r(8 * nbv) + r(4 * nbv) +
+    return r(4 * np) + r(2 * np) + r(4 * np) + r(4 * nb * (long long)kMaxBlockParticles) + r(8 * nbv) + r(8 * nbv) + r(4 * nbv) +
            r(4 * nbv) + r(4 * nb) + r(4 * (nb + 1)) + r(4 * nb) + r(4 * nb) + r(4 * nchunks) + r(4 * nchunks) +
            r(4 * nb * (long long)kBlockFloats) + r(24 * np) + r(4 * (long long)C_COUNT);
 }
@@ -209,7 +209,12 @@ mpm_status enqueue_p2g(mpm_ctx *ctx, const mpm_particles *p, double dt, hipStrea
     launch_compact(ctx->d, s);
     launch_bucket(ctx->d, pa.n, s);
     if (ev) (void)hipEventRecord(ev[1], s);
-    launch_p2g(ctx->d, pa, (float)dt, physics, ready, s);
+    if (!physics) {
+        launch_block_sort(ctx->d, s);
+    } else {
+        if (!ready) launch_stress(ctx->d, pa, s);
+        launch_p2g(ctx->d, pa, (float)dt, s);
+    }
     if (ev) (void)hipEventRecord(ev[2], s);
     ctx->next_ready = nullptr;
     ctx->p2g_done = pa.in;
@@ -268,6 +273,7 @@ mpm_status ctx_create(const mpm_config *cfg, const mpm_material *mats, int32_t n
     const size_t nchunks = (nv + kCompactChunk - 1) / kCompactChunk;
     mpm_status st = MPM_OK;
     if (st == MPM_OK) st = dalloc(ctx, &d.key, np);
+    if (st == MPM_OK) st = dalloc(ctx, &d.sub, np);
     if (st == MPM_OK) st = dalloc(ctx, &d.perm, np);
     if (st == MPM_OK) st = dalloc(ctx, &d.bucket, nb * (size_t)kMaxBlockParticles);
     if (st == MPM_OK) st = dalloc(ctx, &d.pflag, 2 * nv);

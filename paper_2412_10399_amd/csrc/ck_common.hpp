@@ -61,6 +61,7 @@ struct DevCtx {
     int max_blocks;
     long long nbv;         // number of virtual blocks
     uint32_t *key;         // per particle: block * 64 + cell of the current buffer
+    uint16_t *sub;         // per particle: (cell in block) << 3 | half-cell octant, see sub_code
     uint32_t *bucket;      // [max_blocks][kMaxBlockParticles]: particle indices of each particle
                            // block, in arrival order
     uint32_t *perm;        // exact stable sort order
@@ -139,6 +140,16 @@ __device__ __forceinline__ bool cell_coord(const Geometry &g, const float x[3], 
         }
     }
     return ok;
+}
+
+// Position of a particle inside its block: the G- cell (6 bits) and the half of the
+// cell it lies in along each axis (bit a set when the G+ base node is c, i.e. the
+// upper half; then the particle's G+ nodes are c and c + 1, else c - 1 and c).
+__device__ __forceinline__ uint32_t sub_code(const CellCoord &cc) {
+    const uint32_t cell = (uint32_t)((cc.c[2] & 3) * 16 + (cc.c[1] & 3) * 4 + (cc.c[0] & 3));
+    const uint32_t oct = (uint32_t)(cc.bp[0] == cc.c[0]) | ((uint32_t)(cc.bp[1] == cc.c[1]) << 1) |
+                         ((uint32_t)(cc.bp[2] == cc.c[2]) << 2);
+    return (cell << 3) | oct;
 }
 
 __device__ __forceinline__ uint32_t cell_key(const Geometry &g, const CellCoord &cc) {
@@ -631,7 +642,9 @@ void launch_flag_keys(const DevCtx &d, const PartArgs &pa, int epoch_offset, hip
 void launch_clear_flags(const DevCtx &d, hipStream_t s);
 void launch_compact(const DevCtx &d, hipStream_t s);
 void launch_bucket(const DevCtx &d, int n, hipStream_t s);
-void launch_p2g(const DevCtx &d, const PartArgs &pa, float dt, bool physics, bool carried_tau, hipStream_t s);
+void launch_block_sort(const DevCtx &d, hipStream_t s);
+void launch_stress(const DevCtx &d, const PartArgs &pa, hipStream_t s);
+void launch_p2g(const DevCtx &d, const PartArgs &pa, float dt, hipStream_t s);
 void launch_grid_update(const DevCtx &d, float dt, const float gravity[3], hipStream_t s);
 void launch_g2p(const DevCtx &d, const PartArgs &pa, float dt, hipStream_t s);
 void launch_grid_export(const DevCtx &d, float *m, float *vec, hipStream_t s);

@@ -49,6 +49,7 @@ __global__ void __launch_bounds__(kThreads) k_flag_keys(DevCtx d, PartArgs pa, i
         return;
     }
     d.key[i] = cell_key(d.geo, cc);
+    d.sub[i] = (uint16_t)sub_code(cc);
     stamp_blocks(d, cc, epoch);
 }
 

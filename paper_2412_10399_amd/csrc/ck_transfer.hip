@@ -96,209 +96,25 @@ __device__ __forceinline__ void load_particle(const PartArgs &pa, int p, Particl
     for (int a = 0; a < 9; ++a) q.H[a] = pa.in[(15 + a) * S + p];
 }
 
-// ---------------------------------------------------------------- P2G
-// Particle contributions (section 4.4 APIC transfer plus the MLS stress impulse of
-// section 4.5): mass w m_p and momentum w (m_p v_p + Q (x_i - x_p)) with
-//   Q = (m_p B_p - dt V_p^0 tau_p) D_p^-1,
-// where grad Phi_i = w D^-1 (x_i - x_p) and f_i = -V^0 tau grad Phi_i.  In cell units,
-// with xi the particle's fractional position in its G- cell c, G- node c + o
-// (o in {0,1}^3) sits at x_i - x_p = dx (o - xi) and G+ node c + r (r in {-1,0,1}^3)
-// at dx (r + 1/2 - xi), since G+ is shifted half a cell from G-.  With
-// base = m_p v_p - Q xi the momenta are base + Q o and base + Q (r + 1/2).
-//
-// Accumulation without atomics inside the workgroup (LDS float atomics run about
-// a hundred times slower than plain LDS traffic on gfx950): the block's particles,
-// ordered by cell, are staged in LDS as compact records; then lane c of each wave
-// owns G- cell c of the block and sums, in registers, the contributions of that
-// cell's particles to a fixed set of nodes: wave 0 the 8 G- nodes c + o, wave
-// 1 + l the 9 G+ nodes c + (rx, ry, l - 1) of layer l (a G- cell's particles reach
-// G+ nodes c - 1 .. c + 1 on each axis, two of the three per particle).  The
-// register sums are added into the LDS tile in conflict-free phases (within a phase
-// every lane of a wave targets a different node; each G+ wave owns a copy of the G+
-// tile), and every nonzero tile node is flushed to the pool with one global atomic.
+// ---------------------------------------------------------------- block sort
+// Exact stable order of one block's particles by (cell, particle index): counting
+// sort by cell in LDS, then each particle's rank among the equal-cell particles by
+// index.  Used where the sorting permutation itself is asked for.
 constexpr int kSlots = kMaxBlockParticles / kThreads;   // bucket entries per thread
 constexpr uint32_t kIndexMask = (1u << kIndexBits) - 1u;
-constexpr int kChunk = 512;                              // particles staged per pass
-constexpr int kRecVec = 5;                               // float4 per staged record
-constexpr int kRecSlots = kChunk + kChunk / 8;
 
-// Record slot of the k-th staged particle.  Cells of a uniformly sampled block hold
-// eight consecutive particles; one spare slot per eight spreads the records read
-// together by the lanes of a wave over different LDS banks.
-__device__ __forceinline__ int rec_slot(int k) { return k + (k >> 3); }
-
-// Record: xi[3] s+[3] m_p base[3] Q[9] (row-major) and one pad float.
-__device__ __forceinline__ void stage_particle(const DevCtx &d, const PartArgs &pa, int p, int bx, int by, int bz,
-                                               float dt, bool carried_tau, float4 *rec) {
-    float out[20];
-#pragma unroll
-    for (int i = 0; i < 20; ++i) out[i] = 0.0f;
-    const long long S = pa.stride;
-    float x[3], v[3], B[9];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) x[a] = pa.in[a * S + p];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) v[a] = pa.in[(3 + a) * S + p];
-#pragma unroll
-    for (int a = 0; a < 9; ++a) B[a] = pa.in[(6 + a) * S + p];
-    float tau[6];
-    if (carried_tau) {
-#pragma unroll
-        for (int i = 0; i < 6; ++i) tau[i] = d.tau[i * d.tau_stride + p];
-    }
-    const int mi = pa.mat_in ? (int)pa.mat_in[p] : 0;
-    const DevMaterial M = d.mats[mi < d.n_mat ? mi : 0];
-    CellCoord cc;
-    bool ok = cell_coord(d.geo, x, cc);
-    if (!ok) set_status(d.counters, ST_DOMAIN);
-    if (ok && ((cc.c[0] >> 2) != bx || (cc.c[1] >> 2) != by || (cc.c[2] >> 2) != bz)) {
-        set_status(d.counters, ST_STALE);
-        ok = false;
-    }
-    if (ok) {
-        if (!carried_tau) {
-            float H[9];
-#pragma unroll
-            for (int a = 0; a < 9; ++a) H[a] = pa.in[(15 + a) * S + p];
-            kirchhoff(M, H, tau);
-        }
-        Weights w;
-        axis_weights(cc, w);
-        float Di[9];
-        moment_inverse(cc, w, Di);
-        const float T[9] = {tau[0], tau[3], tau[4], tau[3], tau[1], tau[5], tau[4], tau[5], tau[2]};
-        const float k = dt * M.vol0;
-        float A[9];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) A[i] = M.mass * B[i] - k * T[i];
-        const float sc = d.geo.inv_dx_f;
-        float Q[9];
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j)
-                Q[3 * i + j] = sc * (A[3 * i] * Di[j] + A[3 * i + 1] * Di[3 + j] + A[3 * i + 2] * Di[6 + j]);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            out[a] = cc.xm[a];
-            out[3 + a] = w.sp[a];
-            out[7 + a] = M.mass * v[a] - (Q[3 * a] * cc.xm[0] + Q[3 * a + 1] * cc.xm[1] + Q[3 * a + 2] * cc.xm[2]);
-        }
-        out[6] = M.mass;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) out[10 + i] = Q[i];
-    }
-#pragma unroll
-    for (int i = 0; i < kRecVec; ++i) rec[i] = make_float4(out[4 * i], out[4 * i + 1], out[4 * i + 2], out[4 * i + 3]);
-}
-
-struct Rec {
-    float xm[3], sp[3], mass, base[3], Q[9];
-};
-
-__device__ __forceinline__ void read_rec(const float4 *r, Rec &q) {
-    const float4 a = r[0], b = r[1], c = r[2], e = r[3], f = r[4];
-    q.xm[0] = a.x; q.xm[1] = a.y; q.xm[2] = a.z; q.sp[0] = a.w;
-    q.sp[1] = b.x; q.sp[2] = b.y; q.mass = b.z; q.base[0] = b.w;
-    q.base[1] = c.x; q.base[2] = c.y; q.Q[0] = c.z; q.Q[1] = c.w;
-    q.Q[2] = e.x; q.Q[3] = e.y; q.Q[4] = e.z; q.Q[5] = e.w;
-    q.Q[6] = f.x; q.Q[7] = f.y; q.Q[8] = f.z;
-}
-
-// Sums over the records [lo, hi) of one G- cell: the 8 G- nodes c + o
-// (acc[4 o + channel], o = ox + 2 oy + 4 oz).
-__device__ __forceinline__ void accumulate_minus(const float4 *rec, int lo, int hi, float (&acc)[36]) {
-    for (int k = lo; k < hi; ++k) {
-        Rec q;
-        read_rec(&rec[rec_slot(k) * kRecVec], q);
-        float w[3][2];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            w[a][0] = 1.0f - q.xm[a] - q.sp[a];
-            w[a][1] = q.xm[a] + q.sp[a];
-        }
-#pragma unroll
-        for (int o = 0; o < 8; ++o) {
-            const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
-            const float wt = w[0][ox] * w[1][oy] * w[2][oz];
-            acc[4 * o] += wt * q.mass;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const float mom = q.base[a] + (ox ? q.Q[3 * a] : 0.0f) + (oy ? q.Q[3 * a + 1] : 0.0f) +
-                                  (oz ? q.Q[3 * a + 2] : 0.0f);
-                acc[4 * o + 1 + a] += wt * mom;
-            }
-        }
-    }
-}
-
-// Sums over the records [lo, hi) of one G- cell: the 9 G+ nodes c + (rx, ry, rz) of
-// layer rz (acc[4 ((ry + 1) 3 + rx + 1) + channel]).
-__device__ __forceinline__ void accumulate_plus(const float4 *rec, int lo, int hi, int rz, float (&acc)[36]) {
-    for (int k = lo; k < hi; ++k) {
-        Rec q;
-        read_rec(&rec[rec_slot(k) * kRecVec], q);
-        // per axis: weights of the G+ nodes c - 1, c, c + 1 (two are nonzero)
-        float w[3][3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const bool up = q.xm[a] >= 0.5f;                       // G+ cell base is c, else c - 1
-            const float xp = up ? q.xm[a] - 0.5f : q.xm[a] + 0.5f;
-            const float w0 = 1.0f - xp + q.sp[a], w1 = xp - q.sp[a];
-            w[a][0] = up ? 0.0f : w0;
-            w[a][1] = up ? w0 : w1;
-            w[a][2] = up ? w1 : 0.0f;
-        }
-        const float wz = rz < 0 ? w[2][0] : (rz == 0 ? w[2][1] : w[2][2]);
-        const float hz = (float)rz + 0.5f;
-        float m0[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) m0[a] = q.base[a] + 0.5f * (q.Q[3 * a] + q.Q[3 * a + 1]) + hz * q.Q[3 * a + 2];
-#pragma unroll
-        for (int ry = -1; ry <= 1; ++ry) {
-            const float wyz = w[1][ry + 1] * wz;
-#pragma unroll
-            for (int rx = -1; rx <= 1; ++rx) {
-                const int n = 4 * ((ry + 1) * 3 + rx + 1);
-                const float wt = w[0][rx + 1] * wyz;
-                acc[n] += wt * q.mass;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const float mom = m0[a] + (float)rx * q.Q[3 * a] + (float)ry * q.Q[3 * a + 1];
-                    acc[n + 1 + a] += wt * mom;
-                }
-            }
-        }
-    }
-}
-
-template <bool PHYSICS, bool CARRIED_TAU>
-__global__ void __launch_bounds__(kThreads, 2) k_p2g(DevCtx d, PartArgs pa, float dt) {
-    __shared__ float4 rec[kRecSlots * kRecVec];
-    __shared__ float tile_m[4 * kTileMinus];
-    __shared__ float tile_p[3 * 4 * kTilePlus];
-    __shared__ uint32_t ord[kMaxBlockParticles];
+__global__ void __launch_bounds__(kThreads) k_block_sort(DevCtx d) {
+    __shared__ uint32_t lbuf[kMaxBlockParticles];
     __shared__ int ccount[64];
     __shared__ int cstart[65];
-    __shared__ int nbr[27];
-    uint32_t *lbuf = reinterpret_cast<uint32_t *>(rec);
-    static_assert(kMaxBlockParticles * 4 <= kRecSlots * kRecVec * 16, "ordering buffer must fit the record area");
     const int np = (int)d.counters[C_NPB];
-    const int E = (int)d.counters[C_EPOCH];
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int cx = lane & 3, cy = (lane >> 2) & 3, cz = lane >> 4;
     for (int base = 0; base < np; base += gridDim.x) {
         const int r = round_block(base, np);
         if (r < 0) continue;
-        const int vb = d.plist[r];
-        int bx, by, bz;
-        block_coords(d.geo, vb, bx, by, bz);
         const int s = d.pstart[r];
         const int cnt = d.pstart[r + 1] - s;
         if (cnt > kMaxBlockParticles) continue;   // reported by the bucket scan
-        // ---- exact order inside the block: by (cell, particle index)
         if (tid < 64) ccount[tid] = 0;
         __syncthreads();
         uint32_t pk[kSlots];
@@ -341,73 +157,386 @@ __global__ void __launch_bounds__(kThreads, 2) k_p2g(DevCtx d, PartArgs pa, floa
                 const int lo = cstart[c], hi = cstart[c + 1];
                 int rank = lo;
                 for (int q = lo; q < hi; ++q) rank += (lbuf[q] < v) ? 1 : 0;
-                ord[rank] = v & kIndexMask;
                 d.perm[s + rank] = v & kIndexMask;
             }
         }
-        if (!PHYSICS) {
-            __syncthreads();
-            continue;
-        }
+        __syncthreads();
+    }
+}
 
-        // ---- per-cell register sums over passes of kChunk staged particles
-        load_neighbours(d, bx, by, bz, E, nbr);
-        for (int q = tid; q < 4 * kTileMinus; q += kThreads) tile_m[q] = 0.0f;
-        for (int q = tid; q < 3 * 4 * kTilePlus; q += kThreads) tile_p[q] = 0.0f;
-        float acc[36];
+// ---------------------------------------------------------------- stress
+// Kirchhoff stress of every particle of the current buffer, for a P2G that does not
+// follow a G2P of this context (first step, or positions changed by the caller).
+__global__ void __launch_bounds__(kThreads) k_stress(DevCtx d, PartArgs pa) {
+    const int p = blockIdx.x * kThreads + threadIdx.x;
+    if (p >= pa.n) return;
+    const long long S = pa.stride;
+    float H[9];
 #pragma unroll
-        for (int i = 0; i < 36; ++i) acc[i] = 0.0f;
-        for (int r0 = 0; r0 < cnt; r0 += kChunk) {
-            __syncthreads();   // ordering done / previous pass's records consumed
-            for (int j = tid; j < kChunk && r0 + j < cnt; j += kThreads)
-                stage_particle(d, pa, (int)ord[r0 + j], bx, by, bz, dt, CARRIED_TAU, &rec[rec_slot(j) * kRecVec]);
-            __syncthreads();
-            const int lo = max(cstart[lane], r0) - r0;
-            const int hi = min(cstart[lane + 1], r0 + kChunk) - r0;
-            if (wave == 0)
-                accumulate_minus(rec, lo, hi, acc);
-            else
-                accumulate_plus(rec, lo, hi, wave - 2, acc);
+    for (int a = 0; a < 9; ++a) H[a] = pa.in[(15 + a) * S + p];
+    const int mi = pa.mat_in ? (int)pa.mat_in[p] : 0;
+    const DevMaterial M = d.mats[mi < d.n_mat ? mi : 0];
+    float tau[6];
+    kirchhoff(M, H, tau);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) d.tau[i * d.tau_stride + p] = tau[i];
+}
+
+// ---------------------------------------------------------------- P2G
+// Particle contributions (section 4.4 APIC transfer plus the MLS stress impulse of
+// section 4.5): mass w m_p and momentum w (m_p v_p + Q (x_i - x_p)) with
+//   Q = (m_p B_p - dt V_p^0 tau_p) D_p^-1,
+// where grad Phi_i = w D^-1 (x_i - x_p) and f_i = -V^0 tau grad Phi_i.  In cell units,
+// with xi the particle's fractional position in its G- cell c, G- node c + o
+// (o in {0,1}^3) sits at x_i - x_p = dx (o - xi) and G+ node c + r at
+// dx (r + 1/2 - xi), G+ being shifted half a cell from G-.  With base = m_p v_p - Q xi
+// the momenta are base + Q o and base + Q (r + 1/2).
+//
+// One wave per block, lane c owning G- cell c of the block, and no atomics inside
+// the block (LDS float atomics run about a hundred times slower than plain LDS
+// traffic on gfx950).  A particle in the upper or lower half of its cell along an
+// axis reaches G+ nodes c, c + 1 or c - 1, c on that axis, so the half-cell octant
+// fixes which 8 of the 27 G+ nodes around c it touches.  The block's particles are
+// therefore ordered by (octant, cell, index); for each octant in turn, the wave
+// stages that octant's particles as compact records in LDS (lane = particle,
+// coalesced reads: the previous G2P wrote the state in this order), and lane c sums
+// the records of cell c into registers: 8 G- nodes and, at indices known at compile
+// time for the octant, 8 of its 27 G+ nodes.  The register sums are then added into
+// the LDS tile in conflict-free phases (every lane targets a different node in a
+// phase) and each nonzero tile node is flushed to the pool with one global atomic.
+constexpr int kP2GThreads = 64;
+constexpr int kBins = 512;                 // (octant, cell) bins of a block: octant * 64 + cell
+constexpr int kRecVec = 5;                 // float4 per staged record
+constexpr int kHold = 8;                   // bucket entries per lane kept in registers
+constexpr uint32_t kNoRecord = 0xffffu;
+
+// Record: xi[3] s+[3] m_p base[3] Q[9] (row-major), sub code.
+__device__ __forceinline__ void stage_particle(const DevCtx &d, const PartArgs &pa, int p, int bx, int by, int bz,
+                                               float dt, float4 *rec) {
+    float out[19];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) out[i] = 0.0f;
+    uint32_t code = kNoRecord;
+    const long long S = pa.stride;
+    float x[3], v[3], B[9], tau[6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) x[a] = pa.in[a * S + p];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v[a] = pa.in[(3 + a) * S + p];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) B[a] = pa.in[(6 + a) * S + p];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) tau[i] = d.tau[i * d.tau_stride + p];
+    const int mi = pa.mat_in ? (int)pa.mat_in[p] : 0;
+    const DevMaterial M = d.mats[mi < d.n_mat ? mi : 0];
+    CellCoord cc;
+    if (!cell_coord(d.geo, x, cc)) {
+        set_status(d.counters, ST_DOMAIN);
+    } else if ((cc.c[0] >> 2) != bx || (cc.c[1] >> 2) != by || (cc.c[2] >> 2) != bz) {
+        set_status(d.counters, ST_STALE);
+    } else {
+        code = sub_code(cc);
+        Weights w;
+        axis_weights(cc, w);
+        float Di[9];
+        moment_inverse(cc, w, Di);
+        const float T[9] = {tau[0], tau[3], tau[4], tau[3], tau[1], tau[5], tau[4], tau[5], tau[2]};
+        const float k = dt * M.vol0;
+        float A[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) A[i] = M.mass * B[i] - k * T[i];
+        const float sc = d.geo.inv_dx_f;
+        float Q[9];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                Q[3 * i + j] = sc * (A[3 * i] * Di[j] + A[3 * i + 1] * Di[3 + j] + A[3 * i + 2] * Di[6 + j]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            out[a] = cc.xm[a];
+            out[3 + a] = w.sp[a];
+            out[7 + a] = M.mass * v[a] - (Q[3 * a] * cc.xm[0] + Q[3 * a + 1] * cc.xm[1] + Q[3 * a + 2] * cc.xm[2]);
+        }
+        out[6] = M.mass;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) out[10 + i] = Q[i];
+    }
+    rec[0] = make_float4(out[0], out[1], out[2], out[3]);
+    rec[1] = make_float4(out[4], out[5], out[6], out[7]);
+    rec[2] = make_float4(out[8], out[9], out[10], out[11]);
+    rec[3] = make_float4(out[12], out[13], out[14], out[15]);
+    rec[4] = make_float4(out[16], out[17], out[18], __uint_as_float(code));
+}
+
+struct Rec {
+    float xm[3], sp[3], mass, base[3], Q[9];
+    uint32_t code;
+};
+
+__device__ __forceinline__ void read_rec(const float4 *r, Rec &q) {
+    const float4 a = r[0], b = r[1], c = r[2], e = r[3], f = r[4];
+    q.xm[0] = a.x; q.xm[1] = a.y; q.xm[2] = a.z; q.sp[0] = a.w;
+    q.sp[1] = b.x; q.sp[2] = b.y; q.mass = b.z; q.base[0] = b.w;
+    q.base[1] = c.x; q.base[2] = c.y; q.Q[0] = c.z; q.Q[1] = c.w;
+    q.Q[2] = e.x; q.Q[3] = e.y; q.Q[4] = e.z; q.Q[5] = e.w;
+    q.Q[6] = f.x; q.Q[7] = f.y; q.Q[8] = f.z; q.code = __float_as_uint(f.w);
+}
+
+// Adds w (m, m0 + Q o) for the 8 nodes o in {0,1}^3 of one grid, weights w[a][o_a],
+// into acc[4 n(o) + channel], n(o) given by the node map of the grid.
+template <typename NodeMap>
+__device__ __forceinline__ void add_corners(const float (&w)[3][2], float mass, const float (&m0)[3], const float (&Q)[9],
+                                            float *acc, NodeMap node) {
+    float wxy[4];
+#pragma unroll
+    for (int oy = 0; oy < 2; ++oy)
+#pragma unroll
+        for (int ox = 0; ox < 2; ++ox) wxy[2 * oy + ox] = w[0][ox] * w[1][oy];
+#pragma unroll
+    for (int oz = 0; oz < 2; ++oz)
+#pragma unroll
+        for (int oy = 0; oy < 2; ++oy)
+#pragma unroll
+            for (int ox = 0; ox < 2; ++ox) {
+                const float wt = wxy[2 * oy + ox] * w[2][oz];
+                const int n = node(ox, oy, oz);
+                acc[4 * n] += wt * mass;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const float mom = m0[a] + (ox ? Q[3 * a] : 0.0f) + (oy ? Q[3 * a + 1] : 0.0f) + (oz ? Q[3 * a + 2] : 0.0f);
+                    acc[4 * n + 1 + a] += wt * mom;
+                }
+            }
+}
+
+// One record of octant K into the cell sums: 8 G- nodes (am[4 o + ch],
+// o = ox + 2 oy + 4 oz) and 8 of the 27 G+ nodes c + r, r in {-1,0,1}^3
+// (ap[4 ((rz+1) 9 + (ry+1) 3 + rx+1) + ch]); along axis a the G+ nodes are
+// r = o - 1 + bit_a(K).
+template <int K>
+__device__ __forceinline__ void accumulate_octant(const Rec &q, float (&am)[32], float (&ap)[108]) {
+    constexpr int ux = K & 1, uy = (K >> 1) & 1, uz = (K >> 2) & 1;
+    float wm[3][2], wp[3][2];
+    constexpr int up[3] = {ux, uy, uz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        wm[a][0] = 1.0f - q.xm[a] - q.sp[a];
+        wm[a][1] = q.xm[a] + q.sp[a];
+        const float xp = up[a] ? q.xm[a] - 0.5f : q.xm[a] + 0.5f;
+        wp[a][0] = 1.0f - xp + q.sp[a];
+        wp[a][1] = xp - q.sp[a];
+    }
+    add_corners(wm, q.mass, q.base, q.Q, am, [](int ox, int oy, int oz) { return ox + 2 * oy + 4 * oz; });
+    // G+ momentum at the first node r0 = up - 1: base + Q (r0 + 1/2)
+    float m0[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        m0[a] = q.base[a] + (ux - 0.5f) * q.Q[3 * a] + (uy - 0.5f) * q.Q[3 * a + 1] + (uz - 0.5f) * q.Q[3 * a + 2];
+    add_corners(wp, q.mass, m0, q.Q, ap,
+                [](int ox, int oy, int oz) { return (oz + uz) * 9 + (oy + uy) * 3 + (ox + ux); });
+}
+
+// All records of octant K: staged by the wave in chunks of 64, summed by their cell's lane.
+template <int K>
+__device__ __forceinline__ void octant_pass(const DevCtx &d, const PartArgs &pa, float dt, int s, int bx, int by,
+                                            int bz, const int *bstart, float4 *rec, int lane, float (&am)[32],
+                                            float (&ap)[108]) {
+    const uint32_t want = ((uint32_t)lane << 3) | (uint32_t)K;
+    const int olo = bstart[K * 64], ohi = bstart[K * 64 + 64];
+    const int clo = bstart[K * 64 + lane], chi = bstart[K * 64 + lane + 1];
+    for (int t0 = olo; t0 < ohi; t0 += kP2GThreads) {
+        if (t0 + lane < ohi) stage_particle(d, pa, (int)d.perm[s + t0 + lane], bx, by, bz, dt, &rec[lane * kRecVec]);
+        __syncthreads();
+        const int lo = max(clo, t0), hi = min(chi, t0 + kP2GThreads);
+        for (int i = lo; i < hi; ++i) {
+            Rec q;
+            read_rec(&rec[(i - t0) * kRecVec], q);
+            if (q.code != want) {
+                if (q.code != kNoRecord) set_status(d.counters, ST_STALE);
+                continue;
+            }
+            accumulate_octant<K>(q, am, ap);
         }
         __syncthreads();
-        // ---- add the register sums into the tile, one target node per lane and phase
+    }
+}
+
+// Adds the register sums of G+ node c + r, N = (rz+1) 9 + (ry+1) 3 + rx+1, into the
+// tile; every lane targets a different node.
+template <int N>
+__device__ __forceinline__ void flush_plus(float *tile_p, int cx, int cy, int cz, const float (&ap)[108]) {
+    constexpr int rx = N % 3, ry = (N / 3) % 3, rz = N / 9;
+    const int node = (cz + rz) * 36 + (cy + ry) * 6 + cx + rx;
 #pragma unroll
-        for (int ph = 0; ph < 9; ++ph) {
-            if (wave == 0) {
-                if (ph < 8) {
-                    const int node = (cz + (ph >> 2)) * 25 + (cy + ((ph >> 1) & 1)) * 5 + cx + (ph & 1);
+    for (int ch = 0; ch < 4; ++ch) tile_p[ch * kTilePlus + node] += ap[4 * N + ch];
+    __syncthreads();
+}
+
+template <int... N>
+__device__ __forceinline__ void flush_plus_list(float *tile_p, int cx, int cy, int cz, const float (&ap)[108]) {
+    (flush_plus<N>(tile_p, cx, cy, cz, ap), ...);
+}
+
+__device__ __forceinline__ int bin_of(uint32_t sub) { return (int)((sub & 7u) * 64u + (sub >> 3)); }
+
+__global__ void __launch_bounds__(kP2GThreads, 2) k_p2g(DevCtx d, PartArgs pa, float dt) {
+    __shared__ int bcnt[kBins];                 // counts, then placement cursors
+    __shared__ int bstart[kBins + 1];
+    __shared__ int nbr[27];
+    // ordering buffer, later the staged records and the tile
+    constexpr int kTileFloats = 4 * (kTileMinus + kTilePlus);
+    constexpr int kUnionFloats = kMaxBlockParticles > kP2GThreads * 4 * kRecVec + kTileFloats
+                                     ? kMaxBlockParticles
+                                     : kP2GThreads * 4 * kRecVec + kTileFloats;
+    __shared__ float4 area4[kUnionFloats / 4];
+    float *area = reinterpret_cast<float *>(area4);
+    uint32_t *lbuf = reinterpret_cast<uint32_t *>(area4);
+    float4 *rec = area4;
+    float *tile_m = area + kP2GThreads * 4 * kRecVec;   // [4][125]
+    float *tile_p = tile_m + 4 * kTileMinus;              // [4][216]
+    const int np = (int)d.counters[C_NPB];
+    const int E = (int)d.counters[C_EPOCH];
+    const int lane = threadIdx.x;
+    const int cx = lane & 3, cy = (lane >> 2) & 3, cz = lane >> 4;
+    for (int base = 0; base < np; base += gridDim.x) {
+        const int r = round_block(base, np);
+        if (r < 0) continue;
+        const int vb = d.plist[r];
+        int bx, by, bz;
+        block_coords(d.geo, vb, bx, by, bz);
+        const int s = d.pstart[r];
+        const int cnt = d.pstart[r + 1] - s;
+        if (cnt > kMaxBlockParticles) continue;   // reported by the bucket scan
+        const uint32_t *bkt = d.bucket + (size_t)r * kMaxBlockParticles;
+
+        // ---- order the block's particles by (octant, cell, index)
+        for (int b = lane; b < kBins; b += kP2GThreads) bcnt[b] = 0;
+        __syncthreads();
+        uint32_t hidx[kHold];
+        int hbin[kHold];
 #pragma unroll
-                    for (int ch = 0; ch < 4; ++ch) tile_m[ch * kTileMinus + node] += acc[4 * ph + ch];
-                }
-            } else {
-                const int rx = ph % 3 - 1, ry = ph / 3 - 1, rz = wave - 2;
-                const int node = (cz + rz + 1) * 36 + (cy + ry + 1) * 6 + cx + rx + 1;
-                float *tp = &tile_p[(wave - 1) * 4 * kTilePlus];
-#pragma unroll
-                for (int ch = 0; ch < 4; ++ch) tp[ch * kTilePlus + node] += acc[4 * ph + ch];
+        for (int k = 0; k < kMaxBlockParticles / kP2GThreads; ++k) {
+            const int j = lane + k * kP2GThreads;
+            if (j >= cnt) break;
+            const uint32_t idx = bkt[j];
+            const int bin = bin_of(d.sub[idx]);
+            if (k < kHold) {
+                hidx[k] = idx;
+                hbin[k] = bin;
             }
+            atomicAdd(&bcnt[bin], 1);
+        }
+        __syncthreads();
+        {
+            // exclusive scan of the 512 bins, 8 per lane
+            int loc[kBins / kP2GThreads];
+            int sum = 0;
+#pragma unroll
+            for (int k = 0; k < kBins / kP2GThreads; ++k) {
+                loc[k] = bcnt[lane * (kBins / kP2GThreads) + k];
+                sum += loc[k];
+            }
+            int v = sum;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int t = __shfl_up(v, off);
+                if (lane >= off) v += t;
+            }
+            int run = v - sum;
+#pragma unroll
+            for (int k = 0; k < kBins / kP2GThreads; ++k) {
+                bstart[lane * (kBins / kP2GThreads) + k] = run;
+                bcnt[lane * (kBins / kP2GThreads) + k] = run;
+                run += loc[k];
+            }
+            if (lane == 63) bstart[kBins] = run;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kMaxBlockParticles / kP2GThreads; ++k) {
+            const int j = lane + k * kP2GThreads;
+            if (j >= cnt) break;
+            uint32_t idx;
+            int bin;
+            if (k < kHold) {
+                idx = hidx[k];
+                bin = hbin[k];
+            } else {
+                idx = bkt[j];
+                bin = bin_of(d.sub[idx]);
+            }
+            lbuf[atomicAdd(&bcnt[bin], 1)] = idx;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kMaxBlockParticles / kP2GThreads; ++k) {
+            const int j = lane + k * kP2GThreads;
+            if (j >= cnt) break;
+            uint32_t idx;
+            int bin;
+            if (k < kHold) {
+                idx = hidx[k];
+                bin = hbin[k];
+            } else {
+                idx = bkt[j];
+                bin = bin_of(d.sub[idx]);
+            }
+            const int lo = bstart[bin], hi = bstart[bin + 1];
+            int rank = lo;
+            for (int q = lo; q < hi; ++q) rank += (lbuf[q] < idx) ? 1 : 0;
+            d.perm[s + rank] = idx;
+        }
+        __threadfence_block();   // the order is read back below by other lanes
+        __syncthreads();
+
+        // ---- per-cell register sums, one octant at a time
+        load_neighbours(d, bx, by, bz, E, nbr);
+        for (int q = lane; q < kTileFloats; q += kP2GThreads) tile_m[q] = 0.0f;
+        float am[32], ap[108];
+#pragma unroll
+        for (int i = 0; i < 32; ++i) am[i] = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 108; ++i) ap[i] = 0.0f;
+        // Octants in order; a G+ node is added to the tile as soon as no later octant
+        // reaches it, which keeps at most 15 of the 27 node sums live at a time.
+        octant_pass<0>(d, pa, dt, s, bx, by, bz, bstart, rec, lane, am, ap);
+        octant_pass<1>(d, pa, dt, s, bx, by, bz, bstart, rec, lane, am, ap);
+        flush_plus_list<0, 1, 2>(tile_p, cx, cy, cz, ap);                      // ry = rz = -1
+        octant_pass<2>(d, pa, dt, s, bx, by, bz, bstart, rec, lane, am, ap);
+        octant_pass<3>(d, pa, dt, s, bx, by, bz, bstart, rec, lane, am, ap);
+        flush_plus_list<3, 4, 5, 6, 7, 8>(tile_p, cx, cy, cz, ap);             // rz = -1
+        octant_pass<4>(d, pa, dt, s, bx, by, bz, bstart, rec, lane, am, ap);
+        octant_pass<5>(d, pa, dt, s, bx, by, bz, bstart, rec, lane, am, ap);
+        flush_plus_list<9, 10, 11, 18, 19, 20>(tile_p, cx, cy, cz, ap);        // ry = -1
+        octant_pass<6>(d, pa, dt, s, bx, by, bz, bstart, rec, lane, am, ap);
+        octant_pass<7>(d, pa, dt, s, bx, by, bz, bstart, rec, lane, am, ap);
+        flush_plus_list<12, 13, 14, 15, 16, 17, 21, 22, 23, 24, 25, 26>(tile_p, cx, cy, cz, ap);
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+            const int node = (cz + (o >> 2)) * 25 + (cy + ((o >> 1) & 1)) * 5 + cx + (o & 1);
+#pragma unroll
+            for (int ch = 0; ch < 4; ++ch) tile_m[ch * kTileMinus + node] += am[4 * o + ch];
             __syncthreads();
         }
         // ---- flush every nonzero tile node to the pool
-        for (int t = tid; t < 4 * kTileNodes; t += kThreads) {
-            const int ch = t / kTileNodes;
-            const int ni = t - ch * kTileNodes;
-            float val;
-            if (ni < kTileMinus) {
-                val = tile_m[ch * kTileMinus + ni];
-            } else {
-                const int k = ch * kTilePlus + ni - kTileMinus;
-                val = tile_p[k] + tile_p[4 * kTilePlus + k] + tile_p[8 * kTilePlus + k];
-            }
-            if (val == 0.0f) continue;
+        for (int ni = lane; ni < kTileNodes; ni += kP2GThreads) {
             int g, ix, iy, iz;
             tile_node(ni, bx, by, bz, g, ix, iy, iz);
-            const long long a = pool_index(d, nbr, bx, by, bz, g, ix, iy, iz, ch);
+            const long long a = pool_index(d, nbr, bx, by, bz, g, ix, iy, iz, 0);
+            float val[4];
+#pragma unroll
+            for (int ch = 0; ch < 4; ++ch)
+                val[ch] = ni < kTileMinus ? tile_m[ch * kTileMinus + ni] : tile_p[ch * kTilePlus + ni - kTileMinus];
+            const bool any = val[0] != 0.0f || val[1] != 0.0f || val[2] != 0.0f || val[3] != 0.0f;
+            if (!any) continue;
             if (a < 0) {
                 set_status(d.counters, ST_CAPACITY);
                 continue;
             }
-            atomicAdd(&d.pool[a], val);
+#pragma unroll
+            for (int ch = 0; ch < 4; ++ch)
+                if (val[ch] != 0.0f) atomicAdd(&d.pool[a + ch * 64], val[ch]);
         }
         __syncthreads();
     }
@@ -591,6 +720,7 @@ __global__ void __launch_bounds__(kThreads) k_g2p(DevCtx d, PartArgs pa, float d
             CellCoord cn;
             if (finite && cell_coord(d.geo, xn, cn)) {
                 d.key[out] = cell_key(d.geo, cn);
+                d.sub[out] = (uint16_t)sub_code(cn);
                 const Geometry &g = d.geo;
                 int *pf = stamps(d.pflag, d.nbv, E + 1);
                 int *gf = stamps(d.gflag, d.nbv, E + 1);
@@ -658,13 +788,16 @@ int particle_grid(const DevCtx &d) {
 
 }  // namespace
 
-void launch_p2g(const DevCtx &d, const PartArgs &pa, float dt, bool physics, bool carried_tau, hipStream_t s) {
-    if (!physics)
-        hipLaunchKernelGGL((k_p2g<false, false>), dim3(particle_grid(d)), dim3(kThreads), 0, s, d, pa, dt);
-    else if (carried_tau)
-        hipLaunchKernelGGL((k_p2g<true, true>), dim3(particle_grid(d)), dim3(kThreads), 0, s, d, pa, dt);
-    else
-        hipLaunchKernelGGL((k_p2g<true, false>), dim3(particle_grid(d)), dim3(kThreads), 0, s, d, pa, dt);
+void launch_block_sort(const DevCtx &d, hipStream_t s) {
+    hipLaunchKernelGGL(k_block_sort, dim3(particle_grid(d)), dim3(kThreads), 0, s, d);
+}
+
+void launch_stress(const DevCtx &d, const PartArgs &pa, hipStream_t s) {
+    if (pa.n > 0) hipLaunchKernelGGL(k_stress, dim3((pa.n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, d, pa);
+}
+
+void launch_p2g(const DevCtx &d, const PartArgs &pa, float dt, hipStream_t s) {
+    hipLaunchKernelGGL(k_p2g, dim3(particle_grid(d)), dim3(kP2GThreads), 0, s, d, pa, dt);
 }
 
 void launch_grid_update(const DevCtx &d, float dt, const float gravity[3], hipStream_t s) {
