@@ -96,12 +96,16 @@ def main():
 
     torch.cuda.set_device(0)
     if args.copy_probe_mib > 0:
+        # one plain device copy of known size; a 1 GiB fill in between pushes the
+        # source out of the last-level cache, so the copy reads it from HBM
         n = args.copy_probe_mib * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
+        flush = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        flush.fill_(2.0)
         dst.copy_(src)
         torch.cuda.synchronize()
-        del src, dst
+        del src, dst, flush
 
     sc = scenes.sand_column()
     ctx = ckmpm.Context(ckmpm.scene_config(sc), ckmpm.scene_materials(sc))

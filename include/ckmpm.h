@@ -113,10 +113,12 @@ mpm_status mpm_create(const mpm_config *cfg, const mpm_material *mats, int32_t n
 mpm_status mpm_destroy(mpm_ctx *ctx);
 
 /* Sort + activation + P2G (sections 4.3-4.5): computes the particles' cell keys (unless
- * the previous mpm_g2p produced them for this buffer), sorts particles stably by
- * (4^3-cell block, cell), activates the grid blocks the 16-node stencils touch, clears
- * them and scatters mass and momentum m v + (m B - dt V0 tau) D^-1 (x_i - x_p) to both
- * grids.  Reads the current buffer only.  Enqueued on `stream`; asynchronous. */
+ * the previous mpm_g2p produced them for this buffer), orders the particles by
+ * (4^3-cell block, half-cell octant, cell, index) -- the octant being the half of its
+ * G- cell a particle lies in along each axis --, activates the grid blocks the 16-node
+ * stencils touch, clears them and scatters mass and momentum
+ * m v + (m B - dt V0 tau) D^-1 (x_i - x_p) to both grids.  Reads the current buffer
+ * only.  Enqueued on `stream`; asynchronous. */
 mpm_status mpm_p2g(mpm_ctx *ctx, const mpm_particles *p, double dt, void *stream);
 
 /* Grid update (section 4.3): v~ = p/m + dt g on nodes with m > 0, zero elsewhere and
@@ -125,9 +127,9 @@ mpm_status mpm_grid_update(mpm_ctx *ctx, double dt, void *stream);
 
 /* G2P (sections 4.3-4.5): v_p = 1/2 sum w v~, B_p = 1/2 sum w v~ (x_i - x_p)^T,
  * F <- (I + dt B_p D_p^-1) F (applied to H = F - I), Drucker-Prager return mapping,
- * x <- x + dt v_p.  Writes
- * the new state into the other buffer in sorted order (ids and materials permuted
- * alongside), computes the next cell keys, and flips p->current. */
+ * x <- x + dt v_p.  Writes the new state into the other buffer in the order of the
+ * preceding mpm_p2g (ids and materials permuted alongside), computes the next cell
+ * keys, and flips p->current. */
 mpm_status mpm_g2p(mpm_ctx *ctx, mpm_particles *p, double dt, void *stream);
 
 /* nsteps x (p2g, grid_update, g2p), enqueued back to back without host syncs. */
@@ -144,8 +146,9 @@ mpm_status mpm_sync(mpm_ctx *ctx, void *stream);
 mpm_status mpm_grid_read(mpm_ctx *ctx, float *m, float *vec, void *stream);
 
 /* Cell keys of the current buffer (computed from positions) and the stable sorting
- * permutation: keys[p] = block * 64 + cell as defined in mpm_p2g, perm[j] = index of the
- * j-th particle in key order (ties in index order).  Device output arrays of n. */
+ * permutation by key: keys[p] = block * 64 + cell (block = 4^3-cell block of the G- cell
+ * c = floor((x - origin)/dx + 1/4)), perm[j] = index of the j-th particle in key order
+ * (ties in index order).  Device output arrays of n.  Invalidates a pending mpm_g2p. */
 mpm_status mpm_sort_keys(mpm_ctx *ctx, const mpm_particles *p, uint32_t *keys, uint32_t *perm, void *stream);
 
 /* Forget cached cell keys: call after changing particle positions in place. */
@@ -163,8 +166,83 @@ const char *mpm_status_string(mpm_status s);
 int32_t mpm_abi_version(void);
 
 /* Device memory (bytes) a context with this configuration and particle capacity
- * holds, plus two ping-pong particle buffers of n particles with ids. */
+ * holds, plus two ping-pong particle buffers of n particles with ids and material
+ * indices, each buffer counted as the library's allocators pad it (256 bytes of
+ * slack, rounded up to 256).  This is exactly what a served job occupies. */
 int64_t mpm_footprint(const mpm_config *cfg, int64_t n);
+
+/* ------------------------------------------------------------------ serving
+ * A server runs many independent simulation jobs on one GPU with continuous
+ * batching.  It reserves its device memory once (an arena of memory_budget bytes)
+ * and never allocates after that.  A submitted job waits until a resident slot and
+ * enough arena memory (mpm_footprint of the job) are free; it is then admitted: its
+ * context and particle buffers are carved from the arena, its initial state is
+ * copied in, and from then on it stays resident in HBM and advances
+ * steps_per_launch steps at a time on one of the server's streams, interleaved with
+ * the other resident jobs.  After the first launch, a job's launches replay one
+ * HIP graph captured from that job's step sequence.  Finished jobs keep their final
+ * state until released.  All calls are non-blocking except mpm_server_drain,
+ * mpm_server_job_read and mpm_server_destroy.  Calls on one server must not overlap
+ * (one thread at a time). */
+typedef struct mpm_server mpm_server;
+
+typedef struct {
+    int64_t memory_budget;     /* arena bytes for resident jobs (allocated in mpm_server_create)      */
+    int32_t max_jobs;          /* resident (admitted, unreleased) jobs at most, >= 1                   */
+    int32_t n_streams;         /* HIP streams the jobs are spread over, 1..64                          */
+    int32_t steps_per_launch;  /* steps per launch, even (the ping-pong buffer returns to its start)  */
+    int32_t flags;             /* reserved, 0                                                          */
+} mpm_server_config;
+
+typedef struct {
+    mpm_config cfg;            /* grid, walls and capacities of the job (max_particles >= n)           */
+    const mpm_material *mats;  /* copied at submission                                                 */
+    int32_t n_mat;
+    int32_t nsteps;            /* steps to run, >= 0                                                   */
+    int64_t n;                 /* particles, >= 1                                                      */
+    const float *state;        /* initial state (device), 24 planes of stride n, H = F - I; copied at
+                                  admission, so it must stay valid while the job is pending           */
+    const uint8_t *mat;        /* optional per-particle material index (device, n), or NULL           */
+    double dt;
+} mpm_job_desc;
+
+enum { MPM_JOB_PENDING = 0, MPM_JOB_ACTIVE = 1, MPM_JOB_DONE = 2, MPM_JOB_FAILED = 3 };
+
+typedef struct {
+    int32_t state;             /* MPM_JOB_*                                                            */
+    int32_t steps_done;
+    int64_t n;
+    int64_t footprint;         /* arena bytes while resident                                           */
+    double t_submit, t_admit, t_done;   /* seconds on the server's clock (0 until reached)           */
+    mpm_status status;         /* outcome: MPM_OK when done, the device status when failed             */
+    int32_t reserved;
+} mpm_job_info;
+
+/* Allocates the arena and the streams (default priority). */
+mpm_status mpm_server_create(const mpm_server_config *cfg, mpm_server **out);
+/* Waits for every stream, then frees everything, including unreleased jobs. */
+mpm_status mpm_server_destroy(mpm_server *srv);
+/* Queues a job (validated on the host; MPM_E_CAPACITY if its footprint exceeds the
+ * whole budget).  Job ids start at 0 and increase by one per submission. */
+mpm_status mpm_server_submit(mpm_server *srv, const mpm_job_desc *job, int64_t *job_id);
+/* Retires finished launches, admits waiting jobs in submission order and enqueues
+ * the next launch of every resident job that has none in flight.  Returns at once;
+ * the counts are optional. */
+mpm_status mpm_server_poll(mpm_server *srv, int32_t *n_pending, int32_t *n_active, int32_t *n_done);
+/* Polls until no job is pending or active (blocking on in-flight launches). */
+mpm_status mpm_server_drain(mpm_server *srv);
+mpm_status mpm_server_job_info(mpm_server *srv, int64_t job_id, mpm_job_info *info);
+/* Copies a finished job's state (24 planes of stride n) and particle ids (the
+ * initial index of each particle; the state is in the library's particle order)
+ * into device buffers; either pointer may be NULL.  Synchronous. */
+mpm_status mpm_server_job_read(mpm_server *srv, int64_t job_id, float *state, uint32_t *ids);
+/* Returns a finished job's memory to the arena. */
+mpm_status mpm_server_job_release(mpm_server *srv, int64_t job_id);
+/* Per-step latencies (seconds, GPU event time between the ends of consecutive
+ * launches of a job divided by the launch's steps; the first launch of a job is
+ * timed from its admission).  Writes up to cap values in completion order and the
+ * total count to *count. */
+mpm_status mpm_server_step_latencies(mpm_server *srv, double *out, int64_t cap, int64_t *count);
 
 #ifdef __cplusplus
 }

@@ -55,9 +55,30 @@ class mpm_stats(ctypes.Structure):
                 ("reserved", ctypes.c_uint32)]
 
 
+class mpm_server_config(ctypes.Structure):
+    _fields_ = [("memory_budget", ctypes.c_int64), ("max_jobs", ctypes.c_int32), ("n_streams", ctypes.c_int32),
+                ("steps_per_launch", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class mpm_job_desc(ctypes.Structure):
+    _fields_ = [("cfg", mpm_config), ("mats", ctypes.POINTER(mpm_material)), ("n_mat", ctypes.c_int32),
+                ("nsteps", ctypes.c_int32), ("n", ctypes.c_int64), ("state", ctypes.c_void_p),
+                ("mat", ctypes.c_void_p), ("dt", ctypes.c_double)]
+
+
+class mpm_job_info(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("steps_done", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("footprint", ctypes.c_int64), ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("status", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+MPM_JOB_PENDING, MPM_JOB_ACTIVE, MPM_JOB_DONE, MPM_JOB_FAILED = range(4)
+
 EXPORTS = ("mpm_create", "mpm_destroy", "mpm_p2g", "mpm_grid_update", "mpm_g2p", "mpm_step", "mpm_sync",
            "mpm_grid_read", "mpm_sort_keys", "mpm_invalidate", "mpm_get_stats", "mpm_profile_enable",
-           "mpm_profile_read", "mpm_status_string", "mpm_abi_version", "mpm_footprint")
+           "mpm_profile_read", "mpm_status_string", "mpm_abi_version", "mpm_footprint", "mpm_server_create",
+           "mpm_server_destroy", "mpm_server_submit", "mpm_server_poll", "mpm_server_drain", "mpm_server_job_info",
+           "mpm_server_job_read", "mpm_server_job_release", "mpm_server_step_latencies")
 
 
 def lib():
@@ -87,6 +108,16 @@ def lib():
         L.mpm_abi_version.restype = ctypes.c_int32
         L.mpm_footprint.argtypes = [ctypes.POINTER(mpm_config), ctypes.c_int64]
         L.mpm_footprint.restype = ctypes.c_int64
+        i32p, i64p = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
+        L.mpm_server_create.argtypes = [ctypes.POINTER(mpm_server_config), ctypes.POINTER(vp)]
+        L.mpm_server_destroy.argtypes = [vp]
+        L.mpm_server_submit.argtypes = [vp, ctypes.POINTER(mpm_job_desc), i64p]
+        L.mpm_server_poll.argtypes = [vp, i32p, i32p, i32p]
+        L.mpm_server_drain.argtypes = [vp]
+        L.mpm_server_job_info.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(mpm_job_info)]
+        L.mpm_server_job_read.argtypes = [vp, ctypes.c_int64, vp, vp]
+        L.mpm_server_job_release.argtypes = [vp, ctypes.c_int64]
+        L.mpm_server_step_latencies.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int64, i64p]
         for name in EXPORTS:
             if name not in ("mpm_status_string", "mpm_abi_version", "mpm_footprint"):
                 getattr(L, name).restype = st
@@ -176,6 +207,56 @@ def mpm_footprint(cfg: mpm_config, n: int) -> int:
     return int(lib().mpm_footprint(ctypes.byref(cfg), int(n)))
 
 
+def mpm_server_create(cfg: mpm_server_config):
+    h = ctypes.c_void_p()
+    s = lib().mpm_server_create(ctypes.byref(cfg), ctypes.byref(h))
+    return s, h
+
+
+def mpm_server_destroy(srv) -> int:
+    return lib().mpm_server_destroy(srv)
+
+
+def mpm_server_submit(srv, desc: mpm_job_desc):
+    jid = ctypes.c_int64(-1)
+    s = lib().mpm_server_submit(srv, ctypes.byref(desc), ctypes.byref(jid))
+    return s, jid.value
+
+
+def mpm_server_poll(srv):
+    p, a, d = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    s = lib().mpm_server_poll(srv, ctypes.byref(p), ctypes.byref(a), ctypes.byref(d))
+    return s, p.value, a.value, d.value
+
+
+def mpm_server_drain(srv) -> int:
+    return lib().mpm_server_drain(srv)
+
+
+def mpm_server_job_info(srv, job_id: int):
+    out = mpm_job_info()
+    s = lib().mpm_server_job_info(srv, int(job_id), ctypes.byref(out))
+    return s, out
+
+
+def mpm_server_job_read(srv, job_id: int, state_ptr: Optional[int], ids_ptr: Optional[int]) -> int:
+    return lib().mpm_server_job_read(srv, int(job_id), state_ptr, ids_ptr)
+
+
+def mpm_server_job_release(srv, job_id: int) -> int:
+    return lib().mpm_server_job_release(srv, int(job_id))
+
+
+def mpm_server_step_latencies(srv):
+    count = ctypes.c_int64(0)
+    s = lib().mpm_server_step_latencies(srv, None, 0, ctypes.byref(count))
+    if s != MPM_OK or count.value == 0:
+        return s, []
+    buf = (ctypes.c_double * count.value)()
+    s = lib().mpm_server_step_latencies(srv, buf, count.value, ctypes.byref(count))
+    return s, list(buf)
+
+
 def status_string(status: int) -> str:
     try:
         return mpm_status_string(status)
@@ -212,6 +293,32 @@ def make_material(model, E, nu, rho, vol0, friction_deg=30.0) -> mpm_material:
     return m
 
 
+def state_planes(x, v, B, F):
+    """Host arrays (N,3), (N,3), (N,3,3), (N,3,3) as the (24, N) FP32 state layout;
+    the deformation gradient is stored as H = F - I (formed in FP64, then rounded)."""
+    import numpy as np
+    n = len(x)
+    planes = np.zeros((MPM_STATE_PLANES, n), np.float32)
+    planes[X0:X0 + 3] = np.asarray(x, np.float32).reshape(n, 3).T
+    planes[V0:V0 + 3] = np.asarray(v, np.float32).reshape(n, 3).T
+    planes[B0:B0 + 9] = np.asarray(B, np.float32).reshape(n, 9).T
+    H = np.asarray(F, np.float64).reshape(n, 3, 3) - np.eye(3)[None]
+    planes[F0:F0 + 9] = H.reshape(n, 9).T.astype(np.float32)
+    return planes
+
+
+def unpack_state(planes, ids=None):
+    """(24, N) state planes (host) as dict(x, v, B, H, F[, id]); F = I + H in FP64."""
+    import numpy as np
+    n = planes.shape[1]
+    H = planes[F0:F0 + 9].T.reshape(n, 3, 3).copy()
+    out = dict(x=planes[X0:X0 + 3].T.copy(), v=planes[V0:V0 + 3].T.copy(),
+               B=planes[B0:B0 + 9].T.reshape(n, 3, 3).copy(), H=H, F=H.astype(np.float64) + np.eye(3)[None])
+    if ids is not None:
+        out["id"] = np.asarray(ids).copy()
+    return out
+
+
 class Particles:
     """Device particle storage: two ping-pong buffers of 24 FP32 planes, ids and
     optional material indices, as torch tensors on a GPU."""
@@ -242,12 +349,7 @@ class Particles:
         import numpy as np
         import torch
         n = self.n
-        planes = np.zeros((MPM_STATE_PLANES, n), np.float32)
-        planes[X0:X0 + 3] = np.asarray(x, np.float32).reshape(n, 3).T
-        planes[V0:V0 + 3] = np.asarray(v, np.float32).reshape(n, 3).T
-        planes[B0:B0 + 9] = np.asarray(B, np.float32).reshape(n, 9).T
-        H = np.asarray(F, np.float64).reshape(n, 3, 3) - np.eye(3)[None]
-        planes[F0:F0 + 9] = H.reshape(n, 9).T.astype(np.float32)
+        planes = state_planes(x, v, B, F)
         cur = self.current
         self.state[cur, :, :n].copy_(torch.from_numpy(planes))
         idv = np.arange(n, dtype=np.int32) if ids is None else np.asarray(ids, np.int32)
@@ -317,3 +419,102 @@ def particles_from_scene(sc, device="cuda") -> Particles:
     p = Particles(sc.n, device=device, with_mat=len(sc.materials) > 1)
     p.load(sc.x, sc.v, sc.B, sc.F, mat=sc.mat)
     return p
+
+
+def job_config(sc, margin_blocks: int = 3) -> mpm_config:
+    """mpm_config for a served job: capacities sized to the scene's extent (blocks
+    of the particles' bounding box grown by a margin on every side, twice over for
+    the two grids) rather than to the whole grid."""
+    import numpy as np
+    lo = np.floor(sc.x.min(axis=0) / sc.dx).astype(np.int64)
+    hi = np.floor(sc.x.max(axis=0) / sc.dx).astype(np.int64)
+    nb = 1
+    for a in range(3):
+        nb *= int((hi[a] - lo[a]) // 4 + 2 + 2 * margin_blocks)
+    return scene_config(sc, max_particles=sc.n, max_blocks=2 * nb + 64)
+
+
+class Server:
+    """RAII holder for an mpm_server handle, with torch-owned job inputs kept alive
+    until the job is released."""
+
+    def __init__(self, memory_budget: int, max_jobs: int = 32, n_streams: int = 4, steps_per_launch: int = 8):
+        cfg = mpm_server_config()
+        cfg.memory_budget = int(memory_budget)
+        cfg.max_jobs = int(max_jobs)
+        cfg.n_streams = int(n_streams)
+        cfg.steps_per_launch = int(steps_per_launch)
+        cfg.flags = 0
+        s, h = mpm_server_create(cfg)
+        check(s, "mpm_server_create")
+        self.h = h
+        self._inputs = {}
+
+    def submit(self, cfg: mpm_config, mats: Sequence[mpm_material], state, nsteps: int, dt: float, mat=None) -> int:
+        """Queue a job; `state` is a (24, n) float32 CUDA tensor (H = F - I), `mat` an
+        optional (n,) uint8 CUDA tensor."""
+        arr = (mpm_material * len(mats))(*mats)
+        d = mpm_job_desc()
+        d.cfg = cfg
+        d.mats = arr
+        d.n_mat = len(mats)
+        d.nsteps = int(nsteps)
+        d.n = int(state.shape[1])
+        d.state = state.data_ptr()
+        d.mat = mat.data_ptr() if mat is not None else None
+        d.dt = float(dt)
+        s, jid = mpm_server_submit(self.h, d)
+        check(s, "mpm_server_submit")
+        self._inputs[jid] = (state, mat)
+        return jid
+
+    def submit_scene(self, sc, nsteps: int, device="cuda") -> int:
+        import torch
+        state = torch.from_numpy(state_planes(sc.x, sc.v, sc.B, sc.F)).to(device)
+        mat = torch.from_numpy(sc.mat.astype("uint8")).to(device) if len(sc.materials) > 1 else None
+        return self.submit(job_config(sc), scene_materials(sc), state, nsteps, sc.dt, mat)
+
+    def poll(self):
+        s, p, a, d = mpm_server_poll(self.h)
+        check(s, "mpm_server_poll")
+        return p, a, d
+
+    def drain(self):
+        check(mpm_server_drain(self.h), "mpm_server_drain")
+
+    def info(self, jid: int) -> mpm_job_info:
+        s, out = mpm_server_job_info(self.h, jid)
+        check(s, "mpm_server_job_info")
+        return out
+
+    def read(self, jid: int):
+        """Final state of a finished job, reordered so that row k holds particle k."""
+        import torch
+        n = int(self.info(jid).n)
+        st = torch.empty((MPM_STATE_PLANES, n), dtype=torch.float32, device="cuda")
+        ids = torch.empty(n, dtype=torch.int32, device="cuda")
+        check(mpm_server_job_read(self.h, jid, st.data_ptr(), ids.data_ptr()), "mpm_server_job_read")
+        d = unpack_state(st.cpu().numpy(), ids.cpu().numpy())
+        order = d["id"].argsort(kind="stable")
+        return {k: v[order] for k, v in d.items()}
+
+    def release(self, jid: int):
+        check(mpm_server_job_release(self.h, jid), "mpm_server_job_release")
+        self._inputs.pop(jid, None)
+
+    def step_latencies(self):
+        s, lat = mpm_server_step_latencies(self.h)
+        check(s, "mpm_server_step_latencies")
+        return lat
+
+    def close(self):
+        if self.h is not None and self.h.value:
+            mpm_server_destroy(self.h)
+        self.h = None
+        self._inputs.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

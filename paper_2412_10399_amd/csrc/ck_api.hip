@@ -6,8 +6,7 @@
 #include <new>
 #include <vector>
 
-#include "../../include/ckmpm.h"
-#include "ck_common.hpp"
+#include "ck_ctx.hpp"
 
 using namespace ck;
 
@@ -148,13 +147,14 @@ mpm_status dalloc(mpm_ctx *ctx, T **ptr, size_t count) {
     return MPM_OK;
 }
 
-// Bytes of every device buffer a context allocates (each rounded as dalloc does).
-int64_t ctx_device_bytes(const mpm_config &c) {
+// Bytes of every device buffer a context allocates: dalloc asks for 256 bytes of
+// slack per buffer, and allocators hand out multiples of 256 bytes.
+int64_t device_bytes_of(const mpm_config &c) {
     long long nbv = 1;
     for (int a = 0; a < 3; ++a) nbv *= (c.n_cells[a] / 4 + 1);
     const long long np = c.max_particles, nb = c.max_blocks;
     const long long nchunks = (nbv + kCompactChunk - 1) / kCompactChunk;
-    auto r = [](long long bytes) { return bytes + 256; };
+    auto r = [](long long bytes) { return (bytes + 256 + 255) / 256 * 256; };
     return r(4 * np) + r(2 * np) + r(4 * np) + r(4 * nb * (long long)kMaxBlockParticles) + r(8 * nbv) + r(8 * nbv) + r(4 * nbv) +
            r(4 * nbv) + r(4 * nb) + r(4 * (nb + 1)) + r(4 * nb) + r(4 * nb) + r(4 * nchunks) + r(4 * nchunks) +
            r(4 * nb * (long long)kBlockFloats) + r(24 * np) + r(4 * (long long)C_COUNT);
@@ -245,8 +245,6 @@ mpm_status enqueue_g2p(mpm_ctx *ctx, mpm_particles *p, double dt, hipStream_t s)
 
 namespace ck {
 
-void ctx_destroy(mpm_ctx *ctx, bool device_sync);
-
 mpm_status ctx_create(const mpm_config *cfg, const mpm_material *mats, int32_t n_mat, const Allocator *alloc,
                       hipStream_t init_stream, bool device_sync, mpm_ctx **out) {
     if (!out) return MPM_E_INVALID;
@@ -324,9 +322,11 @@ void ctx_destroy(mpm_ctx *ctx, bool device_sync) {
     delete ctx;
 }
 
-mpm_status ctx_read_status(mpm_ctx *ctx) {
-    unsigned int bits = 0;
-    if (hipMemcpy(&bits, ctx->d.counters + C_STATUS, sizeof bits, hipMemcpyDeviceToHost) != hipSuccess) return MPM_E_HIP;
+unsigned int *ctx_status_word(mpm_ctx *ctx) { return ctx->d.counters + C_STATUS; }
+
+int64_t ctx_device_bytes(const mpm_config &c) { return device_bytes_of(c); }
+
+mpm_status status_from_bits(unsigned int bits) {
     if (bits & ST_NONFINITE) return MPM_E_NONFINITE;
     if (bits & ST_DOMAIN) return MPM_E_DOMAIN;
     if (bits & ST_CAPACITY) return MPM_E_CAPACITY;
@@ -366,7 +366,8 @@ mpm_status mpm_destroy(mpm_ctx *ctx) {
 
 int64_t mpm_footprint(const mpm_config *cfg, int64_t n) {
     if (!cfg) return 0;
-    return ctx_device_bytes(*cfg) + 2 * (int64_t)MPM_STATE_PLANES * 4 * n + 2 * 4 * n + 2 * n + 3 * 256;
+    auto r = [](long long bytes) { return (bytes + 256 + 255) / 256 * 256; };
+    return device_bytes_of(*cfg) + 2 * (r((int64_t)MPM_STATE_PLANES * 4 * n) + r(4 * n) + r(n));
 }
 
 mpm_status mpm_p2g(mpm_ctx *ctx, const mpm_particles *p, double dt, void *stream) {
@@ -422,11 +423,7 @@ mpm_status mpm_sync(mpm_ctx *ctx, void *stream) {
     if (hipMemcpy(&bits, ctx->d.counters + C_STATUS, sizeof bits, hipMemcpyDeviceToHost) != hipSuccess) return MPM_E_HIP;
     const unsigned int zero = 0;
     if (hipMemcpy(ctx->d.counters + C_STATUS, &zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess) return MPM_E_HIP;
-    if (bits & ST_NONFINITE) return MPM_E_NONFINITE;
-    if (bits & ST_DOMAIN) return MPM_E_DOMAIN;
-    if (bits & ST_CAPACITY) return MPM_E_CAPACITY;
-    if (bits & ST_STALE) return MPM_E_STALE;
-    return MPM_OK;
+    return status_from_bits(bits);
 }
 
 mpm_status mpm_grid_read(mpm_ctx *ctx, float *m, float *vec, void *stream) {

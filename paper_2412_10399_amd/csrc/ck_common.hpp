@@ -467,7 +467,11 @@ __device__ __forceinline__ void dp_return_map_eig(const DevMaterial &m, float H[
 //   fixed corotated              (F - R) F^T = b - b^(1/2) = E/2 + E^2/8 - E^3/16 + 5E^4/128 - ...,
 //   return mapping               F' = exp(eps' - eps) F (eps and eps' share eigenvectors),
 //                                 tip: F' = exp(-eps) F = R.
-// Six terms reach FP32 rounding for |E|_F <= 0.05; larger strains (and inverted
+// The number of terms is chosen per wave from the largest Frobenius norm r among its
+// lanes (a bound on the spectral norm), so that the first omitted term stays below
+// FP32 rounding relative to the sum: for the logarithm (and the square-root series,
+// whose coefficients are smaller) degree K suffices while r^K / (K+1) <= 6e-8, for
+// the exponential while r^K / (K+1)! <= 6e-8.  Strains with r > 0.05 (and inverted
 // elements) take the eigen-decomposition path above.
 struct Sym3 {
     float xx, yy, zz, xy, xz, yz;
@@ -496,7 +500,30 @@ __device__ __forceinline__ Sym3 horner_step(float c0, const Sym3 &E, const Sym3 
 
 __device__ __forceinline__ Sym3 scaled_identity(float c) { return Sym3{c, c, c, 0.0f, 0.0f, 0.0f}; }
 
+// sum_{k=1..K} c[k] E^k by Horner's rule (K >= 1, the same on every lane of the wave)
+__device__ __forceinline__ Sym3 power_series(const Sym3 &E, const float *c, int K) {
+    Sym3 acc = scaled_identity(c[K]);
+    for (int k = K - 1; k >= 1; --k) acc = horner_step(c[k], E, acc);
+    return sym_mul(E, acc);
+}
+
 constexpr float kSeriesMax2 = 0.0025f;   // |E|_F^2 <= 0.05^2
+
+// Largest degree needed on the wave: K = kmin + number of thresholds some lane's r^2 exceeds.
+__device__ __forceinline__ int wave_terms(float r2, const float *thr2, int n, int kmin) {
+    int K = kmin;
+    for (int i = 0; i < n; ++i) K += __any(r2 > thr2[i]) ? 1 : 0;
+    return K;
+}
+
+// r^2 thresholds for degrees 2..6 of the logarithm and 2..5 of the exponential
+__device__ __constant__ const float kLogThr2[4] = {1.7e-7f, 3.8e-5f, 5.4e-4f, 1.6e-3f};
+__device__ __constant__ const float kExpThr2[3] = {3.6e-7f, 1.28e-4f, 2.7e-3f};
+// coefficients, index = degree
+__device__ __constant__ const float kLogHalf[7] = {0.0f, 0.5f, -0.25f, 1.0f / 6.0f, -0.125f, 0.1f, -1.0f / 12.0f};
+__device__ __constant__ const float kExpm1[6] = {0.0f, 1.0f, 0.5f, 1.0f / 6.0f, 1.0f / 24.0f, 1.0f / 120.0f};
+__device__ __constant__ const float kSqrtDiff[7] = {0.0f,           0.5f,           0.125f,        -1.0f / 16.0f,
+                                                    5.0f / 128.0f, -7.0f / 256.0f, 21.0f / 1024.0f};
 
 __device__ __forceinline__ Sym3 left_cauchy_green_minus_I(const float H[9]) {
     Sym3 E;
@@ -513,27 +540,14 @@ __device__ __forceinline__ float frob2(const Sym3 &a) {
     return a.xx * a.xx + a.yy * a.yy + a.zz * a.zz + 2.0f * (a.xy * a.xy + a.xz * a.xz + a.yz * a.yz);
 }
 
-// 1/2 log(I + E), series to E^6
-__device__ __forceinline__ Sym3 hencky_series(const Sym3 &E) {
-    Sym3 acc = scaled_identity(-1.0f / 6.0f);
-    acc = horner_step(1.0f / 5.0f, E, acc);
-    acc = horner_step(-1.0f / 4.0f, E, acc);
-    acc = horner_step(1.0f / 3.0f, E, acc);
-    acc = horner_step(-1.0f / 2.0f, E, acc);
-    acc = horner_step(1.0f, E, acc);
-    Sym3 L = sym_mul(E, acc);
-    return Sym3{0.5f * L.xx, 0.5f * L.yy, 0.5f * L.zz, 0.5f * L.xy, 0.5f * L.xz, 0.5f * L.yz};
+// 1/2 log(I + E)
+__device__ __forceinline__ Sym3 hencky_series(const Sym3 &E, float r2) {
+    return power_series(E, kLogHalf, wave_terms(r2, kLogThr2, 4, 2));
 }
 
-// exp(X) - I, series to X^6
+// exp(X) - I
 __device__ __forceinline__ Sym3 expm1_series(const Sym3 &X) {
-    Sym3 acc = scaled_identity(1.0f / 720.0f);
-    acc = horner_step(1.0f / 120.0f, X, acc);
-    acc = horner_step(1.0f / 24.0f, X, acc);
-    acc = horner_step(1.0f / 6.0f, X, acc);
-    acc = horner_step(1.0f / 2.0f, X, acc);
-    acc = horner_step(1.0f, X, acc);
-    return sym_mul(X, acc);
+    return power_series(X, kExpm1, wave_terms(frob2(X), kExpThr2, 3, 2));
 }
 
 // H <- H + G (I + H), i.e. F <- (I + G) F
@@ -555,32 +569,26 @@ __device__ __forceinline__ void store_tau(const Sym3 &t, float tau[6]) {
 
 // The path is chosen per wave: if any active lane needs the decomposition, the
 // whole wave takes it (both forms agree to FP32 rounding), so no wave runs both.
-__device__ __forceinline__ bool wave_needs_eig(const Sym3 &E, float jm1) {
-    return __any(frob2(E) > kSeriesMax2 || 1.0f + jm1 <= 0.0f);
+__device__ __forceinline__ bool wave_needs_eig(float r2, float jm1) {
+    return __any(r2 > kSeriesMax2 || 1.0f + jm1 <= 0.0f);
 }
 
 __device__ __forceinline__ void kirchhoff(const DevMaterial &m, const float H[9], float tau[6]) {
     const Sym3 E = left_cauchy_green_minus_I(H);
     const float jm1 = det_minus_one(H);
-    if (wave_needs_eig(E, jm1)) {
+    const float r2 = frob2(E);
+    if (wave_needs_eig(r2, jm1)) {
         kirchhoff_eig(m, H, tau);
         return;
     }
     Sym3 t;
     if (m.model == 0) {
-        // (b - b^(1/2)): coefficients 1/2, 1/8, -1/16, 5/128, -7/256, 21/1024
-        Sym3 acc = scaled_identity(21.0f / 1024.0f);
-        acc = horner_step(-7.0f / 256.0f, E, acc);
-        acc = horner_step(5.0f / 128.0f, E, acc);
-        acc = horner_step(-1.0f / 16.0f, E, acc);
-        acc = horner_step(1.0f / 8.0f, E, acc);
-        acc = horner_step(1.0f / 2.0f, E, acc);
-        const Sym3 D = sym_mul(E, acc);
+        const Sym3 D = power_series(E, kSqrtDiff, wave_terms(r2, kLogThr2, 4, 2));
         const float iso = m.lambda * jm1 * (1.0f + jm1);
         const float k = 2.0f * m.mu;
         t = Sym3{k * D.xx + iso, k * D.yy + iso, k * D.zz + iso, k * D.xy, k * D.xz, k * D.yz};
     } else {
-        const Sym3 e = hencky_series(E);
+        const Sym3 e = hencky_series(E, r2);
         const float iso = m.lambda * (e.xx + e.yy + e.zz);
         const float k = 2.0f * m.mu;
         t = Sym3{k * e.xx + iso, k * e.yy + iso, k * e.zz + iso, k * e.xy, k * e.xz, k * e.yz};
@@ -588,36 +596,32 @@ __device__ __forceinline__ void kirchhoff(const DevMaterial &m, const float H[9]
     store_tau(t, tau);
 }
 
+// Series form of the return mapping above.  The three cases differ only in the
+// strain correction X (tip: -eps, projection: -k eps_hat, inside the cone: 0), so
+// one exponential serves the whole wave: exp(0) - I = 0 leaves H unchanged.
 __device__ __forceinline__ void dp_return_map(const DevMaterial &m, float H[9], float tau[6]) {
     const Sym3 E = left_cauchy_green_minus_I(H);
     const float jm1 = det_minus_one(H);
-    if (wave_needs_eig(E, jm1)) {
+    const float r2 = frob2(E);
+    if (wave_needs_eig(r2, jm1)) {
         dp_return_map_eig(m, H, tau);
         return;
     }
-    const Sym3 e = hencky_series(E);
+    const Sym3 e = hencky_series(E, r2);
     const float tr = e.xx + e.yy + e.zz;
     const float t3 = tr * (1.0f / 3.0f);
     const Sym3 dev{e.xx - t3, e.yy - t3, e.zz - t3, e.xy, e.xz, e.yz};
     const float dn = fast_sqrt(frob2(dev));
-    const float k2 = 2.0f * m.mu;
-    if (tr > 0.0f || dn == 0.0f) {
-        // cone tip: F' = exp(-eps) F, stress free
-        apply_left(expm1_series(Sym3{-e.xx, -e.yy, -e.zz, -e.xy, -e.xz, -e.yz}), H);
-#pragma unroll
-        for (int i = 0; i < 6; ++i) tau[i] = 0.0f;
-        return;
-    }
+    const bool tip = tr > 0.0f || dn == 0.0f;
     const float dgamma = dn + m.dp_coef * tr;
-    const float iso = m.lambda * tr;
-    if (dgamma <= 0.0f) {
-        store_tau(Sym3{k2 * e.xx + iso, k2 * e.yy + iso, k2 * e.zz + iso, k2 * e.xy, k2 * e.xz, k2 * e.yz}, tau);
-        return;
-    }
+    const bool proj = !tip && dgamma > 0.0f;
     // eps' = eps - k eps_hat: F' = exp(-k eps_hat) F, tau from eps' (same trace)
-    const float k = dgamma * fast_rcp(dn);
-    const Sym3 X{-k * dev.xx, -k * dev.yy, -k * dev.zz, -k * dev.xy, -k * dev.xz, -k * dev.yz};
-    apply_left(expm1_series(X), H);
+    const float k = proj ? dgamma * fast_rcp(dn) : 0.0f;
+    const Sym3 X = tip ? Sym3{-e.xx, -e.yy, -e.zz, -e.xy, -e.xz, -e.yz}
+                       : Sym3{-k * dev.xx, -k * dev.yy, -k * dev.zz, -k * dev.xy, -k * dev.xz, -k * dev.yz};
+    if (__any(tip || proj)) apply_left(expm1_series(X), H);
+    const float k2 = tip ? 0.0f : 2.0f * m.mu;
+    const float iso = tip ? 0.0f : m.lambda * tr;
     store_tau(Sym3{k2 * (e.xx + X.xx) + iso, k2 * (e.yy + X.yy) + iso, k2 * (e.zz + X.zz) + iso, k2 * (e.xy + X.xy),
                    k2 * (e.xz + X.xz), k2 * (e.yz + X.yz)},
               tau);

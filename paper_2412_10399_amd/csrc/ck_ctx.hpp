@@ -1,0 +1,24 @@
+// Library-internal access to contexts for other parts of the library (the job
+// server): creation on a given allocator and stream, destruction, status word.
+#pragma once
+
+#include "../../include/ckmpm.h"
+#include "ck_common.hpp"
+
+namespace ck {
+
+// Creates a context whose device buffers come from `alloc`; the initial clears run
+// on `init_stream`, which is then synchronised (the whole device when device_sync).
+mpm_status ctx_create(const mpm_config *cfg, const mpm_material *mats, int32_t n_mat, const Allocator *alloc,
+                      hipStream_t init_stream, bool device_sync, mpm_ctx **out);
+// Returns every buffer to the context's allocator (after a device-wide
+// synchronisation when device_sync; otherwise the caller guarantees that no work
+// on the context is pending).
+void ctx_destroy(mpm_ctx *ctx, bool device_sync);
+// Device address of the context's status word (sticky error bits of the steps).
+unsigned int *ctx_status_word(mpm_ctx *ctx);
+mpm_status status_from_bits(unsigned int bits);
+// Device bytes of every buffer a context with this configuration allocates.
+int64_t ctx_device_bytes(const mpm_config &c);
+
+}  // namespace ck

@@ -78,22 +78,15 @@ __device__ __forceinline__ int round_block(int base, int np) {
     return (y < per && i < m) ? base + i : -1;
 }
 
-struct Particle {
-    float x[3], v[3], B[9], H[9];   // H = F - I
-};
-
-__device__ __forceinline__ void load_particle(const PartArgs &pa, int p, Particle &q, bool full) {
-    const long long S = pa.stride;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) q.x[a] = pa.in[a * S + p];
-    if (full) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) q.v[a] = pa.in[(3 + a) * S + p];
-#pragma unroll
-        for (int a = 0; a < 9; ++a) q.B[a] = pa.in[(6 + a) * S + p];
-    }
-#pragma unroll
-    for (int a = 0; a < 9; ++a) q.H[a] = pa.in[(15 + a) * S + p];
+// Element i of an array whose base is uniform across the wave: 32-bit byte offset
+// on a scalar base (one instruction, no 64-bit address arithmetic per access).
+template <typename T>
+__device__ __forceinline__ T ld_at(const T *base, uint32_t i) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + (size_t)(i * (uint32_t)sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ void st_at(T *base, uint32_t i, T v) {
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + (size_t)(i * (uint32_t)sizeof(T))) = v;
 }
 
 // ---------------------------------------------------------------- block sort
@@ -188,217 +181,181 @@ __global__ void __launch_bounds__(kThreads) k_stress(DevCtx d, PartArgs pa) {
 //   Q = (m_p B_p - dt V_p^0 tau_p) D_p^-1,
 // where grad Phi_i = w D^-1 (x_i - x_p) and f_i = -V^0 tau grad Phi_i.  In cell units,
 // with xi the particle's fractional position in its G- cell c, G- node c + o
-// (o in {0,1}^3) sits at x_i - x_p = dx (o - xi) and G+ node c + r at
-// dx (r + 1/2 - xi), G+ being shifted half a cell from G-.  With base = m_p v_p - Q xi
-// the momenta are base + Q o and base + Q (r + 1/2).
+// (o in {0,1}^3) sits at x_i - x_p = dx (o - xi) and G+ node bp + o at
+// dx (o + bp - c + 1/2 - xi), G+ being shifted half a cell from G-.  With
+// base = m_p v_p - Q xi the momenta are base + Q o and base + Q (o + bp - c + 1/2).
 //
-// One wave per block, lane c owning G- cell c of the block, and no atomics inside
-// the block (LDS float atomics run about a hundred times slower than plain LDS
-// traffic on gfx950).  A particle in the upper or lower half of its cell along an
-// axis reaches G+ nodes c, c + 1 or c - 1, c on that axis, so the half-cell octant
-// fixes which 8 of the 27 G+ nodes around c it touches.  The block's particles are
-// therefore ordered by (octant, cell, index); for each octant in turn, the wave
-// stages that octant's particles as compact records in LDS (lane = particle,
-// coalesced reads: the previous G2P wrote the state in this order), and lane c sums
-// the records of cell c into registers: 8 G- nodes and, at indices known at compile
-// time for the octant, 8 of its 27 G+ nodes.  The register sums are then added into
-// the LDS tile in conflict-free phases (every lane targets a different node in a
-// phase) and each nonzero tile node is flushed to the pool with one global atomic.
-constexpr int kP2GThreads = 64;
+// One workgroup per block, one thread per particle, and the block's 341-node tile
+// in LDS as 64-bit fixed-point integers: LDS float atomics run about 26 times slower
+// than 64-bit integer atomics on gfx950, and integer sums are exact, so the tile is
+// independent of the order of the additions.  The unit of the fixed-point numbers is
+// chosen per block from a bound on every contribution (2^-39 of the largest, so a
+// node's sum of at most 2048 x 8 contributions stays below 2^51 and converts exactly
+// through FP64).  Particles are ordered by (half-cell octant, cell, index): within an
+// octant the particles of a wave mostly sit in different cells, so the lanes of one
+// atomic instruction rarely target the same node.  The tile is then converted back
+// and each nonzero node is added to the pool with one global float atomic.
+constexpr int kP2GThreads = 256;
 constexpr int kBins = 512;                 // (octant, cell) bins of a block: octant * 64 + cell
-constexpr int kRecVec = 5;                 // float4 per staged record
-constexpr int kHold = 8;                   // bucket entries per lane kept in registers
-constexpr uint32_t kNoRecord = 0xffffu;
+constexpr int kPerThread = kMaxBlockParticles / kP2GThreads;   // bucket entries per thread
+constexpr int kHold = 2;                   // of which kept in registers
+constexpr int kChunk = 2 * kP2GThreads;    // particles scattered per pass (two per thread)
+constexpr double kMagic = 6755399441055744.0;                  // 1.5 * 2^52
+constexpr long long kMagicBits = 0x4338000000000000LL;
 
-// Record: xi[3] s+[3] m_p base[3] Q[9] (row-major), sub code.
+__device__ __forceinline__ int bin_of(uint32_t sub) { return (int)((sub & 7u) * 64u + (sub >> 3)); }
+
+// v * S rounded to an integer, |v S| < 2^51: in the binade [2^52, 2^53) FP64 numbers
+// are the integers, so the bit pattern of magic + v S is that of magic plus v S.
+__device__ __forceinline__ unsigned long long to_fixed(float v, double S) {
+    const double d = fma((double)v, S, kMagic);
+    return (unsigned long long)(__double_as_longlong(d) - kMagicBits);
+}
+
+struct Staged {
+    float xm[3], sp[3], mass, base[3], Q[9];
+    int cell;       // G- cell in the block, -1 when the particle does not take part
+    int oct;        // half-cell octant
+};
+
 __device__ __forceinline__ void stage_particle(const DevCtx &d, const PartArgs &pa, int p, int bx, int by, int bz,
-                                               float dt, float4 *rec) {
-    float out[19];
-#pragma unroll
-    for (int i = 0; i < 19; ++i) out[i] = 0.0f;
-    uint32_t code = kNoRecord;
+                                               float dt, Staged &r) {
+    r.cell = -1;
+    r.oct = 0;
     const long long S = pa.stride;
+    const uint32_t up = (uint32_t)p;
     float x[3], v[3], B[9], tau[6];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) x[a] = pa.in[a * S + p];
+    for (int a = 0; a < 3; ++a) x[a] = ld_at(pa.in + a * S, up);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) v[a] = pa.in[(3 + a) * S + p];
+    for (int a = 0; a < 3; ++a) v[a] = ld_at(pa.in + (3 + a) * S, up);
 #pragma unroll
-    for (int a = 0; a < 9; ++a) B[a] = pa.in[(6 + a) * S + p];
+    for (int a = 0; a < 9; ++a) B[a] = ld_at(pa.in + (6 + a) * S, up);
 #pragma unroll
-    for (int i = 0; i < 6; ++i) tau[i] = d.tau[i * d.tau_stride + p];
-    const int mi = pa.mat_in ? (int)pa.mat_in[p] : 0;
+    for (int i = 0; i < 6; ++i) tau[i] = ld_at(d.tau + i * d.tau_stride, up);
+    const int mi = pa.mat_in ? (int)ld_at(pa.mat_in, up) : 0;
     const DevMaterial M = d.mats[mi < d.n_mat ? mi : 0];
     CellCoord cc;
     if (!cell_coord(d.geo, x, cc)) {
         set_status(d.counters, ST_DOMAIN);
-    } else if ((cc.c[0] >> 2) != bx || (cc.c[1] >> 2) != by || (cc.c[2] >> 2) != bz) {
-        set_status(d.counters, ST_STALE);
-    } else {
-        code = sub_code(cc);
-        Weights w;
-        axis_weights(cc, w);
-        float Di[9];
-        moment_inverse(cc, w, Di);
-        const float T[9] = {tau[0], tau[3], tau[4], tau[3], tau[1], tau[5], tau[4], tau[5], tau[2]};
-        const float k = dt * M.vol0;
-        float A[9];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) A[i] = M.mass * B[i] - k * T[i];
-        const float sc = d.geo.inv_dx_f;
-        float Q[9];
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j)
-                Q[3 * i + j] = sc * (A[3 * i] * Di[j] + A[3 * i + 1] * Di[3 + j] + A[3 * i + 2] * Di[6 + j]);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            out[a] = cc.xm[a];
-            out[3 + a] = w.sp[a];
-            out[7 + a] = M.mass * v[a] - (Q[3 * a] * cc.xm[0] + Q[3 * a + 1] * cc.xm[1] + Q[3 * a + 2] * cc.xm[2]);
-        }
-        out[6] = M.mass;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) out[10 + i] = Q[i];
+        return;
     }
-    rec[0] = make_float4(out[0], out[1], out[2], out[3]);
-    rec[1] = make_float4(out[4], out[5], out[6], out[7]);
-    rec[2] = make_float4(out[8], out[9], out[10], out[11]);
-    rec[3] = make_float4(out[12], out[13], out[14], out[15]);
-    rec[4] = make_float4(out[16], out[17], out[18], __uint_as_float(code));
+    if ((cc.c[0] >> 2) != bx || (cc.c[1] >> 2) != by || (cc.c[2] >> 2) != bz) {
+        set_status(d.counters, ST_STALE);
+        return;
+    }
+    const uint32_t code = sub_code(cc);
+    r.cell = (int)(code >> 3);
+    r.oct = (int)(code & 7u);
+    Weights w;
+    axis_weights(cc, w);
+    float Di[9];
+    moment_inverse(cc, w, Di);
+    const float T[9] = {tau[0], tau[3], tau[4], tau[3], tau[1], tau[5], tau[4], tau[5], tau[2]};
+    const float k = dt * M.vol0;
+    float A[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) A[i] = M.mass * B[i] - k * T[i];
+    const float sc = d.geo.inv_dx_f;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            r.Q[3 * i + j] = sc * (A[3 * i] * Di[j] + A[3 * i + 1] * Di[3 + j] + A[3 * i + 2] * Di[6 + j]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        r.xm[a] = cc.xm[a];
+        r.sp[a] = w.sp[a];
+        r.base[a] = M.mass * v[a] - (r.Q[3 * a] * cc.xm[0] + r.Q[3 * a + 1] * cc.xm[1] + r.Q[3 * a + 2] * cc.xm[2]);
+    }
+    r.mass = M.mass;
 }
 
-struct Rec {
-    float xm[3], sp[3], mass, base[3], Q[9];
-    uint32_t code;
-};
-
-__device__ __forceinline__ void read_rec(const float4 *r, Rec &q) {
-    const float4 a = r[0], b = r[1], c = r[2], e = r[3], f = r[4];
-    q.xm[0] = a.x; q.xm[1] = a.y; q.xm[2] = a.z; q.sp[0] = a.w;
-    q.sp[1] = b.x; q.sp[2] = b.y; q.mass = b.z; q.base[0] = b.w;
-    q.base[1] = c.x; q.base[2] = c.y; q.Q[0] = c.z; q.Q[1] = c.w;
-    q.Q[2] = e.x; q.Q[3] = e.y; q.Q[4] = e.z; q.Q[5] = e.w;
-    q.Q[6] = f.x; q.Q[7] = f.y; q.Q[8] = f.z; q.code = __float_as_uint(f.w);
+// Upper bound of |w m| and |w (base + Q t)| over the particle's 16 nodes (w <= 1,
+// every component of t in [-1/2, 3/2]).
+__device__ __forceinline__ float contribution_bound(const Staged &r) {
+    if (r.cell < 0) return 0.0f;
+    float b = r.mass;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        b = fmaxf(b, fabsf(r.base[a]) + 1.5f * (fabsf(r.Q[3 * a]) + fabsf(r.Q[3 * a + 1]) + fabsf(r.Q[3 * a + 2])));
+    return b;
 }
 
-// Adds w (m, m0 + Q o) for the 8 nodes o in {0,1}^3 of one grid, weights w[a][o_a],
-// into acc[4 n(o) + channel], n(o) given by the node map of the grid.
-template <typename NodeMap>
-__device__ __forceinline__ void add_corners(const float (&w)[3][2], float mass, const float (&m0)[3], const float (&Q)[9],
-                                            float *acc, NodeMap node) {
-    float wxy[4];
+// Adds the particle's 8 contributions on one grid: nodes t0 + o (tile index steps
+// sy, sz), weights w[a][o_a], momentum m0 + Q o.
+__device__ __forceinline__ void scatter_grid(unsigned long long *tile, int ntile, int t0, int sy, int sz,
+                                             const float (&w)[3][2], float mass, const float (&m0)[3],
+                                             const float (&Q)[9], double S) {
+    float mo[2][2][2][3];
 #pragma unroll
-    for (int oy = 0; oy < 2; ++oy)
-#pragma unroll
-        for (int ox = 0; ox < 2; ++ox) wxy[2 * oy + ox] = w[0][ox] * w[1][oy];
-#pragma unroll
-    for (int oz = 0; oz < 2; ++oz)
+    for (int a = 0; a < 3; ++a) {
+        mo[0][0][0][a] = m0[a];
+        mo[0][0][1][a] = m0[a] + Q[3 * a];
+        mo[0][1][0][a] = m0[a] + Q[3 * a + 1];
+        mo[0][1][1][a] = mo[0][0][1][a] + Q[3 * a + 1];
 #pragma unroll
         for (int oy = 0; oy < 2; ++oy)
 #pragma unroll
-            for (int ox = 0; ox < 2; ++ox) {
-                const float wt = wxy[2 * oy + ox] * w[2][oz];
-                const int n = node(ox, oy, oz);
-                acc[4 * n] += wt * mass;
+            for (int ox = 0; ox < 2; ++ox) mo[1][oy][ox][a] = mo[0][oy][ox][a] + Q[3 * a + 2];
+    }
 #pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const float mom = m0[a] + (ox ? Q[3 * a] : 0.0f) + (oy ? Q[3 * a + 1] : 0.0f) + (oz ? Q[3 * a + 2] : 0.0f);
-                    acc[4 * n + 1 + a] += wt * mom;
-                }
+    for (int oz = 0; oz < 2; ++oz)
+#pragma unroll
+        for (int oy = 0; oy < 2; ++oy) {
+            const float wyz = w[1][oy] * w[2][oz];
+#pragma unroll
+            for (int ox = 0; ox < 2; ++ox) {
+                const float wt = w[0][ox] * wyz;
+                const int t = t0 + ox + oy * sy + oz * sz;
+                atomicAdd(&tile[t], to_fixed(wt * mass, S));
+#pragma unroll
+                for (int a = 0; a < 3; ++a) atomicAdd(&tile[(1 + a) * ntile + t], to_fixed(wt * mo[oz][oy][ox][a], S));
             }
+        }
 }
 
-// One record of octant K into the cell sums: 8 G- nodes (am[4 o + ch],
-// o = ox + 2 oy + 4 oz) and 8 of the 27 G+ nodes c + r, r in {-1,0,1}^3
-// (ap[4 ((rz+1) 9 + (ry+1) 3 + rx+1) + ch]); along axis a the G+ nodes are
-// r = o - 1 + bit_a(K).
-template <int K>
-__device__ __forceinline__ void accumulate_octant(const Rec &q, float (&am)[32], float (&ap)[108]) {
-    constexpr int ux = K & 1, uy = (K >> 1) & 1, uz = (K >> 2) & 1;
-    float wm[3][2], wp[3][2];
-    constexpr int up[3] = {ux, uy, uz};
+__device__ __forceinline__ void scatter_particle(const Staged &r, unsigned long long *tile_m, unsigned long long *tile_p,
+                                                 double S) {
+    const int cx = r.cell & 3, cy = (r.cell >> 2) & 3, cz = r.cell >> 4;
+    float wm[3][2], wp[3][2], mp[3];
+    int up[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        wm[a][0] = 1.0f - q.xm[a] - q.sp[a];
-        wm[a][1] = q.xm[a] + q.sp[a];
-        const float xp = up[a] ? q.xm[a] - 0.5f : q.xm[a] + 0.5f;
-        wp[a][0] = 1.0f - xp + q.sp[a];
-        wp[a][1] = xp - q.sp[a];
+        up[a] = (r.oct >> a) & 1;                               // G+ base node is c (else c - 1)
+        wm[a][0] = 1.0f - r.xm[a] - r.sp[a];
+        wm[a][1] = r.xm[a] + r.sp[a];
+        const float xp = up[a] ? r.xm[a] - 0.5f : r.xm[a] + 0.5f;
+        wp[a][0] = 1.0f - xp + r.sp[a];
+        wp[a][1] = xp - r.sp[a];
     }
-    add_corners(wm, q.mass, q.base, q.Q, am, [](int ox, int oy, int oz) { return ox + 2 * oy + 4 * oz; });
-    // G+ momentum at the first node r0 = up - 1: base + Q (r0 + 1/2)
-    float m0[3];
+    scatter_grid(tile_m, kTileMinus, (cz * 5 + cy) * 5 + cx, 5, 25, wm, r.mass, r.base, r.Q, S);
+    // G+ momentum at the base node bp = c + up - 1: base + Q (up - 1/2)
 #pragma unroll
     for (int a = 0; a < 3; ++a)
-        m0[a] = q.base[a] + (ux - 0.5f) * q.Q[3 * a] + (uy - 0.5f) * q.Q[3 * a + 1] + (uz - 0.5f) * q.Q[3 * a + 2];
-    add_corners(wp, q.mass, m0, q.Q, ap,
-                [](int ox, int oy, int oz) { return (oz + uz) * 9 + (oy + uy) * 3 + (ox + ux); });
+        mp[a] = r.base[a] + ((float)up[0] - 0.5f) * r.Q[3 * a] + ((float)up[1] - 0.5f) * r.Q[3 * a + 1] +
+                ((float)up[2] - 0.5f) * r.Q[3 * a + 2];
+    const int t0 = ((cz + up[2]) * 6 + (cy + up[1])) * 6 + (cx + up[0]);
+    scatter_grid(tile_p, kTilePlus, t0, 6, 36, wp, r.mass, mp, r.Q, S);
 }
 
-// All records of octant K: staged by the wave in chunks of 64, summed by their cell's lane.
-template <int K>
-__device__ __forceinline__ void octant_pass(const DevCtx &d, const PartArgs &pa, float dt, int s, int bx, int by,
-                                            int bz, const int *bstart, float4 *rec, int lane, float (&am)[32],
-                                            float (&ap)[108]) {
-    const uint32_t want = ((uint32_t)lane << 3) | (uint32_t)K;
-    const int olo = bstart[K * 64], ohi = bstart[K * 64 + 64];
-    const int clo = bstart[K * 64 + lane], chi = bstart[K * 64 + lane + 1];
-    for (int t0 = olo; t0 < ohi; t0 += kP2GThreads) {
-        if (t0 + lane < ohi) stage_particle(d, pa, (int)d.perm[s + t0 + lane], bx, by, bz, dt, &rec[lane * kRecVec]);
-        __syncthreads();
-        const int lo = max(clo, t0), hi = min(chi, t0 + kP2GThreads);
-        for (int i = lo; i < hi; ++i) {
-            Rec q;
-            read_rec(&rec[(i - t0) * kRecVec], q);
-            if (q.code != want) {
-                if (q.code != kNoRecord) set_status(d.counters, ST_STALE);
-                continue;
-            }
-            accumulate_octant<K>(q, am, ap);
-        }
-        __syncthreads();
-    }
-}
-
-// Adds the register sums of G+ node c + r, N = (rz+1) 9 + (ry+1) 3 + rx+1, into the
-// tile; every lane targets a different node.
-template <int N>
-__device__ __forceinline__ void flush_plus(float *tile_p, int cx, int cy, int cz, const float (&ap)[108]) {
-    constexpr int rx = N % 3, ry = (N / 3) % 3, rz = N / 9;
-    const int node = (cz + rz) * 36 + (cy + ry) * 6 + cx + rx;
-#pragma unroll
-    for (int ch = 0; ch < 4; ++ch) tile_p[ch * kTilePlus + node] += ap[4 * N + ch];
-    __syncthreads();
-}
-
-template <int... N>
-__device__ __forceinline__ void flush_plus_list(float *tile_p, int cx, int cy, int cz, const float (&ap)[108]) {
-    (flush_plus<N>(tile_p, cx, cy, cz, ap), ...);
-}
-
-__device__ __forceinline__ int bin_of(uint32_t sub) { return (int)((sub & 7u) * 64u + (sub >> 3)); }
-
-__global__ void __launch_bounds__(kP2GThreads, 2) k_p2g(DevCtx d, PartArgs pa, float dt) {
+__global__ void __launch_bounds__(kP2GThreads) k_p2g(DevCtx d, PartArgs pa, float dt) {
     __shared__ int bcnt[kBins];                 // counts, then placement cursors
     __shared__ int bstart[kBins + 1];
+    __shared__ int wsum[kP2GThreads / 64];
+    __shared__ unsigned int bmax;
     __shared__ int nbr[27];
-    // ordering buffer, later the staged records and the tile
-    constexpr int kTileFloats = 4 * (kTileMinus + kTilePlus);
-    constexpr int kUnionFloats = kMaxBlockParticles > kP2GThreads * 4 * kRecVec + kTileFloats
-                                     ? kMaxBlockParticles
-                                     : kP2GThreads * 4 * kRecVec + kTileFloats;
-    __shared__ float4 area4[kUnionFloats / 4];
-    float *area = reinterpret_cast<float *>(area4);
-    uint32_t *lbuf = reinterpret_cast<uint32_t *>(area4);
-    float4 *rec = area4;
-    float *tile_m = area + kP2GThreads * 4 * kRecVec;   // [4][125]
-    float *tile_p = tile_m + 4 * kTileMinus;              // [4][216]
+    // ordering buffer, then the fixed-point tile [4][125] (G-) and [4][216] (G+)
+    constexpr int kTileWords = 4 * (kTileMinus + kTilePlus);
+    constexpr int kAreaWords = kTileWords > kMaxBlockParticles / 2 ? kTileWords : kMaxBlockParticles / 2;
+    __shared__ unsigned long long area[kAreaWords];
+    uint32_t *lbuf = reinterpret_cast<uint32_t *>(area);
+    unsigned long long *tile_m = area;
+    unsigned long long *tile_p = area + 4 * kTileMinus;
     const int np = (int)d.counters[C_NPB];
     const int E = (int)d.counters[C_EPOCH];
-    const int lane = threadIdx.x;
-    const int cx = lane & 3, cy = (lane >> 2) & 3, cz = lane >> 4;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
     for (int base = 0; base < np; base += gridDim.x) {
         const int r = round_block(base, np);
         if (r < 0) continue;
@@ -411,13 +368,13 @@ __global__ void __launch_bounds__(kP2GThreads, 2) k_p2g(DevCtx d, PartArgs pa, f
         const uint32_t *bkt = d.bucket + (size_t)r * kMaxBlockParticles;
 
         // ---- order the block's particles by (octant, cell, index)
-        for (int b = lane; b < kBins; b += kP2GThreads) bcnt[b] = 0;
+        for (int b = tid; b < kBins; b += kP2GThreads) bcnt[b] = 0;
         __syncthreads();
         uint32_t hidx[kHold];
         int hbin[kHold];
 #pragma unroll
-        for (int k = 0; k < kMaxBlockParticles / kP2GThreads; ++k) {
-            const int j = lane + k * kP2GThreads;
+        for (int k = 0; k < kPerThread; ++k) {
+            const int j = tid + k * kP2GThreads;
             if (j >= cnt) break;
             const uint32_t idx = bkt[j];
             const int bin = bin_of(d.sub[idx]);
@@ -429,33 +386,29 @@ __global__ void __launch_bounds__(kP2GThreads, 2) k_p2g(DevCtx d, PartArgs pa, f
         }
         __syncthreads();
         {
-            // exclusive scan of the 512 bins, 8 per lane
-            int loc[kBins / kP2GThreads];
-            int sum = 0;
-#pragma unroll
-            for (int k = 0; k < kBins / kP2GThreads; ++k) {
-                loc[k] = bcnt[lane * (kBins / kP2GThreads) + k];
-                sum += loc[k];
-            }
-            int v = sum;
+            // exclusive scan of the 512 bins, two per thread
+            const int c0 = bcnt[2 * tid], c1 = bcnt[2 * tid + 1];
+            int v = c0 + c1;
 #pragma unroll
             for (int off = 1; off < 64; off <<= 1) {
                 const int t = __shfl_up(v, off);
                 if (lane >= off) v += t;
             }
-            int run = v - sum;
-#pragma unroll
-            for (int k = 0; k < kBins / kP2GThreads; ++k) {
-                bstart[lane * (kBins / kP2GThreads) + k] = run;
-                bcnt[lane * (kBins / kP2GThreads) + k] = run;
-                run += loc[k];
-            }
-            if (lane == 63) bstart[kBins] = run;
+            if (lane == 63) wsum[w] = v;
+            __syncthreads();
+            int pre = 0;
+            for (int k = 0; k < w; ++k) pre += wsum[k];
+            const int ex = pre + v - c0 - c1;
+            bstart[2 * tid] = ex;
+            bstart[2 * tid + 1] = ex + c0;
+            bcnt[2 * tid] = ex;
+            bcnt[2 * tid + 1] = ex + c0;
+            if (tid == kP2GThreads - 1) bstart[kBins] = ex + c0 + c1;
         }
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < kMaxBlockParticles / kP2GThreads; ++k) {
-            const int j = lane + k * kP2GThreads;
+        for (int k = 0; k < kPerThread; ++k) {
+            const int j = tid + k * kP2GThreads;
             if (j >= cnt) break;
             uint32_t idx;
             int bin;
@@ -470,8 +423,8 @@ __global__ void __launch_bounds__(kP2GThreads, 2) k_p2g(DevCtx d, PartArgs pa, f
         }
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < kMaxBlockParticles / kP2GThreads; ++k) {
-            const int j = lane + k * kP2GThreads;
+        for (int k = 0; k < kPerThread; ++k) {
+            const int j = tid + k * kP2GThreads;
             if (j >= cnt) break;
             uint32_t idx;
             int bin;
@@ -487,58 +440,58 @@ __global__ void __launch_bounds__(kP2GThreads, 2) k_p2g(DevCtx d, PartArgs pa, f
             for (int q = lo; q < hi; ++q) rank += (lbuf[q] < idx) ? 1 : 0;
             d.perm[s + rank] = idx;
         }
-        __threadfence_block();   // the order is read back below by other lanes
+        __threadfence_block();   // the order is read back below by other threads
+        load_neighbours(d, bx, by, bz, E, nbr);
         __syncthreads();
 
-        // ---- per-cell register sums, one octant at a time
-        load_neighbours(d, bx, by, bz, E, nbr);
-        for (int q = lane; q < kTileFloats; q += kP2GThreads) tile_m[q] = 0.0f;
-        float am[32], ap[108];
+        // ---- scatter, kChunk particles per pass (one pass unless the block is dense)
+        for (int c0 = 0; c0 < cnt; c0 += kChunk) {
+            for (int q = tid; q < kTileWords; q += kP2GThreads) area[q] = 0ull;
+            if (tid == 0) bmax = 0u;
+            Staged st[2];
+            float bnd = 0.0f;
 #pragma unroll
-        for (int i = 0; i < 32; ++i) am[i] = 0.0f;
-#pragma unroll
-        for (int i = 0; i < 108; ++i) ap[i] = 0.0f;
-        // Octants in order; a G+ node is added to the tile as soon as no later octant
-        // reaches it, which keeps at most 15 of the 27 node sums live at a time.
-        octant_pass<0>(d, pa, dt, s, bx, by, bz, bstart, rec, lane, am, ap);
-        octant_pass<1>(d, pa, dt, s, bx, by, bz, bstart, rec, lane, am, ap);
-        flush_plus_list<0, 1, 2>(tile_p, cx, cy, cz, ap);                      // ry = rz = -1
-        octant_pass<2>(d, pa, dt, s, bx, by, bz, bstart, rec, lane, am, ap);
-        octant_pass<3>(d, pa, dt, s, bx, by, bz, bstart, rec, lane, am, ap);
-        flush_plus_list<3, 4, 5, 6, 7, 8>(tile_p, cx, cy, cz, ap);             // rz = -1
-        octant_pass<4>(d, pa, dt, s, bx, by, bz, bstart, rec, lane, am, ap);
-        octant_pass<5>(d, pa, dt, s, bx, by, bz, bstart, rec, lane, am, ap);
-        flush_plus_list<9, 10, 11, 18, 19, 20>(tile_p, cx, cy, cz, ap);        // ry = -1
-        octant_pass<6>(d, pa, dt, s, bx, by, bz, bstart, rec, lane, am, ap);
-        octant_pass<7>(d, pa, dt, s, bx, by, bz, bstart, rec, lane, am, ap);
-        flush_plus_list<12, 13, 14, 15, 16, 17, 21, 22, 23, 24, 25, 26>(tile_p, cx, cy, cz, ap);
-#pragma unroll
-        for (int o = 0; o < 8; ++o) {
-            const int node = (cz + (o >> 2)) * 25 + (cy + ((o >> 1) & 1)) * 5 + cx + (o & 1);
-#pragma unroll
-            for (int ch = 0; ch < 4; ++ch) tile_m[ch * kTileMinus + node] += am[4 * o + ch];
-            __syncthreads();
-        }
-        // ---- flush every nonzero tile node to the pool
-        for (int ni = lane; ni < kTileNodes; ni += kP2GThreads) {
-            int g, ix, iy, iz;
-            tile_node(ni, bx, by, bz, g, ix, iy, iz);
-            const long long a = pool_index(d, nbr, bx, by, bz, g, ix, iy, iz, 0);
-            float val[4];
-#pragma unroll
-            for (int ch = 0; ch < 4; ++ch)
-                val[ch] = ni < kTileMinus ? tile_m[ch * kTileMinus + ni] : tile_p[ch * kTilePlus + ni - kTileMinus];
-            const bool any = val[0] != 0.0f || val[1] != 0.0f || val[2] != 0.0f || val[3] != 0.0f;
-            if (!any) continue;
-            if (a < 0) {
-                set_status(d.counters, ST_CAPACITY);
-                continue;
+            for (int k = 0; k < 2; ++k) {
+                st[k].cell = -1;
+                const int j = c0 + tid + k * kP2GThreads;
+                if (j < cnt) stage_particle(d, pa, (int)d.perm[s + j], bx, by, bz, dt, st[k]);
+                bnd = fmaxf(bnd, contribution_bound(st[k]));
             }
 #pragma unroll
-            for (int ch = 0; ch < 4; ++ch)
-                if (val[ch] != 0.0f) atomicAdd(&d.pool[a + ch * 64], val[ch]);
+            for (int off = 32; off > 0; off >>= 1) bnd = fmaxf(bnd, __shfl_xor(bnd, off));
+            __syncthreads();   // tile cleared, bmax reset
+            if (lane == 0) atomicMax(&bmax, __float_as_uint(bnd));
+            __syncthreads();
+            const float m = __uint_as_float(bmax);
+            const double S = m > 0.0f ? ldexp(1.0, 39 - ilogbf(m)) : 1.0;
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+                if (st[k].cell >= 0) scatter_particle(st[k], tile_m, tile_p, S);
+            __syncthreads();
+            // ---- flush every nonzero tile node to the pool
+            const double inv = 1.0 / S;
+            for (int ni = tid; ni < kTileNodes; ni += kP2GThreads) {
+                float val[4];
+#pragma unroll
+                for (int ch = 0; ch < 4; ++ch) {
+                    const long long t = (long long)(ni < kTileMinus ? tile_m[ch * kTileMinus + ni]
+                                                                     : tile_p[ch * kTilePlus + ni - kTileMinus]);
+                    val[ch] = (float)((double)t * inv);
+                }
+                if (val[0] == 0.0f && val[1] == 0.0f && val[2] == 0.0f && val[3] == 0.0f) continue;
+                int g, ix, iy, iz;
+                tile_node(ni, bx, by, bz, g, ix, iy, iz);
+                const long long a = pool_index(d, nbr, bx, by, bz, g, ix, iy, iz, 0);
+                if (a < 0) {
+                    set_status(d.counters, ST_CAPACITY);
+                    continue;
+                }
+#pragma unroll
+                for (int ch = 0; ch < 4; ++ch)
+                    if (val[ch] != 0.0f) atomicAdd(&d.pool[a + ch * 64], val[ch]);
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
@@ -576,6 +529,25 @@ __global__ void __launch_bounds__(128) k_grid_update(DevCtx d, float dt, float g
 // C_p = B_p D_p^-1,   F <- (I + dt C_p) F,   plasticity,   x <- x + dt v_p.
 // The new state is written at the particle's sorted position in the other buffer,
 // together with its next cell key and the activation stamps of the next step.
+struct G2PIn {
+    uint32_t p;
+    float x[3], H[9];
+    int mat;
+    uint32_t id;
+};
+
+__device__ __forceinline__ void g2p_load(const DevCtx &d, const PartArgs &pa, uint32_t pos, G2PIn &q) {
+    const uint32_t p = ld_at(d.perm, pos);
+    q.p = p;
+    const long long S = pa.stride;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) q.x[a] = ld_at(pa.in + a * S, p);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) q.H[a] = ld_at(pa.in + (15 + a) * S, p);
+    q.mat = pa.mat_in ? (int)ld_at(pa.mat_in, p) : 0;
+    q.id = pa.id_in ? ld_at(pa.id_in, p) : 0u;
+}
+
 __global__ void __launch_bounds__(kThreads) k_g2p(DevCtx d, PartArgs pa, float dt) {
     __shared__ float vt[3 * kTileNodes];
     __shared__ int nbr[27];
@@ -592,151 +564,185 @@ __global__ void __launch_bounds__(kThreads) k_g2p(DevCtx d, PartArgs pa, float d
         const int s = d.pstart[r];
         const int cnt = d.pstart[r + 1] - s;
         if (cnt > kMaxBlockParticles) continue;
+        // the first particle's inputs load while the tile is gathered
+        G2PIn nxt;
+        if (tid < cnt) g2p_load(d, pa, (uint32_t)(s + tid), nxt);
         load_neighbours(d, bx, by, bz, E, nbr);
         __syncthreads();
-        for (int t = tid; t < 3 * kTileNodes; t += kThreads) {
-            const int ch = t / kTileNodes;
-            const int ni = t - ch * kTileNodes;
+        for (int ni = tid; ni < kTileNodes; ni += kThreads) {
             int g, ix, iy, iz;
             tile_node(ni, bx, by, bz, g, ix, iy, iz);
-            const long long a = pool_index(d, nbr, bx, by, bz, g, ix, iy, iz, ch + 1);
-            vt[t] = a >= 0 ? d.pool[a] : 0.0f;
+            const long long a = pool_index(d, nbr, bx, by, bz, g, ix, iy, iz, 1);
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) vt[ch * kTileNodes + ni] = a >= 0 ? d.pool[a + ch * 64] : 0.0f;
         }
         __syncthreads();
         for (int j = tid; j < cnt; j += kThreads) {
-            const int p = (int)d.perm[s + j];
-            const int out = s + j;
-            Particle q;
-            load_particle(pa, p, q, false);
+            const G2PIn q = nxt;
+            if (j + kThreads < cnt) g2p_load(d, pa, (uint32_t)(s + j + kThreads), nxt);   // next particle
+            const uint32_t out = (uint32_t)(s + j);
             CellCoord cc;
             bool ok = cell_coord(d.geo, q.x, cc);
             ok = ok && (cc.c[0] >> 2) == bx && (cc.c[1] >> 2) == by && (cc.c[2] >> 2) == bz;
+            // activation stamps of the next step, deduplicated between neighbouring lanes
+            // (sorted particles mostly share their blocks): -1 = none, else the
+            // particle block and whether the stencil reaches the lower / upper
+            // neighbour block along each axis
+            long long sig = -1;
+            CellCoord cn;
             if (!ok) {
                 set_status(d.counters, ST_STALE);
-                d.key[out] = 0xffffffffu;
-                continue;
-            }
-            const int mi = pa.mat_in ? (int)pa.mat_in[p] : 0;
-            const DevMaterial M = d.mats[mi < d.n_mat ? mi : 0];
-            Weights w;
-            axis_weights(cc, w);
-            float Di[9];
-            moment_inverse(cc, w, Di);
-            // Gather.  The affine matrix sums w v~ (x_i - x_p)^T, whose weights have a zero
-            // dual-grid first moment; subtracting one stencil node's velocity c first keeps
-            // the FP32 sums at the size of the velocity differences, and c drops out:
-            //   1/2 sum w (v~ - c)(x_i - x_p)^T = 1/2 sum w v~ (x_i - x_p)^T,
-            //   v_p = c + 1/2 sum w (v~ - c)   (the weights of each grid sum to one).
-            const int tm0 = ((cc.c[2] - 4 * bz) * 5 + (cc.c[1] - 4 * by)) * 5 + (cc.c[0] - 4 * bx);
-            const int tp0 = kTileMinus + ((cc.bp[2] - 4 * bz + 1) * 6 + (cc.bp[1] - 4 * by + 1)) * 6 + (cc.bp[0] - 4 * bx + 1);
-            const float cref[3] = {vt[tm0], vt[kTileNodes + tm0], vt[2 * kTileNodes + tm0]};
-            float vs[3] = {0.0f, 0.0f, 0.0f};
-            float Bh[9];
+                st_at(d.key, out, 0xffffffffu);
+            } else {
+                const DevMaterial M = d.mats[q.mat < d.n_mat ? q.mat : 0];
+                Weights w;
+                axis_weights(cc, w);
+                float Di[9];
+                moment_inverse(cc, w, Di);
+                // Gather.  The affine matrix sums w v~ (x_i - x_p)^T, whose weights have a
+                // zero dual-grid first moment; subtracting one stencil node's velocity c
+                // first keeps the FP32 sums at the size of the velocity differences, and c
+                // drops out:
+                //   1/2 sum w (v~ - c)(x_i - x_p)^T = 1/2 sum w v~ (x_i - x_p)^T,
+                //   v_p = c + 1/2 sum w (v~ - c)   (the weights of each grid sum to one).
+                const int tm0 = ((cc.c[2] - 4 * bz) * 5 + (cc.c[1] - 4 * by)) * 5 + (cc.c[0] - 4 * bx);
+                const int tp0 = kTileMinus + ((cc.bp[2] - 4 * bz + 1) * 6 + (cc.bp[1] - 4 * by + 1)) * 6 +
+                                (cc.bp[0] - 4 * bx + 1);
+                const float cref[3] = {vt[tm0], vt[kTileNodes + tm0], vt[2 * kTileNodes + tm0]};
+                float vs[3] = {0.0f, 0.0f, 0.0f};
+                float Bh[9];
 #pragma unroll
-            for (int i = 0; i < 9; ++i) Bh[i] = 0.0f;
+                for (int i = 0; i < 9; ++i) Bh[i] = 0.0f;
 #pragma unroll
-            for (int g = 0; g < 2; ++g) {
-                const float *xi = g == 0 ? cc.xm : cc.xp;
-                const int t0 = g == 0 ? tm0 : tp0;
-                const int sy = g == 0 ? 5 : 6, sz = g == 0 ? 25 : 36;
-                const float(*wa)[2] = g == 0 ? w.wm : w.wp;
-                float S3[3] = {0.0f, 0.0f, 0.0f};
-                float T[9];
-#pragma unroll
-                for (int i = 0; i < 9; ++i) T[i] = 0.0f;
-#pragma unroll
-                for (int o = 0; o < 8; ++o) {
-                    const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
-                    const float wt = wa[0][ox] * wa[1][oy] * wa[2][oz];
-                    const int t = t0 + ox + oy * sy + oz * sz;
-                    const float wv[3] = {wt * (vt[t] - cref[0]), wt * (vt[kTileNodes + t] - cref[1]),
-                                         wt * (vt[2 * kTileNodes + t] - cref[2])};
+                for (int g = 0; g < 2; ++g) {
+                    const float *xi = g == 0 ? cc.xm : cc.xp;
+                    const int t0 = g == 0 ? tm0 : tp0;
+                    const int sy = g == 0 ? 5 : 6, sz = g == 0 ? 25 : 36;
+                    const float(*wa)[2] = g == 0 ? w.wm : w.wp;
+                    // separable sums over the 2x2x2 nodes: S = sum w v, M_b = sum w v o_b
+                    float S3[3], Mx[3], My[3], Mz[3];
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
-                        S3[a] += wv[a];
-                        if (ox) T[3 * a] += wv[a];
-                        if (oy) T[3 * a + 1] += wv[a];
-                        if (oz) T[3 * a + 2] += wv[a];
+                        float A[2][2], X[2][2];   // [oz][oy]: x-reduced sum and x-moment
+#pragma unroll
+                        for (int oz = 0; oz < 2; ++oz)
+#pragma unroll
+                            for (int oy = 0; oy < 2; ++oy) {
+                                const int t = a * kTileNodes + t0 + oy * sy + oz * sz;
+                                const float v0 = vt[t] - cref[a], v1 = vt[t + 1] - cref[a];
+                                X[oz][oy] = wa[0][1] * v1;
+                                A[oz][oy] = wa[0][0] * v0 + X[oz][oy];
+                            }
+                        float Bz[2], BXz[2], BYz[2];
+#pragma unroll
+                        for (int oz = 0; oz < 2; ++oz) {
+                            BYz[oz] = wa[1][1] * A[oz][1];
+                            Bz[oz] = wa[1][0] * A[oz][0] + BYz[oz];
+                            BXz[oz] = wa[1][0] * X[oz][0] + wa[1][1] * X[oz][1];
+                        }
+                        Mz[a] = wa[2][1] * Bz[1];
+                        S3[a] = wa[2][0] * Bz[0] + Mz[a];
+                        Mx[a] = wa[2][0] * BXz[0] + wa[2][1] * BXz[1];
+                        My[a] = wa[2][0] * BYz[0] + wa[2][1] * BYz[1];
+                    }
+                    // sum_o w v (o - xi)^T = M - S xi^T
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        vs[a] += S3[a];
+                        Bh[3 * a] += Mx[a] - S3[a] * xi[0];
+                        Bh[3 * a + 1] += My[a] - S3[a] * xi[1];
+                        Bh[3 * a + 2] += Mz[a] - S3[a] * xi[2];
                     }
                 }
-                // sum_o w v (o - xi)^T = T - S xi^T
+                float vn[3], Bn[9], C[9];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) vn[a] = cref[a] + 0.5f * vs[a];
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    Bh[i] *= 0.5f;
+                    Bn[i] = Bh[i] * d.geo.dx;
+                }
+                // C = B D^-1 = (dx Bh)(dx^2 Dhat)^-1 = Bh Dhat^-1 / dx
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j2 = 0; j2 < 3; ++j2)
+                        C[3 * i + j2] = d.geo.inv_dx_f *
+                                        (Bh[3 * i] * Di[j2] + Bh[3 * i + 1] * Di[3 + j2] + Bh[3 * i + 2] * Di[6 + j2]);
+                // F' = (I + dt C) F  ->  H' = H + dt (C + C H)
+                float Fn[9];
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j2 = 0; j2 < 3; ++j2)
+                        Fn[3 * i + j2] = q.H[3 * i + j2] + dt * (C[3 * i + j2] + C[3 * i] * q.H[j2] +
+                                                                 C[3 * i + 1] * q.H[3 + j2] + C[3 * i + 2] * q.H[6 + j2]);
+                // stress of the new state for the next step's P2G
+                float tau[6];
+                if (M.model == 1) dp_return_map(M, Fn, tau);
+                else kirchhoff(M, Fn, tau);
+                float xn[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) xn[a] = q.x[a] + dt * vn[a];
+                // x * 0 is NaN exactly when x is infinite or NaN
+                float probe = 0.0f;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) probe += vn[a] * 0.0f + xn[a] * 0.0f;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) probe += Fn[i] * 0.0f + Bn[i] * 0.0f;
+                const bool finite = probe == 0.0f;
+                if (!finite) set_status(d.counters, ST_NONFINITE);
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    vs[a] += S3[a];
+                    st_at(pa.out + a * S, out, xn[a]);
+                    st_at(pa.out + (3 + a) * S, out, vn[a]);
+                }
 #pragma unroll
-                    for (int b = 0; b < 3; ++b) Bh[3 * a + b] += T[3 * a + b] - S3[a] * xi[b];
+                for (int i = 0; i < 9; ++i) {
+                    st_at(pa.out + (6 + i) * S, out, Bn[i]);
+                    st_at(pa.out + (15 + i) * S, out, Fn[i]);
+                }
+#pragma unroll
+                for (int i = 0; i < 6; ++i) st_at(d.tau + i * d.tau_stride, out, tau[i]);
+                if (pa.id_out) st_at(pa.id_out, out, q.id);
+                if (pa.mat_out) st_at(pa.mat_out, out, (uint8_t)q.mat);
+                // next cell key for the following step
+                if (finite && cell_coord(d.geo, xn, cn)) {
+                    const uint32_t key = cell_key(d.geo, cn);
+                    st_at(d.key, out, key);
+                    st_at(d.sub, out, (uint16_t)sub_code(cn));
+                    int reach = 0;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        reach |= ((min(cn.c[a], cn.bp[a]) >> 2) != (cn.c[a] >> 2)) << (2 * a);
+                        reach |= (((cn.c[a] + 1) >> 2) != (cn.c[a] >> 2)) << (2 * a + 1);
+                    }
+                    sig = (long long)(key >> 6) << 6 | reach;
+                } else {
+                    st_at(d.key, out, 0xffffffffu);
+                    set_status(d.counters, ST_DOMAIN);
                 }
             }
-            float vn[3], Bn[9], C[9];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) vn[a] = cref[a] + 0.5f * vs[a];
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                Bh[i] *= 0.5f;
-                Bn[i] = Bh[i] * d.geo.dx;
-            }
-            // C = B D^-1 = (dx Bh)(dx^2 Dhat)^-1 = Bh Dhat^-1 / dx
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int j = 0; j < 3; ++j)
-                    C[3 * i + j] = d.geo.inv_dx_f * (Bh[3 * i] * Di[j] + Bh[3 * i + 1] * Di[3 + j] + Bh[3 * i + 2] * Di[6 + j]);
-            // F' = (I + dt C) F  ->  H' = H + dt (C + C H)
-            float Fn[9];
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int j = 0; j < 3; ++j)
-                    Fn[3 * i + j] = q.H[3 * i + j] +
-                                    dt * (C[3 * i + j] + C[3 * i] * q.H[j] + C[3 * i + 1] * q.H[3 + j] + C[3 * i + 2] * q.H[6 + j]);
-            // stress of the new state for the next step's P2G
-            float tau[6];
-            if (M.model == 1) dp_return_map(M, Fn, tau);
-            else kirchhoff(M, Fn, tau);
-            float xn[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) xn[a] = q.x[a] + dt * vn[a];
-            bool finite = true;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) finite = finite && isfinite(vn[a]) && isfinite(xn[a]);
-#pragma unroll
-            for (int i = 0; i < 9; ++i) finite = finite && isfinite(Fn[i]) && isfinite(Bn[i]);
-            if (!finite) set_status(d.counters, ST_NONFINITE);
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                pa.out[a * S + out] = xn[a];
-                pa.out[(3 + a) * S + out] = vn[a];
-            }
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                pa.out[(6 + i) * S + out] = Bn[i];
-                pa.out[(15 + i) * S + out] = Fn[i];
-            }
-#pragma unroll
-            for (int i = 0; i < 6; ++i) d.tau[i * d.tau_stride + out] = tau[i];
-            if (pa.id_out) pa.id_out[out] = pa.id_in[p];
-            if (pa.mat_out) pa.mat_out[out] = pa.mat_in[p];
-            // next cell key and activation stamps for the following step
-            CellCoord cn;
-            if (finite && cell_coord(d.geo, xn, cn)) {
-                d.key[out] = cell_key(d.geo, cn);
-                d.sub[out] = (uint16_t)sub_code(cn);
+            const long long prev = __shfl_up(sig, 1);
+            if (sig >= 0 && ((threadIdx.x & 63) == 0 || prev != sig)) {
                 const Geometry &g = d.geo;
                 int *pf = stamps(d.pflag, d.nbv, E + 1);
                 int *gf = stamps(d.gflag, d.nbv, E + 1);
-                pf[vblock_id(g, cn.c[0] >> 2, cn.c[1] >> 2, cn.c[2] >> 2)] = E + 1;
+                const int vbn = (int)(sig >> 6);
+                pf[vbn] = E + 1;
+                int bc[3];
+                bc[0] = vbn % g.NB[0];
+                bc[1] = (vbn / g.NB[0]) % g.NB[1];
+                bc[2] = vbn / (g.NB[0] * g.NB[1]);
                 int lo[3], hi[3];
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    lo[a] = min(cn.c[a], cn.bp[a]) >> 2;
-                    hi[a] = (cn.c[a] + 1) >> 2;
+                    lo[a] = bc[a] - (int)((sig >> (2 * a)) & 1);
+                    hi[a] = bc[a] + (int)((sig >> (2 * a + 1)) & 1);
                 }
                 for (int zz = lo[2]; zz <= hi[2]; ++zz)
                     for (int yy = lo[1]; yy <= hi[1]; ++yy)
                         for (int xx = lo[0]; xx <= hi[0]; ++xx) gf[vblock_id(g, xx, yy, zz)] = E + 1;
-            } else {
-                d.key[out] = 0xffffffffu;
-                set_status(d.counters, ST_DOMAIN);
             }
         }
         __syncthreads();

@@ -170,6 +170,66 @@ def sphere(rng: np.random.Generator, centre, radius, dx) -> np.ndarray:
     return pts[keep].astype(np.float32)
 
 
+@dataclasses.dataclass
+class JobSpec:
+    """One job of the serving workload: everything needed to build its scene."""
+    index: int
+    seed: int
+    n_target: int        # drawn particle count
+    side: int            # box side in cells (the box holds side^3 cells at 8 ppc)
+    grid: int            # cells per axis of the job's grid
+    sand: bool           # Drucker-Prager sand at rest on the floor, else a falling elastic cube
+    nsteps: int
+    arrival: float       # seconds after the first arrival (Poisson process of unit rate)
+
+
+def serving_workload(seed: int = 4, n_jobs: int = 256, nsteps: int = 200,
+                     n_min: float = 1e3, n_max: float = 2e6) -> List[JobSpec]:
+    """Job mix of the serving benchmark: particle counts log-uniform in
+    [n_min, n_max], each a box of N/8 cells at 8 ppc on the smallest power-of-two
+    grid in {32, 64, 128, 256} that holds twice the box side plus 8 cells; a fair
+    coin picks a falling elastic cube or sand resting on the floor; arrival times
+    are a Poisson process of unit rate (scale them to the wanted rate)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    t = 0.0
+    for i in range(n_jobs):
+        n_target = int(round(math.exp(rng.uniform(math.log(n_min), math.log(n_max)))))
+        side = max(2, int(round((n_target / 8.0) ** (1.0 / 3.0))))
+        grid = next((g for g in (32, 64, 128, 256) if g >= 2 * side + 8), 256)
+        sand = bool(rng.random() < 0.5)
+        if i > 0:
+            t += float(rng.exponential(1.0))
+        out.append(JobSpec(i, int(rng.integers(0, 2 ** 31 - 1)), n_target, side, grid, sand, nsteps, t))
+    return out
+
+
+def serving_job(spec: JobSpec) -> Scene:
+    """Scene of one serving job.  Elastic: fixed-corotated (rho=1000, E=1e4,
+    nu=0.3), centred, falling at 1 m/s, dt=1e-4.  Sand: Drucker-Prager (phi=30 deg,
+    rho=1600, E=3.5e5, nu=0.3) on the floor band, at rest, dt=2e-5.  Gravity -9.8,
+    sticky walls two cells thick."""
+    n = spec.grid
+    dx = 1.0 / n
+    rng = np.random.Generator(np.random.PCG64(spec.seed))
+    s = spec.side
+    if spec.sand:
+        lo_cells = ((n - s) // 2, 2, (n - s) // 2)
+    else:
+        lo_cells = ((n - s) // 2, (n - s) // 2, (n - s) // 2)
+    x = stratified_box(rng, tuple(c * dx for c in lo_cells), (s, s, s), dx)
+    v, B, F = _rest_state(x.shape[0])
+    if spec.sand:
+        mats = [Material(DRUCKER_PRAGER, 3.5e5, 0.3, 1600.0, dx ** 3 / 8, 30.0)]
+        dt = 2e-5
+    else:
+        v[:, 1] = -1.0
+        mats = [Material(FIXED_COROTATED, 1e4, 0.3, 1000.0, dx ** 3 / 8, 30.0)]
+        dt = 1e-4
+    return Scene("job_%d" % spec.index, (n, n, n), dx, (0.0, 0.0, 0.0), (0.0, -9.8, 0.0), 2, dt, spec.nsteps,
+                 mats, x, v, B, F, np.zeros(x.shape[0], np.uint8))
+
+
 PRESETS = {
     "cube_elastic": cube_elastic,
     "cube_elastic_perturbed": lambda: cube_elastic_perturbed(1),
