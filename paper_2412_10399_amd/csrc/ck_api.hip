@@ -155,7 +155,7 @@ int64_t device_bytes_of(const mpm_config &c) {
     const long long np = c.max_particles, nb = c.max_blocks;
     const long long nchunks = (nbv + kCompactChunk - 1) / kCompactChunk;
     auto r = [](long long bytes) { return (bytes + 256 + 255) / 256 * 256; };
-    return r(4 * np) + r(2 * np) + r(4 * np) + r(4 * nb * (long long)kMaxBlockParticles) + r(8 * nbv) + r(8 * nbv) + r(4 * nbv) +
+    return r(4 * np) + r(2 * np) + r(4 * np) + r(4 * nb * (long long)kMaxBlockParticles) + r(2 * nb * (long long)kMaxBlockParticles) + r(8 * nbv) + r(8 * nbv) + r(4 * nbv) +
            r(4 * nbv) + r(4 * nb) + r(4 * (nb + 1)) + r(4 * nb) + r(4 * nb) + r(4 * nchunks) + r(4 * nchunks) +
            r(4 * nb * (long long)kBlockFloats) + r(24 * np) + r(4 * (long long)C_COUNT);
 }
@@ -274,6 +274,7 @@ mpm_status ctx_create(const mpm_config *cfg, const mpm_material *mats, int32_t n
     if (st == MPM_OK) st = dalloc(ctx, &d.sub, np);
     if (st == MPM_OK) st = dalloc(ctx, &d.perm, np);
     if (st == MPM_OK) st = dalloc(ctx, &d.bucket, nb * (size_t)kMaxBlockParticles);
+    if (st == MPM_OK) st = dalloc(ctx, &d.bsub, nb * (size_t)kMaxBlockParticles);
     if (st == MPM_OK) st = dalloc(ctx, &d.pflag, 2 * nv);
     if (st == MPM_OK) st = dalloc(ctx, &d.gflag, 2 * nv);
     if (st == MPM_OK) st = dalloc(ctx, &d.page, nv);

@@ -62,6 +62,7 @@ struct DevCtx {
     long long nbv;         // number of virtual blocks
     uint32_t *key;         // per particle: block * 64 + cell of the current buffer
     uint16_t *sub;         // per particle: (cell in block) << 3 | half-cell octant, see sub_code
+    uint16_t *bsub;        // [max_blocks][kMaxBlockParticles]: sub code of each bucket entry
     uint32_t *bucket;      // [max_blocks][kMaxBlockParticles]: particle indices of each particle
                            // block, in arrival order
     uint32_t *perm;        // exact stable sort order
@@ -93,6 +94,14 @@ struct PartArgs {
 };
 
 // ------------------------------------------------------------------ helpers
+// Workgroup barrier that orders LDS accesses only: outstanding global stores and
+// atomics of the workgroup are not waited for.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Hardware reciprocal and square root (about 1 ulp).  Used where a correctly
 // rounded result buys nothing: rotation angles, inverses of well-conditioned
 // quantities, normalisations.

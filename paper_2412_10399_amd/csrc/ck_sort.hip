@@ -315,7 +315,10 @@ __global__ void __launch_bounds__(kThreads) k_bucket_count(DevCtx d, int n) {
         const int j = tid * kCountPer + k;
         if (r[k] < 0) continue;
         const int slot = base_of[st[k]] + (j - st[k]);
-        if (slot < kMaxBlockParticles) d.bucket[(size_t)r[k] * kMaxBlockParticles + slot] = (uint32_t)(base + j);
+        if (slot < kMaxBlockParticles) {
+            d.bucket[(size_t)r[k] * kMaxBlockParticles + slot] = (uint32_t)(base + j);
+            d.bsub[(size_t)r[k] * kMaxBlockParticles + slot] = d.sub[base + j];
+        }
     }
 }
 

@@ -200,6 +200,13 @@ constexpr int kBins = 512;                 // (octant, cell) bins of a block: oc
 constexpr int kPerThread = kMaxBlockParticles / kP2GThreads;   // bucket entries per thread
 constexpr int kHold = 2;                   // of which kept in registers
 constexpr int kChunk = 2 * kP2GThreads;    // particles scattered per pass (two per thread)
+// Padded tile layout (64-bit words): node (x, y, z) of a grid at x + kTY y + kTZ z.
+// For any node offset, the 4 x 4 x 4 cells of a block then map x + kTY y onto 16
+// distinct residues modulo 16 (and kTZ is a multiple of 16), so the lanes of one
+// atomic spread evenly over the LDS banks.
+constexpr int kTY = 12, kTZ = 80;
+constexpr int kTileMStride = 4 * kTZ + 5 * kTY;   // words per channel, G- ([0,4]^3)
+constexpr int kTilePStride = 5 * kTZ + 6 * kTY;   // words per channel, G+ ([0,5]^3)
 constexpr double kMagic = 6755399441055744.0;                  // 1.5 * 2^52
 constexpr long long kMagicBits = 0x4338000000000000LL;
 
@@ -329,14 +336,14 @@ __device__ __forceinline__ void scatter_particle(const Staged &r, unsigned long 
         wp[a][0] = 1.0f - xp + r.sp[a];
         wp[a][1] = xp - r.sp[a];
     }
-    scatter_grid(tile_m, kTileMinus, (cz * 5 + cy) * 5 + cx, 5, 25, wm, r.mass, r.base, r.Q, S);
+    scatter_grid(tile_m, kTileMStride, cz * kTZ + cy * kTY + cx, kTY, kTZ, wm, r.mass, r.base, r.Q, S);
     // G+ momentum at the base node bp = c + up - 1: base + Q (up - 1/2)
 #pragma unroll
     for (int a = 0; a < 3; ++a)
         mp[a] = r.base[a] + ((float)up[0] - 0.5f) * r.Q[3 * a] + ((float)up[1] - 0.5f) * r.Q[3 * a + 1] +
                 ((float)up[2] - 0.5f) * r.Q[3 * a + 2];
-    const int t0 = ((cz + up[2]) * 6 + (cy + up[1])) * 6 + (cx + up[0]);
-    scatter_grid(tile_p, kTilePlus, t0, 6, 36, wp, r.mass, mp, r.Q, S);
+    const int t0 = (cz + up[2]) * kTZ + (cy + up[1]) * kTY + (cx + up[0]);
+    scatter_grid(tile_p, kTilePStride, t0, kTY, kTZ, wp, r.mass, mp, r.Q, S);
 }
 
 __global__ void __launch_bounds__(kP2GThreads) k_p2g(DevCtx d, PartArgs pa, float dt) {
@@ -345,13 +352,14 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g(DevCtx d, PartArgs pa, floa
     __shared__ int wsum[kP2GThreads / 64];
     __shared__ unsigned int bmax;
     __shared__ int nbr[27];
-    // ordering buffer, then the fixed-point tile [4][125] (G-) and [4][216] (G+)
-    constexpr int kTileWords = 4 * (kTileMinus + kTilePlus);
+    __shared__ uint32_t ord[kMaxBlockParticles];   // particle index at each position of the block order
+    // ordering buffer, then the fixed-point tile [4][G-] and [4][G+]
+    constexpr int kTileWords = 4 * (kTileMStride + kTilePStride);
     constexpr int kAreaWords = kTileWords > kMaxBlockParticles / 2 ? kTileWords : kMaxBlockParticles / 2;
     __shared__ unsigned long long area[kAreaWords];
     uint32_t *lbuf = reinterpret_cast<uint32_t *>(area);
     unsigned long long *tile_m = area;
-    unsigned long long *tile_p = area + 4 * kTileMinus;
+    unsigned long long *tile_p = area + 4 * kTileMStride;
     const int np = (int)d.counters[C_NPB];
     const int E = (int)d.counters[C_EPOCH];
     const int tid = threadIdx.x;
@@ -366,10 +374,11 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g(DevCtx d, PartArgs pa, floa
         const int cnt = d.pstart[r + 1] - s;
         if (cnt > kMaxBlockParticles) continue;   // reported by the bucket scan
         const uint32_t *bkt = d.bucket + (size_t)r * kMaxBlockParticles;
+        const uint16_t *bsb = d.bsub + (size_t)r * kMaxBlockParticles;
 
         // ---- order the block's particles by (octant, cell, index)
         for (int b = tid; b < kBins; b += kP2GThreads) bcnt[b] = 0;
-        __syncthreads();
+        lds_barrier();
         uint32_t hidx[kHold];
         int hbin[kHold];
 #pragma unroll
@@ -377,14 +386,14 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g(DevCtx d, PartArgs pa, floa
             const int j = tid + k * kP2GThreads;
             if (j >= cnt) break;
             const uint32_t idx = bkt[j];
-            const int bin = bin_of(d.sub[idx]);
+            const int bin = bin_of(bsb[j]);
             if (k < kHold) {
                 hidx[k] = idx;
                 hbin[k] = bin;
             }
             atomicAdd(&bcnt[bin], 1);
         }
-        __syncthreads();
+        lds_barrier();
         {
             // exclusive scan of the 512 bins, two per thread
             const int c0 = bcnt[2 * tid], c1 = bcnt[2 * tid + 1];
@@ -395,7 +404,7 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g(DevCtx d, PartArgs pa, floa
                 if (lane >= off) v += t;
             }
             if (lane == 63) wsum[w] = v;
-            __syncthreads();
+            lds_barrier();
             int pre = 0;
             for (int k = 0; k < w; ++k) pre += wsum[k];
             const int ex = pre + v - c0 - c1;
@@ -405,7 +414,7 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g(DevCtx d, PartArgs pa, floa
             bcnt[2 * tid + 1] = ex + c0;
             if (tid == kP2GThreads - 1) bstart[kBins] = ex + c0 + c1;
         }
-        __syncthreads();
+        lds_barrier();
 #pragma unroll
         for (int k = 0; k < kPerThread; ++k) {
             const int j = tid + k * kP2GThreads;
@@ -417,11 +426,11 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g(DevCtx d, PartArgs pa, floa
                 bin = hbin[k];
             } else {
                 idx = bkt[j];
-                bin = bin_of(d.sub[idx]);
+                bin = bin_of(bsb[j]);
             }
             lbuf[atomicAdd(&bcnt[bin], 1)] = idx;
         }
-        __syncthreads();
+        lds_barrier();
 #pragma unroll
         for (int k = 0; k < kPerThread; ++k) {
             const int j = tid + k * kP2GThreads;
@@ -433,16 +442,16 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g(DevCtx d, PartArgs pa, floa
                 bin = hbin[k];
             } else {
                 idx = bkt[j];
-                bin = bin_of(d.sub[idx]);
+                bin = bin_of(bsb[j]);
             }
             const int lo = bstart[bin], hi = bstart[bin + 1];
             int rank = lo;
             for (int q = lo; q < hi; ++q) rank += (lbuf[q] < idx) ? 1 : 0;
-            d.perm[s + rank] = idx;
+            ord[rank] = idx;
+            st_at(d.perm, (uint32_t)(s + rank), idx);
         }
-        __threadfence_block();   // the order is read back below by other threads
         load_neighbours(d, bx, by, bz, E, nbr);
-        __syncthreads();
+        lds_barrier();
 
         // ---- scatter, kChunk particles per pass (one pass unless the block is dense)
         for (int c0 = 0; c0 < cnt; c0 += kChunk) {
@@ -454,33 +463,33 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g(DevCtx d, PartArgs pa, floa
             for (int k = 0; k < 2; ++k) {
                 st[k].cell = -1;
                 const int j = c0 + tid + k * kP2GThreads;
-                if (j < cnt) stage_particle(d, pa, (int)d.perm[s + j], bx, by, bz, dt, st[k]);
+                if (j < cnt) stage_particle(d, pa, (int)ord[j], bx, by, bz, dt, st[k]);
                 bnd = fmaxf(bnd, contribution_bound(st[k]));
             }
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) bnd = fmaxf(bnd, __shfl_xor(bnd, off));
-            __syncthreads();   // tile cleared, bmax reset
+            lds_barrier();   // tile cleared, bmax reset
             if (lane == 0) atomicMax(&bmax, __float_as_uint(bnd));
-            __syncthreads();
+            lds_barrier();
             const float m = __uint_as_float(bmax);
             const double S = m > 0.0f ? ldexp(1.0, 39 - ilogbf(m)) : 1.0;
 #pragma unroll
             for (int k = 0; k < 2; ++k)
                 if (st[k].cell >= 0) scatter_particle(st[k], tile_m, tile_p, S);
-            __syncthreads();
+            lds_barrier();
             // ---- flush every nonzero tile node to the pool
             const double inv = 1.0 / S;
             for (int ni = tid; ni < kTileNodes; ni += kP2GThreads) {
-                float val[4];
-#pragma unroll
-                for (int ch = 0; ch < 4; ++ch) {
-                    const long long t = (long long)(ni < kTileMinus ? tile_m[ch * kTileMinus + ni]
-                                                                     : tile_p[ch * kTilePlus + ni - kTileMinus]);
-                    val[ch] = (float)((double)t * inv);
-                }
-                if (val[0] == 0.0f && val[1] == 0.0f && val[2] == 0.0f && val[3] == 0.0f) continue;
                 int g, ix, iy, iz;
                 tile_node(ni, bx, by, bz, g, ix, iy, iz);
+                const int lx = ix - 4 * bx + g, ly = iy - 4 * by + g, lz = iz - 4 * bz + g;   // tile-local
+                const unsigned long long *tb = g == 0 ? tile_m : tile_p;
+                const int cs = g == 0 ? kTileMStride : kTilePStride;
+                const int t = lx + ly * kTY + lz * kTZ;
+                float val[4];
+#pragma unroll
+                for (int ch = 0; ch < 4; ++ch) val[ch] = (float)((double)(long long)tb[ch * cs + t] * inv);
+                if (val[0] == 0.0f && val[1] == 0.0f && val[2] == 0.0f && val[3] == 0.0f) continue;
                 const long long a = pool_index(d, nbr, bx, by, bz, g, ix, iy, iz, 0);
                 if (a < 0) {
                     set_status(d.counters, ST_CAPACITY);
@@ -490,7 +499,7 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g(DevCtx d, PartArgs pa, floa
                 for (int ch = 0; ch < 4; ++ch)
                     if (val[ch] != 0.0f) atomicAdd(&d.pool[a + ch * 64], val[ch]);
             }
-            __syncthreads();
+            lds_barrier();
         }
     }
 }
@@ -568,7 +577,7 @@ __global__ void __launch_bounds__(kThreads) k_g2p(DevCtx d, PartArgs pa, float d
         G2PIn nxt;
         if (tid < cnt) g2p_load(d, pa, (uint32_t)(s + tid), nxt);
         load_neighbours(d, bx, by, bz, E, nbr);
-        __syncthreads();
+        lds_barrier();
         for (int ni = tid; ni < kTileNodes; ni += kThreads) {
             int g, ix, iy, iz;
             tile_node(ni, bx, by, bz, g, ix, iy, iz);
@@ -576,7 +585,7 @@ __global__ void __launch_bounds__(kThreads) k_g2p(DevCtx d, PartArgs pa, float d
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) vt[ch * kTileNodes + ni] = a >= 0 ? d.pool[a + ch * 64] : 0.0f;
         }
-        __syncthreads();
+        lds_barrier();
         for (int j = tid; j < cnt; j += kThreads) {
             const G2PIn q = nxt;
             if (j + kThreads < cnt) g2p_load(d, pa, (uint32_t)(s + j + kThreads), nxt);   // next particle
@@ -745,7 +754,7 @@ __global__ void __launch_bounds__(kThreads) k_g2p(DevCtx d, PartArgs pa, float d
                         for (int xx = lo[0]; xx <= hi[0]; ++xx) gf[vblock_id(g, xx, yy, zz)] = E + 1;
             }
         }
-        __syncthreads();
+        lds_barrier();
     }
 }
 
