@@ -75,6 +75,92 @@ def cpu_baseline(sc, max_seconds=30.0):
                       (steps, sc.n, dt)}
 
 
+def serve(srv, jobs, states, rate, ckmpm):
+    """Submit jobs on a Poisson clock of `rate` jobs/s (unit-rate arrival times
+    scaled), poll, and release finished jobs; returns per-job (submit, done, n, steps)
+    and the step latencies."""
+    t0 = time.perf_counter()
+    pending = list(range(len(jobs)))
+    live = {}
+    done = []
+    while pending or live:
+        now = time.perf_counter() - t0
+        while pending and jobs[pending[0]].arrival / rate <= now:
+            k = pending.pop(0)
+            cfg, mats, st, dt = states[k]
+            jid = srv.submit(cfg, mats, st, jobs[k].nsteps, dt)
+            live[jid] = k
+        srv.poll()
+        for jid in list(live):
+            info = srv.info(jid)
+            if info.state in (ckmpm.MPM_JOB_DONE, ckmpm.MPM_JOB_FAILED):
+                if info.state == ckmpm.MPM_JOB_FAILED:
+                    raise RuntimeError("job %d failed: %s" % (live[jid], ckmpm.status_string(info.status)))
+                done.append((info.t_submit, info.t_done, int(info.n), int(info.steps_done)))
+                srv.release(jid)
+                del live[jid]
+        time.sleep(0.0002)
+    return done, srv.step_latencies()
+
+
+def serving_main(args):
+    """Served-job benchmark: the seeded mix of 256 jobs (1e3-2e6 particles, elastic or
+    sand, 200 steps), first run one at a time through the server, then arriving as a
+    Poisson stream at 0.8x and 1.5x the one-at-a-time capacity."""
+    import numpy as np
+    import torch
+
+    import scenes
+    from paper_2412_10399_amd import ckmpm
+
+    torch.cuda.set_device(0)
+    jobs = scenes.serving_workload(seed=4, n_jobs=args.jobs)
+    states = []
+    for spec in jobs:
+        sc = scenes.serving_job(spec)
+        st = torch.from_numpy(ckmpm.state_planes(sc.x, sc.v, sc.B, sc.F)).to("cuda")
+        states.append((ckmpm.job_config(sc), ckmpm.scene_materials(sc), st, sc.dt))
+    torch.cuda.synchronize()
+    work = float(sum(st.shape[1] * j.nsteps for (_, _, st, _), j in zip(states, jobs)))
+    budget = 64 << 30
+
+    def summary(done, lat, wall):
+        jl = np.array([d - s for s, d, _, _ in done])
+        lat = np.array(lat)
+        return {"jobs": len(done), "particle_steps_per_s": work / wall, "wall_s": wall,
+                "step_latency_ms_p50": 1e3 * float(np.percentile(lat, 50)),
+                "step_latency_ms_p99": 1e3 * float(np.percentile(lat, 99)),
+                "job_latency_s_p50": float(np.percentile(jl, 50)), "job_latency_s_p99": float(np.percentile(jl, 99))}
+
+    # one at a time: every job submitted at t = 0, one resident job
+    srv = ckmpm.Server(budget, max_jobs=1, n_streams=1, steps_per_launch=args.steps_per_launch)
+    t0 = time.perf_counter()
+    done, lat = serve(srv, [dataclass_at_zero(j) for j in jobs], states, 1.0, ckmpm)
+    seq = summary(done, lat, time.perf_counter() - t0)
+    srv.close()
+    capacity_jobs = len(jobs) / seq["wall_s"]            # jobs/s the GPU finishes one at a time
+    out = {"metric": "served p99 step latency", "unit": "ms", "higher_is_better": False, "n_gpus": 1,
+           "data": "synthetic", "config": {"workload": "serving_mix_%d_jobs" % len(jobs), "seed": 4,
+                                           "particles_total": int(sum(st.shape[1] for _, _, st, _ in states)),
+                                           "steps_per_job": jobs[0].nsteps, "steps_per_launch": args.steps_per_launch,
+                                           "streams": args.streams, "max_jobs": args.max_jobs},
+           "one_at_a_time": seq}
+    for load in (0.8, 1.5):
+        srv = ckmpm.Server(budget, max_jobs=args.max_jobs, n_streams=args.streams,
+                           steps_per_launch=args.steps_per_launch)
+        t0 = time.perf_counter()
+        done, lat = serve(srv, jobs, states, load * capacity_jobs, ckmpm)
+        out["load_%.1f" % load] = summary(done, lat, time.perf_counter() - t0)
+        srv.close()
+    out["value"] = out["load_0.8"]["step_latency_ms_p99"]
+    print(json.dumps(out), flush=True)
+
+
+def dataclass_at_zero(spec):
+    import dataclasses
+    return dataclasses.replace(spec, arrival=0.0)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,11 +169,20 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this size first (calibrates HBM counters under rocprofv3)")
+    ap.add_argument("--serving", action="store_true", help="served-job benchmark instead of the step throughput")
+    ap.add_argument("--jobs", type=int, default=256)
+    ap.add_argument("--streams", type=int, default=4)
+    ap.add_argument("--max-jobs", type=int, default=32)
+    ap.add_argument("--steps-per-launch", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the step on a single MI355X; "
               "multi-GPU sharding is a design note only (--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+
+    if args.serving:
+        serving_main(args)
+        return
 
     import torch
 
