@@ -25,6 +25,8 @@ struct mpm_ctx {
     const float *next_ready = nullptr;   // buffer whose keys and next-epoch stamps are in place
     long long next_n = -1;
     const float *p2g_done = nullptr;     // buffer the last p2g ran on
+    int grid_pool = 0, grid_table = 0;   // the grid the last p2g (or fused step) wrote: pool and page table
+    int next_table = 0;                  // page table the next sort builds
     unsigned int *host_counters = nullptr;
     // profiling
     bool prof = false;
@@ -155,9 +157,11 @@ int64_t device_bytes_of(const mpm_config &c) {
     const long long np = c.max_particles, nb = c.max_blocks;
     const long long nchunks = (nbv + kCompactChunk - 1) / kCompactChunk;
     auto r = [](long long bytes) { return (bytes + 256 + 255) / 256 * 256; };
-    return r(4 * np) + r(2 * np) + r(4 * np) + r(4 * nb * (long long)kMaxBlockParticles) + r(2 * nb * (long long)kMaxBlockParticles) + r(8 * nbv) + r(8 * nbv) + r(4 * nbv) +
-           r(4 * nbv) + r(4 * nb) + r(4 * (nb + 1)) + r(4 * nb) + r(4 * nb) + r(4 * nchunks) + r(4 * nchunks) +
-           r(4 * nb * (long long)kBlockFloats) + r(24 * np) + r(4 * (long long)C_COUNT);
+    // the buffers of ctx_create, in its order
+    return r(4 * np) + r(2 * np) + r(4 * np) + r(4 * nb * (long long)kMaxBlockParticles) +
+           r(2 * nb * (long long)kMaxBlockParticles) + r(8 * nbv) + r(8 * nbv) + 2 * r(4 * nbv) + r(4 * nbv) +
+           r(4 * nb) + r(4 * (nb + 1)) + r(4 * nb) + 2 * r(4 * nb) + r(4 * nchunks) + r(4 * nchunks) +
+           2 * r(4 * nb * (long long)kBlockFloats) + r(24 * np) + r(4 * (long long)C_COUNT);
 }
 
 PartArgs part_args(const mpm_particles *p, bool with_out) {
@@ -206,14 +210,18 @@ mpm_status enqueue_p2g(mpm_ctx *ctx, const mpm_particles *p, double dt, hipStrea
     const bool ready = ctx->next_ready == pa.in && ctx->next_n == pa.n;
     if (ev) (void)hipEventRecord(ev[0], s);
     if (!ready) launch_flag_keys(ctx->d, pa, 1, s);
-    launch_compact(ctx->d, s);
-    launch_bucket(ctx->d, pa.n, s);
+    const int t = ctx->next_table;
+    launch_compact(ctx->d, t, s);
+    launch_bucket(ctx->d, pa.n, t, t, s);
+    ctx->next_table = t ^ 1;
     if (ev) (void)hipEventRecord(ev[1], s);
     if (!physics) {
         launch_block_sort(ctx->d, s);
     } else {
         if (!ready) launch_stress(ctx->d, pa, s);
-        launch_p2g(ctx->d, pa, (float)dt, s);
+        launch_p2g(ctx->d, pa, (float)dt, t, t, s);
+        ctx->grid_pool = t;
+        ctx->grid_table = t;
     }
     if (ev) (void)hipEventRecord(ev[2], s);
     ctx->next_ready = nullptr;
@@ -223,7 +231,7 @@ mpm_status enqueue_p2g(mpm_ctx *ctx, const mpm_particles *p, double dt, hipStrea
 
 mpm_status enqueue_update(mpm_ctx *ctx, double dt, hipStream_t s) {
     float g[3] = {(float)ctx->cfg.gravity[0], (float)ctx->cfg.gravity[1], (float)ctx->cfg.gravity[2]};
-    launch_grid_update(ctx->d, (float)dt, g, s);
+    launch_grid_update(ctx->d, (float)dt, g, ctx->grid_pool, ctx->grid_table, s);
     return last_error();
 }
 
@@ -233,7 +241,7 @@ mpm_status enqueue_g2p(mpm_ctx *ctx, mpm_particles *p, double dt, hipStream_t s)
     if ((p->id[0] == nullptr) != (p->id[1] == nullptr)) return MPM_E_INVALID;
     if ((p->mat[0] == nullptr) != (p->mat[1] == nullptr)) return MPM_E_INVALID;
     const PartArgs pa = part_args(p, true);
-    launch_g2p(ctx->d, pa, (float)dt, s);
+    launch_g2p(ctx->d, pa, (float)dt, ctx->grid_pool, ctx->grid_table, s);
     p->current ^= 1;
     ctx->next_ready = pa.out;
     ctx->next_n = pa.n;
@@ -277,15 +285,18 @@ mpm_status ctx_create(const mpm_config *cfg, const mpm_material *mats, int32_t n
     if (st == MPM_OK) st = dalloc(ctx, &d.bsub, nb * (size_t)kMaxBlockParticles);
     if (st == MPM_OK) st = dalloc(ctx, &d.pflag, 2 * nv);
     if (st == MPM_OK) st = dalloc(ctx, &d.gflag, 2 * nv);
-    if (st == MPM_OK) st = dalloc(ctx, &d.page, nv);
+    if (st == MPM_OK) st = dalloc(ctx, &d.page[0], nv);
+    if (st == MPM_OK) st = dalloc(ctx, &d.page[1], nv);
     if (st == MPM_OK) st = dalloc(ctx, &d.prank, nv);
     if (st == MPM_OK) st = dalloc(ctx, &d.plist, nb);
     if (st == MPM_OK) st = dalloc(ctx, &d.pstart, nb + 1);
     if (st == MPM_OK) st = dalloc(ctx, &d.bcount, nb);
-    if (st == MPM_OK) st = dalloc(ctx, &d.glist, nb);
+    if (st == MPM_OK) st = dalloc(ctx, &d.glist[0], nb);
+    if (st == MPM_OK) st = dalloc(ctx, &d.glist[1], nb);
     if (st == MPM_OK) st = dalloc(ctx, &d.chunk_p, nchunks);
     if (st == MPM_OK) st = dalloc(ctx, &d.chunk_g, nchunks);
-    if (st == MPM_OK) st = dalloc(ctx, &d.pool, nb * kBlockFloats);
+    if (st == MPM_OK) st = dalloc(ctx, &d.pool[0], nb * kBlockFloats);
+    if (st == MPM_OK) st = dalloc(ctx, &d.pool[1], nb * kBlockFloats);
     if (st == MPM_OK) st = dalloc(ctx, &d.tau, 6 * np);
     d.tau_stride = (long long)np;
     if (st == MPM_OK) st = dalloc(ctx, &d.counters, (size_t)C_COUNT);
@@ -298,7 +309,8 @@ mpm_status ctx_create(const mpm_config *cfg, const mpm_material *mats, int32_t n
     if (st == MPM_OK) {
         bool ok = hipMemsetAsync(d.pflag, 0, 2 * nv * sizeof(int), init_stream) == hipSuccess &&
                   hipMemsetAsync(d.gflag, 0, 2 * nv * sizeof(int), init_stream) == hipSuccess &&
-                  hipMemsetAsync(d.page, 0xff, nv * sizeof(int), init_stream) == hipSuccess &&
+                  hipMemsetAsync(d.page[0], 0xff, nv * sizeof(int), init_stream) == hipSuccess &&
+                  hipMemsetAsync(d.page[1], 0xff, nv * sizeof(int), init_stream) == hipSuccess &&
                   hipMemsetAsync(d.prank, 0xff, nv * sizeof(int), init_stream) == hipSuccess &&
                   hipMemsetAsync(d.pstart, 0, (nb + 1) * sizeof(int), init_stream) == hipSuccess &&
                   hipMemsetAsync(d.counters, 0, C_COUNT * sizeof(unsigned int), init_stream) == hipSuccess;
@@ -430,7 +442,7 @@ mpm_status mpm_sync(mpm_ctx *ctx, void *stream) {
 mpm_status mpm_grid_read(mpm_ctx *ctx, float *m, float *vec, void *stream) {
     if (!ctx) return MPM_E_INVALID;
     DeviceGuard g(ctx->device);
-    launch_grid_export(ctx->d, m, vec, (hipStream_t)stream);
+    launch_grid_export(ctx->d, m, vec, ctx->grid_pool, ctx->grid_table, (hipStream_t)stream);
     return last_error();
 }
 
@@ -461,7 +473,7 @@ mpm_status mpm_get_stats(mpm_ctx *ctx, mpm_stats *out, void *stream) {
     if (hipMemcpy(ctx->host_counters, ctx->d.counters, C_COUNT * sizeof(unsigned int), hipMemcpyDeviceToHost) != hipSuccess)
         return MPM_E_HIP;
     out->n_particle_blocks = ctx->host_counters[C_NPB];
-    out->n_grid_blocks = ctx->host_counters[C_NGB];
+    out->n_grid_blocks = ctx->host_counters[ngb_slot(ctx->grid_table)];
     out->max_block_particles = ctx->host_counters[C_MAXPB];
     out->status_bits = ctx->host_counters[C_STATUS];
     out->reserved = 0;

@@ -28,13 +28,16 @@ enum StatusBits : uint32_t {
 
 enum Counter : int {
     C_NPB = 0,      // particle blocks this step
-    C_NGB = 1,      // grid blocks this step
+    C_NGB = 1,      // grid blocks of page table 0 (table 1: C_NGB1)
     C_STATUS = 2,   // status bits
     C_EPOCH = 3,    // current activation epoch
     C_MAXPB = 4,    // largest particle count of a block
     C_TOTAL = 5,    // particles placed by the sort
+    C_NGB1 = 6,
     C_COUNT = 8
 };
+
+__host__ __device__ constexpr int ngb_slot(int table) { return table ? C_NGB1 : C_NGB; }
 
 struct DevMaterial {
     int model;      // 0 fixed corotated, 1 Drucker-Prager
@@ -66,17 +69,18 @@ struct DevCtx {
     uint32_t *bucket;      // [max_blocks][kMaxBlockParticles]: particle indices of each particle
                            // block, in arrival order
     uint32_t *perm;        // exact stable sort order
-    int *pflag, *gflag;    // [2][nbv] epoch stamps ("holds particles" / "grid block touched"),
-                           // double-buffered by epoch parity so that stamping the next step
-                           // never disturbs readers of the current one
-    int *page;             // per virtual block: physical pool block
+    int *pflag, *gflag;    // [2][nbv] epoch stamps ("holds particles" / "within one block of a
+                           // block holding particles"), double-buffered by epoch parity so that
+                           // stamping the next step never disturbs readers of the current one
+    int *page[2];          // two page tables: per virtual block the physical pool block, or -1
     int *prank;            // per virtual block: rank among the particle blocks
     int *plist;            // particle blocks in increasing virtual id
     int *pstart;           // first sorted position of each particle block (+1 sentinel)
     int *bcount;           // particles per particle block
-    int *glist;            // virtual id of each physical pool block
+    int *glist[2];         // per page table: virtual id of each physical pool block
     int *chunk_p, *chunk_g;
-    float *pool;           // max_blocks * 512 floats
+    float *pool[2];        // two grids of max_blocks * 512 floats (the fused step reads one and
+                           // writes the other)
     float *tau;            // [6][max_particles] Kirchhoff stress of the state G2P wrote, at its sorted position
     long long tau_stride;
     unsigned int *counters;
@@ -653,14 +657,14 @@ struct Allocator {
 
 void launch_flag_keys(const DevCtx &d, const PartArgs &pa, int epoch_offset, hipStream_t s);
 void launch_clear_flags(const DevCtx &d, hipStream_t s);
-void launch_compact(const DevCtx &d, hipStream_t s);
-void launch_bucket(const DevCtx &d, int n, hipStream_t s);
+void launch_compact(const DevCtx &d, int table, hipStream_t s);
+void launch_bucket(const DevCtx &d, int n, int zero_pool, int zero_table, hipStream_t s);
 void launch_block_sort(const DevCtx &d, hipStream_t s);
 void launch_stress(const DevCtx &d, const PartArgs &pa, hipStream_t s);
-void launch_p2g(const DevCtx &d, const PartArgs &pa, float dt, hipStream_t s);
-void launch_grid_update(const DevCtx &d, float dt, const float gravity[3], hipStream_t s);
-void launch_g2p(const DevCtx &d, const PartArgs &pa, float dt, hipStream_t s);
-void launch_grid_export(const DevCtx &d, float *m, float *vec, hipStream_t s);
+void launch_p2g(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, hipStream_t s);
+void launch_grid_update(const DevCtx &d, float dt, const float gravity[3], int gp, int gt, hipStream_t s);
+void launch_g2p(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, hipStream_t s);
+void launch_grid_export(const DevCtx &d, float *m, float *vec, int gp, int gt, hipStream_t s);
 void launch_copy_keys(const DevCtx &d, uint32_t *keys, uint32_t *perm, int n, hipStream_t s);
 
 }  // namespace ck

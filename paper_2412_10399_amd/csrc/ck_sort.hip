@@ -18,39 +18,42 @@ namespace {
 
 __device__ __forceinline__ int wave_lane() { return __lane_id(); }
 
-// Stamp the virtual blocks a particle needs: its own block (it holds particles) and
-// every block containing one of its 16 stencil nodes (G- nodes c..c+1 and G+ nodes
-// bp..bp+1 on each axis, so at most two blocks per axis).
-__device__ __forceinline__ void stamp_blocks(const DevCtx &d, const CellCoord &cc, int epoch) {
+// Stamp the virtual blocks a particle needs: its own block (it holds particles) and,
+// as grid blocks, the 3 x 3 x 3 blocks around it.  That neighbourhood holds the
+// particle's 16-node stencil, and also the stencil after a move of up to three
+// cells, which lets one sort serve the grid that the next step's fused transfer
+// writes.
+__device__ __forceinline__ void stamp_blocks(const DevCtx &d, int bx, int by, int bz, int epoch) {
     const Geometry &g = d.geo;
     int *pf = stamps(d.pflag, d.nbv, epoch);
     int *gf = stamps(d.gflag, d.nbv, epoch);
-    pf[vblock_id(g, cc.c[0] >> 2, cc.c[1] >> 2, cc.c[2] >> 2)] = epoch;
-    int lo[3], hi[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        lo[a] = min(cc.c[a], cc.bp[a]) >> 2;
-        hi[a] = (cc.c[a] + 1) >> 2;
-    }
-    for (int bz = lo[2]; bz <= hi[2]; ++bz)
-        for (int by = lo[1]; by <= hi[1]; ++by)
-            for (int bx = lo[0]; bx <= hi[0]; ++bx) gf[vblock_id(g, bx, by, bz)] = epoch;
+    pf[vblock_id(g, bx, by, bz)] = epoch;
+    for (int z = max(bz - 1, 0); z <= min(bz + 1, g.NB[2] - 1); ++z)
+        for (int y = max(by - 1, 0); y <= min(by + 1, g.NB[1] - 1); ++y)
+            for (int x = max(bx - 1, 0); x <= min(bx + 1, g.NB[0] - 1); ++x) gf[vblock_id(g, x, y, z)] = epoch;
 }
 
 __global__ void __launch_bounds__(kThreads) k_flag_keys(DevCtx d, PartArgs pa, int epoch_offset) {
     const int i = blockIdx.x * kThreads + threadIdx.x;
-    if (i >= pa.n) return;
     const int epoch = (int)d.counters[C_EPOCH] + epoch_offset;
-    const float x[3] = {pa.in[i], pa.in[pa.stride + i], pa.in[2 * pa.stride + i]};
+    bool ok = i < pa.n;
     CellCoord cc;
-    if (!cell_coord(d.geo, x, cc)) {
-        d.key[i] = 0xffffffffu;
-        set_status(d.counters, ST_DOMAIN);
-        return;
+    if (ok) {
+        const float x[3] = {pa.in[i], pa.in[pa.stride + i], pa.in[2 * pa.stride + i]};
+        ok = cell_coord(d.geo, x, cc);
+        if (!ok) {
+            d.key[i] = 0xffffffffu;
+            set_status(d.counters, ST_DOMAIN);
+        }
     }
+    // every lane takes part in the neighbour comparison below
+    const int vb = ok ? vblock_id(d.geo, cc.c[0] >> 2, cc.c[1] >> 2, cc.c[2] >> 2) : -1;
+    const int prev = __shfl_up(vb, 1);
+    if (!ok) return;
     d.key[i] = cell_key(d.geo, cc);
     d.sub[i] = (uint16_t)sub_code(cc);
-    stamp_blocks(d, cc, epoch);
+    // one stamping lane per run of equal blocks (particles mostly arrive sorted)
+    if ((threadIdx.x & 63) == 0 || prev != vb) stamp_blocks(d, cc.c[0] >> 2, cc.c[1] >> 2, cc.c[2] >> 2, epoch);
 }
 
 __global__ void k_clear_flags(DevCtx d) {
@@ -150,14 +153,14 @@ __device__ int wg_scan_inplace(int *data, int n, int *sh) {
     return total;
 }
 
-__global__ void __launch_bounds__(1024) k_compact_scan(DevCtx d, int nchunks) {
+__global__ void __launch_bounds__(1024) k_compact_scan(DevCtx d, int nchunks, int table) {
     __shared__ int sh[32];
     const int np = wg_scan_inplace<1024>(d.chunk_p, nchunks, sh);
     const int ng = wg_scan_inplace<1024>(d.chunk_g, nchunks, sh);
     if (threadIdx.x == 0) {
         if (ng > d.max_blocks || np > d.max_blocks) set_status(d.counters, ST_CAPACITY);
         d.counters[C_NPB] = (unsigned)min(np, d.max_blocks);
-        d.counters[C_NGB] = (unsigned)min(ng, d.max_blocks);
+        d.counters[ngb_slot(table)] = (unsigned)min(ng, d.max_blocks);
         d.counters[C_EPOCH] += 1u;
         d.counters[C_MAXPB] = 0u;
         d.counters[C_TOTAL] = 0u;
@@ -188,7 +191,7 @@ __device__ __forceinline__ int wg_excl_scan(int x, int &excl, int *sh) {
     return tot;
 }
 
-__global__ void __launch_bounds__(kThreads) k_compact_emit(DevCtx d) {
+__global__ void __launch_bounds__(kThreads) k_compact_emit(DevCtx d, int table) {
     __shared__ int sh[8];
     const int E = (int)d.counters[C_EPOCH];
     const int *pf = stamps(d.pflag, d.nbv, E);
@@ -223,14 +226,17 @@ __global__ void __launch_bounds__(kThreads) k_compact_emit(DevCtx d) {
             }
             ++rp;
         }
-        if (fg[k]) {
-            if (rg < d.max_blocks) {
-                d.glist[rg] = v;
-                d.page[v] = rg;
-            } else {
-                d.page[v] = -1;
+        if (v < d.nbv) {
+            // every virtual block gets its entry, so the table is valid without stamps
+            int ph = -1;
+            if (fg[k]) {
+                if (rg < d.max_blocks) {
+                    d.glist[table][rg] = v;
+                    ph = rg;
+                }
+                ++rg;
             }
-            ++rg;
+            d.page[table][v] = ph;
         }
     }
     (void)gtot;
@@ -245,7 +251,7 @@ __global__ void __launch_bounds__(kThreads) k_compact_emit(DevCtx d) {
 constexpr int kCountPer = 4;                       // consecutive particles per thread
 constexpr int kCountTile = kThreads * kCountPer;   // particles per workgroup
 
-__global__ void __launch_bounds__(kThreads) k_bucket_count(DevCtx d, int n) {
+__global__ void __launch_bounds__(kThreads) k_bucket_count(DevCtx d, int n, int zero_pool, int zero_table) {
     __shared__ int rblk[kCountTile];   // particle block rank of each particle of the tile (-1: skipped)
     __shared__ int base_of[kCountTile];
     __shared__ int wmax[kThreads / 64];
@@ -255,8 +261,8 @@ __global__ void __launch_bounds__(kThreads) k_bucket_count(DevCtx d, int n) {
     const int base = blockIdx.x * kCountTile;
     // zero a share of the pool blocks handed out this step
     {
-        const long long nfl = (long long)d.counters[C_NGB] * (kBlockFloats / 4);
-        float4 *pool4 = reinterpret_cast<float4 *>(d.pool);
+        const long long nfl = (long long)d.counters[ngb_slot(zero_table)] * (kBlockFloats / 4);
+        float4 *pool4 = reinterpret_cast<float4 *>(d.pool[zero_pool]);
         for (long long t = (long long)blockIdx.x * kThreads + tid; t < nfl; t += (long long)gridDim.x * kThreads)
             pool4[t] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
@@ -397,17 +403,18 @@ void launch_clear_flags(const DevCtx &d, hipStream_t s) {
     hipLaunchKernelGGL(k_clear_flags, dim3(1024), dim3(256), 0, s, d);
 }
 
-void launch_compact(const DevCtx &d, hipStream_t s) {
+void launch_compact(const DevCtx &d, int table, hipStream_t s) {
     const int nchunks = (int)((d.nbv + kCompactChunk - 1) / kCompactChunk);
     hipLaunchKernelGGL(k_compact_count, dim3(nchunks), dim3(kThreads), 0, s, d);
-    hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, s, d, nchunks);
-    hipLaunchKernelGGL(k_compact_emit, dim3(nchunks), dim3(kThreads), 0, s, d);
+    hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, s, d, nchunks, table);
+    hipLaunchKernelGGL(k_compact_emit, dim3(nchunks), dim3(kThreads), 0, s, d, table);
 }
 
-void launch_bucket(const DevCtx &d, int n, hipStream_t s) {
+void launch_bucket(const DevCtx &d, int n, int zero_pool, int zero_table, hipStream_t s) {
     // at least a few hundred workgroups, so that the pool clearing is spread wide
     const int tiles = (n + kCountTile - 1) / kCountTile;
-    hipLaunchKernelGGL(k_bucket_count, dim3(tiles > 1024 ? tiles : 1024), dim3(kThreads), 0, s, d, n);
+    hipLaunchKernelGGL(k_bucket_count, dim3(tiles > 1024 ? tiles : 1024), dim3(kThreads), 0, s, d, n, zero_pool,
+                       zero_table);
     hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, d);
 }
 

@@ -21,17 +21,41 @@ __device__ __forceinline__ void block_coords(const Geometry &g, int vb, int &bx,
     bz = vb / (g.NB[0] * g.NB[1]);
 }
 
-// Physical pool block of the 27 neighbours of block (bx,by,bz), -1 when inactive.
-__device__ __forceinline__ void load_neighbours(const DevCtx &d, int bx, int by, int bz, int E, int *nbr) {
+// Physical pool block of the 27 neighbours of block (bx,by,bz) in page table
+// `table`, -1 when inactive.
+__device__ __forceinline__ void load_neighbours(const DevCtx &d, int table, int bx, int by, int bz, int *nbr) {
     const int t = threadIdx.x;
     if (t < 27) {
         const int x = bx + t % 3 - 1, y = by + (t / 3) % 3 - 1, z = bz + t / 9 - 1;
         int ph = -1;
-        if (x >= 0 && y >= 0 && z >= 0 && x < d.geo.NB[0] && y < d.geo.NB[1] && z < d.geo.NB[2]) {
-            const int v = vblock_id(d.geo, x, y, z);
-            if (stamps(d.gflag, d.nbv, E)[v] == E) ph = d.page[v];
-        }
+        if (x >= 0 && y >= 0 && z >= 0 && x < d.geo.NB[0] && y < d.geo.NB[1] && z < d.geo.NB[2])
+            ph = d.page[table][vblock_id(d.geo, x, y, z)];
         nbr[t] = ph;
+    }
+}
+
+// Stamps, for the next sort (epoch E), every distinct block among the lanes of a
+// wave (vb < 0: none) as holding particles and its 3 x 3 x 3 neighbourhood as grid
+// blocks, lanes 0..26 writing one neighbour each.  Called by every lane of the wave;
+// particles in block order mostly share a few blocks per wave.
+__device__ __forceinline__ void wave_stamp(const DevCtx &d, int vb, int E) {
+    const int lane = threadIdx.x & 63;
+    const int prev = __shfl_up(vb, 1);
+    unsigned long long lead = __ballot(vb >= 0 && (lane == 0 || prev != vb));
+    const Geometry &g = d.geo;
+    int *pf = stamps(d.pflag, d.nbv, E);
+    int *gf = stamps(d.gflag, d.nbv, E);
+    while (lead) {
+        const int l = __ffsll((long long)lead) - 1;
+        lead &= lead - 1;
+        const int v = __shfl(vb, l);
+        const int bx = v % g.NB[0], by = (v / g.NB[0]) % g.NB[1], bz = v / (g.NB[0] * g.NB[1]);
+        if (lane < 27) {
+            const int x = bx + lane % 3 - 1, y = by + (lane / 3) % 3 - 1, z = bz + lane / 9 - 1;
+            if (x >= 0 && y >= 0 && z >= 0 && x < g.NB[0] && y < g.NB[1] && z < g.NB[2]) gf[vblock_id(g, x, y, z)] = E;
+        } else if (lane == 27) {
+            pf[v] = E;
+        }
     }
 }
 
@@ -346,7 +370,7 @@ __device__ __forceinline__ void scatter_particle(const Staged &r, unsigned long 
     scatter_grid(tile_p, kTilePStride, t0, kTY, kTZ, wp, r.mass, mp, r.Q, S);
 }
 
-__global__ void __launch_bounds__(kP2GThreads) k_p2g(DevCtx d, PartArgs pa, float dt) {
+__global__ void __launch_bounds__(kP2GThreads) k_p2g(DevCtx d, PartArgs pa, float dt, int gp, int gt) {
     __shared__ int bcnt[kBins];                 // counts, then placement cursors
     __shared__ int bstart[kBins + 1];
     __shared__ int wsum[kP2GThreads / 64];
@@ -361,7 +385,6 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g(DevCtx d, PartArgs pa, floa
     unsigned long long *tile_m = area;
     unsigned long long *tile_p = area + 4 * kTileMStride;
     const int np = (int)d.counters[C_NPB];
-    const int E = (int)d.counters[C_EPOCH];
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
     for (int base = 0; base < np; base += gridDim.x) {
@@ -450,7 +473,7 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g(DevCtx d, PartArgs pa, floa
             ord[rank] = idx;
             st_at(d.perm, (uint32_t)(s + rank), idx);
         }
-        load_neighbours(d, bx, by, bz, E, nbr);
+        load_neighbours(d, gt, bx, by, bz, nbr);
         lds_barrier();
 
         // ---- scatter, kChunk particles per pass (one pass unless the block is dense)
@@ -497,7 +520,7 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g(DevCtx d, PartArgs pa, floa
                 }
 #pragma unroll
                 for (int ch = 0; ch < 4; ++ch)
-                    if (val[ch] != 0.0f) atomicAdd(&d.pool[a + ch * 64], val[ch]);
+                    if (val[ch] != 0.0f) atomicAdd(&d.pool[gp][a + ch * 64], val[ch]);
             }
             lds_barrier();
         }
@@ -507,18 +530,18 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g(DevCtx d, PartArgs pa, floa
 // ---------------------------------------------------------------- grid update
 // Section 4.3 grid update on each grid: m v~ = m v + dt f (the stress impulse is
 // already in the momentum), plus gravity; v~ = 0 where m = 0 and on wall nodes.
-__global__ void __launch_bounds__(128) k_grid_update(DevCtx d, float dt, float g0, float g1, float g2) {
-    const int ng = (int)d.counters[C_NGB];
+__global__ void __launch_bounds__(128) k_grid_update(DevCtx d, float dt, float g0, float g1, float g2, int gp, int gt) {
+    const int ng = (int)d.counters[ngb_slot(gt)];
     const int t = threadIdx.x;
     const int g = t >> 6, l = t & 63;
     const int lx = l & 3, ly = (l >> 2) & 3, lz = l >> 4;
     for (int b = blockIdx.x; b < ng; b += gridDim.x) {
         int bx, by, bz;
-        block_coords(d.geo, d.glist[b], bx, by, bz);
+        block_coords(d.geo, d.glist[gt][b], bx, by, bz);
         const int ix = 4 * bx + lx, iy = 4 * by + ly, iz = 4 * bz + lz;
         const bool inside = ix >= d.geo.stick_lo[g] && iy >= d.geo.stick_lo[g] && iz >= d.geo.stick_lo[g] &&
                             ix <= d.geo.stick_hi[g][0] && iy <= d.geo.stick_hi[g][1] && iz <= d.geo.stick_hi[g][2];
-        float *blk = d.pool + (size_t)b * kBlockFloats + g * 256;
+        float *blk = d.pool[gp] + (size_t)b * kBlockFloats + g * 256;
         const float m = blk[l];
         float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f;
         if (m > 0.0f && inside) {
@@ -557,7 +580,7 @@ __device__ __forceinline__ void g2p_load(const DevCtx &d, const PartArgs &pa, ui
     q.id = pa.id_in ? ld_at(pa.id_in, p) : 0u;
 }
 
-__global__ void __launch_bounds__(kThreads) k_g2p(DevCtx d, PartArgs pa, float dt) {
+__global__ void __launch_bounds__(kThreads) k_g2p(DevCtx d, PartArgs pa, float dt, int gp, int gt) {
     __shared__ float vt[3 * kTileNodes];
     __shared__ int nbr[27];
     const int np = (int)d.counters[C_NPB];
@@ -576,33 +599,33 @@ __global__ void __launch_bounds__(kThreads) k_g2p(DevCtx d, PartArgs pa, float d
         // the first particle's inputs load while the tile is gathered
         G2PIn nxt;
         if (tid < cnt) g2p_load(d, pa, (uint32_t)(s + tid), nxt);
-        load_neighbours(d, bx, by, bz, E, nbr);
+        load_neighbours(d, gt, bx, by, bz, nbr);
         lds_barrier();
         for (int ni = tid; ni < kTileNodes; ni += kThreads) {
             int g, ix, iy, iz;
             tile_node(ni, bx, by, bz, g, ix, iy, iz);
             const long long a = pool_index(d, nbr, bx, by, bz, g, ix, iy, iz, 1);
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) vt[ch * kTileNodes + ni] = a >= 0 ? d.pool[a + ch * 64] : 0.0f;
+            for (int ch = 0; ch < 3; ++ch) vt[ch * kTileNodes + ni] = a >= 0 ? d.pool[gp][a + ch * 64] : 0.0f;
         }
         lds_barrier();
-        for (int j = tid; j < cnt; j += kThreads) {
+        for (int j0 = 0; j0 < cnt; j0 += kThreads) {   // the same trip count for every lane
+            const int j = j0 + tid;
+            const bool act = j < cnt;
             const G2PIn q = nxt;
             if (j + kThreads < cnt) g2p_load(d, pa, (uint32_t)(s + j + kThreads), nxt);   // next particle
             const uint32_t out = (uint32_t)(s + j);
             CellCoord cc;
-            bool ok = cell_coord(d.geo, q.x, cc);
+            bool ok = act && cell_coord(d.geo, q.x, cc);
             ok = ok && (cc.c[0] >> 2) == bx && (cc.c[1] >> 2) == by && (cc.c[2] >> 2) == bz;
             // activation stamps of the next step, deduplicated between neighbouring lanes
-            // (sorted particles mostly share their blocks): -1 = none, else the
-            // particle block and whether the stencil reaches the lower / upper
-            // neighbour block along each axis
-            long long sig = -1;
+            // (sorted particles mostly share their blocks): -1 = none, else the block
+            int sig = -1;
             CellCoord cn;
-            if (!ok) {
+            if (act && !ok) {
                 set_status(d.counters, ST_STALE);
                 st_at(d.key, out, 0xffffffffu);
-            } else {
+            } else if (ok) {
                 const DevMaterial M = d.mats[q.mat < d.n_mat ? q.mat : 0];
                 Weights w;
                 axis_weights(cc, w);
@@ -720,65 +743,36 @@ __global__ void __launch_bounds__(kThreads) k_g2p(DevCtx d, PartArgs pa, float d
                     const uint32_t key = cell_key(d.geo, cn);
                     st_at(d.key, out, key);
                     st_at(d.sub, out, (uint16_t)sub_code(cn));
-                    int reach = 0;
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        reach |= ((min(cn.c[a], cn.bp[a]) >> 2) != (cn.c[a] >> 2)) << (2 * a);
-                        reach |= (((cn.c[a] + 1) >> 2) != (cn.c[a] >> 2)) << (2 * a + 1);
-                    }
-                    sig = (long long)(key >> 6) << 6 | reach;
+                    sig = (int)(key >> 6);
                 } else {
                     st_at(d.key, out, 0xffffffffu);
                     set_status(d.counters, ST_DOMAIN);
                 }
             }
-            const long long prev = __shfl_up(sig, 1);
-            if (sig >= 0 && ((threadIdx.x & 63) == 0 || prev != sig)) {
-                const Geometry &g = d.geo;
-                int *pf = stamps(d.pflag, d.nbv, E + 1);
-                int *gf = stamps(d.gflag, d.nbv, E + 1);
-                const int vbn = (int)(sig >> 6);
-                pf[vbn] = E + 1;
-                int bc[3];
-                bc[0] = vbn % g.NB[0];
-                bc[1] = (vbn / g.NB[0]) % g.NB[1];
-                bc[2] = vbn / (g.NB[0] * g.NB[1]);
-                int lo[3], hi[3];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    lo[a] = bc[a] - (int)((sig >> (2 * a)) & 1);
-                    hi[a] = bc[a] + (int)((sig >> (2 * a + 1)) & 1);
-                }
-                for (int zz = lo[2]; zz <= hi[2]; ++zz)
-                    for (int yy = lo[1]; yy <= hi[1]; ++yy)
-                        for (int xx = lo[0]; xx <= hi[0]; ++xx) gf[vblock_id(g, xx, yy, zz)] = E + 1;
-            }
+            wave_stamp(d, sig, E + 1);
         }
         lds_barrier();
     }
 }
 
 // ---------------------------------------------------------------- exports
-__global__ void k_grid_export(DevCtx d, float *m, float *vec) {
+__global__ void k_grid_export(DevCtx d, float *m, float *vec, int gp, int gt) {
     const long long nx = d.geo.n[0] + 1, ny = d.geo.n[1] + 1, nz = d.geo.n[2] + 1;
     const long long nodes = nx * ny * nz;
-    const int E = (int)d.counters[C_EPOCH];
     for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < 2 * nodes; t += (long long)gridDim.x * blockDim.x) {
         const int g = (int)(t / nodes);
         const long long r = t - g * nodes;
         const int ix = (int)(r % nx), iy = (int)((r / nx) % ny), iz = (int)(r / (nx * ny));
         const int v = vblock_id(d.geo, ix >> 2, iy >> 2, iz >> 2);
         float mm = 0.0f, a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
-        if (stamps(d.gflag, d.nbv, E)[v] == E) {
-            const int ph = d.page[v];
-            if (ph >= 0) {
-                const float *blk = d.pool + (size_t)ph * kBlockFloats + g * 256;
-                const int l = (iz & 3) * 16 + (iy & 3) * 4 + (ix & 3);
-                mm = blk[l];
-                a0 = blk[64 + l];
-                a1 = blk[128 + l];
-                a2 = blk[192 + l];
-            }
+        const int ph = d.page[gt][v];
+        if (ph >= 0) {
+            const float *blk = d.pool[gp] + (size_t)ph * kBlockFloats + g * 256;
+            const int l = (iz & 3) * 16 + (iy & 3) * 4 + (ix & 3);
+            mm = blk[l];
+            a0 = blk[64 + l];
+            a1 = blk[128 + l];
+            a2 = blk[192 + l];
         }
         if (m) m[t] = mm;
         if (vec) {
@@ -811,21 +805,21 @@ void launch_stress(const DevCtx &d, const PartArgs &pa, hipStream_t s) {
     if (pa.n > 0) hipLaunchKernelGGL(k_stress, dim3((pa.n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, d, pa);
 }
 
-void launch_p2g(const DevCtx &d, const PartArgs &pa, float dt, hipStream_t s) {
-    hipLaunchKernelGGL(k_p2g, dim3(particle_grid(d)), dim3(kP2GThreads), 0, s, d, pa, dt);
+void launch_p2g(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, hipStream_t s) {
+    hipLaunchKernelGGL(k_p2g, dim3(particle_grid(d)), dim3(kP2GThreads), 0, s, d, pa, dt, gp, gt);
 }
 
-void launch_grid_update(const DevCtx &d, float dt, const float gravity[3], hipStream_t s) {
+void launch_grid_update(const DevCtx &d, float dt, const float gravity[3], int gp, int gt, hipStream_t s) {
     hipLaunchKernelGGL(k_grid_update, dim3(d.max_blocks < 16384 ? d.max_blocks : 16384), dim3(128), 0, s, d, dt,
-                       gravity[0], gravity[1], gravity[2]);
+                       gravity[0], gravity[1], gravity[2], gp, gt);
 }
 
-void launch_g2p(const DevCtx &d, const PartArgs &pa, float dt, hipStream_t s) {
-    hipLaunchKernelGGL(k_g2p, dim3(particle_grid(d)), dim3(kThreads), 0, s, d, pa, dt);
+void launch_g2p(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, hipStream_t s) {
+    hipLaunchKernelGGL(k_g2p, dim3(particle_grid(d)), dim3(kThreads), 0, s, d, pa, dt, gp, gt);
 }
 
-void launch_grid_export(const DevCtx &d, float *m, float *vec, hipStream_t s) {
-    hipLaunchKernelGGL(k_grid_export, dim3(4096), dim3(256), 0, s, d, m, vec);
+void launch_grid_export(const DevCtx &d, float *m, float *vec, int gp, int gt, hipStream_t s) {
+    hipLaunchKernelGGL(k_grid_export, dim3(4096), dim3(256), 0, s, d, m, vec, gp, gt);
 }
 
 void launch_copy_keys(const DevCtx &d, uint32_t *keys, uint32_t *perm, int n, hipStream_t s) {
