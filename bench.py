@@ -25,13 +25,20 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PARTICLE_BYTES = {"p2g": 96, "g2p": 144}            # algorithmic particle bytes per kernel
-GRID_BLOCK_BYTES = {"p2g": 2048, "g2p": 1536, "grid_update": 3584}
+# algorithmic bytes per particle and per active grid block of each kernel: p2g reads
+# the state (96 B) and adds its grid (2048 B/block); g2p reads x, F (48 B), writes x,
+# v, B, F (96 B) and reads the grid velocities (1536 B/block); the fused g2p2g reads
+# x, F and writes x, v, B, F (144 B), reads grid n's velocities and adds grid n+1
+PARTICLE_BYTES = {"p2g": 96, "g2p": 144, "g2p2g": 144}
+GRID_BLOCK_BYTES = {"p2g": 2048, "g2p": 1536, "grid_update": 3584, "g2p2g": 3584}
+# one step: p2g + g2p particle bytes (the fused step reads x, F once and writes x, v,
+# B, F once); per grid block: clearing, the P2G flush, the update and the G2P read
 STEP_PARTICLE_BYTES = 240
-STEP_GRID_BLOCK_BYTES = 9 * 1024
+STEP_PARTICLE_BYTES_FUSED = 144
+STEP_GRID_BLOCK_BYTES = 2048 + 2048 + 3584 + 1536
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sand_column_4M.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2412_10399_amd", "csrc", f) for f in ("ck_transfer.hip", "ck_common.hpp")]
-KERNEL_SYMBOL = {"p2g": "k_p2g", "g2p": "k_g2p", "grid_update": "k_grid_update"}
+KERNEL_SYMBOL = {"p2g": "k_p2g", "g2p": "k_g2p", "grid_update": "k_grid_update", "g2p2g": "k_g2p2g"}
 
 
 def source_digest():
@@ -167,6 +174,7 @@ def main():
     ap.add_argument("--steps", type=int, default=490)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fused", action="store_true", help="fused G2P+P2G kernel from the second step on")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this size first (calibrates HBM counters under rocprofv3)")
     ap.add_argument("--serving", action="store_true", help="served-job benchmark instead of the step throughput")
@@ -203,7 +211,7 @@ def main():
         del src, dst, flush
 
     sc = scenes.sand_column()
-    ctx = ckmpm.Context(ckmpm.scene_config(sc), ckmpm.scene_materials(sc))
+    ctx = ckmpm.Context(ckmpm.scene_config(sc, fused=args.fused), ckmpm.scene_materials(sc))
     parts = ckmpm.particles_from_scene(sc, "cuda:0")
     stream = torch.cuda.current_stream()
     h = ctx.h
@@ -231,11 +239,11 @@ def main():
     value = sc.n * args.steps / (total_ms / 1e3)
     avg = {name: (phase_ms[i] / phase_n[i] if phase_n[i] else 0.0) for i, name in enumerate(ckmpm.PHASES)}
     ngb = int(stats.n_grid_blocks)
-    dominant = max(("p2g", "g2p", "grid_update"), key=lambda k: avg[k])
+    dominant = max(("p2g", "g2p", "grid_update", "g2p2g"), key=lambda k: avg[k] * phase_n[ckmpm.PHASES.index(k)])
     alg_bytes = PARTICLE_BYTES.get(dominant, 0) * sc.n + GRID_BLOCK_BYTES[dominant] * ngb
     achieved = alg_bytes / (avg[dominant] * 1e-3) / 1e9
     traffic = measured_traffic(dominant, sc.n)
-    step_bytes = STEP_PARTICLE_BYTES * sc.n + STEP_GRID_BLOCK_BYTES * ngb
+    step_bytes = (STEP_PARTICLE_BYTES_FUSED if args.fused else STEP_PARTICLE_BYTES) * sc.n + STEP_GRID_BLOCK_BYTES * ngb
     result = {
         "metric": "particle-steps/s at 4M particles",
         "value": value,
@@ -251,7 +259,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "sand_column_drucker_prager", "particles": sc.n, "grid": "256^3", "dx": sc.dx,
                    "dt": sc.dt, "ppc": 8, "active_grid_blocks": ngb,
-                   "particle_blocks": int(stats.n_particle_blocks)},
+                   "particle_blocks": int(stats.n_particle_blocks), "fused_g2p2g": bool(args.fused)},
         "roofline": {"bound": "hbm", "kernel": KERNEL_SYMBOL[dominant], "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "alg_bytes_per_launch": alg_bytes,

@@ -54,12 +54,16 @@ typedef enum {
     MPM_E_CAPACITY = 4,  /* block pool or per-block particle capacity exceeded (device)      */
     MPM_E_NONFINITE = 5, /* a NaN/Inf appeared in v, B or F (device-detected)                */
     MPM_E_HIP = 6,       /* a HIP runtime call failed                                        */
-    MPM_E_STALE = 7      /* positions changed after the library computed their cell keys      */
+    MPM_E_STALE = 7,     /* positions changed after the library computed their cell keys      */
+    MPM_E_CFL = 8        /* in mpm_step, a particle moved more than three cells in one step    */
 } mpm_status;
 
 enum { MPM_FIXED_COROTATED = 0, MPM_DRUCKER_PRAGER = 1 };
 enum { MPM_BC_NONE = 0, MPM_BC_STICKY = 1 };
 enum { MPM_TRANSFER_MLS = 0 };
+/* mpm_config.flags: mpm_step runs each step's G2P and the next step's P2G as one
+ * kernel (section 3.2's fused transfer); same results up to summation order. */
+enum { MPM_FLAG_FUSED_G2P2G = 1 };
 
 typedef struct {
     int32_t n_cells[3];    /* cells per axis; nodes per axis and grid = n_cells + 1                */
@@ -73,7 +77,7 @@ typedef struct {
                               device memory is about 10 KiB per block (2 KiB of grid, 8 KiB of
                               sort buckets of up to 2048 particles per block)                      */
     int32_t transfer;      /* MPM_TRANSFER_MLS                                                      */
-    int32_t flags;         /* reserved, must be 0                                                   */
+    int32_t flags;         /* 0 or MPM_FLAG_FUSED_G2P2G                                             */
 } mpm_config;
 
 typedef struct {
@@ -132,11 +136,17 @@ mpm_status mpm_grid_update(mpm_ctx *ctx, double dt, void *stream);
  * keys, and flips p->current. */
 mpm_status mpm_g2p(mpm_ctx *ctx, mpm_particles *p, double dt, void *stream);
 
-/* nsteps x (p2g, grid_update, g2p), enqueued back to back without host syncs. */
+/* nsteps x (p2g, grid_update, g2p), enqueued back to back without host syncs.  With
+ * MPM_FLAG_FUSED_G2P2G, each step's G2P and the next step's P2G run as one kernel
+ * from the second step on (the same arithmetic; the grid each fused P2G writes is the
+ * 3x3x3 block neighbourhood of the particle blocks, so a particle may move at most
+ * three cells per step, else MPM_E_CFL).  Either way the state, the grid left for
+ * mpm_grid_read and the carried keys and stress afterwards are those of the phase
+ * calls, up to summation order. */
 mpm_status mpm_step(mpm_ctx *ctx, mpm_particles *p, double dt, int32_t nsteps, void *stream);
 
 /* Wait for `stream`, then return (and clear) the device status word as a status code:
- * NONFINITE before DOMAIN before CAPACITY before STALE. */
+ * NONFINITE before DOMAIN before CAPACITY before STALE before CFL. */
 mpm_status mpm_sync(mpm_ctx *ctx, void *stream);
 
 /* Export the grid as dense arrays (device pointers): m[2][nz+1][ny+1][nx+1] and
@@ -158,7 +168,10 @@ mpm_status mpm_invalidate(mpm_ctx *ctx);
 mpm_status mpm_get_stats(mpm_ctx *ctx, mpm_stats *out, void *stream);
 
 /* Per-phase timing with HIP events on the launch stream: enable, read totals (ms) and
- * launch counts of the phases {sort+activate, p2g, grid update, g2p} since enabling. */
+ * interval counts of the phases {sort+activate, p2g, grid update, g2p, fused g2p+p2g}
+ * since enabling (n_phases <= 5 are filled).  In mpm_step the steps after the first
+ * time the fused kernel as phase 4 and have no separate g2p; the last step's sort and
+ * G2P together count as g2p. */
 mpm_status mpm_profile_enable(mpm_ctx *ctx, int32_t enable);
 mpm_status mpm_profile_read(mpm_ctx *ctx, double *total_ms, int64_t *count, int32_t n_phases);
 

@@ -14,12 +14,13 @@ from typing import Optional, Sequence
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libckmpm.so")
 _lib = None
 
-MPM_OK, MPM_E_INVALID, MPM_E_OOM, MPM_E_DOMAIN, MPM_E_CAPACITY, MPM_E_NONFINITE, MPM_E_HIP, MPM_E_STALE = range(8)
+MPM_OK, MPM_E_INVALID, MPM_E_OOM, MPM_E_DOMAIN, MPM_E_CAPACITY, MPM_E_NONFINITE, MPM_E_HIP, MPM_E_STALE, MPM_E_CFL = range(9)
 MPM_FIXED_COROTATED, MPM_DRUCKER_PRAGER = 0, 1
 MPM_BC_NONE, MPM_BC_STICKY = 0, 1
 MPM_TRANSFER_MLS = 0
+MPM_FLAG_FUSED_G2P2G = 1
 MPM_STATE_PLANES = 24
-PHASES = ("sort", "p2g", "grid_update", "g2p")
+PHASES = ("sort", "p2g", "grid_update", "g2p", "g2p2g")
 
 # plane offsets inside one state buffer
 X0, V0, B0, F0 = 0, 3, 6, 15
@@ -187,7 +188,7 @@ def mpm_profile_enable(ctx, enable: bool) -> int:
     return lib().mpm_profile_enable(ctx, 1 if enable else 0)
 
 
-def mpm_profile_read(ctx, n_phases: int = 4):
+def mpm_profile_read(ctx, n_phases: int = 5):
     ms = (ctypes.c_double * n_phases)()
     cnt = (ctypes.c_int64 * n_phases)()
     s = lib().mpm_profile_read(ctx, ms, cnt, n_phases)
@@ -271,7 +272,7 @@ def check(status: int, what: str = "ckmpm") -> None:
 
 # --------------------------------------------------------- struct construction
 def make_config(n_cells, dx, origin=(0.0, 0.0, 0.0), gravity=(0.0, 0.0, 0.0), bc_band=0, max_particles=1,
-                max_blocks=1024, bc=None) -> mpm_config:
+                max_blocks=1024, bc=None, fused=False) -> mpm_config:
     c = mpm_config()
     for a in range(3):
         c.n_cells[a] = int(n_cells[a])
@@ -283,7 +284,7 @@ def make_config(n_cells, dx, origin=(0.0, 0.0, 0.0), gravity=(0.0, 0.0, 0.0), bc
     c.max_particles = int(max_particles)
     c.max_blocks = int(max_blocks)
     c.transfer = MPM_TRANSFER_MLS
-    c.flags = 0
+    c.flags = MPM_FLAG_FUSED_G2P2G if fused else 0
     return c
 
 
@@ -400,7 +401,7 @@ class Context:
             pass
 
 
-def scene_config(sc, max_particles=None, max_blocks=None) -> mpm_config:
+def scene_config(sc, max_particles=None, max_blocks=None, fused=False) -> mpm_config:
     """mpm_config for a scene from the `scenes` package."""
     n = sc.n if max_particles is None else max_particles
     if max_blocks is None:
@@ -408,7 +409,7 @@ def scene_config(sc, max_particles=None, max_blocks=None) -> mpm_config:
         for a in range(3):
             nb *= sc.n_cells[a] // 4 + 1
         max_blocks = min(nb, 2 * (n // 256) + 4096)
-    return make_config(sc.n_cells, sc.dx, sc.origin, sc.gravity, sc.bc_band, max(n, 1), max_blocks)
+    return make_config(sc.n_cells, sc.dx, sc.origin, sc.gravity, sc.bc_band, max(n, 1), max_blocks, fused=fused)
 
 
 def scene_materials(sc):
@@ -421,7 +422,7 @@ def particles_from_scene(sc, device="cuda") -> Particles:
     return p
 
 
-def job_config(sc, margin_blocks: int = 3) -> mpm_config:
+def job_config(sc, margin_blocks: int = 3, fused=False) -> mpm_config:
     """mpm_config for a served job: capacities sized to the scene's extent (blocks
     of the particles' bounding box grown by a margin on every side, twice over for
     the two grids) rather than to the whole grid."""
@@ -431,7 +432,7 @@ def job_config(sc, margin_blocks: int = 3) -> mpm_config:
     nb = 1
     for a in range(3):
         nb *= int((hi[a] - lo[a]) // 4 + 2 + 2 * margin_blocks)
-    return scene_config(sc, max_particles=sc.n, max_blocks=2 * nb + 64)
+    return scene_config(sc, max_particles=sc.n, max_blocks=2 * nb + 64, fused=fused)
 
 
 class Server:

@@ -12,7 +12,8 @@ using namespace ck;
 
 namespace {
 
-constexpr int kPhases = 4;          // sort+activate, p2g, grid update, g2p
+constexpr int kPhases = 5;          // sort+activate, p2g, grid update, g2p, fused g2p+p2g
+constexpr int kSlotEvents = 5;      // boundaries of one step: sort | p2g | update | g2p |
 constexpr int kEventRing = 512;     // steps recorded before the ring is folded into the totals
 
 }  // namespace
@@ -30,11 +31,12 @@ struct mpm_ctx {
     unsigned int *host_counters = nullptr;
     // profiling
     bool prof = false;
-    std::vector<hipEvent_t> ev;          // kEventRing x (kPhases + 1)
+    std::vector<hipEvent_t> ev;          // kEventRing x kSlotEvents
+    std::vector<char> ev_fused;          // per slot: its p2g interval is the fused kernel, no g2p
     int ev_used = 0;
     hipStream_t ev_stream = nullptr;
-    double totals[kPhases] = {0, 0, 0, 0};
-    long long counts[kPhases] = {0, 0, 0, 0};
+    double totals[kPhases] = {0, 0, 0, 0, 0};
+    long long counts[kPhases] = {0, 0, 0, 0, 0};
     std::vector<void *> allocs;
     ck::Allocator alloc;                 // where the device buffers came from
     bool host_counters_pinned = false;
@@ -76,7 +78,7 @@ mpm_status validate_config(const mpm_config *c, const mpm_material *m, int32_t n
     if (c->max_blocks < 1 || c->max_blocks >= (1ll << 26)) return MPM_E_INVALID;
     if (c->bc != MPM_BC_NONE && c->bc != MPM_BC_STICKY) return MPM_E_INVALID;
     if (c->bc_band < 0) return MPM_E_INVALID;
-    if (c->transfer != MPM_TRANSFER_MLS || c->flags != 0) return MPM_E_INVALID;
+    if (c->transfer != MPM_TRANSFER_MLS || (c->flags & ~MPM_FLAG_FUSED_G2P2G) != 0) return MPM_E_INVALID;
     for (int i = 0; i < n_mat; ++i) {
         const mpm_material &q = m[i];
         if (q.model != MPM_FIXED_COROTATED && q.model != MPM_DRUCKER_PRAGER) return MPM_E_INVALID;
@@ -184,11 +186,14 @@ void fold_events(mpm_ctx *ctx) {
     if (ctx->ev_used == 0) return;
     (void)hipStreamSynchronize(ctx->ev_stream);
     for (int s = 0; s < ctx->ev_used; ++s) {
-        for (int ph = 0; ph < kPhases; ++ph) {
+        const bool fused = ctx->ev_fused[s] != 0;
+        for (int ph = 0; ph < kSlotEvents - 1; ++ph) {
+            if (ctx->ev_fused[s] == 1 && ph == 3) continue;
+            const int to = (fused && ph == 1) ? 4 : ph;
             float ms = 0.0f;
-            if (hipEventElapsedTime(&ms, ctx->ev[s * (kPhases + 1) + ph], ctx->ev[s * (kPhases + 1) + ph + 1]) == hipSuccess) {
-                ctx->totals[ph] += ms;
-                ctx->counts[ph] += 1;
+            if (hipEventElapsedTime(&ms, ctx->ev[s * kSlotEvents + ph], ctx->ev[s * kSlotEvents + ph + 1]) == hipSuccess) {
+                ctx->totals[to] += ms;
+                ctx->counts[to] += 1;
             }
         }
     }
@@ -199,7 +204,8 @@ hipEvent_t *event_slot(mpm_ctx *ctx, hipStream_t s) {
     if (!ctx->prof) return nullptr;
     if (ctx->ev_used == kEventRing || (ctx->ev_used > 0 && s != ctx->ev_stream)) fold_events(ctx);
     ctx->ev_stream = s;
-    return &ctx->ev[ctx->ev_used * (kPhases + 1)];
+    ctx->ev_fused[ctx->ev_used] = 0;
+    return &ctx->ev[ctx->ev_used * kSlotEvents];
 }
 
 // sort + activation + P2G; ev (optional) receives phase boundaries 0, 1, 2
@@ -344,6 +350,7 @@ mpm_status status_from_bits(unsigned int bits) {
     if (bits & ST_DOMAIN) return MPM_E_DOMAIN;
     if (bits & ST_CAPACITY) return MPM_E_CAPACITY;
     if (bits & ST_STALE) return MPM_E_STALE;
+    if (bits & ST_CFL) return MPM_E_CFL;
     return MPM_OK;
 }
 
@@ -363,6 +370,7 @@ const char *mpm_status_string(mpm_status s) {
         case MPM_E_NONFINITE: return "non-finite particle state";
         case MPM_E_HIP: return "HIP runtime error";
         case MPM_E_STALE: return "particle positions changed after their cell keys were computed";
+        case MPM_E_CFL: return "a particle moved more than three cells in one fused step";
     }
     return "unknown status";
 }
@@ -410,21 +418,86 @@ mpm_status mpm_step(mpm_ctx *ctx, mpm_particles *p, double dt, int32_t nsteps, v
     if (v != MPM_OK) return v;
     if (!std::isfinite(dt) || dt < 0 || nsteps < 0) return MPM_E_INVALID;
     if (!p->state[p->current ^ 1]) return MPM_E_INVALID;
+    if ((p->id[0] == nullptr) != (p->id[1] == nullptr)) return MPM_E_INVALID;
+    if ((p->mat[0] == nullptr) != (p->mat[1] == nullptr)) return MPM_E_INVALID;
     DeviceGuard g(ctx->device);
     hipStream_t s = (hipStream_t)stream;
-    for (int k = 0; k < nsteps; ++k) {
-        hipEvent_t *ev = event_slot(ctx, s);
-        mpm_status st = enqueue_p2g(ctx, p, dt, s, ev, true);
-        if (st == MPM_OK) st = enqueue_update(ctx, dt, s);
-        if (st == MPM_OK && ev) (void)hipEventRecord(ev[3], s);
-        if (st == MPM_OK) st = enqueue_g2p(ctx, p, dt, s);
-        if (st == MPM_OK && ev) {
-            (void)hipEventRecord(ev[4], s);
-            ctx->ev_used += 1;
+    if (nsteps == 0) return MPM_OK;
+    if (!(ctx->cfg.flags & MPM_FLAG_FUSED_G2P2G)) {
+        for (int k = 0; k < nsteps; ++k) {
+            hipEvent_t *ev = event_slot(ctx, s);
+            mpm_status st = enqueue_p2g(ctx, p, dt, s, ev, true);
+            if (st == MPM_OK) st = enqueue_update(ctx, dt, s);
+            if (st == MPM_OK && ev) (void)hipEventRecord(ev[3], s);
+            if (st == MPM_OK) st = enqueue_g2p(ctx, p, dt, s);
+            if (st == MPM_OK && ev) {
+                (void)hipEventRecord(ev[4], s);
+                ctx->ev_used += 1;
+            }
+            if (st != MPM_OK) return st;
         }
-        if (st != MPM_OK) return st;
+        return MPM_OK;
     }
-    return MPM_OK;
+    // first step: sort, P2G, grid update
+    hipEvent_t *ev = event_slot(ctx, s);
+    mpm_status st = enqueue_p2g(ctx, p, dt, s, ev, true);
+    if (st == MPM_OK) st = enqueue_update(ctx, dt, s);
+    if (st != MPM_OK) return st;
+    if (ev) (void)hipEventRecord(ev[3], s);
+    // steps 1 .. nsteps-1: G2P of the previous step fused with this step's P2G
+    for (int k = 1; k < nsteps; ++k) {
+        if (ev) {
+            (void)hipEventRecord(ev[4], s);   // previous step: no separate G2P
+            ctx->ev_used += 1;
+            ev = event_slot(ctx, s);
+            if (ev) {
+                (void)hipEventRecord(ev[0], s);
+                ctx->ev_fused[ctx->ev_used] = 1;
+            }
+        }
+        const int gin = ctx->grid_pool, tin = ctx->grid_table;
+        const int gout = gin ^ 1;
+        int tout;
+        if (k == 1) {
+            // the first sort's block set (neighbourhood of the particle blocks) serves
+            // the second grid as well
+            tout = tin;
+            launch_zero_pool(ctx->d, gout, tout, s);
+        } else {
+            tout = ctx->next_table;
+            const PartArgs pa = part_args(p, false);
+            launch_compact(ctx->d, tout, s);
+            launch_bucket(ctx->d, pa.n, gout, tout, s);
+            ctx->next_table = tout ^ 1;
+        }
+        if (ev) (void)hipEventRecord(ev[1], s);
+        const PartArgs pa = part_args(p, true);
+        launch_g2p2g(ctx->d, pa, (float)dt, gin, tin, gout, tout, s);
+        p->current ^= 1;
+        ctx->grid_pool = gout;
+        ctx->grid_table = tout;
+        if (ev) (void)hipEventRecord(ev[2], s);
+        st = enqueue_update(ctx, dt, s);
+        if (st != MPM_OK) return st;
+        if (ev) (void)hipEventRecord(ev[3], s);
+    }
+    if (nsteps > 1) {
+        // the last step's G2P needs the blocks of the state the fused kernel wrote
+        const PartArgs pa = part_args(p, false);
+        const int t = ctx->next_table;
+        launch_compact(ctx->d, t, s);
+        launch_bucket(ctx->d, pa.n, ctx->grid_pool ^ 1, t, s);
+        ctx->next_table = t ^ 1;
+        launch_block_order(ctx->d, s);
+        ctx->p2g_done = pa.in;
+    }
+    st = enqueue_g2p(ctx, p, dt, s);
+    if (st == MPM_OK && ev) {
+        (void)hipEventRecord(ev[4], s);
+        if (ctx->ev_fused[ctx->ev_used]) ctx->ev_fused[ctx->ev_used] = 2;   // keeps its g2p interval
+        ctx->ev_used += 1;
+    }
+    return st;
 }
 
 mpm_status mpm_sync(mpm_ctx *ctx, void *stream) {
@@ -484,7 +557,8 @@ mpm_status mpm_profile_enable(mpm_ctx *ctx, int32_t enable) {
     if (!ctx) return MPM_E_INVALID;
     DeviceGuard g(ctx->device);
     if (enable && ctx->ev.empty()) {
-        ctx->ev.resize((size_t)kEventRing * (kPhases + 1));
+        ctx->ev.resize((size_t)kEventRing * kSlotEvents);
+        ctx->ev_fused.assign(kEventRing, 0);
         for (auto &e : ctx->ev)
             if (hipEventCreate(&e) != hipSuccess) return MPM_E_HIP;
     }

@@ -24,6 +24,7 @@ enum StatusBits : uint32_t {
     ST_CAPACITY = 2u,
     ST_NONFINITE = 4u,
     ST_STALE = 8u,
+    ST_CFL = 16u,
 };
 
 enum Counter : int {
@@ -665,6 +666,10 @@ void launch_p2g(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, h
 void launch_grid_update(const DevCtx &d, float dt, const float gravity[3], int gp, int gt, hipStream_t s);
 void launch_g2p(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, hipStream_t s);
 void launch_grid_export(const DevCtx &d, float *m, float *vec, int gp, int gt, hipStream_t s);
+void launch_block_order(const DevCtx &d, hipStream_t s);
+void launch_g2p2g(const DevCtx &d, const PartArgs &pa, float dt, int gp_in, int gt_in, int gp_out, int gt_out,
+                  hipStream_t s);
+void launch_zero_pool(const DevCtx &d, int gp, int gt, hipStream_t s);
 void launch_copy_keys(const DevCtx &d, uint32_t *keys, uint32_t *perm, int n, hipStream_t s);
 
 }  // namespace ck

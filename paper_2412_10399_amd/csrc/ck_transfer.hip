@@ -23,8 +23,10 @@ __device__ __forceinline__ void block_coords(const Geometry &g, int vb, int &bx,
 
 // Physical pool block of the 27 neighbours of block (bx,by,bz) in page table
 // `table`, -1 when inactive.
-__device__ __forceinline__ void load_neighbours(const DevCtx &d, int table, int bx, int by, int bz, int *nbr) {
-    const int t = threadIdx.x;
+__device__ __forceinline__ void load_neighbours(const DevCtx &d, int table, int bx, int by, int bz, int *nbr,
+                                                int first_thread = 0) {
+    const int t = (int)threadIdx.x - first_thread;
+    if (t < 0) return;
     if (t < 27) {
         const int x = bx + t % 3 - 1, y = by + (t / 3) % 3 - 1, z = bz + t / 9 - 1;
         int ph = -1;
@@ -245,39 +247,20 @@ __device__ __forceinline__ unsigned long long to_fixed(float v, double S) {
 
 struct Staged {
     float xm[3], sp[3], mass, base[3], Q[9];
-    int cell;       // G- cell in the block, -1 when the particle does not take part
+    int c[3];       // G- cell
     int oct;        // half-cell octant
+    bool on;        // takes part in the scatter
 };
 
-__device__ __forceinline__ void stage_particle(const DevCtx &d, const PartArgs &pa, int p, int bx, int by, int bz,
-                                               float dt, Staged &r) {
-    r.cell = -1;
-    r.oct = 0;
-    const long long S = pa.stride;
-    const uint32_t up = (uint32_t)p;
-    float x[3], v[3], B[9], tau[6];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) x[a] = ld_at(pa.in + a * S, up);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) v[a] = ld_at(pa.in + (3 + a) * S, up);
-#pragma unroll
-    for (int a = 0; a < 9; ++a) B[a] = ld_at(pa.in + (6 + a) * S, up);
-#pragma unroll
-    for (int i = 0; i < 6; ++i) tau[i] = ld_at(d.tau + i * d.tau_stride, up);
-    const int mi = pa.mat_in ? (int)ld_at(pa.mat_in, up) : 0;
-    const DevMaterial M = d.mats[mi < d.n_mat ? mi : 0];
-    CellCoord cc;
-    if (!cell_coord(d.geo, x, cc)) {
-        set_status(d.counters, ST_DOMAIN);
-        return;
-    }
-    if ((cc.c[0] >> 2) != bx || (cc.c[1] >> 2) != by || (cc.c[2] >> 2) != bz) {
-        set_status(d.counters, ST_STALE);
-        return;
-    }
+// P2G record of a particle at cell coordinates cc with velocity v, affine matrix B
+// and Kirchhoff stress tau (6 values).
+__device__ __forceinline__ void stage_compute(const DevCtx &d, const DevMaterial &M, const CellCoord &cc,
+                                              const float (&v)[3], const float (&B)[9], const float (&tau)[6], float dt,
+                                              Staged &r) {
     const uint32_t code = sub_code(cc);
-    r.cell = (int)(code >> 3);
     r.oct = (int)(code & 7u);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) r.c[a] = cc.c[a];
     Weights w;
     axis_weights(cc, w);
     float Di[9];
@@ -300,12 +283,41 @@ __device__ __forceinline__ void stage_particle(const DevCtx &d, const PartArgs &
         r.base[a] = M.mass * v[a] - (r.Q[3 * a] * cc.xm[0] + r.Q[3 * a + 1] * cc.xm[1] + r.Q[3 * a + 2] * cc.xm[2]);
     }
     r.mass = M.mass;
+    r.on = true;
+}
+
+__device__ __forceinline__ void stage_particle(const DevCtx &d, const PartArgs &pa, int p, int bx, int by, int bz,
+                                               float dt, Staged &r) {
+    r.on = false;
+    const long long S = pa.stride;
+    const uint32_t up = (uint32_t)p;
+    float x[3], v[3], B[9], tau[6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) x[a] = ld_at(pa.in + a * S, up);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v[a] = ld_at(pa.in + (3 + a) * S, up);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) B[a] = ld_at(pa.in + (6 + a) * S, up);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) tau[i] = ld_at(d.tau + i * d.tau_stride, up);
+    const int mi = pa.mat_in ? (int)ld_at(pa.mat_in, up) : 0;
+    const DevMaterial M = d.mats[mi < d.n_mat ? mi : 0];
+    CellCoord cc;
+    if (!cell_coord(d.geo, x, cc)) {
+        set_status(d.counters, ST_DOMAIN);
+        return;
+    }
+    if ((cc.c[0] >> 2) != bx || (cc.c[1] >> 2) != by || (cc.c[2] >> 2) != bz) {
+        set_status(d.counters, ST_STALE);
+        return;
+    }
+    stage_compute(d, M, cc, v, B, tau, dt, r);
 }
 
 // Upper bound of |w m| and |w (base + Q t)| over the particle's 16 nodes (w <= 1,
 // every component of t in [-1/2, 3/2]).
 __device__ __forceinline__ float contribution_bound(const Staged &r) {
-    if (r.cell < 0) return 0.0f;
+    if (!r.on) return 0.0f;
     float b = r.mass;
 #pragma unroll
     for (int a = 0; a < 3; ++a)
@@ -346,28 +358,165 @@ __device__ __forceinline__ void scatter_grid(unsigned long long *tile, int ntile
         }
 }
 
-__device__ __forceinline__ void scatter_particle(const Staged &r, unsigned long long *tile_m, unsigned long long *tile_p,
-                                                 double S) {
-    const int cx = r.cell & 3, cy = (r.cell >> 2) & 3, cz = r.cell >> 4;
-    float wm[3][2], wp[3][2], mp[3];
-    int up[3];
+// Per-axis weights of a staged particle on both grids, the G+ base offset up (the
+// G+ base node is c + up - 1) and the G+ momentum at that base node.
+__device__ __forceinline__ void staged_weights(const Staged &r, float (&wm)[3][2], float (&wp)[3][2], int (&up)[3],
+                                               float (&mp)[3]) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        up[a] = (r.oct >> a) & 1;                               // G+ base node is c (else c - 1)
+        up[a] = (r.oct >> a) & 1;
         wm[a][0] = 1.0f - r.xm[a] - r.sp[a];
         wm[a][1] = r.xm[a] + r.sp[a];
         const float xp = up[a] ? r.xm[a] - 0.5f : r.xm[a] + 0.5f;
         wp[a][0] = 1.0f - xp + r.sp[a];
         wp[a][1] = xp - r.sp[a];
     }
-    scatter_grid(tile_m, kTileMStride, cz * kTZ + cy * kTY + cx, kTY, kTZ, wm, r.mass, r.base, r.Q, S);
-    // G+ momentum at the base node bp = c + up - 1: base + Q (up - 1/2)
+    // base + Q (up - 1/2)
 #pragma unroll
     for (int a = 0; a < 3; ++a)
         mp[a] = r.base[a] + ((float)up[0] - 0.5f) * r.Q[3 * a] + ((float)up[1] - 0.5f) * r.Q[3 * a + 1] +
                 ((float)up[2] - 0.5f) * r.Q[3 * a + 2];
-    const int t0 = (cz + up[2]) * kTZ + (cy + up[1]) * kTY + (cx + up[0]);
-    scatter_grid(tile_p, kTilePStride, t0, kTY, kTZ, wp, r.mass, mp, r.Q, S);
+}
+
+// Scatter into a fixed-point tile whose G- nodes start one node below the G+ origin
+// offset: G- cell c at tile coordinates l, G+ base node at l + up.
+template <int TY, int TZ, int SM, int SP>
+__device__ __forceinline__ void scatter_particle(const Staged &r, int lx, int ly, int lz, unsigned long long *tile_m,
+                                                 unsigned long long *tile_p, double S) {
+    float wm[3][2], wp[3][2], mp[3];
+    int up[3];
+    staged_weights(r, wm, wp, up, mp);
+    scatter_grid(tile_m, SM, lz * TZ + ly * TY + lx, TY, TZ, wm, r.mass, r.base, r.Q, S);
+    scatter_grid(tile_p, SP, (lz + up[2]) * TZ + (ly + up[1]) * TY + (lx + up[0]), TY, TZ, wp, r.mass, mp, r.Q, S);
+}
+
+// Direct float atomics into the pool for a particle outside the workgroup's tile
+// (moved more than one cell in a fused step); nbr holds the pool blocks around
+// block (bx,by,bz).
+__device__ __forceinline__ void scatter_pool(const DevCtx &d, float *pool, const int *nbr, int bx, int by, int bz,
+                                             const Staged &r) {
+    float wm[3][2], wp[3][2], mp[3];
+    int up[3];
+    staged_weights(r, wm, wp, up, mp);
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+        const float(*w)[2] = g == 0 ? wm : wp;
+        const float *m0 = g == 0 ? r.base : mp;
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+            const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
+            const int ix = r.c[0] + (g ? up[0] - 1 : 0) + ox, iy = r.c[1] + (g ? up[1] - 1 : 0) + oy,
+                      iz = r.c[2] + (g ? up[2] - 1 : 0) + oz;
+            // nbr covers blocks bx-1 .. bx+1: a node outside them is out of reach
+            const bool near = (unsigned)((ix >> 2) - bx + 1) <= 2u && (unsigned)((iy >> 2) - by + 1) <= 2u &&
+                              (unsigned)((iz >> 2) - bz + 1) <= 2u;
+            const long long a = near ? pool_index(d, nbr, bx, by, bz, g, ix, iy, iz, 0) : -1;
+            if (a < 0) {
+                set_status(d.counters, ST_CFL);
+                continue;
+            }
+            const float wt = w[0][ox] * w[1][oy] * w[2][oz];
+            atomicAdd(&pool[a], wt * r.mass);
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                atomicAdd(&pool[a + (1 + c) * 64], wt * (m0[c] + ox * r.Q[3 * c] + oy * r.Q[3 * c + 1] + oz * r.Q[3 * c + 2]));
+        }
+    }
+}
+
+// Orders the particles of block r (count cnt, first sorted position s) by (half-cell
+// octant, cell, index): ord[j] = particle index at position j of the block, also
+// written to the global permutation.  Uses bcnt, bstart, wsum and lbuf (LDS).
+__device__ __forceinline__ void order_block(const DevCtx &d, int r, int s, int cnt, int *bcnt, int *bstart, int *wsum,
+                                            uint32_t *lbuf, uint32_t *ord) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
+    const uint32_t *bkt = d.bucket + (size_t)r * kMaxBlockParticles;
+    const uint16_t *bsb = d.bsub + (size_t)r * kMaxBlockParticles;
+    for (int b = tid; b < kBins; b += kP2GThreads) bcnt[b] = 0;
+    lds_barrier();
+    uint32_t hidx[kHold];
+    int hbin[kHold];
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+        const int j = tid + k * kP2GThreads;
+        if (j >= cnt) break;
+        const uint32_t idx = bkt[j];
+        const int bin = bin_of(bsb[j]);
+        if (k < kHold) {
+            hidx[k] = idx;
+            hbin[k] = bin;
+        }
+        atomicAdd(&bcnt[bin], 1);
+    }
+    lds_barrier();
+    {
+        // exclusive scan of the 512 bins, two per thread
+        const int c0 = bcnt[2 * tid], c1 = bcnt[2 * tid + 1];
+        int v = c0 + c1;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int t = __shfl_up(v, off);
+            if (lane >= off) v += t;
+        }
+        if (lane == 63) wsum[w] = v;
+        lds_barrier();
+        int pre = 0;
+        for (int k = 0; k < w; ++k) pre += wsum[k];
+        const int ex = pre + v - c0 - c1;
+        bstart[2 * tid] = ex;
+        bstart[2 * tid + 1] = ex + c0;
+        bcnt[2 * tid] = ex;
+        bcnt[2 * tid + 1] = ex + c0;
+        if (tid == kP2GThreads - 1) bstart[kBins] = ex + c0 + c1;
+    }
+    lds_barrier();
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+        const int j = tid + k * kP2GThreads;
+        if (j >= cnt) break;
+        uint32_t idx;
+        int bin;
+        if (k < kHold) {
+            idx = hidx[k];
+            bin = hbin[k];
+        } else {
+            idx = bkt[j];
+            bin = bin_of(bsb[j]);
+        }
+        lbuf[atomicAdd(&bcnt[bin], 1)] = idx;
+    }
+    lds_barrier();
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+        const int j = tid + k * kP2GThreads;
+        if (j >= cnt) break;
+        uint32_t idx;
+        int bin;
+        if (k < kHold) {
+            idx = hidx[k];
+            bin = hbin[k];
+        } else {
+            idx = bkt[j];
+            bin = bin_of(bsb[j]);
+        }
+        const int lo = bstart[bin], hi = bstart[bin + 1];
+        int rank = lo;
+        for (int q = lo; q < hi; ++q) rank += (lbuf[q] < idx) ? 1 : 0;
+        ord[rank] = idx;
+        st_at(d.perm, (uint32_t)(s + rank), idx);
+    }
+}
+
+// Reduces a per-thread contribution bound over the workgroup (bmax in LDS, reset by
+// the caller before the preceding barrier) and returns the fixed-point scale.
+__device__ __forceinline__ double block_scale(float bnd, unsigned int *bmax) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) bnd = fmaxf(bnd, __shfl_xor(bnd, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(bmax, __float_as_uint(bnd));
+    lds_barrier();
+    const float m = __uint_as_float(*bmax);
+    return m > 0.0f ? ldexp(1.0, 39 - ilogbf(m)) : 1.0;
 }
 
 __global__ void __launch_bounds__(kP2GThreads) k_p2g(DevCtx d, PartArgs pa, float dt, int gp, int gt) {
@@ -386,7 +535,6 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g(DevCtx d, PartArgs pa, floa
     unsigned long long *tile_p = area + 4 * kTileMStride;
     const int np = (int)d.counters[C_NPB];
     const int tid = threadIdx.x;
-    const int lane = tid & 63, w = tid >> 6;
     for (int base = 0; base < np; base += gridDim.x) {
         const int r = round_block(base, np);
         if (r < 0) continue;
@@ -396,83 +544,7 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g(DevCtx d, PartArgs pa, floa
         const int s = d.pstart[r];
         const int cnt = d.pstart[r + 1] - s;
         if (cnt > kMaxBlockParticles) continue;   // reported by the bucket scan
-        const uint32_t *bkt = d.bucket + (size_t)r * kMaxBlockParticles;
-        const uint16_t *bsb = d.bsub + (size_t)r * kMaxBlockParticles;
-
-        // ---- order the block's particles by (octant, cell, index)
-        for (int b = tid; b < kBins; b += kP2GThreads) bcnt[b] = 0;
-        lds_barrier();
-        uint32_t hidx[kHold];
-        int hbin[kHold];
-#pragma unroll
-        for (int k = 0; k < kPerThread; ++k) {
-            const int j = tid + k * kP2GThreads;
-            if (j >= cnt) break;
-            const uint32_t idx = bkt[j];
-            const int bin = bin_of(bsb[j]);
-            if (k < kHold) {
-                hidx[k] = idx;
-                hbin[k] = bin;
-            }
-            atomicAdd(&bcnt[bin], 1);
-        }
-        lds_barrier();
-        {
-            // exclusive scan of the 512 bins, two per thread
-            const int c0 = bcnt[2 * tid], c1 = bcnt[2 * tid + 1];
-            int v = c0 + c1;
-#pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const int t = __shfl_up(v, off);
-                if (lane >= off) v += t;
-            }
-            if (lane == 63) wsum[w] = v;
-            lds_barrier();
-            int pre = 0;
-            for (int k = 0; k < w; ++k) pre += wsum[k];
-            const int ex = pre + v - c0 - c1;
-            bstart[2 * tid] = ex;
-            bstart[2 * tid + 1] = ex + c0;
-            bcnt[2 * tid] = ex;
-            bcnt[2 * tid + 1] = ex + c0;
-            if (tid == kP2GThreads - 1) bstart[kBins] = ex + c0 + c1;
-        }
-        lds_barrier();
-#pragma unroll
-        for (int k = 0; k < kPerThread; ++k) {
-            const int j = tid + k * kP2GThreads;
-            if (j >= cnt) break;
-            uint32_t idx;
-            int bin;
-            if (k < kHold) {
-                idx = hidx[k];
-                bin = hbin[k];
-            } else {
-                idx = bkt[j];
-                bin = bin_of(bsb[j]);
-            }
-            lbuf[atomicAdd(&bcnt[bin], 1)] = idx;
-        }
-        lds_barrier();
-#pragma unroll
-        for (int k = 0; k < kPerThread; ++k) {
-            const int j = tid + k * kP2GThreads;
-            if (j >= cnt) break;
-            uint32_t idx;
-            int bin;
-            if (k < kHold) {
-                idx = hidx[k];
-                bin = hbin[k];
-            } else {
-                idx = bkt[j];
-                bin = bin_of(bsb[j]);
-            }
-            const int lo = bstart[bin], hi = bstart[bin + 1];
-            int rank = lo;
-            for (int q = lo; q < hi; ++q) rank += (lbuf[q] < idx) ? 1 : 0;
-            ord[rank] = idx;
-            st_at(d.perm, (uint32_t)(s + rank), idx);
-        }
+        order_block(d, r, s, cnt, bcnt, bstart, wsum, lbuf, ord);
         load_neighbours(d, gt, bx, by, bz, nbr);
         lds_barrier();
 
@@ -484,21 +556,18 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g(DevCtx d, PartArgs pa, floa
             float bnd = 0.0f;
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
-                st[k].cell = -1;
+                st[k].on = false;
                 const int j = c0 + tid + k * kP2GThreads;
                 if (j < cnt) stage_particle(d, pa, (int)ord[j], bx, by, bz, dt, st[k]);
                 bnd = fmaxf(bnd, contribution_bound(st[k]));
             }
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) bnd = fmaxf(bnd, __shfl_xor(bnd, off));
             lds_barrier();   // tile cleared, bmax reset
-            if (lane == 0) atomicMax(&bmax, __float_as_uint(bnd));
-            lds_barrier();
-            const float m = __uint_as_float(bmax);
-            const double S = m > 0.0f ? ldexp(1.0, 39 - ilogbf(m)) : 1.0;
+            const double S = block_scale(bnd, &bmax);
 #pragma unroll
             for (int k = 0; k < 2; ++k)
-                if (st[k].cell >= 0) scatter_particle(st[k], tile_m, tile_p, S);
+                if (st[k].on)
+                    scatter_particle<kTY, kTZ, kTileMStride, kTilePStride>(st[k], st[k].c[0] - 4 * bx, st[k].c[1] - 4 * by,
+                                                                           st[k].c[2] - 4 * bz, tile_m, tile_p, S);
             lds_barrier();
             // ---- flush every nonzero tile node to the pool
             const double inv = 1.0 / S;
@@ -568,8 +637,7 @@ struct G2PIn {
     uint32_t id;
 };
 
-__device__ __forceinline__ void g2p_load(const DevCtx &d, const PartArgs &pa, uint32_t pos, G2PIn &q) {
-    const uint32_t p = ld_at(d.perm, pos);
+__device__ __forceinline__ void g2p_load_index(const PartArgs &pa, uint32_t p, G2PIn &q) {
     q.p = p;
     const long long S = pa.stride;
 #pragma unroll
@@ -580,13 +648,169 @@ __device__ __forceinline__ void g2p_load(const DevCtx &d, const PartArgs &pa, ui
     q.id = pa.id_in ? ld_at(pa.id_in, p) : 0u;
 }
 
+__device__ __forceinline__ void g2p_load(const DevCtx &d, const PartArgs &pa, uint32_t pos, G2PIn &q) {
+    g2p_load_index(pa, ld_at(d.perm, pos), q);
+}
+
+// G2P of one particle (section 4.3 gather, section 4.5 affine matrix, F update,
+// return mapping, advection) on the velocity tile vt of block (bx,by,bz): writes the
+// new state at position `out` of the output buffer (and its stress when write_tau),
+// the particle's next cell key and sub code, and returns its new block for the
+// activation stamps (-1 when it is not placed).  On return `placed` tells whether
+// the new state is finite and inside the domain; then ns and cn hold it.
+struct NewState {
+    float x[3], v[3], B[9], tau[6];
+};
+
+__device__ __forceinline__ int g2p_particle(const DevCtx &d, const PartArgs &pa, float dt, const G2PIn &q,
+                                            const CellCoord &cc, int bx, int by, int bz, const float *vt, uint32_t out,
+                                            bool write_tau, NewState &ns, CellCoord &cn, bool &placed) {
+    const long long S = pa.stride;
+    int sig = -1;
+    placed = false;
+    const DevMaterial M = d.mats[q.mat < d.n_mat ? q.mat : 0];
+    Weights w;
+    axis_weights(cc, w);
+    float Di[9];
+    moment_inverse(cc, w, Di);
+    // Gather.  The affine matrix sums w v~ (x_i - x_p)^T, whose weights have a
+    // zero dual-grid first moment; subtracting one stencil node's velocity c
+    // first keeps the FP32 sums at the size of the velocity differences, and c
+    // drops out:
+    //   1/2 sum w (v~ - c)(x_i - x_p)^T = 1/2 sum w v~ (x_i - x_p)^T,
+    //   v_p = c + 1/2 sum w (v~ - c)   (the weights of each grid sum to one).
+    const int tm0 = ((cc.c[2] - 4 * bz) * 5 + (cc.c[1] - 4 * by)) * 5 + (cc.c[0] - 4 * bx);
+    const int tp0 = kTileMinus + ((cc.bp[2] - 4 * bz + 1) * 6 + (cc.bp[1] - 4 * by + 1)) * 6 +
+                    (cc.bp[0] - 4 * bx + 1);
+    const float cref[3] = {vt[tm0], vt[kTileNodes + tm0], vt[2 * kTileNodes + tm0]};
+    float vs[3] = {0.0f, 0.0f, 0.0f};
+    float Bh[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Bh[i] = 0.0f;
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+        const float *xi = g == 0 ? cc.xm : cc.xp;
+        const int t0 = g == 0 ? tm0 : tp0;
+        const int sy = g == 0 ? 5 : 6, sz = g == 0 ? 25 : 36;
+        const float(*wa)[2] = g == 0 ? w.wm : w.wp;
+        // separable sums over the 2x2x2 nodes: S = sum w v, M_b = sum w v o_b
+        float S3[3], Mx[3], My[3], Mz[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            float A[2][2], X[2][2];   // [oz][oy]: x-reduced sum and x-moment
+#pragma unroll
+            for (int oz = 0; oz < 2; ++oz)
+#pragma unroll
+                for (int oy = 0; oy < 2; ++oy) {
+                    const int t = a * kTileNodes + t0 + oy * sy + oz * sz;
+                    const float v0 = vt[t] - cref[a], v1 = vt[t + 1] - cref[a];
+                    X[oz][oy] = wa[0][1] * v1;
+                    A[oz][oy] = wa[0][0] * v0 + X[oz][oy];
+                }
+            float Bz[2], BXz[2], BYz[2];
+#pragma unroll
+            for (int oz = 0; oz < 2; ++oz) {
+                BYz[oz] = wa[1][1] * A[oz][1];
+                Bz[oz] = wa[1][0] * A[oz][0] + BYz[oz];
+                BXz[oz] = wa[1][0] * X[oz][0] + wa[1][1] * X[oz][1];
+            }
+            Mz[a] = wa[2][1] * Bz[1];
+            S3[a] = wa[2][0] * Bz[0] + Mz[a];
+            Mx[a] = wa[2][0] * BXz[0] + wa[2][1] * BXz[1];
+            My[a] = wa[2][0] * BYz[0] + wa[2][1] * BYz[1];
+        }
+        // sum_o w v (o - xi)^T = M - S xi^T
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            vs[a] += S3[a];
+            Bh[3 * a] += Mx[a] - S3[a] * xi[0];
+            Bh[3 * a + 1] += My[a] - S3[a] * xi[1];
+            Bh[3 * a + 2] += Mz[a] - S3[a] * xi[2];
+        }
+    }
+    float vn[3], Bn[9], C[9];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) vn[a] = cref[a] + 0.5f * vs[a];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        Bh[i] *= 0.5f;
+        Bn[i] = Bh[i] * d.geo.dx;
+    }
+    // C = B D^-1 = (dx Bh)(dx^2 Dhat)^-1 = Bh Dhat^-1 / dx
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j2 = 0; j2 < 3; ++j2)
+            C[3 * i + j2] = d.geo.inv_dx_f *
+                            (Bh[3 * i] * Di[j2] + Bh[3 * i + 1] * Di[3 + j2] + Bh[3 * i + 2] * Di[6 + j2]);
+    // F' = (I + dt C) F  ->  H' = H + dt (C + C H)
+    float Fn[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j2 = 0; j2 < 3; ++j2)
+            Fn[3 * i + j2] = q.H[3 * i + j2] + dt * (C[3 * i + j2] + C[3 * i] * q.H[j2] +
+                                                     C[3 * i + 1] * q.H[3 + j2] + C[3 * i + 2] * q.H[6 + j2]);
+    // stress of the new state for the next step's P2G
+    float tau[6];
+    if (M.model == 1) dp_return_map(M, Fn, tau);
+    else kirchhoff(M, Fn, tau);
+    float xn[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) xn[a] = q.x[a] + dt * vn[a];
+    // x * 0 is NaN exactly when x is infinite or NaN
+    float probe = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) probe += vn[a] * 0.0f + xn[a] * 0.0f;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) probe += Fn[i] * 0.0f + Bn[i] * 0.0f;
+    const bool finite = probe == 0.0f;
+    if (!finite) set_status(d.counters, ST_NONFINITE);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        st_at(pa.out + a * S, out, xn[a]);
+        st_at(pa.out + (3 + a) * S, out, vn[a]);
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        st_at(pa.out + (6 + i) * S, out, Bn[i]);
+        st_at(pa.out + (15 + i) * S, out, Fn[i]);
+    }
+    if (write_tau) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) st_at(d.tau + i * d.tau_stride, out, tau[i]);
+    }
+    if (pa.id_out) st_at(pa.id_out, out, q.id);
+    if (pa.mat_out) st_at(pa.mat_out, out, (uint8_t)q.mat);
+    // next cell key for the following step
+    if (finite && cell_coord(d.geo, xn, cn)) {
+        const uint32_t key = cell_key(d.geo, cn);
+        st_at(d.key, out, key);
+        st_at(d.sub, out, (uint16_t)sub_code(cn));
+        sig = (int)(key >> 6);
+        placed = true;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            ns.x[a] = xn[a];
+            ns.v[a] = vn[a];
+        }
+#pragma unroll
+        for (int i = 0; i < 9; ++i) ns.B[i] = Bn[i];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) ns.tau[i] = tau[i];
+    } else {
+        st_at(d.key, out, 0xffffffffu);
+        set_status(d.counters, ST_DOMAIN);
+    }
+    return sig;
+}
+
 __global__ void __launch_bounds__(kThreads) k_g2p(DevCtx d, PartArgs pa, float dt, int gp, int gt) {
     __shared__ float vt[3 * kTileNodes];
     __shared__ int nbr[27];
     const int np = (int)d.counters[C_NPB];
     const int E = (int)d.counters[C_EPOCH];
     const int tid = threadIdx.x;
-    const long long S = pa.stride;
     for (int base = 0; base < np; base += gridDim.x) {
         const int r = round_block(base, np);
         if (r < 0) continue;
@@ -618,136 +842,16 @@ __global__ void __launch_bounds__(kThreads) k_g2p(DevCtx d, PartArgs pa, float d
             CellCoord cc;
             bool ok = act && cell_coord(d.geo, q.x, cc);
             ok = ok && (cc.c[0] >> 2) == bx && (cc.c[1] >> 2) == by && (cc.c[2] >> 2) == bz;
-            // activation stamps of the next step, deduplicated between neighbouring lanes
-            // (sorted particles mostly share their blocks): -1 = none, else the block
+            // activation stamps of the next step (-1: none), deduplicated across the wave
             int sig = -1;
-            CellCoord cn;
             if (act && !ok) {
                 set_status(d.counters, ST_STALE);
                 st_at(d.key, out, 0xffffffffu);
             } else if (ok) {
-                const DevMaterial M = d.mats[q.mat < d.n_mat ? q.mat : 0];
-                Weights w;
-                axis_weights(cc, w);
-                float Di[9];
-                moment_inverse(cc, w, Di);
-                // Gather.  The affine matrix sums w v~ (x_i - x_p)^T, whose weights have a
-                // zero dual-grid first moment; subtracting one stencil node's velocity c
-                // first keeps the FP32 sums at the size of the velocity differences, and c
-                // drops out:
-                //   1/2 sum w (v~ - c)(x_i - x_p)^T = 1/2 sum w v~ (x_i - x_p)^T,
-                //   v_p = c + 1/2 sum w (v~ - c)   (the weights of each grid sum to one).
-                const int tm0 = ((cc.c[2] - 4 * bz) * 5 + (cc.c[1] - 4 * by)) * 5 + (cc.c[0] - 4 * bx);
-                const int tp0 = kTileMinus + ((cc.bp[2] - 4 * bz + 1) * 6 + (cc.bp[1] - 4 * by + 1)) * 6 +
-                                (cc.bp[0] - 4 * bx + 1);
-                const float cref[3] = {vt[tm0], vt[kTileNodes + tm0], vt[2 * kTileNodes + tm0]};
-                float vs[3] = {0.0f, 0.0f, 0.0f};
-                float Bh[9];
-#pragma unroll
-                for (int i = 0; i < 9; ++i) Bh[i] = 0.0f;
-#pragma unroll
-                for (int g = 0; g < 2; ++g) {
-                    const float *xi = g == 0 ? cc.xm : cc.xp;
-                    const int t0 = g == 0 ? tm0 : tp0;
-                    const int sy = g == 0 ? 5 : 6, sz = g == 0 ? 25 : 36;
-                    const float(*wa)[2] = g == 0 ? w.wm : w.wp;
-                    // separable sums over the 2x2x2 nodes: S = sum w v, M_b = sum w v o_b
-                    float S3[3], Mx[3], My[3], Mz[3];
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        float A[2][2], X[2][2];   // [oz][oy]: x-reduced sum and x-moment
-#pragma unroll
-                        for (int oz = 0; oz < 2; ++oz)
-#pragma unroll
-                            for (int oy = 0; oy < 2; ++oy) {
-                                const int t = a * kTileNodes + t0 + oy * sy + oz * sz;
-                                const float v0 = vt[t] - cref[a], v1 = vt[t + 1] - cref[a];
-                                X[oz][oy] = wa[0][1] * v1;
-                                A[oz][oy] = wa[0][0] * v0 + X[oz][oy];
-                            }
-                        float Bz[2], BXz[2], BYz[2];
-#pragma unroll
-                        for (int oz = 0; oz < 2; ++oz) {
-                            BYz[oz] = wa[1][1] * A[oz][1];
-                            Bz[oz] = wa[1][0] * A[oz][0] + BYz[oz];
-                            BXz[oz] = wa[1][0] * X[oz][0] + wa[1][1] * X[oz][1];
-                        }
-                        Mz[a] = wa[2][1] * Bz[1];
-                        S3[a] = wa[2][0] * Bz[0] + Mz[a];
-                        Mx[a] = wa[2][0] * BXz[0] + wa[2][1] * BXz[1];
-                        My[a] = wa[2][0] * BYz[0] + wa[2][1] * BYz[1];
-                    }
-                    // sum_o w v (o - xi)^T = M - S xi^T
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        vs[a] += S3[a];
-                        Bh[3 * a] += Mx[a] - S3[a] * xi[0];
-                        Bh[3 * a + 1] += My[a] - S3[a] * xi[1];
-                        Bh[3 * a + 2] += Mz[a] - S3[a] * xi[2];
-                    }
-                }
-                float vn[3], Bn[9], C[9];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) vn[a] = cref[a] + 0.5f * vs[a];
-#pragma unroll
-                for (int i = 0; i < 9; ++i) {
-                    Bh[i] *= 0.5f;
-                    Bn[i] = Bh[i] * d.geo.dx;
-                }
-                // C = B D^-1 = (dx Bh)(dx^2 Dhat)^-1 = Bh Dhat^-1 / dx
-#pragma unroll
-                for (int i = 0; i < 3; ++i)
-#pragma unroll
-                    for (int j2 = 0; j2 < 3; ++j2)
-                        C[3 * i + j2] = d.geo.inv_dx_f *
-                                        (Bh[3 * i] * Di[j2] + Bh[3 * i + 1] * Di[3 + j2] + Bh[3 * i + 2] * Di[6 + j2]);
-                // F' = (I + dt C) F  ->  H' = H + dt (C + C H)
-                float Fn[9];
-#pragma unroll
-                for (int i = 0; i < 3; ++i)
-#pragma unroll
-                    for (int j2 = 0; j2 < 3; ++j2)
-                        Fn[3 * i + j2] = q.H[3 * i + j2] + dt * (C[3 * i + j2] + C[3 * i] * q.H[j2] +
-                                                                 C[3 * i + 1] * q.H[3 + j2] + C[3 * i + 2] * q.H[6 + j2]);
-                // stress of the new state for the next step's P2G
-                float tau[6];
-                if (M.model == 1) dp_return_map(M, Fn, tau);
-                else kirchhoff(M, Fn, tau);
-                float xn[3];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) xn[a] = q.x[a] + dt * vn[a];
-                // x * 0 is NaN exactly when x is infinite or NaN
-                float probe = 0.0f;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) probe += vn[a] * 0.0f + xn[a] * 0.0f;
-#pragma unroll
-                for (int i = 0; i < 9; ++i) probe += Fn[i] * 0.0f + Bn[i] * 0.0f;
-                const bool finite = probe == 0.0f;
-                if (!finite) set_status(d.counters, ST_NONFINITE);
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    st_at(pa.out + a * S, out, xn[a]);
-                    st_at(pa.out + (3 + a) * S, out, vn[a]);
-                }
-#pragma unroll
-                for (int i = 0; i < 9; ++i) {
-                    st_at(pa.out + (6 + i) * S, out, Bn[i]);
-                    st_at(pa.out + (15 + i) * S, out, Fn[i]);
-                }
-#pragma unroll
-                for (int i = 0; i < 6; ++i) st_at(d.tau + i * d.tau_stride, out, tau[i]);
-                if (pa.id_out) st_at(pa.id_out, out, q.id);
-                if (pa.mat_out) st_at(pa.mat_out, out, (uint8_t)q.mat);
-                // next cell key for the following step
-                if (finite && cell_coord(d.geo, xn, cn)) {
-                    const uint32_t key = cell_key(d.geo, cn);
-                    st_at(d.key, out, key);
-                    st_at(d.sub, out, (uint16_t)sub_code(cn));
-                    sig = (int)(key >> 6);
-                } else {
-                    st_at(d.key, out, 0xffffffffu);
-                    set_status(d.counters, ST_DOMAIN);
-                }
+                NewState ns;
+                CellCoord cn;
+                bool placed;
+                sig = g2p_particle(d, pa, dt, q, cc, bx, by, bz, vt, out, true, ns, cn, placed);
             }
             wave_stamp(d, sig, E + 1);
         }
@@ -756,6 +860,172 @@ __global__ void __launch_bounds__(kThreads) k_g2p(DevCtx d, PartArgs pa, float d
 }
 
 // ---------------------------------------------------------------- exports
+// Order of a block's particles alone (for a G2P that follows a sort without P2G).
+__global__ void __launch_bounds__(kP2GThreads) k_block_order(DevCtx d) {
+    __shared__ int bcnt[kBins];
+    __shared__ int bstart[kBins + 1];
+    __shared__ int wsum[kP2GThreads / 64];
+    __shared__ uint32_t lbuf[kMaxBlockParticles];
+    __shared__ uint32_t ord[kMaxBlockParticles];
+    const int np = (int)d.counters[C_NPB];
+    for (int base = 0; base < np; base += gridDim.x) {
+        const int r = round_block(base, np);
+        if (r < 0) continue;
+        const int s = d.pstart[r];
+        const int cnt = d.pstart[r + 1] - s;
+        if (cnt > kMaxBlockParticles) continue;
+        order_block(d, r, s, cnt, bcnt, bstart, wsum, lbuf, ord);
+        lds_barrier();
+    }
+}
+
+// ---------------------------------------------------------------- fused G2P + P2G
+// G2P of step n fused with P2G of step n+1 (the paper's G2P2G kernel structure):
+// each workgroup gathers its block's particles from grid n, updates them, writes
+// the new state, and scatters the new state into grid n+1 through a fixed-point
+// tile covering every node the block's particles reach after moving at most one
+// cell: G- nodes [4B-1, 4B+5]^3 and G+ nodes [4B-2, 4B+5]^3 (7^3 + 8^3 = 855
+// nodes).  Particles that moved further add to the pool with float atomics (up to
+// three cells; beyond that the step reports MPM_E_CFL).  Grid n+1 is the 3 x 3 x 3
+// block neighbourhood of the particle blocks of step n, prepared by the same sort.
+constexpr int kFTY = 8, kFTZ = 66;                   // for every node offset the 64 cells of a block
+                                                     // fall on 16 distinct residues modulo 16
+constexpr int kFMStride = 6 * kFTZ + 6 * kFTY + 7;   // words per channel, G- (tile-local [0,6]^3)
+constexpr int kFPStride = 7 * kFTZ + 7 * kFTY + 8;   // G+ ([0,7]^3)
+constexpr int kFNodesM = 343, kFNodesP = 512;
+
+__global__ void __launch_bounds__(kP2GThreads, 2) k_g2p2g(DevCtx d, PartArgs pa, float dt, int gp_in, int gt_in,
+                                                       int gp_out, int gt_out) {
+    __shared__ int bcnt[kBins];
+    __shared__ int bstart[kBins + 1];
+    __shared__ int wsum[kP2GThreads / 64];
+    __shared__ unsigned int bmax;
+    __shared__ int nbr_in[27], nbr_out[27];
+    __shared__ uint32_t ord[kMaxBlockParticles];
+    __shared__ float vt[3 * kTileNodes];
+    constexpr int kTileWords = 4 * (kFMStride + kFPStride);
+    constexpr int kAreaWords = kTileWords > kMaxBlockParticles / 2 ? kTileWords : kMaxBlockParticles / 2;
+    __shared__ unsigned long long area[kAreaWords];
+    uint32_t *lbuf = reinterpret_cast<uint32_t *>(area);
+    unsigned long long *tile_m = area;
+    unsigned long long *tile_p = area + 4 * kFMStride;
+    const int np = (int)d.counters[C_NPB];
+    const int E = (int)d.counters[C_EPOCH];
+    const int tid = threadIdx.x;
+    for (int base = 0; base < np; base += gridDim.x) {
+        const int r = round_block(base, np);
+        if (r < 0) continue;
+        const int vb = d.plist[r];
+        int bx, by, bz;
+        block_coords(d.geo, vb, bx, by, bz);
+        const int s = d.pstart[r];
+        const int cnt = d.pstart[r + 1] - s;
+        if (cnt > kMaxBlockParticles) continue;   // reported by the bucket scan
+        order_block(d, r, s, cnt, bcnt, bstart, wsum, lbuf, ord);
+        load_neighbours(d, gt_in, bx, by, bz, nbr_in);
+        load_neighbours(d, gt_out, bx, by, bz, nbr_out, 64);
+        lds_barrier();
+        for (int ni = tid; ni < kTileNodes; ni += kP2GThreads) {
+            int g, ix, iy, iz;
+            tile_node(ni, bx, by, bz, g, ix, iy, iz);
+            const long long a = pool_index(d, nbr_in, bx, by, bz, g, ix, iy, iz, 1);
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) vt[ch * kTileNodes + ni] = a >= 0 ? d.pool[gp_in][a + ch * 64] : 0.0f;
+        }
+        for (int c0 = 0; c0 < cnt; c0 += kChunk) {
+            lds_barrier();   // velocity tile in place; previous pass's tile flushed
+            for (int q = tid; q < kTileWords; q += kP2GThreads) area[q] = 0ull;
+            if (tid == 0) bmax = 0u;
+            G2PIn in[2];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int j = c0 + tid + k * kP2GThreads;
+                if (j < cnt) g2p_load_index(pa, ord[j], in[k]);
+            }
+            Staged st[2];
+            float bnd = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int j = c0 + tid + k * kP2GThreads;
+                const bool act = j < cnt;
+                const uint32_t out = (uint32_t)(s + j);
+                st[k].on = false;
+                CellCoord cc;
+                bool ok = act && cell_coord(d.geo, in[k].x, cc);
+                ok = ok && (cc.c[0] >> 2) == bx && (cc.c[1] >> 2) == by && (cc.c[2] >> 2) == bz;
+                int sig = -1;
+                if (act && !ok) {
+                    set_status(d.counters, ST_STALE);
+                    st_at(d.key, out, 0xffffffffu);
+                } else if (ok) {
+                    NewState ns;
+                    CellCoord cn;
+                    bool placed;
+                    sig = g2p_particle(d, pa, dt, in[k], cc, bx, by, bz, vt, out, false, ns, cn, placed);
+                    if (placed) {
+                        const DevMaterial M = d.mats[in[k].mat < d.n_mat ? in[k].mat : 0];
+                        stage_compute(d, M, cn, ns.v, ns.B, ns.tau, dt, st[k]);
+                    }
+                }
+                wave_stamp(d, sig, E + 1);
+                bnd = fmaxf(bnd, contribution_bound(st[k]));
+            }
+            lds_barrier();   // tile cleared, bmax reset
+            const double S = block_scale(bnd, &bmax);
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                if (!st[k].on) continue;
+                const int lx = st[k].c[0] - 4 * bx + 1, ly = st[k].c[1] - 4 * by + 1, lz = st[k].c[2] - 4 * bz + 1;
+                if (lx >= 0 && ly >= 0 && lz >= 0 && lx <= 5 && ly <= 5 && lz <= 5)
+                    scatter_particle<kFTY, kFTZ, kFMStride, kFPStride>(st[k], lx, ly, lz, tile_m, tile_p, S);
+                else
+                    scatter_pool(d, d.pool[gp_out], nbr_out, bx, by, bz, st[k]);
+            }
+            lds_barrier();
+            // ---- flush every nonzero tile node to grid n+1
+            const double inv = 1.0 / S;
+            for (int ni = tid; ni < kFNodesM + kFNodesP; ni += kP2GThreads) {
+                const int g = ni < kFNodesM ? 0 : 1;
+                int lx, ly, lz;
+                if (g == 0) {
+                    lx = ni % 7;
+                    ly = (ni / 7) % 7;
+                    lz = ni / 49;
+                } else {
+                    const int k = ni - kFNodesM;
+                    lx = k & 7;
+                    ly = (k >> 3) & 7;
+                    lz = k >> 6;
+                }
+                const unsigned long long *tb = g == 0 ? tile_m : tile_p;
+                const int cs = g == 0 ? kFMStride : kFPStride;
+                const int t = lx + ly * kFTY + lz * kFTZ;
+                float val[4];
+#pragma unroll
+                for (int ch = 0; ch < 4; ++ch) val[ch] = (float)((double)(long long)tb[ch * cs + t] * inv);
+                if (val[0] == 0.0f && val[1] == 0.0f && val[2] == 0.0f && val[3] == 0.0f) continue;
+                const int ix = 4 * bx - 1 - g + lx, iy = 4 * by - 1 - g + ly, iz = 4 * bz - 1 - g + lz;
+                const long long a = pool_index(d, nbr_out, bx, by, bz, g, ix, iy, iz, 0);
+                if (a < 0) {
+                    set_status(d.counters, ST_CFL);
+                    continue;
+                }
+#pragma unroll
+                for (int ch = 0; ch < 4; ++ch)
+                    if (val[ch] != 0.0f) atomicAdd(&d.pool[gp_out][a + ch * 64], val[ch]);
+            }
+        }
+        lds_barrier();
+    }
+}
+
+__global__ void k_zero_pool(DevCtx d, int gp, int gt) {
+    const long long nfl = (long long)d.counters[ngb_slot(gt)] * (kBlockFloats / 4);
+    float4 *pool4 = reinterpret_cast<float4 *>(d.pool[gp]);
+    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < nfl; t += (long long)gridDim.x * blockDim.x)
+        pool4[t] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
 __global__ void k_grid_export(DevCtx d, float *m, float *vec, int gp, int gt) {
     const long long nx = d.geo.n[0] + 1, ny = d.geo.n[1] + 1, nz = d.geo.n[2] + 1;
     const long long nodes = nx * ny * nz;
@@ -816,6 +1086,20 @@ void launch_grid_update(const DevCtx &d, float dt, const float gravity[3], int g
 
 void launch_g2p(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, hipStream_t s) {
     hipLaunchKernelGGL(k_g2p, dim3(particle_grid(d)), dim3(kThreads), 0, s, d, pa, dt, gp, gt);
+}
+
+void launch_block_order(const DevCtx &d, hipStream_t s) {
+    hipLaunchKernelGGL(k_block_order, dim3(particle_grid(d)), dim3(kP2GThreads), 0, s, d);
+}
+
+void launch_g2p2g(const DevCtx &d, const PartArgs &pa, float dt, int gp_in, int gt_in, int gp_out, int gt_out,
+                  hipStream_t s) {
+    hipLaunchKernelGGL(k_g2p2g, dim3(particle_grid(d)), dim3(kP2GThreads), 0, s, d, pa, dt, gp_in, gt_in, gp_out,
+                       gt_out);
+}
+
+void launch_zero_pool(const DevCtx &d, int gp, int gt, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_pool, dim3(2048), dim3(256), 0, s, d, gp, gt);
 }
 
 void launch_grid_export(const DevCtx &d, float *m, float *vec, int gp, int gt, hipStream_t s) {

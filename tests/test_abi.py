@@ -38,8 +38,9 @@ def test_every_declared_symbol_is_exported(ck):
 
 def test_abi_version_and_strings(ck):
     assert ck.mpm_abi_version() == 1
-    for s in range(8):
+    for s in range(9):
         assert len(ck.mpm_status_string(s)) >= 2
+    assert ck.mpm_status_string(9) == "unknown status"
 
 
 def test_struct_layouts(ck):
@@ -59,7 +60,7 @@ def _good():
 
 @pytest.mark.parametrize("field,value", [
     ("dx", 0.03), ("dx", -0.5), ("dx", 0.0), ("max_particles", 0), ("max_particles", 1 << 26),
-    ("max_blocks", 0), ("bc", 7), ("bc_band", -1), ("transfer", 3), ("flags", 1),
+    ("max_blocks", 0), ("bc", 7), ("bc_band", -1), ("transfer", 3), ("flags", 2), ("flags", -1),
 ])
 def test_invalid_config_rejected_on_host(ck, field, value):
     cfg, mat = _good()
