@@ -72,6 +72,8 @@ def lib():
         L.ora_energy_density.restype = ctypes.c_double
         L.ora_energy_density.argtypes = [ctypes.POINTER(OraMaterial), ctypes.c_double, dp]
         L.ora_dp_return_map.argtypes = [ctypes.POINTER(OraMaterial), ctypes.c_double, dp]
+        L.ora_kirchhoff_vjp.argtypes = [ctypes.POINTER(OraMaterial), ctypes.c_double, dp, dp, dp,
+                                        ctypes.POINTER(ctypes.c_double)]
         L.ora_cell_keys.argtypes = [ctypes.POINTER(OraConfig), ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
                                     ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]
         L.ora_stable_sort.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]
@@ -79,6 +81,10 @@ def lib():
         L.ora_step.argtypes = [ctypes.POINTER(OraConfig), ctypes.POINTER(OraMaterial), ctypes.c_int32,
                                ctypes.c_int64, dp, dp, dp, dp, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                ctypes.POINTER(OraOutputs)]
+        L.ora_step_vjp.restype = ctypes.c_int
+        L.ora_step_vjp.argtypes = [ctypes.POINTER(OraConfig), ctypes.POINTER(OraMaterial), ctypes.c_int32,
+                                   ctypes.c_int64, dp, dp, dp, dp, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                   dp, dp, dp, dp, dp, dp, dp, dp, ctypes.c_void_p]
         L.ora_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -167,6 +173,16 @@ def energy_density(mat: OraMaterial, F, logE: Optional[float] = None) -> float:
     return lib().ora_energy_density(ctypes.byref(mat), float("nan") if logE is None else float(logE), _dptr(F))
 
 
+def kirchhoff_vjp(mat: OraMaterial, F, logE, tb):
+    """Adjoint of the fixed-corotated Kirchhoff stress: (dL/dF, dL/dlogE) from dL/dtau."""
+    F = np.ascontiguousarray(F, dtype=np.float64)
+    tb = np.ascontiguousarray(tb, dtype=np.float64)
+    Fb = np.zeros((3, 3))
+    lb = ctypes.c_double(0.0)
+    lib().ora_kirchhoff_vjp(ctypes.byref(mat), float(logE), _dptr(F), _dptr(tb), _dptr(Fb), ctypes.byref(lb))
+    return Fb, lb.value
+
+
 def dp_return_map(mat: OraMaterial, F, logE: Optional[float] = None) -> np.ndarray:
     F = np.array(F, dtype=np.float64, order="C")
     lib().ora_dp_return_map(ctypes.byref(mat), float("nan") if logE is None else float(logE), _dptr(F))
@@ -234,3 +250,82 @@ def step(cfg: OraConfig, mats, st: State, dt: float, grids: bool = False):
 
 def num_threads() -> int:
     return lib().ora_num_threads()
+
+
+def step_vjp(cfg: OraConfig, mats, st: State, dt: float, xb, vb, Bb, Fb):
+    """Cotangents of the state entering one step from those of the state it
+    produces (fixed corotated, MLS).  Returns (status, dict(x, v, B, F, logE));
+    logE is None when the state has no per-particle log modulus."""
+    n = st.n
+    c = [np.array(a, dtype=np.float64, order="C") for a in (xb, vb, Bb, Fb)]
+    out = dict(x=np.zeros((n, 3)), v=np.zeros((n, 3)), B=np.zeros((n, 3, 3)), F=np.zeros((n, 3, 3)))
+    out["logE"] = None if st.logE is None else np.zeros(n)
+    mat_ptr = None if st.mat is None else st.mat.ctypes.data
+    loge_ptr = None if st.logE is None else st.logE.ctypes.data
+    status = lib().ora_step_vjp(ctypes.byref(cfg), mats, len(mats), n, _dptr(st.x), _dptr(st.v), _dptr(st.B),
+                                _dptr(st.F), mat_ptr, loge_ptr, float(dt), _dptr(c[0]), _dptr(c[1]), _dptr(c[2]),
+                                _dptr(c[3]), _dptr(out["x"]), _dptr(out["v"]), _dptr(out["B"]), _dptr(out["F"]),
+                                None if out["logE"] is None else out["logE"].ctypes.data)
+    return status, out
+
+
+def particle_masses(mats, st: State) -> np.ndarray:
+    idx = np.zeros(st.n, np.int64) if st.mat is None else st.mat.astype(np.int64)
+    return np.array([mats[i].rho * mats[i].vol0 for i in range(len(mats))])[idx]
+
+
+def com_loss(target):
+    """Squared distance of the mass-weighted centre of mass to `target`, as a loss
+    callable (mats, state) -> (value, dL/dx)."""
+    t = np.asarray(target, np.float64)
+
+    def f(mats, st):
+        m = particle_masses(mats, st)
+        com = (m[:, None] * st.x).sum(axis=0) / m.sum()
+        d = com - t
+        return float(d @ d), (2.0 * d)[None, :] * (m / m.sum())[:, None]
+    return f
+
+
+def spread_loss(mats, st):
+    """Mass-weighted mean squared distance of the particles from their centre of
+    mass (depends on how the body deforms, so on its stiffness)."""
+    m = particle_masses(mats, st)
+    M = m.sum()
+    com = (m[:, None] * st.x).sum(axis=0) / M
+    r = st.x - com
+    return float((m * (r * r).sum(axis=1)).sum() / M), 2.0 * (m / M)[:, None] * r
+
+
+def rollout_loss(cfg: OraConfig, mats, st0: State, dt: float, nsteps: int, loss) -> float:
+    st = st0.copy()
+    for _ in range(nsteps):
+        status, _, _ = step(cfg, mats, st, dt)
+        if status != 0:
+            raise RuntimeError("oracle step failed with status %d" % status)
+    return loss(mats, st)[0]
+
+
+def rollout_loss_grad(cfg: OraConfig, mats, st0: State, dt: float, nsteps: int, loss):
+    """Loss of an n-step rollout and its gradient with respect to the initial state
+    (x, v, B, F) and the per-particle log modulus, by running the steps forward,
+    keeping every entering state, and applying step_vjp in reverse."""
+    states = [st0.copy()]
+    for _ in range(nsteps):
+        st = states[-1].copy()
+        status, _, _ = step(cfg, mats, st, dt)
+        if status != 0:
+            raise RuntimeError("oracle step failed with status %d" % status)
+        states.append(st)
+    value, xb = loss(mats, states[-1])
+    n = st0.n
+    vb, Bb, Fb = np.zeros((n, 3)), np.zeros((n, 3, 3)), np.zeros((n, 3, 3))
+    logEb = None if st0.logE is None else np.zeros(n)
+    for k in range(nsteps - 1, -1, -1):
+        status, g = step_vjp(cfg, mats, states[k], dt, xb, vb, Bb, Fb)
+        if status != 0:
+            raise RuntimeError("oracle step_vjp failed with status %d" % status)
+        xb, vb, Bb, Fb = g["x"], g["v"], g["B"], g["F"]
+        if logEb is not None:
+            logEb += g["logE"]
+    return value, dict(x=xb, v=vb, B=Bb, F=Fb, logE=logEb)

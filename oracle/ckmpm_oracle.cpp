@@ -274,6 +274,58 @@ double energy_density(const ora_material *m, double logE, const M3 &F) {
     return L.mu * e2 + 0.5 * L.lambda * tr * tr;
 }
 
+// Vector-Jacobian product of the fixed-corotated Kirchhoff stress above, the
+// differentiable step's constitutive adjoint: given tb = dL/dtau (a full 3x3
+// matrix; tau is symmetric for every F), returns dL/dF and dL/dlogE.
+//   dtau = 2 mu (dF F^T + F dF^T - dR F^T - R dF^T) + lambda (2J - 1) dJ I,
+//   dJ = <cof F, dF>,  and tau is linear in E = exp(logE).
+// The rotation R = U V^T of F = U S V^T moves as dR = U M V^T with
+// M_ij = (A_ij - A_ji) / (s_i + s_j), A = U^T dF V (the derivative of the polar
+// factor), so its adjoint adds U Z V^T, Z_ij = (Y_ij - Y_ji) / (s_i + s_j),
+// Y = U^T Rbar V.
+void kirchhoff_fc_vjp(const ora_material *m, double logE, const M3 &F, const M3 &tb, M3 &Fb, double &logEb) {
+    const Lame L = lame(m, logE);
+    M3 U, V;
+    double s[3];
+    svd_jacobi(F, U, s, V);
+    const M3 R = mul(U, transpose(V));
+    const double J = det(F);
+    const M3 tbT = transpose(tb);
+    const M3 t1 = mul(tb, F), t2 = mul(tbT, F), t3 = mul(tbT, R);
+    Fb = zero3();
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Fb.a[i][j] = 2.0 * L.mu * (t1.a[i][j] + t2.a[i][j] - t3.a[i][j]);
+    M3 Rb;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Rb.a[i][j] = -2.0 * L.mu * t1.a[i][j];
+    const M3 Y = mul(transpose(U), mul(Rb, V));
+    M3 Z = zero3();
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            if (i != j) Z.a[i][j] = (Y.a[i][j] - Y.a[j][i]) / (s[i] + s[j]);
+    const M3 dFR = mul(U, mul(Z, transpose(V)));
+    // cofactor matrix cof(F) = J F^-T
+    M3 cof;
+    const auto &f = F.a;
+    cof.a[0][0] = f[1][1] * f[2][2] - f[1][2] * f[2][1];
+    cof.a[0][1] = f[1][2] * f[2][0] - f[1][0] * f[2][2];
+    cof.a[0][2] = f[1][0] * f[2][1] - f[1][1] * f[2][0];
+    cof.a[1][0] = f[0][2] * f[2][1] - f[0][1] * f[2][2];
+    cof.a[1][1] = f[0][0] * f[2][2] - f[0][2] * f[2][0];
+    cof.a[1][2] = f[0][1] * f[2][0] - f[0][0] * f[2][1];
+    cof.a[2][0] = f[0][1] * f[1][2] - f[0][2] * f[1][1];
+    cof.a[2][1] = f[0][2] * f[1][0] - f[0][0] * f[1][2];
+    cof.a[2][2] = f[0][0] * f[1][1] - f[0][1] * f[1][0];
+    const double trtb = tb.a[0][0] + tb.a[1][1] + tb.a[2][2];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Fb.a[i][j] += dFR.a[i][j] + L.lambda * (2.0 * J - 1.0) * trtb * cof.a[i][j];
+    const M3 tau = kirchhoff(m, logE, F);
+    logEb = 0.0;
+    if (!std::isnan(logE))
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) logEb += tb.a[i][j] * tau.a[i][j];
+}
+
 // Drucker-Prager return mapping (Klar et al. 2016, projection onto the cone in
 // log-strain space), applied to the trial elastic F after the F update.
 void dp_return_map(const ora_material *m, double logE, M3 &F) {
@@ -384,6 +436,33 @@ M3 moment_matrix(const Stencil &st) {
     return D;
 }
 
+// Adjoint of D_p = 1/2 sum_k sum_i w (x_i - x_p)(x_i - x_p)^T with respect to the
+// particle position, term by term: given Db = dL/dD, adds to xb
+//   1/2 sum [ grad w (d^T Db d) - w (Db d + Db^T d) ],   d = x_i - x_p.
+void moment_matrix_vjp(const Stencil &st, const M3 &Db, double xb[3]) {
+    for (int g = 0; g < 2; ++g)
+        for (int o = 0; o < 8; ++o) {
+            const double *d = st.d[g][o];
+            double Dd[3] = {0, 0, 0}, DTd[3] = {0, 0, 0}, q = 0;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) {
+                    Dd[a] += Db.a[a][b] * d[b];
+                    DTd[a] += Db.a[b][a] * d[b];
+                    q += d[a] * Db.a[a][b] * d[b];
+                }
+            for (int a = 0; a < 3; ++a) xb[a] += 0.5 * (st.gw[g][o][a] * q - st.w[g][o] * (Dd[a] + DTd[a]));
+        }
+}
+
+// d(D^-1) = -D^-1 dD D^-1, so the adjoint of the inverse is Db = -D^-T Dib D^-T.
+M3 inverse_vjp(const M3 &Di, const M3 &Dib) {
+    const M3 DiT = transpose(Di);
+    M3 r = mul(DiT, mul(Dib, DiT));
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) r.a[i][j] = -r.a[i][j];
+    return r;
+}
+
 bool in_domain(const ora_config *c, const double xp[3]) {
     for (int a = 0; a < 3; ++a) {
         const double X = (xp[a] - c->origin[a]) / c->dx;
@@ -456,6 +535,15 @@ void ora_kirchhoff(const ora_material *m, double logE, const double F[9], double
 
 double ora_energy_density(const ora_material *m, double logE, const double F[9]) {
     return energy_density(m, logE, load3(F));
+}
+
+void ora_kirchhoff_vjp(const ora_material *m, double logE, const double F[9], const double tb[9], double Fb[9],
+                       double *logEb) {
+    M3 fb;
+    double lb = 0.0;
+    kirchhoff_fc_vjp(m, logE, load3(F), load3(tb), fb, lb);
+    store3(fb, Fb);
+    if (logEb) *logEb = lb;
 }
 
 void ora_dp_return_map(const ora_material *m, double logE, double F[9]) {
@@ -689,6 +777,195 @@ int ora_step(const ora_config *cfg, const ora_material *mats, int32_t n_mat, int
             for (int64_t i = 0; i < 6 * nodes; ++i) out->grid_p[i] = gmv[i] + dt * gf[i];
         if (out->grid_v) std::copy(gv.begin(), gv.end(), out->grid_v);
         if (out->diag) std::copy(diag, diag + 32, out->diag);
+    }
+    return 0;
+}
+
+// Reverse-mode derivative (vector-Jacobian product) of one MLS step with the
+// fixed-corotated model, for the differentiable rollout: given the state entering
+// the step (x, v, B, F, logE) and the cotangents of the state it produces
+// (xb_out .. Fb_out), returns the cotangents of the entering state and of logE.
+// The forward step is recomputed here; then its three phases are reversed in
+// turn, every product rule written out:
+//   G2P:  x' = x + dt v',  v' = 1/2 sum w v~,  B' = 1/2 sum w v~ d^T,
+//         F' = (I + dt B' D^-1) F,  with w, d = x_i - x and D depending on x;
+//   grid: v~ = p / m + dt g where m > 0 and the node is free, else 0;
+//   P2G:  m_i = sum w m_p,  p_i = sum w (m_p v + (m_p B - dt V0 tau) D^-1 d).
+// Returns 0 on success, 1 for a bad material index, 2 for a configuration it does
+// not differentiate (Drucker-Prager or the exact-gradient transfer), 3 for a
+// particle outside the valid domain.
+int ora_step_vjp(const ora_config *cfg, const ora_material *mats, int32_t n_mat, int64_t n, const double *x,
+                 const double *v, const double *B, const double *F, const uint8_t *mat, const double *logE, double dt,
+                 const double *xb_out, const double *vb_out, const double *Bb_out, const double *Fb_out, double *xb,
+                 double *vb, double *Bb, double *Fb, double *logEb) {
+    if (cfg->transfer != 0) return 2;
+    for (int64_t p = 0; p < n; ++p) {
+        if (mat && mat[p] >= n_mat) return 1;
+        if (mats[mat ? mat[p] : 0].model != 0) return 2;
+        if (!in_domain(cfg, x + 3 * p)) return 3;
+    }
+    const int64_t nx = cfg->n_cells[0] + 1, ny = cfg->n_cells[1] + 1, nz = cfg->n_cells[2] + 1;
+    const int64_t nodes = nx * ny * nz;
+    auto material = [&](int64_t p) -> const ora_material * { return &mats[mat ? mat[p] : 0]; };
+    auto logEp = [&](int64_t p) { return logE ? logE[p] : std::nan(""); };
+
+    // ---- forward recomputation: D^-1, tau, grid mass and momentum, grid velocity
+    std::vector<double> Dinv(9 * n), tau(9 * n), gm(2 * nodes, 0.0), gp(6 * nodes, 0.0), gv(6 * nodes, 0.0);
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < n; ++p) {
+        Stencil st;
+        stencil(cfg, x + 3 * p, st);
+        store3(inverse(moment_matrix(st)), &Dinv[9 * p]);
+        store3(kirchhoff(material(p), logEp(p), load3(F + 9 * p)), &tau[9 * p]);
+    }
+    for (int64_t p = 0; p < n; ++p) {
+        Stencil st;
+        stencil(cfg, x + 3 * p, st);
+        const double m = material(p)->rho * material(p)->vol0, V0 = material(p)->vol0;
+        const M3 Di = load3(&Dinv[9 * p]), T = load3(&tau[9 * p]), Bp = load3(B + 9 * p);
+        M3 A;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) A.a[i][j] = m * Bp.a[i][j] - dt * V0 * T.a[i][j];
+        const M3 Q = mul(A, Di);
+        for (int g = 0; g < 2; ++g)
+            for (int o = 0; o < 8; ++o) {
+                const int64_t id = g * nodes + st.node[g][o];
+                const double w = st.w[g][o];
+                gm[id] += w * m;
+                for (int a = 0; a < 3; ++a) {
+                    double qd = 0;
+                    for (int b = 0; b < 3; ++b) qd += Q.a[a][b] * st.d[g][o][b];
+                    gp[id * 3 + a] += w * (m * v[3 * p + a] + qd);
+                }
+            }
+    }
+    std::vector<char> live(2 * nodes, 0);
+    for (int64_t id = 0; id < 2 * nodes; ++id) {
+        const int g = (int)(id / nodes);
+        const int64_t r = id % nodes;
+        const int32_t ijk[3] = {(int32_t)(r % nx), (int32_t)((r / nx) % ny), (int32_t)(r / (nx * ny))};
+        if (gm[id] > 0.0 && !sticky(cfg, ijk, g == 0 ? -1.0 : 1.0)) {
+            live[id] = 1;
+            for (int a = 0; a < 3; ++a) gv[id * 3 + a] = gp[id * 3 + a] / gm[id] + dt * cfg->gravity[a];
+        }
+    }
+    (void)nz;
+
+    // ---- G2P reversed (per particle; the grid cotangent is summed serially)
+    std::vector<double> gvb(6 * nodes, 0.0);
+    for (int64_t p = 0; p < n; ++p) {
+        Stencil st;
+        stencil(cfg, x + 3 * p, st);
+        const M3 Di = load3(&Dinv[9 * p]), Fp = load3(F + 9 * p), Fbo = load3(Fb_out + 9 * p);
+        M3 Bn = zero3();
+        for (int g = 0; g < 2; ++g)
+            for (int o = 0; o < 8; ++o) {
+                const double *vi = &gv[(g * nodes + st.node[g][o]) * 3];
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) Bn.a[a][b] += 0.5 * st.w[g][o] * vi[a] * st.d[g][o][b];
+            }
+        const M3 C = mul(Bn, Di);
+        double xbar[3], vbt[3];
+        for (int a = 0; a < 3; ++a) {
+            xbar[a] = xb_out[3 * p + a];
+            vbt[a] = vb_out[3 * p + a] + dt * xb_out[3 * p + a];
+        }
+        M3 Cb = mul(Fbo, transpose(Fp));
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) Cb.a[i][j] *= dt;
+        M3 IC = eye3();
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) IC.a[i][j] += dt * C.a[i][j];
+        store3(mul(transpose(IC), Fbo), Fb + 9 * p);
+        M3 Bbt = mul(Cb, transpose(Di));
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) Bbt.a[i][j] += Bb_out[9 * p + 3 * i + j];
+        const M3 Dib = mul(transpose(Bn), Cb);
+        for (int g = 0; g < 2; ++g)
+            for (int o = 0; o < 8; ++o) {
+                const int64_t id = g * nodes + st.node[g][o];
+                const double *vi = &gv[id * 3];
+                const double w = st.w[g][o];
+                double gvec[3], wb = 0;
+                for (int a = 0; a < 3; ++a) {
+                    gvec[a] = vbt[a];
+                    for (int b = 0; b < 3; ++b) gvec[a] += Bbt.a[a][b] * st.d[g][o][b];
+                }
+                for (int a = 0; a < 3; ++a) {
+                    gvb[id * 3 + a] += 0.5 * w * gvec[a];
+                    wb += 0.5 * vi[a] * gvec[a];
+                }
+                for (int b = 0; b < 3; ++b) {
+                    double db = 0;   // dL/d(d_b) = 1/2 w (Bbt^T v~)_b ; d = x_i - x
+                    for (int a = 0; a < 3; ++a) db += 0.5 * w * Bbt.a[a][b] * vi[a];
+                    xbar[b] += wb * st.gw[g][o][b] - db;
+                }
+            }
+        moment_matrix_vjp(st, inverse_vjp(Di, Dib), xbar);
+        for (int a = 0; a < 3; ++a) xb[3 * p + a] = xbar[a];
+    }
+
+    // ---- grid update reversed: p-bar = v~-bar / m, m-bar = -(v~-bar . p) / m^2
+    std::vector<double> gmb(2 * nodes, 0.0), gpb(6 * nodes, 0.0);
+    for (int64_t id = 0; id < 2 * nodes; ++id) {
+        if (!live[id]) continue;
+        double dot = 0;
+        for (int a = 0; a < 3; ++a) {
+            gpb[id * 3 + a] = gvb[id * 3 + a] / gm[id];
+            dot += gvb[id * 3 + a] * gp[id * 3 + a];
+        }
+        gmb[id] = -dot / (gm[id] * gm[id]);
+    }
+
+    // ---- P2G reversed (a gather per particle)
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < n; ++p) {
+        Stencil st;
+        stencil(cfg, x + 3 * p, st);
+        const double m = material(p)->rho * material(p)->vol0, V0 = material(p)->vol0;
+        const M3 Di = load3(&Dinv[9 * p]), T = load3(&tau[9 * p]), Bp = load3(B + 9 * p);
+        M3 A;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) A.a[i][j] = m * Bp.a[i][j] - dt * V0 * T.a[i][j];
+        const M3 Q = mul(A, Di);
+        double xbar[3] = {xb[3 * p], xb[3 * p + 1], xb[3 * p + 2]}, vbar[3] = {0, 0, 0};
+        M3 Qb = zero3();
+        for (int g = 0; g < 2; ++g)
+            for (int o = 0; o < 8; ++o) {
+                const int64_t id = g * nodes + st.node[g][o];
+                const double w = st.w[g][o];
+                const double *pb = &gpb[id * 3];
+                double wb = m * gmb[id];
+                for (int a = 0; a < 3; ++a) {
+                    double pi = m * v[3 * p + a];
+                    for (int b = 0; b < 3; ++b) pi += Q.a[a][b] * st.d[g][o][b];
+                    wb += pb[a] * pi;
+                    vbar[a] += w * m * pb[a];
+                    for (int b = 0; b < 3; ++b) Qb.a[a][b] += w * pb[a] * st.d[g][o][b];
+                }
+                for (int b = 0; b < 3; ++b) {
+                    double db = 0;   // dL/d(d_b) = w (Q^T p-bar)_b
+                    for (int a = 0; a < 3; ++a) db += w * Q.a[a][b] * pb[a];
+                    xbar[b] += wb * st.gw[g][o][b] - db;
+                }
+            }
+        const M3 Ab = mul(Qb, transpose(Di));
+        moment_matrix_vjp(st, inverse_vjp(Di, mul(transpose(A), Qb)), xbar);
+        M3 tb;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                Bb[9 * p + 3 * i + j] = m * Ab.a[i][j];
+                tb.a[i][j] = -dt * V0 * Ab.a[i][j];
+            }
+        M3 Ftb;
+        double lb;
+        kirchhoff_fc_vjp(material(p), logEp(p), load3(F + 9 * p), tb, Ftb, lb);
+        for (int i = 0; i < 9; ++i) Fb[9 * p + i] += Ftb.a[i / 3][i % 3];
+        if (logEb) logEb[p] = lb;
+        for (int a = 0; a < 3; ++a) {
+            xb[3 * p + a] = xbar[a];
+            vb[3 * p + a] = vbar[a];
+        }
     }
     return 0;
 }

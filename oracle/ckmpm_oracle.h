@@ -50,6 +50,9 @@ void   ora_moment_matrix(const ora_config *cfg, const double xp[3], double D[9])
 int    ora_svd3(const double F[9], double U[9], double S[3], double V[9]);
 void   ora_kirchhoff(const ora_material *m, double logE_or_nan, const double F[9], double tau[9]);
 double ora_energy_density(const ora_material *m, double logE_or_nan, const double F[9]);
+/* adjoint of the fixed-corotated stress: tb = dL/dtau -> dL/dF, dL/dlogE */
+void   ora_kirchhoff_vjp(const ora_material *m, double logE, const double F[9], const double tb[9], double Fb[9],
+                         double *logEb);
 void   ora_dp_return_map(const ora_material *m, double logE_or_nan, double F[9]);
 void   ora_cell_keys(const ora_config *cfg, int64_t n, const float *x_soa, int64_t stride, uint32_t *keys,
                      int32_t *bad);
@@ -57,6 +60,13 @@ void   ora_stable_sort(int64_t n, const uint32_t *keys, uint32_t *perm);
 int    ora_step(const ora_config *cfg, const ora_material *mats, int32_t n_mat, int64_t n,
                 double *x, double *v, double *B, double *F, const uint8_t *mat, const double *logE,
                 double dt, ora_outputs *out);
+/* Reverse-mode derivative of ora_step (fixed corotated, MLS transfer): cotangents of
+ * the entering state (and of the per-particle log Young's modulus, when logE is
+ * given) from those of the produced state; AoS layouts as above. */
+int    ora_step_vjp(const ora_config *cfg, const ora_material *mats, int32_t n_mat, int64_t n, const double *x,
+                    const double *v, const double *B, const double *F, const uint8_t *mat, const double *logE,
+                    double dt, const double *xb_out, const double *vb_out, const double *Bb_out,
+                    const double *Fb_out, double *xb, double *vb, double *Bb, double *Fb, double *logEb);
 int    ora_num_threads(void);
 
 #ifdef __cplusplus

@@ -140,6 +140,35 @@ def sand_column(seed: int = 2, scale: int = 1) -> Scene:
                  2e-5, 500, mats, x, v, B, F, np.zeros(x.shape[0], np.uint8))
 
 
+def diff_box(seed: int = 5, scale: int = 1) -> Scene:
+    """The differentiation workload: a 32x16x16-cell elastic box at 8 ppc (65,536
+    particles) centred in a 64^3 grid (dx = 1/64), fixed corotated E = 5e4, nu = 0.3,
+    rho = 1000, initial velocity N(0, 0.1^2) per component, a per-particle log
+    Young's modulus field starting at log 5e4, gravity -9.8, sticky walls, dt = 1e-4,
+    64 steps.  `scale` k shrinks the box k-fold per axis and the grid to 64/k cells
+    (at least 16) at the same dx, for CPU-sized versions."""
+    dx = 1.0 / 64
+    n = max(16, 64 // scale)
+    ext = (max(1, 32 // scale), max(1, 16 // scale), max(1, 16 // scale))
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lo = tuple((n / 2 - e / 2) * dx for e in ext)
+    x = stratified_box(rng, lo, ext, dx)
+    v, B, F = _rest_state(x.shape[0])
+    v = (0.1 * rng.standard_normal(v.shape)).astype(np.float32)
+    mats = [Material(FIXED_COROTATED, 5e4, 0.3, 1000.0, dx ** 3 / 8)]
+    logE = np.full(x.shape[0], np.log(5e4), np.float32)
+    return Scene("diff_box_%d" % x.shape[0], (n, n, n), dx, (0.0, 0.0, 0.0), (0.0, -9.8, 0.0), 2,
+                 1e-4, 64, mats, x, v, B, F, np.zeros(x.shape[0], np.uint8), logE)
+
+
+def diff_target(seed: int = 5, scale: int = 1) -> np.ndarray:
+    """Target point of the differentiation workload's centre-of-mass loss, uniform in
+    the middle 40 % of the domain per axis ([0.3, 0.7]^3 of the unit box)."""
+    n = max(16, 64 // scale)
+    rng = np.random.Generator(np.random.PCG64(seed + 1000))
+    return (0.3 + 0.4 * rng.random(3)) * (n / 64.0)
+
+
 def random_blob(seed: int, n_cells=(8, 8, 8), lo_cells=(2.5, 2.5, 2.5), ext_cells=(3, 3, 3),
                 model: int = FIXED_COROTATED, v_scale=0.5, B_scale=2.0, F_scale=0.05,
                 gravity=(0.0, 0.0, 0.0), bc_band: int = 0, dt: float = 1e-3,
