@@ -79,7 +79,8 @@ EXPORTS = ("mpm_create", "mpm_destroy", "mpm_p2g", "mpm_grid_update", "mpm_g2p",
            "mpm_grid_read", "mpm_sort_keys", "mpm_invalidate", "mpm_get_stats", "mpm_profile_enable",
            "mpm_profile_read", "mpm_status_string", "mpm_abi_version", "mpm_footprint", "mpm_server_create",
            "mpm_server_destroy", "mpm_server_submit", "mpm_server_poll", "mpm_server_drain", "mpm_server_job_info",
-           "mpm_server_job_read", "mpm_server_job_release", "mpm_server_step_latencies")
+           "mpm_server_job_read", "mpm_server_job_release", "mpm_server_step_latencies", "mpm_ad_create",
+           "mpm_ad_destroy", "mpm_ad_forward", "mpm_ad_backward", "mpm_ad_sync")
 
 
 def lib():
@@ -119,6 +120,11 @@ def lib():
         L.mpm_server_job_read.argtypes = [vp, ctypes.c_int64, vp, vp]
         L.mpm_server_job_release.argtypes = [vp, ctypes.c_int64]
         L.mpm_server_step_latencies.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int64, i64p]
+        L.mpm_ad_create.argtypes = [ctypes.POINTER(mpm_config), ctypes.POINTER(mpm_material), ctypes.POINTER(vp)]
+        L.mpm_ad_destroy.argtypes = [vp]
+        L.mpm_ad_forward.argtypes = [vp, ctypes.c_int64, ctypes.c_int64, vp, vp, vp, ctypes.c_double, vp]
+        L.mpm_ad_backward.argtypes = [vp, ctypes.c_int64, ctypes.c_int64, vp, vp, vp, vp, vp, ctypes.c_double, vp]
+        L.mpm_ad_sync.argtypes = [vp, vp]
         for name in EXPORTS:
             if name not in ("mpm_status_string", "mpm_abi_version", "mpm_footprint"):
                 getattr(L, name).restype = st
@@ -193,6 +199,29 @@ def mpm_profile_read(ctx, n_phases: int = 5):
     cnt = (ctypes.c_int64 * n_phases)()
     s = lib().mpm_profile_read(ctx, ms, cnt, n_phases)
     return s, list(ms), list(cnt)
+
+
+def mpm_ad_create(cfg: mpm_config, mat: mpm_material):
+    h = ctypes.c_void_p()
+    s = lib().mpm_ad_create(ctypes.byref(cfg), ctypes.byref(mat), ctypes.byref(h))
+    return s, h
+
+
+def mpm_ad_destroy(h) -> int:
+    return lib().mpm_ad_destroy(h)
+
+
+def mpm_ad_forward(h, n: int, stride: int, state_in: int, logE: int, state_out: int, dt: float, stream=None) -> int:
+    return lib().mpm_ad_forward(h, n, stride, state_in, logE, state_out, dt, _stream(stream))
+
+
+def mpm_ad_backward(h, n: int, stride: int, state_in: int, logE: int, cot_out: int, cot_in: int, logE_cot: int,
+                    dt: float, stream=None) -> int:
+    return lib().mpm_ad_backward(h, n, stride, state_in, logE, cot_out, cot_in, logE_cot, dt, _stream(stream))
+
+
+def mpm_ad_sync(h, stream=None) -> int:
+    return lib().mpm_ad_sync(h, _stream(stream))
 
 
 def mpm_status_string(status: int) -> str:

@@ -354,6 +354,12 @@ mpm_status status_from_bits(unsigned int bits) {
     return MPM_OK;
 }
 
+mpm_status check_config(const mpm_config *c, const mpm_material *m, int32_t n_mat) {
+    return validate_config(c, m, n_mat);
+}
+void geometry_of(const mpm_config &c, Geometry &g) { fill_geometry(c, g); }
+DevMaterial device_material(const mpm_material &m) { return dev_material(m); }
+
 }  // namespace ck
 
 extern "C" {

@@ -20,5 +20,10 @@ unsigned int *ctx_status_word(mpm_ctx *ctx);
 mpm_status status_from_bits(unsigned int bits);
 // Device bytes of every buffer a context with this configuration allocates.
 int64_t ctx_device_bytes(const mpm_config &c);
+// Host-side validation of a configuration and its materials, the device geometry
+// (origin, cell size, wall bounds) and the device form of a material.
+mpm_status check_config(const mpm_config *c, const mpm_material *m, int32_t n_mat);
+void geometry_of(const mpm_config &c, Geometry &g);
+DevMaterial device_material(const mpm_material &m);
 
 }  // namespace ck

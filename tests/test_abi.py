@@ -1,5 +1,5 @@
 """CPU-side checks of the C ABI: the built library loads and exports every entry
-point include/ckmpm.h declares, struct layouts match the header, and host-side
+point include/*.h declares, struct layouts match the header, and host-side
 validation rejects bad configurations before touching a GPU."""
 import ctypes
 import os
@@ -23,7 +23,8 @@ def ck():
 
 
 def declared_functions():
-    text = open(HEADER).read()
+    import glob
+    text = "".join(open(h).read() for h in sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))))
     return sorted(set(re.findall(r"^\s*(?:mpm_status|const char \*|int32_t|int64_t)\s*\*?\s*(mpm_\w+)\s*\(", text, re.M)))
 
 
