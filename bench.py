@@ -110,6 +110,52 @@ def serve(srv, jobs, states, rate, ckmpm):
     return done, srv.step_latencies()
 
 
+def adjoint_main(args):
+    """Differentiated rollouts: the differentiation workload (65,536 elastic particles,
+    64 steps, checkpoints every 8 steps) forward and backward through the
+    checkpointed rollout, loss = squared distance of the centre of mass to a seeded
+    target; gradients in the initial velocity and the log-modulus field."""
+    import torch
+
+    import scenes
+    from paper_2412_10399_amd import ckmpm, diff
+
+    torch.cuda.set_device(0)
+    sc = scenes.diff_box()
+    target = torch.tensor(scenes.diff_target(), dtype=torch.float32, device="cuda")
+    ad = diff.AdContext(ckmpm.scene_config(sc), ckmpm.scene_materials(sc)[0])
+    s0 = torch.from_numpy(ckmpm.state_planes(sc.x, sc.v, sc.B, sc.F)).cuda()
+    logE0 = torch.from_numpy(sc.logE).cuda()
+    n = sc.n
+
+    def once():
+        v0 = s0[3:6].t().clone().requires_grad_(True)
+        logE = logE0.clone().requires_grad_(True)
+        state0 = diff.planes(s0[0:3].t(), v0, s0[6:15].t().reshape(n, 3, 3), s0[15:24].t().reshape(n, 3, 3))
+        fin = diff.rollout(ad, state0, logE, sc.steps, sc.dt, checkpoint_every=8)
+        loss = ((fin[0:3].t().mean(dim=0) - target) ** 2).sum()
+        loss.backward()
+        return loss
+
+    for _ in range(2):   # first call loads the library and sizes the allocator
+        once()
+    torch.cuda.synchronize()
+    reps = max(1, min(args.steps, 10))
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        once()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    out = {"metric": "differentiated particle-steps/s", "value": n * sc.steps / wall, "unit": "particle-steps/s",
+           "higher_is_better": True, "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+           "ms_per_rollout": 1e3 * wall, "rollouts": reps,
+           "config": {"workload": "diff_box_65536", "particles": n, "grid": "64^3", "steps": sc.steps,
+                      "checkpoint_every": 8, "loss": "centre-of-mass distance squared",
+                      "gradients": ["v0", "logE"]}}
+    ad.close()
+    print(json.dumps(out), flush=True)
+
+
 def serving_main(args):
     """Served-job benchmark: the seeded mix of 256 jobs (1e3-2e6 particles, elastic or
     sand, 200 steps), first run one at a time through the server, then arriving as a
@@ -178,6 +224,7 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this size first (calibrates HBM counters under rocprofv3)")
     ap.add_argument("--serving", action="store_true", help="served-job benchmark instead of the step throughput")
+    ap.add_argument("--adjoint", action="store_true", help="differentiated-rollout benchmark")
     ap.add_argument("--jobs", type=int, default=256)
     ap.add_argument("--streams", type=int, default=4)
     ap.add_argument("--max-jobs", type=int, default=32)
@@ -190,6 +237,9 @@ def main():
 
     if args.serving:
         serving_main(args)
+        return
+    if args.adjoint:
+        adjoint_main(args)
         return
 
     import torch
