@@ -110,6 +110,44 @@ def serve(srv, jobs, states, rate, ckmpm):
     return done, srv.step_latencies()
 
 
+def stress_main(args):
+    """Stress scale: ~30.6M particles (random sand stacks and an elastic sphere at
+    20 m/s) on a 1024^3 virtual grid, dt = 5e-6; two warm-up steps, then `steps`
+    (at most the workload's 200) timed steps of the same phase kernels."""
+    import torch
+
+    import scenes
+    from paper_2412_10399_amd import ckmpm
+
+    torch.cuda.set_device(0)
+    sc = scenes.stress_scene()
+    ctx = ckmpm.Context(ckmpm.scene_config(sc), ckmpm.scene_materials(sc))
+    parts = ckmpm.particles_from_scene(sc, "cuda:0")
+    stream = torch.cuda.current_stream()
+    ckmpm.check(ckmpm.mpm_step(ctx.h, parts.c, sc.dt, 2, stream), "warmup")
+    ckmpm.check(ckmpm.mpm_sync(ctx.h, stream), "warmup status")
+    steps = max(1, min(args.steps, sc.steps))
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    ckmpm.check(ckmpm.mpm_step(ctx.h, parts.c, sc.dt, steps, stream), "timed steps")
+    stop.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    ckmpm.check(ckmpm.mpm_sync(ctx.h, stream), "timed status")
+    s, stats = ckmpm.mpm_get_stats(ctx.h, stream)
+    ckmpm.check(s)
+    out = {"metric": "particle-steps/s at stress scale", "value": sc.n * steps / (ms * 1e-3), "unit": "particle-steps/s",
+           "higher_is_better": True, "n_gpus": 1, "dtype": "f32", "data": "synthetic", "steps": steps,
+           "ms_per_step": ms / steps,
+           "config": {"workload": "stress_sand_stacks_and_sphere", "particles": sc.n, "grid": "1024^3 virtual",
+                      "dt": sc.dt, "active_grid_blocks": int(stats.n_grid_blocks),
+                      "particle_blocks": int(stats.n_particle_blocks)}}
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def adjoint_main(args):
     """Differentiated rollouts: the differentiation workload (65,536 elastic particles,
     64 steps, checkpoints every 8 steps) forward and backward through the
@@ -225,6 +263,7 @@ def main():
                     help="run one plain device copy of this size first (calibrates HBM counters under rocprofv3)")
     ap.add_argument("--serving", action="store_true", help="served-job benchmark instead of the step throughput")
     ap.add_argument("--adjoint", action="store_true", help="differentiated-rollout benchmark")
+    ap.add_argument("--stress", action="store_true", help="30M-particle stress-scale benchmark")
     ap.add_argument("--jobs", type=int, default=256)
     ap.add_argument("--streams", type=int, default=4)
     ap.add_argument("--max-jobs", type=int, default=32)
@@ -240,6 +279,9 @@ def main():
         return
     if args.adjoint:
         adjoint_main(args)
+        return
+    if args.stress:
+        stress_main(args)
         return
 
     import torch

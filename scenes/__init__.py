@@ -169,6 +169,47 @@ def diff_target(seed: int = 5, scale: int = 1) -> np.ndarray:
     return (0.3 + 0.4 * rng.random(3)) * (n / 64.0)
 
 
+def stress_scene(seed: int = 3, sand_cells: int = 3_190_000, scale: int = 1) -> Scene:
+    """The stress-scale workload on a 1024^3 virtual grid (dx = 1/1024): seeded random
+    axis-aligned sand boxes (sides uniform in [0.03, 0.15], Drucker-Prager as the sand
+    column) stacked on the floor by a height map until about `sand_cells` cells are
+    covered (~25.5M particles at 8 ppc), and an elastic sphere of radius 0.05
+    (fixed corotated, E = 1e7, nu = 0.3, rho = 2000, ~4.5M particles) moving at
+    20 m/s along +x towards the stacks; dt = 5e-6, 200 steps.  Boxes are placed in
+    x, z in [0.35, 0.9], each resting on the highest column under its footprint, so
+    they never overlap.  `scale` k divides every length (and the sand volume) by k
+    on a 1024/k grid at the same dx, for smaller versions."""
+    n = 1024 // scale
+    dx = 1.0 / 1024
+    rng = np.random.Generator(np.random.PCG64(seed))
+    height = np.full((n, n), 2, np.int64)          # first free cell per (x, z) column, above the wall band
+    boxes = []
+    covered = 0
+    lo_xz, hi_xz = int(0.35 * n), int(0.9 * n)
+    while covered < sand_cells // (scale ** 3):
+        side = np.maximum(1, np.round(rng.uniform(0.03, 0.15, 3) * 1024 / scale).astype(np.int64))
+        x0 = int(rng.integers(lo_xz, max(lo_xz + 1, hi_xz - side[0])))
+        z0 = int(rng.integers(lo_xz, max(lo_xz + 1, hi_xz - side[2])))
+        y0 = int(height[x0:x0 + side[0], z0:z0 + side[2]].max())
+        if y0 + side[1] > n - 8:
+            continue
+        height[x0:x0 + side[0], z0:z0 + side[2]] = y0 + side[1]
+        boxes.append(((x0, y0, z0), tuple(int(c) for c in side)))
+        covered += int(side.prod())
+    parts = [stratified_box(rng, tuple(c * dx for c in lo), ext, dx) for lo, ext in boxes]
+    sand = np.concatenate(parts) if parts else np.zeros((0, 3), np.float32)
+    ball = sphere(rng, (0.2 / scale, 0.12 / scale, 0.6 / scale), 0.05 / scale, dx)
+    x = np.concatenate([sand, ball]).astype(np.float32)
+    v, B, F = _rest_state(x.shape[0])
+    v[sand.shape[0]:, 0] = 20.0
+    mat = np.zeros(x.shape[0], np.uint8)
+    mat[sand.shape[0]:] = 1
+    mats = [Material(DRUCKER_PRAGER, 3.5e5, 0.3, 1600.0, dx ** 3 / 8, 30.0),
+            Material(FIXED_COROTATED, 1e7, 0.3, 2000.0, dx ** 3 / 8)]
+    return Scene("stress_%d" % x.shape[0], (n, n, n), dx, (0.0, 0.0, 0.0), (0.0, -9.8, 0.0), 2,
+                 5e-6, 200, mats, x, v, B, F, mat)
+
+
 def random_blob(seed: int, n_cells=(8, 8, 8), lo_cells=(2.5, 2.5, 2.5), ext_cells=(3, 3, 3),
                 model: int = FIXED_COROTATED, v_scale=0.5, B_scale=2.0, F_scale=0.05,
                 gravity=(0.0, 0.0, 0.0), bc_band: int = 0, dt: float = 1e-3,
