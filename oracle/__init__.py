@@ -85,6 +85,12 @@ def lib():
         L.ora_step_vjp.argtypes = [ctypes.POINTER(OraConfig), ctypes.POINTER(OraMaterial), ctypes.c_int32,
                                    ctypes.c_int64, dp, dp, dp, dp, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                    dp, dp, dp, dp, dp, dp, dp, dp, ctypes.c_void_p]
+        L.ora_step_quadratic.restype = ctypes.c_int
+        L.ora_step_quadratic.argtypes = L.ora_step.argtypes
+        L.ora_Nq.restype = ctypes.c_double
+        L.ora_Nq.argtypes = [ctypes.c_double]
+        L.ora_dNq.restype = ctypes.c_double
+        L.ora_dNq.argtypes = [ctypes.c_double]
         L.ora_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -246,6 +252,30 @@ def step(cfg: OraConfig, mats, st: State, dt: float, grids: bool = False):
     status = lib().ora_step(ctypes.byref(cfg), mats, len(mats), n, _dptr(st.x), _dptr(st.v), _dptr(st.B),
                             _dptr(st.F), mat_ptr, loge_ptr, float(dt), ctypes.byref(out))
     return status, diag, g
+
+
+def step_quadratic(cfg: OraConfig, mats, st: State, dt: float, grids: bool = False):
+    """One step of the single-grid quadratic B-spline comparison kernel, in place.
+    Returns (status, diag[32], grids-or-None) with grids = dict(m, p, v) of the one
+    grid, indexed [iz][iy][ix](,3)."""
+    n = st.n
+    dims = (cfg.n_cells[2] + 1, cfg.n_cells[1] + 1, cfg.n_cells[0] + 1)
+    out = OraOutputs()
+    diag = np.zeros(32)
+    out.diag = diag.ctypes.data
+    g = None
+    if grids:
+        g = dict(m=np.zeros(dims), p=np.zeros(dims + (3,)), v=np.zeros(dims + (3,)))
+        out.grid_m, out.grid_p, out.grid_v = g["m"].ctypes.data, g["p"].ctypes.data, g["v"].ctypes.data
+    mat_ptr = None if st.mat is None else st.mat.ctypes.data
+    loge_ptr = None if st.logE is None else st.logE.ctypes.data
+    status = lib().ora_step_quadratic(ctypes.byref(cfg), mats, len(mats), n, _dptr(st.x), _dptr(st.v), _dptr(st.B),
+                                      _dptr(st.F), mat_ptr, loge_ptr, float(dt), ctypes.byref(out))
+    return status, diag, g
+
+
+def Nq(r: float) -> float:
+    return lib().ora_Nq(float(r))
 
 
 def num_threads() -> int:

@@ -143,3 +143,47 @@ def step(sc, x, v, B, F, dt, mats=None, transfer="mls"):
             Fn[p] = dp_project(mt.E, mt.nu, mt.friction_deg, Fn[p])
     return dict(x=x + dt * vnew, v=vnew, B=Bnew, F=Fn, m=np.stack(out["m"]), p=np.stack(out["p"]),
                 vt=np.stack(out["vt"]))
+
+
+def Nq(r):
+    """Quadratic B-spline: 3/4 - r^2 (|r| < 1/2), (3/2 - |r|)^2 / 2 (1/2 <= |r| < 3/2)."""
+    a = np.abs(r)
+    return np.where(a < 0.5, 0.75 - a * a, np.where(a < 1.5, 0.5 * (1.5 - a) ** 2, 0.0))
+
+
+def step_quadratic(sc, x, v, B, F, dt, mats=None):
+    """One step of the single-grid quadratic B-spline comparison kernel against every
+    node of the grid (node i at origin + i dx).  Same return layout as `step`, with
+    m, p, vt of the one grid."""
+    mats = sc.materials if mats is None else mats
+    n_cells, dx, origin = sc.n_cells, sc.dx, np.asarray(sc.origin, np.float64)
+    N = x.shape[0]
+    mat = sc.mat if sc.mat is not None else np.zeros(N, np.uint8)
+    mp = np.array([mats[m].rho * mats[m].vol0 for m in mat])
+    V0 = np.array([mats[m].vol0 for m in mat])
+    xi = node_positions(n_cells, dx, origin, 0.0)
+    d = xi[None, :, :] - x[:, None, :]
+    wa = Nq(d / dx)
+    w = wa[..., 0] * wa[..., 1] * wa[..., 2]
+    D = np.einsum("pn,pna,pnb->pab", w, d, d)
+    Dinv = np.linalg.inv(D)
+    tau = np.stack([tau_of(mats[mat[p]].model, mats[mat[p]].E, mats[mat[p]].nu, F[p]) for p in range(N)])
+    m = w.T @ mp
+    Q = np.einsum("pab,pbc->pac", mp[:, None, None] * B - dt * V0[:, None, None] * tau, Dinv)
+    p = np.einsum("pn,pna->na", w, mp[:, None, None] * v[:, None, :] + np.einsum("pab,pnb->pna", Q, d))
+    vt = np.zeros_like(p)
+    pos = m > 0
+    vt[pos] = p[pos] / m[pos, None] + dt * np.asarray(sc.gravity)[None, :]
+    if sc.bc_band > 0:
+        cells = (xi - origin[None, :]) / dx
+        stick = np.any((cells < sc.bc_band) | (cells > np.asarray(n_cells)[None, :] - sc.bc_band), axis=1)
+        vt[stick] = 0.0
+    vnew = np.einsum("pn,na->pa", w, vt)
+    Bnew = np.einsum("pn,na,pnb->pab", w, vt, d)
+    C = np.einsum("pab,pbc->pac", Bnew, Dinv)
+    Fn = np.einsum("pab,pbc->pac", np.eye(3)[None] + dt * C, F)
+    for q in range(N):
+        mt = mats[mat[q]]
+        if mt.model == 1:
+            Fn[q] = dp_project(mt.E, mt.nu, mt.friction_deg, Fn[q])
+    return dict(x=x + dt * vnew, v=vnew, B=Bnew, F=Fn, m=m, p=p, vt=vt)

@@ -383,6 +383,22 @@ double d2K1(double x) {
     return -2.0 * kPi * std::sin(2.0 * kPi * a);
 }
 
+// Quadratic B-spline N(r) = 3/4 - r^2 for |r| < 1/2, (3/2 - |r|)^2 / 2 for 1/2 <= |r| < 3/2,
+// the single-grid kernel the paper compares the compact kernel against (27 nodes).
+double Nq(double r) {
+    const double a = std::fabs(r);
+    if (a < 0.5) return 0.75 - a * a;
+    if (a < 1.5) return 0.5 * (1.5 - a) * (1.5 - a);
+    return 0.0;
+}
+double dNq(double r) {
+    const double a = std::fabs(r);
+    const double sg = (r > 0) ? 1.0 : (r < 0 ? -1.0 : 0.0);
+    if (a < 0.5) return -2.0 * r;
+    if (a < 1.5) return -sg * (1.5 - a);
+    return 0.0;
+}
+
 struct Stencil {
     int64_t node[2][8];     // dense node index per grid, -1 when off the grid
     int32_t ijk[2][8][3];
@@ -780,6 +796,141 @@ int ora_step(const ora_config *cfg, const ora_material *mats, int32_t n_mat, int
     }
     return 0;
 }
+
+// One explicit step with the quadratic B-spline kernel on a single grid (node i at
+// origin + i dx, the 27 nodes of the 3x3x3 neighbourhood), the baseline of the
+// paper's comparison (section 6): the same MLS transfers, constitutive models,
+// grid update and return mapping as ora_step, with the sums over one grid only:
+//   m_i = sum_p w m_p,  p_i = sum_p w (m_p v_p + (m_p B_p - dt V0 tau_p) D_p^-1 d),
+//   D_p = sum_i w d d^T  (= dx^2/4 I for this kernel),
+//   v_p = sum_i w v~_i,  B_p = sum_i w v~_i d^T,  F <- (I + dt B_p D_p^-1) F.
+// Valid positions: (x - origin)/dx in [1/2, n - 1/2) on every axis (all 27 nodes on
+// the grid).  grid_m / grid_p / grid_v hold the single grid ([nodes] / [nodes][3]);
+// diag as for ora_step with the grid totals taken over the one grid.
+int ora_step_quadratic(const ora_config *cfg, const ora_material *mats, int32_t n_mat, int64_t n, double *x,
+                       double *v, double *B, double *F, const uint8_t *mat, const double *logE, double dt,
+                       ora_outputs *out) {
+    for (int64_t p = 0; p < n; ++p) {
+        for (int a = 0; a < 3; ++a) {
+            const double X = (x[3 * p + a] - cfg->origin[a]) / cfg->dx;
+            if (!(X >= 0.5 && X < cfg->n_cells[a] - 0.5)) return 3;
+        }
+        if (mat && mat[p] >= n_mat) return 1;
+    }
+    const int64_t nx = cfg->n_cells[0] + 1, ny = cfg->n_cells[1] + 1, nz = cfg->n_cells[2] + 1;
+    const int64_t nodes = nx * ny * nz;
+    std::vector<double> gm(nodes, 0.0), gp(3 * nodes, 0.0), gv(3 * nodes, 0.0);
+    double diag[32] = {0};
+    auto material = [&](int64_t p) -> const ora_material * { return &mats[mat ? mat[p] : 0]; };
+    auto mass = [&](int64_t p) { return material(p)->rho * material(p)->vol0; };
+    auto logEp = [&](int64_t p) { return logE ? logE[p] : std::nan(""); };
+    // the 27 nodes of a particle: index, weight, d = x_i - x_p
+    struct Q27 {
+        int64_t id[27];
+        double w[27], d[27][3];
+    };
+    auto stencil27 = [&](const double *xp, Q27 &q) {
+        int32_t base[3];
+        for (int a = 0; a < 3; ++a) base[a] = (int32_t)std::floor((xp[a] - cfg->origin[a]) / cfg->dx - 0.5);
+        for (int o = 0; o < 27; ++o) {
+            const int off[3] = {o % 3, (o / 3) % 3, o / 9};
+            int32_t ijk[3];
+            double w = 1.0;
+            for (int a = 0; a < 3; ++a) {
+                ijk[a] = base[a] + off[a];
+                q.d[o][a] = cfg->origin[a] + ijk[a] * cfg->dx - xp[a];
+                w *= Nq(q.d[o][a] / cfg->dx);
+            }
+            q.w[o] = w;
+            q.id[o] = node_index(cfg, ijk);
+        }
+    };
+    for (int64_t p = 0; p < n; ++p) {
+        const double m = mass(p);
+        diag[0] += m;
+        for (int a = 0; a < 3; ++a) diag[1 + a] += m * v[3 * p + a];
+    }
+    // P2G (serial scatter)
+    for (int64_t p = 0; p < n; ++p) {
+        Q27 q;
+        stencil27(x + 3 * p, q);
+        M3 D = zero3();
+        for (int o = 0; o < 27; ++o)
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) D.a[a][b] += q.w[o] * q.d[o][a] * q.d[o][b];
+        const M3 Di = inverse(D);
+        const M3 T = kirchhoff(material(p), logEp(p), load3(F + 9 * p));
+        const double m = mass(p), V0 = material(p)->vol0;
+        M3 A;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) A.a[i][j] = m * B[9 * p + 3 * i + j] - dt * V0 * T.a[i][j];
+        const M3 Qm = mul(A, Di);
+        for (int o = 0; o < 27; ++o) {
+            gm[q.id[o]] += q.w[o] * m;
+            for (int a = 0; a < 3; ++a) {
+                double qd = 0;
+                for (int b = 0; b < 3; ++b) qd += Qm.a[a][b] * q.d[o][b];
+                gp[3 * q.id[o] + a] += q.w[o] * (m * v[3 * p + a] + qd);
+            }
+        }
+    }
+    // grid update
+    for (int64_t id = 0; id < nodes; ++id) {
+        const int32_t ijk[3] = {(int32_t)(id % nx), (int32_t)((id / nx) % ny), (int32_t)(id / (nx * ny))};
+        if (gm[id] > 0.0 && !sticky(cfg, ijk, 0.0))
+            for (int a = 0; a < 3; ++a) gv[3 * id + a] = gp[3 * id + a] / gm[id] + dt * cfg->gravity[a];
+        if (gm[id] > 0.0) {
+            diag[7] += gm[id];
+            for (int a = 0; a < 3; ++a) {
+                diag[8 + a] += gp[3 * id + a];
+                diag[20 + a] += gm[id] * gv[3 * id + a];
+            }
+        }
+    }
+    (void)nz;
+    // G2P
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < n; ++p) {
+        Q27 q;
+        stencil27(x + 3 * p, q);
+        M3 D = zero3(), Bn = zero3();
+        double vp[3] = {0, 0, 0};
+        for (int o = 0; o < 27; ++o) {
+            const double *vi = &gv[3 * q.id[o]];
+            for (int a = 0; a < 3; ++a) {
+                vp[a] += q.w[o] * vi[a];
+                for (int b = 0; b < 3; ++b) {
+                    Bn.a[a][b] += q.w[o] * vi[a] * q.d[o][b];
+                    D.a[a][b] += q.w[o] * q.d[o][a] * q.d[o][b];
+                }
+            }
+        }
+        const M3 C = mul(Bn, inverse(D));
+        M3 Ip = eye3();
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) Ip.a[a][b] += dt * C.a[a][b];
+        M3 Fn = mul(Ip, load3(F + 9 * p));
+        if (material(p)->model == 1) dp_return_map(material(p), logEp(p), Fn);
+        store3(Fn, F + 9 * p);
+        store3(Bn, B + 9 * p);
+        for (int a = 0; a < 3; ++a) {
+            v[3 * p + a] = vp[a];
+            x[3 * p + a] += dt * vp[a];
+        }
+    }
+    for (int64_t p = 0; p < n; ++p)
+        for (int a = 0; a < 3; ++a) diag[26 + a] += mass(p) * v[3 * p + a];
+    if (out) {
+        if (out->grid_m) std::copy(gm.begin(), gm.end(), out->grid_m);
+        if (out->grid_p) std::copy(gp.begin(), gp.end(), out->grid_p);
+        if (out->grid_v) std::copy(gv.begin(), gv.end(), out->grid_v);
+        if (out->diag) std::copy(diag, diag + 32, out->diag);
+    }
+    return 0;
+}
+
+double ora_Nq(double r) { return Nq(r); }
+double ora_dNq(double r) { return dNq(r); }
 
 // Reverse-mode derivative (vector-Jacobian product) of one MLS step with the
 // fixed-corotated model, for the differentiable rollout: given the state entering

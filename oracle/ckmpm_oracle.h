@@ -67,6 +67,13 @@ int    ora_step_vjp(const ora_config *cfg, const ora_material *mats, int32_t n_m
                     const double *v, const double *B, const double *F, const uint8_t *mat, const double *logE,
                     double dt, const double *xb_out, const double *vb_out, const double *Bb_out,
                     const double *Fb_out, double *xb, double *vb, double *Bb, double *Fb, double *logEb);
+/* One step with the single-grid quadratic B-spline kernel (27 nodes), the
+ * comparison baseline; grids in the outputs are the one grid ([nodes], [nodes][3]). */
+int    ora_step_quadratic(const ora_config *cfg, const ora_material *mats, int32_t n_mat, int64_t n, double *x,
+                          double *v, double *B, double *F, const uint8_t *mat, const double *logE, double dt,
+                          ora_outputs *out);
+double ora_Nq(double r);
+double ora_dNq(double r);
 int    ora_num_threads(void);
 
 #ifdef __cplusplus
