@@ -61,9 +61,16 @@ typedef enum {
 enum { MPM_FIXED_COROTATED = 0, MPM_DRUCKER_PRAGER = 1 };
 enum { MPM_BC_NONE = 0, MPM_BC_STICKY = 1 };
 enum { MPM_TRANSFER_MLS = 0 };
-/* mpm_config.flags: mpm_step runs each step's G2P and the next step's P2G as one
- * kernel (section 3.2's fused transfer); same results up to summation order. */
-enum { MPM_FLAG_FUSED_G2P2G = 1 };
+/* mpm_config.flags:
+ * MPM_FLAG_FUSED_G2P2G: mpm_step runs each step's G2P and the next step's P2G as one
+ *   kernel (section 3.2's fused transfer); same results up to summation order.
+ * MPM_FLAG_QUADRATIC: the single-grid quadratic B-spline kernel (27 nodes; node i at
+ *   origin + i dx) instead of the compact kernel on the two staggered grids, the
+ *   baseline of the paper's comparison (section 6); the same MLS transfers, models
+ *   and walls.  mpm_grid_read then fills only the first grid's half.  Positions must
+ *   stay in (x - origin)/dx in [1/2, n - 1/2) (MPM_E_DOMAIN).  Not with the fused
+ *   step. */
+enum { MPM_FLAG_FUSED_G2P2G = 1, MPM_FLAG_QUADRATIC = 2 };
 
 typedef struct {
     int32_t n_cells[3];    /* cells per axis; nodes per axis and grid = n_cells + 1                */
@@ -77,7 +84,7 @@ typedef struct {
                               device memory is about 10 KiB per block (2 KiB of grid, 8 KiB of
                               sort buckets of up to 2048 particles per block)                      */
     int32_t transfer;      /* MPM_TRANSFER_MLS                                                      */
-    int32_t flags;         /* 0 or MPM_FLAG_FUSED_G2P2G                                             */
+    int32_t flags;         /* 0, MPM_FLAG_FUSED_G2P2G or MPM_FLAG_QUADRATIC                          */
 } mpm_config;
 
 typedef struct {

@@ -19,6 +19,7 @@ MPM_FIXED_COROTATED, MPM_DRUCKER_PRAGER = 0, 1
 MPM_BC_NONE, MPM_BC_STICKY = 0, 1
 MPM_TRANSFER_MLS = 0
 MPM_FLAG_FUSED_G2P2G = 1
+MPM_FLAG_QUADRATIC = 2
 MPM_STATE_PLANES = 24
 PHASES = ("sort", "p2g", "grid_update", "g2p", "g2p2g")
 
@@ -301,7 +302,7 @@ def check(status: int, what: str = "ckmpm") -> None:
 
 # --------------------------------------------------------- struct construction
 def make_config(n_cells, dx, origin=(0.0, 0.0, 0.0), gravity=(0.0, 0.0, 0.0), bc_band=0, max_particles=1,
-                max_blocks=1024, bc=None, fused=False) -> mpm_config:
+                max_blocks=1024, bc=None, fused=False, quadratic=False) -> mpm_config:
     c = mpm_config()
     for a in range(3):
         c.n_cells[a] = int(n_cells[a])
@@ -313,7 +314,7 @@ def make_config(n_cells, dx, origin=(0.0, 0.0, 0.0), gravity=(0.0, 0.0, 0.0), bc
     c.max_particles = int(max_particles)
     c.max_blocks = int(max_blocks)
     c.transfer = MPM_TRANSFER_MLS
-    c.flags = MPM_FLAG_FUSED_G2P2G if fused else 0
+    c.flags = (MPM_FLAG_FUSED_G2P2G if fused else 0) | (MPM_FLAG_QUADRATIC if quadratic else 0)
     return c
 
 
@@ -430,7 +431,7 @@ class Context:
             pass
 
 
-def scene_config(sc, max_particles=None, max_blocks=None, fused=False) -> mpm_config:
+def scene_config(sc, max_particles=None, max_blocks=None, fused=False, quadratic=False) -> mpm_config:
     """mpm_config for a scene from the `scenes` package."""
     n = sc.n if max_particles is None else max_particles
     if max_blocks is None:
@@ -438,7 +439,8 @@ def scene_config(sc, max_particles=None, max_blocks=None, fused=False) -> mpm_co
         for a in range(3):
             nb *= sc.n_cells[a] // 4 + 1
         max_blocks = min(nb, 2 * (n // 256) + 4096)
-    return make_config(sc.n_cells, sc.dx, sc.origin, sc.gravity, sc.bc_band, max(n, 1), max_blocks, fused=fused)
+    return make_config(sc.n_cells, sc.dx, sc.origin, sc.gravity, sc.bc_band, max(n, 1), max_blocks, fused=fused,
+                       quadratic=quadratic)
 
 
 def scene_materials(sc):

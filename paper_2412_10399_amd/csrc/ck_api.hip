@@ -78,7 +78,9 @@ mpm_status validate_config(const mpm_config *c, const mpm_material *m, int32_t n
     if (c->max_blocks < 1 || c->max_blocks >= (1ll << 26)) return MPM_E_INVALID;
     if (c->bc != MPM_BC_NONE && c->bc != MPM_BC_STICKY) return MPM_E_INVALID;
     if (c->bc_band < 0) return MPM_E_INVALID;
-    if (c->transfer != MPM_TRANSFER_MLS || (c->flags & ~MPM_FLAG_FUSED_G2P2G) != 0) return MPM_E_INVALID;
+    if (c->transfer != MPM_TRANSFER_MLS || (c->flags & ~(MPM_FLAG_FUSED_G2P2G | MPM_FLAG_QUADRATIC)) != 0)
+        return MPM_E_INVALID;
+    if ((c->flags & MPM_FLAG_FUSED_G2P2G) && (c->flags & MPM_FLAG_QUADRATIC)) return MPM_E_INVALID;
     for (int i = 0; i < n_mat; ++i) {
         const mpm_material &q = m[i];
         if (q.model != MPM_FIXED_COROTATED && q.model != MPM_DRUCKER_PRAGER) return MPM_E_INVALID;
@@ -107,10 +109,12 @@ void fill_geometry(const mpm_config &c, Geometry &g) {
     g.inv_dx = 1.0 / c.dx;
     g.dx = (float)c.dx;
     g.inv_dx_f = (float)(1.0 / c.dx);
-    // a node i of grid G_k (k = -1, +1) sits at (i + k/4) cells; it is inside the
-    // sticky walls when band <= i + k/4 <= n - band on every axis
+    // a node i of grid G_k (k = -1, +1) sits at (i + k/4) cells (the quadratic
+    // comparison kernel's single grid, stored as G-, at i cells); it is inside the
+    // sticky walls when band <= its position <= n - band on every axis
+    const bool quad = (c.flags & MPM_FLAG_QUADRATIC) != 0;
     for (int gi = 0; gi < 2; ++gi) {
-        const double k = gi == 0 ? -0.25 : 0.25;
+        const double k = quad ? 0.0 : (gi == 0 ? -0.25 : 0.25);
         if (c.bc == MPM_BC_STICKY && c.bc_band > 0) {
             g.stick_lo[gi] = (int)std::ceil(c.bc_band - k);
             for (int a = 0; a < 3; ++a) g.stick_hi[gi][a] = (int)std::floor(c.n_cells[a] - c.bc_band - k);
@@ -277,6 +281,7 @@ mpm_status ctx_create(const mpm_config *cfg, const mpm_material *mats, int32_t n
     DevCtx &d = ctx->d;
     std::memset(&d, 0, sizeof d);
     fill_geometry(*cfg, d.geo);
+    d.quadratic = (cfg->flags & MPM_FLAG_QUADRATIC) ? 1 : 0;
     for (int i = 0; i < n_mat; ++i) d.mats[i] = dev_material(mats[i]);
     d.n_mat = n_mat;
     d.max_blocks = (int)cfg->max_blocks;

@@ -60,6 +60,7 @@ struct Geometry {
 
 struct DevCtx {
     Geometry geo;
+    int quadratic;         // single-grid quadratic B-spline comparison kernel instead of the compact kernel
     DevMaterial mats[kMaxMaterials];
     int n_mat;
     int max_blocks;

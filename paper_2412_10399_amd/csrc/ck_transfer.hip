@@ -665,12 +665,14 @@ struct NewState {
     float x[3], v[3], B[9], tau[6];
 };
 
+__device__ __forceinline__ int g2p_finish(const DevCtx &d, const PartArgs &pa, float dt, const G2PIn &q,
+                                          const DevMaterial &M, const float (&vn)[3], const float (&Bh)[9],
+                                          const float (&Di)[9], uint32_t out, bool write_tau, NewState &ns,
+                                          CellCoord &cn, bool &placed);
+
 __device__ __forceinline__ int g2p_particle(const DevCtx &d, const PartArgs &pa, float dt, const G2PIn &q,
                                             const CellCoord &cc, int bx, int by, int bz, const float *vt, uint32_t out,
                                             bool write_tau, NewState &ns, CellCoord &cn, bool &placed) {
-    const long long S = pa.stride;
-    int sig = -1;
-    placed = false;
     const DevMaterial M = d.mats[q.mat < d.n_mat ? q.mat : 0];
     Weights w;
     axis_weights(cc, w);
@@ -731,14 +733,27 @@ __device__ __forceinline__ int g2p_particle(const DevCtx &d, const PartArgs &pa,
             Bh[3 * a + 2] += Mz[a] - S3[a] * xi[2];
         }
     }
-    float vn[3], Bn[9], C[9];
+    float vn[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) vn[a] = cref[a] + 0.5f * vs[a];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        Bh[i] *= 0.5f;
-        Bn[i] = Bh[i] * d.geo.dx;
-    }
+    for (int i = 0; i < 9; ++i) Bh[i] *= 0.5f;
+    return g2p_finish(d, pa, dt, q, M, vn, Bh, Di, out, write_tau, ns, cn, placed);
+}
+
+// The rest of G2P from the gathered velocity vn and Bh = B / dx (the affine sum in
+// cell units), with Di = dx^2 D^-1: C = B D^-1, F update, constitutive update and
+// return mapping, advection, stores of the new state, next cell key and sub code.
+__device__ __forceinline__ int g2p_finish(const DevCtx &d, const PartArgs &pa, float dt, const G2PIn &q,
+                                          const DevMaterial &M, const float (&vn)[3], const float (&Bh)[9],
+                                          const float (&Di)[9], uint32_t out, bool write_tau, NewState &ns,
+                                          CellCoord &cn, bool &placed) {
+    const long long S = pa.stride;
+    int sig = -1;
+    placed = false;
+    float Bn[9], C[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Bn[i] = Bh[i] * d.geo.dx;
     // C = B D^-1 = (dx Bh)(dx^2 Dhat)^-1 = Bh Dhat^-1 / dx
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -855,6 +870,280 @@ __global__ void __launch_bounds__(kThreads) k_g2p(DevCtx d, PartArgs pa, float d
                 CellCoord cn;
                 bool placed;
                 sig = g2p_particle(d, pa, dt, q, cc, bx, by, bz, vt, out, true, ns, cn, placed);
+            }
+            wave_stamp(d, sig, E + 1);
+        }
+        lds_barrier();
+    }
+}
+
+// ---------------------------------------------------------------- quadratic B-spline
+// The single-grid quadratic B-spline kernel the paper measures the compact kernel
+// against (section 6).  Node i sits at origin + i dx; a particle at X (cells) reaches
+// the 27 nodes base + o, base = floor(X - 1/2), o in {0,1,2}^3, with per-axis weights
+//   1/2 (3/2 - xi)^2,  3/4 - (1 - xi)^2,  1/2 (xi - 1/2)^2,   xi = X - base in [1/2, 3/2),
+// whose second moment is 1/4 on every axis: D = dx^2/4 I, so the momentum a particle
+// gives node base + o is m v + Qc (o - xi) with Qc = (m B - dt V0 tau) 4/dx.
+// The particles of block B reach nodes [4B-1, 4B+5]^3 (7^3 = 343), staged as one
+// fixed-point tile in P2G and one velocity tile in G2P; the grid lives in the G-
+// half of each pool block (the G+ half stays empty).
+struct QStaged {
+    float xi[3];
+    int lb[3];      // base node relative to 4B - 1
+    float mass, mom0[3], Qc[9];
+    bool on;
+};
+
+// Quadratic base node and fraction from the G- cell coordinates (X = c + xm - 1/4):
+// false when some node would fall off the grid.
+__device__ __forceinline__ bool quad_coords(const Geometry &g, const CellCoord &cc, int bx, int by, int bz,
+                                            float (&xi)[3], int (&lb)[3]) {
+    const int b4[3] = {4 * bx - 1, 4 * by - 1, 4 * bz - 1};
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const bool up = cc.xm[a] >= 0.75f;
+        const int base = up ? cc.c[a] : cc.c[a] - 1;
+        xi[a] = up ? cc.xm[a] - 0.25f : cc.xm[a] + 0.75f;
+        ok = ok && base >= 0 && base + 2 <= g.n[a];
+        lb[a] = base - b4[a];
+    }
+    return ok;
+}
+
+__device__ __forceinline__ void quad_weights(const float (&xi)[3], float (&w)[3][3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float u = 1.5f - xi[a], c = 1.0f - xi[a], l = xi[a] - 0.5f;
+        w[a][0] = 0.5f * u * u;
+        w[a][1] = 0.75f - c * c;
+        w[a][2] = 0.5f * l * l;
+    }
+}
+
+__device__ __forceinline__ void quad_stage(const DevCtx &d, const PartArgs &pa, int p, int bx, int by, int bz,
+                                           float dt, QStaged &r) {
+    r.on = false;
+    const long long S = pa.stride;
+    const uint32_t up = (uint32_t)p;
+    float x[3], v[3], B[9], tau[6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) x[a] = ld_at(pa.in + a * S, up);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v[a] = ld_at(pa.in + (3 + a) * S, up);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) B[a] = ld_at(pa.in + (6 + a) * S, up);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) tau[i] = ld_at(d.tau + i * d.tau_stride, up);
+    const int mi = pa.mat_in ? (int)ld_at(pa.mat_in, up) : 0;
+    const DevMaterial M = d.mats[mi < d.n_mat ? mi : 0];
+    CellCoord cc;
+    if (!cell_coord(d.geo, x, cc)) {
+        set_status(d.counters, ST_DOMAIN);
+        return;
+    }
+    if ((cc.c[0] >> 2) != bx || (cc.c[1] >> 2) != by || (cc.c[2] >> 2) != bz) {
+        set_status(d.counters, ST_STALE);
+        return;
+    }
+    if (!quad_coords(d.geo, cc, bx, by, bz, r.xi, r.lb)) {
+        set_status(d.counters, ST_DOMAIN);
+        return;
+    }
+    const float T[9] = {tau[0], tau[3], tau[4], tau[3], tau[1], tau[5], tau[4], tau[5], tau[2]};
+    const float k = dt * M.vol0, sc = 4.0f * d.geo.inv_dx_f;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) r.Qc[i] = sc * (M.mass * B[i] - k * T[i]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        r.mom0[a] = M.mass * v[a] - (r.Qc[3 * a] * r.xi[0] + r.Qc[3 * a + 1] * r.xi[1] + r.Qc[3 * a + 2] * r.xi[2]);
+    r.mass = M.mass;
+    r.on = true;
+}
+
+__device__ __forceinline__ float quad_bound(const QStaged &r) {
+    if (!r.on) return 0.0f;
+    float b = r.mass;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        b = fmaxf(b, fabsf(r.mom0[a]) + 2.0f * (fabsf(r.Qc[3 * a]) + fabsf(r.Qc[3 * a + 1]) + fabsf(r.Qc[3 * a + 2])));
+    return b;
+}
+
+constexpr int kQTY = 8, kQTZ = 66;                    // padded strides of the 7^3 tile
+constexpr int kQStride = 6 * kQTZ + 6 * kQTY + 7;     // words per channel
+constexpr int kQNodes = 343;
+
+__device__ __forceinline__ void quad_scatter(const QStaged &r, unsigned long long *tile, double S) {
+    float w[3][3];
+    quad_weights(r.xi, w);
+#pragma unroll
+    for (int oz = 0; oz < 3; ++oz)
+#pragma unroll
+        for (int oy = 0; oy < 3; ++oy) {
+            const float wyz = w[1][oy] * w[2][oz];
+#pragma unroll
+            for (int ox = 0; ox < 3; ++ox) {
+                const float wt = w[0][ox] * wyz;
+                const int t = (r.lb[0] + ox) + (r.lb[1] + oy) * kQTY + (r.lb[2] + oz) * kQTZ;
+                atomicAdd(&tile[t], to_fixed(wt * r.mass, S));
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    atomicAdd(&tile[(1 + a) * kQStride + t],
+                              to_fixed(wt * (r.mom0[a] + r.Qc[3 * a] * ox + r.Qc[3 * a + 1] * oy + r.Qc[3 * a + 2] * oz), S));
+            }
+        }
+}
+
+__global__ void __launch_bounds__(kP2GThreads, 4) k_p2g_quad(DevCtx d, PartArgs pa, float dt, int gp, int gt) {
+    __shared__ int bcnt[kBins];
+    __shared__ int bstart[kBins + 1];
+    __shared__ int wsum[kP2GThreads / 64];
+    __shared__ unsigned int bmax;
+    __shared__ int nbr[27];
+    __shared__ uint32_t ord[kMaxBlockParticles];
+    constexpr int kTileWords = 4 * kQStride;
+    constexpr int kAreaWords = kTileWords > kMaxBlockParticles / 2 ? kTileWords : kMaxBlockParticles / 2;
+    __shared__ unsigned long long area[kAreaWords];
+    uint32_t *lbuf = reinterpret_cast<uint32_t *>(area);
+    unsigned long long *tile = area;
+    const int np = (int)d.counters[C_NPB];
+    const int tid = threadIdx.x;
+    for (int base = 0; base < np; base += gridDim.x) {
+        const int r = round_block(base, np);
+        if (r < 0) continue;
+        const int vb = d.plist[r];
+        int bx, by, bz;
+        block_coords(d.geo, vb, bx, by, bz);
+        const int s = d.pstart[r];
+        const int cnt = d.pstart[r + 1] - s;
+        if (cnt > kMaxBlockParticles) continue;   // reported by the bucket scan
+        order_block(d, r, s, cnt, bcnt, bstart, wsum, lbuf, ord);
+        load_neighbours(d, gt, bx, by, bz, nbr);
+        lds_barrier();
+        for (int c0 = 0; c0 < cnt; c0 += kChunk) {
+            for (int q = tid; q < kTileWords; q += kP2GThreads) area[q] = 0ull;
+            if (tid == 0) bmax = 0u;
+            QStaged st[2];
+            float bnd = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                st[k].on = false;
+                const int j = c0 + tid + k * kP2GThreads;
+                if (j < cnt) quad_stage(d, pa, (int)ord[j], bx, by, bz, dt, st[k]);
+                bnd = fmaxf(bnd, quad_bound(st[k]));
+            }
+            lds_barrier();   // tile cleared, bmax reset
+            const double S = block_scale(bnd, &bmax);
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+                if (st[k].on) quad_scatter(st[k], tile, S);
+            lds_barrier();
+            const double inv = 1.0 / S;
+            for (int ni = tid; ni < kQNodes; ni += kP2GThreads) {
+                const int lx = ni % 7, ly = (ni / 7) % 7, lz = ni / 49;
+                const int t = lx + ly * kQTY + lz * kQTZ;
+                float val[4];
+#pragma unroll
+                for (int ch = 0; ch < 4; ++ch) val[ch] = (float)((double)(long long)tile[ch * kQStride + t] * inv);
+                if (val[0] == 0.0f && val[1] == 0.0f && val[2] == 0.0f && val[3] == 0.0f) continue;
+                const int ix = 4 * bx - 1 + lx, iy = 4 * by - 1 + ly, iz = 4 * bz - 1 + lz;
+                const long long a = pool_index(d, nbr, bx, by, bz, 0, ix, iy, iz, 0);
+                if (a < 0) {
+                    set_status(d.counters, ST_CAPACITY);
+                    continue;
+                }
+#pragma unroll
+                for (int ch = 0; ch < 4; ++ch)
+                    if (val[ch] != 0.0f) atomicAdd(&d.pool[gp][a + ch * 64], val[ch]);
+            }
+            lds_barrier();
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kThreads) k_g2p_quad(DevCtx d, PartArgs pa, float dt, int gp, int gt) {
+    __shared__ float vt[3 * kQNodes];
+    __shared__ int nbr[27];
+    const int np = (int)d.counters[C_NPB];
+    const int E = (int)d.counters[C_EPOCH];
+    const int tid = threadIdx.x;
+    for (int base = 0; base < np; base += gridDim.x) {
+        const int r = round_block(base, np);
+        if (r < 0) continue;
+        const int vb = d.plist[r];
+        int bx, by, bz;
+        block_coords(d.geo, vb, bx, by, bz);
+        const int s = d.pstart[r];
+        const int cnt = d.pstart[r + 1] - s;
+        if (cnt > kMaxBlockParticles) continue;
+        G2PIn nxt;
+        if (tid < cnt) g2p_load(d, pa, (uint32_t)(s + tid), nxt);
+        load_neighbours(d, gt, bx, by, bz, nbr);
+        lds_barrier();
+        for (int ni = tid; ni < kQNodes; ni += kThreads) {
+            const int ix = 4 * bx - 1 + ni % 7, iy = 4 * by - 1 + (ni / 7) % 7, iz = 4 * bz - 1 + ni / 49;
+            const long long a = pool_index(d, nbr, bx, by, bz, 0, ix, iy, iz, 1);
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) vt[ch * kQNodes + ni] = a >= 0 ? d.pool[gp][a + ch * 64] : 0.0f;
+        }
+        lds_barrier();
+        for (int j0 = 0; j0 < cnt; j0 += kThreads) {
+            const int j = j0 + tid;
+            const bool act = j < cnt;
+            const G2PIn q = nxt;
+            if (j + kThreads < cnt) g2p_load(d, pa, (uint32_t)(s + j + kThreads), nxt);
+            const uint32_t out = (uint32_t)(s + j);
+            CellCoord cc;
+            bool ok = act && cell_coord(d.geo, q.x, cc);
+            ok = ok && (cc.c[0] >> 2) == bx && (cc.c[1] >> 2) == by && (cc.c[2] >> 2) == bz;
+            float xi[3];
+            int lb[3];
+            const bool inside = ok && quad_coords(d.geo, cc, bx, by, bz, xi, lb);
+            int sig = -1;
+            if (act && !ok) {
+                set_status(d.counters, ST_STALE);
+                st_at(d.key, out, 0xffffffffu);
+            } else if (ok && !inside) {
+                set_status(d.counters, ST_DOMAIN);
+                st_at(d.key, out, 0xffffffffu);
+            } else if (ok) {
+                // v = sum w v~, Bh = sum w v~ (o - xi)^T, relative to the velocity c of
+                // the middle node (the weights sum to one and have zero first moment)
+                float w[3][3];
+                quad_weights(xi, w);
+                const int t1 = (lb[0] + 1) + (lb[1] + 1) * 7 + (lb[2] + 1) * 49;
+                const float cref[3] = {vt[t1], vt[kQNodes + t1], vt[2 * kQNodes + t1]};
+                float vs[3] = {0.0f, 0.0f, 0.0f}, Bh[9];
+#pragma unroll
+                for (int i = 0; i < 9; ++i) Bh[i] = 0.0f;
+#pragma unroll
+                for (int oz = 0; oz < 3; ++oz)
+#pragma unroll
+                    for (int oy = 0; oy < 3; ++oy)
+#pragma unroll
+                        for (int ox = 0; ox < 3; ++ox) {
+                            const float wt = w[0][ox] * w[1][oy] * w[2][oz];
+                            const int t = (lb[0] + ox) + (lb[1] + oy) * 7 + (lb[2] + oz) * 49;
+                            const float dxo = (float)ox - xi[0], dyo = (float)oy - xi[1], dzo = (float)oz - xi[2];
+#pragma unroll
+                            for (int a = 0; a < 3; ++a) {
+                                const float dv = wt * (vt[a * kQNodes + t] - cref[a]);
+                                vs[a] += dv;
+                                Bh[3 * a] += dv * dxo;
+                                Bh[3 * a + 1] += dv * dyo;
+                                Bh[3 * a + 2] += dv * dzo;
+                            }
+                        }
+                float vn[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) vn[a] = cref[a] + vs[a];
+                const float Di[9] = {4.0f, 0.0f, 0.0f, 0.0f, 4.0f, 0.0f, 0.0f, 0.0f, 4.0f};
+                const DevMaterial M = d.mats[q.mat < d.n_mat ? q.mat : 0];
+                NewState ns;
+                CellCoord cn;
+                bool placed;
+                sig = g2p_finish(d, pa, dt, q, M, vn, Bh, Di, out, true, ns, cn, placed);
             }
             wave_stamp(d, sig, E + 1);
         }
@@ -1079,7 +1368,10 @@ void launch_stress(const DevCtx &d, const PartArgs &pa, hipStream_t s) {
 }
 
 void launch_p2g(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, hipStream_t s) {
-    hipLaunchKernelGGL(k_p2g, dim3(particle_grid(d)), dim3(kP2GThreads), 0, s, d, pa, dt, gp, gt);
+    if (d.quadratic)
+        hipLaunchKernelGGL(k_p2g_quad, dim3(particle_grid(d)), dim3(kP2GThreads), 0, s, d, pa, dt, gp, gt);
+    else
+        hipLaunchKernelGGL(k_p2g, dim3(particle_grid(d)), dim3(kP2GThreads), 0, s, d, pa, dt, gp, gt);
 }
 
 void launch_grid_update(const DevCtx &d, float dt, const float gravity[3], int gp, int gt, hipStream_t s) {
@@ -1088,7 +1380,10 @@ void launch_grid_update(const DevCtx &d, float dt, const float gravity[3], int g
 }
 
 void launch_g2p(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, hipStream_t s) {
-    hipLaunchKernelGGL(k_g2p, dim3(particle_grid(d)), dim3(kThreads), 0, s, d, pa, dt, gp, gt);
+    if (d.quadratic)
+        hipLaunchKernelGGL(k_g2p_quad, dim3(particle_grid(d)), dim3(kThreads), 0, s, d, pa, dt, gp, gt);
+    else
+        hipLaunchKernelGGL(k_g2p, dim3(particle_grid(d)), dim3(kThreads), 0, s, d, pa, dt, gp, gt);
 }
 
 void launch_block_order(const DevCtx &d, hipStream_t s) {
