@@ -85,7 +85,9 @@ def dp_project(E, nu, phi_deg, F):
 
 
 def step(sc, x, v, B, F, dt, mats=None, transfer="mls"):
-    """One step on all nodes of both grids.  Inputs are FP64 arrays (N,3), (N,3,3);
+    """One step on all nodes of both grids, transfer "mls" (section 4.5), "apic"
+    (section 4.4, exact kernel gradients) or "pic" (section 4.3: no affine term,
+    exact gradients, B not carried).  Inputs are FP64 arrays (N,3), (N,3,3);
     returns dict(x, v, B, F, m[2,nodes], p[2,nodes,3], vt[2,nodes,3])."""
     mats = sc.materials if mats is None else mats
     n_cells, dx, origin = sc.n_cells, sc.dx, np.asarray(sc.origin, np.float64)
@@ -111,7 +113,7 @@ def step(sc, x, v, B, F, dt, mats=None, transfer="mls"):
     vts = []
     for (k, xi, d, w, gw) in grids:
         m = w.T @ mp
-        BD = np.einsum("pab,pbc->pac", B, Dinv)
+        BD = np.zeros_like(B) if transfer == "pic" else np.einsum("pab,pbc->pac", B, Dinv)
         mom = np.einsum("pn,p,pna->na", w, mp, v[:, None, :] + np.einsum("pab,pnb->pna", BD, d))
         if transfer == "mls":
             grad = np.einsum("pn,pab,pnb->pna", w, Dinv, d)
@@ -141,6 +143,8 @@ def step(sc, x, v, B, F, dt, mats=None, transfer="mls"):
         mt = mats[mat[p]]
         if mt.model == 1:
             Fn[p] = dp_project(mt.E, mt.nu, mt.friction_deg, Fn[p])
+    if transfer == "pic":
+        Bnew = np.zeros_like(Bnew)
     return dict(x=x + dt * vnew, v=vnew, B=Bnew, F=Fn, m=np.stack(out["m"]), p=np.stack(out["p"]),
                 vt=np.stack(out["vt"]))
 

@@ -625,6 +625,7 @@ int ora_step(const ora_config *cfg, const ora_material *mats, int32_t n_mat, int
     const int64_t nx = cfg->n_cells[0] + 1, ny = cfg->n_cells[1] + 1, nz = cfg->n_cells[2] + 1;
     const int64_t nodes = nx * ny * nz;
     const bool mls = (cfg->transfer == 0);
+    const bool pic = (cfg->transfer == 2);   // section 4.3: no affine term, particles carry no B
     std::vector<double> gm(2 * nodes, 0.0), gmv(6 * nodes, 0.0), gf(6 * nodes, 0.0), gv(6 * nodes, 0.0);
     double diag[32] = {0};
 
@@ -687,7 +688,7 @@ int ora_step(const ora_config *cfg, const ora_material *mats, int32_t n_mat, int
                 for (int a = 0; a < 3; ++a) {
                     double aff = 0, fa = 0;
                     for (int b = 0; b < 3; ++b) {
-                        aff += BD.a[a][b] * st.d[g][o][b];
+                        if (!pic) aff += BD.a[a][b] * st.d[g][o][b];
                         fa += T.a[a][b] * grad[b];
                     }
                     gmv[(g * nodes + id) * 3 + a] += w * m * (v[3 * p + a] + aff);
@@ -765,7 +766,7 @@ int ora_step(const ora_config *cfg, const ora_material *mats, int32_t n_mat, int
         M3 Fn = mul(A, load3(F + 9 * p));
         if (material(p)->model == 1) dp_return_map(material(p), logEp(p), Fn);
         store3(Fn, F + 9 * p);
-        store3(Bn, B + 9 * p);
+        store3(pic ? zero3() : Bn, B + 9 * p);
         for (int a = 0; a < 3; ++a) {
             v[3 * p + a] = vp[a];
             x[3 * p + a] += dt * vp[a];

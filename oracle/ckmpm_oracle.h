@@ -25,7 +25,8 @@ typedef struct {
     double origin[3];
     double gravity[3];
     int32_t bc_band;     /* sticky wall band width in cells (0 = no walls) */
-    int32_t transfer;    /* 0 = MLS-MPM (section 4.5), 1 = APIC with exact kernel gradients (section 4.4) */
+    int32_t transfer;    /* 0 = MLS-MPM (section 4.5), 1 = APIC with exact kernel gradients (section 4.4),
+                            2 = PIC (section 4.3: momentum m v only, exact kernel gradients, no B carried) */
 } ora_config;
 
 typedef struct {

@@ -23,7 +23,7 @@ CASES = [
 
 
 @pytest.mark.parametrize("case", CASES)
-@pytest.mark.parametrize("transfer", [0, 1])
+@pytest.mark.parametrize("transfer", [0, 1, 2])
 def test_oracle_matches_bruteforce(ora, case, transfer):
     sc = scenes.random_blob(**case)
     st = ora.State.from_scene(sc)
@@ -31,7 +31,7 @@ def test_oracle_matches_bruteforce(ora, case, transfer):
     dt = 1e-3
     status, diag, g = ora.step(ora.scene_config(sc, transfer), ora.scene_materials(sc), st, dt, grids=True)
     assert status == 0
-    r = bf.step(sc, x0, v0, B0, F0, dt, transfer="mls" if transfer == 0 else "apic")
+    r = bf.step(sc, x0, v0, B0, F0, dt, transfer=("mls", "apic", "pic")[transfer])
     assert _rel(st.x, r["x"]) < 1e-13
     assert _rel(st.v, r["v"]) < 1e-13
     assert _rel(st.B, r["B"]) < 1e-13

@@ -44,6 +44,20 @@ def test_momentum_conservation(ora, model, transfer, seed):
     assert np.abs(d[17:20]).max() * 1e-3 <= 1e-12 * sL
 
 
+@pytest.mark.parametrize("model", [scenes.FIXED_COROTATED, scenes.DRUCKER_PRAGER])
+def test_pic_linear_momentum_conservation(ora, model):
+    """Section 4.3 with the supplement's first theorem: the PIC transfer conserves
+    linear momentum through P2G, the grid update (no gravity, no walls) and G2P, and
+    the particles come out with no affine matrix."""
+    sc = scenes.random_blob(4, model=model, E=1e5, v_scale=1.0, B_scale=3.0, F_scale=0.1)
+    st, d, _ = _run(ora, sc, 1e-3, 2)
+    P0 = sc.materials[0].rho * sc.materials[0].vol0 * sc.v.astype(np.float64).sum(axis=0)
+    s = np.abs(P0).max()
+    for p in (d[8:11], d[20:23], d[26:29]):
+        assert np.abs(p - P0).max() <= 1e-12 * s
+    assert np.abs(st.B).max() == 0.0
+
+
 def test_momentum_conservation_detects_missing_affine_term(ora):
     """Negative control: with B set but its contribution dropped from P2G the
     angular momentum identity fails, so the test above can see such a mistake."""
