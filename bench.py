@@ -259,6 +259,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fused", action="store_true", help="fused G2P+P2G kernel from the second step on")
+    ap.add_argument("--transfer", choices=["mls", "apic", "pic"], default="mls",
+                    help="particle-grid transfer (apic and pic use exact kernel gradients)")
     ap.add_argument("--quadratic", action="store_true",
                     help="the single-grid quadratic B-spline comparison kernel instead of the compact kernel")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -305,7 +307,9 @@ def main():
         del src, dst, flush
 
     sc = scenes.sand_column()
-    ctx = ckmpm.Context(ckmpm.scene_config(sc, fused=args.fused, quadratic=args.quadratic), ckmpm.scene_materials(sc))
+    transfer = {"mls": 0, "apic": 1, "pic": 2}[args.transfer]
+    ctx = ckmpm.Context(ckmpm.scene_config(sc, fused=args.fused, quadratic=args.quadratic, transfer=transfer),
+                        ckmpm.scene_materials(sc))
     parts = ckmpm.particles_from_scene(sc, "cuda:0")
     stream = torch.cuda.current_stream()
     h = ctx.h
@@ -336,7 +340,7 @@ def main():
     dominant = max(("p2g", "g2p", "grid_update", "g2p2g"), key=lambda k: avg[k] * phase_n[ckmpm.PHASES.index(k)])
     alg_bytes = PARTICLE_BYTES.get(dominant, 0) * sc.n + GRID_BLOCK_BYTES[dominant] * ngb
     achieved = alg_bytes / (avg[dominant] * 1e-3) / 1e9
-    traffic = None if args.quadratic else measured_traffic(dominant, sc.n)
+    traffic = None if (args.quadratic or transfer) else measured_traffic(dominant, sc.n)
     step_bytes = (STEP_PARTICLE_BYTES_FUSED if args.fused else STEP_PARTICLE_BYTES) * sc.n + STEP_GRID_BLOCK_BYTES * ngb
     result = {
         "metric": "particle-steps/s at 4M particles",
@@ -354,9 +358,11 @@ def main():
         "config": {"workload": "sand_column_drucker_prager", "particles": sc.n, "grid": "256^3", "dx": sc.dx,
                    "dt": sc.dt, "ppc": 8, "active_grid_blocks": ngb,
                    "particle_blocks": int(stats.n_particle_blocks), "fused_g2p2g": bool(args.fused),
-                   "kernel": "quadratic_bspline_single_grid" if args.quadratic else "compact_dual_grid"},
+                   "kernel": "quadratic_bspline_single_grid" if args.quadratic else "compact_dual_grid",
+                   "transfer": args.transfer},
         "roofline": {"bound": "hbm",
-                     "kernel": KERNEL_SYMBOL[dominant] + ("_quad" if args.quadratic and dominant in ("p2g", "g2p") else ""),
+                     "kernel": KERNEL_SYMBOL[dominant] + ("_quad" if args.quadratic and dominant in ("p2g", "g2p") else
+                                                         "_grad" if transfer and dominant in ("p2g", "g2p") else ""),
                      "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "alg_bytes_per_launch": alg_bytes,

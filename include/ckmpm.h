@@ -60,7 +60,12 @@ typedef enum {
 
 enum { MPM_FIXED_COROTATED = 0, MPM_DRUCKER_PRAGER = 1 };
 enum { MPM_BC_NONE = 0, MPM_BC_STICKY = 1 };
-enum { MPM_TRANSFER_MLS = 0 };
+/* mpm_config.transfer: MLS-MPM (section 4.5, the hot path); APIC with the exact
+ * kernel gradient for the force and the velocity gradient (section 4.4); PIC
+ * (section 4.3: momentum m v only, exact gradients, particles carry no B — their B
+ * output is zero).  The exact-gradient transfers run only as phase kernels on the
+ * compact kernel (flags 0). */
+enum { MPM_TRANSFER_MLS = 0, MPM_TRANSFER_APIC = 1, MPM_TRANSFER_PIC = 2 };
 /* mpm_config.flags:
  * MPM_FLAG_FUSED_G2P2G: mpm_step runs each step's G2P and the next step's P2G as one
  *   kernel (section 3.2's fused transfer); same results up to summation order.
@@ -83,7 +88,7 @@ typedef struct {
     int64_t max_blocks;    /* capacity of the grid block pool (blocks of 4x4x4 nodes, both grids);
                               device memory is about 10 KiB per block (2 KiB of grid, 8 KiB of
                               sort buckets of up to 2048 particles per block)                      */
-    int32_t transfer;      /* MPM_TRANSFER_MLS                                                      */
+    int32_t transfer;      /* MPM_TRANSFER_MLS, _APIC or _PIC                                       */
     int32_t flags;         /* 0, MPM_FLAG_FUSED_G2P2G or MPM_FLAG_QUADRATIC                          */
 } mpm_config;
 

@@ -17,7 +17,7 @@ _lib = None
 MPM_OK, MPM_E_INVALID, MPM_E_OOM, MPM_E_DOMAIN, MPM_E_CAPACITY, MPM_E_NONFINITE, MPM_E_HIP, MPM_E_STALE, MPM_E_CFL = range(9)
 MPM_FIXED_COROTATED, MPM_DRUCKER_PRAGER = 0, 1
 MPM_BC_NONE, MPM_BC_STICKY = 0, 1
-MPM_TRANSFER_MLS = 0
+MPM_TRANSFER_MLS, MPM_TRANSFER_APIC, MPM_TRANSFER_PIC = 0, 1, 2
 MPM_FLAG_FUSED_G2P2G = 1
 MPM_FLAG_QUADRATIC = 2
 MPM_STATE_PLANES = 24
@@ -302,7 +302,7 @@ def check(status: int, what: str = "ckmpm") -> None:
 
 # --------------------------------------------------------- struct construction
 def make_config(n_cells, dx, origin=(0.0, 0.0, 0.0), gravity=(0.0, 0.0, 0.0), bc_band=0, max_particles=1,
-                max_blocks=1024, bc=None, fused=False, quadratic=False) -> mpm_config:
+                max_blocks=1024, bc=None, fused=False, quadratic=False, transfer=0) -> mpm_config:
     c = mpm_config()
     for a in range(3):
         c.n_cells[a] = int(n_cells[a])
@@ -313,7 +313,7 @@ def make_config(n_cells, dx, origin=(0.0, 0.0, 0.0), gravity=(0.0, 0.0, 0.0), bc
     c.bc_band = int(bc_band)
     c.max_particles = int(max_particles)
     c.max_blocks = int(max_blocks)
-    c.transfer = MPM_TRANSFER_MLS
+    c.transfer = int(transfer)
     c.flags = (MPM_FLAG_FUSED_G2P2G if fused else 0) | (MPM_FLAG_QUADRATIC if quadratic else 0)
     return c
 
@@ -431,7 +431,7 @@ class Context:
             pass
 
 
-def scene_config(sc, max_particles=None, max_blocks=None, fused=False, quadratic=False) -> mpm_config:
+def scene_config(sc, max_particles=None, max_blocks=None, fused=False, quadratic=False, transfer=0) -> mpm_config:
     """mpm_config for a scene from the `scenes` package."""
     n = sc.n if max_particles is None else max_particles
     if max_blocks is None:
@@ -440,7 +440,7 @@ def scene_config(sc, max_particles=None, max_blocks=None, fused=False, quadratic
             nb *= sc.n_cells[a] // 4 + 1
         max_blocks = min(nb, 2 * (n // 256) + 4096)
     return make_config(sc.n_cells, sc.dx, sc.origin, sc.gravity, sc.bc_band, max(n, 1), max_blocks, fused=fused,
-                       quadratic=quadratic)
+                       quadratic=quadratic, transfer=transfer)
 
 
 def scene_materials(sc):

@@ -78,9 +78,11 @@ mpm_status validate_config(const mpm_config *c, const mpm_material *m, int32_t n
     if (c->max_blocks < 1 || c->max_blocks >= (1ll << 26)) return MPM_E_INVALID;
     if (c->bc != MPM_BC_NONE && c->bc != MPM_BC_STICKY) return MPM_E_INVALID;
     if (c->bc_band < 0) return MPM_E_INVALID;
-    if (c->transfer != MPM_TRANSFER_MLS || (c->flags & ~(MPM_FLAG_FUSED_G2P2G | MPM_FLAG_QUADRATIC)) != 0)
+    if (c->transfer != MPM_TRANSFER_MLS && c->transfer != MPM_TRANSFER_APIC && c->transfer != MPM_TRANSFER_PIC)
         return MPM_E_INVALID;
+    if ((c->flags & ~(MPM_FLAG_FUSED_G2P2G | MPM_FLAG_QUADRATIC)) != 0) return MPM_E_INVALID;
     if ((c->flags & MPM_FLAG_FUSED_G2P2G) && (c->flags & MPM_FLAG_QUADRATIC)) return MPM_E_INVALID;
+    if (c->flags != 0 && c->transfer != MPM_TRANSFER_MLS) return MPM_E_INVALID;
     for (int i = 0; i < n_mat; ++i) {
         const mpm_material &q = m[i];
         if (q.model != MPM_FIXED_COROTATED && q.model != MPM_DRUCKER_PRAGER) return MPM_E_INVALID;
@@ -282,6 +284,7 @@ mpm_status ctx_create(const mpm_config *cfg, const mpm_material *mats, int32_t n
     std::memset(&d, 0, sizeof d);
     fill_geometry(*cfg, d.geo);
     d.quadratic = (cfg->flags & MPM_FLAG_QUADRATIC) ? 1 : 0;
+    d.transfer = cfg->transfer;
     for (int i = 0; i < n_mat; ++i) d.mats[i] = dev_material(mats[i]);
     d.n_mat = n_mat;
     d.max_blocks = (int)cfg->max_blocks;

@@ -61,6 +61,7 @@ struct Geometry {
 struct DevCtx {
     Geometry geo;
     int quadratic;         // single-grid quadratic B-spline comparison kernel instead of the compact kernel
+    int transfer;          // 0 MLS, 1 APIC with exact kernel gradients, 2 PIC
     DevMaterial mats[kMaxMaterials];
     int n_mat;
     int max_blocks;

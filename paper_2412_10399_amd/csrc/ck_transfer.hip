@@ -744,23 +744,20 @@ __device__ __forceinline__ int g2p_particle(const DevCtx &d, const PartArgs &pa,
 // The rest of G2P from the gathered velocity vn and Bh = B / dx (the affine sum in
 // cell units), with Di = dx^2 D^-1: C = B D^-1, F update, constitutive update and
 // return mapping, advection, stores of the new state, next cell key and sub code.
-__device__ __forceinline__ int g2p_finish(const DevCtx &d, const PartArgs &pa, float dt, const G2PIn &q,
-                                          const DevMaterial &M, const float (&vn)[3], const float (&Bh)[9],
-                                          const float (&Di)[9], uint32_t out, bool write_tau, NewState &ns,
-                                          CellCoord &cn, bool &placed) {
+// As g2p_finish, with the velocity gradient given directly: C = Cc / dx.
+__device__ __forceinline__ int g2p_finish_c(const DevCtx &d, const PartArgs &pa, float dt, const G2PIn &q,
+                                            const DevMaterial &M, const float (&vn)[3], const float (&Bh)[9],
+                                            const float (&Cc)[9], uint32_t out, bool write_tau, NewState &ns,
+                                            CellCoord &cn, bool &placed) {
     const long long S = pa.stride;
     int sig = -1;
     placed = false;
     float Bn[9], C[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) Bn[i] = Bh[i] * d.geo.dx;
-    // C = B D^-1 = (dx Bh)(dx^2 Dhat)^-1 = Bh Dhat^-1 / dx
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j2 = 0; j2 < 3; ++j2)
-            C[3 * i + j2] = d.geo.inv_dx_f *
-                            (Bh[3 * i] * Di[j2] + Bh[3 * i + 1] * Di[3 + j2] + Bh[3 * i + 2] * Di[6 + j2]);
+    for (int i = 0; i < 9; ++i) {
+        Bn[i] = Bh[i] * d.geo.dx;
+        C[i] = d.geo.inv_dx_f * Cc[i];
+    }
     // F' = (I + dt C) F  ->  H' = H + dt (C + C H)
     float Fn[9];
 #pragma unroll
@@ -823,6 +820,20 @@ __device__ __forceinline__ int g2p_finish(const DevCtx &d, const PartArgs &pa, f
     return sig;
 }
 
+// C = B D^-1 = (dx Bh)(dx^2 Dhat)^-1 = Bh Dhat^-1 / dx
+__device__ __forceinline__ int g2p_finish(const DevCtx &d, const PartArgs &pa, float dt, const G2PIn &q,
+                                          const DevMaterial &M, const float (&vn)[3], const float (&Bh)[9],
+                                          const float (&Di)[9], uint32_t out, bool write_tau, NewState &ns,
+                                          CellCoord &cn, bool &placed) {
+    float Cc[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j2 = 0; j2 < 3; ++j2)
+            Cc[3 * i + j2] = Bh[3 * i] * Di[j2] + Bh[3 * i + 1] * Di[3 + j2] + Bh[3 * i + 2] * Di[6 + j2];
+    return g2p_finish_c(d, pa, dt, q, M, vn, Bh, Cc, out, write_tau, ns, cn, placed);
+}
+
 __global__ void __launch_bounds__(kThreads) k_g2p(DevCtx d, PartArgs pa, float dt, int gp, int gt) {
     __shared__ float vt[3 * kTileNodes];
     __shared__ int nbr[27];
@@ -870,6 +881,326 @@ __global__ void __launch_bounds__(kThreads) k_g2p(DevCtx d, PartArgs pa, float d
                 CellCoord cn;
                 bool placed;
                 sig = g2p_particle(d, pa, dt, q, cc, bx, by, bz, vt, out, true, ns, cn, placed);
+            }
+            wave_stamp(d, sig, E + 1);
+        }
+        lds_barrier();
+    }
+}
+
+// ---------------------------------------------------------------- exact-gradient transfers
+// APIC (section 4.4) and PIC (section 4.3) on the two staggered grids: the stress
+// force uses the exact kernel gradient, f_i = -sum_p V0 tau grad w_ip, and G2P takes
+// the velocity gradient as 1/2 sum_k sum_i v~_i grad w^T; APIC keeps the affine
+// momentum m B D^-1 (x_i - x_p) and carries B, PIC transfers m v alone and carries no
+// B.  Per axis on grid k with fraction xi the two weights 1 - xi + s, xi - s have
+// x_p-derivatives (cos(2 pi xi) - 1)/dx and (1 - cos(2 pi xi))/dx, and the G- cosine
+// is minus the G+ one (the fractions differ by half a cell).
+struct GStaged {
+    float xm[3], sp[3], cp[3];   // G- fraction, G+ sine and cosine per axis
+    float mass, base[3], Q[9];   // affine part as in the MLS staging (Q = 0 for PIC)
+    float T[9];                  // -dt V0 tau / dx: force per unit weight gradient (cell units)
+    int c[3], oct;
+    bool on;
+};
+
+__device__ __forceinline__ void grad_stage(const DevCtx &d, const PartArgs &pa, int p, int bx, int by, int bz,
+                                           float dt, bool pic, GStaged &r) {
+    r.on = false;
+    const long long S = pa.stride;
+    const uint32_t up = (uint32_t)p;
+    float x[3], v[3], B[9], tau[6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) x[a] = ld_at(pa.in + a * S, up);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v[a] = ld_at(pa.in + (3 + a) * S, up);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) B[a] = pic ? 0.0f : ld_at(pa.in + (6 + a) * S, up);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) tau[i] = ld_at(d.tau + i * d.tau_stride, up);
+    const int mi = pa.mat_in ? (int)ld_at(pa.mat_in, up) : 0;
+    const DevMaterial M = d.mats[mi < d.n_mat ? mi : 0];
+    CellCoord cc;
+    if (!cell_coord(d.geo, x, cc)) {
+        set_status(d.counters, ST_DOMAIN);
+        return;
+    }
+    if ((cc.c[0] >> 2) != bx || (cc.c[1] >> 2) != by || (cc.c[2] >> 2) != bz) {
+        set_status(d.counters, ST_STALE);
+        return;
+    }
+    r.oct = (int)(sub_code(cc) & 7u);
+    Weights w;
+    axis_weights(cc, w);
+    float Di[9];
+    moment_inverse(cc, w, Di);
+    const float sc = d.geo.inv_dx_f;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            r.Q[3 * i + j] = sc * M.mass * (B[3 * i] * Di[j] + B[3 * i + 1] * Di[3 + j] + B[3 * i + 2] * Di[6 + j]);
+    const float Tf[9] = {tau[0], tau[3], tau[4], tau[3], tau[1], tau[5], tau[4], tau[5], tau[2]};
+    const float k = -dt * M.vol0 * sc;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) r.T[i] = k * Tf[i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        r.c[a] = cc.c[a];
+        r.xm[a] = cc.xm[a];
+        r.sp[a] = w.sp[a];
+        r.cp[a] = __builtin_amdgcn_cosf(cc.xp[a]);
+        r.base[a] = M.mass * v[a] - (r.Q[3 * a] * cc.xm[0] + r.Q[3 * a + 1] * cc.xm[1] + r.Q[3 * a + 2] * cc.xm[2]);
+    }
+    r.mass = M.mass;
+    r.on = true;
+}
+
+__device__ __forceinline__ float grad_bound(const GStaged &r) {
+    if (!r.on) return 0.0f;
+    float b = r.mass;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        b = fmaxf(b, fabsf(r.base[a]) + 1.5f * (fabsf(r.Q[3 * a]) + fabsf(r.Q[3 * a + 1]) + fabsf(r.Q[3 * a + 2])) +
+                         2.0f * (fabsf(r.T[3 * a]) + fabsf(r.T[3 * a + 1]) + fabsf(r.T[3 * a + 2])));
+    return b;
+}
+
+// Per-axis weights and x_p-derivatives (cell units) of both grids, the G+ base offset
+// and the affine momentum at each grid's base node.
+__device__ __forceinline__ void grad_axes(const GStaged &r, float (&w)[2][3][2], float (&dw)[2][3][2], int (&up)[3],
+                                          float (&m0)[2][3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        up[a] = (r.oct >> a) & 1;
+        const float xp = up[a] ? r.xm[a] - 0.5f : r.xm[a] + 0.5f;
+        w[0][a][0] = 1.0f - r.xm[a] - r.sp[a];
+        w[0][a][1] = r.xm[a] + r.sp[a];
+        w[1][a][0] = 1.0f - xp + r.sp[a];
+        w[1][a][1] = xp - r.sp[a];
+        dw[1][a][0] = r.cp[a] - 1.0f;
+        dw[1][a][1] = 1.0f - r.cp[a];
+        dw[0][a][0] = -r.cp[a] - 1.0f;
+        dw[0][a][1] = 1.0f + r.cp[a];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        m0[0][a] = r.base[a];
+        m0[1][a] = r.base[a] + ((float)up[0] - 0.5f) * r.Q[3 * a] + ((float)up[1] - 0.5f) * r.Q[3 * a + 1] +
+                   ((float)up[2] - 0.5f) * r.Q[3 * a + 2];
+    }
+}
+
+// Adds the particle's 16 contributions to the fixed-point tile (layout of k_p2g's).
+__device__ __forceinline__ void grad_scatter(const GStaged &r, int lx, int ly, int lz, unsigned long long *tile_m,
+                                             unsigned long long *tile_p, double S) {
+    float w[2][3][2], dw[2][3][2], m0[2][3];
+    int up[3];
+    grad_axes(r, w, dw, up, m0);
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+        unsigned long long *tile = g == 0 ? tile_m : tile_p;
+        const int ntile = g == 0 ? kTileMStride : kTilePStride;
+        const int t0 = g == 0 ? lz * kTZ + ly * kTY + lx : (lz + up[2]) * kTZ + (ly + up[1]) * kTY + (lx + up[0]);
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+            const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
+            const float wx = w[g][0][ox], wy = w[g][1][oy], wz = w[g][2][oz];
+            const float wt = wx * wy * wz;
+            const float gx = dw[g][0][ox] * wy * wz, gy = wx * dw[g][1][oy] * wz, gz = wx * wy * dw[g][2][oz];
+            const int t = t0 + ox + oy * kTY + oz * kTZ;
+            atomicAdd(&tile[t], to_fixed(wt * r.mass, S));
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const float mom = wt * (m0[g][a] + ox * r.Q[3 * a] + oy * r.Q[3 * a + 1] + oz * r.Q[3 * a + 2]) +
+                                  r.T[3 * a] * gx + r.T[3 * a + 1] * gy + r.T[3 * a + 2] * gz;
+                atomicAdd(&tile[(1 + a) * ntile + t], to_fixed(mom, S));
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kP2GThreads) k_p2g_grad(DevCtx d, PartArgs pa, float dt, int gp, int gt) {
+    __shared__ int bcnt[kBins];
+    __shared__ int bstart[kBins + 1];
+    __shared__ int wsum[kP2GThreads / 64];
+    __shared__ unsigned int bmax;
+    __shared__ int nbr[27];
+    __shared__ uint32_t ord[kMaxBlockParticles];
+    constexpr int kTileWords = 4 * (kTileMStride + kTilePStride);
+    constexpr int kAreaWords = kTileWords > kMaxBlockParticles / 2 ? kTileWords : kMaxBlockParticles / 2;
+    __shared__ unsigned long long area[kAreaWords];
+    uint32_t *lbuf = reinterpret_cast<uint32_t *>(area);
+    unsigned long long *tile_m = area;
+    unsigned long long *tile_p = area + 4 * kTileMStride;
+    const bool pic = d.transfer == 2;
+    const int np = (int)d.counters[C_NPB];
+    const int tid = threadIdx.x;
+    for (int base = 0; base < np; base += gridDim.x) {
+        const int r = round_block(base, np);
+        if (r < 0) continue;
+        const int vb = d.plist[r];
+        int bx, by, bz;
+        block_coords(d.geo, vb, bx, by, bz);
+        const int s = d.pstart[r];
+        const int cnt = d.pstart[r + 1] - s;
+        if (cnt > kMaxBlockParticles) continue;
+        order_block(d, r, s, cnt, bcnt, bstart, wsum, lbuf, ord);
+        load_neighbours(d, gt, bx, by, bz, nbr);
+        lds_barrier();
+        for (int c0 = 0; c0 < cnt; c0 += kChunk) {
+            for (int q = tid; q < kTileWords; q += kP2GThreads) area[q] = 0ull;
+            if (tid == 0) bmax = 0u;
+            GStaged st[2];
+            float bnd = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                st[k].on = false;
+                const int j = c0 + tid + k * kP2GThreads;
+                if (j < cnt) grad_stage(d, pa, (int)ord[j], bx, by, bz, dt, pic, st[k]);
+                bnd = fmaxf(bnd, grad_bound(st[k]));
+            }
+            lds_barrier();
+            const double S = block_scale(bnd, &bmax);
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+                if (st[k].on)
+                    grad_scatter(st[k], st[k].c[0] - 4 * bx, st[k].c[1] - 4 * by, st[k].c[2] - 4 * bz, tile_m, tile_p, S);
+            lds_barrier();
+            const double inv = 1.0 / S;
+            for (int ni = tid; ni < kTileNodes; ni += kP2GThreads) {
+                int g, ix, iy, iz;
+                tile_node(ni, bx, by, bz, g, ix, iy, iz);
+                const int lx = ix - 4 * bx + g, ly = iy - 4 * by + g, lz = iz - 4 * bz + g;
+                const unsigned long long *tb = g == 0 ? tile_m : tile_p;
+                const int cs = g == 0 ? kTileMStride : kTilePStride;
+                const int t = lx + ly * kTY + lz * kTZ;
+                float val[4];
+#pragma unroll
+                for (int ch = 0; ch < 4; ++ch) val[ch] = (float)((double)(long long)tb[ch * cs + t] * inv);
+                if (val[0] == 0.0f && val[1] == 0.0f && val[2] == 0.0f && val[3] == 0.0f) continue;
+                const long long a = pool_index(d, nbr, bx, by, bz, g, ix, iy, iz, 0);
+                if (a < 0) {
+                    set_status(d.counters, ST_CAPACITY);
+                    continue;
+                }
+#pragma unroll
+                for (int ch = 0; ch < 4; ++ch)
+                    if (val[ch] != 0.0f) atomicAdd(&d.pool[gp][a + ch * 64], val[ch]);
+            }
+            lds_barrier();
+        }
+    }
+}
+
+// G2P with the exact velocity gradient: v = 1/2 sum w v~, B = 1/2 sum w v~ d^T (APIC;
+// zero for PIC), C = 1/2 sum v~ grad w^T, all relative to the velocity of one stencil
+// node (the weights of a grid sum to one, their gradients to zero).
+__global__ void __launch_bounds__(kThreads) k_g2p_grad(DevCtx d, PartArgs pa, float dt, int gp, int gt) {
+    __shared__ float vt[3 * kTileNodes];
+    __shared__ int nbr[27];
+    const bool pic = d.transfer == 2;
+    const int np = (int)d.counters[C_NPB];
+    const int E = (int)d.counters[C_EPOCH];
+    const int tid = threadIdx.x;
+    for (int base = 0; base < np; base += gridDim.x) {
+        const int r = round_block(base, np);
+        if (r < 0) continue;
+        const int vb = d.plist[r];
+        int bx, by, bz;
+        block_coords(d.geo, vb, bx, by, bz);
+        const int s = d.pstart[r];
+        const int cnt = d.pstart[r + 1] - s;
+        if (cnt > kMaxBlockParticles) continue;
+        G2PIn nxt;
+        if (tid < cnt) g2p_load(d, pa, (uint32_t)(s + tid), nxt);
+        load_neighbours(d, gt, bx, by, bz, nbr);
+        lds_barrier();
+        for (int ni = tid; ni < kTileNodes; ni += kThreads) {
+            int g, ix, iy, iz;
+            tile_node(ni, bx, by, bz, g, ix, iy, iz);
+            const long long a = pool_index(d, nbr, bx, by, bz, g, ix, iy, iz, 1);
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) vt[ch * kTileNodes + ni] = a >= 0 ? d.pool[gp][a + ch * 64] : 0.0f;
+        }
+        lds_barrier();
+        for (int j0 = 0; j0 < cnt; j0 += kThreads) {
+            const int j = j0 + tid;
+            const bool act = j < cnt;
+            const G2PIn q = nxt;
+            if (j + kThreads < cnt) g2p_load(d, pa, (uint32_t)(s + j + kThreads), nxt);
+            const uint32_t out = (uint32_t)(s + j);
+            CellCoord cc;
+            bool ok = act && cell_coord(d.geo, q.x, cc);
+            ok = ok && (cc.c[0] >> 2) == bx && (cc.c[1] >> 2) == by && (cc.c[2] >> 2) == bz;
+            int sig = -1;
+            if (act && !ok) {
+                set_status(d.counters, ST_STALE);
+                st_at(d.key, out, 0xffffffffu);
+            } else if (ok) {
+                Weights wt;
+                axis_weights(cc, wt);
+                float cp[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) cp[a] = __builtin_amdgcn_cosf(cc.xp[a]);
+                const int tm0 = ((cc.c[2] - 4 * bz) * 5 + (cc.c[1] - 4 * by)) * 5 + (cc.c[0] - 4 * bx);
+                const int tp0 = kTileMinus + ((cc.bp[2] - 4 * bz + 1) * 6 + (cc.bp[1] - 4 * by + 1)) * 6 +
+                                (cc.bp[0] - 4 * bx + 1);
+                const float cref[3] = {vt[tm0], vt[kTileNodes + tm0], vt[2 * kTileNodes + tm0]};
+                float vs[3] = {0.0f, 0.0f, 0.0f}, Bh[9], Cc[9];
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    Bh[i] = 0.0f;
+                    Cc[i] = 0.0f;
+                }
+#pragma unroll
+                for (int g = 0; g < 2; ++g) {
+                    const float *xi = g == 0 ? cc.xm : cc.xp;
+                    const int t0 = g == 0 ? tm0 : tp0;
+                    const int sy = g == 0 ? 5 : 6, sz = g == 0 ? 25 : 36;
+                    const float(*wa)[2] = g == 0 ? wt.wm : wt.wp;
+#pragma unroll
+                    for (int o = 0; o < 8; ++o) {
+                        const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
+                        const int off[3] = {ox, oy, oz};
+                        float wv = 1.0f, gd[3];
+                        float wa3[3], dwa3[3];
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            wa3[a] = wa[a][off[a]];
+                            const float c = g == 0 ? -cp[a] : cp[a];
+                            dwa3[a] = off[a] ? 1.0f - c : c - 1.0f;
+                            wv *= wa3[a];
+                        }
+                        gd[0] = dwa3[0] * wa3[1] * wa3[2];
+                        gd[1] = wa3[0] * dwa3[1] * wa3[2];
+                        gd[2] = wa3[0] * wa3[1] * dwa3[2];
+                        const int t = t0 + ox + oy * sy + oz * sz;
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            const float dv = vt[a * kTileNodes + t] - cref[a];
+                            vs[a] += wv * dv;
+#pragma unroll
+                            for (int b = 0; b < 3; ++b) {
+                                Bh[3 * a + b] += wv * dv * ((float)off[b] - xi[b]);
+                                Cc[3 * a + b] += dv * gd[b];
+                            }
+                        }
+                    }
+                }
+                float vn[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) vn[a] = cref[a] + 0.5f * vs[a];
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    Bh[i] = pic ? 0.0f : 0.5f * Bh[i];
+                    Cc[i] *= 0.5f;
+                }
+                const DevMaterial M = d.mats[q.mat < d.n_mat ? q.mat : 0];
+                NewState ns;
+                CellCoord cn;
+                bool placed;
+                sig = g2p_finish_c(d, pa, dt, q, M, vn, Bh, Cc, out, true, ns, cn, placed);
             }
             wave_stamp(d, sig, E + 1);
         }
@@ -1370,6 +1701,8 @@ void launch_stress(const DevCtx &d, const PartArgs &pa, hipStream_t s) {
 void launch_p2g(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, hipStream_t s) {
     if (d.quadratic)
         hipLaunchKernelGGL(k_p2g_quad, dim3(particle_grid(d)), dim3(kP2GThreads), 0, s, d, pa, dt, gp, gt);
+    else if (d.transfer != 0)
+        hipLaunchKernelGGL(k_p2g_grad, dim3(particle_grid(d)), dim3(kP2GThreads), 0, s, d, pa, dt, gp, gt);
     else
         hipLaunchKernelGGL(k_p2g, dim3(particle_grid(d)), dim3(kP2GThreads), 0, s, d, pa, dt, gp, gt);
 }
@@ -1382,6 +1715,8 @@ void launch_grid_update(const DevCtx &d, float dt, const float gravity[3], int g
 void launch_g2p(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, hipStream_t s) {
     if (d.quadratic)
         hipLaunchKernelGGL(k_g2p_quad, dim3(particle_grid(d)), dim3(kThreads), 0, s, d, pa, dt, gp, gt);
+    else if (d.transfer != 0)
+        hipLaunchKernelGGL(k_g2p_grad, dim3(particle_grid(d)), dim3(kThreads), 0, s, d, pa, dt, gp, gt);
     else
         hipLaunchKernelGGL(k_g2p, dim3(particle_grid(d)), dim3(kThreads), 0, s, d, pa, dt, gp, gt);
 }

@@ -61,7 +61,7 @@ def _good():
 
 @pytest.mark.parametrize("field,value", [
     ("dx", 0.03), ("dx", -0.5), ("dx", 0.0), ("max_particles", 0), ("max_particles", 1 << 26),
-    ("max_blocks", 0), ("bc", 7), ("bc_band", -1), ("transfer", 3), ("flags", 3), ("flags", 4), ("flags", -1),
+    ("max_blocks", 0), ("bc", 7), ("bc_band", -1), ("transfer", 3), ("transfer", -1), ("flags", 3), ("flags", 4), ("flags", -1),
 ])
 def test_invalid_config_rejected_on_host(ck, field, value):
     cfg, mat = _good()
