@@ -110,6 +110,47 @@ def serve(srv, jobs, states, rate, ckmpm):
     return done, srv.step_latencies()
 
 
+def diffusion_main(args):
+    """Numerical diffusion (the paper's energy-decay comparison): the cuboid with a
+    high-frequency velocity 0.2 sin(500 z), run with the compact kernel and with the
+    quadratic B-spline kernel; kinetic, elastic and total energy every frame (5
+    steps) for 100 frames, from the read-back state."""
+    import numpy as np
+    import torch
+
+    import scenes
+    from paper_2412_10399_amd import ckmpm, diagnostics
+
+    torch.cuda.set_device(0)
+    out = {"metric": "energy retained after 100 frames", "unit": "fraction", "higher_is_better": True,
+           "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "diffusion_cuboid_224000", "grid": "256^3", "dt": 2e-5, "frames": 100,
+                      "steps_per_frame": 5, "material": "fixed corotated E=1e5 nu=0.3 rho=1000"}}
+    for name, quad in (("compact", False), ("quadratic", True)):
+        sc = scenes.diffusion_cuboid()
+        m = sc.materials[0]
+        ctx = ckmpm.Context(ckmpm.scene_config(sc, quadratic=quad), ckmpm.scene_materials(sc))
+        parts = ckmpm.particles_from_scene(sc, "cuda:0")
+        stream = torch.cuda.current_stream()
+        kin, ela = [], []
+        for frame in range(101):
+            if frame:
+                ckmpm.check(ckmpm.mpm_step(ctx.h, parts.c, sc.dt, 5, stream), "steps")
+            ckmpm.check(ckmpm.mpm_sync(ctx.h, stream), "status")
+            d = parts.read()
+            k, e = diagnostics.energies(d["v"], d["F"], m.rho * m.vol0, m.vol0, m.E, m.nu)
+            kin.append(k)
+            ela.append(e)
+        ctx.close()
+        tot = np.array(kin) + np.array(ela)
+        out[name] = {"total_energy": [float(tot[i]) for i in (0, 1, 10, 25, 50, 100)],
+                     "kinetic": [float(kin[i]) for i in (0, 1, 10, 25, 50, 100)],
+                     "elastic": [float(ela[i]) for i in (0, 1, 10, 25, 50, 100)],
+                     "frames": [0, 1, 10, 25, 50, 100], "retained": float(tot[-1] / tot[0])}
+    out["value"] = out["compact"]["retained"]
+    print(json.dumps(out), flush=True)
+
+
 def stress_main(args):
     """Stress scale: ~30.6M particles (random sand stacks and an elastic sphere at
     20 m/s) on a 1024^3 virtual grid, dt = 5e-6; two warm-up steps, then `steps`
@@ -268,6 +309,7 @@ def main():
     ap.add_argument("--serving", action="store_true", help="served-job benchmark instead of the step throughput")
     ap.add_argument("--adjoint", action="store_true", help="differentiated-rollout benchmark")
     ap.add_argument("--stress", action="store_true", help="30M-particle stress-scale benchmark")
+    ap.add_argument("--diffusion", action="store_true", help="energy decay of the compact and quadratic kernels")
     ap.add_argument("--jobs", type=int, default=256)
     ap.add_argument("--streams", type=int, default=4)
     ap.add_argument("--max-jobs", type=int, default=32)
@@ -286,6 +328,9 @@ def main():
         return
     if args.stress:
         stress_main(args)
+        return
+    if args.diffusion:
+        diffusion_main(args)
         return
 
     import torch

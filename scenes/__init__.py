@@ -210,6 +210,26 @@ def stress_scene(seed: int = 3, sand_cells: int = 3_190_000, scale: int = 1) -> 
                  5e-6, 200, mats, x, v, B, F, mat)
 
 
+def diffusion_cuboid(seed: int = 6, scale: int = 1) -> Scene:
+    """Numerical-diffusion scene: a cuboid of 20 x 10 x 140 cells (dx = 1/256) at 8 ppc
+    (224,000 particles) centred in a 256^3 grid, at rest except for the velocity
+    0.2 sin(500 z) along y (z in metres); fixed corotated, E = 1e5, nu = 0.3,
+    rho = 1000 (the material is not stated for this experiment); no gravity;
+    dt = 2e-5, 500 steps (100 frames at 10,000 frames per second).  `scale` k
+    shortens the cuboid's z extent k-fold."""
+    n = 256
+    dx = 1.0 / n
+    ext = (20, 10, max(4, 140 // scale))
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lo = tuple((n / 2 - e / 2) * dx for e in ext)
+    x = stratified_box(rng, lo, ext, dx)
+    v, B, F = _rest_state(x.shape[0])
+    v[:, 1] = (0.2 * np.sin(500.0 * x[:, 2].astype(np.float64))).astype(np.float32)
+    mats = [Material(FIXED_COROTATED, 1e5, 0.3, 1000.0, dx ** 3 / 8)]
+    return Scene("diffusion_cuboid_%d" % x.shape[0], (n, n, n), dx, (0.0, 0.0, 0.0), (0.0, 0.0, 0.0), 2,
+                 2e-5, 500, mats, x, v, B, F, np.zeros(x.shape[0], np.uint8))
+
+
 def random_blob(seed: int, n_cells=(8, 8, 8), lo_cells=(2.5, 2.5, 2.5), ext_cells=(3, 3, 3),
                 model: int = FIXED_COROTATED, v_scale=0.5, B_scale=2.0, F_scale=0.05,
                 gravity=(0.0, 0.0, 0.0), bc_band: int = 0, dt: float = 1e-3,
