@@ -267,15 +267,21 @@ __global__ void __launch_bounds__(kThreads) k_bucket_count(DevCtx d, int n, int 
             pool4[t] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
     int r[kCountPer];
+    uint16_t sb[kCountPer];
 #pragma unroll
     for (int k = 0; k < kCountPer; ++k) {
         const int i = base + tid * kCountPer + k;
         r[k] = -1;
+        sb[k] = 0;
         if (i < n) {
             const uint32_t key = d.key[i];
+            sb[k] = d.sub[i];
             if (key != 0xffffffffu) {
-                // a key whose block was not stamped this step cannot be placed
-                if (pf[key >> 6] == E) r[k] = d.prank[key >> 6];
+                // a key whose block was not stamped this step cannot be placed; the
+                // stamp and the rank are loaded together (one memory round trip)
+                const int f = pf[key >> 6];
+                const int pr = d.prank[key >> 6];
+                if (f == E) r[k] = pr;
                 else set_status(d.counters, ST_STALE);
             }
         }
@@ -323,7 +329,7 @@ __global__ void __launch_bounds__(kThreads) k_bucket_count(DevCtx d, int n, int 
         const int slot = base_of[st[k]] + (j - st[k]);
         if (slot < kMaxBlockParticles) {
             d.bucket[(size_t)r[k] * kMaxBlockParticles + slot] = (uint32_t)(base + j);
-            d.bsub[(size_t)r[k] * kMaxBlockParticles + slot] = d.sub[base + j];
+            d.bsub[(size_t)r[k] * kMaxBlockParticles + slot] = sb[k];
         }
     }
 }

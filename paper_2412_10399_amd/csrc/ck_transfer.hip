@@ -614,13 +614,14 @@ __global__ void __launch_bounds__(128) k_grid_update(DevCtx d, float dt, float g
         const bool inside = ix >= d.geo.stick_lo[g] && iy >= d.geo.stick_lo[g] && iz >= d.geo.stick_lo[g] &&
                             ix <= d.geo.stick_hi[g][0] && iy <= d.geo.stick_hi[g][1] && iz <= d.geo.stick_hi[g][2];
         float *blk = d.pool[gp] + (size_t)b * kBlockFloats + g * 256;
-        const float m = blk[l];
+        // all four channels in one memory round trip
+        const float m = blk[l], p0 = blk[64 + l], p1 = blk[128 + l], p2 = blk[192 + l];
         float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f;
         if (m > 0.0f && inside) {
             const float im = fast_rcp(m);
-            v0 = blk[64 + l] * im + dt * g0;
-            v1 = blk[128 + l] * im + dt * g1;
-            v2 = blk[192 + l] * im + dt * g2;
+            v0 = p0 * im + dt * g0;
+            v1 = p1 * im + dt * g1;
+            v2 = p2 * im + dt * g2;
         }
         blk[64 + l] = v0;
         blk[128 + l] = v1;
