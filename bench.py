@@ -265,7 +265,7 @@ def serving_main(args):
                 "job_latency_s_p50": float(np.percentile(jl, 50)), "job_latency_s_p99": float(np.percentile(jl, 99))}
 
     # one at a time: every job submitted at t = 0, one resident job
-    srv = ckmpm.Server(budget, max_jobs=1, n_streams=1, steps_per_launch=args.steps_per_launch)
+    srv = ckmpm.Server(budget, max_jobs=1, n_streams=1, steps_per_launch=args.steps_per_launch, grouped=args.grouped)
     t0 = time.perf_counter()
     done, lat = serve(srv, [dataclass_at_zero(j) for j in jobs], states, 1.0, ckmpm)
     seq = summary(done, lat, time.perf_counter() - t0)
@@ -275,11 +275,12 @@ def serving_main(args):
            "data": "synthetic", "config": {"workload": "serving_mix_%d_jobs" % len(jobs), "seed": 4,
                                            "particles_total": int(sum(st.shape[1] for _, _, st, _ in states)),
                                            "steps_per_job": jobs[0].nsteps, "steps_per_launch": args.steps_per_launch,
-                                           "streams": args.streams, "max_jobs": args.max_jobs},
+                                           "streams": args.streams, "max_jobs": args.max_jobs,
+                                           "grouped": bool(args.grouped)},
            "one_at_a_time": seq}
     for load in (0.8, 1.5):
         srv = ckmpm.Server(budget, max_jobs=args.max_jobs, n_streams=args.streams,
-                           steps_per_launch=args.steps_per_launch)
+                           steps_per_launch=args.steps_per_launch, grouped=args.grouped)
         t0 = time.perf_counter()
         done, lat = serve(srv, jobs, states, load * capacity_jobs, ckmpm)
         out["load_%.1f" % load] = summary(done, lat, time.perf_counter() - t0)
@@ -314,6 +315,8 @@ def main():
     ap.add_argument("--streams", type=int, default=4)
     ap.add_argument("--max-jobs", type=int, default=32)
     ap.add_argument("--steps-per-launch", type=int, default=10)
+    ap.add_argument("--grouped", action="store_true",
+                    help="serving: one launch per phase for all active jobs instead of per-job launches")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the step on a single MI355X; "

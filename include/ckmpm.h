@@ -216,8 +216,15 @@ typedef struct {
     int32_t max_jobs;          /* resident (admitted, unreleased) jobs at most, >= 1                   */
     int32_t n_streams;         /* HIP streams the jobs are spread over, 1..64                          */
     int32_t steps_per_launch;  /* steps per launch, even (the ping-pong buffer returns to its start)  */
-    int32_t flags;             /* reserved, 0                                                          */
+    int32_t flags;             /* 0 or MPM_SERVER_GROUPED                                              */
 } mpm_server_config;
+
+/* mpm_server_config.flags: every phase of a step runs as one launch for all active
+ * jobs (workgroup row y of each launch works on job y, the grid sized for the
+ * largest job), steps_per_launch steps per round, instead of each job launching
+ * its own kernels on its own stream.  Jobs must use the compact kernel with the MLS
+ * transfer and no config flags (else mpm_server_submit returns MPM_E_INVALID). */
+enum { MPM_SERVER_GROUPED = 1 };
 
 typedef struct {
     mpm_config cfg;            /* grid, walls and capacities of the job (max_particles >= n)           */

@@ -75,6 +75,7 @@ class mpm_job_info(ctypes.Structure):
 
 
 MPM_JOB_PENDING, MPM_JOB_ACTIVE, MPM_JOB_DONE, MPM_JOB_FAILED = range(4)
+MPM_SERVER_GROUPED = 1
 
 EXPORTS = ("mpm_create", "mpm_destroy", "mpm_p2g", "mpm_grid_update", "mpm_g2p", "mpm_step", "mpm_sync",
            "mpm_grid_read", "mpm_sort_keys", "mpm_invalidate", "mpm_get_stats", "mpm_profile_enable",
@@ -470,13 +471,14 @@ class Server:
     """RAII holder for an mpm_server handle, with torch-owned job inputs kept alive
     until the job is released."""
 
-    def __init__(self, memory_budget: int, max_jobs: int = 32, n_streams: int = 4, steps_per_launch: int = 8):
+    def __init__(self, memory_budget: int, max_jobs: int = 32, n_streams: int = 4, steps_per_launch: int = 8,
+                 grouped: bool = False):
         cfg = mpm_server_config()
         cfg.memory_budget = int(memory_budget)
         cfg.max_jobs = int(max_jobs)
         cfg.n_streams = int(n_streams)
         cfg.steps_per_launch = int(steps_per_launch)
-        cfg.flags = 0
+        cfg.flags = MPM_SERVER_GROUPED if grouped else 0
         s, h = mpm_server_create(cfg)
         check(s, "mpm_server_create")
         self.h = h

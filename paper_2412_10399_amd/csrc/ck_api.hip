@@ -362,6 +362,35 @@ mpm_status status_from_bits(unsigned int bits) {
     return MPM_OK;
 }
 
+bool group_capable(const mpm_ctx *ctx) { return ctx->cfg.flags == 0 && ctx->cfg.transfer == MPM_TRANSFER_MLS; }
+
+mpm_status group_step(mpm_ctx *ctx, mpm_particles *p, double dt, JobStep &out) {
+    const mpm_status v = validate_particles(ctx, p);
+    if (v != MPM_OK) return v;
+    if (!std::isfinite(dt) || dt < 0 || !p->state[p->current ^ 1]) return MPM_E_INVALID;
+    if ((p->id[0] == nullptr) != (p->id[1] == nullptr)) return MPM_E_INVALID;
+    if ((p->mat[0] == nullptr) != (p->mat[1] == nullptr)) return MPM_E_INVALID;
+    // the bookkeeping of one unfused step of mpm_step: sort into the next page table,
+    // P2G, update and G2P on it, G2P writing the other buffer and the next keys
+    const PartArgs pa = part_args(p, true);
+    const bool ready = ctx->next_ready == pa.in && ctx->next_n == pa.n;
+    const int t = ctx->next_table;
+    ctx->next_table = t ^ 1;
+    ctx->grid_pool = t;
+    ctx->grid_table = t;
+    out.d = ctx->d;
+    out.pa = pa;
+    out.dt = (float)dt;
+    for (int a = 0; a < 3; ++a) out.g[a] = (float)ctx->cfg.gravity[a];
+    out.table = t;
+    out.first = ready ? 0 : 1;
+    p->current ^= 1;
+    ctx->next_ready = pa.out;
+    ctx->next_n = pa.n;
+    ctx->p2g_done = nullptr;
+    return MPM_OK;
+}
+
 mpm_status check_config(const mpm_config *c, const mpm_material *m, int32_t n_mat) {
     return validate_config(c, m, n_mat);
 }

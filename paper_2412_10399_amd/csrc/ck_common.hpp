@@ -100,6 +100,20 @@ struct PartArgs {
     uint8_t *mat_out;
 };
 
+// One job's share of a step run for many jobs at once (one launch per phase, row y
+// of every grid working on job y): the job's device context and particles, its time
+// step and gravity, the page table and pool its sort builds and its P2G, update and
+// G2P use, and whether its keys, stamps and stress still have to be formed (first
+// step).
+struct JobStep {
+    DevCtx d;
+    PartArgs pa;           // in: this step's state, out: the other buffer
+    float dt;
+    float g[3];
+    int table;
+    int first;
+};
+
 // ------------------------------------------------------------------ helpers
 // Workgroup barrier that orders LDS accesses only: outstanding global stores and
 // atomics of the workgroup are not waited for.
@@ -673,5 +687,9 @@ void launch_g2p2g(const DevCtx &d, const PartArgs &pa, float dt, int gp_in, int 
                   hipStream_t s);
 void launch_zero_pool(const DevCtx &d, int gp, int gt, hipStream_t s);
 void launch_copy_keys(const DevCtx &d, uint32_t *keys, uint32_t *perm, int n, hipStream_t s);
+// Every phase of one step for `njobs` jobs (host copy `host`, the same table already
+// enqueued to `dev`), compact-kernel MLS jobs only: one launch per phase for each run
+// of consecutive entries of one size class, sized for the largest job of the run.
+void launch_step_multi(const JobStep *dev, const JobStep *host, int njobs, hipStream_t s);
 
 }  // namespace ck

@@ -25,5 +25,11 @@ int64_t ctx_device_bytes(const mpm_config &c);
 mpm_status check_config(const mpm_config *c, const mpm_material *m, int32_t n_mat);
 void geometry_of(const mpm_config &c, Geometry &g);
 DevMaterial device_material(const mpm_material &m);
+// Steps of many jobs in shared launches: whether a context can take part (compact
+// kernel, MLS transfer, no flags), and the table entry of its next step — the host
+// bookkeeping of one unfused step (page table, buffers, key readiness) is done here,
+// the launch itself by launch_step_multi.
+bool group_capable(const mpm_ctx *ctx);
+mpm_status group_step(mpm_ctx *ctx, mpm_particles *p, double dt, JobStep &out);
 
 }  // namespace ck

@@ -120,6 +120,13 @@ double seconds_since(std::chrono::steady_clock::time_point t0) {
 struct mpm_server {
     mpm_server_config cfg{};
     int device = 0;
+    // grouped mode: one launch per phase for all active jobs
+    bool grouped = false;
+    ck::JobStep *table_host = nullptr;     // pinned, max_jobs x steps_per_launch entries
+    ck::JobStep *table_dev = nullptr;
+    hipEvent_t gev[2] = {nullptr, nullptr};   // start and end of the round in flight
+    bool round_in_flight = false;
+    std::vector<std::pair<int64_t, int>> round;   // (job, steps) of the round in flight
     Arena arena;
     std::vector<hipStream_t> streams;
     hipStream_t init_stream = nullptr;
@@ -208,8 +215,8 @@ bool admit(mpm_server *srv, Job &j) {
         return true;
     }
     j.ctx = ctx;
-    j.stream = srv->next_stream;
-    srv->next_stream = (srv->next_stream + 1) % (int)srv->streams.size();
+    j.stream = srv->grouped ? 0 : srv->next_stream;   // grouped rounds run on stream 0
+    if (!srv->grouped) srv->next_stream = (srv->next_stream + 1) % (int)srv->streams.size();
     hipStream_t s = srv->streams[j.stream];
     j.parts = mpm_particles{};
     j.parts.n = n;
@@ -273,7 +280,118 @@ mpm_status launch(mpm_server *srv, Job &j) {
     return MPM_OK;
 }
 
+// Grouped mode: retire the round in flight, admit, then run the next round of every
+// active job (steps_per_launch steps, fewer for jobs that need fewer).
+mpm_status poll_grouped(mpm_server *srv, bool *progressed) {
+    bool moved = false;
+    hipStream_t s = srv->streams[0];
+    if (srv->round_in_flight) {
+        const hipError_t q = hipEventQuery(srv->gev[1]);
+        if (q != hipErrorNotReady) {
+            moved = true;
+            srv->round_in_flight = false;
+            float ms = 0.0f;
+            const bool timed = q == hipSuccess && hipEventElapsedTime(&ms, srv->gev[0], srv->gev[1]) == hipSuccess;
+            int longest = 1;
+            for (const auto &js : srv->round) longest = std::max(longest, js.second);
+            for (const auto &js : srv->round) {
+                Job &j = *srv->jobs[js.first];
+                j.in_flight = false;
+                if (q != hipSuccess) {
+                    fail(srv, j, MPM_E_HIP);
+                    continue;
+                }
+                if (timed)
+                    for (int k = 0; k < js.second; ++k) srv->step_lat.push_back(ms * 1e-3 / longest);
+                j.info.steps_done += js.second;
+                const unsigned int bits = srv->status_host[j.slot];
+                if (bits != 0) {
+                    fail(srv, j, ck::status_from_bits(bits));
+                } else if (j.info.steps_done >= j.desc.nsteps) {
+                    j.info.state = MPM_JOB_DONE;
+                    j.info.status = MPM_OK;
+                    j.info.t_done = seconds_since(srv->t0);
+                    srv->active -= 1;
+                }
+            }
+            srv->round.clear();
+        }
+    }
+    while (!srv->pending.empty() && srv->resident < srv->cfg.max_jobs) {
+        Job &j = *srv->jobs[srv->pending.front()];
+        if (!admit(srv, j)) break;
+        srv->pending.pop_front();
+        moved = true;
+    }
+    if (!srv->round_in_flight) {
+        // jobs with no steps to run finish at once
+        std::vector<Job *> run;
+        for (auto &kv : srv->jobs) {
+            Job &j = *kv.second;
+            if (j.info.state != MPM_JOB_ACTIVE || j.in_flight) continue;
+            if (j.info.steps_done >= j.desc.nsteps) {
+                j.info.state = MPM_JOB_DONE;
+                j.info.status = MPM_OK;
+                j.info.t_done = seconds_since(srv->t0);
+                srv->active -= 1;
+                moved = true;
+                continue;
+            }
+            run.push_back(&j);
+        }
+        if (!run.empty()) {
+            // largest jobs first: each step's entries then fall into contiguous size classes
+            std::stable_sort(run.begin(), run.end(), [](const Job *a, const Job *b) { return a->desc.n > b->desc.n; });
+            const int spl = srv->cfg.steps_per_launch;
+            std::vector<int> steps(run.size()), count(spl, 0);
+            size_t used = 0;
+            bool ok = hipEventRecord(srv->gev[0], s) == hipSuccess;
+            // step k of the round: entries of every job with more than k steps left
+            for (int k = 0; k < spl && ok; ++k) {
+                for (size_t r = 0; r < run.size(); ++r) {
+                    Job &j = *run[r];
+                    if (j.desc.nsteps - j.info.steps_done <= k) continue;
+                    const mpm_status st = ck::group_step(j.ctx, &j.parts, j.desc.dt, srv->table_host[used]);
+                    if (st != MPM_OK) {
+                        ok = false;
+                        break;
+                    }
+                    ++used;
+                    ++count[k];
+                    steps[r] += 1;
+                }
+            }
+            ok = ok && hipMemcpyAsync(srv->table_dev, srv->table_host, used * sizeof(ck::JobStep),
+                                      hipMemcpyHostToDevice, s) == hipSuccess;
+            size_t off = 0;
+            for (int k = 0; k < spl && ok; ++k) {
+                if (count[k] == 0) break;
+                ck::launch_step_multi(srv->table_dev + off, srv->table_host + off, count[k], s);
+                off += (size_t)count[k];
+            }
+            ok = ok && hipGetLastError() == hipSuccess;
+            for (size_t r = 0; r < run.size() && ok; ++r)
+                ok = hipMemcpyAsync(&srv->status_host[run[r]->slot], ck::ctx_status_word(run[r]->ctx),
+                                    sizeof(unsigned int), hipMemcpyDeviceToHost, s) == hipSuccess;
+            ok = ok && hipEventRecord(srv->gev[1], s) == hipSuccess;
+            if (!ok) {
+                for (Job *j : run) fail(srv, *j, MPM_E_HIP);
+            } else {
+                for (size_t r = 0; r < run.size(); ++r) {
+                    run[r]->in_flight = true;
+                    srv->round.emplace_back(run[r]->id, steps[r]);
+                }
+                srv->round_in_flight = true;
+            }
+            moved = true;
+        }
+    }
+    if (progressed) *progressed = moved;
+    return MPM_OK;
+}
+
 mpm_status poll_once(mpm_server *srv, bool *progressed) {
+    if (srv->grouped) return poll_grouped(srv, progressed);
     bool moved = false;
     // retire finished launches
     for (auto &kv : srv->jobs) {
@@ -335,7 +453,7 @@ mpm_status mpm_server_create(const mpm_server_config *cfg, mpm_server **out) {
     if (!cfg || !out) return MPM_E_INVALID;
     *out = nullptr;
     if (cfg->memory_budget <= 0 || cfg->max_jobs < 1 || cfg->n_streams < 1 || cfg->n_streams > 64 ||
-        cfg->steps_per_launch < 2 || (cfg->steps_per_launch & 1) || cfg->flags != 0)
+        cfg->steps_per_launch < 2 || (cfg->steps_per_launch & 1) || (cfg->flags & ~MPM_SERVER_GROUPED) != 0)
         return MPM_E_INVALID;
     mpm_server *srv = new (std::nothrow) mpm_server();
     if (!srv) return MPM_E_OOM;
@@ -361,6 +479,17 @@ mpm_status mpm_server_create(const mpm_server_config *cfg, mpm_server **out) {
         return MPM_E_HIP;
     }
     std::memset(srv->status_host, 0, sizeof(unsigned int) * (size_t)cfg->max_jobs);
+    srv->grouped = (cfg->flags & MPM_SERVER_GROUPED) != 0;
+    if (srv->grouped) {
+        const size_t entries = (size_t)cfg->max_jobs * (size_t)cfg->steps_per_launch;
+        ok = hipHostMalloc((void **)&srv->table_host, entries * sizeof(ck::JobStep), hipHostMallocDefault) == hipSuccess;
+        ok = ok && hipMalloc((void **)&srv->table_dev, entries * sizeof(ck::JobStep)) == hipSuccess;
+        for (int k = 0; ok && k < 2; ++k) ok = hipEventCreate(&srv->gev[k]) == hipSuccess;
+        if (!ok) {
+            (void)mpm_server_destroy(srv);
+            return MPM_E_HIP;
+        }
+    }
     *out = srv;
     return MPM_OK;
 }
@@ -380,6 +509,10 @@ mpm_status mpm_server_destroy(mpm_server *srv) {
     for (hipStream_t s : srv->streams) (void)hipStreamDestroy(s);
     if (srv->init_stream) (void)hipStreamDestroy(srv->init_stream);
     if (srv->status_host) (void)hipHostFree(srv->status_host);
+    if (srv->table_host) (void)hipHostFree(srv->table_host);
+    if (srv->table_dev) (void)hipFree(srv->table_dev);
+    for (hipEvent_t e : srv->gev)
+        if (e) (void)hipEventDestroy(e);
     srv->arena.release();
     delete srv;
     return MPM_OK;
@@ -391,6 +524,7 @@ mpm_status mpm_server_submit(mpm_server *srv, const mpm_job_desc *job, int64_t *
     if (!(job->dt >= 0.0) || !(job->dt < 1e30)) return MPM_E_INVALID;
     if ((reinterpret_cast<uintptr_t>(job->state) & 3u) != 0) return MPM_E_INVALID;
     if (job->n_mat < 1 || job->n_mat > ck::kMaxMaterials) return MPM_E_INVALID;
+    if (srv->grouped && (job->cfg.flags != 0 || job->cfg.transfer != MPM_TRANSFER_MLS)) return MPM_E_INVALID;
     const int64_t fp = mpm_footprint(&job->cfg, job->n);
     if (fp <= 0) return MPM_E_INVALID;
     if ((size_t)fp > srv->arena.size()) return MPM_E_CAPACITY;
@@ -428,7 +562,9 @@ mpm_status mpm_server_drain(mpm_server *srv) {
         if (st != MPM_OK) return st;
         if (moved) continue;
         // nothing to do until a launch ends: block on the oldest one in flight
+        if (srv->grouped && srv->round_in_flight) (void)hipEventSynchronize(srv->gev[1]);
         for (auto &kv : srv->jobs) {
+            if (srv->grouped) break;
             Job &j = *kv.second;
             if (j.info.state == MPM_JOB_ACTIVE && j.in_flight) {
                 (void)hipEventSynchronize(srv->slots[j.slot].ev[j.ev_cur]);

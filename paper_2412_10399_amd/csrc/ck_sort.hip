@@ -12,6 +12,8 @@
 // position, so the resulting permutation is deterministic and exact.
 #include "ck_common.hpp"
 
+#include <algorithm>
+
 namespace ck {
 
 namespace {
@@ -33,7 +35,7 @@ __device__ __forceinline__ void stamp_blocks(const DevCtx &d, int bx, int by, in
             for (int x = max(bx - 1, 0); x <= min(bx + 1, g.NB[0] - 1); ++x) gf[vblock_id(g, x, y, z)] = epoch;
 }
 
-__global__ void __launch_bounds__(kThreads) k_flag_keys(DevCtx d, PartArgs pa, int epoch_offset) {
+__device__ __forceinline__ void b_flag_keys(const DevCtx &d, const PartArgs &pa, int epoch_offset) {
     const int i = blockIdx.x * kThreads + threadIdx.x;
     const int epoch = (int)d.counters[C_EPOCH] + epoch_offset;
     bool ok = i < pa.n;
@@ -54,6 +56,15 @@ __global__ void __launch_bounds__(kThreads) k_flag_keys(DevCtx d, PartArgs pa, i
     d.sub[i] = (uint16_t)sub_code(cc);
     // one stamping lane per run of equal blocks (particles mostly arrive sorted)
     if ((threadIdx.x & 63) == 0 || prev != vb) stamp_blocks(d, cc.c[0] >> 2, cc.c[1] >> 2, cc.c[2] >> 2, epoch);
+}
+
+__global__ void __launch_bounds__(kThreads) k_flag_keys(DevCtx d, PartArgs pa, int epoch_offset) { b_flag_keys(d, pa, epoch_offset); }
+
+// one launch for many jobs: workgroup row y runs job y
+__global__ void __launch_bounds__(kThreads) k_flag_keys_multi(const JobStep *__restrict__ jobs) {
+    const JobStep &J = jobs[blockIdx.y];
+    if (!J.first) return;
+    b_flag_keys(J.d, J.pa, 1);
 }
 
 __global__ void k_clear_flags(DevCtx d) {
@@ -92,7 +103,7 @@ __device__ __forceinline__ void wg_sum2(int &a, int &b, int *sh) {
 
 constexpr int kPerThread = kCompactChunk / kThreads;   // 4 virtual blocks per thread
 
-__global__ void __launch_bounds__(kThreads) k_compact_count(DevCtx d) {
+__device__ __forceinline__ void b_compact_count(const DevCtx &d) {
     __shared__ int sh[16];
     const int E = (int)d.counters[C_EPOCH] + 1;
     const int *pf = stamps(d.pflag, d.nbv, E);
@@ -112,6 +123,15 @@ __global__ void __launch_bounds__(kThreads) k_compact_count(DevCtx d) {
         d.chunk_p[blockIdx.x] = cp;
         d.chunk_g[blockIdx.x] = cg;
     }
+}
+
+__global__ void __launch_bounds__(kThreads) k_compact_count(DevCtx d) { b_compact_count(d); }
+
+// one launch for many jobs: workgroup row y runs job y
+__global__ void __launch_bounds__(kThreads) k_compact_count_multi(const JobStep *__restrict__ jobs) {
+    const JobStep &J = jobs[blockIdx.y];
+    if ((long long)blockIdx.x * kCompactChunk >= J.d.nbv) return;
+    b_compact_count(J.d);
 }
 
 // Exclusive scan of `n` ints in place by one workgroup of 1024 threads; returns the total.
@@ -153,7 +173,7 @@ __device__ int wg_scan_inplace(int *data, int n, int *sh) {
     return total;
 }
 
-__global__ void __launch_bounds__(1024) k_compact_scan(DevCtx d, int nchunks, int table) {
+__device__ __forceinline__ void b_compact_scan(const DevCtx &d, int nchunks, int table) {
     __shared__ int sh[32];
     const int np = wg_scan_inplace<1024>(d.chunk_p, nchunks, sh);
     const int ng = wg_scan_inplace<1024>(d.chunk_g, nchunks, sh);
@@ -165,6 +185,14 @@ __global__ void __launch_bounds__(1024) k_compact_scan(DevCtx d, int nchunks, in
         d.counters[C_MAXPB] = 0u;
         d.counters[C_TOTAL] = 0u;
     }
+}
+
+__global__ void __launch_bounds__(1024) k_compact_scan(DevCtx d, int nchunks, int table) { b_compact_scan(d, nchunks, table); }
+
+// one launch for many jobs: workgroup row y runs job y
+__global__ void __launch_bounds__(1024) k_compact_scan_multi(const JobStep *__restrict__ jobs) {
+    const JobStep &J = jobs[blockIdx.y];
+    b_compact_scan(J.d, (int)((J.d.nbv + kCompactChunk - 1) / kCompactChunk), J.table);
 }
 
 // Workgroup exclusive scan of one int per thread (256 threads); returns the total.
@@ -191,7 +219,7 @@ __device__ __forceinline__ int wg_excl_scan(int x, int &excl, int *sh) {
     return tot;
 }
 
-__global__ void __launch_bounds__(kThreads) k_compact_emit(DevCtx d, int table) {
+__device__ __forceinline__ void b_compact_emit(const DevCtx &d, int table) {
     __shared__ int sh[8];
     const int E = (int)d.counters[C_EPOCH];
     const int *pf = stamps(d.pflag, d.nbv, E);
@@ -242,6 +270,15 @@ __global__ void __launch_bounds__(kThreads) k_compact_emit(DevCtx d, int table) 
     (void)gtot;
 }
 
+__global__ void __launch_bounds__(kThreads) k_compact_emit(DevCtx d, int table) { b_compact_emit(d, table); }
+
+// one launch for many jobs: workgroup row y runs job y
+__global__ void __launch_bounds__(kThreads) k_compact_emit_multi(const JobStep *__restrict__ jobs) {
+    const JobStep &J = jobs[blockIdx.y];
+    if ((long long)blockIdx.x * kCompactChunk >= J.d.nbv) return;
+    b_compact_emit(J.d, J.table);
+}
+
 // Each particle takes a slot in its block's bucket and writes its index there.
 // Particles arrive nearly sorted (the previous G2P wrote them in block order), so
 // a workgroup's 1024 consecutive particles span few blocks: slots are ranked
@@ -251,7 +288,7 @@ __global__ void __launch_bounds__(kThreads) k_compact_emit(DevCtx d, int table) 
 constexpr int kCountPer = 4;                       // consecutive particles per thread
 constexpr int kCountTile = kThreads * kCountPer;   // particles per workgroup
 
-__global__ void __launch_bounds__(kThreads) k_bucket_count(DevCtx d, int n, int zero_pool, int zero_table) {
+__device__ __forceinline__ void b_bucket_count(const DevCtx &d, int n, int zero_pool, int zero_table) {
     __shared__ int rblk[kCountTile];   // particle block rank of each particle of the tile (-1: skipped)
     __shared__ int base_of[kCountTile];
     __shared__ int wmax[kThreads / 64];
@@ -334,9 +371,17 @@ __global__ void __launch_bounds__(kThreads) k_bucket_count(DevCtx d, int n, int 
     }
 }
 
+__global__ void __launch_bounds__(kThreads) k_bucket_count(DevCtx d, int n, int zero_pool, int zero_table) { b_bucket_count(d, n, zero_pool, zero_table); }
+
+// one launch for many jobs: workgroup row y runs job y
+__global__ void __launch_bounds__(kThreads) k_bucket_count_multi(const JobStep *__restrict__ jobs) {
+    const JobStep &J = jobs[blockIdx.y];
+    b_bucket_count(J.d, J.pa.n, J.table, J.table);
+}
+
 // Exclusive scan of the bucket sizes into the first sorted position of every
 // particle block (one workgroup; sizes staged through LDS in chunks).
-__global__ void __launch_bounds__(1024) k_bucket_scan(DevCtx d) {
+__device__ __forceinline__ void b_bucket_scan(const DevCtx &d) {
     constexpr int kChunk = 8192;
     __shared__ int buf[kChunk];
     __shared__ int wsum[16];
@@ -398,6 +443,14 @@ __global__ void __launch_bounds__(1024) k_bucket_scan(DevCtx d) {
     }
 }
 
+__global__ void __launch_bounds__(1024) k_bucket_scan(DevCtx d) { b_bucket_scan(d); }
+
+// one launch for many jobs: workgroup row y runs job y
+__global__ void __launch_bounds__(1024) k_bucket_scan_multi(const JobStep *__restrict__ jobs) {
+    const JobStep &J = jobs[blockIdx.y];
+    b_bucket_scan(J.d);
+}
+
 }  // namespace
 
 void launch_flag_keys(const DevCtx &d, const PartArgs &pa, int epoch_offset, hipStream_t s) {
@@ -414,6 +467,22 @@ void launch_compact(const DevCtx &d, int table, hipStream_t s) {
     hipLaunchKernelGGL(k_compact_count, dim3(nchunks), dim3(kThreads), 0, s, d);
     hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, s, d, nchunks, table);
     hipLaunchKernelGGL(k_compact_emit, dim3(nchunks), dim3(kThreads), 0, s, d, table);
+}
+
+void launch_sort_multi(const JobStep *dev, const JobStep *host, int njobs, hipStream_t s) {
+    int flag_grid = 0, chunks = 1, tiles = 1024;
+    for (int j = 0; j < njobs; ++j) {
+        const JobStep &J = host[j];
+        if (J.first) flag_grid = std::max(flag_grid, (J.pa.n + kThreads - 1) / kThreads);
+        chunks = std::max(chunks, (int)((J.d.nbv + kCompactChunk - 1) / kCompactChunk));
+        tiles = std::max(tiles, (J.pa.n + kCountTile - 1) / kCountTile);
+    }
+    if (flag_grid > 0) hipLaunchKernelGGL(k_flag_keys_multi, dim3(flag_grid, njobs), dim3(kThreads), 0, s, dev);
+    hipLaunchKernelGGL(k_compact_count_multi, dim3(chunks, njobs), dim3(kThreads), 0, s, dev);
+    hipLaunchKernelGGL(k_compact_scan_multi, dim3(1, njobs), dim3(1024), 0, s, dev);
+    hipLaunchKernelGGL(k_compact_emit_multi, dim3(chunks, njobs), dim3(kThreads), 0, s, dev);
+    hipLaunchKernelGGL(k_bucket_count_multi, dim3(tiles, njobs), dim3(kThreads), 0, s, dev);
+    hipLaunchKernelGGL(k_bucket_scan_multi, dim3(1, njobs), dim3(1024), 0, s, dev);
 }
 
 void launch_bucket(const DevCtx &d, int n, int zero_pool, int zero_table, hipStream_t s) {

@@ -11,6 +11,8 @@
 // reached through a page table indexed by virtual block id.
 #include "ck_common.hpp"
 
+#include <algorithm>
+
 namespace ck {
 
 namespace {
@@ -186,7 +188,7 @@ __global__ void __launch_bounds__(kThreads) k_block_sort(DevCtx d) {
 // ---------------------------------------------------------------- stress
 // Kirchhoff stress of every particle of the current buffer, for a P2G that does not
 // follow a G2P of this context (first step, or positions changed by the caller).
-__global__ void __launch_bounds__(kThreads) k_stress(DevCtx d, PartArgs pa) {
+__device__ __forceinline__ void b_stress(const DevCtx &d, const PartArgs &pa) {
     const int p = blockIdx.x * kThreads + threadIdx.x;
     if (p >= pa.n) return;
     const long long S = pa.stride;
@@ -199,6 +201,15 @@ __global__ void __launch_bounds__(kThreads) k_stress(DevCtx d, PartArgs pa) {
     kirchhoff(M, H, tau);
 #pragma unroll
     for (int i = 0; i < 6; ++i) d.tau[i * d.tau_stride + p] = tau[i];
+}
+
+__global__ void __launch_bounds__(kThreads) k_stress(DevCtx d, PartArgs pa) { b_stress(d, pa); }
+
+// one launch for many jobs: workgroup row y runs job y
+__global__ void __launch_bounds__(kThreads) k_stress_multi(const JobStep *__restrict__ jobs) {
+    const JobStep &J = jobs[blockIdx.y];
+    if (!J.first) return;
+    b_stress(J.d, J.pa);
 }
 
 // ---------------------------------------------------------------- P2G
@@ -522,7 +533,7 @@ __device__ __forceinline__ double block_scale(float bnd, unsigned int *bmax) {
 // Four waves per SIMD (at most 128 VGPRs, a few spilled): the LDS of four
 // workgroups fits one CU, and the extra workgroup hides more of the load and LDS
 // latency than the spills cost (about 5% faster than three).
-__global__ void __launch_bounds__(kP2GThreads, 4) k_p2g(DevCtx d, PartArgs pa, float dt, int gp, int gt) {
+__device__ __forceinline__ void b_p2g(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt) {
     __shared__ int bcnt[kBins];                 // counts, then placement cursors
     __shared__ int bstart[kBins + 1];
     __shared__ int wsum[kP2GThreads / 64];
@@ -599,10 +610,18 @@ __global__ void __launch_bounds__(kP2GThreads, 4) k_p2g(DevCtx d, PartArgs pa, f
     }
 }
 
+__global__ void __launch_bounds__(kP2GThreads, 4) k_p2g(DevCtx d, PartArgs pa, float dt, int gp, int gt) { b_p2g(d, pa, dt, gp, gt); }
+
+// one launch for many jobs: workgroup row y runs job y
+__global__ void __launch_bounds__(kP2GThreads, 4) k_p2g_multi(const JobStep *__restrict__ jobs) {
+    const JobStep &J = jobs[blockIdx.y];
+    b_p2g(J.d, J.pa, J.dt, J.table, J.table);
+}
+
 // ---------------------------------------------------------------- grid update
 // Section 4.3 grid update on each grid: m v~ = m v + dt f (the stress impulse is
 // already in the momentum), plus gravity; v~ = 0 where m = 0 and on wall nodes.
-__global__ void __launch_bounds__(128) k_grid_update(DevCtx d, float dt, float g0, float g1, float g2, int gp, int gt) {
+__device__ __forceinline__ void b_grid_update(const DevCtx &d, float dt, float g0, float g1, float g2, int gp, int gt) {
     const int ng = (int)d.counters[ngb_slot(gt)];
     const int t = threadIdx.x;
     const int g = t >> 6, l = t & 63;
@@ -627,6 +646,14 @@ __global__ void __launch_bounds__(128) k_grid_update(DevCtx d, float dt, float g
         blk[128 + l] = v1;
         blk[192 + l] = v2;
     }
+}
+
+__global__ void __launch_bounds__(128) k_grid_update(DevCtx d, float dt, float g0, float g1, float g2, int gp, int gt) { b_grid_update(d, dt, g0, g1, g2, gp, gt); }
+
+// one launch for many jobs: workgroup row y runs job y
+__global__ void __launch_bounds__(128) k_grid_update_multi(const JobStep *__restrict__ jobs) {
+    const JobStep &J = jobs[blockIdx.y];
+    b_grid_update(J.d, J.dt, J.g[0], J.g[1], J.g[2], J.table, J.table);
 }
 
 // ---------------------------------------------------------------- G2P
@@ -835,7 +862,7 @@ __device__ __forceinline__ int g2p_finish(const DevCtx &d, const PartArgs &pa, f
     return g2p_finish_c(d, pa, dt, q, M, vn, Bh, Cc, out, write_tau, ns, cn, placed);
 }
 
-__global__ void __launch_bounds__(kThreads) k_g2p(DevCtx d, PartArgs pa, float dt, int gp, int gt) {
+__device__ __forceinline__ void b_g2p(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt) {
     __shared__ float vt[3 * kTileNodes];
     __shared__ int nbr[27];
     const int np = (int)d.counters[C_NPB];
@@ -887,6 +914,14 @@ __global__ void __launch_bounds__(kThreads) k_g2p(DevCtx d, PartArgs pa, float d
         }
         lds_barrier();
     }
+}
+
+__global__ void __launch_bounds__(kThreads) k_g2p(DevCtx d, PartArgs pa, float dt, int gp, int gt) { b_g2p(d, pa, dt, gp, gt); }
+
+// one launch for many jobs: workgroup row y runs job y
+__global__ void __launch_bounds__(kThreads) k_g2p_multi(const JobStep *__restrict__ jobs) {
+    const JobStep &J = jobs[blockIdx.y];
+    b_g2p(J.d, J.pa, J.dt, J.table, J.table);
 }
 
 // ---------------------------------------------------------------- exact-gradient transfers
@@ -1738,6 +1773,48 @@ void launch_zero_pool(const DevCtx &d, int gp, int gt, hipStream_t s) {
 
 void launch_grid_export(const DevCtx &d, float *m, float *vec, int gp, int gt, hipStream_t s) {
     hipLaunchKernelGGL(k_grid_export, dim3(4096), dim3(256), 0, s, d, m, vec, gp, gt);
+}
+
+void launch_sort_multi(const JobStep *dev, const JobStep *host, int njobs, hipStream_t s);
+
+namespace {
+
+// Launches for the jobs of one size class (every grid sized for the largest of them).
+void launch_step_run(const JobStep *dev, const JobStep *host, int njobs, hipStream_t s) {
+    launch_sort_multi(dev, host, njobs, s);
+    int stress_grid = 0, pgrid = 8, ugrid = 1;
+    for (int j = 0; j < njobs; ++j) {
+        const JobStep &J = host[j];
+        if (J.first) stress_grid = std::max(stress_grid, (J.pa.n + kThreads - 1) / kThreads);
+        pgrid = std::max(pgrid, particle_grid(J.d));
+        ugrid = std::max(ugrid, J.d.max_blocks < 16384 ? J.d.max_blocks : 16384);
+    }
+    if (stress_grid > 0) hipLaunchKernelGGL(k_stress_multi, dim3(stress_grid, njobs), dim3(kThreads), 0, s, dev);
+    hipLaunchKernelGGL(k_p2g_multi, dim3(pgrid, njobs), dim3(kP2GThreads), 0, s, dev);
+    hipLaunchKernelGGL(k_grid_update_multi, dim3(ugrid, njobs), dim3(128), 0, s, dev);
+    hipLaunchKernelGGL(k_g2p_multi, dim3(pgrid, njobs), dim3(kThreads), 0, s, dev);
+}
+
+int size_class(const JobStep &J) {
+    const int w = std::max(particle_grid(J.d), (J.pa.n + kThreads - 1) / kThreads);
+    int c = 0;
+    while ((1 << c) < w) ++c;
+    return c / 2;   // classes four-fold apart: at most 3/4 of a launch's rows are idle
+}
+
+}  // namespace
+
+void launch_step_multi(const JobStep *dev, const JobStep *host, int njobs, hipStream_t s) {
+    // consecutive entries of one size class share launches, so that small jobs do not
+    // run empty workgroups sized for the largest job of the round
+    int i0 = 0;
+    while (i0 < njobs) {
+        int i1 = i0 + 1;
+        const int c = size_class(host[i0]);
+        while (i1 < njobs && size_class(host[i1]) == c) ++i1;
+        launch_step_run(dev + i0, host + i0, i1 - i0, s);
+        i0 = i1;
+    }
 }
 
 void launch_copy_keys(const DevCtx &d, uint32_t *keys, uint32_t *perm, int n, hipStream_t s) {

@@ -69,13 +69,16 @@ def _compare(a, b):
     assert np.array_equal(a["id"], b["id"])
 
 
+@pytest.mark.parametrize("grouped", [False, True])
 @pytest.mark.parametrize("spl", [2, 4])
-def test_jobs_alone_equal_jobs_in_the_mix(spl):
+def test_jobs_alone_equal_jobs_in_the_mix(spl, grouped):
+    """Per-job launches on several streams, or (grouped) one launch per phase for all
+    active jobs."""
     from paper_2412_10399_amd import ckmpm
     jobs = _jobs()
     nsteps = 12
     ref = [_alone(sc, nsteps) for sc in jobs]
-    srv = ckmpm.Server(memory_budget=1 << 30, max_jobs=8, n_streams=3, steps_per_launch=spl)
+    srv = ckmpm.Server(memory_budget=1 << 30, max_jobs=8, n_streams=3, steps_per_launch=spl, grouped=grouped)
     jids = [srv.submit_scene(sc, nsteps) for sc in jobs]
     got, infos = _collect(srv, jids)
     for k, j in enumerate(jids):
@@ -88,14 +91,15 @@ def test_jobs_alone_equal_jobs_in_the_mix(spl):
     srv.close()
 
 
-def test_low_memory_budget_admits_one_job_at_a_time():
+@pytest.mark.parametrize("grouped", [False, True])
+def test_low_memory_budget_admits_one_job_at_a_time(grouped):
     from paper_2412_10399_amd import ckmpm
     jobs = _jobs()[:4]
     nsteps = 6
     fps = [ckmpm.mpm_footprint(ckmpm.job_config(sc), sc.n) for sc in jobs]
     budget = max(fps) + min(fps) // 2          # never two of these jobs at once
     ref = [_alone(sc, nsteps) for sc in jobs]
-    srv = ckmpm.Server(memory_budget=budget, max_jobs=8, n_streams=2, steps_per_launch=2)
+    srv = ckmpm.Server(memory_budget=budget, max_jobs=8, n_streams=2, steps_per_launch=2, grouped=grouped)
     jids = [srv.submit_scene(sc, nsteps) for sc in jobs]
     got, infos = _collect(srv, jids)
     admits = [infos[j][3] for j in jids]
@@ -128,4 +132,32 @@ def test_job_larger_than_budget_is_refused_and_empty_job_finishes():
     out = srv.read(j)
     assert np.array_equal(out["x"], sc.x) and np.array_equal(out["v"], sc.v)
     srv.release(j)
+    srv.close()
+
+
+def test_grouped_server_uneven_steps_and_refusals():
+    """Grouped rounds with jobs of different step counts (each round runs a job only
+    for the steps it has left), a zero-step job, and refusal of a job the grouped
+    launches cannot run (the quadratic comparison kernel)."""
+    import torch
+    from paper_2412_10399_amd import ckmpm
+    jobs = _jobs()[:3]
+    steps = [6, 10, 0]
+    ref = [_alone(sc, k) if k else None for sc, k in zip(jobs, steps)]
+    srv = ckmpm.Server(memory_budget=1 << 30, max_jobs=8, n_streams=1, steps_per_launch=4, grouped=True)
+    jids = [srv.submit_scene(sc, k) for sc, k in zip(jobs, steps)]
+    got, infos = _collect(srv, jids)
+    for k, j in enumerate(jids):
+        assert infos[j][0] == ckmpm.MPM_JOB_DONE and infos[j][5] == steps[k]
+        if steps[k]:
+            _compare(got[j], ref[k])
+        else:
+            assert np.array_equal(got[j]["x"], jobs[k].x)
+    sc = jobs[0]
+    cfg = ckmpm.job_config(sc)
+    cfg.flags = ckmpm.MPM_FLAG_QUADRATIC
+    state = torch.from_numpy(ckmpm.state_planes(sc.x, sc.v, sc.B, sc.F)).cuda()
+    with pytest.raises(ckmpm.CkMpmError) as e:
+        srv.submit(cfg, ckmpm.scene_materials(sc), state, 4, sc.dt)
+    assert e.value.status == ckmpm.MPM_E_INVALID
     srv.close()
