@@ -58,7 +58,10 @@ def test_fused_equals_unfused(nsteps):
         assert nerr(da[k], db[k]) < 1e-6, k
     ma, va = a.grids()
     mb, vb = b.grids()
-    assert nerr(ma, mb) < 1e-6 and nerr(va, vb) < 1e-5
+    # v~ = p / m loses relative precision on nearly empty nodes (float atomics add the
+    # block sums in a different order); compare the momentum m v~ as the parity tests do
+    assert nerr(ma, mb) < 1e-6
+    assert nerr(ma[..., None].astype(np.float64) * va, mb[..., None].astype(np.float64) * vb) < 1e-5
     # a following unfused phase step continues from the fused state
     pa = a.phase_step(sc.dt, want_grids=False)
     pb = b.phase_step(sc.dt, want_grids=False)
