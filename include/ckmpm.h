@@ -129,9 +129,12 @@ mpm_status mpm_create(const mpm_config *cfg, const mpm_material *mats, int32_t n
 mpm_status mpm_destroy(mpm_ctx *ctx);
 
 /* Sort + activation + P2G (sections 4.3-4.5): computes the particles' cell keys (unless
- * the previous mpm_g2p produced them for this buffer), orders the particles by
- * (4^3-cell block, half-cell octant, cell, index) -- the octant being the half of its
- * G- cell a particle lies in along each axis --, activates the grid blocks the 16-node
+ * the previous mpm_g2p produced them for this buffer), orders the particles by 4^3-cell
+ * block and, inside a block, in layers of one particle per (half-cell octant, cell) bin
+ * -- the octant being the half of its G- cell a particle lies in along each axis; layer
+ * q takes the q-th particle by index of every bin, in (octant, cell) order, or the
+ * whole block runs in (octant, cell, index) order when a bin holds more than 16 --,
+ * activates the grid blocks the 16-node
  * stencils touch, clears them and scatters mass and momentum
  * m v + (m B - dt V0 tau) D^-1 (x_i - x_p) to both grids.  Reads the current buffer
  * only.  Enqueued on `stream`; asynchronous. */

@@ -228,10 +228,12 @@ __global__ void __launch_bounds__(kThreads) k_stress_multi(const JobStep *__rest
 // independent of the order of the additions.  The unit of the fixed-point numbers is
 // chosen per block from a bound on every contribution (2^-39 of the largest, so a
 // node's sum of at most 2048 x 8 contributions stays below 2^51 and converts exactly
-// through FP64).  Particles are ordered by (half-cell octant, cell, index): within an
-// octant the particles of a wave mostly sit in different cells, so the lanes of one
-// atomic instruction rarely target the same node.  The tile is then converted back
-// and each nonzero node is added to the pool with one global float atomic.
+// through FP64).  Particles are ordered in layers: layer q holds the q-th particle
+// (by index) of every nonempty (half-cell octant, cell) bin, and each layer runs in
+// (octant, cell) order.  Within an octant distinct cells have distinct nodes on both
+// grids, and spreading each bin's particles over the layers keeps most lanes of one
+// atomic instruction off each other's nodes.  The tile is then converted back and
+// each nonzero node is added to the pool with one global float atomic.
 constexpr int kP2GThreads = 256;
 constexpr int kBins = 512;                 // (octant, cell) bins of a block: octant * 64 + cell
 constexpr int kPerThread = kMaxBlockParticles / kP2GThreads;   // bucket entries per thread
@@ -435,11 +437,27 @@ __device__ __forceinline__ void scatter_pool(const DevCtx &d, float *pool, const
     }
 }
 
+// Layered block order: the q-th particles (by index) of all nonempty (octant, cell)
+// bins form layer q, and the block is ordered by (layer, octant, cell).  The 64 lanes
+// of a wave then mostly hold particles of distinct bins, where the (octant, cell,
+// index) order puts every particle of a bin into the same wave, so one scatter
+// instruction hits fewer equal LDS addresses.  Bins of more than kLayers particles
+// (dense blocks) keep the (octant, cell, index) order.
+constexpr int kLayers = 16;
+constexpr int kLayWords = 2 * kLayers * (kP2GThreads / 64) + kP2GThreads / 64;   // LDS ints of the layer tables
+// 64-bit words of the ordering buffer plus the layer table, which share a kernel's
+// LDS area with its fixed-point tile
+constexpr int kOrderWords = (kMaxBlockParticles * 4 + kLayers * kBins * 2) / 8;
+
 // Orders the particles of block r (count cnt, first sorted position s) by (half-cell
-// octant, cell, index): ord[j] = particle index at position j of the block, also
-// written to the global permutation.  Uses bcnt, bstart, wsum and lbuf (LDS).
+// octant, cell, index), or in the layered order when `layered`: ord[j] = particle
+// index at position j of the block, also written to the global permutation.  Uses
+// bcnt, bstart, wsum and lbuf (LDS); the layered order also uses lay (kLayWords ints)
+// and rt (kLayers * kBins 16-bit entries).
+template <bool layered = false>
 __device__ __forceinline__ void order_block(const DevCtx &d, int r, int s, int cnt, int *bcnt, int *bstart, int *wsum,
-                                            uint32_t *lbuf, uint32_t *ord) {
+                                            uint32_t *lbuf, uint32_t *ord, int *lay = nullptr,
+                                            uint16_t *rt = nullptr) {
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
     const uint32_t *bkt = d.bucket + (size_t)r * kMaxBlockParticles;
@@ -471,6 +489,13 @@ __device__ __forceinline__ void order_block(const DevCtx &d, int r, int s, int c
             if (lane >= off) v += t;
         }
         if (lane == 63) wsum[w] = v;
+        int mx = 0;
+        if (layered) {
+            mx = max(c0, c1);
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off));
+            if (lane == 0) lay[2 * kLayers * 4 + w] = mx;
+        }
         lds_barrier();
         int pre = 0;
         for (int k = 0; k < w; ++k) pre += wsum[k];
@@ -480,8 +505,43 @@ __device__ __forceinline__ void order_block(const DevCtx &d, int r, int s, int c
         bcnt[2 * tid] = ex;
         bcnt[2 * tid + 1] = ex + c0;
         if (tid == kP2GThreads - 1) bstart[kBins] = ex + c0 + c1;
+        if (layered) {
+            // largest bin of the block; layer tables when every bin fits kLayers layers:
+            // rt[q][b] = bins before b (in its wave's 128 bins) holding more than q
+            // particles, lay[q * 4 + w] = such bins in wave w's range
+            mx = max(max(lay[2 * kLayers * 4], lay[2 * kLayers * 4 + 1]),
+                     max(lay[2 * kLayers * 4 + 2], lay[2 * kLayers * 4 + 3]));
+            if (mx <= kLayers) {
+                const unsigned long long lt = (1ull << lane) - 1ull;
+                for (int q = 0; q < mx; ++q) {
+                    const bool f0 = c0 > q, f1 = c1 > q;
+                    const unsigned long long m0 = __ballot(f0), m1 = __ballot(f1);
+                    const int pq = __popcll(m0 & lt) + __popcll(m1 & lt);
+                    rt[q * kBins + 2 * tid] = (uint16_t)pq;
+                    rt[q * kBins + 2 * tid + 1] = (uint16_t)(pq + (f0 ? 1 : 0));
+                    if (lane == 0) lay[q * 4 + w] = __popcll(m0) + __popcll(m1);
+                }
+            }
+        }
     }
     lds_barrier();
+    bool lay_on = false;
+    if (layered) {
+        const int mx = max(max(lay[2 * kLayers * 4], lay[2 * kLayers * 4 + 1]),
+                           max(lay[2 * kLayers * 4 + 2], lay[2 * kLayers * 4 + 3]));
+        lay_on = mx <= kLayers;
+        // first position of (layer q, wave range w): exclusive scan over (q, w) in order
+        if (lay_on && tid < 64) {
+            const int e = tid < mx * 4 ? lay[tid] : 0;
+            int v = e;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int t = __shfl_up(v, off);
+                if (lane >= off) v += t;
+            }
+            lay[kLayers * 4 + tid] = v - e;
+        }
+    }
 #pragma unroll
     for (int k = 0; k < kPerThread; ++k) {
         const int j = tid + k * kP2GThreads;
@@ -514,6 +574,10 @@ __device__ __forceinline__ void order_block(const DevCtx &d, int r, int s, int c
         const int lo = bstart[bin], hi = bstart[bin + 1];
         int rank = lo;
         for (int q = lo; q < hi; ++q) rank += (lbuf[q] < idx) ? 1 : 0;
+        if (lay_on) {
+            const int q = rank - lo;
+            rank = lay[kLayers * 4 + q * 4 + (bin >> 7)] + rt[q * kBins + bin];
+        }
         ord[rank] = idx;
         st_at(d.perm, (uint32_t)(s + rank), idx);
     }
@@ -542,9 +606,11 @@ __device__ __forceinline__ void b_p2g(const DevCtx &d, const PartArgs &pa, float
     __shared__ uint32_t ord[kMaxBlockParticles];   // particle index at each position of the block order
     // ordering buffer, then the fixed-point tile [4][G-] and [4][G+]
     constexpr int kTileWords = 4 * (kTileMStride + kTilePStride);
-    constexpr int kAreaWords = kTileWords > kMaxBlockParticles / 2 ? kTileWords : kMaxBlockParticles / 2;
+    constexpr int kAreaWords = kTileWords > kOrderWords ? kTileWords : kOrderWords;
     __shared__ unsigned long long area[kAreaWords];
+    __shared__ int lay[kLayWords];
     uint32_t *lbuf = reinterpret_cast<uint32_t *>(area);
+    uint16_t *rt = reinterpret_cast<uint16_t *>(lbuf + kMaxBlockParticles);   // after the ordering buffer
     unsigned long long *tile_m = area;
     unsigned long long *tile_p = area + 4 * kTileMStride;
     const int np = (int)d.counters[C_NPB];
@@ -558,7 +624,7 @@ __device__ __forceinline__ void b_p2g(const DevCtx &d, const PartArgs &pa, float
         const int s = d.pstart[r];
         const int cnt = d.pstart[r + 1] - s;
         if (cnt > kMaxBlockParticles) continue;   // reported by the bucket scan
-        order_block(d, r, s, cnt, bcnt, bstart, wsum, lbuf, ord);
+        order_block<true>(d, r, s, cnt, bcnt, bstart, wsum, lbuf, ord, lay, rt);
         load_neighbours(d, gt, bx, by, bz, nbr);
         lds_barrier();
 
@@ -1064,9 +1130,11 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g_grad(DevCtx d, PartArgs pa,
     __shared__ int nbr[27];
     __shared__ uint32_t ord[kMaxBlockParticles];
     constexpr int kTileWords = 4 * (kTileMStride + kTilePStride);
-    constexpr int kAreaWords = kTileWords > kMaxBlockParticles / 2 ? kTileWords : kMaxBlockParticles / 2;
+    constexpr int kAreaWords = kTileWords > kOrderWords ? kTileWords : kOrderWords;
     __shared__ unsigned long long area[kAreaWords];
+    __shared__ int lay[kLayWords];
     uint32_t *lbuf = reinterpret_cast<uint32_t *>(area);
+    uint16_t *rt = reinterpret_cast<uint16_t *>(lbuf + kMaxBlockParticles);   // after the ordering buffer
     unsigned long long *tile_m = area;
     unsigned long long *tile_p = area + 4 * kTileMStride;
     const bool pic = d.transfer == 2;
@@ -1081,7 +1149,7 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g_grad(DevCtx d, PartArgs pa,
         const int s = d.pstart[r];
         const int cnt = d.pstart[r + 1] - s;
         if (cnt > kMaxBlockParticles) continue;
-        order_block(d, r, s, cnt, bcnt, bstart, wsum, lbuf, ord);
+        order_block<true>(d, r, s, cnt, bcnt, bstart, wsum, lbuf, ord, lay, rt);
         load_neighbours(d, gt, bx, by, bz, nbr);
         lds_barrier();
         for (int c0 = 0; c0 < cnt; c0 += kChunk) {
@@ -1370,9 +1438,11 @@ __global__ void __launch_bounds__(kP2GThreads, 4) k_p2g_quad(DevCtx d, PartArgs 
     __shared__ int nbr[27];
     __shared__ uint32_t ord[kMaxBlockParticles];
     constexpr int kTileWords = 4 * kQStride;
-    constexpr int kAreaWords = kTileWords > kMaxBlockParticles / 2 ? kTileWords : kMaxBlockParticles / 2;
+    constexpr int kAreaWords = kTileWords > kOrderWords ? kTileWords : kOrderWords;
     __shared__ unsigned long long area[kAreaWords];
+    __shared__ int lay[kLayWords];
     uint32_t *lbuf = reinterpret_cast<uint32_t *>(area);
+    uint16_t *rt = reinterpret_cast<uint16_t *>(lbuf + kMaxBlockParticles);   // after the ordering buffer
     unsigned long long *tile = area;
     const int np = (int)d.counters[C_NPB];
     const int tid = threadIdx.x;
@@ -1385,7 +1455,7 @@ __global__ void __launch_bounds__(kP2GThreads, 4) k_p2g_quad(DevCtx d, PartArgs 
         const int s = d.pstart[r];
         const int cnt = d.pstart[r + 1] - s;
         if (cnt > kMaxBlockParticles) continue;   // reported by the bucket scan
-        order_block(d, r, s, cnt, bcnt, bstart, wsum, lbuf, ord);
+        order_block<true>(d, r, s, cnt, bcnt, bstart, wsum, lbuf, ord, lay, rt);
         load_neighbours(d, gt, bx, by, bz, nbr);
         lds_barrier();
         for (int c0 = 0; c0 < cnt; c0 += kChunk) {
@@ -1526,6 +1596,8 @@ __global__ void __launch_bounds__(kP2GThreads) k_block_order(DevCtx d) {
     __shared__ int wsum[kP2GThreads / 64];
     __shared__ uint32_t lbuf[kMaxBlockParticles];
     __shared__ uint32_t ord[kMaxBlockParticles];
+    __shared__ int lay[kLayWords];
+    __shared__ uint16_t rt[kLayers * kBins];
     const int np = (int)d.counters[C_NPB];
     for (int base = 0; base < np; base += gridDim.x) {
         const int r = round_block(base, np);
@@ -1533,7 +1605,7 @@ __global__ void __launch_bounds__(kP2GThreads) k_block_order(DevCtx d) {
         const int s = d.pstart[r];
         const int cnt = d.pstart[r + 1] - s;
         if (cnt > kMaxBlockParticles) continue;
-        order_block(d, r, s, cnt, bcnt, bstart, wsum, lbuf, ord);
+        order_block<true>(d, r, s, cnt, bcnt, bstart, wsum, lbuf, ord, lay, rt);
         lds_barrier();
     }
 }
@@ -1563,9 +1635,11 @@ __global__ void __launch_bounds__(kP2GThreads, 2) k_g2p2g(DevCtx d, PartArgs pa,
     __shared__ uint32_t ord[kMaxBlockParticles];
     __shared__ float vt[3 * kTileNodes];
     constexpr int kTileWords = 4 * (kFMStride + kFPStride);
-    constexpr int kAreaWords = kTileWords > kMaxBlockParticles / 2 ? kTileWords : kMaxBlockParticles / 2;
+    constexpr int kAreaWords = kTileWords > kOrderWords ? kTileWords : kOrderWords;
     __shared__ unsigned long long area[kAreaWords];
+    __shared__ int lay[kLayWords];
     uint32_t *lbuf = reinterpret_cast<uint32_t *>(area);
+    uint16_t *rt = reinterpret_cast<uint16_t *>(lbuf + kMaxBlockParticles);   // after the ordering buffer
     unsigned long long *tile_m = area;
     unsigned long long *tile_p = area + 4 * kFMStride;
     const int np = (int)d.counters[C_NPB];
@@ -1580,7 +1654,7 @@ __global__ void __launch_bounds__(kP2GThreads, 2) k_g2p2g(DevCtx d, PartArgs pa,
         const int s = d.pstart[r];
         const int cnt = d.pstart[r + 1] - s;
         if (cnt > kMaxBlockParticles) continue;   // reported by the bucket scan
-        order_block(d, r, s, cnt, bcnt, bstart, wsum, lbuf, ord);
+        order_block<true>(d, r, s, cnt, bcnt, bstart, wsum, lbuf, ord, lay, rt);
         load_neighbours(d, gt_in, bx, by, bz, nbr_in);
         load_neighbours(d, gt_out, bx, by, bz, nbr_out, 64);
         lds_barrier();
