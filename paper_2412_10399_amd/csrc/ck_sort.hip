@@ -134,49 +134,65 @@ __global__ void __launch_bounds__(kThreads) k_compact_count_multi(const JobStep 
     b_compact_count(J.d);
 }
 
-// Exclusive scan of `n` ints in place by one workgroup of 1024 threads; returns the total.
+// Exclusive scans of two arrays of `n` ints in place by one workgroup of T threads,
+// side by side (every load of both in flight together); returns the two totals.
 template <int T>
-__device__ int wg_scan_inplace(int *data, int n, int *sh) {
+__device__ void wg_scan2_inplace(int *da, int *db, int n, int *sh, int &ta, int &tb) {
     const int per = (n + T - 1) / T;
     const int beg = min(n, threadIdx.x * per), end = min(n, beg + per);
-    int local = 0;
-    for (int i = beg; i < end; ++i) local += data[i];
-    // inclusive scan of the per-thread sums across the workgroup
-    int v = local;
+    int la = 0, lb = 0;
+    for (int i = beg; i < end; ++i) {
+        la += da[i];
+        lb += db[i];
+    }
+    // inclusive scans of the per-thread sums across the workgroup
+    int va = la, vb = lb;
     const int lane = wave_lane();
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-        const int t = __shfl_up(v, off);
-        if (lane >= off) v += t;
+        const int t = __shfl_up(va, off), u = __shfl_up(vb, off);
+        if (lane >= off) {
+            va += t;
+            vb += u;
+        }
     }
     const int w = threadIdx.x >> 6;
-    if (lane == 63) sh[w] = v;
+    constexpr int W = T / 64;
+    if (lane == 63) {
+        sh[w] = va;
+        sh[W + 1 + w] = vb;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        int acc = 0;
-        for (int k = 0; k < T / 64; ++k) {
-            const int t = sh[k];
-            sh[k] = acc;
-            acc += t;
+        int aa = 0, ab = 0;
+        for (int k = 0; k < W; ++k) {
+            const int t = sh[k], u = sh[W + 1 + k];
+            sh[k] = aa;
+            sh[W + 1 + k] = ab;
+            aa += t;
+            ab += u;
         }
-        sh[T / 64] = acc;
+        sh[W] = aa;
+        sh[2 * W + 1] = ab;
     }
     __syncthreads();
-    int run = sh[w] + v - local;
+    int ra = sh[w] + va - la, rb = sh[W + 1 + w] + vb - lb;
     for (int i = beg; i < end; ++i) {
-        const int t = data[i];
-        data[i] = run;
-        run += t;
+        const int t = da[i], u = db[i];
+        da[i] = ra;
+        db[i] = rb;
+        ra += t;
+        rb += u;
     }
-    const int total = sh[T / 64];
+    ta = sh[W];
+    tb = sh[2 * W + 1];
     __syncthreads();
-    return total;
 }
 
 __device__ __forceinline__ void b_compact_scan(const DevCtx &d, int nchunks, int table) {
-    __shared__ int sh[32];
-    const int np = wg_scan_inplace<1024>(d.chunk_p, nchunks, sh);
-    const int ng = wg_scan_inplace<1024>(d.chunk_g, nchunks, sh);
+    __shared__ int sh[2 * (1024 / 64) + 2];
+    int np, ng;
+    wg_scan2_inplace<1024>(d.chunk_p, d.chunk_g, nchunks, sh, np, ng);
     if (threadIdx.x == 0) {
         if (ng > d.max_blocks || np > d.max_blocks) set_status(d.counters, ST_CAPACITY);
         d.counters[C_NPB] = (unsigned)min(np, d.max_blocks);
@@ -393,10 +409,18 @@ __device__ __forceinline__ void b_bucket_scan(const DevCtx &d) {
     __syncthreads();
     for (int base = 0; base < np; base += kChunk) {
         const int len = min(kChunk, np - base);
-        for (int k = tid; k < len; k += 1024) {
-            const int c = d.bcount[base + k];
-            buf[k] = c;
-            mx = max(mx, c);
+        // all of a thread's loads in flight together, then staged through LDS
+        int cv[kChunk / 1024];
+#pragma unroll
+        for (int u = 0; u < kChunk / 1024; ++u) {
+            const int k = tid + u * 1024;
+            cv[u] = k < len ? d.bcount[base + k] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kChunk / 1024; ++u) {
+            const int k = tid + u * 1024;
+            if (k < len) buf[k] = cv[u];
+            mx = max(mx, cv[u]);
         }
         __syncthreads();
         // each thread owns 8 consecutive entries

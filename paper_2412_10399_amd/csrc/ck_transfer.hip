@@ -594,9 +594,9 @@ __device__ __forceinline__ double block_scale(float bnd, unsigned int *bmax) {
     return m > 0.0f ? ldexp(1.0, 39 - ilogbf(m)) : 1.0;
 }
 
-// Four waves per SIMD (at most 128 VGPRs, a few spilled): the LDS of four
-// workgroups fits one CU, and the extra workgroup hides more of the load and LDS
-// latency than the spills cost (about 5% faster than three).
+// Three waves per SIMD (at most 168 VGPRs, none spilled).  At four (128 VGPRs) the
+// staged particles spill about 56 B per lane, which costs more in scratch traffic
+// than the fourth workgroup hides (0.271 against 0.260 ms on the sand column).
 __device__ __forceinline__ void b_p2g(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt) {
     __shared__ int bcnt[kBins];                 // counts, then placement cursors
     __shared__ int bstart[kBins + 1];
@@ -676,10 +676,10 @@ __device__ __forceinline__ void b_p2g(const DevCtx &d, const PartArgs &pa, float
     }
 }
 
-__global__ void __launch_bounds__(kP2GThreads, 4) k_p2g(DevCtx d, PartArgs pa, float dt, int gp, int gt) { b_p2g(d, pa, dt, gp, gt); }
+__global__ void __launch_bounds__(kP2GThreads, 3) k_p2g(DevCtx d, PartArgs pa, float dt, int gp, int gt) { b_p2g(d, pa, dt, gp, gt); }
 
 // one launch for many jobs: workgroup row y runs job y
-__global__ void __launch_bounds__(kP2GThreads, 4) k_p2g_multi(const JobStep *__restrict__ jobs) {
+__global__ void __launch_bounds__(kP2GThreads, 3) k_p2g_multi(const JobStep *__restrict__ jobs) {
     const JobStep &J = jobs[blockIdx.y];
     b_p2g(J.d, J.pa, J.dt, J.table, J.table);
 }
