@@ -687,30 +687,52 @@ __global__ void __launch_bounds__(kP2GThreads, 3) k_p2g_multi(const JobStep *__r
 // ---------------------------------------------------------------- grid update
 // Section 4.3 grid update on each grid: m v~ = m v + dt f (the stress impulse is
 // already in the momentum), plus gravity; v~ = 0 where m = 0 and on wall nodes.
+constexpr int kGridPer = 4;   // grid blocks per workgroup and pass of the update
+constexpr int kGridWGs = 3072;
+
 __device__ __forceinline__ void b_grid_update(const DevCtx &d, float dt, float g0, float g1, float g2, int gp, int gt) {
     const int ng = (int)d.counters[ngb_slot(gt)];
     const int t = threadIdx.x;
     const int g = t >> 6, l = t & 63;
     const int lx = l & 3, ly = (l >> 2) & 3, lz = l >> 4;
-    for (int b = blockIdx.x; b < ng; b += gridDim.x) {
-        int bx, by, bz;
-        block_coords(d.geo, d.glist[gt][b], bx, by, bz);
-        const int ix = 4 * bx + lx, iy = 4 * by + ly, iz = 4 * bz + lz;
-        const bool inside = ix >= d.geo.stick_lo[g] && iy >= d.geo.stick_lo[g] && iz >= d.geo.stick_lo[g] &&
-                            ix <= d.geo.stick_hi[g][0] && iy <= d.geo.stick_hi[g][1] && iz <= d.geo.stick_hi[g][2];
-        float *blk = d.pool[gp] + (size_t)b * kBlockFloats + g * 256;
-        // all four channels in one memory round trip
-        const float m = blk[l], p0 = blk[64 + l], p1 = blk[128 + l], p2 = blk[192 + l];
-        float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f;
-        if (m > 0.0f && inside) {
-            const float im = fast_rcp(m);
-            v0 = p0 * im + dt * g0;
-            v1 = p1 * im + dt * g1;
-            v2 = p2 * im + dt * g2;
+    // kGridPer blocks per workgroup and pass, every load of all of them (block ids and
+    // the four channels) in one memory round trip
+    for (int b0 = blockIdx.x; b0 < ng; b0 += kGridPer * gridDim.x) {
+        float m[kGridPer], p0[kGridPer], p1[kGridPer], p2[kGridPer];
+        int vb[kGridPer];
+#pragma unroll
+        for (int k = 0; k < kGridPer; ++k) {
+            const int b = b0 + k * gridDim.x;
+            if (b < ng) {
+                const float *blk = d.pool[gp] + (size_t)b * kBlockFloats + g * 256;
+                vb[k] = d.glist[gt][b];
+                m[k] = blk[l];
+                p0[k] = blk[64 + l];
+                p1[k] = blk[128 + l];
+                p2[k] = blk[192 + l];
+            }
         }
-        blk[64 + l] = v0;
-        blk[128 + l] = v1;
-        blk[192 + l] = v2;
+#pragma unroll
+        for (int k = 0; k < kGridPer; ++k) {
+            const int b = b0 + k * gridDim.x;
+            if (b >= ng) break;
+            int bx, by, bz;
+            block_coords(d.geo, vb[k], bx, by, bz);
+            const int ix = 4 * bx + lx, iy = 4 * by + ly, iz = 4 * bz + lz;
+            const bool inside = ix >= d.geo.stick_lo[g] && iy >= d.geo.stick_lo[g] && iz >= d.geo.stick_lo[g] &&
+                                ix <= d.geo.stick_hi[g][0] && iy <= d.geo.stick_hi[g][1] && iz <= d.geo.stick_hi[g][2];
+            float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f;
+            if (m[k] > 0.0f && inside) {
+                const float im = fast_rcp(m[k]);
+                v0 = p0[k] * im + dt * g0;
+                v1 = p1[k] * im + dt * g1;
+                v2 = p2[k] * im + dt * g2;
+            }
+            float *blk = d.pool[gp] + (size_t)b * kBlockFloats + g * 256;
+            blk[64 + l] = v0;
+            blk[128 + l] = v1;
+            blk[192 + l] = v2;
+        }
     }
 }
 
@@ -1824,7 +1846,7 @@ void launch_p2g(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, h
 }
 
 void launch_grid_update(const DevCtx &d, float dt, const float gravity[3], int gp, int gt, hipStream_t s) {
-    hipLaunchKernelGGL(k_grid_update, dim3(d.max_blocks < 16384 ? d.max_blocks : 16384), dim3(128), 0, s, d, dt,
+    hipLaunchKernelGGL(k_grid_update, dim3(d.max_blocks < kGridWGs ? d.max_blocks : kGridWGs), dim3(128), 0, s, d, dt,
                        gravity[0], gravity[1], gravity[2], gp, gt);
 }
 
@@ -1867,7 +1889,7 @@ void launch_step_run(const JobStep *dev, const JobStep *host, int njobs, hipStre
         const JobStep &J = host[j];
         if (J.first) stress_grid = std::max(stress_grid, (J.pa.n + kThreads - 1) / kThreads);
         pgrid = std::max(pgrid, particle_grid(J.d));
-        ugrid = std::max(ugrid, J.d.max_blocks < 16384 ? J.d.max_blocks : 16384);
+        ugrid = std::max(ugrid, J.d.max_blocks < kGridWGs ? J.d.max_blocks : kGridWGs);
     }
     if (stress_grid > 0) hipLaunchKernelGGL(k_stress_multi, dim3(stress_grid, njobs), dim3(kThreads), 0, s, dev);
     hipLaunchKernelGGL(k_p2g_multi, dim3(pgrid, njobs), dim3(kP2GThreads), 0, s, dev);
