@@ -396,73 +396,69 @@ __global__ void __launch_bounds__(kThreads) k_bucket_count_multi(const JobStep *
 }
 
 // Exclusive scan of the bucket sizes into the first sorted position of every
-// particle block (one workgroup; sizes staged through LDS in chunks).
+// particle block (one workgroup of 1024 threads).  In a pass, element
+// base + 1024 u + t (row u) belongs to thread t: the 16 loads of a thread are
+// coalesced across the workgroup and all in flight together.  Each row is scanned
+// across the workgroup (wave scans, then the wave totals through LDS), and the rows
+// follow each other.
 __device__ __forceinline__ void b_bucket_scan(const DevCtx &d) {
-    constexpr int kChunk = 8192;
-    __shared__ int buf[kChunk];
-    __shared__ int wsum[16];
-    __shared__ int carry_sh;
+    constexpr int kRows = 16, kPass = kRows * 1024;
+    __shared__ int wtot[kRows][16];   // per row: wave totals, then their exclusive scan
+    __shared__ int rtot[kRows];       // per row: total
+    __shared__ int wmx[16];
     const int np = (int)d.counters[C_NPB];
     const int tid = threadIdx.x, lane = wave_lane(), w = tid >> 6;
-    int mx = 0;
-    if (tid == 0) carry_sh = 0;
-    __syncthreads();
-    for (int base = 0; base < np; base += kChunk) {
-        const int len = min(kChunk, np - base);
-        // all of a thread's loads in flight together, then staged through LDS
-        int cv[kChunk / 1024];
+    int mx = 0, carry = 0;
+    for (int base = 0; base < np; base += kPass) {
+        int c[kRows], incl[kRows];
 #pragma unroll
-        for (int u = 0; u < kChunk / 1024; ++u) {
-            const int k = tid + u * 1024;
-            cv[u] = k < len ? d.bcount[base + k] : 0;
+        for (int u = 0; u < kRows; ++u) {
+            const int k = base + u * 1024 + tid;
+            c[u] = k < np ? d.bcount[k] : 0;
         }
 #pragma unroll
-        for (int u = 0; u < kChunk / 1024; ++u) {
-            const int k = tid + u * 1024;
-            if (k < len) buf[k] = cv[u];
-            mx = max(mx, cv[u]);
-        }
-        __syncthreads();
-        // each thread owns 8 consecutive entries
-        const int b0 = tid * 8;
-        int loc[8];
-        int sum = 0;
+        for (int u = 0; u < kRows; ++u) {
+            int v = c[u];
+            mx = max(mx, v);
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            loc[k] = (b0 + k < len) ? buf[b0 + k] : 0;
-            sum += loc[k];
-        }
-        int v = sum;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const int t = __shfl_up(v, off);
-            if (lane >= off) v += t;
-        }
-        if (lane == 63) wsum[w] = v;
-        __syncthreads();
-        int pre = carry_sh;
-        for (int k = 0; k < w; ++k) pre += wsum[k];
-        int run = pre + v - sum;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            if (b0 + k < len) d.pstart[base + b0 + k] = run;
-            run += loc[k];
+            for (int off = 1; off < 64; off <<= 1) {
+                const int t = __shfl_up(v, off);
+                if (lane >= off) v += t;
+            }
+            incl[u] = v;
+            if (lane == 63) wtot[u][w] = v;
         }
         __syncthreads();
-        if (tid == 1023) carry_sh = run;
+        if (tid < kRows) {
+            int run = 0;
+            for (int k = 0; k < 16; ++k) {
+                const int t = wtot[tid][k];
+                wtot[tid][k] = run;
+                run += t;
+            }
+            rtot[tid] = run;
+        }
         __syncthreads();
+        int run = carry;
+#pragma unroll
+        for (int u = 0; u < kRows; ++u) {
+            const int k = base + u * 1024 + tid;
+            if (k < np) d.pstart[k] = run + wtot[u][w] + incl[u] - c[u];
+            run += rtot[u];
+        }
+        carry = run;
+        __syncthreads();   // wtot and rtot are rewritten by the next pass
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_down(mx, off));
-    if (lane == 0) wsum[w] = mx;
+    if (lane == 0) wmx[w] = mx;
     __syncthreads();
     if (tid == 0) {
         int m = 0;
-        for (int k = 0; k < 16; ++k) m = max(m, wsum[k]);
-        const int total = carry_sh;
-        d.pstart[np] = total;
+        for (int k = 0; k < 16; ++k) m = max(m, wmx[k]);
+        d.pstart[np] = carry;
         d.counters[C_MAXPB] = (unsigned)m;
-        d.counters[C_TOTAL] = (unsigned)total;
+        d.counters[C_TOTAL] = (unsigned)carry;
         if (m > kMaxBlockParticles) set_status(d.counters, ST_CAPACITY);
     }
 }
