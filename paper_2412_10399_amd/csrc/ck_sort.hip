@@ -321,14 +321,37 @@ __device__ __forceinline__ void b_bucket_count(const DevCtx &d, int n, int zero_
     }
     int r[kCountPer];
     uint16_t sb[kCountPer];
+    uint32_t kv[kCountPer];
+    {
+        // the thread's 4 keys and sub-cell codes in one 16-byte and one 8-byte load
+        // (the library's buffers are 256-byte aligned), element loads at the tail
+        const int i0 = base + tid * kCountPer;
+        if (i0 + kCountPer <= n) {
+            const uint4 k4 = *reinterpret_cast<const uint4 *>(d.key + i0);
+            const uint2 s4 = *reinterpret_cast<const uint2 *>(d.sub + i0);
+            kv[0] = k4.x;
+            kv[1] = k4.y;
+            kv[2] = k4.z;
+            kv[3] = k4.w;
+            sb[0] = (uint16_t)(s4.x & 0xffffu);
+            sb[1] = (uint16_t)(s4.x >> 16);
+            sb[2] = (uint16_t)(s4.y & 0xffffu);
+            sb[3] = (uint16_t)(s4.y >> 16);
+        } else {
+#pragma unroll
+            for (int k = 0; k < kCountPer; ++k) {
+                kv[k] = i0 + k < n ? d.key[i0 + k] : 0xffffffffu;
+                sb[k] = i0 + k < n ? d.sub[i0 + k] : (uint16_t)0;
+            }
+        }
+    }
+    static_assert(kCountPer == 4, "vector loads take 4 keys");
 #pragma unroll
     for (int k = 0; k < kCountPer; ++k) {
         const int i = base + tid * kCountPer + k;
         r[k] = -1;
-        sb[k] = 0;
         if (i < n) {
-            const uint32_t key = d.key[i];
-            sb[k] = d.sub[i];
+            const uint32_t key = kv[k];
             if (key != 0xffffffffu) {
                 // a key whose block was not stamped this step cannot be placed; the
                 // stamp and the rank are loaded together (one memory round trip)
