@@ -167,7 +167,7 @@ int64_t device_bytes_of(const mpm_config &c) {
     auto r = [](long long bytes) { return (bytes + 256 + 255) / 256 * 256; };
     // the buffers of ctx_create, in its order
     return r(4 * np) + r(2 * np) + r(4 * np) + r(4 * nb * (long long)kMaxBlockParticles) +
-           r(2 * nb * (long long)kMaxBlockParticles) + r(8 * nbv) + r(8 * nbv) + 2 * r(4 * nbv) + r(4 * nbv) +
+           r(2 * nb * (long long)kMaxBlockParticles) + 2 * r(8 * stamp_stride(nbv)) + 2 * r(4 * nbv) + r(4 * nbv) +
            r(4 * nb) + r(4 * (nb + 1)) + r(4 * nb) + 2 * r(4 * nb) + r(4 * nchunks) + r(4 * nchunks) +
            2 * r(4 * nb * (long long)kBlockFloats) + r(24 * np) + r(4 * (long long)C_COUNT);
 }
@@ -297,8 +297,8 @@ mpm_status ctx_create(const mpm_config *cfg, const mpm_material *mats, int32_t n
     if (st == MPM_OK) st = dalloc(ctx, &d.perm, np);
     if (st == MPM_OK) st = dalloc(ctx, &d.bucket, nb * (size_t)kMaxBlockParticles);
     if (st == MPM_OK) st = dalloc(ctx, &d.bsub, nb * (size_t)kMaxBlockParticles);
-    if (st == MPM_OK) st = dalloc(ctx, &d.pflag, 2 * nv);
-    if (st == MPM_OK) st = dalloc(ctx, &d.gflag, 2 * nv);
+    if (st == MPM_OK) st = dalloc(ctx, &d.pflag, 2 * (size_t)stamp_stride(d.nbv));
+    if (st == MPM_OK) st = dalloc(ctx, &d.gflag, 2 * (size_t)stamp_stride(d.nbv));
     if (st == MPM_OK) st = dalloc(ctx, &d.page[0], nv);
     if (st == MPM_OK) st = dalloc(ctx, &d.page[1], nv);
     if (st == MPM_OK) st = dalloc(ctx, &d.prank, nv);
@@ -321,8 +321,8 @@ mpm_status ctx_create(const mpm_config *cfg, const mpm_material *mats, int32_t n
             st = MPM_E_OOM;
     }
     if (st == MPM_OK) {
-        bool ok = hipMemsetAsync(d.pflag, 0, 2 * nv * sizeof(int), init_stream) == hipSuccess &&
-                  hipMemsetAsync(d.gflag, 0, 2 * nv * sizeof(int), init_stream) == hipSuccess &&
+        bool ok = hipMemsetAsync(d.pflag, 0, 2 * stamp_stride(d.nbv) * sizeof(int), init_stream) == hipSuccess &&
+                  hipMemsetAsync(d.gflag, 0, 2 * stamp_stride(d.nbv) * sizeof(int), init_stream) == hipSuccess &&
                   hipMemsetAsync(d.page[0], 0xff, nv * sizeof(int), init_stream) == hipSuccess &&
                   hipMemsetAsync(d.page[1], 0xff, nv * sizeof(int), init_stream) == hipSuccess &&
                   hipMemsetAsync(d.prank, 0xff, nv * sizeof(int), init_stream) == hipSuccess &&

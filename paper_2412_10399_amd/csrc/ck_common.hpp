@@ -72,7 +72,7 @@ struct DevCtx {
     uint32_t *bucket;      // [max_blocks][kMaxBlockParticles]: particle indices of each particle
                            // block, in arrival order
     uint32_t *perm;        // exact stable sort order
-    int *pflag, *gflag;    // [2][nbv] epoch stamps ("holds particles" / "within one block of a
+    int *pflag, *gflag;    // [2][stamp_stride(nbv)] epoch stamps ("holds particles" / "within one block of a
                            // block holding particles"), double-buffered by epoch parity so that
                            // stamping the next step never disturbs readers of the current one
     int *page[2];          // two page tables: per virtual block the physical pool block, or -1
@@ -138,7 +138,12 @@ __device__ __forceinline__ int vblock_id(const Geometry &g, int bx, int by, int 
 }
 
 // Stamp array of a given epoch (double buffer indexed by the epoch's parity).
-__device__ __forceinline__ int *stamps(int *base, long long nbv, int epoch) { return base + (epoch & 1) * nbv; }
+// Each epoch's stamps start at a multiple of 64 entries, so that both halves are
+// 256-byte aligned for vector loads.
+__host__ __device__ constexpr long long stamp_stride(long long nbv) { return (nbv + 63) / 64 * 64; }
+__device__ __forceinline__ int *stamps(int *base, long long nbv, int epoch) {
+    return base + (epoch & 1) * stamp_stride(nbv);
+}
 
 // Cell of a position on grid G- (particle keys) and the fractional coordinates on
 // both grids.  The integer part is taken in FP64 from the FP32 position so that it

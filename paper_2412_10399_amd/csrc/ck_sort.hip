@@ -68,7 +68,8 @@ __global__ void __launch_bounds__(kThreads) k_flag_keys_multi(const JobStep *__r
 }
 
 __global__ void k_clear_flags(DevCtx d) {
-    for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < 2 * d.nbv; v += (long long)gridDim.x * blockDim.x) {
+    const long long nst = 2 * stamp_stride(d.nbv);
+    for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < nst; v += (long long)gridDim.x * blockDim.x) {
         d.pflag[v] = 0;
         d.gflag[v] = 0;
     }
@@ -103,20 +104,46 @@ __device__ __forceinline__ void wg_sum2(int &a, int &b, int *sh) {
 
 constexpr int kPerThread = kCompactChunk / kThreads;   // 4 virtual blocks per thread
 
+// Flags (stamp == E) of the kPerThread consecutive virtual blocks from `base`, both
+// stamp arrays in one 16-byte load each (every epoch's stamps are 256-byte aligned);
+// element loads where the range ends inside them.
+__device__ __forceinline__ void load_flags(const DevCtx &d, const int *pf, const int *gf, long long base, int E,
+                                           int (&fp)[kPerThread], int (&fg)[kPerThread]) {
+    static_assert(kPerThread == 4, "one int4 per array");
+    if (base + kPerThread <= d.nbv) {
+        const int4 a = *reinterpret_cast<const int4 *>(pf + base);
+        const int4 b = *reinterpret_cast<const int4 *>(gf + base);
+        fp[0] = a.x == E;
+        fp[1] = a.y == E;
+        fp[2] = a.z == E;
+        fp[3] = a.w == E;
+        fg[0] = b.x == E;
+        fg[1] = b.y == E;
+        fg[2] = b.z == E;
+        fg[3] = b.w == E;
+    } else {
+#pragma unroll
+        for (int k = 0; k < kPerThread; ++k) {
+            const long long v = base + k;
+            fp[k] = (v < d.nbv) && (pf[v] == E);
+            fg[k] = (v < d.nbv) && (gf[v] == E);
+        }
+    }
+}
+
 __device__ __forceinline__ void b_compact_count(const DevCtx &d) {
     __shared__ int sh[16];
     const int E = (int)d.counters[C_EPOCH] + 1;
     const int *pf = stamps(d.pflag, d.nbv, E);
     const int *gf = stamps(d.gflag, d.nbv, E);
     const long long base = (long long)blockIdx.x * kCompactChunk + threadIdx.x * kPerThread;
+    int fp[kPerThread], fg[kPerThread];
+    load_flags(d, pf, gf, base, E, fp, fg);
     int cp = 0, cg = 0;
 #pragma unroll
     for (int k = 0; k < kPerThread; ++k) {
-        const long long v = base + k;
-        if (v < d.nbv) {
-            cp += (pf[v] == E);
-            cg += (gf[v] == E);
-        }
+        cp += fp[k];
+        cg += fg[k];
     }
     wg_sum2(cp, cg, sh);
     if (threadIdx.x == 0) {
@@ -242,12 +269,10 @@ __device__ __forceinline__ void b_compact_emit(const DevCtx &d, int table) {
     const int *gf = stamps(d.gflag, d.nbv, E);
     const long long base = (long long)blockIdx.x * kCompactChunk + threadIdx.x * kPerThread;
     int fp[kPerThread], fg[kPerThread];
+    load_flags(d, pf, gf, base, E, fp, fg);
     int cp = 0, cg = 0;
 #pragma unroll
     for (int k = 0; k < kPerThread; ++k) {
-        const long long v = base + k;
-        fp[k] = (v < d.nbv) && (pf[v] == E);
-        fg[k] = (v < d.nbv) && (gf[v] == E);
         cp += fp[k];
         cg += fg[k];
     }
@@ -257,6 +282,7 @@ __device__ __forceinline__ void b_compact_emit(const DevCtx &d, int table) {
     const int offp = d.chunk_p[blockIdx.x] + ep;
     const int offg = d.chunk_g[blockIdx.x] + eg;
     int rp = offp, rg = offg;
+    int ph[kPerThread];
 #pragma unroll
     for (int k = 0; k < kPerThread; ++k) {
         const int v = (int)(base + k);
@@ -270,18 +296,22 @@ __device__ __forceinline__ void b_compact_emit(const DevCtx &d, int table) {
             }
             ++rp;
         }
-        if (v < d.nbv) {
-            // every virtual block gets its entry, so the table is valid without stamps
-            int ph = -1;
-            if (fg[k]) {
-                if (rg < d.max_blocks) {
-                    d.glist[table][rg] = v;
-                    ph = rg;
-                }
-                ++rg;
+        ph[k] = -1;
+        if (fg[k]) {
+            if (rg < d.max_blocks) {
+                d.glist[table][rg] = v;
+                ph[k] = rg;
             }
-            d.page[table][v] = ph;
+            ++rg;
         }
+    }
+    // every virtual block gets its page entry, so the table is valid without stamps
+    if (base + kPerThread <= d.nbv) {
+        *reinterpret_cast<int4 *>(d.page[table] + base) = make_int4(ph[0], ph[1], ph[2], ph[3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < kPerThread; ++k)
+            if (base + k < d.nbv) d.page[table][base + k] = ph[k];
     }
     (void)gtot;
 }
