@@ -24,6 +24,8 @@
 #include <cmath>
 #include <new>
 
+#include <climits>
+
 using namespace ck;
 
 struct mpm_ad_ctx {
@@ -315,6 +317,101 @@ __device__ __forceinline__ void load_planes(const float *base, long long stride,
     for (int i = 0; i < count; ++i) out[i] = base[(first + i) * stride + p];
 }
 
+// ------------------------------------------------------------ workgroup node tiles
+// The two scattering kernels accumulate into a 64-bit fixed-point LDS tile over the
+// node box of their workgroup's 256 particles (both grids), then add every nonzero
+// node to the dense grid with one float atomic per channel.  Particles keep their
+// creation order, cell by cell, so consecutive particles sit in neighbouring cells
+// and the box is small (a row of about 34 x 3 x 3 nodes for the box workload); a
+// workgroup whose box does not fit adds its contributions to the grid directly.
+// Integer sums are exact; the unit is 2^-39 of the largest contribution bound of
+// the workgroup, so a node's sum of at most 256 contributions stays below 2^48.
+constexpr int kAdTileWords = 5120;   // 40 KiB
+
+struct AdTile {
+    unsigned long long *w;   // [channel][grid][T]
+    int lo[3], L[3], T;
+    bool on;
+    double S;
+};
+
+// round(v S) as a two's-complement 64-bit integer (|v S| < 2^51): in [2^52, 2^53) the
+// FP64 numbers are the integers, so magic + v S carries it in its low bits.
+__device__ __forceinline__ unsigned long long ad_fixed(float v, double S) {
+    constexpr double kMagic = 6755399441055744.0;   // 1.5 * 2^52
+    return (unsigned long long)(__double_as_longlong(fma((double)v, S, kMagic)) - 0x4338000000000000LL);
+}
+
+// Called by every thread of the workgroup: node box of the valid particles'
+// stencils on both grids, scale from the largest bound `bnd`, tile of `nch`
+// channels cleared when it fits.  sh: 7 ints of LDS.
+__device__ void ad_tile_begin(bool valid, const AdStencil &st, float bnd, int nch, unsigned long long *words, int *sh,
+                              AdTile &t) {
+    const int tid = threadIdx.x;
+    if (tid < 3) sh[tid] = INT_MAX;
+    else if (tid < 6) sh[tid] = INT_MIN;
+    else if (tid == 6) sh[6] = 0;
+    __syncthreads();
+    if (valid) {
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            atomicMin(&sh[ax], min(st.base[0][ax], st.base[1][ax]));
+            atomicMax(&sh[3 + ax], max(st.base[0][ax], st.base[1][ax]) + 1);
+        }
+    }
+    float b = valid ? bnd : 0.0f;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) b = fmaxf(b, __shfl_xor(b, off));
+    if ((tid & 63) == 0) atomicMax(reinterpret_cast<unsigned int *>(&sh[6]), __float_as_uint(b));
+    __syncthreads();
+    t.w = words;
+    long long T = 1;
+    bool on = sh[0] <= sh[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        t.lo[ax] = sh[ax];
+        t.L[ax] = on ? sh[3 + ax] - sh[ax] + 1 : 0;
+        T *= t.L[ax];
+    }
+    on = on && 2 * T * nch <= kAdTileWords;
+    t.on = on;
+    t.T = on ? (int)T : 0;
+    const float m = __uint_as_float((unsigned int)sh[6]);
+    t.S = m > 0.0f ? ldexp(1.0, 39 - ilogbf(m)) : 1.0;
+    if (on)
+        for (int q = tid; q < 2 * t.T * nch; q += blockDim.x) words[q] = 0ull;
+    __syncthreads();
+}
+
+// Adds v to channel ch of node (ix, iy, iz) of grid g (dense index id): into the tile,
+// or straight into plane plane0 + ch of the grid when the tile is off.
+__device__ __forceinline__ void ad_tile_add(const AdArgs &a, const AdTile &t, int plane0, int ch, int g, int ix, int iy,
+                                            int iz, long long id, float v) {
+    if (t.on) {
+        const int r = ((iz - t.lo[2]) * t.L[1] + (iy - t.lo[1])) * t.L[0] + (ix - t.lo[0]);
+        atomicAdd(&t.w[(ch * 2 + g) * t.T + r], ad_fixed(v, t.S));
+    } else {
+        atomicAdd(&plane(a, plane0 + ch)[id], v);
+    }
+}
+
+// Called by every thread after its adds: every nonzero tile node to the grid.
+__device__ void ad_tile_flush(const AdArgs &a, const AdTile &t, int plane0, int nch) {
+    __syncthreads();
+    if (!t.on) return;
+    const double inv = 1.0 / t.S;
+    const int LxLy = t.L[0] * t.L[1];
+    for (int q = threadIdx.x; q < 2 * t.T; q += blockDim.x) {
+        const int g = q >= t.T ? 1 : 0, r = q - g * t.T;
+        const int ix = t.lo[0] + r % t.L[0], iy = t.lo[1] + (r / t.L[0]) % t.L[1], iz = t.lo[2] + r / LxLy;
+        const long long id = (long long)g * a.nodes + ((long long)iz * a.ny + iy) * a.nx + ix;
+        for (int ch = 0; ch < nch; ++ch) {
+            const long long v = (long long)t.w[(ch * 2 + g) * t.T + r];
+            if (v != 0) atomicAdd(&plane(a, plane0 + ch)[id], (float)((double)v * inv));
+        }
+    }
+}
+
 // ------------------------------------------------------------ kernels
 __global__ void k_ad_clear(AdArgs a, int first_plane, int nplanes) {
     const long long total = (long long)nplanes * 2 * a.nodes;
@@ -323,44 +420,64 @@ __global__ void k_ad_clear(AdArgs a, int first_plane, int nplanes) {
         g[t] = 0.0f;
 }
 
-// P2G with float atomics into the dense grids.
+// P2G through the workgroup's node tile (direct float atomics when it does not fit).
 __global__ void __launch_bounds__(256) k_ad_p2g(AdArgs a, const float *state, const float *logE) {
+    __shared__ unsigned long long tw[kAdTileWords];
+    __shared__ int sh[8];
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= a.n) return;
-    float x[3], v[3], B[9], H[9];
-    load_planes(state, a.stride, p, 0, 3, x);
-    load_planes(state, a.stride, p, 3, 3, v);
-    load_planes(state, a.stride, p, 6, 9, B);
-    load_planes(state, a.stride, p, 15, 9, H);
+    float x[3], v[3], Q[9];
     AdStencil st;
-    if (!ad_stencil(a, x, st)) {
-        set_status(a.status, ST_DOMAIN);
-        return;
-    }
-    const float E = expf(logE[p]);
-    Polar P;
-    ad_polar(H, P);
-    float tau[9];
-    ad_tau(H, P, a.nu_mu * E, a.nu_lambda * E, tau);
-    float A[9], Q[9];
+    bool valid = false;
+    if (p < a.n) {
+        float B[9], H[9];
+        load_planes(state, a.stride, p, 0, 3, x);
+        load_planes(state, a.stride, p, 3, 3, v);
+        load_planes(state, a.stride, p, 6, 9, B);
+        load_planes(state, a.stride, p, 15, 9, H);
+        valid = ad_stencil(a, x, st);
+        if (!valid) {
+            set_status(a.status, ST_DOMAIN);
+        } else {
+            const float E = expf(logE[p]);
+            Polar P;
+            ad_polar(H, P);
+            float tau[9];
+            ad_tau(H, P, a.nu_mu * E, a.nu_lambda * E, tau);
+            float A[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) A[i] = a.mass * B[i] - a.dt * a.vol0 * tau[i];
+            for (int i = 0; i < 9; ++i) A[i] = a.mass * B[i] - a.dt * a.vol0 * tau[i];
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+            for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < 3; ++j)
-            Q[3 * i + j] = A[3 * i] * st.Dinv[j] + A[3 * i + 1] * st.Dinv[3 + j] + A[3 * i + 2] * st.Dinv[6 + j];
-    float *gm = plane(a, GM);
-    for (int g = 0; g < 2; ++g)
-        for (int o = 0; o < 8; ++o) {
-            float w, d[3], gw[3];
-            const long long id = ad_node(a, st, g, o, w, d, gw);
-            atomicAdd(&gm[id], w * a.mass);
-#pragma unroll
-            for (int ax = 0; ax < 3; ++ax)
-                atomicAdd(&plane(a, GP + ax)[id],
-                          w * (a.mass * v[ax] + Q[3 * ax] * d[0] + Q[3 * ax + 1] * d[1] + Q[3 * ax + 2] * d[2]));
+                for (int j = 0; j < 3; ++j)
+                    Q[3 * i + j] = A[3 * i] * st.Dinv[j] + A[3 * i + 1] * st.Dinv[3 + j] + A[3 * i + 2] * st.Dinv[6 + j];
         }
+    }
+    // |w m| <= m and |w (m v + Q d)| <= |m v| + dx sum |Q| (w <= 1, |d_b| <= dx)
+    float bnd = 0.0f;
+    if (valid) {
+        bnd = a.mass;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax)
+            bnd = fmaxf(bnd, fabsf(a.mass * v[ax]) +
+                                 a.geo.dx * (fabsf(Q[3 * ax]) + fabsf(Q[3 * ax + 1]) + fabsf(Q[3 * ax + 2])));
+    }
+    AdTile t;
+    ad_tile_begin(valid, st, bnd, 4, tw, sh, t);
+    if (valid) {
+        for (int g = 0; g < 2; ++g)
+            for (int o = 0; o < 8; ++o) {
+                float w, d[3], gw[3];
+                const long long id = ad_node(a, st, g, o, w, d, gw);
+                const int ix = st.base[g][0] + (o & 1), iy = st.base[g][1] + ((o >> 1) & 1), iz = st.base[g][2] + (o >> 2);
+                ad_tile_add(a, t, GM, 0, g, ix, iy, iz, id, w * a.mass);
+#pragma unroll
+                for (int ax = 0; ax < 3; ++ax)
+                    ad_tile_add(a, t, GM, 1 + ax, g, ix, iy, iz, id,
+                                w * (a.mass * v[ax] + Q[3 * ax] * d[0] + Q[3 * ax + 1] * d[1] + Q[3 * ax + 2] * d[2]));
+            }
+    }
+    ad_tile_flush(a, t, GM, 4);
 }
 
 __device__ __forceinline__ bool node_free(const AdArgs &a, long long id, int &g) {
@@ -442,21 +559,32 @@ __global__ void __launch_bounds__(256) k_ad_g2p(AdArgs a, const float *state, fl
 // G2P reversed: scatters dL/dv~ to the grid, writes the G2P part of dL/dx and dL/dF.
 __global__ void __launch_bounds__(256) k_ad_g2p_vjp(AdArgs a, const float *state, const float *cot_out,
                                                     float *cot_in) {
+    __shared__ unsigned long long tw[kAdTileWords];
+    __shared__ int sh[8];
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= a.n) return;
     float x[3], H[9];
-    load_planes(state, a.stride, p, 0, 3, x);
-    load_planes(state, a.stride, p, 15, 9, H);
     float xbo[3], vbo[3], Bbo[9], Fbo[9];
-    load_planes(cot_out, a.stride, p, 0, 3, xbo);
-    load_planes(cot_out, a.stride, p, 3, 3, vbo);
-    load_planes(cot_out, a.stride, p, 6, 9, Bbo);
-    load_planes(cot_out, a.stride, p, 15, 9, Fbo);
     AdStencil st;
-    if (!ad_stencil(a, x, st)) {
-        // the forward step left this particle unchanged
-        set_status(a.status, ST_DOMAIN);
-        for (int i = 0; i < MPM_STATE_PLANES; ++i) cot_in[i * a.stride + p] = cot_out[i * a.stride + p];
+    bool valid = false;
+    if (p < a.n) {
+        load_planes(state, a.stride, p, 0, 3, x);
+        load_planes(state, a.stride, p, 15, 9, H);
+        load_planes(cot_out, a.stride, p, 0, 3, xbo);
+        load_planes(cot_out, a.stride, p, 3, 3, vbo);
+        load_planes(cot_out, a.stride, p, 6, 9, Bbo);
+        load_planes(cot_out, a.stride, p, 15, 9, Fbo);
+        valid = ad_stencil(a, x, st);
+        if (!valid) {
+            // the forward step left this particle unchanged
+            set_status(a.status, ST_DOMAIN);
+            for (int i = 0; i < MPM_STATE_PLANES; ++i) cot_in[i * a.stride + p] = cot_out[i * a.stride + p];
+        }
+    }
+    // every thread takes part in the tile's set-up and flush; invalid lanes add nothing
+    if (!valid) {
+        AdTile t;
+        ad_tile_begin(false, st, 0.0f, 3, tw, sh, t);
+        ad_tile_flush(a, t, GVB, 3);
         return;
     }
     // forward quantities: B' and C = B' D^-1
@@ -512,6 +640,14 @@ __global__ void __launch_bounds__(256) k_ad_g2p_vjp(AdArgs a, const float *state
                              Cb[3 * i + 2] * st.Dinv[3 * j + 2];
             Dib[3 * i + j] = Bn[i] * Cb[j] + Bn[3 + i] * Cb[3 + j] + Bn[6 + i] * Cb[6 + j];
         }
+    // |1/2 w (v'b + B'b d)| <= 1/2 (|v'b| + dx sum |B'b|)
+    float bnd = 0.0f;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax)
+        bnd = fmaxf(bnd, 0.5f * (fabsf(vbt[ax]) +
+                                 a.geo.dx * (fabsf(Bbt[3 * ax]) + fabsf(Bbt[3 * ax + 1]) + fabsf(Bbt[3 * ax + 2]))));
+    AdTile t;
+    ad_tile_begin(true, st, bnd, 3, tw, sh, t);
     // v' = 1/2 sum w v~,  B' = 1/2 sum w v~ d^T:
     //   v~b_i += 1/2 w (v'b + B'b d),  wb = 1/2 v~ . (v'b + B'b d),  db = 1/2 w B'b^T v~,
     //   and d = x_i - x_p moves against x_p
@@ -519,6 +655,7 @@ __global__ void __launch_bounds__(256) k_ad_g2p_vjp(AdArgs a, const float *state
         for (int o = 0; o < 8; ++o) {
             float w, d[3], gw[3];
             const long long id = ad_node(a, st, g, o, w, d, gw);
+            const int ix = st.base[g][0] + (o & 1), iy = st.base[g][1] + ((o >> 1) & 1), iz = st.base[g][2] + (o >> 2);
             float vi[3], gv[3];
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax) {
@@ -528,7 +665,7 @@ __global__ void __launch_bounds__(256) k_ad_g2p_vjp(AdArgs a, const float *state
             float wb = 0.0f;
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax) {
-                atomicAdd(&plane(a, GVB + ax)[id], 0.5f * w * gv[ax]);
+                ad_tile_add(a, t, GVB, ax, g, ix, iy, iz, id, 0.5f * w * gv[ax]);
                 wb += 0.5f * vi[ax] * gv[ax];
             }
 #pragma unroll
@@ -544,6 +681,7 @@ __global__ void __launch_bounds__(256) k_ad_g2p_vjp(AdArgs a, const float *state
     for (int ax = 0; ax < 3; ++ax) cot_in[ax * a.stride + p] = xb[ax];
 #pragma unroll
     for (int i = 0; i < 9; ++i) cot_in[(15 + i) * a.stride + p] = Fb[i];
+    ad_tile_flush(a, t, GVB, 3);
 }
 
 // Grid update reversed: pb = v~b / m,  mb = -(v~b . p) / m^2 on live nodes.
