@@ -1,5 +1,6 @@
 """The differentiable step on the GPU (include/ckmpm_adjoint.h) against the FP64
-oracle: one forward step, one reverse-mode step with random cotangents, rollout
+oracle: one forward step, one reverse-mode step with random cotangents (also with
+the particles shuffled, which takes the scatters' direct path), rollout
 gradients of the differentiation workload (65,536 particles, 64 steps, checkpoints
 every 8 steps) against the oracle's adjoint, and 32 random directional derivatives
 against central differences of the oracle's forward rollout."""
@@ -93,6 +94,61 @@ def test_backward_step_matches_oracle_adjoint(near_wall):
     for k in ("x", "v", "B", "F", "logE"):
         e = nerr(got[k], ref[k])
         log("reverse step (near wall %s): d/d%s %.2e" % (near_wall, k, e))
+        assert e <= 1e-4, k
+    ad.close()
+
+
+def test_shuffled_particles_take_the_direct_scatter():
+    """Particles in random order: every workgroup's node box spans the body and
+    exceeds the scatter tile, so both scatters add straight into the grid; forward
+    and reverse step still match the oracle."""
+    import torch
+    from paper_2412_10399_amd import ckmpm
+    sc = scenes.random_blob(35, n_cells=(16, 16, 16), lo_cells=(3.2, 3.4, 3.1), ext_cells=(10, 8, 9),
+                            model=scenes.FIXED_COROTATED, v_scale=0.5, B_scale=2.0, F_scale=0.05,
+                            gravity=(0.3, -9.8, 0.1), bc_band=2, dt=1e-4, E=5e4)
+    rng = np.random.default_rng(36)
+    perm = rng.permutation(sc.n)
+    sc.x, sc.v, sc.B, sc.F, sc.mat = sc.x[perm], sc.v[perm], sc.B[perm], sc.F[perm], sc.mat[perm]
+    sc.logE = (np.log(5e4) + 0.2 * rng.standard_normal(sc.n)).astype(np.float32)
+    # a 256-particle workgroup's box needs more than the 5120-word tile
+    X = sc.x[:256].astype(np.float64) / sc.dx
+    span = np.floor(X.max(0) + 0.25) - np.floor(X.min(0) - 0.25) + 2
+    assert 2 * np.prod(span) * 3 > 5120
+    ad = _ctx(sc)
+    n = sc.n
+    s0 = _state(sc)
+    logE = torch.from_numpy(sc.logE).cuda()
+    stream = torch.cuda.current_stream()
+    out = torch.empty_like(s0)
+    ckmpm.check(ckmpm.mpm_ad_forward(ad.h, n, n, s0.data_ptr(), logE.data_ptr(), out.data_ptr(), sc.dt, stream))
+    ckmpm.check(ckmpm.mpm_ad_sync(ad.h, stream))
+    got = _unpack(out)
+    st = oracle.State(sc.x, sc.v, sc.B, sc.F, sc.mat, sc.logE)
+    status, _, _ = oracle.step(oracle.scene_config(sc), oracle.scene_materials(sc), st, sc.dt)
+    assert status == 0
+    for k in ("x", "v", "F"):
+        e = nerr(got[k], getattr(st, k))
+        log("shuffled forward step: %s %.2e" % (k, e))
+        assert e <= TOL, k
+    cot = [rng.standard_normal((n, 3)), rng.standard_normal((n, 3)), 64 * rng.standard_normal((n, 3, 3)),
+           rng.standard_normal((n, 3, 3))]
+    st = oracle.State(sc.x, sc.v, sc.B, sc.F, sc.mat, sc.logE)
+    status, ref = oracle.step_vjp(oracle.scene_config(sc), oracle.scene_materials(sc), st, sc.dt, *cot)
+    assert status == 0
+    cot_out = torch.from_numpy(np.concatenate([cot[0].T, cot[1].T, cot[2].reshape(n, 9).T, cot[3].reshape(n, 9).T])
+                               .astype(np.float32)).cuda().contiguous()
+    cot_in = torch.empty_like(cot_out)
+    lcot = torch.zeros(n, dtype=torch.float32, device="cuda")
+    ckmpm.check(ckmpm.mpm_ad_backward(ad.h, n, n, s0.data_ptr(), logE.data_ptr(), cot_out.data_ptr(),
+                                      cot_in.data_ptr(), lcot.data_ptr(), sc.dt, stream))
+    ckmpm.check(ckmpm.mpm_ad_sync(ad.h, stream))
+    g = cot_in.cpu().numpy().astype(np.float64)
+    got = dict(x=g[0:3].T, v=g[3:6].T, B=g[6:15].T.reshape(n, 3, 3), F=g[15:24].T.reshape(n, 3, 3),
+               logE=lcot.cpu().numpy())
+    for k in ("x", "v", "B", "F", "logE"):
+        e = nerr(got[k], ref[k])
+        log("shuffled reverse step: d/d%s %.2e" % (k, e))
         assert e <= 1e-4, k
     ad.close()
 
