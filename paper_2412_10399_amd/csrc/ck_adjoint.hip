@@ -413,11 +413,13 @@ __device__ void ad_tile_flush(const AdArgs &a, const AdTile &t, int plane0, int 
 }
 
 // ------------------------------------------------------------ kernels
+// Zeroes planes [first_plane, first_plane + nplanes): 2 * nodes floats per plane, so
+// every plane starts 8-byte aligned and the range is cleared two floats at a time.
 __global__ void k_ad_clear(AdArgs a, int first_plane, int nplanes) {
-    const long long total = (long long)nplanes * 2 * a.nodes;
-    float *g = plane(a, first_plane);
-    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total; t += (long long)gridDim.x * blockDim.x)
-        g[t] = 0.0f;
+    const long long total2 = (long long)nplanes * a.nodes;
+    float2 *g = reinterpret_cast<float2 *>(plane(a, first_plane));
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total2; t += (long long)gridDim.x * blockDim.x)
+        g[t] = make_float2(0.0f, 0.0f);
 }
 
 // P2G through the workgroup's node tile (direct float atomics when it does not fit).
@@ -819,7 +821,7 @@ int grid_blocks(long long work) {
 }
 
 void enqueue_forward_grid(const AdArgs &a, const float *state, const float *logE, hipStream_t s) {
-    hipLaunchKernelGGL(k_ad_clear, dim3(grid_blocks(4 * 2 * a.nodes)), dim3(256), 0, s, a, (int)GM, 4);
+    hipLaunchKernelGGL(k_ad_clear, dim3(grid_blocks(4 * a.nodes)), dim3(256), 0, s, a, (int)GM, 4);
     if (a.n > 0) hipLaunchKernelGGL(k_ad_p2g, dim3((a.n + 255) / 256), dim3(256), 0, s, a, state, logE);
     hipLaunchKernelGGL(k_ad_grid, dim3(grid_blocks(2 * a.nodes)), dim3(256), 0, s, a);
 }
@@ -900,7 +902,7 @@ mpm_status mpm_ad_backward(mpm_ad_ctx *c, int64_t n, int64_t stride, const float
     hipStream_t s = (hipStream_t)stream;
     const AdArgs a = make_args(c, n, stride, dt);
     enqueue_forward_grid(a, state_in, logE, s);
-    hipLaunchKernelGGL(k_ad_clear, dim3(grid_blocks(3 * 2 * a.nodes)), dim3(256), 0, s, a, (int)GVB, 3);
+    hipLaunchKernelGGL(k_ad_clear, dim3(grid_blocks(3 * a.nodes)), dim3(256), 0, s, a, (int)GVB, 3);
     if (n > 0)
         hipLaunchKernelGGL(k_ad_g2p_vjp, dim3((n + 255) / 256), dim3(256), 0, s, a, state_in, cot_out, cot_in);
     hipLaunchKernelGGL(k_ad_grid_vjp, dim3(grid_blocks(2 * a.nodes)), dim3(256), 0, s, a);
