@@ -950,10 +950,11 @@ __device__ __forceinline__ int g2p_finish(const DevCtx &d, const PartArgs &pa, f
     return g2p_finish_c(d, pa, dt, q, M, vn, Bh, Cc, out, write_tau, ns, cn, placed);
 }
 
-// G2P workgroups of 128 threads: the block's tile gather at the start of every block
-// is latency-bound, and six such workgroups per CU (against three of 256 threads at
-// the same three waves per SIMD) overlap more of those gathers with other blocks'
-// particle work (G2P 0.251 -> 0.238 ms on the sand column).
+// G2P workgroups of 128 threads (all G2P kernels): the block's tile gather at the
+// start of every block is latency-bound, and six such workgroups per CU (against
+// three of 256 threads at the same three waves per SIMD) overlap more of those
+// gathers with other blocks' particle work (G2P 0.251 -> 0.238 ms on the sand
+// column; the quadratic and gradient G2P gain 9 %).
 constexpr int kG2PThreads = 128;
 
 __device__ __forceinline__ void b_g2p(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt) {
@@ -1228,7 +1229,7 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g_grad(DevCtx d, PartArgs pa,
 // G2P with the exact velocity gradient: v = 1/2 sum w v~, B = 1/2 sum w v~ d^T (APIC;
 // zero for PIC), C = 1/2 sum v~ grad w^T, all relative to the velocity of one stencil
 // node (the weights of a grid sum to one, their gradients to zero).
-__global__ void __launch_bounds__(kThreads) k_g2p_grad(DevCtx d, PartArgs pa, float dt, int gp, int gt) {
+__global__ void __launch_bounds__(kG2PThreads) k_g2p_grad(DevCtx d, PartArgs pa, float dt, int gp, int gt) {
     __shared__ float vt[3 * kTileNodes];
     __shared__ int nbr[27];
     const bool pic = d.transfer == 2;
@@ -1248,7 +1249,7 @@ __global__ void __launch_bounds__(kThreads) k_g2p_grad(DevCtx d, PartArgs pa, fl
         if (tid < cnt) g2p_load(d, pa, (uint32_t)(s + tid), nxt);
         load_neighbours(d, gt, bx, by, bz, nbr);
         lds_barrier();
-        for (int ni = tid; ni < kTileNodes; ni += kThreads) {
+        for (int ni = tid; ni < kTileNodes; ni += kG2PThreads) {
             int g, ix, iy, iz;
             tile_node(ni, bx, by, bz, g, ix, iy, iz);
             const long long a = pool_index(d, nbr, bx, by, bz, g, ix, iy, iz, 1);
@@ -1256,11 +1257,11 @@ __global__ void __launch_bounds__(kThreads) k_g2p_grad(DevCtx d, PartArgs pa, fl
             for (int ch = 0; ch < 3; ++ch) vt[ch * kTileNodes + ni] = a >= 0 ? d.pool[gp][a + ch * 64] : 0.0f;
         }
         lds_barrier();
-        for (int j0 = 0; j0 < cnt; j0 += kThreads) {
+        for (int j0 = 0; j0 < cnt; j0 += kG2PThreads) {
             const int j = j0 + tid;
             const bool act = j < cnt;
             const G2PIn q = nxt;
-            if (j + kThreads < cnt) g2p_load(d, pa, (uint32_t)(s + j + kThreads), nxt);
+            if (j + kG2PThreads < cnt) g2p_load(d, pa, (uint32_t)(s + j + kG2PThreads), nxt);
             const uint32_t out = (uint32_t)(s + j);
             CellCoord cc;
             bool ok = act && cell_coord(d.geo, q.x, cc);
@@ -1527,7 +1528,7 @@ __global__ void __launch_bounds__(kP2GThreads, 4) k_p2g_quad(DevCtx d, PartArgs 
     }
 }
 
-__global__ void __launch_bounds__(kThreads) k_g2p_quad(DevCtx d, PartArgs pa, float dt, int gp, int gt) {
+__global__ void __launch_bounds__(kG2PThreads) k_g2p_quad(DevCtx d, PartArgs pa, float dt, int gp, int gt) {
     __shared__ float vt[3 * kQNodes];
     __shared__ int nbr[27];
     const int np = (int)d.counters[C_NPB];
@@ -1546,18 +1547,18 @@ __global__ void __launch_bounds__(kThreads) k_g2p_quad(DevCtx d, PartArgs pa, fl
         if (tid < cnt) g2p_load(d, pa, (uint32_t)(s + tid), nxt);
         load_neighbours(d, gt, bx, by, bz, nbr);
         lds_barrier();
-        for (int ni = tid; ni < kQNodes; ni += kThreads) {
+        for (int ni = tid; ni < kQNodes; ni += kG2PThreads) {
             const int ix = 4 * bx - 1 + ni % 7, iy = 4 * by - 1 + (ni / 7) % 7, iz = 4 * bz - 1 + ni / 49;
             const long long a = pool_index(d, nbr, bx, by, bz, 0, ix, iy, iz, 1);
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) vt[ch * kQNodes + ni] = a >= 0 ? d.pool[gp][a + ch * 64] : 0.0f;
         }
         lds_barrier();
-        for (int j0 = 0; j0 < cnt; j0 += kThreads) {
+        for (int j0 = 0; j0 < cnt; j0 += kG2PThreads) {
             const int j = j0 + tid;
             const bool act = j < cnt;
             const G2PIn q = nxt;
-            if (j + kThreads < cnt) g2p_load(d, pa, (uint32_t)(s + j + kThreads), nxt);
+            if (j + kG2PThreads < cnt) g2p_load(d, pa, (uint32_t)(s + j + kG2PThreads), nxt);
             const uint32_t out = (uint32_t)(s + j);
             CellCoord cc;
             bool ok = act && cell_coord(d.geo, q.x, cc);
@@ -1852,9 +1853,9 @@ void launch_grid_update(const DevCtx &d, float dt, const float gravity[3], int g
 
 void launch_g2p(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, hipStream_t s) {
     if (d.quadratic)
-        hipLaunchKernelGGL(k_g2p_quad, dim3(particle_grid(d)), dim3(kThreads), 0, s, d, pa, dt, gp, gt);
+        hipLaunchKernelGGL(k_g2p_quad, dim3(particle_grid(d)), dim3(kG2PThreads), 0, s, d, pa, dt, gp, gt);
     else if (d.transfer != 0)
-        hipLaunchKernelGGL(k_g2p_grad, dim3(particle_grid(d)), dim3(kThreads), 0, s, d, pa, dt, gp, gt);
+        hipLaunchKernelGGL(k_g2p_grad, dim3(particle_grid(d)), dim3(kG2PThreads), 0, s, d, pa, dt, gp, gt);
     else
         hipLaunchKernelGGL(k_g2p, dim3(particle_grid(d)), dim3(kG2PThreads), 0, s, d, pa, dt, gp, gt);
 }
