@@ -422,9 +422,34 @@ def main():
     }
     ctx.close()
     del parts
+    copy_gbs = measured_copy_gbs()
+    result["copy_bandwidth"] = {"GBs": copy_gbs, "kernel_frac": achieved / copy_gbs,
+                                "step_frac": result["step_roofline"]["achieved_GBs"] / copy_gbs,
+                                "probe": "device-to-device copy of 1 GiB, read + write bytes, mean of 5"}
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(scenes.sand_column())
     print(json.dumps(result), flush=True)
+
+
+def measured_copy_gbs(mib=1024, reps=5):
+    """HBM bandwidth a plain device copy reaches (bytes read + written per second),
+    timed with events after the step's timed region: the practical ceiling beside
+    the 8 TB/s specification."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    del src, dst
+    return 2.0 * n * 4 / sec / 1e9
 
 
 if __name__ == "__main__":
