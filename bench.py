@@ -319,8 +319,8 @@ def main():
                     help="serving: one launch per phase for all active jobs instead of per-job launches")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs the step on a single MI355X; "
-              "multi-GPU sharding is a design note only (--gpus %d requested)" % args.gpus, file=sys.stderr)
+        print("bench.py measures one GPU: the step runs on a single MI355X and sharding across GPUs "
+              "is not implemented (--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     if args.serving:
