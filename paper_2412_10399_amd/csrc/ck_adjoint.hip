@@ -413,15 +413,6 @@ __device__ void ad_tile_flush(const AdArgs &a, const AdTile &t, int plane0, int 
 }
 
 // ------------------------------------------------------------ kernels
-// Zeroes planes [first_plane, first_plane + nplanes): 2 * nodes floats per plane, so
-// every plane starts 8-byte aligned and the range is cleared two floats at a time.
-__global__ void k_ad_clear(AdArgs a, int first_plane, int nplanes) {
-    const long long total2 = (long long)nplanes * a.nodes;
-    float2 *g = reinterpret_cast<float2 *>(plane(a, first_plane));
-    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total2; t += (long long)gridDim.x * blockDim.x)
-        g[t] = make_float2(0.0f, 0.0f);
-}
-
 // P2G through the workgroup's node tile (direct float atomics when it does not fit).
 __global__ void __launch_bounds__(256) k_ad_p2g(AdArgs a, const float *state, const float *logE) {
     __shared__ unsigned long long tw[kAdTileWords];
@@ -490,15 +481,22 @@ __device__ __forceinline__ bool node_free(const AdArgs &a, long long id, int &g)
            ix <= a.geo.stick_hi[g][0] && iy <= a.geo.stick_hi[g][1] && iz <= a.geo.stick_hi[g][2];
 }
 
-__global__ void k_ad_grid(AdArgs a) {
-    const float *gm = plane(a, GM);
+// Grid update on the dense grids.  With zero_mp (a forward call: m and p have no
+// later reader) m and p are zeroed after the read, ready for the next P2G.
+__global__ void k_ad_grid(AdArgs a, int zero_mp) {
+    float *gm = plane(a, GM);
     for (long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x; id < 2 * a.nodes;
          id += (long long)gridDim.x * blockDim.x) {
         int g;
-        const bool live = gm[id] > 0.0f && node_free(a, id, g);
+        const float m = gm[id];
+        const bool live = m > 0.0f && node_free(a, id, g);
 #pragma unroll
-        for (int ax = 0; ax < 3; ++ax)
-            plane(a, GV + ax)[id] = live ? plane(a, GP + ax)[id] / gm[id] + a.dt * a.g[ax] : 0.0f;
+        for (int ax = 0; ax < 3; ++ax) {
+            float *pp = plane(a, GP + ax) + id;
+            plane(a, GV + ax)[id] = live ? *pp / m + a.dt * a.g[ax] : 0.0f;
+            if (zero_mp) *pp = 0.0f;
+        }
+        if (zero_mp) gm[id] = 0.0f;
     }
 }
 
@@ -687,8 +685,10 @@ __global__ void __launch_bounds__(256) k_ad_g2p_vjp(AdArgs a, const float *state
 }
 
 // Grid update reversed: pb = v~b / m,  mb = -(v~b . p) / m^2 on live nodes.
+// As the last reader of m, p and v~b in a backward call, it also zeroes them for the
+// next call's scatters.
 __global__ void k_ad_grid_vjp(AdArgs a) {
-    const float *gm = plane(a, GM);
+    float *gm = plane(a, GM);
     for (long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x; id < 2 * a.nodes;
          id += (long long)gridDim.x * blockDim.x) {
         int g;
@@ -698,11 +698,16 @@ __global__ void k_ad_grid_vjp(AdArgs a) {
         const float im = live ? 1.0f / m : 0.0f;
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
-            const float vb = plane(a, GVB + ax)[id];
+            float *vbp = plane(a, GVB + ax) + id;
+            float *pp = plane(a, GP + ax) + id;
+            const float vb = *vbp;
             plane(a, GPB + ax)[id] = vb * im;
-            dot += vb * plane(a, GP + ax)[id];
+            dot += vb * *pp;
+            *vbp = 0.0f;
+            *pp = 0.0f;
         }
         plane(a, GMB)[id] = live ? -dot * im * im : 0.0f;
+        gm[id] = 0.0f;
     }
 }
 
@@ -820,10 +825,10 @@ int grid_blocks(long long work) {
     return (int)(b < 8192 ? (b > 0 ? b : 1) : 8192);
 }
 
-void enqueue_forward_grid(const AdArgs &a, const float *state, const float *logE, hipStream_t s) {
-    hipLaunchKernelGGL(k_ad_clear, dim3(grid_blocks(4 * a.nodes)), dim3(256), 0, s, a, (int)GM, 4);
+// P2G into the (zero) m and p planes and the grid update; zero_mp for a forward call.
+void enqueue_forward_grid(const AdArgs &a, const float *state, const float *logE, int zero_mp, hipStream_t s) {
     if (a.n > 0) hipLaunchKernelGGL(k_ad_p2g, dim3((a.n + 255) / 256), dim3(256), 0, s, a, state, logE);
-    hipLaunchKernelGGL(k_ad_grid, dim3(grid_blocks(2 * a.nodes)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_ad_grid, dim3(grid_blocks(2 * a.nodes)), dim3(256), 0, s, a, zero_mp);
 }
 
 mpm_status check_call(const mpm_ad_ctx *c, int64_t n, int64_t stride, const float *state, double dt) {
@@ -859,6 +864,12 @@ mpm_status mpm_ad_create(const mpm_config *cfg, const mpm_material *mat, mpm_ad_
         delete c;
         return MPM_E_OOM;
     }
+    // the scatter targets (m, p, v~b) start at zero; every call leaves them at zero
+    if (hipMemset(c->grid, 0, bytes) != hipSuccess) {
+        (void)hipFree(c->grid);
+        delete c;
+        return MPM_E_HIP;
+    }
     if (hipMalloc(&c->status, sizeof(unsigned int)) != hipSuccess ||
         hipMemset(c->status, 0, sizeof(unsigned int)) != hipSuccess) {
         (void)hipFree(c->grid);
@@ -888,7 +899,7 @@ mpm_status mpm_ad_forward(mpm_ad_ctx *c, int64_t n, int64_t stride, const float 
     if (hipSetDevice(c->device) != hipSuccess) return MPM_E_HIP;
     hipStream_t s = (hipStream_t)stream;
     const AdArgs a = make_args(c, n, stride, dt);
-    enqueue_forward_grid(a, state_in, logE, s);
+    enqueue_forward_grid(a, state_in, logE, 1, s);
     if (n > 0) hipLaunchKernelGGL(k_ad_g2p, dim3((n + 255) / 256), dim3(256), 0, s, a, state_in, state_out);
     return hipGetLastError() == hipSuccess ? MPM_OK : MPM_E_HIP;
 }
@@ -901,8 +912,7 @@ mpm_status mpm_ad_backward(mpm_ad_ctx *c, int64_t n, int64_t stride, const float
     if (hipSetDevice(c->device) != hipSuccess) return MPM_E_HIP;
     hipStream_t s = (hipStream_t)stream;
     const AdArgs a = make_args(c, n, stride, dt);
-    enqueue_forward_grid(a, state_in, logE, s);
-    hipLaunchKernelGGL(k_ad_clear, dim3(grid_blocks(3 * a.nodes)), dim3(256), 0, s, a, (int)GVB, 3);
+    enqueue_forward_grid(a, state_in, logE, 0, s);
     if (n > 0)
         hipLaunchKernelGGL(k_ad_g2p_vjp, dim3((n + 255) / 256), dim3(256), 0, s, a, state_in, cot_out, cot_in);
     hipLaunchKernelGGL(k_ad_grid_vjp, dim3(grid_blocks(2 * a.nodes)), dim3(256), 0, s, a);
