@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define CKMPM_ABI_VERSION 1
+#define CKMPM_ABI_VERSION 2
 #define MPM_STATE_PLANES 24
 
 typedef struct mpm_ctx mpm_ctx; /* opaque, owned by the library */
@@ -90,7 +90,20 @@ typedef struct {
                               sort buckets of up to 2048 particles per block)                      */
     int32_t transfer;      /* MPM_TRANSFER_MLS, _APIC or _PIC                                       */
     int32_t flags;         /* 0, MPM_FLAG_FUSED_G2P2G or MPM_FLAG_QUADRATIC                          */
+    int32_t deterministic; /* 0 or 1: bitwise reproducible steps (see below)                        */
 } mpm_config;
+
+/* mpm_config.deterministic = 1: every result is a function of the inputs alone, so
+ * equal inputs give bitwise equal outputs from run to run, alone or beside other
+ * work, and a run resumed from a copy of its particle state continues bitwise as
+ * the uninterrupted run would.  The only order-dependent sums of the step are the
+ * P2G's cross-block additions into the grid (sections 4.3-4.5; per block the
+ * fixed-point tile sums are exact).  In this mode each particle block leaves its
+ * tile in a staging area (4 x 341 floats per block of max_blocks, allocated in
+ * mpm_create) and a gather adds the tiles of the blocks around every node in a fixed
+ * order in FP64; the Kirchhoff stress is recomputed from F by every P2G instead of
+ * being carried from the previous G2P.  Requires the compact kernel with the MLS
+ * transfer and flags 0 (else MPM_E_INVALID). */
 
 typedef struct {
     int32_t model;         /* MPM_FIXED_COROTATED or MPM_DRUCKER_PRAGER                             */
@@ -164,11 +177,18 @@ mpm_status mpm_step(mpm_ctx *ctx, mpm_particles *p, double dt, int32_t nsteps, v
  * NONFINITE before DOMAIN before CAPACITY before STALE before CFL. */
 mpm_status mpm_sync(mpm_ctx *ctx, void *stream);
 
-/* Export the grid as dense arrays (device pointers): m[2][nz+1][ny+1][nx+1] and
- * vec[2][nz+1][ny+1][nx+1][3], grid 0 = G-, 1 = G+.  After mpm_p2g vec holds momentum,
- * after mpm_grid_update it holds v~.  Nodes outside active blocks are written as 0.
- * Either pointer may be NULL.  For tests and diagnostics. */
-mpm_status mpm_grid_read(mpm_ctx *ctx, float *m, float *vec, void *stream);
+/* Export grid `grid` as dense arrays (device pointers): -1 for G-, +1 for G+, each as
+ * m[nz+1][ny+1][nx+1] and vec[nz+1][ny+1][nx+1][3]; 0 for both, as m[2][..] and
+ * vec[2][..][3] with index 0 = G-, 1 = G+.  After mpm_p2g vec holds momentum, after
+ * mpm_grid_update it holds v~.  Nodes outside active blocks are written as 0.
+ * Either pointer may be NULL; any other `grid` is MPM_E_INVALID.  For tests and
+ * diagnostics. */
+mpm_status mpm_grid_read(mpm_ctx *ctx, int32_t grid, float *m, float *vec, void *stream);
+
+/* Which ping-pong buffer (0 or 1) the last mpm_g2p or mpm_step of this context wrote
+ * the particle state into -- the value it left in mpm_particles.current -- or -1
+ * before the first one (or for a NULL context). */
+int32_t mpm_current_buffer(const mpm_ctx *ctx);
 
 /* Cell keys of the current buffer (computed from positions) and the stable sorting
  * permutation by key: keys[p] = block * 64 + cell (block = 4^3-cell block of the G- cell
@@ -239,6 +259,9 @@ typedef struct {
                                   admission, so it must stay valid while the job is pending           */
     const uint8_t *mat;        /* optional per-particle material index (device, n), or NULL           */
     double dt;
+    void *stream;              /* hipStream_t on which state and mat were produced (NULL = the null
+                                  stream): the admission copy waits for the work queued there before
+                                  mpm_server_submit (an event recorded at submission)               */
 } mpm_job_desc;
 
 enum { MPM_JOB_PENDING = 0, MPM_JOB_ACTIVE = 1, MPM_JOB_DONE = 2, MPM_JOB_FAILED = 3 };

@@ -37,7 +37,7 @@ class mpm_config(ctypes.Structure):
     _fields_ = [("n_cells", ctypes.c_int32 * 3), ("dx", ctypes.c_double), ("origin", ctypes.c_double * 3),
                 ("gravity", ctypes.c_double * 3), ("bc", ctypes.c_int32), ("bc_band", ctypes.c_int32),
                 ("max_particles", ctypes.c_int64), ("max_blocks", ctypes.c_int64), ("transfer", ctypes.c_int32),
-                ("flags", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("deterministic", ctypes.c_int32)]
 
 
 class mpm_material(ctypes.Structure):
@@ -65,7 +65,7 @@ class mpm_server_config(ctypes.Structure):
 class mpm_job_desc(ctypes.Structure):
     _fields_ = [("cfg", mpm_config), ("mats", ctypes.POINTER(mpm_material)), ("n_mat", ctypes.c_int32),
                 ("nsteps", ctypes.c_int32), ("n", ctypes.c_int64), ("state", ctypes.c_void_p),
-                ("mat", ctypes.c_void_p), ("dt", ctypes.c_double)]
+                ("mat", ctypes.c_void_p), ("dt", ctypes.c_double), ("stream", ctypes.c_void_p)]
 
 
 class mpm_job_info(ctypes.Structure):
@@ -78,7 +78,7 @@ MPM_JOB_PENDING, MPM_JOB_ACTIVE, MPM_JOB_DONE, MPM_JOB_FAILED = range(4)
 MPM_SERVER_GROUPED = 1
 
 EXPORTS = ("mpm_create", "mpm_destroy", "mpm_p2g", "mpm_grid_update", "mpm_g2p", "mpm_step", "mpm_sync",
-           "mpm_grid_read", "mpm_sort_keys", "mpm_invalidate", "mpm_get_stats", "mpm_profile_enable",
+           "mpm_grid_read", "mpm_current_buffer", "mpm_sort_keys", "mpm_invalidate", "mpm_get_stats", "mpm_profile_enable",
            "mpm_profile_read", "mpm_status_string", "mpm_abi_version", "mpm_footprint", "mpm_server_create",
            "mpm_server_destroy", "mpm_server_submit", "mpm_server_poll", "mpm_server_drain", "mpm_server_job_info",
            "mpm_server_job_read", "mpm_server_job_release", "mpm_server_step_latencies", "mpm_ad_create",
@@ -100,7 +100,8 @@ def lib():
         L.mpm_g2p.argtypes = [vp, ctypes.POINTER(mpm_particles), ctypes.c_double, vp]
         L.mpm_step.argtypes = [vp, ctypes.POINTER(mpm_particles), ctypes.c_double, ctypes.c_int32, vp]
         L.mpm_sync.argtypes = [vp, vp]
-        L.mpm_grid_read.argtypes = [vp, vp, vp, vp]
+        L.mpm_grid_read.argtypes = [vp, ctypes.c_int32, vp, vp, vp]
+        L.mpm_current_buffer.argtypes = [vp]
         L.mpm_sort_keys.argtypes = [vp, ctypes.POINTER(mpm_particles), vp, vp, vp]
         L.mpm_invalidate.argtypes = [vp]
         L.mpm_get_stats.argtypes = [vp, ctypes.POINTER(mpm_stats), vp]
@@ -128,8 +129,9 @@ def lib():
         L.mpm_ad_backward.argtypes = [vp, ctypes.c_int64, ctypes.c_int64, vp, vp, vp, vp, vp, ctypes.c_double, vp]
         L.mpm_ad_sync.argtypes = [vp, vp]
         for name in EXPORTS:
-            if name not in ("mpm_status_string", "mpm_abi_version", "mpm_footprint"):
+            if name not in ("mpm_status_string", "mpm_abi_version", "mpm_footprint", "mpm_current_buffer"):
                 getattr(L, name).restype = st
+        L.mpm_current_buffer.restype = ctypes.c_int32
         _lib = L
     return _lib
 
@@ -174,8 +176,12 @@ def mpm_sync(ctx, stream=None) -> int:
     return lib().mpm_sync(ctx, _stream(stream))
 
 
-def mpm_grid_read(ctx, m_ptr: Optional[int], vec_ptr: Optional[int], stream=None) -> int:
-    return lib().mpm_grid_read(ctx, m_ptr, vec_ptr, _stream(stream))
+def mpm_grid_read(ctx, grid: int, m_ptr: Optional[int], vec_ptr: Optional[int], stream=None) -> int:
+    return lib().mpm_grid_read(ctx, int(grid), m_ptr, vec_ptr, _stream(stream))
+
+
+def mpm_current_buffer(ctx) -> int:
+    return int(lib().mpm_current_buffer(ctx))
 
 
 def mpm_sort_keys(ctx, parts: mpm_particles, keys_ptr: Optional[int], perm_ptr: Optional[int], stream=None) -> int:
@@ -303,7 +309,8 @@ def check(status: int, what: str = "ckmpm") -> None:
 
 # --------------------------------------------------------- struct construction
 def make_config(n_cells, dx, origin=(0.0, 0.0, 0.0), gravity=(0.0, 0.0, 0.0), bc_band=0, max_particles=1,
-                max_blocks=1024, bc=None, fused=False, quadratic=False, transfer=0) -> mpm_config:
+                max_blocks=1024, bc=None, fused=False, quadratic=False, transfer=0,
+                deterministic=False) -> mpm_config:
     c = mpm_config()
     for a in range(3):
         c.n_cells[a] = int(n_cells[a])
@@ -316,6 +323,7 @@ def make_config(n_cells, dx, origin=(0.0, 0.0, 0.0), gravity=(0.0, 0.0, 0.0), bc
     c.max_blocks = int(max_blocks)
     c.transfer = int(transfer)
     c.flags = (MPM_FLAG_FUSED_G2P2G if fused else 0) | (MPM_FLAG_QUADRATIC if quadratic else 0)
+    c.deterministic = 1 if deterministic else 0
     return c
 
 
@@ -432,7 +440,8 @@ class Context:
             pass
 
 
-def scene_config(sc, max_particles=None, max_blocks=None, fused=False, quadratic=False, transfer=0) -> mpm_config:
+def scene_config(sc, max_particles=None, max_blocks=None, fused=False, quadratic=False, transfer=0,
+                 deterministic=False) -> mpm_config:
     """mpm_config for a scene from the `scenes` package."""
     n = sc.n if max_particles is None else max_particles
     if max_blocks is None:
@@ -441,7 +450,7 @@ def scene_config(sc, max_particles=None, max_blocks=None, fused=False, quadratic
             nb *= sc.n_cells[a] // 4 + 1
         max_blocks = min(nb, 2 * (n // 256) + 4096)
     return make_config(sc.n_cells, sc.dx, sc.origin, sc.gravity, sc.bc_band, max(n, 1), max_blocks, fused=fused,
-                       quadratic=quadratic, transfer=transfer)
+                       quadratic=quadratic, transfer=transfer, deterministic=deterministic)
 
 
 def scene_materials(sc):
@@ -454,7 +463,7 @@ def particles_from_scene(sc, device="cuda") -> Particles:
     return p
 
 
-def job_config(sc, margin_blocks: int = 3, fused=False) -> mpm_config:
+def job_config(sc, margin_blocks: int = 3, fused=False, deterministic=False) -> mpm_config:
     """mpm_config for a served job: capacities sized to the scene's extent (blocks
     of the particles' bounding box grown by a margin on every side, twice over for
     the two grids) rather than to the whole grid."""
@@ -464,7 +473,7 @@ def job_config(sc, margin_blocks: int = 3, fused=False) -> mpm_config:
     nb = 1
     for a in range(3):
         nb *= int((hi[a] - lo[a]) // 4 + 2 + 2 * margin_blocks)
-    return scene_config(sc, max_particles=sc.n, max_blocks=2 * nb + 64, fused=fused)
+    return scene_config(sc, max_particles=sc.n, max_blocks=2 * nb + 64, fused=fused, deterministic=deterministic)
 
 
 class Server:
@@ -497,16 +506,20 @@ class Server:
         d.state = state.data_ptr()
         d.mat = mat.data_ptr() if mat is not None else None
         d.dt = float(dt)
+        # the admission copy waits for the work torch queued on its current stream,
+        # which produced `state` and `mat`
+        import torch
+        d.stream = _stream(torch.cuda.current_stream())
         s, jid = mpm_server_submit(self.h, d)
         check(s, "mpm_server_submit")
         self._inputs[jid] = (state, mat)
         return jid
 
-    def submit_scene(self, sc, nsteps: int, device="cuda") -> int:
+    def submit_scene(self, sc, nsteps: int, device="cuda", deterministic=False) -> int:
         import torch
         state = torch.from_numpy(state_planes(sc.x, sc.v, sc.B, sc.F)).to(device)
         mat = torch.from_numpy(sc.mat.astype("uint8")).to(device) if len(sc.materials) > 1 else None
-        return self.submit(job_config(sc), scene_materials(sc), state, nsteps, sc.dt, mat)
+        return self.submit(job_config(sc, deterministic=deterministic), scene_materials(sc), state, nsteps, sc.dt, mat)
 
     def poll(self):
         s, p, a, d = mpm_server_poll(self.h)

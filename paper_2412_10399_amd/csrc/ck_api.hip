@@ -28,6 +28,7 @@ struct mpm_ctx {
     const float *p2g_done = nullptr;     // buffer the last p2g ran on
     int grid_pool = 0, grid_table = 0;   // the grid the last p2g (or fused step) wrote: pool and page table
     int next_table = 0;                  // page table the next sort builds
+    int written = -1;                    // buffer the last g2p wrote (mpm_current_buffer)
     unsigned int *host_counters = nullptr;
     // profiling
     bool prof = false;
@@ -83,6 +84,8 @@ mpm_status validate_config(const mpm_config *c, const mpm_material *m, int32_t n
     if ((c->flags & ~(MPM_FLAG_FUSED_G2P2G | MPM_FLAG_QUADRATIC)) != 0) return MPM_E_INVALID;
     if ((c->flags & MPM_FLAG_FUSED_G2P2G) && (c->flags & MPM_FLAG_QUADRATIC)) return MPM_E_INVALID;
     if (c->flags != 0 && c->transfer != MPM_TRANSFER_MLS) return MPM_E_INVALID;
+    if (c->deterministic != 0 && c->deterministic != 1) return MPM_E_INVALID;
+    if (c->deterministic && (c->flags != 0 || c->transfer != MPM_TRANSFER_MLS)) return MPM_E_INVALID;
     for (int i = 0; i < n_mat; ++i) {
         const mpm_material &q = m[i];
         if (q.model != MPM_FIXED_COROTATED && q.model != MPM_DRUCKER_PRAGER) return MPM_E_INVALID;
@@ -148,17 +151,8 @@ void *hip_alloc(void *, size_t bytes) {
 }
 void hip_free(void *, void *p) { (void)hipFree(p); }
 
-template <typename T>
-mpm_status dalloc(mpm_ctx *ctx, T **ptr, size_t count) {
-    void *p = ctx->alloc.alloc(ctx->alloc.self, count * sizeof(T) + 256);
-    if (!p) return MPM_E_OOM;
-    ctx->allocs.push_back(p);
-    *ptr = static_cast<T *>(p);
-    return MPM_OK;
-}
-
-// Bytes of every device buffer a context allocates: dalloc asks for 256 bytes of
-// slack per buffer, and allocators hand out multiples of 256 bytes.
+// Bytes of every device buffer a context allocates: carve_buffers asks for 256 bytes
+// of slack per buffer, and allocators hand out multiples of 256 bytes.
 int64_t device_bytes_of(const mpm_config &c) {
     long long nbv = 1;
     for (int a = 0; a < 3; ++a) nbv *= (c.n_cells[a] / 4 + 1);
@@ -169,7 +163,8 @@ int64_t device_bytes_of(const mpm_config &c) {
     return r(4 * np) + r(2 * np) + r(4 * np) + r(4 * nb * (long long)kMaxBlockParticles) +
            r(2 * nb * (long long)kMaxBlockParticles) + 2 * r(8 * stamp_stride(nbv)) + 2 * r(4 * nbv) + r(4 * nbv) +
            r(4 * nb) + r(4 * (nb + 1)) + r(4 * nb) + 2 * r(4 * nb) + r(4 * nchunks) + r(4 * nchunks) +
-           2 * r(4 * nb * (long long)kBlockFloats) + r(24 * np) + r(4 * (long long)C_COUNT);
+           2 * r(4 * nb * (long long)kBlockFloats) + r(24 * np) + r(4 * (long long)C_COUNT) +
+           (c.deterministic ? r(4 * nb * (long long)kStageFloats) : 0);
 }
 
 PartArgs part_args(const mpm_particles *p, bool with_out) {
@@ -230,8 +225,11 @@ mpm_status enqueue_p2g(mpm_ctx *ctx, const mpm_particles *p, double dt, hipStrea
     if (!physics) {
         launch_block_sort(ctx->d, s);
     } else {
-        if (!ready) launch_stress(ctx->d, pa, s);
+        // deterministic mode recomputes the stress from F every step, so that a run
+        // resumed from its particle state sees the same stress as the uninterrupted run
+        if (!ready || ctx->d.det) launch_stress(ctx->d, pa, s);
         launch_p2g(ctx->d, pa, (float)dt, t, t, s);
+        if (ctx->d.det) launch_det_gather(ctx->d, t, t, s);
         ctx->grid_pool = t;
         ctx->grid_table = t;
     }
@@ -255,10 +253,54 @@ mpm_status enqueue_g2p(mpm_ctx *ctx, mpm_particles *p, double dt, hipStream_t s)
     const PartArgs pa = part_args(p, true);
     launch_g2p(ctx->d, pa, (float)dt, ctx->grid_pool, ctx->grid_table, s);
     p->current ^= 1;
+    ctx->written = p->current;
     ctx->next_ready = pa.out;
     ctx->next_n = pa.n;
     ctx->p2g_done = nullptr;
     return last_error();
+}
+
+// Device-context fields of a validated configuration (everything but the buffers).
+void fill_devctx(DevCtx &d, const mpm_config &cfg, const mpm_material *mats, int32_t n_mat) {
+    std::memset(&d, 0, sizeof d);
+    fill_geometry(cfg, d.geo);
+    d.quadratic = (cfg.flags & MPM_FLAG_QUADRATIC) ? 1 : 0;
+    d.transfer = cfg.transfer;
+    for (int i = 0; i < n_mat; ++i) d.mats[i] = dev_material(mats[i]);
+    d.n_mat = n_mat;
+    d.max_blocks = (int)cfg.max_blocks;
+    d.nbv = (long long)d.geo.NB[0] * d.geo.NB[1] * d.geo.NB[2];
+    d.tau_stride = (long long)cfg.max_particles;
+    d.det = cfg.deterministic ? 1 : 0;
+}
+
+template <typename T, typename Take>
+bool take_buffer(Take &take, T **ptr, size_t count) {
+    // 256 bytes of slack per buffer, as device_bytes_of counts them
+    *ptr = static_cast<T *>(take(count * sizeof(T) + 256));
+    return *ptr != nullptr;
+}
+
+// Every device buffer of a context, in the order device_bytes_of counts them, from
+// `take(bytes)` (nullptr when it cannot): MPM_E_OOM when one is refused.
+template <typename Take>
+mpm_status carve_buffers(DevCtx &d, const mpm_config &cfg, Take take) {
+    const size_t np = (size_t)cfg.max_particles, nb = (size_t)cfg.max_blocks, nv = (size_t)d.nbv;
+    const size_t nchunks = (nv + kCompactChunk - 1) / kCompactChunk;
+    const bool ok = take_buffer(take, &d.key, np) && take_buffer(take, &d.sub, np) && take_buffer(take, &d.perm, np) &&
+                    take_buffer(take, &d.bucket, nb * (size_t)kMaxBlockParticles) &&
+                    take_buffer(take, &d.bsub, nb * (size_t)kMaxBlockParticles) &&
+                    take_buffer(take, &d.pflag, 2 * (size_t)stamp_stride(d.nbv)) &&
+                    take_buffer(take, &d.gflag, 2 * (size_t)stamp_stride(d.nbv)) &&
+                    take_buffer(take, &d.page[0], nv) && take_buffer(take, &d.page[1], nv) &&
+                    take_buffer(take, &d.prank, nv) && take_buffer(take, &d.plist, nb) &&
+                    take_buffer(take, &d.pstart, nb + 1) && take_buffer(take, &d.bcount, nb) &&
+                    take_buffer(take, &d.glist[0], nb) && take_buffer(take, &d.glist[1], nb) &&
+                    take_buffer(take, &d.chunk_p, nchunks) && take_buffer(take, &d.chunk_g, nchunks) &&
+                    take_buffer(take, &d.pool[0], nb * kBlockFloats) && take_buffer(take, &d.pool[1], nb * kBlockFloats) &&
+                    take_buffer(take, &d.tau, 6 * np) && take_buffer(take, &d.counters, (size_t)C_COUNT) &&
+                    (!d.det || take_buffer(take, &d.stage, nb * (size_t)kStageFloats));
+    return ok ? MPM_OK : MPM_E_OOM;
 }
 
 }  // namespace
@@ -281,39 +323,13 @@ mpm_status ctx_create(const mpm_config *cfg, const mpm_material *mats, int32_t n
         return MPM_E_HIP;
     }
     DevCtx &d = ctx->d;
-    std::memset(&d, 0, sizeof d);
-    fill_geometry(*cfg, d.geo);
-    d.quadratic = (cfg->flags & MPM_FLAG_QUADRATIC) ? 1 : 0;
-    d.transfer = cfg->transfer;
-    for (int i = 0; i < n_mat; ++i) d.mats[i] = dev_material(mats[i]);
-    d.n_mat = n_mat;
-    d.max_blocks = (int)cfg->max_blocks;
-    d.nbv = (long long)d.geo.NB[0] * d.geo.NB[1] * d.geo.NB[2];
-    const size_t np = (size_t)cfg->max_particles, nb = (size_t)cfg->max_blocks, nv = (size_t)d.nbv;
-    const size_t nchunks = (nv + kCompactChunk - 1) / kCompactChunk;
-    mpm_status st = MPM_OK;
-    if (st == MPM_OK) st = dalloc(ctx, &d.key, np);
-    if (st == MPM_OK) st = dalloc(ctx, &d.sub, np);
-    if (st == MPM_OK) st = dalloc(ctx, &d.perm, np);
-    if (st == MPM_OK) st = dalloc(ctx, &d.bucket, nb * (size_t)kMaxBlockParticles);
-    if (st == MPM_OK) st = dalloc(ctx, &d.bsub, nb * (size_t)kMaxBlockParticles);
-    if (st == MPM_OK) st = dalloc(ctx, &d.pflag, 2 * (size_t)stamp_stride(d.nbv));
-    if (st == MPM_OK) st = dalloc(ctx, &d.gflag, 2 * (size_t)stamp_stride(d.nbv));
-    if (st == MPM_OK) st = dalloc(ctx, &d.page[0], nv);
-    if (st == MPM_OK) st = dalloc(ctx, &d.page[1], nv);
-    if (st == MPM_OK) st = dalloc(ctx, &d.prank, nv);
-    if (st == MPM_OK) st = dalloc(ctx, &d.plist, nb);
-    if (st == MPM_OK) st = dalloc(ctx, &d.pstart, nb + 1);
-    if (st == MPM_OK) st = dalloc(ctx, &d.bcount, nb);
-    if (st == MPM_OK) st = dalloc(ctx, &d.glist[0], nb);
-    if (st == MPM_OK) st = dalloc(ctx, &d.glist[1], nb);
-    if (st == MPM_OK) st = dalloc(ctx, &d.chunk_p, nchunks);
-    if (st == MPM_OK) st = dalloc(ctx, &d.chunk_g, nchunks);
-    if (st == MPM_OK) st = dalloc(ctx, &d.pool[0], nb * kBlockFloats);
-    if (st == MPM_OK) st = dalloc(ctx, &d.pool[1], nb * kBlockFloats);
-    if (st == MPM_OK) st = dalloc(ctx, &d.tau, 6 * np);
-    d.tau_stride = (long long)np;
-    if (st == MPM_OK) st = dalloc(ctx, &d.counters, (size_t)C_COUNT);
+    fill_devctx(d, *cfg, mats, n_mat);
+    mpm_status st = carve_buffers(d, *cfg, [ctx](size_t bytes) -> void * {
+        void *p = ctx->alloc.alloc(ctx->alloc.self, bytes);
+        if (p) ctx->allocs.push_back(p);
+        return p;
+    });
+    const size_t nb = (size_t)cfg->max_blocks, nv = (size_t)d.nbv;
     if (st == MPM_OK) {
         if (hipHostMalloc((void **)&ctx->host_counters, C_COUNT * sizeof(unsigned int), hipHostMallocDefault) == hipSuccess)
             ctx->host_counters_pinned = true;
@@ -385,6 +401,7 @@ mpm_status group_step(mpm_ctx *ctx, mpm_particles *p, double dt, JobStep &out) {
     out.table = t;
     out.first = ready ? 0 : 1;
     p->current ^= 1;
+    ctx->written = p->current;
     ctx->next_ready = pa.out;
     ctx->next_n = pa.n;
     ctx->p2g_done = nullptr;
@@ -517,6 +534,7 @@ mpm_status mpm_step(mpm_ctx *ctx, mpm_particles *p, double dt, int32_t nsteps, v
         const PartArgs pa = part_args(p, true);
         launch_g2p2g(ctx->d, pa, (float)dt, gin, tin, gout, tout, s);
         p->current ^= 1;
+        ctx->written = p->current;
         ctx->grid_pool = gout;
         ctx->grid_table = tout;
         if (ev) (void)hipEventRecord(ev[2], s);
@@ -555,12 +573,15 @@ mpm_status mpm_sync(mpm_ctx *ctx, void *stream) {
     return status_from_bits(bits);
 }
 
-mpm_status mpm_grid_read(mpm_ctx *ctx, float *m, float *vec, void *stream) {
-    if (!ctx) return MPM_E_INVALID;
+mpm_status mpm_grid_read(mpm_ctx *ctx, int32_t grid, float *m, float *vec, void *stream) {
+    if (!ctx || (grid != -1 && grid != 0 && grid != 1)) return MPM_E_INVALID;
     DeviceGuard g(ctx->device);
-    launch_grid_export(ctx->d, m, vec, ctx->grid_pool, ctx->grid_table, (hipStream_t)stream);
+    const int g0 = grid == 1 ? 1 : 0, ng = grid == 0 ? 2 : 1;
+    launch_grid_export(ctx->d, m, vec, ctx->grid_pool, ctx->grid_table, g0, ng, (hipStream_t)stream);
     return last_error();
 }
+
+int32_t mpm_current_buffer(const mpm_ctx *ctx) { return ctx ? ctx->written : -1; }
 
 mpm_status mpm_sort_keys(mpm_ctx *ctx, const mpm_particles *p, uint32_t *keys, uint32_t *perm, void *stream) {
     const mpm_status v = validate_particles(ctx, p);

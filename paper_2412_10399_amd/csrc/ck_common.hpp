@@ -87,7 +87,11 @@ struct DevCtx {
     float *tau;            // [6][max_particles] Kirchhoff stress of the state G2P wrote, at its sorted position
     long long tau_stride;
     unsigned int *counters;
+    int det;               // deterministic P2G: block tiles go to `stage`, then a fixed-order gather
+    float *stage;          // [max_blocks][4 channels][kTileNodes] per particle block (deterministic mode)
 };
+
+constexpr int kStageFloats = 4 * kTileNodes;   // one particle block's tile in the deterministic staging area
 
 struct PartArgs {
     const float *in;       // 24 planes
@@ -685,8 +689,9 @@ void launch_block_sort(const DevCtx &d, hipStream_t s);
 void launch_stress(const DevCtx &d, const PartArgs &pa, hipStream_t s);
 void launch_p2g(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, hipStream_t s);
 void launch_grid_update(const DevCtx &d, float dt, const float gravity[3], int gp, int gt, hipStream_t s);
+void launch_det_gather(const DevCtx &d, int gp, int gt, hipStream_t s);
 void launch_g2p(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, hipStream_t s);
-void launch_grid_export(const DevCtx &d, float *m, float *vec, int gp, int gt, hipStream_t s);
+void launch_grid_export(const DevCtx &d, float *m, float *vec, int gp, int gt, int g0, int ng, hipStream_t s);
 void launch_block_order(const DevCtx &d, hipStream_t s);
 void launch_g2p2g(const DevCtx &d, const PartArgs &pa, float dt, int gp_in, int gt_in, int gp_out, int gt_out,
                   hipStream_t s);

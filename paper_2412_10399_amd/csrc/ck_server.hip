@@ -3,7 +3,10 @@
 // first-fit into the contexts and particle buffers of resident jobs, and a set of
 // non-blocking streams; every resident job advances a fixed number of steps per
 // launch on its stream, and all launches after a job's first replay one HIP graph
-// captured from that job's step sequence.  Nothing here allocates device memory
+// captured from that job's step sequence.  In grouped mode a round runs every phase
+// of every active job as shared launches; the round's launch sequence is captured in
+// a HIP graph and replayed while the set of jobs and their step counts stay the
+// same, and captured again when they change.  Nothing here allocates device memory
 // after mpm_server_create, and no call synchronises the whole device.
 #include <algorithm>
 #include <chrono>
@@ -104,6 +107,10 @@ struct Job {
     int chunk = 0;                      // steps of the launch in flight
     int ev_cur = 0;                     // event the launch in flight records
     hipGraphExec_t graph = nullptr;
+    hipEvent_t ready = nullptr;         // recorded on the submitter's stream: the input is complete
+    ~Job() {
+        if (ready) (void)hipEventDestroy(ready);
+    }
 };
 
 struct Slot {
@@ -127,6 +134,9 @@ struct mpm_server {
     hipEvent_t gev[2] = {nullptr, nullptr};   // start and end of the round in flight
     bool round_in_flight = false;
     std::vector<std::pair<int64_t, int>> round;   // (job, steps) of the round in flight
+    hipGraphExec_t round_graph = nullptr;         // the last round's captured launch sequence
+    std::vector<int64_t> round_sig;               // what it was captured for (see poll_grouped)
+    int64_t graph_captures = 0, graph_replays = 0;
     Arena arena;
     std::vector<hipStream_t> streams;
     hipStream_t init_stream = nullptr;
@@ -228,7 +238,9 @@ bool admit(mpm_server *srv, Job &j) {
     j.parts.mat[0] = with_mat ? m0 : nullptr;
     j.parts.mat[1] = with_mat ? m1 : nullptr;
     j.parts.current = 0;
-    bool ok = hipMemcpyAsync(st0, j.desc.state, state_bytes, hipMemcpyDeviceToDevice, s) == hipSuccess;
+    // the copy-in waits for the work the submitter queued before submitting
+    bool ok = !j.ready || hipStreamWaitEvent(s, j.ready, 0) == hipSuccess;
+    ok = ok && hipMemcpyAsync(st0, j.desc.state, state_bytes, hipMemcpyDeviceToDevice, s) == hipSuccess;
     if (with_mat) ok = ok && hipMemcpyAsync(m0, j.desc.mat, (size_t)n, hipMemcpyDeviceToDevice, s) == hipSuccess;
     const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
     hipLaunchKernelGGL(k_iota, dim3(blocks), dim3(256), 0, s, id0, (long long)n);
@@ -361,18 +373,56 @@ mpm_status poll_grouped(mpm_server *srv, bool *progressed) {
                     steps[r] += 1;
                 }
             }
-            ok = ok && hipMemcpyAsync(srv->table_dev, srv->table_host, used * sizeof(ck::JobStep),
-                                      hipMemcpyHostToDevice, s) == hipSuccess;
-            size_t off = 0;
-            for (int k = 0; k < spl && ok; ++k) {
-                if (count[k] == 0) break;
-                ck::launch_step_multi(srv->table_dev + off, srv->table_host + off, count[k], s);
-                off += (size_t)count[k];
+            // the round's launches depend only on which job takes which table entry and
+            // whether that entry is the job's first step; the table's contents are
+            // uploaded by the graph's own copy from pinned memory on every replay
+            std::vector<int64_t> sig;
+            sig.reserve(used + (size_t)spl + 1);
+            sig.push_back((int64_t)used);
+            for (int k = 0; k < spl; ++k) sig.push_back(count[k]);
+            {
+                size_t e = 0;
+                for (int k = 0; k < spl; ++k)
+                    for (size_t r = 0; r < run.size(); ++r) {
+                        Job &j = *run[r];
+                        if (j.desc.nsteps - j.info.steps_done <= k) continue;
+                        sig.push_back(j.id * 2 + srv->table_host[e].first);
+                        ++e;
+                    }
             }
-            ok = ok && hipGetLastError() == hipSuccess;
-            for (size_t r = 0; r < run.size() && ok; ++r)
-                ok = hipMemcpyAsync(&srv->status_host[run[r]->slot], ck::ctx_status_word(run[r]->ctx),
-                                    sizeof(unsigned int), hipMemcpyDeviceToHost, s) == hipSuccess;
+            if (ok && (!srv->round_graph || sig != srv->round_sig)) {
+                if (srv->round_graph) (void)hipGraphExecDestroy(srv->round_graph);
+                srv->round_graph = nullptr;
+                srv->round_sig.clear();
+                hipGraph_t g = nullptr;
+                ok = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) == hipSuccess;
+                if (ok) {
+                    bool cap = hipMemcpyAsync(srv->table_dev, srv->table_host, used * sizeof(ck::JobStep),
+                                              hipMemcpyHostToDevice, s) == hipSuccess;
+                    size_t off = 0;
+                    for (int k = 0; k < spl && cap; ++k) {
+                        if (count[k] == 0) break;
+                        ck::launch_step_multi(srv->table_dev + off, srv->table_host + off, count[k], s);
+                        off += (size_t)count[k];
+                    }
+                    cap = cap && hipGetLastError() == hipSuccess;
+                    for (size_t r = 0; r < run.size() && cap; ++r)
+                        cap = hipMemcpyAsync(&srv->status_host[run[r]->slot], ck::ctx_status_word(run[r]->ctx),
+                                             sizeof(unsigned int), hipMemcpyDeviceToHost, s) == hipSuccess;
+                    const hipError_t ce = hipStreamEndCapture(s, &g);
+                    ok = cap && ce == hipSuccess && g &&
+                         hipGraphInstantiate(&srv->round_graph, g, nullptr, nullptr, 0) == hipSuccess;
+                    if (g) (void)hipGraphDestroy(g);
+                    if (!ok) srv->round_graph = nullptr;
+                }
+                if (ok) {
+                    srv->round_sig.swap(sig);
+                    srv->graph_captures += 1;
+                }
+            } else if (ok) {
+                srv->graph_replays += 1;
+            }
+            ok = ok && hipGraphLaunch(srv->round_graph, s) == hipSuccess;
             ok = ok && hipEventRecord(srv->gev[1], s) == hipSuccess;
             if (!ok) {
                 for (Job *j : run) fail(srv, *j, MPM_E_HIP);
@@ -513,6 +563,7 @@ mpm_status mpm_server_destroy(mpm_server *srv) {
     if (srv->table_dev) (void)hipFree(srv->table_dev);
     for (hipEvent_t e : srv->gev)
         if (e) (void)hipEventDestroy(e);
+    if (srv->round_graph) (void)hipGraphExecDestroy(srv->round_graph);
     srv->arena.release();
     delete srv;
     return MPM_OK;
@@ -530,6 +581,14 @@ mpm_status mpm_server_submit(mpm_server *srv, const mpm_job_desc *job, int64_t *
     if ((size_t)fp > srv->arena.size()) return MPM_E_CAPACITY;
     std::unique_ptr<Job> j(new (std::nothrow) Job());
     if (!j) return MPM_E_OOM;
+    // order the admission's copy of state and mat after the submitter's work (the
+    // server's streams do not synchronise with any other stream, the null stream
+    // included)
+    if (hipEventCreateWithFlags(&j->ready, hipEventDisableTiming) != hipSuccess) {
+        j->ready = nullptr;
+        return MPM_E_HIP;
+    }
+    if (hipEventRecord(j->ready, (hipStream_t)job->stream) != hipSuccess) return MPM_E_HIP;
     j->id = srv->next_id++;
     j->desc = *job;
     j->mats.assign(job->mats, job->mats + job->n_mat);

@@ -208,7 +208,7 @@ __global__ void __launch_bounds__(kThreads) k_stress(DevCtx d, PartArgs pa) { b_
 // one launch for many jobs: workgroup row y runs job y
 __global__ void __launch_bounds__(kThreads) k_stress_multi(const JobStep *__restrict__ jobs) {
     const JobStep &J = jobs[blockIdx.y];
-    if (!J.first) return;
+    if (!J.first && !J.d.det) return;
     b_stress(J.d, J.pa);
 }
 
@@ -225,10 +225,12 @@ __global__ void __launch_bounds__(kThreads) k_stress_multi(const JobStep *__rest
 // One workgroup per block, one thread per particle, and the block's 341-node tile
 // in LDS as 64-bit fixed-point integers: LDS float atomics run about 26 times slower
 // than 64-bit integer atomics on gfx950, and integer sums are exact, so the tile is
-// independent of the order of the additions.  The unit of the fixed-point numbers is
-// chosen per block from a bound on every contribution (2^-39 of the largest, so a
-// node's sum of at most 2048 x 8 contributions stays below 2^51 and converts exactly
-// through FP64).  Particles are ordered in layers: layer q holds the q-th particle
+// independent of the order of the additions.  A block is scattered in passes of at
+// most kChunk particles, each pass into a cleared tile with its own unit: 2^-39 of
+// the pass's largest contribution bound, so every contribution is below 2^40 units
+// and a node, which takes at most one contribution per particle, sums fewer than
+// kChunk * 2^40 = 2^49 units in a pass -- below 2^51, where the magic-number
+// conversion through FP64 stays exact.  Particles are ordered in layers: layer q holds the q-th particle
 // (by index) of every nonempty (half-cell octant, cell) bin, and each layer runs in
 // (octant, cell) order.  Within an octant distinct cells have distinct nodes on both
 // grids, and spreading each bin's particles over the layers keeps most lanes of one
@@ -239,6 +241,9 @@ constexpr int kBins = 512;                 // (octant, cell) bins of a block: oc
 constexpr int kPerThread = kMaxBlockParticles / kP2GThreads;   // bucket entries per thread
 constexpr int kHold = 2;                   // of which kept in registers
 constexpr int kChunk = 2 * kP2GThreads;    // particles scattered per pass (two per thread)
+// a pass's node sums (< kChunk * 2^40 units) must stay below 2^51 for to_fixed and the
+// conversion back through FP64 to be exact
+static_assert((double)kChunk * 1099511627776.0 < 2251799813685248.0, "fixed-point tile sums would overflow 2^51");
 // Padded tile layout (64-bit words): node (x, y, z) of a grid at x + kTY y + kTZ z.
 // For any node offset, the 4 x 4 x 4 cells of a block then map x + kTY y onto 16
 // distinct residues modulo 16 (and kTZ is a multiple of 16), so the lanes of one
@@ -629,7 +634,9 @@ __device__ __forceinline__ void b_p2g(const DevCtx &d, const PartArgs &pa, float
         lds_barrier();
 
         // ---- scatter, kChunk particles per pass (one pass unless the block is dense)
-        for (int c0 = 0; c0 < cnt; c0 += kChunk) {
+        // (in deterministic mode a block without valid particles still writes a zero tile)
+        const int cend = (d.det && cnt == 0) ? 1 : cnt;
+        for (int c0 = 0; c0 < cend; c0 += kChunk) {
             for (int q = tid; q < kTileWords; q += kP2GThreads) area[q] = 0ull;
             if (tid == 0) bmax = 0u;
             Staged st[2];
@@ -661,6 +668,15 @@ __device__ __forceinline__ void b_p2g(const DevCtx &d, const PartArgs &pa, float
                 float val[4];
 #pragma unroll
                 for (int ch = 0; ch < 4; ++ch) val[ch] = (float)((double)(long long)tb[ch * cs + t] * inv);
+                if (d.det) {
+                    // deterministic mode: the block's tile (the same thread owns node ni in
+                    // every pass, so later passes add to what it wrote before)
+                    float *sg = d.stage + (size_t)r * kStageFloats + ni;
+#pragma unroll
+                    for (int ch = 0; ch < 4; ++ch)
+                        sg[ch * kTileNodes] = c0 == 0 ? val[ch] : sg[ch * kTileNodes] + val[ch];
+                    continue;
+                }
                 if (val[0] == 0.0f && val[1] == 0.0f && val[2] == 0.0f && val[3] == 0.0f) continue;
                 const long long a = pool_index(d, nbr, bx, by, bz, g, ix, iy, iz, 0);
                 if (a < 0) {
@@ -682,6 +698,66 @@ __global__ void __launch_bounds__(kP2GThreads, 3) k_p2g(DevCtx d, PartArgs pa, f
 __global__ void __launch_bounds__(kP2GThreads, 3) k_p2g_multi(const JobStep *__restrict__ jobs) {
     const JobStep &J = jobs[blockIdx.y];
     b_p2g(J.d, J.pa, J.dt, J.table, J.table);
+}
+
+// ---------------------------------------------------------------- deterministic P2G sums
+// Deterministic mode: each particle block's P2G left its whole tile (exact fixed-point
+// sums converted to FP32) in the staging area instead of adding it to the pool with
+// float atomics.  Here every node of every active grid block sums the tiles of the
+// particle blocks that cover it -- per axis the block itself, the one below at a
+// block's first node, and on G+ also the one above at its last node -- in a fixed
+// order (z, then y, then x offset) in FP64, and stores the result.  No step of the
+// pool sums depends on scheduling, so equal inputs give bitwise equal grids.
+__device__ __forceinline__ void b_det_gather(const DevCtx &d, int gp, int gt) {
+    const int ng = (int)d.counters[ngb_slot(gt)];
+    const int E = (int)d.counters[C_EPOCH];
+    const int *pf = stamps(d.pflag, d.nbv, E);
+    const int t = threadIdx.x;
+    const int g = t >> 6, l = t & 63;
+    const int lc[3] = {l & 3, (l >> 2) & 3, l >> 4};
+    int lo[3], hi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = lc[a] == 0 ? -1 : 0;
+        hi[a] = (g == 1 && lc[a] == 3) ? 1 : 0;
+    }
+    for (int b = blockIdx.x; b < ng; b += gridDim.x) {
+        int bc[3];
+        block_coords(d.geo, d.glist[gt][b], bc[0], bc[1], bc[2]);
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int oz = lo[2]; oz <= hi[2]; ++oz)
+            for (int oy = lo[1]; oy <= hi[1]; ++oy)
+                for (int ox = lo[0]; ox <= hi[0]; ++ox) {
+                    const int P[3] = {bc[0] + ox, bc[1] + oy, bc[2] + oz};
+                    if (P[0] < 0 || P[1] < 0 || P[2] < 0 || P[0] >= d.geo.NB[0] || P[1] >= d.geo.NB[1] ||
+                        P[2] >= d.geo.NB[2])
+                        continue;
+                    const int v = vblock_id(d.geo, P[0], P[1], P[2]);
+                    if (pf[v] != E) continue;   // no particles in that block this step
+                    const int r = d.prank[v];
+                    if (r < 0) continue;
+                    // the node in block P's tile: G- [4P, 4P+4], G+ [4P-1, 4P+4] per axis
+                    int tl[3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) tl[a] = 4 * (bc[a] - P[a]) + lc[a] + g;
+                    const int ni = g == 0 ? tl[0] + 5 * tl[1] + 25 * tl[2] : kTileMinus + tl[0] + 6 * tl[1] + 36 * tl[2];
+                    const float *sg = d.stage + (size_t)r * kStageFloats + ni;
+#pragma unroll
+                    for (int ch = 0; ch < 4; ++ch) acc[ch] += (double)sg[ch * kTileNodes];
+                }
+        float *blk = d.pool[gp] + (size_t)b * kBlockFloats + g * 256;
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) blk[ch * 64 + l] = (float)acc[ch];
+    }
+}
+
+__global__ void __launch_bounds__(128) k_det_gather(DevCtx d, int gp, int gt) { b_det_gather(d, gp, gt); }
+
+// one launch for many jobs: workgroup row y runs job y
+__global__ void __launch_bounds__(128) k_det_gather_multi(const JobStep *__restrict__ jobs) {
+    const JobStep &J = jobs[blockIdx.y];
+    if (!J.d.det) return;
+    b_det_gather(J.d, J.table, J.table);
 }
 
 // ---------------------------------------------------------------- grid update
@@ -1788,12 +1864,13 @@ __global__ void k_zero_pool(DevCtx d, int gp, int gt) {
         pool4[t] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
-__global__ void k_grid_export(DevCtx d, float *m, float *vec, int gp, int gt) {
+// Dense export of grids g0 .. g0 + ng - 1 (ng = 1 or 2).
+__global__ void k_grid_export(DevCtx d, float *m, float *vec, int gp, int gt, int g0, int ng) {
     const long long nx = d.geo.n[0] + 1, ny = d.geo.n[1] + 1, nz = d.geo.n[2] + 1;
     const long long nodes = nx * ny * nz;
-    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < 2 * nodes; t += (long long)gridDim.x * blockDim.x) {
-        const int g = (int)(t / nodes);
-        const long long r = t - g * nodes;
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < ng * nodes; t += (long long)gridDim.x * blockDim.x) {
+        const int g = g0 + (int)(t / nodes);
+        const long long r = t - (g - g0) * nodes;
         const int ix = (int)(r % nx), iy = (int)((r / nx) % ny), iz = (int)(r / (nx * ny));
         const int v = vblock_id(d.geo, ix >> 2, iy >> 2, iz >> 2);
         float mm = 0.0f, a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
@@ -1846,6 +1923,10 @@ void launch_p2g(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, h
         hipLaunchKernelGGL(k_p2g, dim3(particle_grid(d)), dim3(kP2GThreads), 0, s, d, pa, dt, gp, gt);
 }
 
+void launch_det_gather(const DevCtx &d, int gp, int gt, hipStream_t s) {
+    hipLaunchKernelGGL(k_det_gather, dim3(d.max_blocks < kGridWGs ? d.max_blocks : kGridWGs), dim3(128), 0, s, d, gp, gt);
+}
+
 void launch_grid_update(const DevCtx &d, float dt, const float gravity[3], int gp, int gt, hipStream_t s) {
     hipLaunchKernelGGL(k_grid_update, dim3(d.max_blocks < kGridWGs ? d.max_blocks : kGridWGs), dim3(128), 0, s, d, dt,
                        gravity[0], gravity[1], gravity[2], gp, gt);
@@ -1874,8 +1955,8 @@ void launch_zero_pool(const DevCtx &d, int gp, int gt, hipStream_t s) {
     hipLaunchKernelGGL(k_zero_pool, dim3(2048), dim3(256), 0, s, d, gp, gt);
 }
 
-void launch_grid_export(const DevCtx &d, float *m, float *vec, int gp, int gt, hipStream_t s) {
-    hipLaunchKernelGGL(k_grid_export, dim3(4096), dim3(256), 0, s, d, m, vec, gp, gt);
+void launch_grid_export(const DevCtx &d, float *m, float *vec, int gp, int gt, int g0, int ng, hipStream_t s) {
+    hipLaunchKernelGGL(k_grid_export, dim3(4096), dim3(256), 0, s, d, m, vec, gp, gt, g0, ng);
 }
 
 void launch_sort_multi(const JobStep *dev, const JobStep *host, int njobs, hipStream_t s);
@@ -1886,14 +1967,17 @@ namespace {
 void launch_step_run(const JobStep *dev, const JobStep *host, int njobs, hipStream_t s) {
     launch_sort_multi(dev, host, njobs, s);
     int stress_grid = 0, pgrid = 8, ugrid = 1;
+    bool any_det = false;
     for (int j = 0; j < njobs; ++j) {
         const JobStep &J = host[j];
-        if (J.first) stress_grid = std::max(stress_grid, (J.pa.n + kThreads - 1) / kThreads);
+        if (J.first || J.d.det) stress_grid = std::max(stress_grid, (J.pa.n + kThreads - 1) / kThreads);
         pgrid = std::max(pgrid, particle_grid(J.d));
         ugrid = std::max(ugrid, J.d.max_blocks < kGridWGs ? J.d.max_blocks : kGridWGs);
+        any_det = any_det || J.d.det;
     }
     if (stress_grid > 0) hipLaunchKernelGGL(k_stress_multi, dim3(stress_grid, njobs), dim3(kThreads), 0, s, dev);
     hipLaunchKernelGGL(k_p2g_multi, dim3(pgrid, njobs), dim3(kP2GThreads), 0, s, dev);
+    if (any_det) hipLaunchKernelGGL(k_det_gather_multi, dim3(ugrid, njobs), dim3(128), 0, s, dev);
     hipLaunchKernelGGL(k_grid_update_multi, dim3(ugrid, njobs), dim3(128), 0, s, dev);
     hipLaunchKernelGGL(k_g2p_multi, dim3(pgrid, njobs), dim3(kG2PThreads), 0, s, dev);
 }

@@ -29,14 +29,15 @@ def log(*args):
 class GpuRun:
     """One scene resident on the GPU with its context and stream."""
 
-    def __init__(self, sc, max_blocks=None, device="cuda:0", fused=False, quadratic=False, transfer=0):
+    def __init__(self, sc, max_blocks=None, device="cuda:0", fused=False, quadratic=False, transfer=0,
+                 deterministic=False):
         import torch
         from paper_2412_10399_amd import ckmpm
         self.torch = torch
         self.ck = ckmpm
         self.sc = sc
         self.ctx = ckmpm.Context(ckmpm.scene_config(sc, max_blocks=max_blocks, fused=fused, quadratic=quadratic,
-                                                    transfer=transfer),
+                                                    transfer=transfer, deterministic=deterministic),
                                  ckmpm.scene_materials(sc))
         self.parts = ckmpm.particles_from_scene(sc, device)
         self.stream = torch.cuda.current_stream()
@@ -51,7 +52,7 @@ class GpuRun:
             n = int(np.prod(self.dims))
             self._m = torch.zeros(n, dtype=torch.float32, device="cuda")
             self._vec = torch.zeros(3 * n, dtype=torch.float32, device="cuda")
-        self.ck.check(self.ck.mpm_grid_read(self.ctx.h, self._m.data_ptr(), self._vec.data_ptr(), self.stream))
+        self.ck.check(self.ck.mpm_grid_read(self.ctx.h, 0, self._m.data_ptr(), self._vec.data_ptr(), self.stream))
         torch.cuda.synchronize()
         return self._m.cpu().numpy().reshape(self.dims), self._vec.cpu().numpy().reshape(self.dims + (3,))
 

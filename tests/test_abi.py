@@ -38,7 +38,7 @@ def test_every_declared_symbol_is_exported(ck):
 
 
 def test_abi_version_and_strings(ck):
-    assert ck.mpm_abi_version() == 1
+    assert ck.mpm_abi_version() == 2
     for s in range(9):
         assert len(ck.mpm_status_string(s)) >= 2
     assert ck.mpm_status_string(9) == "unknown status"
@@ -46,7 +46,8 @@ def test_abi_version_and_strings(ck):
 
 def test_struct_layouts(ck):
     # sizes implied by the C declarations (natural alignment, x86-64)
-    assert ctypes.sizeof(ck.mpm_config) == 4 * 3 + 4 + 8 + 24 + 24 + 4 + 4 + 8 + 8 + 4 + 4
+    assert ctypes.sizeof(ck.mpm_config) == 4 * 3 + 4 + 8 + 24 + 24 + 4 + 4 + 8 + 8 + 4 + 4 + 4 + 4
+    assert ck.mpm_config.deterministic.offset == 104
     assert ctypes.sizeof(ck.mpm_material) == 24
     assert ctypes.sizeof(ck.mpm_particles) == 8 + 8 + 16 + 16 + 16 + 4 + 4
     assert ctypes.sizeof(ck.mpm_stats) == 32
@@ -62,12 +63,38 @@ def _good():
 @pytest.mark.parametrize("field,value", [
     ("dx", 0.03), ("dx", -0.5), ("dx", 0.0), ("max_particles", 0), ("max_particles", 1 << 26),
     ("max_blocks", 0), ("bc", 7), ("bc_band", -1), ("transfer", 3), ("transfer", -1), ("flags", 3), ("flags", 4), ("flags", -1),
+    ("deterministic", 2), ("deterministic", -1),
 ])
 def test_invalid_config_rejected_on_host(ck, field, value):
     cfg, mat = _good()
     setattr(cfg, field, value)
     s, h = ck.mpm_create(cfg, [mat])
     assert s == ck.MPM_E_INVALID and not h.value
+
+
+@pytest.mark.parametrize("flags,transfer", [(1, 0), (2, 0), (0, 1), (0, 2)])
+def test_deterministic_mode_needs_plain_compact_mls(ck, flags, transfer):
+    # the bitwise mode covers the phase kernels of the compact kernel with the MLS
+    # transfer; every other combination is refused on the host
+    cfg, mat = _good()
+    cfg.deterministic = 1
+    cfg.flags = flags
+    cfg.transfer = transfer
+    s, h = ck.mpm_create(cfg, [mat])
+    assert s == ck.MPM_E_INVALID and not h.value
+
+
+def test_footprint_counts_the_deterministic_staging(ck):
+    cfg, _ = _good()
+    plain = ck.mpm_footprint(cfg, 1000)
+    cfg.deterministic = 1
+    # 4 channels x 341 tile nodes x 4 bytes per block of max_blocks, padded like every buffer
+    extra = (cfg.max_blocks * 4 * 341 * 4 + 256 + 255) // 256 * 256
+    assert ck.mpm_footprint(cfg, 1000) - plain == extra
+
+
+def test_current_buffer_of_null_context(ck):
+    assert ck.mpm_current_buffer(None) == -1
 
 
 @pytest.mark.parametrize("field,value", [("E", 0.0), ("nu", 0.5), ("nu", -0.1), ("rho", 0.0), ("vol0", -1.0),
@@ -128,6 +155,8 @@ int main(void) {
   printf("%zu %zu %zu %zu\\n", sizeof(mpm_config), sizeof(mpm_material), sizeof(mpm_particles), sizeof(mpm_stats));
   printf("%zu %zu %zu %zu %zu\\n", offsetof(mpm_config, dx), offsetof(mpm_config, max_particles),
          offsetof(mpm_config, transfer), offsetof(mpm_particles, state), offsetof(mpm_particles, current));
+  printf("%zu %zu %zu %zu %zu\\n", offsetof(mpm_config, deterministic), sizeof(mpm_job_desc),
+         offsetof(mpm_job_desc, dt), offsetof(mpm_job_desc, stream), sizeof(mpm_job_info));
   return 0;
 }
 """)
@@ -135,7 +164,10 @@ int main(void) {
     subprocess.check_call([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     out = subprocess.check_output([str(exe)]).decode().split()
     sizes = [int(v) for v in out[:4]]
-    offs = [int(v) for v in out[4:]]
+    offs = [int(v) for v in out[4:9]]
+    more = [int(v) for v in out[9:]]
+    assert more == [ck.mpm_config.deterministic.offset, ctypes.sizeof(ck.mpm_job_desc), ck.mpm_job_desc.dt.offset,
+                    ck.mpm_job_desc.stream.offset, ctypes.sizeof(ck.mpm_job_info)]
     assert sizes == [ctypes.sizeof(ck.mpm_config), ctypes.sizeof(ck.mpm_material), ctypes.sizeof(ck.mpm_particles),
                      ctypes.sizeof(ck.mpm_stats)]
     assert offs == [ck.mpm_config.dx.offset, ck.mpm_config.max_particles.offset, ck.mpm_config.transfer.offset,

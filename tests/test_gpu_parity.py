@@ -7,7 +7,8 @@ field, bounded by 1e-5:
   * over the first 10 steps of the elastic cube (plain, perturbed, and touching
     the sticky floor) and of a reduced sand column, with the checker running its
     own FP64 trajectory from the same initial state (grids compared every step);
-  * two steps of the full 4,194,304-particle sand column.
+  * the first ten steps of the full 4,194,304-particle sand column (particles
+    every step, grids after steps 1, 5 and 10).
 """
 import numpy as np
 import pytest
@@ -117,16 +118,24 @@ def test_reseeded_step_parity(name):
     run.close()
 
 
-def test_full_sand_column_two_steps():
+@pytest.mark.timeout(1200)
+def test_full_sand_column_ten_steps():
+    """The 4,194,304-particle sand column at full size: ten phase steps against the
+    checker's own FP64 trajectory from the same initial state, particle x, v, F every
+    step and grid mass, momentum and m v~ after steps 1, 5 and 10."""
     sc = scenes.sand_column()
     assert sc.n == 4194304
     run = GpuRun(sc)
-    got = run.steps(sc.dt, 2)
-    assert got["status"] == 0
     st = oracle_state(dict(x=sc.x, v=sc.v, B=sc.B, F=sc.F))
-    for _ in range(2):
-        oracle_step(sc, st, sc.dt, grids=False)
-    _cmp_particles("sand_column full, 2 steps", got, st, sc.dx)
+    for k in range(10):
+        with_grids = k + 1 in (1, 5, 10)
+        got = run.phase_step(sc.dt, want_grids=with_grids)
+        assert got["status"] == 0, "step %d status %d" % (k + 1, got["status"])
+        _, g = oracle_step(sc, st, sc.dt, grids=with_grids)
+        if with_grids:
+            _cmp_grids("sand_column full, step %d" % (k + 1), got, g)
+            del g
+        _cmp_particles("sand_column full, step %d" % (k + 1), got, st, sc.dx)
     run.close()
 
 

@@ -1,13 +1,14 @@
-"""Job server on the GPU: every job's result is the same alone and in the mix,
-admission respects the memory budget and submission order, and a job larger than
-the whole budget is refused."""
+"""Job server on the GPU: every served job matches the FP64 checker's own
+trajectory and is the same alone and in the mix, admission respects the memory
+budget and submission order, and a job larger than the whole budget is refused."""
+import functools
 import time
 
 import numpy as np
 import pytest
 
 import scenes
-from gpu_util import TOL, log, nerr
+from gpu_util import TOL, log, nerr, oracle_state, oracle_step
 
 pytestmark = pytest.mark.gpu
 
@@ -41,6 +42,25 @@ def _alone(sc, nsteps):
     out = parts.read_by_id()
     ctx.close()
     return out
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle_final(k, nsteps):
+    """The checker's FP64 state of job k of _jobs() after nsteps steps."""
+    sc = _jobs()[k]
+    st = oracle_state(dict(x=sc.x, v=sc.v, B=sc.B, F=sc.F))
+    for _ in range(nsteps):
+        oracle_step(sc, st, sc.dt, grids=False)
+    return st
+
+
+def _check_oracle(tag, got, st):
+    """x, v, F of a served job (read back in particle-id order) against the checker."""
+    assert np.array_equal(got["id"], np.arange(st.n))
+    errs = {name: nerr(got[name], getattr(st, name)) for name in ("x", "v", "F")}
+    log("%s vs checker: %s" % (tag, " ".join("%s=%.2e" % kv for kv in errs.items())))
+    for name, e in errs.items():
+        assert e <= TOL, "%s: %s error %.3e" % (tag, name, e)
 
 
 def _collect(srv, jids, timeout=120.0):
@@ -84,6 +104,8 @@ def test_jobs_alone_equal_jobs_in_the_mix(spl, grouped):
     for k, j in enumerate(jids):
         state, status, *_ , steps = infos[j]
         assert state == ckmpm.MPM_JOB_DONE and status == 0 and steps == nsteps
+        _check_oracle("job %d (%d particles, %s, %d steps/launch)" % (k, jobs[k].n, "grouped" if grouped else
+                                                                      "per-job", spl), got[j], _oracle_final(k, nsteps))
         _compare(got[j], ref[k])
     lat = srv.step_latencies()
     assert len(lat) == nsteps * len(jobs) and min(lat) > 0.0
