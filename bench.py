@@ -63,23 +63,67 @@ def measured_traffic(kernel, n_launch_units):
     return (k["fetch_kib"] * t["fetch_scale"] + k["write_kib"] * t["write_scale"]) * 1024.0
 
 
-def cpu_baseline(sc, max_seconds=30.0):
+def host_cpu():
+    """CPU model and the processors this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
+
+
+def time_oracle(sc, threads, max_steps, max_seconds):
+    """The FP64 checker stepping scene `sc` from its initial state with `threads`
+    OpenMP threads: (particle-steps/s, steps, seconds)."""
     import oracle
+    oracle.set_num_threads(threads)
     st = oracle.State.from_scene(sc)
     cfg, mats = oracle.scene_config(sc), oracle.scene_materials(sc)
     steps = 0
     t0 = time.perf_counter()
-    while True:
+    while steps < max_steps:
         status, _, _ = oracle.step(cfg, mats, st, sc.dt)
         if status != 0:
             break
         steps += 1
-        if time.perf_counter() - t0 > max_seconds / 2 or steps >= 10:
+        if time.perf_counter() - t0 > max_seconds:
             break
-    dt = time.perf_counter() - t0
-    return {"value": sc.n * steps / dt, "unit": "particle-steps/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": "%d step(s) of the same %d-particle sand column from its initial state, FP64, %.1f s" %
-                      (steps, sc.n, dt)}
+    sec = time.perf_counter() - t0
+    return sc.n * steps / sec, steps, sec
+
+
+def cpu_baseline():
+    """The checker as it stands, timed on this host: the headline figure on two
+    steps of the sand column with every thread OpenMP gives it, then one thread on
+    the 32,768-particle elastic cube (a bounded sample) and the elastic cube's whole
+    100-step run with every thread."""
+    import oracle
+
+    import scenes
+    threads = oracle.num_threads()
+    rate, steps, sec = time_oracle(scenes.sand_column(), threads, 2, 25.0)
+    out = {"value": rate, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
+           "sample": "%d step(s) of the same %d-particle sand column from its initial state, FP64, %d threads, "
+                     "%.1f s" % (steps, 4194304, threads, sec)}
+    out.update(host_cpu())
+    cube = scenes.cube_elastic()
+    r1, s1, t1 = time_oracle(cube, 1, 100, 12.0)
+    out["one_thread"] = {"value": r1, "unit": "particle-steps/s", "threads": 1,
+                         "sample": "%d step(s) of the %d-particle elastic cube, %.1f s" % (s1, cube.n, t1)}
+    rn, sn, tn = time_oracle(scenes.cube_elastic(), threads, 100, 60.0)
+    out["elastic_cube_full"] = {"value": rn, "unit": "particle-steps/s", "threads": threads, "steps": sn,
+                                "seconds": tn, "particles": cube.n}
+    oracle.set_num_threads(threads)
+    return out
 
 
 def serve(srv, jobs, states, rate, ckmpm):
@@ -427,7 +471,7 @@ def main():
                                 "step_frac": result["step_roofline"]["achieved_GBs"] / copy_gbs,
                                 "probe": "device-to-device copy of 1 GiB, read + write bytes, mean of 5"}
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(scenes.sand_column())
+        result["cpu_baseline"] = cpu_baseline()
     print(json.dumps(result), flush=True)
 
 

@@ -92,6 +92,7 @@ def lib():
         L.ora_dNq.restype = ctypes.c_double
         L.ora_dNq.argtypes = [ctypes.c_double]
         L.ora_num_threads.restype = ctypes.c_int
+        L.ora_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -280,6 +281,12 @@ def Nq(r: float) -> float:
 
 def num_threads() -> int:
     return lib().ora_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads of the checker's parallel loops (for timing; its results are
+    the same for any thread count)."""
+    lib().ora_set_num_threads(int(n))
 
 
 def step_vjp(cfg: OraConfig, mats, st: State, dt: float, xb, vb, Bb, Fb):

@@ -518,6 +518,15 @@ int ora_num_threads(void) {
 #endif
 }
 
+// Threads of the following parallel loops (timing only; results do not depend on it).
+void ora_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 void ora_stencil(const ora_config *cfg, const double xp[3], int32_t nodes[2][8][3], double w[2][8], double dpos[2][8][3]) {
     Stencil st;
     stencil(cfg, xp, st);

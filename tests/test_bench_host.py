@@ -42,3 +42,27 @@ def test_step_byte_model():
     # per active block: clear 2 KiB, P2G flush 2 KiB, update reads 2 KiB and writes
     # 1.5 KiB, G2P reads 1.5 KiB
     assert bench.STEP_GRID_BLOCK_BYTES == 2048 + 2048 + 2048 + 1536 + 1536
+
+
+def test_checker_timing_helpers():
+    """The CPU-baseline leg: host description, and the checker timed at one and at
+    two threads on a small scene; the checker's state after a step does not depend
+    on its thread count (its scatter is serial), so both timings run the same work."""
+    import numpy as np
+
+    import oracle
+    import scenes
+    h = bench.host_cpu()
+    assert h["logical_cpus"] >= 1 and h["usable_cpus"] >= 1
+    sc = scenes.random_blob(3, n_cells=(16, 16, 16), lo_cells=(5.0, 5.0, 5.0), ext_cells=(4, 4, 4), F_scale=0.02)
+    states = []
+    for threads in (1, 2):
+        rate, steps, sec = bench.time_oracle(sc, threads, 2, 30.0)
+        assert steps == 2 and rate > 0 and sec > 0
+        oracle.set_num_threads(threads)
+        assert oracle.num_threads() == threads
+        st = oracle.State.from_scene(sc)
+        oracle.step(oracle.scene_config(sc), oracle.scene_materials(sc), st, sc.dt)
+        states.append(st)
+    for name in ("x", "v", "B", "F"):
+        assert np.array_equal(getattr(states[0], name), getattr(states[1], name)), name
