@@ -25,11 +25,16 @@
  *     k = -1 (G-) or +1 (G+):   origin + (i + k/4) * dx;
  *   - a particle is valid while (x - origin)/dx lies in [1/4, n_cells - 1/4) on every
  *     axis (all 16 nodes of its stencil then exist);
- *   - particle state is structure-of-arrays FP32: one allocation of 24 planes of
+ *   - particle state is structure-of-arrays FP32: one allocation of 27 planes of
  *     `stride` floats each, plane order x0 x1 x2 | v0 v1 v2 | B00 B01 B02 B10 .. B22 |
- *     H00 H01 .. H22 (matrices row-major), element p of plane q at base[q*stride + p].
- *     The deformation gradient is stored as H = F - I: an FP32 F near the identity
- *     resolves strains only to about 6e-8, H keeps them to FP32 relative precision;
+ *     H00 H01 .. H22 | r0 r1 r2 (matrices row-major), element p of plane q at
+ *     base[q*stride + p].  The deformation gradient is stored as H = F - I: an FP32 F
+ *     near the identity resolves strains only to about 6e-8, H keeps them to FP32
+ *     relative precision.  The position is the unevaluated sum x + r: x is the
+ *     position rounded to FP32 and r the FP32 remainder (|r| <= ulp(x)/2; zero is
+ *     always a valid r).  An FP32 position alone cannot move by less than half its
+ *     ulp in a step -- at x = 0.5 a particle slower than 1.5e-3 m/s would not move at
+ *     dt = 2e-5 -- so every step advances the pair;
  *   - streams are hipStream_t values passed as void* (NULL = the null stream).
  */
 #ifndef CKMPM_H
@@ -41,8 +46,8 @@
 extern "C" {
 #endif
 
-#define CKMPM_ABI_VERSION 2
-#define MPM_STATE_PLANES 24
+#define CKMPM_ABI_VERSION 3
+#define MPM_STATE_PLANES 27
 
 typedef struct mpm_ctx mpm_ctx; /* opaque, owned by the library */
 
@@ -115,7 +120,7 @@ typedef struct {
 typedef struct {
     int64_t n;             /* live particles                                                         */
     int64_t stride;        /* elements per state plane, n <= stride                                  */
-    float *state[2];       /* ping-pong buffers (device), 24 planes each, see above                  */
+    float *state[2];       /* ping-pong buffers (device), MPM_STATE_PLANES planes each, see above    */
     uint32_t *id[2];       /* optional particle ids (device), permuted with the state; may be NULL   */
     uint8_t *mat[2];       /* optional material index per particle (device), permuted with the state;
                               NULL means material 0 for every particle                               */
@@ -255,7 +260,7 @@ typedef struct {
     int32_t n_mat;
     int32_t nsteps;            /* steps to run, >= 0                                                   */
     int64_t n;                 /* particles, >= 1                                                      */
-    const float *state;        /* initial state (device), 24 planes of stride n, H = F - I; copied at
+    const float *state;        /* initial state (device), 27 planes of stride n, H = F - I; copied at
                                   admission, so it must stay valid while the job is pending           */
     const uint8_t *mat;        /* optional per-particle material index (device, n), or NULL           */
     double dt;
@@ -290,7 +295,7 @@ mpm_status mpm_server_poll(mpm_server *srv, int32_t *n_pending, int32_t *n_activ
 /* Polls until no job is pending or active (blocking on in-flight launches). */
 mpm_status mpm_server_drain(mpm_server *srv);
 mpm_status mpm_server_job_info(mpm_server *srv, int64_t job_id, mpm_job_info *info);
-/* Copies a finished job's state (24 planes of stride n) and particle ids (the
+/* Copies a finished job's state (27 planes of stride n) and particle ids (the
  * initial index of each particle; the state is in the library's particle order)
  * into device buffers; either pointer may be NULL.  Synchronous. */
 mpm_status mpm_server_job_read(mpm_server *srv, int64_t job_id, float *state, uint32_t *ids);

@@ -18,9 +18,12 @@
  * staggered grids, allocated once by mpm_ad_create (about 112 B per node of the
  * (n+1)^3 lattice); the calls allocate nothing.
  *
- * State and cotangent layout: 24 planes of `stride` floats, the layout of
- * mpm_particles (x[3] v[3] B[9] H[9], H = F - I, row-major 3x3); a cotangent
- * array has the same planes, its H planes holding dL/dF.  All pointers are device
+ * State and cotangent layout: 27 planes of `stride` floats, the layout of
+ * mpm_particles (x[3] v[3] B[9] H[9] r[3], H = F - I, row-major 3x3, position
+ * x + r); a cotangent array has the same planes, its H planes holding dL/dF and its
+ * x planes dL/d(position).  The backward call reads the position cotangent from
+ * the x planes only and writes dL/d(position) to both the x and the r planes of
+ * cot_in (the position depends on x and r alike).  All pointers are device
  * memory owned by the caller; calls are stream-ordered on `stream` (a hipStream_t,
  * NULL for the default stream) and return before the work completes.
  */
@@ -50,8 +53,8 @@ mpm_status mpm_ad_destroy(mpm_ad_ctx *ctx);
 mpm_status mpm_ad_forward(mpm_ad_ctx *ctx, int64_t n, int64_t stride, const float *state_in, const float *logE,
                           float *state_out, double dt, void *stream);
 
-/* Reverse mode of the same step: given dL/d state_out (cot_out, 24 planes), writes
- * dL/d state_in into cot_in (24 planes) and adds this step's dL/dlogE to
+/* Reverse mode of the same step: given dL/d state_out (cot_out, 27 planes), writes
+ * dL/d state_in into cot_in (27 planes) and adds this step's dL/dlogE to
  * logE_cot (n floats, accumulated so that a rollout sums over its steps).  The
  * step's grid is recomputed from state_in.  cot_in must not overlap cot_out or
  * state_in. */

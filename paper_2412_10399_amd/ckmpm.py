@@ -20,11 +20,11 @@ MPM_BC_NONE, MPM_BC_STICKY = 0, 1
 MPM_TRANSFER_MLS, MPM_TRANSFER_APIC, MPM_TRANSFER_PIC = 0, 1, 2
 MPM_FLAG_FUSED_G2P2G = 1
 MPM_FLAG_QUADRATIC = 2
-MPM_STATE_PLANES = 24
+MPM_STATE_PLANES = 27
 PHASES = ("sort", "p2g", "grid_update", "g2p", "g2p2g")
 
 # plane offsets inside one state buffer
-X0, V0, B0, F0 = 0, 3, 6, 15
+X0, V0, B0, F0, R0 = 0, 3, 6, 15, 24
 
 
 class CkMpmError(RuntimeError):
@@ -334,12 +334,16 @@ def make_material(model, E, nu, rho, vol0, friction_deg=30.0) -> mpm_material:
 
 
 def state_planes(x, v, B, F):
-    """Host arrays (N,3), (N,3), (N,3,3), (N,3,3) as the (24, N) FP32 state layout;
-    the deformation gradient is stored as H = F - I (formed in FP64, then rounded)."""
+    """Host arrays (N,3), (N,3), (N,3,3), (N,3,3) as the (27, N) FP32 state layout;
+    the deformation gradient is stored as H = F - I (formed in FP64, then rounded),
+    the position as its FP32 rounding x and the FP32 remainder r of an FP64 x."""
     import numpy as np
     n = len(x)
     planes = np.zeros((MPM_STATE_PLANES, n), np.float32)
-    planes[X0:X0 + 3] = np.asarray(x, np.float32).reshape(n, 3).T
+    x64 = np.asarray(x, np.float64).reshape(n, 3)
+    xh = x64.astype(np.float32)
+    planes[X0:X0 + 3] = xh.T
+    planes[R0:R0 + 3] = (x64 - xh.astype(np.float64)).astype(np.float32).T
     planes[V0:V0 + 3] = np.asarray(v, np.float32).reshape(n, 3).T
     planes[B0:B0 + 9] = np.asarray(B, np.float32).reshape(n, 9).T
     H = np.asarray(F, np.float64).reshape(n, 3, 3) - np.eye(3)[None]
@@ -348,19 +352,22 @@ def state_planes(x, v, B, F):
 
 
 def unpack_state(planes, ids=None):
-    """(24, N) state planes (host) as dict(x, v, B, H, F[, id]); F = I + H in FP64."""
+    """(27, N) state planes (host) as dict(x, x32, v, B, H, F[, id]): x = x32 + r and
+    F = I + H formed in FP64, x32 the FP32 position plane as stored."""
     import numpy as np
     n = planes.shape[1]
     H = planes[F0:F0 + 9].T.reshape(n, 3, 3).copy()
-    out = dict(x=planes[X0:X0 + 3].T.copy(), v=planes[V0:V0 + 3].T.copy(),
-               B=planes[B0:B0 + 9].T.reshape(n, 3, 3).copy(), H=H, F=H.astype(np.float64) + np.eye(3)[None])
+    x32 = planes[X0:X0 + 3].T.copy()
+    out = dict(x=x32.astype(np.float64) + planes[R0:R0 + 3].T.astype(np.float64), x32=x32,
+               v=planes[V0:V0 + 3].T.copy(), B=planes[B0:B0 + 9].T.reshape(n, 3, 3).copy(), H=H,
+               F=H.astype(np.float64) + np.eye(3)[None])
     if ids is not None:
         out["id"] = np.asarray(ids).copy()
     return out
 
 
 class Particles:
-    """Device particle storage: two ping-pong buffers of 24 FP32 planes, ids and
+    """Device particle storage: two ping-pong buffers of 27 FP32 planes, ids and
     optional material indices, as torch tensors on a GPU."""
 
     def __init__(self, n: int, stride: Optional[int] = None, device="cuda", with_mat: bool = False):
@@ -399,15 +406,11 @@ class Particles:
             self.mats[cur, :n].copy_(torch.from_numpy(mv))
 
     def read(self):
-        """Current buffer to host in storage (sorted) order: dict(x, v, B, H, F, id[, mat]);
-        H = F - I as stored (FP32), F = I + H formed in FP64."""
-        import numpy as np
+        """Current buffer to host in storage (sorted) order: dict(x, x32, v, B, H, F, id[, mat]);
+        x = x32 + r formed in FP64, H = F - I as stored (FP32), F = I + H formed in FP64."""
         cur = self.current
         n = self.n
-        pl = self.state[cur, :, :n].cpu().numpy()
-        H = pl[F0:F0 + 9].T.reshape(n, 3, 3).copy()
-        out = dict(x=pl[X0:X0 + 3].T.copy(), v=pl[V0:V0 + 3].T.copy(), B=pl[B0:B0 + 9].T.reshape(n, 3, 3).copy(),
-                   H=H, F=H.astype(np.float64) + np.eye(3)[None], id=self.ids[cur, :n].cpu().numpy().copy())
+        out = unpack_state(self.state[cur, :, :n].cpu().numpy(), self.ids[cur, :n].cpu().numpy())
         if self.mats is not None:
             out["mat"] = self.mats[cur, :n].cpu().numpy().copy()
         return out

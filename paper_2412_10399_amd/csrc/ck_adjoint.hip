@@ -69,12 +69,13 @@ struct AdStencil {
 };
 
 // False (and nothing filled in) when the particle is outside the valid domain.
-__device__ __forceinline__ bool ad_stencil(const AdArgs &a, const float x[3], AdStencil &st) {
+// The position is x + r (FP32 rounding and remainder), summed in FP64.
+__device__ __forceinline__ bool ad_stencil(const AdArgs &a, const float x[3], const float r[3], AdStencil &st) {
     constexpr float kInv2Pi = 0.15915494309189535f;
     float X[3];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-        X[ax] = (float)(((double)x[ax] - a.geo.origin[ax]) * a.geo.inv_dx);
+        X[ax] = (float)(((double)x[ax] + (double)r[ax] - a.geo.origin[ax]) * a.geo.inv_dx);
         if (!(X[ax] >= 0.25f && X[ax] < (float)a.geo.n[ax] - 0.25f)) return false;
     }
 #pragma unroll
@@ -422,12 +423,13 @@ __global__ void __launch_bounds__(256) k_ad_p2g(AdArgs a, const float *state, co
     AdStencil st;
     bool valid = false;
     if (p < a.n) {
-        float B[9], H[9];
+        float B[9], H[9], xr[3];
         load_planes(state, a.stride, p, 0, 3, x);
         load_planes(state, a.stride, p, 3, 3, v);
         load_planes(state, a.stride, p, 6, 9, B);
         load_planes(state, a.stride, p, 15, 9, H);
-        valid = ad_stencil(a, x, st);
+        load_planes(state, a.stride, p, kPlaneR, 3, xr);
+        valid = ad_stencil(a, x, xr, st);
         if (!valid) {
             set_status(a.status, ST_DOMAIN);
         } else {
@@ -503,11 +505,12 @@ __global__ void k_ad_grid(AdArgs a, int zero_mp) {
 __global__ void __launch_bounds__(256) k_ad_g2p(AdArgs a, const float *state, float *out) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= a.n) return;
-    float x[3], H[9];
+    float x[3], xr[3], H[9];
     load_planes(state, a.stride, p, 0, 3, x);
+    load_planes(state, a.stride, p, kPlaneR, 3, xr);
     load_planes(state, a.stride, p, 15, 9, H);
     AdStencil st;
-    if (!ad_stencil(a, x, st)) {
+    if (!ad_stencil(a, x, xr, st)) {
         set_status(a.status, ST_DOMAIN);
         for (int i = 0; i < MPM_STATE_PLANES; ++i) out[i * a.stride + p] = state[i * a.stride + p];
         return;
@@ -543,7 +546,10 @@ __global__ void __launch_bounds__(256) k_ad_g2p(AdArgs a, const float *state, fl
     float probe = 0.0f;
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-        out[ax * a.stride + p] = x[ax] + a.dt * vp[ax];
+        float xn, xrn;
+        advance_position(x[ax], xr[ax], a.dt * vp[ax], xn, xrn);
+        out[ax * a.stride + p] = xn;
+        out[(kPlaneR + ax) * a.stride + p] = xrn;
         out[(3 + ax) * a.stride + p] = vp[ax];
         probe += vp[ax] * 0.0f;
     }
@@ -562,22 +568,25 @@ __global__ void __launch_bounds__(256) k_ad_g2p_vjp(AdArgs a, const float *state
     __shared__ unsigned long long tw[kAdTileWords];
     __shared__ int sh[8];
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    float x[3], H[9];
+    float x[3], xr[3], H[9];
     float xbo[3], vbo[3], Bbo[9], Fbo[9];
     AdStencil st;
     bool valid = false;
     if (p < a.n) {
         load_planes(state, a.stride, p, 0, 3, x);
+        load_planes(state, a.stride, p, kPlaneR, 3, xr);
         load_planes(state, a.stride, p, 15, 9, H);
         load_planes(cot_out, a.stride, p, 0, 3, xbo);
         load_planes(cot_out, a.stride, p, 3, 3, vbo);
         load_planes(cot_out, a.stride, p, 6, 9, Bbo);
         load_planes(cot_out, a.stride, p, 15, 9, Fbo);
-        valid = ad_stencil(a, x, st);
+        valid = ad_stencil(a, x, xr, st);
         if (!valid) {
-            // the forward step left this particle unchanged
+            // the forward step left this particle unchanged; the position cotangent
+            // is that of the x planes, written to the r planes as well
             set_status(a.status, ST_DOMAIN);
             for (int i = 0; i < MPM_STATE_PLANES; ++i) cot_in[i * a.stride + p] = cot_out[i * a.stride + p];
+            for (int i = 0; i < 3; ++i) cot_in[(kPlaneR + i) * a.stride + p] = xbo[i];
         }
     }
     // every thread takes part in the tile's set-up and flush; invalid lanes add nothing
@@ -716,13 +725,14 @@ __global__ void __launch_bounds__(256) k_ad_p2g_vjp(AdArgs a, const float *state
                                                     float *logE_cot) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= a.n) return;
-    float x[3], v[3], B[9], H[9];
+    float x[3], xr[3], v[3], B[9], H[9];
     load_planes(state, a.stride, p, 0, 3, x);
+    load_planes(state, a.stride, p, kPlaneR, 3, xr);
     load_planes(state, a.stride, p, 3, 3, v);
     load_planes(state, a.stride, p, 6, 9, B);
     load_planes(state, a.stride, p, 15, 9, H);
     AdStencil st;
-    if (!ad_stencil(a, x, st)) return;   // cotangent already passed through by the G2P adjoint
+    if (!ad_stencil(a, x, xr, st)) return;   // cotangent already passed through by the G2P adjoint
     const float E = expf(logE[p]);
     const float mu = a.nu_mu * E, lam = a.nu_lambda * E;
     Polar P;
@@ -790,6 +800,7 @@ __global__ void __launch_bounds__(256) k_ad_p2g_vjp(AdArgs a, const float *state
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
         cot_in[ax * a.stride + p] = xb[ax];
+        cot_in[(kPlaneR + ax) * a.stride + p] = xb[ax];   // the position is x + r
         cot_in[(3 + ax) * a.stride + p] = vb[ax];
     }
 #pragma unroll

@@ -93,9 +93,13 @@ struct DevCtx {
 
 constexpr int kStageFloats = 4 * kTileNodes;   // one particle block's tile in the deterministic staging area
 
+// First plane of each field in a particle state buffer (MPM_STATE_PLANES planes):
+// position x, velocity v, affine matrix B, H = F - I, position remainder r.
+constexpr int kPlaneX = 0, kPlaneV = 3, kPlaneB = 6, kPlaneH = 15, kPlaneR = 24;
+
 struct PartArgs {
-    const float *in;       // 24 planes
-    float *out;            // 24 planes
+    const float *in;       // MPM_STATE_PLANES planes
+    float *out;            // MPM_STATE_PLANES planes
     long long stride;
     int n;
     const uint32_t *id_in;
@@ -150,8 +154,10 @@ __device__ __forceinline__ int *stamps(int *base, long long nbv, int epoch) {
 }
 
 // Cell of a position on grid G- (particle keys) and the fractional coordinates on
-// both grids.  The integer part is taken in FP64 from the FP32 position so that it
-// is exact and identical to any FP64 evaluation of floor((x - origin)/dx + 1/4).
+// both grids.  A position is the unevaluated sum x + r of two FP32 numbers (x the
+// position rounded to FP32, r the remainder, |r| <= ulp(x)/2).  The integer part is
+// taken in FP64 from the FP64 sum x + r, so that it is identical to any FP64
+// evaluation of floor((x + r - origin)/dx + 1/4) from that sum.
 struct CellCoord {
     int c[3];       // G- cell: nodes c, c+1 of G- carry the particle
     int bp[3];      // G+ base node: nodes bp, bp+1 of G+ carry the particle (bp = c or c-1)
@@ -159,11 +165,11 @@ struct CellCoord {
     float xp[3];    // fractional position inside the G+ cell, in [0, 1)
 };
 
-__device__ __forceinline__ bool cell_coord(const Geometry &g, const float x[3], CellCoord &cc) {
+__device__ __forceinline__ bool cell_coord(const Geometry &g, const float x[3], const float r[3], CellCoord &cc) {
     bool ok = true;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const double X = ((double)x[a] - g.origin[a]) * g.inv_dx;
+        const double X = ((double)x[a] + (double)r[a] - g.origin[a]) * g.inv_dx;
         ok = ok && (X >= 0.25) && (X < (double)g.n[a] - 0.25);
         const double Xm = X + 0.25;
         const double fl = floor(Xm);
@@ -179,6 +185,17 @@ __device__ __forceinline__ bool cell_coord(const Geometry &g, const float x[3], 
         }
     }
     return ok;
+}
+
+// Advection x + r <- x + r + dt v: the sum is formed in FP64 and split again into
+// its FP32 rounding and the FP32 remainder.  An FP32 position alone cannot move by
+// less than half its ulp per step (3e-8 at x = 0.5: a particle slower than 1.5e-3
+// m/s at dt = 2e-5 would not move at all); the pair resolves the displacement to
+// FP32 relative precision.
+__device__ __forceinline__ void advance_position(float x, float r, float d, float &xn, float &rn) {
+    const double s = ((double)x + (double)r) + (double)d;
+    xn = (float)s;
+    rn = (float)(s - (double)xn);
 }
 
 // Position of a particle inside its block: the G- cell (6 bits) and the half of the

@@ -42,7 +42,9 @@ __device__ __forceinline__ void b_flag_keys(const DevCtx &d, const PartArgs &pa,
     CellCoord cc;
     if (ok) {
         const float x[3] = {pa.in[i], pa.in[pa.stride + i], pa.in[2 * pa.stride + i]};
-        ok = cell_coord(d.geo, x, cc);
+        const float xr[3] = {pa.in[kPlaneR * pa.stride + i], pa.in[(kPlaneR + 1) * pa.stride + i],
+                             pa.in[(kPlaneR + 2) * pa.stride + i]};
+        ok = cell_coord(d.geo, x, xr, cc);
         if (!ok) {
             d.key[i] = 0xffffffffu;
             set_status(d.counters, ST_DOMAIN);

@@ -309,9 +309,11 @@ __device__ __forceinline__ void stage_particle(const DevCtx &d, const PartArgs &
     r.on = false;
     const long long S = pa.stride;
     const uint32_t up = (uint32_t)p;
-    float x[3], v[3], B[9], tau[6];
+    float x[3], xr[3], v[3], B[9], tau[6];
 #pragma unroll
     for (int a = 0; a < 3; ++a) x[a] = ld_at(pa.in + a * S, up);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) xr[a] = ld_at(pa.in + (kPlaneR + a) * S, up);
 #pragma unroll
     for (int a = 0; a < 3; ++a) v[a] = ld_at(pa.in + (3 + a) * S, up);
 #pragma unroll
@@ -321,7 +323,7 @@ __device__ __forceinline__ void stage_particle(const DevCtx &d, const PartArgs &
     const int mi = pa.mat_in ? (int)ld_at(pa.mat_in, up) : 0;
     const DevMaterial M = d.mats[mi < d.n_mat ? mi : 0];
     CellCoord cc;
-    if (!cell_coord(d.geo, x, cc)) {
+    if (!cell_coord(d.geo, x, xr, cc)) {
         set_status(d.counters, ST_DOMAIN);
         return;
     }
@@ -827,7 +829,7 @@ __global__ void __launch_bounds__(128) k_grid_update_multi(const JobStep *__rest
 // together with its next cell key and the activation stamps of the next step.
 struct G2PIn {
     uint32_t p;
-    float x[3], H[9];
+    float x[3], xr[3], H[9];
     int mat;
     uint32_t id;
 };
@@ -837,6 +839,8 @@ __device__ __forceinline__ void g2p_load_index(const PartArgs &pa, uint32_t p, G
     const long long S = pa.stride;
 #pragma unroll
     for (int a = 0; a < 3; ++a) q.x[a] = ld_at(pa.in + a * S, p);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) q.xr[a] = ld_at(pa.in + (kPlaneR + a) * S, p);
 #pragma unroll
     for (int a = 0; a < 9; ++a) q.H[a] = ld_at(pa.in + (15 + a) * S, p);
     q.mat = pa.mat_in ? (int)ld_at(pa.mat_in, p) : 0;
@@ -962,9 +966,9 @@ __device__ __forceinline__ int g2p_finish_c(const DevCtx &d, const PartArgs &pa,
     float tau[6];
     if (M.model == 1) dp_return_map(M, Fn, tau);
     else kirchhoff(M, Fn, tau);
-    float xn[3];
+    float xn[3], xrn[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) xn[a] = q.x[a] + dt * vn[a];
+    for (int a = 0; a < 3; ++a) advance_position(q.x[a], q.xr[a], dt * vn[a], xn[a], xrn[a]);
     // x * 0 is NaN exactly when x is infinite or NaN
     float probe = 0.0f;
 #pragma unroll
@@ -977,6 +981,7 @@ __device__ __forceinline__ int g2p_finish_c(const DevCtx &d, const PartArgs &pa,
     for (int a = 0; a < 3; ++a) {
         st_at(pa.out + a * S, out, xn[a]);
         st_at(pa.out + (3 + a) * S, out, vn[a]);
+        st_at(pa.out + (kPlaneR + a) * S, out, xrn[a]);
     }
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -990,7 +995,7 @@ __device__ __forceinline__ int g2p_finish_c(const DevCtx &d, const PartArgs &pa,
     if (pa.id_out) st_at(pa.id_out, out, q.id);
     if (pa.mat_out) st_at(pa.mat_out, out, (uint8_t)q.mat);
     // next cell key for the following step
-    if (finite && cell_coord(d.geo, xn, cn)) {
+    if (finite && cell_coord(d.geo, xn, xrn, cn)) {
         const uint32_t key = cell_key(d.geo, cn);
         st_at(d.key, out, key);
         st_at(d.sub, out, (uint16_t)sub_code(cn));
@@ -1068,7 +1073,7 @@ __device__ __forceinline__ void b_g2p(const DevCtx &d, const PartArgs &pa, float
             if (j + kG2PThreads < cnt) g2p_load(d, pa, (uint32_t)(s + j + kG2PThreads), nxt);   // next particle
             const uint32_t out = (uint32_t)(s + j);
             CellCoord cc;
-            bool ok = act && cell_coord(d.geo, q.x, cc);
+            bool ok = act && cell_coord(d.geo, q.x, q.xr, cc);
             ok = ok && (cc.c[0] >> 2) == bx && (cc.c[1] >> 2) == by && (cc.c[2] >> 2) == bz;
             // activation stamps of the next step (-1: none), deduplicated across the wave
             int sig = -1;
@@ -1116,9 +1121,11 @@ __device__ __forceinline__ void grad_stage(const DevCtx &d, const PartArgs &pa, 
     r.on = false;
     const long long S = pa.stride;
     const uint32_t up = (uint32_t)p;
-    float x[3], v[3], B[9], tau[6];
+    float x[3], xr[3], v[3], B[9], tau[6];
 #pragma unroll
     for (int a = 0; a < 3; ++a) x[a] = ld_at(pa.in + a * S, up);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) xr[a] = ld_at(pa.in + (kPlaneR + a) * S, up);
 #pragma unroll
     for (int a = 0; a < 3; ++a) v[a] = ld_at(pa.in + (3 + a) * S, up);
 #pragma unroll
@@ -1128,7 +1135,7 @@ __device__ __forceinline__ void grad_stage(const DevCtx &d, const PartArgs &pa, 
     const int mi = pa.mat_in ? (int)ld_at(pa.mat_in, up) : 0;
     const DevMaterial M = d.mats[mi < d.n_mat ? mi : 0];
     CellCoord cc;
-    if (!cell_coord(d.geo, x, cc)) {
+    if (!cell_coord(d.geo, x, xr, cc)) {
         set_status(d.counters, ST_DOMAIN);
         return;
     }
@@ -1340,7 +1347,7 @@ __global__ void __launch_bounds__(kG2PThreads) k_g2p_grad(DevCtx d, PartArgs pa,
             if (j + kG2PThreads < cnt) g2p_load(d, pa, (uint32_t)(s + j + kG2PThreads), nxt);
             const uint32_t out = (uint32_t)(s + j);
             CellCoord cc;
-            bool ok = act && cell_coord(d.geo, q.x, cc);
+            bool ok = act && cell_coord(d.geo, q.x, q.xr, cc);
             ok = ok && (cc.c[0] >> 2) == bx && (cc.c[1] >> 2) == by && (cc.c[2] >> 2) == bz;
             int sig = -1;
             if (act && !ok) {
@@ -1466,9 +1473,11 @@ __device__ __forceinline__ void quad_stage(const DevCtx &d, const PartArgs &pa, 
     r.on = false;
     const long long S = pa.stride;
     const uint32_t up = (uint32_t)p;
-    float x[3], v[3], B[9], tau[6];
+    float x[3], xr[3], v[3], B[9], tau[6];
 #pragma unroll
     for (int a = 0; a < 3; ++a) x[a] = ld_at(pa.in + a * S, up);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) xr[a] = ld_at(pa.in + (kPlaneR + a) * S, up);
 #pragma unroll
     for (int a = 0; a < 3; ++a) v[a] = ld_at(pa.in + (3 + a) * S, up);
 #pragma unroll
@@ -1478,7 +1487,7 @@ __device__ __forceinline__ void quad_stage(const DevCtx &d, const PartArgs &pa, 
     const int mi = pa.mat_in ? (int)ld_at(pa.mat_in, up) : 0;
     const DevMaterial M = d.mats[mi < d.n_mat ? mi : 0];
     CellCoord cc;
-    if (!cell_coord(d.geo, x, cc)) {
+    if (!cell_coord(d.geo, x, xr, cc)) {
         set_status(d.counters, ST_DOMAIN);
         return;
     }
@@ -1637,7 +1646,7 @@ __global__ void __launch_bounds__(kG2PThreads) k_g2p_quad(DevCtx d, PartArgs pa,
             if (j + kG2PThreads < cnt) g2p_load(d, pa, (uint32_t)(s + j + kG2PThreads), nxt);
             const uint32_t out = (uint32_t)(s + j);
             CellCoord cc;
-            bool ok = act && cell_coord(d.geo, q.x, cc);
+            bool ok = act && cell_coord(d.geo, q.x, q.xr, cc);
             ok = ok && (cc.c[0] >> 2) == bx && (cc.c[1] >> 2) == by && (cc.c[2] >> 2) == bz;
             float xi[3];
             int lb[3];
@@ -1789,7 +1798,7 @@ __global__ void __launch_bounds__(kP2GThreads, 2) k_g2p2g(DevCtx d, PartArgs pa,
                 const uint32_t out = (uint32_t)(s + j);
                 st[k].on = false;
                 CellCoord cc;
-                bool ok = act && cell_coord(d.geo, in[k].x, cc);
+                bool ok = act && cell_coord(d.geo, in[k].x, in[k].xr, cc);
                 ok = ok && (cc.c[0] >> 2) == bx && (cc.c[1] >> 2) == by && (cc.c[2] >> 2) == bz;
                 int sig = -1;
                 if (act && !ok) {

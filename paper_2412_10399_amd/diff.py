@@ -86,7 +86,7 @@ class _Rollout(torch.autograd.Function):
 
 def rollout(ad: AdContext, state0: torch.Tensor, logE: torch.Tensor, nsteps: int, dt: float,
             checkpoint_every: int = 8) -> torch.Tensor:
-    """State after `nsteps` steps from `state0` ((24, n) FP32 planes x, v, B, H on the
+    """State after `nsteps` steps from `state0` ((27, n) FP32 planes x, v, B, H, r on the
     GPU) with per-particle log modulus `logE` ((n,) FP32); differentiable with respect
     to both.  Memory: ceil(nsteps / checkpoint_every) saved states plus one segment."""
     if nsteps <= 0:
@@ -98,6 +98,8 @@ def rollout(ad: AdContext, state0: torch.Tensor, logE: torch.Tensor, nsteps: int
 
 
 def planes(x: torch.Tensor, v: torch.Tensor, B: torch.Tensor, H: torch.Tensor) -> torch.Tensor:
-    """(24, n) state from x, v (n, 3), B, H (n, 3, 3) (differentiable concatenation)."""
+    """(27, n) state from x, v (n, 3), B, H (n, 3, 3) (differentiable concatenation;
+    the position remainder planes are zero)."""
     n = x.shape[0]
-    return torch.cat([x.t(), v.t(), B.reshape(n, 9).t(), H.reshape(n, 9).t()], dim=0).contiguous()
+    r = torch.zeros((3, n), dtype=x.dtype, device=x.device)
+    return torch.cat([x.t(), v.t(), B.reshape(n, 9).t(), H.reshape(n, 9).t(), r], dim=0).contiguous()

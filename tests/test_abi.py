@@ -38,7 +38,7 @@ def test_every_declared_symbol_is_exported(ck):
 
 
 def test_abi_version_and_strings(ck):
-    assert ck.mpm_abi_version() == 2
+    assert ck.mpm_abi_version() == 3
     for s in range(9):
         assert len(ck.mpm_status_string(s)) >= 2
     assert ck.mpm_status_string(9) == "unknown status"
@@ -172,3 +172,4 @@ int main(void) {
                      ctypes.sizeof(ck.mpm_stats)]
     assert offs == [ck.mpm_config.dx.offset, ck.mpm_config.max_particles.offset, ck.mpm_config.transfer.offset,
                     ck.mpm_particles.state.offset, ck.mpm_particles.current.offset]
+

@@ -80,7 +80,8 @@ def test_backward_step_matches_oracle_adjoint(near_wall):
     assert status == 0
     s0 = _state(sc)
     logE = torch.from_numpy(sc.logE).cuda()
-    cot_out = torch.from_numpy(np.concatenate([cot[0].T, cot[1].T, cot[2].reshape(n, 9).T, cot[3].reshape(n, 9).T])
+    cot_out = torch.from_numpy(np.concatenate([cot[0].T, cot[1].T, cot[2].reshape(n, 9).T, cot[3].reshape(n, 9).T,
+                                               np.zeros((3, n))])
                                .astype(np.float32)).cuda().contiguous()
     cot_in = torch.empty_like(cot_out)
     lcot = torch.zeros(n, dtype=torch.float32, device="cuda")
@@ -89,6 +90,7 @@ def test_backward_step_matches_oracle_adjoint(near_wall):
                                       cot_in.data_ptr(), lcot.data_ptr(), sc.dt, stream))
     ckmpm.check(ckmpm.mpm_ad_sync(ad.h, stream))
     g = cot_in.cpu().numpy().astype(np.float64)
+    assert np.array_equal(g[24:27], g[0:3])   # the position x + r: one cotangent for both
     got = dict(x=g[0:3].T, v=g[3:6].T, B=g[6:15].T.reshape(n, 3, 3), F=g[15:24].T.reshape(n, 3, 3),
                logE=lcot.cpu().numpy())
     for k in ("x", "v", "B", "F", "logE"):
@@ -136,7 +138,8 @@ def test_shuffled_particles_take_the_direct_scatter():
     st = oracle.State(sc.x, sc.v, sc.B, sc.F, sc.mat, sc.logE)
     status, ref = oracle.step_vjp(oracle.scene_config(sc), oracle.scene_materials(sc), st, sc.dt, *cot)
     assert status == 0
-    cot_out = torch.from_numpy(np.concatenate([cot[0].T, cot[1].T, cot[2].reshape(n, 9).T, cot[3].reshape(n, 9).T])
+    cot_out = torch.from_numpy(np.concatenate([cot[0].T, cot[1].T, cot[2].reshape(n, 9).T, cot[3].reshape(n, 9).T,
+                                               np.zeros((3, n))])
                                .astype(np.float32)).cuda().contiguous()
     cot_in = torch.empty_like(cot_out)
     lcot = torch.zeros(n, dtype=torch.float32, device="cuda")
@@ -144,6 +147,7 @@ def test_shuffled_particles_take_the_direct_scatter():
                                       cot_in.data_ptr(), lcot.data_ptr(), sc.dt, stream))
     ckmpm.check(ckmpm.mpm_ad_sync(ad.h, stream))
     g = cot_in.cpu().numpy().astype(np.float64)
+    assert np.array_equal(g[24:27], g[0:3])   # the position x + r: one cotangent for both
     got = dict(x=g[0:3].T, v=g[3:6].T, B=g[6:15].T.reshape(n, 3, 3), F=g[15:24].T.reshape(n, 3, 3),
                logE=lcot.cpu().numpy())
     for k in ("x", "v", "B", "F", "logE"):

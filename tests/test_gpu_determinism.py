@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _raw(run):
-    """Current buffer (24 planes) and ids in storage order, as host arrays."""
+    """Current buffer (all state planes) and ids in storage order, as host arrays."""
     p = run.parts
     cur = p.current
     return p.state[cur, :, :p.n].cpu().numpy().copy(), p.ids[cur, :p.n].cpu().numpy().copy()
@@ -63,7 +63,7 @@ def test_phase_calls_and_mpm_step_bitwise_equal():
 
 
 def test_resume_from_particle_state_is_bitwise():
-    """Checkpoint the particle SoA (24 planes and ids, as stored) after 5 steps, resume
+    """Checkpoint the particle SoA (all state planes and ids, as stored) after 5 steps, resume
     it in a fresh context and compare 7 further steps with the uninterrupted run."""
     import torch
     sc = scenes.sand_column(scale=4)
