@@ -60,7 +60,8 @@ typedef enum {
     MPM_E_NONFINITE = 5, /* a NaN/Inf appeared in v, B or F (device-detected)                */
     MPM_E_HIP = 6,       /* a HIP runtime call failed                                        */
     MPM_E_STALE = 7,     /* positions changed after the library computed their cell keys      */
-    MPM_E_CFL = 8        /* in mpm_step, a particle moved more than three cells in one step    */
+    MPM_E_CFL = 8,       /* in mpm_step, a particle moved more than three cells in one step    */
+    MPM_E_SCRATCH = 9    /* mpm_step_noalloc: the buffers do not fit its static scratch          */
 } mpm_status;
 
 enum { MPM_FIXED_COROTATED = 0, MPM_DRUCKER_PRAGER = 1 };
@@ -177,6 +178,32 @@ mpm_status mpm_g2p(mpm_ctx *ctx, mpm_particles *p, double dt, void *stream);
  * mpm_grid_read and the carried keys and stress afterwards are those of the phase
  * calls, up to summation order. */
 mpm_status mpm_step(mpm_ctx *ctx, mpm_particles *p, double dt, int32_t nsteps, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops that must not call hipMalloc, harnesses that forbid it): mpm_step
+ * without a context.  The call validates cfg, mats and p as mpm_create and mpm_step
+ * do, then runs nsteps steps exactly as mpm_step on a context created from the same
+ * configuration would (same kernels, same results), with every library buffer carved
+ * from one static device array of MPM_NOALLOC_SCRATCH_BYTES per GPU, held from the
+ * first call on that GPU until the process ends.  It calls no hipMalloc, hipFree or
+ * other allocating routine; the caller still owns the particle buffers.
+ *   - The buffers needed are those mpm_create would allocate for cfg (a function of
+ *     n_cells, max_particles, max_blocks and deterministic; mpm_footprint(cfg, 0)
+ *     counts them); beyond MPM_NOALLOC_SCRATCH_BYTES the call returns MPM_E_SCRATCH
+ *     before any GPU work.  A 32^3-cell grid with 32,768 particles and max_blocks 729
+ *     needs about 14 MB.
+ *   - Every call starts from a cleared state (keys, stress and page tables are
+ *     recomputed from the particles) by fill kernels on `stream`; nothing carries over
+ *     from the previous call, whose contents stay in the array.
+ *   - Calls that overlap on one GPU share the array and race: serialise them (one
+ *     stream, or events).
+ *   - Device-detected errors: when `status` (device memory, one int32) is not NULL, a
+ *     kernel enqueued after the steps writes the mpm_status code mpm_sync would have
+ *     returned (MPM_OK when none); the call itself returns host-detected errors only.
+ * Asynchronous on `stream`; p->current flips as in mpm_step. */
+#define MPM_NOALLOC_SCRATCH_BYTES (32 * 1024 * 1024)
+mpm_status mpm_step_noalloc(const mpm_config *cfg, const mpm_material *mats, int32_t n_mat, mpm_particles *p,
+                            double dt, int32_t nsteps, int32_t *status, void *stream);
 
 /* Wait for `stream`, then return (and clear) the device status word as a status code:
  * NONFINITE before DOMAIN before CAPACITY before STALE before CFL. */

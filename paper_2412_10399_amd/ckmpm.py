@@ -14,7 +14,9 @@ from typing import Optional, Sequence
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libckmpm.so")
 _lib = None
 
-MPM_OK, MPM_E_INVALID, MPM_E_OOM, MPM_E_DOMAIN, MPM_E_CAPACITY, MPM_E_NONFINITE, MPM_E_HIP, MPM_E_STALE, MPM_E_CFL = range(9)
+(MPM_OK, MPM_E_INVALID, MPM_E_OOM, MPM_E_DOMAIN, MPM_E_CAPACITY, MPM_E_NONFINITE, MPM_E_HIP, MPM_E_STALE, MPM_E_CFL,
+ MPM_E_SCRATCH) = range(10)
+MPM_NOALLOC_SCRATCH_BYTES = 32 * 1024 * 1024
 MPM_FIXED_COROTATED, MPM_DRUCKER_PRAGER = 0, 1
 MPM_BC_NONE, MPM_BC_STICKY = 0, 1
 MPM_TRANSFER_MLS, MPM_TRANSFER_APIC, MPM_TRANSFER_PIC = 0, 1, 2
@@ -82,7 +84,7 @@ EXPORTS = ("mpm_create", "mpm_destroy", "mpm_p2g", "mpm_grid_update", "mpm_g2p",
            "mpm_profile_read", "mpm_status_string", "mpm_abi_version", "mpm_footprint", "mpm_server_create",
            "mpm_server_destroy", "mpm_server_submit", "mpm_server_poll", "mpm_server_drain", "mpm_server_job_info",
            "mpm_server_job_read", "mpm_server_job_release", "mpm_server_step_latencies", "mpm_ad_create",
-           "mpm_ad_destroy", "mpm_ad_forward", "mpm_ad_backward", "mpm_ad_sync")
+           "mpm_ad_destroy", "mpm_ad_forward", "mpm_ad_backward", "mpm_ad_sync", "mpm_step_noalloc")
 
 
 def lib():
@@ -99,6 +101,8 @@ def lib():
         L.mpm_grid_update.argtypes = [vp, ctypes.c_double, vp]
         L.mpm_g2p.argtypes = [vp, ctypes.POINTER(mpm_particles), ctypes.c_double, vp]
         L.mpm_step.argtypes = [vp, ctypes.POINTER(mpm_particles), ctypes.c_double, ctypes.c_int32, vp]
+        L.mpm_step_noalloc.argtypes = [ctypes.POINTER(mpm_config), ctypes.POINTER(mpm_material), ctypes.c_int32,
+                                       ctypes.POINTER(mpm_particles), ctypes.c_double, ctypes.c_int32, vp, vp]
         L.mpm_sync.argtypes = [vp, vp]
         L.mpm_grid_read.argtypes = [vp, ctypes.c_int32, vp, vp, vp]
         L.mpm_current_buffer.argtypes = [vp]
@@ -170,6 +174,15 @@ def mpm_g2p(ctx, parts: mpm_particles, dt: float, stream=None) -> int:
 
 def mpm_step(ctx, parts: mpm_particles, dt: float, nsteps: int, stream=None) -> int:
     return lib().mpm_step(ctx, ctypes.byref(parts), float(dt), int(nsteps), _stream(stream))
+
+
+def mpm_step_noalloc(cfg: mpm_config, mats: Sequence[mpm_material], parts: mpm_particles, dt: float, nsteps: int,
+                     status_ptr: Optional[int] = None, stream=None) -> int:
+    """mpm_step without a context: library buffers from the static device scratch;
+    status_ptr is a device int32 that receives the device-detected status (or None)."""
+    arr = (mpm_material * len(mats))(*mats)
+    return lib().mpm_step_noalloc(ctypes.byref(cfg), arr, len(mats), ctypes.byref(parts), float(dt), int(nsteps),
+                                  status_ptr, _stream(stream))
 
 
 def mpm_sync(ctx, stream=None) -> int:

@@ -3,6 +3,7 @@
 // reporting and per-phase event timing.  No allocation happens after mpm_create.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -17,6 +18,14 @@ constexpr int kSlotEvents = 5;      // boundaries of one step: sort | p2g | upda
 constexpr int kEventRing = 512;     // steps recorded before the ring is folded into the totals
 
 }  // namespace
+
+// Device memory of mpm_step_noalloc: every buffer of its work (sort scratch, page
+// tables, grid pools, stress, status word) is carved from this array.  Each GPU the
+// library runs on holds its own copy until the process ends.  In host code the
+// array's name is no device address: the address comes from hipGetSymbolAddress
+// with the device current (noalloc_scratch below).
+static_assert(MPM_NOALLOC_SCRATCH_BYTES % 256 == 0, "scratch size");
+static __device__ __align__(256) unsigned char scratch[MPM_NOALLOC_SCRATCH_BYTES];
 
 struct mpm_ctx {
     mpm_config cfg;
@@ -431,6 +440,7 @@ const char *mpm_status_string(mpm_status s) {
         case MPM_E_HIP: return "HIP runtime error";
         case MPM_E_STALE: return "particle positions changed after their cell keys were computed";
         case MPM_E_CFL: return "a particle moved more than three cells in one fused step";
+        case MPM_E_SCRATCH: return "buffers exceed the static scratch of mpm_step_noalloc";
     }
     return "unknown status";
 }
@@ -473,15 +483,23 @@ mpm_status mpm_g2p(mpm_ctx *ctx, mpm_particles *p, double dt, void *stream) {
     return enqueue_g2p(ctx, p, dt, (hipStream_t)stream);
 }
 
-mpm_status mpm_step(mpm_ctx *ctx, mpm_particles *p, double dt, int32_t nsteps, void *stream) {
+}  // extern "C"
+
+namespace {
+
+// Host-side checks of mpm_step's arguments.
+mpm_status validate_step(const mpm_ctx *ctx, const mpm_particles *p, double dt, int32_t nsteps) {
     const mpm_status v = validate_particles(ctx, p);
     if (v != MPM_OK) return v;
     if (!std::isfinite(dt) || dt < 0 || nsteps < 0) return MPM_E_INVALID;
     if (!p->state[p->current ^ 1]) return MPM_E_INVALID;
     if ((p->id[0] == nullptr) != (p->id[1] == nullptr)) return MPM_E_INVALID;
     if ((p->mat[0] == nullptr) != (p->mat[1] == nullptr)) return MPM_E_INVALID;
-    DeviceGuard g(ctx->device);
-    hipStream_t s = (hipStream_t)stream;
+    return MPM_OK;
+}
+
+// The launch sequence of nsteps steps (mpm_step), on the context's buffers.
+mpm_status step_sequence(mpm_ctx *ctx, mpm_particles *p, double dt, int32_t nsteps, hipStream_t s) {
     if (nsteps == 0) return MPM_OK;
     if (!(ctx->cfg.flags & MPM_FLAG_FUSED_G2P2G)) {
         for (int k = 0; k < nsteps; ++k) {
@@ -561,6 +579,17 @@ mpm_status mpm_step(mpm_ctx *ctx, mpm_particles *p, double dt, int32_t nsteps, v
     return st;
 }
 
+}  // namespace
+
+extern "C" {
+
+mpm_status mpm_step(mpm_ctx *ctx, mpm_particles *p, double dt, int32_t nsteps, void *stream) {
+    const mpm_status v = validate_step(ctx, p, dt, nsteps);
+    if (v != MPM_OK) return v;
+    DeviceGuard g(ctx->device);
+    return step_sequence(ctx, p, dt, nsteps, (hipStream_t)stream);
+}
+
 mpm_status mpm_sync(mpm_ctx *ctx, void *stream) {
     if (!ctx) return MPM_E_INVALID;
     DeviceGuard g(ctx->device);
@@ -634,6 +663,99 @@ mpm_status mpm_profile_enable(mpm_ctx *ctx, int32_t enable) {
     }
     ctx->ev_used = 0;
     return MPM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch_addr[kMaxDevices];   // per device: the address of `scratch` there
+
+// Address of the current device's scratch array, looked up once per device.
+mpm_status noalloc_scratch(int dev, unsigned char **out) {
+    if (dev < 0 || dev >= kMaxDevices) return MPM_E_HIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_addr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return MPM_E_HIP;
+        g_scratch_addr[dev] = ptr;
+    }
+    *out = static_cast<unsigned char *>(g_scratch_addr[dev]);
+    return MPM_OK;
+}
+
+__global__ void k_fill_words(uint32_t *p, uint32_t value, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+void fill_words(void *p, uint32_t value, long long n, hipStream_t s) {
+    const long long blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_fill_words, dim3((unsigned)(blocks < 1024 ? (blocks > 0 ? blocks : 1) : 1024)), dim3(256), 0, s,
+                       static_cast<uint32_t *>(p), value, n);
+}
+
+// mpm_status code of the status bits, in mpm_sync's order.
+__global__ void k_status_code(const unsigned int *counters, int32_t *out) {
+    const unsigned int b = counters[C_STATUS];
+    *out = (b & ST_NONFINITE) ? MPM_E_NONFINITE
+         : (b & ST_DOMAIN)    ? MPM_E_DOMAIN
+         : (b & ST_CAPACITY)  ? MPM_E_CAPACITY
+         : (b & ST_STALE)     ? MPM_E_STALE
+         : (b & ST_CFL)       ? MPM_E_CFL
+                              : MPM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mpm_status mpm_step_noalloc(const mpm_config *cfg, const mpm_material *mats, int32_t n_mat, mpm_particles *p,
+                            double dt, int32_t nsteps, int32_t *status, void *stream) {
+    const mpm_status vc = validate_config(cfg, mats, n_mat);
+    if (vc != MPM_OK) return vc;
+    if (device_bytes_of(*cfg) > (int64_t)MPM_NOALLOC_SCRATCH_BYTES) return MPM_E_SCRATCH;
+    // a context on the stack: its buffers come from the scratch array; nothing in it
+    // allocates (the vectors stay empty, profiling stays off)
+    mpm_ctx ctx;
+    ctx.cfg = *cfg;
+    const mpm_status v = validate_step(&ctx, p, dt, nsteps);
+    if (v != MPM_OK) return v;
+    if (hipGetDevice(&ctx.device) != hipSuccess) return MPM_E_HIP;
+    unsigned char *base = nullptr;
+    const mpm_status sa = noalloc_scratch(ctx.device, &base);
+    if (sa != MPM_OK) return sa;
+    DevCtx &d = ctx.d;
+    fill_devctx(d, *cfg, mats, n_mat);
+    size_t used = 0;
+    const mpm_status sc = carve_buffers(d, *cfg, [&](size_t bytes) -> void * {
+        const size_t at = (used + 255) / 256 * 256;
+        if (at + bytes > (size_t)MPM_NOALLOC_SCRATCH_BYTES) return nullptr;
+        used = at + bytes;
+        return base + at;
+    });
+    if (sc != MPM_OK) return MPM_E_SCRATCH;
+    // the previous call's contents stay in the array: reset what a new context starts
+    // from (epoch stamps, page tables, block ranks, block starts, counters), with fill
+    // kernels on the caller's stream
+    hipStream_t s = (hipStream_t)stream;
+    const long long nv = d.nbv, nb = cfg->max_blocks;
+    fill_words(d.pflag, 0u, 2 * stamp_stride(nv), s);
+    fill_words(d.gflag, 0u, 2 * stamp_stride(nv), s);
+    fill_words(d.page[0], 0xffffffffu, nv, s);
+    fill_words(d.page[1], 0xffffffffu, nv, s);
+    fill_words(d.prank, 0xffffffffu, nv, s);
+    fill_words(d.pstart, 0u, nb + 1, s);
+    fill_words(d.counters, 0u, C_COUNT, s);
+    mpm_status st = last_error();
+    if (st == MPM_OK) st = step_sequence(&ctx, p, dt, nsteps, s);
+    if (st == MPM_OK && status) {
+        hipLaunchKernelGGL(k_status_code, dim3(1), dim3(1), 0, s, d.counters, status);
+        st = last_error();
+    }
+    return st;
 }
 
 mpm_status mpm_profile_read(mpm_ctx *ctx, double *total_ms, int64_t *count, int32_t n_phases) {

@@ -39,9 +39,9 @@ def test_every_declared_symbol_is_exported(ck):
 
 def test_abi_version_and_strings(ck):
     assert ck.mpm_abi_version() == 3
-    for s in range(9):
+    for s in range(10):
         assert len(ck.mpm_status_string(s)) >= 2
-    assert ck.mpm_status_string(9) == "unknown status"
+    assert ck.mpm_status_string(10) == "unknown status"
 
 
 def test_struct_layouts(ck):
@@ -173,3 +173,18 @@ int main(void) {
     assert offs == [ck.mpm_config.dx.offset, ck.mpm_config.max_particles.offset, ck.mpm_config.transfer.offset,
                     ck.mpm_particles.state.offset, ck.mpm_particles.current.offset]
 
+
+def test_noalloc_step_rejects_oversized_buffers_on_host(ck):
+    """mpm_step_noalloc refuses, before any GPU work, a configuration whose buffers
+    exceed its static scratch, and a bad configuration as mpm_create does."""
+    cfg, mat = _good()
+    cfg.max_particles = 1 << 22   # 34 B of sort scratch and stress per particle: 136 MiB
+    p = ck.mpm_particles()
+    L = ck.lib()
+    assert L.mpm_step_noalloc(ctypes.byref(cfg), ctypes.byref(mat), 1, ctypes.byref(p), 1e-3, 1, None,
+                              None) == ck.MPM_E_SCRATCH
+    cfg, mat = _good()
+    cfg.dx = 0.03
+    assert L.mpm_step_noalloc(ctypes.byref(cfg), ctypes.byref(mat), 1, ctypes.byref(p), 1e-3, 1, None,
+                              None) == ck.MPM_E_INVALID
+    assert L.mpm_step_noalloc(None, None, 1, None, 1e-3, 1, None, None) == ck.MPM_E_INVALID
