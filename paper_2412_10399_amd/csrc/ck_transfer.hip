@@ -117,6 +117,35 @@ __device__ __forceinline__ void st_at(T *base, uint32_t i, T v) {
     *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + (size_t)(i * (uint32_t)sizeof(T))) = v;
 }
 
+// Element i of N consecutive planes of `stride` elements from plane `first`: one
+// per-lane address advanced by the stride, instead of one wave-uniform base per
+// plane (a kernel storing some thirty planes otherwise keeps thirty 64-bit bases in
+// scalar registers, and the ones that do not fit cost two lane reads per access).
+typedef __attribute__((address_space(1))) float global_float;
+template <int N>
+__device__ __forceinline__ void st_planes(float *base, long long stride, int first, uint32_t i, const float (&v)[N]) {
+    uint64_t a = reinterpret_cast<uint64_t>(base + (long long)first * stride + i);
+    const uint64_t step = (uint64_t)stride * sizeof(float);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        *reinterpret_cast<global_float *>(a) = v[k];
+        a += step;
+        asm volatile("" : "+v"(a));   // keep the address per lane
+    }
+}
+typedef const __attribute__((address_space(1))) float global_cfloat;
+template <int N>
+__device__ __forceinline__ void ld_planes(const float *base, long long stride, int first, uint32_t i, float (&v)[N]) {
+    uint64_t a = reinterpret_cast<uint64_t>(base + (long long)first * stride + i);
+    const uint64_t step = (uint64_t)stride * sizeof(float);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        v[k] = *reinterpret_cast<global_cfloat *>(a);
+        a += step;
+        asm volatile("" : "+v"(a));
+    }
+}
+
 // ---------------------------------------------------------------- block sort
 // Exact stable order of one block's particles by (cell, particle index): counting
 // sort by cell in LDS, then each particle's rank among the equal-cell particles by
@@ -310,16 +339,11 @@ __device__ __forceinline__ void stage_particle(const DevCtx &d, const PartArgs &
     const long long S = pa.stride;
     const uint32_t up = (uint32_t)p;
     float x[3], xr[3], v[3], B[9], tau[6];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) x[a] = ld_at(pa.in + a * S, up);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) xr[a] = ld_at(pa.in + (kPlaneR + a) * S, up);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) v[a] = ld_at(pa.in + (3 + a) * S, up);
-#pragma unroll
-    for (int a = 0; a < 9; ++a) B[a] = ld_at(pa.in + (6 + a) * S, up);
-#pragma unroll
-    for (int i = 0; i < 6; ++i) tau[i] = ld_at(d.tau + i * d.tau_stride, up);
+    ld_planes(pa.in, S, kPlaneX, up, x);
+    ld_planes(pa.in, S, kPlaneR, up, xr);
+    ld_planes(pa.in, S, kPlaneV, up, v);
+    ld_planes(pa.in, S, kPlaneB, up, B);
+    ld_planes(d.tau, d.tau_stride, 0, up, tau);
     const int mi = pa.mat_in ? (int)ld_at(pa.mat_in, up) : 0;
     const DevMaterial M = d.mats[mi < d.n_mat ? mi : 0];
     CellCoord cc;
@@ -408,6 +432,51 @@ __device__ __forceinline__ void scatter_particle(const Staged &r, int lx, int ly
     staged_weights(r, wm, wp, up, mp);
     scatter_grid(tile_m, SM, lz * TZ + ly * TY + lx, TY, TZ, wm, r.mass, r.base, r.Q, S);
     scatter_grid(tile_p, SP, (lz + up[2]) * TZ + (ly + up[1]) * TY + (lx + up[0]), TY, TZ, wp, r.mass, mp, r.Q, S);
+}
+
+// FP64 form of scatter_grid: each contribution is the exact FP64 product of the
+// FP32 weight and the FP32 mass or momentum term, added with an FP64 LDS atomic
+// (as fast as the 64-bit integer add on gfx950, with no conversion to fixed point).
+__device__ __forceinline__ void scatter_grid_f64(double *tile, int ntile, int t0, int sy, int sz,
+                                                 const float (&w)[3][2], double mass, const float (&m0)[3],
+                                                 const float (&Q)[9]) {
+    float mo[2][2][2][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        mo[0][0][0][a] = m0[a];
+        mo[0][0][1][a] = m0[a] + Q[3 * a];
+        mo[0][1][0][a] = m0[a] + Q[3 * a + 1];
+        mo[0][1][1][a] = mo[0][0][1][a] + Q[3 * a + 1];
+#pragma unroll
+        for (int oy = 0; oy < 2; ++oy)
+#pragma unroll
+            for (int ox = 0; ox < 2; ++ox) mo[1][oy][ox][a] = mo[0][oy][ox][a] + Q[3 * a + 2];
+    }
+#pragma unroll
+    for (int oz = 0; oz < 2; ++oz)
+#pragma unroll
+        for (int oy = 0; oy < 2; ++oy) {
+            const float wyz = w[1][oy] * w[2][oz];
+#pragma unroll
+            for (int ox = 0; ox < 2; ++ox) {
+                const double wt = (double)(w[0][ox] * wyz);
+                const int t = t0 + ox + oy * sy + oz * sz;
+                atomicAdd(&tile[t], wt * mass);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) atomicAdd(&tile[(1 + a) * ntile + t], wt * (double)mo[oz][oy][ox][a]);
+            }
+        }
+}
+
+template <int TY, int TZ, int SM, int SP>
+__device__ __forceinline__ void scatter_particle_f64(const Staged &r, int lx, int ly, int lz, double *tile_m,
+                                                     double *tile_p) {
+    float wm[3][2], wp[3][2], mp[3];
+    int up[3];
+    staged_weights(r, wm, wp, up, mp);
+    const double mass = (double)r.mass;
+    scatter_grid_f64(tile_m, SM, lz * TZ + ly * TY + lx, TY, TZ, wm, mass, r.base, r.Q);
+    scatter_grid_f64(tile_p, SP, (lz + up[2]) * TZ + (ly + up[1]) * TY + (lx + up[0]), TY, TZ, wp, mass, mp, r.Q);
 }
 
 // Direct float atomics into the pool for a particle outside the workgroup's tile
@@ -601,9 +670,12 @@ __device__ __forceinline__ double block_scale(float bnd, unsigned int *bmax) {
     return m > 0.0f ? ldexp(1.0, 39 - ilogbf(m)) : 1.0;
 }
 
-// Three waves per SIMD (at most 168 VGPRs, none spilled).  At four (128 VGPRs) the
-// staged particles spill about 56 B per lane, which costs more in scratch traffic
-// than the fourth workgroup hides (0.271 against 0.260 ms on the sand column).
+// P2G of the particle blocks.  kFixed (deterministic mode): the fixed-point tile,
+// whose sums are exact and so independent of the order of the atomics; each pass
+// stages two particles per thread, takes the block's unit from their bounds, then
+// scatters them.  Otherwise an FP64 tile: every thread stages and scatters one
+// particle at a time (no unit to agree on first), and the block takes a single pass.
+template <bool kFixed>
 __device__ __forceinline__ void b_p2g(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt) {
     __shared__ int bcnt[kBins];                 // counts, then placement cursors
     __shared__ int bstart[kBins + 1];
@@ -620,6 +692,8 @@ __device__ __forceinline__ void b_p2g(const DevCtx &d, const PartArgs &pa, float
     uint16_t *rt = reinterpret_cast<uint16_t *>(lbuf + kMaxBlockParticles);   // after the ordering buffer
     unsigned long long *tile_m = area;
     unsigned long long *tile_p = area + 4 * kTileMStride;
+    double *ftile_m = reinterpret_cast<double *>(area);
+    double *ftile_p = ftile_m + 4 * kTileMStride;
     const int np = (int)d.counters[C_NPB];
     const int tid = threadIdx.x;
     for (int base = 0; base < np; base += gridDim.x) {
@@ -635,7 +709,48 @@ __device__ __forceinline__ void b_p2g(const DevCtx &d, const PartArgs &pa, float
         load_neighbours(d, gt, bx, by, bz, nbr);
         lds_barrier();
 
-        // ---- scatter, kChunk particles per pass (one pass unless the block is dense)
+        if (!kFixed) {
+            // ---- FP64 tile: with no unit to agree on, every thread stages and scatters
+            // one particle at a time (the first one loads while the tile is cleared);
+            // holding one staged particle instead of two lets the kernel run four waves
+            // per SIMD without spills, which beats overlapping two particles' loads
+            Staged st;
+            st.on = false;
+            if (tid < cnt) stage_particle(d, pa, (int)ord[tid], bx, by, bz, dt, st);
+            for (int q = tid; q < kTileWords; q += kP2GThreads) area[q] = 0ull;
+            lds_barrier();
+            for (int j = tid; j < cnt; j += kP2GThreads) {
+                if (j > tid) stage_particle(d, pa, (int)ord[j], bx, by, bz, dt, st);
+                if (st.on)
+                    scatter_particle_f64<kTY, kTZ, kTileMStride, kTilePStride>(st, st.c[0] - 4 * bx, st.c[1] - 4 * by,
+                                                                               st.c[2] - 4 * bz, ftile_m, ftile_p);
+            }
+            lds_barrier();
+            for (int ni = tid; ni < kTileNodes; ni += kP2GThreads) {
+                int g, ix, iy, iz;
+                tile_node(ni, bx, by, bz, g, ix, iy, iz);
+                const int lx = ix - 4 * bx + g, ly = iy - 4 * by + g, lz = iz - 4 * bz + g;   // tile-local
+                const double *tb = g == 0 ? ftile_m : ftile_p;
+                const int cs = g == 0 ? kTileMStride : kTilePStride;
+                const int t = lx + ly * kTY + lz * kTZ;
+                float val[4];
+#pragma unroll
+                for (int ch = 0; ch < 4; ++ch) val[ch] = (float)tb[ch * cs + t];
+                if (val[0] == 0.0f && val[1] == 0.0f && val[2] == 0.0f && val[3] == 0.0f) continue;
+                const long long a = pool_index(d, nbr, bx, by, bz, g, ix, iy, iz, 0);
+                if (a < 0) {
+                    set_status(d.counters, ST_CAPACITY);
+                    continue;
+                }
+#pragma unroll
+                for (int ch = 0; ch < 4; ++ch)
+                    if (val[ch] != 0.0f) atomicAdd(&d.pool[gp][a + ch * 64], val[ch]);
+            }
+            lds_barrier();
+            continue;
+        }
+
+        // ---- fixed-point tile, kChunk particles per pass (one pass unless the block is dense)
         // (in deterministic mode a block without valid particles still writes a zero tile)
         const int cend = (d.det && cnt == 0) ? 1 : cnt;
         for (int c0 = 0; c0 < cend; c0 += kChunk) {
@@ -694,12 +809,26 @@ __device__ __forceinline__ void b_p2g(const DevCtx &d, const PartArgs &pa, float
     }
 }
 
-__global__ void __launch_bounds__(kP2GThreads, 3) k_p2g(DevCtx d, PartArgs pa, float dt, int gp, int gt) { b_p2g(d, pa, dt, gp, gt); }
+// Four waves per SIMD (128 VGPRs, none spilled; 40 KiB of LDS, four workgroups per
+// CU): 0.263 ms on the sand column against 0.303 ms at three.
+__global__ void __launch_bounds__(kP2GThreads, 4) k_p2g(DevCtx d, PartArgs pa, float dt, int gp, int gt) {
+    b_p2g<false>(d, pa, dt, gp, gt);
+}
+__global__ void __launch_bounds__(kP2GThreads, 3) k_p2g_det(DevCtx d, PartArgs pa, float dt, int gp, int gt) {
+    b_p2g<true>(d, pa, dt, gp, gt);
+}
 
-// one launch for many jobs: workgroup row y runs job y
-__global__ void __launch_bounds__(kP2GThreads, 3) k_p2g_multi(const JobStep *__restrict__ jobs) {
+// one launch for many jobs: workgroup row y runs job y (rows of deterministic-mode
+// jobs return at once; k_p2g_det_multi runs those)
+__global__ void __launch_bounds__(kP2GThreads, 4) k_p2g_multi(const JobStep *__restrict__ jobs) {
     const JobStep &J = jobs[blockIdx.y];
-    b_p2g(J.d, J.pa, J.dt, J.table, J.table);
+    if (J.d.det) return;
+    b_p2g<false>(J.d, J.pa, J.dt, J.table, J.table);
+}
+__global__ void __launch_bounds__(kP2GThreads, 3) k_p2g_det_multi(const JobStep *__restrict__ jobs) {
+    const JobStep &J = jobs[blockIdx.y];
+    if (!J.d.det) return;
+    b_p2g<true>(J.d, J.pa, J.dt, J.table, J.table);
 }
 
 // ---------------------------------------------------------------- deterministic P2G sums
@@ -837,12 +966,9 @@ struct G2PIn {
 __device__ __forceinline__ void g2p_load_index(const PartArgs &pa, uint32_t p, G2PIn &q) {
     q.p = p;
     const long long S = pa.stride;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) q.x[a] = ld_at(pa.in + a * S, p);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) q.xr[a] = ld_at(pa.in + (kPlaneR + a) * S, p);
-#pragma unroll
-    for (int a = 0; a < 9; ++a) q.H[a] = ld_at(pa.in + (15 + a) * S, p);
+    ld_planes(pa.in, S, kPlaneX, p, q.x);
+    ld_planes(pa.in, S, kPlaneR, p, q.xr);
+    ld_planes(pa.in, S, kPlaneH, p, q.H);
     q.mat = pa.mat_in ? (int)ld_at(pa.mat_in, p) : 0;
     q.id = pa.id_in ? ld_at(pa.id_in, p) : 0u;
 }
@@ -977,21 +1103,22 @@ __device__ __forceinline__ int g2p_finish_c(const DevCtx &d, const PartArgs &pa,
     for (int i = 0; i < 9; ++i) probe += Fn[i] * 0.0f + Bn[i] * 0.0f;
     const bool finite = probe == 0.0f;
     if (!finite) set_status(d.counters, ST_NONFINITE);
+    {
+        float st[24];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        st_at(pa.out + a * S, out, xn[a]);
-        st_at(pa.out + (3 + a) * S, out, vn[a]);
-        st_at(pa.out + (kPlaneR + a) * S, out, xrn[a]);
-    }
+        for (int a = 0; a < 3; ++a) {
+            st[a] = xn[a];
+            st[3 + a] = vn[a];
+        }
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        st_at(pa.out + (6 + i) * S, out, Bn[i]);
-        st_at(pa.out + (15 + i) * S, out, Fn[i]);
+        for (int i = 0; i < 9; ++i) {
+            st[6 + i] = Bn[i];
+            st[15 + i] = Fn[i];
+        }
+        st_planes(pa.out, S, kPlaneX, out, st);
+        st_planes(pa.out, S, kPlaneR, out, xrn);
     }
-    if (write_tau) {
-#pragma unroll
-        for (int i = 0; i < 6; ++i) st_at(d.tau + i * d.tau_stride, out, tau[i]);
-    }
+    if (write_tau) st_planes(d.tau, d.tau_stride, 0, out, tau);
     if (pa.id_out) st_at(pa.id_out, out, q.id);
     if (pa.mat_out) st_at(pa.mat_out, out, (uint8_t)q.mat);
     // next cell key for the following step
@@ -1474,16 +1601,11 @@ __device__ __forceinline__ void quad_stage(const DevCtx &d, const PartArgs &pa, 
     const long long S = pa.stride;
     const uint32_t up = (uint32_t)p;
     float x[3], xr[3], v[3], B[9], tau[6];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) x[a] = ld_at(pa.in + a * S, up);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) xr[a] = ld_at(pa.in + (kPlaneR + a) * S, up);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) v[a] = ld_at(pa.in + (3 + a) * S, up);
-#pragma unroll
-    for (int a = 0; a < 9; ++a) B[a] = ld_at(pa.in + (6 + a) * S, up);
-#pragma unroll
-    for (int i = 0; i < 6; ++i) tau[i] = ld_at(d.tau + i * d.tau_stride, up);
+    ld_planes(pa.in, S, kPlaneX, up, x);
+    ld_planes(pa.in, S, kPlaneR, up, xr);
+    ld_planes(pa.in, S, kPlaneV, up, v);
+    ld_planes(pa.in, S, kPlaneB, up, B);
+    ld_planes(d.tau, d.tau_stride, 0, up, tau);
     const int mi = pa.mat_in ? (int)ld_at(pa.mat_in, up) : 0;
     const DevMaterial M = d.mats[mi < d.n_mat ? mi : 0];
     CellCoord cc;
@@ -1928,6 +2050,8 @@ void launch_p2g(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, h
         hipLaunchKernelGGL(k_p2g_quad, dim3(particle_grid(d)), dim3(kP2GThreads), 0, s, d, pa, dt, gp, gt);
     else if (d.transfer != 0)
         hipLaunchKernelGGL(k_p2g_grad, dim3(particle_grid(d)), dim3(kP2GThreads), 0, s, d, pa, dt, gp, gt);
+    else if (d.det)
+        hipLaunchKernelGGL(k_p2g_det, dim3(particle_grid(d)), dim3(kP2GThreads), 0, s, d, pa, dt, gp, gt);
     else
         hipLaunchKernelGGL(k_p2g, dim3(particle_grid(d)), dim3(kP2GThreads), 0, s, d, pa, dt, gp, gt);
 }
@@ -1976,16 +2100,18 @@ namespace {
 void launch_step_run(const JobStep *dev, const JobStep *host, int njobs, hipStream_t s) {
     launch_sort_multi(dev, host, njobs, s);
     int stress_grid = 0, pgrid = 8, ugrid = 1;
-    bool any_det = false;
+    bool any_det = false, any_plain = false;
     for (int j = 0; j < njobs; ++j) {
         const JobStep &J = host[j];
         if (J.first || J.d.det) stress_grid = std::max(stress_grid, (J.pa.n + kThreads - 1) / kThreads);
         pgrid = std::max(pgrid, particle_grid(J.d));
         ugrid = std::max(ugrid, J.d.max_blocks < kGridWGs ? J.d.max_blocks : kGridWGs);
         any_det = any_det || J.d.det;
+        any_plain = any_plain || !J.d.det;
     }
     if (stress_grid > 0) hipLaunchKernelGGL(k_stress_multi, dim3(stress_grid, njobs), dim3(kThreads), 0, s, dev);
-    hipLaunchKernelGGL(k_p2g_multi, dim3(pgrid, njobs), dim3(kP2GThreads), 0, s, dev);
+    if (any_plain) hipLaunchKernelGGL(k_p2g_multi, dim3(pgrid, njobs), dim3(kP2GThreads), 0, s, dev);
+    if (any_det) hipLaunchKernelGGL(k_p2g_det_multi, dim3(pgrid, njobs), dim3(kP2GThreads), 0, s, dev);
     if (any_det) hipLaunchKernelGGL(k_det_gather_multi, dim3(ugrid, njobs), dim3(128), 0, s, dev);
     hipLaunchKernelGGL(k_grid_update_multi, dim3(ugrid, njobs), dim3(128), 0, s, dev);
     hipLaunchKernelGGL(k_g2p_multi, dim3(pgrid, njobs), dim3(kG2PThreads), 0, s, dev);
