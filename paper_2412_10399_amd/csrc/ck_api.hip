@@ -172,7 +172,7 @@ int64_t device_bytes_of(const mpm_config &c) {
     return r(4 * np) + r(2 * np) + r(4 * np) + r(4 * nb * (long long)kMaxBlockParticles) +
            r(2 * nb * (long long)kMaxBlockParticles) + 2 * r(8 * stamp_stride(nbv)) + 2 * r(4 * nbv) + r(4 * nbv) +
            r(4 * nb) + r(4 * (nb + 1)) + r(4 * nb) + 2 * r(4 * nb) + r(4 * nchunks) + r(4 * nchunks) +
-           2 * r(4 * nb * (long long)kBlockFloats) + r(24 * np) + r(4 * (long long)C_COUNT) +
+           2 * r(4 * nb * (long long)kBlockFloats) + r(24 * np) + r(4 * (long long)C_COUNT) + r(4 * (long long)kBoundWords) +
            (c.deterministic ? r(4 * nb * (long long)kStageFloats) : 0);
 }
 
@@ -226,6 +226,11 @@ mpm_status enqueue_p2g(mpm_ctx *ctx, const mpm_particles *p, double dt, hipStrea
     const bool ready = ctx->next_ready == pa.in && ctx->next_n == pa.n;
     if (ev) (void)hipEventRecord(ev[0], s);
     if (!ready) launch_flag_keys(ctx->d, pa, 1, s);
+    // deterministic mode recomputes the stress from F every step, so that a run
+    // resumed from its particle state sees the same stress as the uninterrupted run;
+    // the stress pass also adds the state's contribution bound, which the bucket scan
+    // below hands to the P2G
+    if (physics && (!ready || ctx->d.det)) launch_stress(ctx->d, pa, s);
     const int t = ctx->next_table;
     launch_compact(ctx->d, t, s);
     launch_bucket(ctx->d, pa.n, t, t, s);
@@ -234,9 +239,6 @@ mpm_status enqueue_p2g(mpm_ctx *ctx, const mpm_particles *p, double dt, hipStrea
     if (!physics) {
         launch_block_sort(ctx->d, s);
     } else {
-        // deterministic mode recomputes the stress from F every step, so that a run
-        // resumed from its particle state sees the same stress as the uninterrupted run
-        if (!ready || ctx->d.det) launch_stress(ctx->d, pa, s);
         launch_p2g(ctx->d, pa, (float)dt, t, t, s);
         if (ctx->d.det) launch_det_gather(ctx->d, t, t, s);
         ctx->grid_pool = t;
@@ -308,6 +310,7 @@ mpm_status carve_buffers(DevCtx &d, const mpm_config &cfg, Take take) {
                     take_buffer(take, &d.chunk_p, nchunks) && take_buffer(take, &d.chunk_g, nchunks) &&
                     take_buffer(take, &d.pool[0], nb * kBlockFloats) && take_buffer(take, &d.pool[1], nb * kBlockFloats) &&
                     take_buffer(take, &d.tau, 6 * np) && take_buffer(take, &d.counters, (size_t)C_COUNT) &&
+                    take_buffer(take, &d.bslots, (size_t)kBoundWords) &&
                     (!d.det || take_buffer(take, &d.stage, nb * (size_t)kStageFloats));
     return ok ? MPM_OK : MPM_E_OOM;
 }
@@ -352,7 +355,8 @@ mpm_status ctx_create(const mpm_config *cfg, const mpm_material *mats, int32_t n
                   hipMemsetAsync(d.page[1], 0xff, nv * sizeof(int), init_stream) == hipSuccess &&
                   hipMemsetAsync(d.prank, 0xff, nv * sizeof(int), init_stream) == hipSuccess &&
                   hipMemsetAsync(d.pstart, 0, (nb + 1) * sizeof(int), init_stream) == hipSuccess &&
-                  hipMemsetAsync(d.counters, 0, C_COUNT * sizeof(unsigned int), init_stream) == hipSuccess;
+                  hipMemsetAsync(d.counters, 0, C_COUNT * sizeof(unsigned int), init_stream) == hipSuccess &&
+                  hipMemsetAsync(d.bslots, 0, kBoundWords * sizeof(unsigned int), init_stream) == hipSuccess;
         ok = ok && (device_sync ? hipDeviceSynchronize() : hipStreamSynchronize(init_stream)) == hipSuccess;
         if (!ok) st = MPM_E_HIP;
     }
@@ -749,6 +753,7 @@ mpm_status mpm_step_noalloc(const mpm_config *cfg, const mpm_material *mats, int
     fill_words(d.prank, 0xffffffffu, nv, s);
     fill_words(d.pstart, 0u, nb + 1, s);
     fill_words(d.counters, 0u, C_COUNT, s);
+    fill_words(d.bslots, 0u, kBoundWords, s);
     mpm_status st = last_error();
     if (st == MPM_OK) st = step_sequence(&ctx, p, dt, nsteps, s);
     if (st == MPM_OK && status) {

@@ -35,7 +35,9 @@ enum Counter : int {
     C_MAXPB = 4,    // largest particle count of a block
     C_TOTAL = 5,    // particles placed by the sort
     C_NGB1 = 6,
-    C_COUNT = 8
+    C_BOUND_X = 7,  // P2G contribution bound, as X + dt Y (FP32 bit patterns, maxima from bslots):
+    C_BOUND_Y = 8,  //   the stress pass's exact form, or headroom times the previous P2G's largest
+    C_COUNT = 10
 };
 
 __host__ __device__ constexpr int ngb_slot(int table) { return table ? C_NGB1 : C_NGB; }
@@ -89,9 +91,14 @@ struct DevCtx {
     unsigned int *counters;
     int det;               // deterministic P2G: block tiles go to `stage`, then a fixed-order gather
     float *stage;          // [max_blocks][4 channels][kTileNodes] per particle block (deterministic mode)
+    unsigned int *bslots;  // [2][kBoundSlots][32]: partial maxima of the contribution bound (X, then Y),
+                           // one 128-byte line per slot, reduced into the counters by the bucket scan
 };
 
 constexpr int kStageFloats = 4 * kTileNodes;   // one particle block's tile in the deterministic staging area
+constexpr int kBoundSlots = 64;                // slots the contribution-bound maxima are spread over
+constexpr float kBoundHeadroom = 4.0f;         // next step's bound over this step's largest contribution bound
+constexpr int kBoundWords = 2 * kBoundSlots * 32;
 
 // First plane of each field in a particle state buffer (MPM_STATE_PLANES planes):
 // position x, velocity v, affine matrix B, H = F - I, position remainder r.
@@ -139,6 +146,46 @@ __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sq
 
 __device__ __forceinline__ void set_status(unsigned int *counters, uint32_t bits) {
     atomicOr(&counters[C_STATUS], bits);
+}
+
+// Bound, for any time step dt, on every P2G contribution of a particle of mass m and
+// initial volume V0 with velocity v, affine matrix B and Kirchhoff stress tau, in the
+// form X + dt Y.  The contributions are w m (w <= 1) and w (base + Q t) with t in
+// [-1/2, 3/2] per axis, base = m v - Q xi (xi in [0, 1)), Q = (m B - dt V0 tau) D^-1 / dx
+// (D in cell units, whose eigenvalues are at least 3/16 - 1/(4 pi) - 1/(4 pi^2) =
+// 0.08259, so |D^-1| <= 12.108): per component |base + Q t| <= m |v| + 2.5 sum_b |Q_ab|
+// <= m |v| + 2.5 sqrt(3) 12.108 |row a of (m B - dt V0 tau)| / dx.  1% of slack covers
+// the FP32 rounding of Q.
+__device__ __forceinline__ void contribution_bound_xy(float m, float vol0, float inv_dx, const float v[3],
+                                                      const float B[9], const float tau[6], float &X, float &Y) {
+    constexpr float kQ = 2.5f * 1.7320508f * 12.108f * 1.01f;
+    float vmax = fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fabsf(v[2]));
+    float b2 = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) b2 += B[i] * B[i];
+    const float t2 = tau[0] * tau[0] + tau[1] * tau[1] + tau[2] * tau[2] +
+                     2.0f * (tau[3] * tau[3] + tau[4] * tau[4] + tau[5] * tau[5]);
+    X = fmaxf(m, m * vmax + kQ * inv_dx * m * __builtin_sqrtf(b2));
+    Y = kQ * inv_dx * vol0 * __builtin_sqrtf(t2);
+}
+
+// Wave-wide maxima of X and Y into bound slot `slot` (called by every lane; lanes
+// without a particle pass zeros).  The maxima of a whole launch would meet at one
+// address; spread over kBoundSlots lines they do not queue behind each other.
+// Non-finite values are left out (the status word reports them).
+__device__ __forceinline__ void wave_bound(unsigned int *bslots, int slot, float X, float Y) {
+    X = (X == X && X <= 3.0e38f) ? X : 0.0f;
+    Y = (Y == Y && Y <= 3.0e38f) ? Y : 0.0f;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        X = fmaxf(X, __shfl_xor(X, off));
+        Y = fmaxf(Y, __shfl_xor(Y, off));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        const int k = slot & (kBoundSlots - 1);
+        if (X > 0.0f) atomicMax(&bslots[k * 32], __float_as_uint(X));
+        if (Y > 0.0f) atomicMax(&bslots[(kBoundSlots + k) * 32], __float_as_uint(Y));
+    }
 }
 
 __device__ __forceinline__ int vblock_id(const Geometry &g, int bx, int by, int bz) {

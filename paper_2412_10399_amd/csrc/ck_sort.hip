@@ -37,6 +37,7 @@ __device__ __forceinline__ void stamp_blocks(const DevCtx &d, int bx, int by, in
 
 __device__ __forceinline__ void b_flag_keys(const DevCtx &d, const PartArgs &pa, int epoch_offset) {
     const int i = blockIdx.x * kThreads + threadIdx.x;
+
     const int epoch = (int)d.counters[C_EPOCH] + epoch_offset;
     bool ok = i < pa.n;
     CellCoord cc;
@@ -515,6 +516,25 @@ __device__ __forceinline__ void b_bucket_scan(const DevCtx &d) {
         d.counters[C_MAXPB] = (unsigned)m;
         d.counters[C_TOTAL] = (unsigned)carry;
         if (m > kMaxBlockParticles) set_status(d.counters, ST_CAPACITY);
+    }
+    // the contribution bound for the P2G about to run: maxima of the slots the previous
+    // P2G (or the stress pass) filled, which are cleared for the next.  Empty slots (a
+    // sequence of fused steps, which form no bound) leave the last bound in place.
+    static_assert(kBoundSlots == 64, "one wave reduces the slots");
+    if (tid < kBoundSlots) {
+        unsigned int *sx = d.bslots + tid * 32, *sy = d.bslots + (kBoundSlots + tid) * 32;
+        unsigned int bxv = *sx, byv = *sy;
+        *sx = 0u;
+        *sy = 0u;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            bxv = max(bxv, (unsigned int)__shfl_xor((int)bxv, off));
+            byv = max(byv, (unsigned int)__shfl_xor((int)byv, off));
+        }
+        if (tid == 0 && (bxv | byv) != 0u) {
+            d.counters[C_BOUND_X] = bxv;
+            d.counters[C_BOUND_Y] = byv;
+        }
     }
 }
 

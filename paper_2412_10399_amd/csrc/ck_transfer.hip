@@ -217,19 +217,28 @@ __global__ void __launch_bounds__(kThreads) k_block_sort(DevCtx d) {
 // ---------------------------------------------------------------- stress
 // Kirchhoff stress of every particle of the current buffer, for a P2G that does not
 // follow a G2P of this context (first step, or positions changed by the caller).
+// Also adds the P2G contribution bound of the state to the bound slots.
 __device__ __forceinline__ void b_stress(const DevCtx &d, const PartArgs &pa) {
     const int p = blockIdx.x * kThreads + threadIdx.x;
-    if (p >= pa.n) return;
-    const long long S = pa.stride;
-    float H[9];
+    float X = 0.0f, Y = 0.0f;
+    if (p < pa.n) {
+        const long long S = pa.stride;
+        float H[9], v[3], B[9];
 #pragma unroll
-    for (int a = 0; a < 9; ++a) H[a] = pa.in[(15 + a) * S + p];
-    const int mi = pa.mat_in ? (int)pa.mat_in[p] : 0;
-    const DevMaterial M = d.mats[mi < d.n_mat ? mi : 0];
-    float tau[6];
-    kirchhoff(M, H, tau);
+        for (int a = 0; a < 9; ++a) H[a] = pa.in[(kPlaneH + a) * S + p];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) d.tau[i * d.tau_stride + p] = tau[i];
+        for (int a = 0; a < 3; ++a) v[a] = pa.in[(kPlaneV + a) * S + p];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) B[a] = pa.in[(kPlaneB + a) * S + p];
+        const int mi = pa.mat_in ? (int)pa.mat_in[p] : 0;
+        const DevMaterial M = d.mats[mi < d.n_mat ? mi : 0];
+        float tau[6];
+        kirchhoff(M, H, tau);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) d.tau[i * d.tau_stride + p] = tau[i];
+        contribution_bound_xy(M.mass, M.vol0, d.geo.inv_dx_f, v, B, tau, X, Y);
+    }
+    wave_bound(d.bslots, (int)blockIdx.x, X, Y);
 }
 
 __global__ void __launch_bounds__(kThreads) k_stress(DevCtx d, PartArgs pa) { b_stress(d, pa); }
@@ -468,6 +477,55 @@ __device__ __forceinline__ void scatter_grid_f64(double *tile, int ntile, int t0
         }
 }
 
+// scatter_grid with FP64 products: each contribution is the exact FP64 product of the
+// FP32 weight and the FP32 mass or momentum term, rounded once to the fixed-point unit
+// 1/S (|product| S < 2^51) and added as a 64-bit integer.
+__device__ __forceinline__ void scatter_grid_unit(unsigned long long *tile, int ntile, int t0, int sy, int sz,
+                                                  const float (&w)[3][2], double mS, const float (&m0)[3],
+                                                  const float (&Q)[9], double S) {
+    float mo[2][2][2][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        mo[0][0][0][a] = m0[a];
+        mo[0][0][1][a] = m0[a] + Q[3 * a];
+        mo[0][1][0][a] = m0[a] + Q[3 * a + 1];
+        mo[0][1][1][a] = mo[0][0][1][a] + Q[3 * a + 1];
+#pragma unroll
+        for (int oy = 0; oy < 2; ++oy)
+#pragma unroll
+            for (int ox = 0; ox < 2; ++ox) mo[1][oy][ox][a] = mo[0][oy][ox][a] + Q[3 * a + 2];
+    }
+#pragma unroll
+    for (int oz = 0; oz < 2; ++oz)
+#pragma unroll
+        for (int oy = 0; oy < 2; ++oy) {
+            const float wyz = w[1][oy] * w[2][oz];
+#pragma unroll
+            for (int ox = 0; ox < 2; ++ox) {
+                const double wt = (double)(w[0][ox] * wyz);
+                const double wS = wt * S;
+                const int t = t0 + ox + oy * sy + oz * sz;
+                atomicAdd(&tile[t], (unsigned long long)(__double_as_longlong(fma(wt, mS, kMagic)) - kMagicBits));
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    atomicAdd(&tile[(1 + a) * ntile + t],
+                              (unsigned long long)(__double_as_longlong(fma((double)mo[oz][oy][ox][a], wS, kMagic)) -
+                                                   kMagicBits));
+            }
+        }
+}
+
+template <int TY, int TZ, int SM, int SP>
+__device__ __forceinline__ void scatter_particle_unit(const Staged &r, int lx, int ly, int lz, unsigned long long *tile_m,
+                                                      unsigned long long *tile_p, double S) {
+    float wm[3][2], wp[3][2], mp[3];
+    int up[3];
+    staged_weights(r, wm, wp, up, mp);
+    const double mS = (double)r.mass * S;
+    scatter_grid_unit(tile_m, SM, lz * TZ + ly * TY + lx, TY, TZ, wm, mS, r.base, r.Q, S);
+    scatter_grid_unit(tile_p, SP, (lz + up[2]) * TZ + (ly + up[1]) * TY + (lx + up[0]), TY, TZ, wp, mS, mp, r.Q, S);
+}
+
 template <int TY, int TZ, int SM, int SP>
 __device__ __forceinline__ void scatter_particle_f64(const Staged &r, int lx, int ly, int lz, double *tile_m,
                                                      double *tile_p) {
@@ -692,10 +750,15 @@ __device__ __forceinline__ void b_p2g(const DevCtx &d, const PartArgs &pa, float
     uint16_t *rt = reinterpret_cast<uint16_t *>(lbuf + kMaxBlockParticles);   // after the ordering buffer
     unsigned long long *tile_m = area;
     unsigned long long *tile_p = area + 4 * kTileMStride;
-    double *ftile_m = reinterpret_cast<double *>(area);
-    double *ftile_p = ftile_m + 4 * kTileMStride;
     const int np = (int)d.counters[C_NPB];
     const int tid = threadIdx.x;
+    // step-global fixed-point unit (plain mode): 2^(e-39) for the contribution bound in
+    // [2^e, 2^(e+1)), so that every contribution is below 2^40 units and a node's sum
+    // over the at most kMaxBlockParticles particles of a block below 2^51
+    const float bound = __uint_as_float(d.counters[C_BOUND_X]) + dt * __uint_as_float(d.counters[C_BOUND_Y]);
+    const double S = (bound > 0.0f && bound <= 3.0e38f) ? ldexp(1.0, 39 - ilogbf(bound)) : 1.0;
+    const double inv_unit = 1.0 / S;
+    float seen = 0.0f;   // largest contribution bound of this thread's particles
     for (int base = 0; base < np; base += gridDim.x) {
         const int r = round_block(base, np);
         if (r < 0) continue;
@@ -710,10 +773,11 @@ __device__ __forceinline__ void b_p2g(const DevCtx &d, const PartArgs &pa, float
         lds_barrier();
 
         if (!kFixed) {
-            // ---- FP64 tile: with no unit to agree on, every thread stages and scatters
-            // one particle at a time (the first one loads while the tile is cleared);
-            // holding one staged particle instead of two lets the kernel run four waves
-            // per SIMD without spills, which beats overlapping two particles' loads
+            // ---- fixed-point tile with the step-global unit: the bound the preceding G2P
+            // (or stress pass) formed over every particle of the state, so that every
+            // thread stages and scatters one particle at a time (the first one loads while
+            // the tile is cleared).  A particle above the bound (a state changed in place
+            // without mpm_invalidate) adds to the pool with float atomics instead.
             Staged st;
             st.on = false;
             if (tid < cnt) stage_particle(d, pa, (int)ord[tid], bx, by, bz, dt, st);
@@ -721,21 +785,26 @@ __device__ __forceinline__ void b_p2g(const DevCtx &d, const PartArgs &pa, float
             lds_barrier();
             for (int j = tid; j < cnt; j += kP2GThreads) {
                 if (j > tid) stage_particle(d, pa, (int)ord[j], bx, by, bz, dt, st);
-                if (st.on)
-                    scatter_particle_f64<kTY, kTZ, kTileMStride, kTilePStride>(st, st.c[0] - 4 * bx, st.c[1] - 4 * by,
-                                                                               st.c[2] - 4 * bz, ftile_m, ftile_p);
+                if (!st.on) continue;
+                const float cb = contribution_bound(st);
+                seen = fmaxf(seen, cb);
+                if (cb <= bound)
+                    scatter_particle_unit<kTY, kTZ, kTileMStride, kTilePStride>(
+                        st, st.c[0] - 4 * bx, st.c[1] - 4 * by, st.c[2] - 4 * bz, tile_m, tile_p, S);
+                else
+                    scatter_pool(d, d.pool[gp], nbr, bx, by, bz, st);
             }
             lds_barrier();
             for (int ni = tid; ni < kTileNodes; ni += kP2GThreads) {
                 int g, ix, iy, iz;
                 tile_node(ni, bx, by, bz, g, ix, iy, iz);
                 const int lx = ix - 4 * bx + g, ly = iy - 4 * by + g, lz = iz - 4 * bz + g;   // tile-local
-                const double *tb = g == 0 ? ftile_m : ftile_p;
+                const unsigned long long *tb = g == 0 ? tile_m : tile_p;
                 const int cs = g == 0 ? kTileMStride : kTilePStride;
                 const int t = lx + ly * kTY + lz * kTZ;
                 float val[4];
 #pragma unroll
-                for (int ch = 0; ch < 4; ++ch) val[ch] = (float)tb[ch * cs + t];
+                for (int ch = 0; ch < 4; ++ch) val[ch] = (float)((double)(long long)tb[ch * cs + t] * inv_unit);
                 if (val[0] == 0.0f && val[1] == 0.0f && val[2] == 0.0f && val[3] == 0.0f) continue;
                 const long long a = pool_index(d, nbr, bx, by, bz, g, ix, iy, iz, 0);
                 if (a < 0) {
@@ -807,6 +876,10 @@ __device__ __forceinline__ void b_p2g(const DevCtx &d, const PartArgs &pa, float
             lds_barrier();
         }
     }
+    // the next step's unit: kBoundHeadroom times the largest contribution bound of this
+    // step (contributions change little from one step to the next; a particle beyond
+    // the headroom takes the float-atomic path)
+    if (!kFixed) wave_bound(d.bslots, (int)blockIdx.x, kBoundHeadroom * seen, 0.0f);
 }
 
 // Four waves per SIMD (128 VGPRs, none spilled; 40 KiB of LDS, four workgroups per
@@ -990,11 +1063,12 @@ struct NewState {
 __device__ __forceinline__ int g2p_finish(const DevCtx &d, const PartArgs &pa, float dt, const G2PIn &q,
                                           const DevMaterial &M, const float (&vn)[3], const float (&Bh)[9],
                                           const float (&Di)[9], uint32_t out, bool write_tau, NewState &ns,
-                                          CellCoord &cn, bool &placed);
+                                          CellCoord &cn, bool &placed, bool write_vB = true);
 
 __device__ __forceinline__ int g2p_particle(const DevCtx &d, const PartArgs &pa, float dt, const G2PIn &q,
                                             const CellCoord &cc, int bx, int by, int bz, const float *vt, uint32_t out,
-                                            bool write_tau, NewState &ns, CellCoord &cn, bool &placed) {
+                                            bool write_tau, NewState &ns, CellCoord &cn, bool &placed,
+                                            bool write_vB = true) {
     const DevMaterial M = d.mats[q.mat < d.n_mat ? q.mat : 0];
     Weights w;
     axis_weights(cc, w);
@@ -1060,7 +1134,7 @@ __device__ __forceinline__ int g2p_particle(const DevCtx &d, const PartArgs &pa,
     for (int a = 0; a < 3; ++a) vn[a] = cref[a] + 0.5f * vs[a];
 #pragma unroll
     for (int i = 0; i < 9; ++i) Bh[i] *= 0.5f;
-    return g2p_finish(d, pa, dt, q, M, vn, Bh, Di, out, write_tau, ns, cn, placed);
+    return g2p_finish(d, pa, dt, q, M, vn, Bh, Di, out, write_tau, ns, cn, placed, write_vB);
 }
 
 // The rest of G2P from the gathered velocity vn and Bh = B / dx (the affine sum in
@@ -1070,7 +1144,7 @@ __device__ __forceinline__ int g2p_particle(const DevCtx &d, const PartArgs &pa,
 __device__ __forceinline__ int g2p_finish_c(const DevCtx &d, const PartArgs &pa, float dt, const G2PIn &q,
                                             const DevMaterial &M, const float (&vn)[3], const float (&Bh)[9],
                                             const float (&Cc)[9], uint32_t out, bool write_tau, NewState &ns,
-                                            CellCoord &cn, bool &placed) {
+                                            CellCoord &cn, bool &placed, bool write_vB = true) {
     const long long S = pa.stride;
     int sig = -1;
     placed = false;
@@ -1103,7 +1177,7 @@ __device__ __forceinline__ int g2p_finish_c(const DevCtx &d, const PartArgs &pa,
     for (int i = 0; i < 9; ++i) probe += Fn[i] * 0.0f + Bn[i] * 0.0f;
     const bool finite = probe == 0.0f;
     if (!finite) set_status(d.counters, ST_NONFINITE);
-    {
+    if (write_vB) {
         float st[24];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -1116,8 +1190,13 @@ __device__ __forceinline__ int g2p_finish_c(const DevCtx &d, const PartArgs &pa,
             st[15 + i] = Fn[i];
         }
         st_planes(pa.out, S, kPlaneX, out, st);
-        st_planes(pa.out, S, kPlaneR, out, xrn);
+    } else {
+        // the fused step: v and B go straight into the next P2G, only x and H are read
+        // again (by the next step's G2P)
+        st_planes(pa.out, S, kPlaneX, out, xn);
+        st_planes(pa.out, S, kPlaneH, out, Fn);
     }
+    st_planes(pa.out, S, kPlaneR, out, xrn);
     if (write_tau) st_planes(d.tau, d.tau_stride, 0, out, tau);
     if (pa.id_out) st_at(pa.id_out, out, q.id);
     if (pa.mat_out) st_at(pa.mat_out, out, (uint8_t)q.mat);
@@ -1148,14 +1227,14 @@ __device__ __forceinline__ int g2p_finish_c(const DevCtx &d, const PartArgs &pa,
 __device__ __forceinline__ int g2p_finish(const DevCtx &d, const PartArgs &pa, float dt, const G2PIn &q,
                                           const DevMaterial &M, const float (&vn)[3], const float (&Bh)[9],
                                           const float (&Di)[9], uint32_t out, bool write_tau, NewState &ns,
-                                          CellCoord &cn, bool &placed) {
+                                          CellCoord &cn, bool &placed, bool write_vB) {
     float Cc[9];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j2 = 0; j2 < 3; ++j2)
             Cc[3 * i + j2] = Bh[3 * i] * Di[j2] + Bh[3 * i + 1] * Di[3 + j2] + Bh[3 * i + 2] * Di[6 + j2];
-    return g2p_finish_c(d, pa, dt, q, M, vn, Bh, Cc, out, write_tau, ns, cn, placed);
+    return g2p_finish_c(d, pa, dt, q, M, vn, Bh, Cc, out, write_tau, ns, cn, placed, write_vB);
 }
 
 // G2P workgroups of 128 threads (all G2P kernels): the block's tile gather at the
@@ -1849,10 +1928,12 @@ __global__ void __launch_bounds__(kP2GThreads) k_block_order(DevCtx d) {
 // ---------------------------------------------------------------- fused G2P + P2G
 // G2P of step n fused with P2G of step n+1 (the paper's G2P2G kernel structure):
 // each workgroup gathers its block's particles from grid n, updates them, writes
-// the new state, and scatters the new state into grid n+1 through a fixed-point
-// tile covering every node the block's particles reach after moving at most one
-// cell: G- nodes [4B-1, 4B+5]^3 and G+ nodes [4B-2, 4B+5]^3 (7^3 + 8^3 = 855
-// nodes).  Particles that moved further add to the pool with float atomics (up to
+// the new positions and deformation gradients (the new v and B go straight into the
+// scatter and are never stored; the last step of a sequence runs the plain G2P, which
+// stores the whole state), and scatters every particle into grid n+1 as soon as it is
+// updated, through an FP64 tile covering every node the block's particles reach after
+// moving at most one cell: G- nodes [4B-1, 4B+5]^3 and G+ nodes [4B-2, 4B+5]^3
+// (7^3 + 8^3 = 855 nodes).  Particles that moved further add to the pool with float atomics (up to
 // three cells; beyond that the step reports MPM_E_CFL).  Grid n+1 is the 3 x 3 x 3
 // block neighbourhood of the particle blocks of step n, prepared by the same sort.
 constexpr int kFTY = 8, kFTZ = 66;                   // for every node offset the 64 cells of a block
@@ -1866,7 +1947,6 @@ __global__ void __launch_bounds__(kP2GThreads, 2) k_g2p2g(DevCtx d, PartArgs pa,
     __shared__ int bcnt[kBins];
     __shared__ int bstart[kBins + 1];
     __shared__ int wsum[kP2GThreads / 64];
-    __shared__ unsigned int bmax;
     __shared__ int nbr_in[27], nbr_out[27];
     __shared__ uint32_t ord[kMaxBlockParticles];
     __shared__ float vt[3 * kTileNodes];
@@ -1876,8 +1956,8 @@ __global__ void __launch_bounds__(kP2GThreads, 2) k_g2p2g(DevCtx d, PartArgs pa,
     __shared__ int lay[kLayWords];
     uint32_t *lbuf = reinterpret_cast<uint32_t *>(area);
     uint16_t *rt = reinterpret_cast<uint16_t *>(lbuf + kMaxBlockParticles);   // after the ordering buffer
-    unsigned long long *tile_m = area;
-    unsigned long long *tile_p = area + 4 * kFMStride;
+    double *tile_m = reinterpret_cast<double *>(area);
+    double *tile_p = tile_m + 4 * kFMStride;
     const int np = (int)d.counters[C_NPB];
     const int E = (int)d.counters[C_EPOCH];
     const int tid = threadIdx.x;
@@ -1894,6 +1974,10 @@ __global__ void __launch_bounds__(kP2GThreads, 2) k_g2p2g(DevCtx d, PartArgs pa,
         load_neighbours(d, gt_in, bx, by, bz, nbr_in);
         load_neighbours(d, gt_out, bx, by, bz, nbr_out, 64);
         lds_barrier();
+        // grid n's velocity tile, the first particle's inputs and the cleared FP64 tile
+        // of grid n+1 (which reuses the ordering buffers) in one round
+        G2PIn nxt;
+        if (tid < cnt) g2p_load_index(pa, ord[tid], nxt);
         for (int ni = tid; ni < kTileNodes; ni += kP2GThreads) {
             int g, ix, iy, iz;
             tile_node(ni, bx, by, bz, g, ix, iy, iz);
@@ -1901,88 +1985,75 @@ __global__ void __launch_bounds__(kP2GThreads, 2) k_g2p2g(DevCtx d, PartArgs pa,
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) vt[ch * kTileNodes + ni] = a >= 0 ? d.pool[gp_in][a + ch * 64] : 0.0f;
         }
-        for (int c0 = 0; c0 < cnt; c0 += kChunk) {
-            lds_barrier();   // velocity tile in place; previous pass's tile flushed
-            for (int q = tid; q < kTileWords; q += kP2GThreads) area[q] = 0ull;
-            if (tid == 0) bmax = 0u;
-            G2PIn in[2];
-#pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                const int j = c0 + tid + k * kP2GThreads;
-                if (j < cnt) g2p_load_index(pa, ord[j], in[k]);
-            }
-            Staged st[2];
-            float bnd = 0.0f;
-#pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                const int j = c0 + tid + k * kP2GThreads;
-                const bool act = j < cnt;
-                const uint32_t out = (uint32_t)(s + j);
-                st[k].on = false;
-                CellCoord cc;
-                bool ok = act && cell_coord(d.geo, in[k].x, in[k].xr, cc);
-                ok = ok && (cc.c[0] >> 2) == bx && (cc.c[1] >> 2) == by && (cc.c[2] >> 2) == bz;
-                int sig = -1;
-                if (act && !ok) {
-                    set_status(d.counters, ST_STALE);
-                    st_at(d.key, out, 0xffffffffu);
-                } else if (ok) {
-                    NewState ns;
-                    CellCoord cn;
-                    bool placed;
-                    sig = g2p_particle(d, pa, dt, in[k], cc, bx, by, bz, vt, out, false, ns, cn, placed);
-                    if (placed) {
-                        const DevMaterial M = d.mats[in[k].mat < d.n_mat ? in[k].mat : 0];
-                        stage_compute(d, M, cn, ns.v, ns.B, ns.tau, dt, st[k]);
-                    }
+        for (int q = tid; q < kTileWords; q += kP2GThreads) area[q] = 0ull;
+        lds_barrier();
+        // each particle: G2P from grid n, then at once its P2G into grid n+1 (no block
+        // unit to agree on with an FP64 tile, so nothing is held between particles)
+        for (int j0 = 0; j0 < cnt; j0 += kP2GThreads) {   // the same trip count for every lane
+            const int j = j0 + tid;
+            const bool act = j < cnt;
+            const G2PIn q = nxt;
+            if (j + kP2GThreads < cnt) g2p_load_index(pa, ord[j + kP2GThreads], nxt);
+            const uint32_t out = (uint32_t)(s + j);
+            CellCoord cc;
+            bool ok = act && cell_coord(d.geo, q.x, q.xr, cc);
+            ok = ok && (cc.c[0] >> 2) == bx && (cc.c[1] >> 2) == by && (cc.c[2] >> 2) == bz;
+            int sig = -1;
+            Staged st;
+            st.on = false;
+            if (act && !ok) {
+                set_status(d.counters, ST_STALE);
+                st_at(d.key, out, 0xffffffffu);
+            } else if (ok) {
+                NewState ns;
+                CellCoord cn;
+                bool placed;
+                sig = g2p_particle(d, pa, dt, q, cc, bx, by, bz, vt, out, false, ns, cn, placed, false);
+                if (placed) {
+                    const DevMaterial M = d.mats[q.mat < d.n_mat ? q.mat : 0];
+                    stage_compute(d, M, cn, ns.v, ns.B, ns.tau, dt, st);
                 }
-                wave_stamp(d, sig, E + 1);
-                bnd = fmaxf(bnd, contribution_bound(st[k]));
             }
-            lds_barrier();   // tile cleared, bmax reset
-            const double S = block_scale(bnd, &bmax);
-#pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                if (!st[k].on) continue;
-                const int lx = st[k].c[0] - 4 * bx + 1, ly = st[k].c[1] - 4 * by + 1, lz = st[k].c[2] - 4 * bz + 1;
+            wave_stamp(d, sig, E + 1);
+            if (st.on) {
+                const int lx = st.c[0] - 4 * bx + 1, ly = st.c[1] - 4 * by + 1, lz = st.c[2] - 4 * bz + 1;
                 if (lx >= 0 && ly >= 0 && lz >= 0 && lx <= 5 && ly <= 5 && lz <= 5)
-                    scatter_particle<kFTY, kFTZ, kFMStride, kFPStride>(st[k], lx, ly, lz, tile_m, tile_p, S);
+                    scatter_particle_f64<kFTY, kFTZ, kFMStride, kFPStride>(st, lx, ly, lz, tile_m, tile_p);
                 else
-                    scatter_pool(d, d.pool[gp_out], nbr_out, bx, by, bz, st[k]);
+                    scatter_pool(d, d.pool[gp_out], nbr_out, bx, by, bz, st);
             }
-            lds_barrier();
-            // ---- flush every nonzero tile node to grid n+1
-            const double inv = 1.0 / S;
-            for (int ni = tid; ni < kFNodesM + kFNodesP; ni += kP2GThreads) {
-                const int g = ni < kFNodesM ? 0 : 1;
-                int lx, ly, lz;
-                if (g == 0) {
-                    lx = ni % 7;
-                    ly = (ni / 7) % 7;
-                    lz = ni / 49;
-                } else {
-                    const int k = ni - kFNodesM;
-                    lx = k & 7;
-                    ly = (k >> 3) & 7;
-                    lz = k >> 6;
-                }
-                const unsigned long long *tb = g == 0 ? tile_m : tile_p;
-                const int cs = g == 0 ? kFMStride : kFPStride;
-                const int t = lx + ly * kFTY + lz * kFTZ;
-                float val[4];
-#pragma unroll
-                for (int ch = 0; ch < 4; ++ch) val[ch] = (float)((double)(long long)tb[ch * cs + t] * inv);
-                if (val[0] == 0.0f && val[1] == 0.0f && val[2] == 0.0f && val[3] == 0.0f) continue;
-                const int ix = 4 * bx - 1 - g + lx, iy = 4 * by - 1 - g + ly, iz = 4 * bz - 1 - g + lz;
-                const long long a = pool_index(d, nbr_out, bx, by, bz, g, ix, iy, iz, 0);
-                if (a < 0) {
-                    set_status(d.counters, ST_CFL);
-                    continue;
-                }
-#pragma unroll
-                for (int ch = 0; ch < 4; ++ch)
-                    if (val[ch] != 0.0f) atomicAdd(&d.pool[gp_out][a + ch * 64], val[ch]);
+        }
+        lds_barrier();
+        // ---- flush every nonzero tile node to grid n+1
+        for (int ni = tid; ni < kFNodesM + kFNodesP; ni += kP2GThreads) {
+            const int g = ni < kFNodesM ? 0 : 1;
+            int lx, ly, lz;
+            if (g == 0) {
+                lx = ni % 7;
+                ly = (ni / 7) % 7;
+                lz = ni / 49;
+            } else {
+                const int k = ni - kFNodesM;
+                lx = k & 7;
+                ly = (k >> 3) & 7;
+                lz = k >> 6;
             }
+            const double *tb = g == 0 ? tile_m : tile_p;
+            const int cs = g == 0 ? kFMStride : kFPStride;
+            const int t = lx + ly * kFTY + lz * kFTZ;
+            float val[4];
+#pragma unroll
+            for (int ch = 0; ch < 4; ++ch) val[ch] = (float)tb[ch * cs + t];
+            if (val[0] == 0.0f && val[1] == 0.0f && val[2] == 0.0f && val[3] == 0.0f) continue;
+            const int ix = 4 * bx - 1 - g + lx, iy = 4 * by - 1 - g + ly, iz = 4 * bz - 1 - g + lz;
+            const long long a = pool_index(d, nbr_out, bx, by, bz, g, ix, iy, iz, 0);
+            if (a < 0) {
+                set_status(d.counters, ST_CFL);
+                continue;
+            }
+#pragma unroll
+            for (int ch = 0; ch < 4; ++ch)
+                if (val[ch] != 0.0f) atomicAdd(&d.pool[gp_out][a + ch * 64], val[ch]);
         }
         lds_barrier();
     }
@@ -2098,18 +2169,21 @@ namespace {
 
 // Launches for the jobs of one size class (every grid sized for the largest of them).
 void launch_step_run(const JobStep *dev, const JobStep *host, int njobs, hipStream_t s) {
-    launch_sort_multi(dev, host, njobs, s);
     int stress_grid = 0, pgrid = 8, ugrid = 1;
+    for (int j = 0; j < njobs; ++j)
+        if (host[j].first || host[j].d.det)
+            stress_grid = std::max(stress_grid, (host[j].pa.n + kThreads - 1) / kThreads);
+    // the stress pass adds the contribution bound that the sort's bucket scan hands to P2G
+    if (stress_grid > 0) hipLaunchKernelGGL(k_stress_multi, dim3(stress_grid, njobs), dim3(kThreads), 0, s, dev);
+    launch_sort_multi(dev, host, njobs, s);
     bool any_det = false, any_plain = false;
     for (int j = 0; j < njobs; ++j) {
         const JobStep &J = host[j];
-        if (J.first || J.d.det) stress_grid = std::max(stress_grid, (J.pa.n + kThreads - 1) / kThreads);
         pgrid = std::max(pgrid, particle_grid(J.d));
         ugrid = std::max(ugrid, J.d.max_blocks < kGridWGs ? J.d.max_blocks : kGridWGs);
         any_det = any_det || J.d.det;
         any_plain = any_plain || !J.d.det;
     }
-    if (stress_grid > 0) hipLaunchKernelGGL(k_stress_multi, dim3(stress_grid, njobs), dim3(kThreads), 0, s, dev);
     if (any_plain) hipLaunchKernelGGL(k_p2g_multi, dim3(pgrid, njobs), dim3(kP2GThreads), 0, s, dev);
     if (any_det) hipLaunchKernelGGL(k_p2g_det_multi, dim3(pgrid, njobs), dim3(kP2GThreads), 0, s, dev);
     if (any_det) hipLaunchKernelGGL(k_det_gather_multi, dim3(ugrid, njobs), dim3(128), 0, s, dev);
