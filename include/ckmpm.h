@@ -170,7 +170,12 @@ mpm_status mpm_grid_update(mpm_ctx *ctx, double dt, void *stream);
  * keys, and flips p->current. */
 mpm_status mpm_g2p(mpm_ctx *ctx, mpm_particles *p, double dt, void *stream);
 
-/* nsteps x (p2g, grid_update, g2p), enqueued back to back without host syncs.  With
+/* nsteps x (p2g, grid_update, g2p), enqueued back to back without host syncs.  Inside
+ * the sequence (compact kernel, MLS transfer, not deterministic) every G2P but the last
+ * stores, in place of B, the matrix Q = (m B - dt V0 tau) D^-1 / dx that the next P2G
+ * scatters, and no stress, so that the next P2G reads neither; the last step stores
+ * the whole state.  The other ping-pong buffer's contents afterwards are unspecified.
+ * With
  * MPM_FLAG_FUSED_G2P2G, each step's G2P and the next step's P2G run as one kernel
  * from the second step on (the same arithmetic; the grid each fused P2G writes is the
  * 3x3x3 block neighbourhood of the particle blocks, so a particle may move at most
@@ -274,11 +279,14 @@ typedef struct {
     int32_t flags;             /* 0 or MPM_SERVER_GROUPED                                              */
 } mpm_server_config;
 
-/* mpm_server_config.flags: every phase of a step runs as one launch for all active
- * jobs (workgroup row y of each launch works on job y, the grid sized for the
- * largest job), steps_per_launch steps per round, instead of each job launching
- * its own kernels on its own stream.  Jobs must use the compact kernel with the MLS
- * transfer and no config flags (else mpm_server_submit returns MPM_E_INVALID). */
+/* mpm_server_config.flags: jobs are sorted into size-class lanes (particle counts
+ * eight-fold apart from 2^10 up, min(n_streams, 4) lanes, the last taking every larger
+ * job); every phase of a step runs as one launch for all active jobs of a lane
+ * (workgroup row y of each launch works on job y), steps_per_launch steps per round,
+ * instead of each job launching its own kernels on its own stream.  Each lane runs its
+ * rounds on its own stream, a round replaying a captured HIP graph while the lane's
+ * job set is unchanged.  Jobs must use the compact kernel with the MLS transfer and
+ * no config flags (else mpm_server_submit returns MPM_E_INVALID). */
 enum { MPM_SERVER_GROUPED = 1 };
 
 typedef struct {

@@ -35,6 +35,7 @@ struct mpm_ctx {
     const float *next_ready = nullptr;   // buffer whose keys and next-epoch stamps are in place
     long long next_n = -1;
     const float *p2g_done = nullptr;     // buffer the last p2g ran on
+    const float *carried = nullptr;      // buffer whose B planes hold Q (an mpm_step G2P with carry wrote it)
     int grid_pool = 0, grid_table = 0;   // the grid the last p2g (or fused step) wrote: pool and page table
     int next_table = 0;                  // page table the next sort builds
     int written = -1;                    // buffer the last g2p wrote (mpm_current_buffer)
@@ -239,7 +240,7 @@ mpm_status enqueue_p2g(mpm_ctx *ctx, const mpm_particles *p, double dt, hipStrea
     if (!physics) {
         launch_block_sort(ctx->d, s);
     } else {
-        launch_p2g(ctx->d, pa, (float)dt, t, t, s);
+        launch_p2g(ctx->d, pa, (float)dt, t, t, s, ready && ctx->carried == pa.in);
         if (ctx->d.det) launch_det_gather(ctx->d, t, t, s);
         ctx->grid_pool = t;
         ctx->grid_table = t;
@@ -247,6 +248,7 @@ mpm_status enqueue_p2g(mpm_ctx *ctx, const mpm_particles *p, double dt, hipStrea
     if (ev) (void)hipEventRecord(ev[2], s);
     ctx->next_ready = nullptr;
     ctx->p2g_done = pa.in;
+    ctx->carried = nullptr;
     return last_error();
 }
 
@@ -256,13 +258,21 @@ mpm_status enqueue_update(mpm_ctx *ctx, double dt, hipStream_t s) {
     return last_error();
 }
 
-mpm_status enqueue_g2p(mpm_ctx *ctx, mpm_particles *p, double dt, hipStream_t s) {
+// carry (inside mpm_step, for every step but the last): the new state's B planes take
+// Q = (m B - dt V0 tau) D^-1 / dx for the next step's P2G, which then reads neither B nor
+// the carried stress (24 B less written and read per particle); the plain compact-kernel
+// MLS path only, and not in deterministic mode.
+bool can_carry(const mpm_ctx *ctx) { return !ctx->d.det && !ctx->d.quadratic && ctx->d.transfer == MPM_TRANSFER_MLS; }
+
+mpm_status enqueue_g2p(mpm_ctx *ctx, mpm_particles *p, double dt, hipStream_t s, bool carry = false) {
     if (ctx->p2g_done != p->state[p->current]) return MPM_E_INVALID;
     if (!p->state[p->current ^ 1]) return MPM_E_INVALID;
     if ((p->id[0] == nullptr) != (p->id[1] == nullptr)) return MPM_E_INVALID;
     if ((p->mat[0] == nullptr) != (p->mat[1] == nullptr)) return MPM_E_INVALID;
     const PartArgs pa = part_args(p, true);
-    launch_g2p(ctx->d, pa, (float)dt, ctx->grid_pool, ctx->grid_table, s);
+    carry = carry && can_carry(ctx);
+    launch_g2p(ctx->d, pa, (float)dt, ctx->grid_pool, ctx->grid_table, s, carry);
+    ctx->carried = carry ? pa.out : nullptr;
     p->current ^= 1;
     ctx->written = p->current;
     ctx->next_ready = pa.out;
@@ -511,7 +521,7 @@ mpm_status step_sequence(mpm_ctx *ctx, mpm_particles *p, double dt, int32_t nste
             mpm_status st = enqueue_p2g(ctx, p, dt, s, ev, true);
             if (st == MPM_OK) st = enqueue_update(ctx, dt, s);
             if (st == MPM_OK && ev) (void)hipEventRecord(ev[3], s);
-            if (st == MPM_OK) st = enqueue_g2p(ctx, p, dt, s);
+            if (st == MPM_OK) st = enqueue_g2p(ctx, p, dt, s, k + 1 < nsteps);
             if (st == MPM_OK && ev) {
                 (void)hipEventRecord(ev[4], s);
                 ctx->ev_used += 1;

@@ -751,10 +751,14 @@ void launch_compact(const DevCtx &d, int table, hipStream_t s);
 void launch_bucket(const DevCtx &d, int n, int zero_pool, int zero_table, hipStream_t s);
 void launch_block_sort(const DevCtx &d, hipStream_t s);
 void launch_stress(const DevCtx &d, const PartArgs &pa, hipStream_t s);
-void launch_p2g(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, hipStream_t s);
+// carried: the B planes of pa.in hold Q and there is no carried stress (the state an
+// mpm_step G2P with carry left for the next step)
+void launch_p2g(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, hipStream_t s, bool carried = false);
 void launch_grid_update(const DevCtx &d, float dt, const float gravity[3], int gp, int gt, hipStream_t s);
 void launch_det_gather(const DevCtx &d, int gp, int gt, hipStream_t s);
-void launch_g2p(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, hipStream_t s);
+// carry: store Q = (m B - dt V0 tau) D^-1 / dx in the B planes and no stress, for a P2G
+// with `carried` that follows in the same step sequence
+void launch_g2p(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, hipStream_t s, bool carry = false);
 void launch_grid_export(const DevCtx &d, float *m, float *vec, int gp, int gt, int g0, int ng, hipStream_t s);
 void launch_block_order(const DevCtx &d, hipStream_t s);
 void launch_g2p2g(const DevCtx &d, const PartArgs &pa, float dt, int gp_in, int gt_in, int gp_out, int gt_out,

@@ -103,6 +103,7 @@ struct Job {
     std::vector<void *> bufs;           // arena buffers of the particle state
     int slot = -1;                      // resident slot: events and pinned status word
     int stream = 0;
+    int lane = 0;                       // grouped mode: size-class lane
     bool in_flight = false;
     int chunk = 0;                      // steps of the launch in flight
     int ev_cur = 0;                     // event the launch in flight records
@@ -118,6 +119,30 @@ struct Slot {
     bool used = false;
 };
 
+// Grouped mode: the jobs of one size class share one launch per phase (their lane's
+// round), and the lanes run on their own streams, each round as soon as that lane's
+// previous one has finished, so a large job's step does not wait for the small jobs'
+// launches, nor small jobs for the large one.
+struct Lane {
+    ck::JobStep *table_host = nullptr;         // pinned, max_jobs x steps_per_launch entries
+    ck::JobStep *table_dev = nullptr;
+    hipEvent_t gev[2] = {nullptr, nullptr};    // start and end of the round in flight
+    bool in_flight = false;
+    std::vector<std::pair<int64_t, int>> round;   // (job, steps) of the round in flight
+    hipGraphExec_t graph = nullptr;               // the last round's captured launch sequence
+    std::vector<int64_t> sig;                     // what it was captured for (see poll_grouped)
+    hipStream_t stream = nullptr;
+};
+
+// Lane of a job of n particles: classes eight-fold apart in particle count from 2^10 up,
+// the last lane taking every larger job.
+int lane_of(int64_t n, int lanes) {
+    int lg = 0;
+    while (lg < 62 && (int64_t(1) << (lg + 1)) <= n) ++lg;
+    const int c = (lg - 10) / 3;
+    return c < 0 ? 0 : (c >= lanes ? lanes - 1 : c);
+}
+
 double seconds_since(std::chrono::steady_clock::time_point t0) {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -127,15 +152,9 @@ double seconds_since(std::chrono::steady_clock::time_point t0) {
 struct mpm_server {
     mpm_server_config cfg{};
     int device = 0;
-    // grouped mode: one launch per phase for all active jobs
+    // grouped mode: one launch per phase for all active jobs of a size-class lane
     bool grouped = false;
-    ck::JobStep *table_host = nullptr;     // pinned, max_jobs x steps_per_launch entries
-    ck::JobStep *table_dev = nullptr;
-    hipEvent_t gev[2] = {nullptr, nullptr};   // start and end of the round in flight
-    bool round_in_flight = false;
-    std::vector<std::pair<int64_t, int>> round;   // (job, steps) of the round in flight
-    hipGraphExec_t round_graph = nullptr;         // the last round's captured launch sequence
-    std::vector<int64_t> round_sig;               // what it was captured for (see poll_grouped)
+    std::vector<Lane> lanes;
     int64_t graph_captures = 0, graph_replays = 0;
     Arena arena;
     std::vector<hipStream_t> streams;
@@ -225,7 +244,9 @@ bool admit(mpm_server *srv, Job &j) {
         return true;
     }
     j.ctx = ctx;
-    j.stream = srv->grouped ? 0 : srv->next_stream;   // grouped rounds run on stream 0
+    // grouped: the job's lane runs its rounds on stream `lane`, after this copy-in
+    if (srv->grouped) j.lane = lane_of(n, (int)srv->lanes.size());
+    j.stream = srv->grouped ? j.lane : srv->next_stream;
     if (!srv->grouped) srv->next_stream = (srv->next_stream + 1) % (int)srv->streams.size();
     hipStream_t s = srv->streams[j.stream];
     j.parts = mpm_particles{};
@@ -292,42 +313,130 @@ mpm_status launch(mpm_server *srv, Job &j) {
     return MPM_OK;
 }
 
-// Grouped mode: retire the round in flight, admit, then run the next round of every
-// active job (steps_per_launch steps, fewer for jobs that need fewer).
+// Grouped mode: retire the rounds in flight, admit, then run the next round of every
+// idle lane (steps_per_launch steps of each of its active jobs, fewer for jobs that
+// need fewer).
+void retire_round(mpm_server *srv, Lane &ln, hipError_t q) {
+    ln.in_flight = false;
+    float ms = 0.0f;
+    const bool timed = q == hipSuccess && hipEventElapsedTime(&ms, ln.gev[0], ln.gev[1]) == hipSuccess;
+    int longest = 1;
+    for (const auto &js : ln.round) longest = std::max(longest, js.second);
+    for (const auto &js : ln.round) {
+        Job &j = *srv->jobs[js.first];
+        j.in_flight = false;
+        if (q != hipSuccess) {
+            fail(srv, j, MPM_E_HIP);
+            continue;
+        }
+        if (timed)
+            for (int k = 0; k < js.second; ++k) srv->step_lat.push_back(ms * 1e-3 / longest);
+        j.info.steps_done += js.second;
+        const unsigned int bits = srv->status_host[j.slot];
+        if (bits != 0) {
+            fail(srv, j, ck::status_from_bits(bits));
+        } else if (j.info.steps_done >= j.desc.nsteps) {
+            j.info.state = MPM_JOB_DONE;
+            j.info.status = MPM_OK;
+            j.info.t_done = seconds_since(srv->t0);
+            srv->active -= 1;
+        }
+    }
+    ln.round.clear();
+}
+
+// Builds and enqueues lane ln's next round over `run` (its idle active jobs, largest
+// first).  The round's launches depend only on which job takes which table entry and
+// whether that entry is the job's first step; the table's contents are uploaded by the
+// graph's own copy from pinned memory on every replay, so the captured graph is
+// replayed while that signature holds.
+void start_round(mpm_server *srv, Lane &ln, std::vector<Job *> &run) {
+    hipStream_t s = ln.stream;
+    const int spl = srv->cfg.steps_per_launch;
+    std::vector<int> steps(run.size()), count(spl, 0);
+    size_t used = 0;
+    bool ok = hipEventRecord(ln.gev[0], s) == hipSuccess;
+    // step k of the round: entries of every job with more than k steps left
+    for (int k = 0; k < spl && ok; ++k) {
+        for (size_t r = 0; r < run.size(); ++r) {
+            Job &j = *run[r];
+            if (j.desc.nsteps - j.info.steps_done <= k) continue;
+            const mpm_status st = ck::group_step(j.ctx, &j.parts, j.desc.dt, ln.table_host[used]);
+            if (st != MPM_OK) {
+                ok = false;
+                break;
+            }
+            ++used;
+            ++count[k];
+            steps[r] += 1;
+        }
+    }
+    std::vector<int64_t> sig;
+    sig.reserve(used + (size_t)spl + 1);
+    sig.push_back((int64_t)used);
+    for (int k = 0; k < spl; ++k) sig.push_back(count[k]);
+    {
+        size_t e = 0;
+        for (int k = 0; k < spl; ++k)
+            for (size_t r = 0; r < run.size(); ++r) {
+                Job &j = *run[r];
+                if (j.desc.nsteps - j.info.steps_done <= k) continue;
+                sig.push_back(j.id * 2 + ln.table_host[e].first);
+                ++e;
+            }
+    }
+    if (ok && (!ln.graph || sig != ln.sig)) {
+        if (ln.graph) (void)hipGraphExecDestroy(ln.graph);
+        ln.graph = nullptr;
+        ln.sig.clear();
+        hipGraph_t g = nullptr;
+        ok = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) == hipSuccess;
+        if (ok) {
+            bool cap = hipMemcpyAsync(ln.table_dev, ln.table_host, used * sizeof(ck::JobStep), hipMemcpyHostToDevice,
+                                      s) == hipSuccess;
+            size_t off = 0;
+            for (int k = 0; k < spl && cap; ++k) {
+                if (count[k] == 0) break;
+                ck::launch_step_multi(ln.table_dev + off, ln.table_host + off, count[k], s);
+                off += (size_t)count[k];
+            }
+            cap = cap && hipGetLastError() == hipSuccess;
+            for (size_t r = 0; r < run.size() && cap; ++r)
+                cap = hipMemcpyAsync(&srv->status_host[run[r]->slot], ck::ctx_status_word(run[r]->ctx),
+                                     sizeof(unsigned int), hipMemcpyDeviceToHost, s) == hipSuccess;
+            const hipError_t ce = hipStreamEndCapture(s, &g);
+            ok = cap && ce == hipSuccess && g && hipGraphInstantiate(&ln.graph, g, nullptr, nullptr, 0) == hipSuccess;
+            if (g) (void)hipGraphDestroy(g);
+            if (!ok) ln.graph = nullptr;
+        }
+        if (ok) {
+            ln.sig.swap(sig);
+            srv->graph_captures += 1;
+        }
+    } else if (ok) {
+        srv->graph_replays += 1;
+    }
+    ok = ok && hipGraphLaunch(ln.graph, s) == hipSuccess;
+    ok = ok && hipEventRecord(ln.gev[1], s) == hipSuccess;
+    if (!ok) {
+        for (Job *j : run) fail(srv, *j, MPM_E_HIP);
+        return;
+    }
+    for (size_t r = 0; r < run.size(); ++r) {
+        run[r]->in_flight = true;
+        ln.round.emplace_back(run[r]->id, steps[r]);
+    }
+    ln.in_flight = true;
+}
+
 mpm_status poll_grouped(mpm_server *srv, bool *progressed) {
     bool moved = false;
-    hipStream_t s = srv->streams[0];
-    if (srv->round_in_flight) {
-        const hipError_t q = hipEventQuery(srv->gev[1]);
-        if (q != hipErrorNotReady) {
-            moved = true;
-            srv->round_in_flight = false;
-            float ms = 0.0f;
-            const bool timed = q == hipSuccess && hipEventElapsedTime(&ms, srv->gev[0], srv->gev[1]) == hipSuccess;
-            int longest = 1;
-            for (const auto &js : srv->round) longest = std::max(longest, js.second);
-            for (const auto &js : srv->round) {
-                Job &j = *srv->jobs[js.first];
-                j.in_flight = false;
-                if (q != hipSuccess) {
-                    fail(srv, j, MPM_E_HIP);
-                    continue;
-                }
-                if (timed)
-                    for (int k = 0; k < js.second; ++k) srv->step_lat.push_back(ms * 1e-3 / longest);
-                j.info.steps_done += js.second;
-                const unsigned int bits = srv->status_host[j.slot];
-                if (bits != 0) {
-                    fail(srv, j, ck::status_from_bits(bits));
-                } else if (j.info.steps_done >= j.desc.nsteps) {
-                    j.info.state = MPM_JOB_DONE;
-                    j.info.status = MPM_OK;
-                    j.info.t_done = seconds_since(srv->t0);
-                    srv->active -= 1;
-                }
-            }
-            srv->round.clear();
-        }
+    for (Lane &ln : srv->lanes) {
+        if (!ln.in_flight) continue;
+        const hipError_t q = hipEventQuery(ln.gev[1]);
+        if (q == hipErrorNotReady) continue;
+        moved = true;
+        retire_round(srv, ln, q);
     }
     while (!srv->pending.empty() && srv->resident < srv->cfg.max_jobs) {
         Job &j = *srv->jobs[srv->pending.front()];
@@ -335,106 +444,27 @@ mpm_status poll_grouped(mpm_server *srv, bool *progressed) {
         srv->pending.pop_front();
         moved = true;
     }
-    if (!srv->round_in_flight) {
-        // jobs with no steps to run finish at once
-        std::vector<Job *> run;
-        for (auto &kv : srv->jobs) {
-            Job &j = *kv.second;
-            if (j.info.state != MPM_JOB_ACTIVE || j.in_flight) continue;
-            if (j.info.steps_done >= j.desc.nsteps) {
-                j.info.state = MPM_JOB_DONE;
-                j.info.status = MPM_OK;
-                j.info.t_done = seconds_since(srv->t0);
-                srv->active -= 1;
-                moved = true;
-                continue;
-            }
-            run.push_back(&j);
-        }
-        if (!run.empty()) {
-            // largest jobs first: each step's entries then fall into contiguous size classes
-            std::stable_sort(run.begin(), run.end(), [](const Job *a, const Job *b) { return a->desc.n > b->desc.n; });
-            const int spl = srv->cfg.steps_per_launch;
-            std::vector<int> steps(run.size()), count(spl, 0);
-            size_t used = 0;
-            bool ok = hipEventRecord(srv->gev[0], s) == hipSuccess;
-            // step k of the round: entries of every job with more than k steps left
-            for (int k = 0; k < spl && ok; ++k) {
-                for (size_t r = 0; r < run.size(); ++r) {
-                    Job &j = *run[r];
-                    if (j.desc.nsteps - j.info.steps_done <= k) continue;
-                    const mpm_status st = ck::group_step(j.ctx, &j.parts, j.desc.dt, srv->table_host[used]);
-                    if (st != MPM_OK) {
-                        ok = false;
-                        break;
-                    }
-                    ++used;
-                    ++count[k];
-                    steps[r] += 1;
-                }
-            }
-            // the round's launches depend only on which job takes which table entry and
-            // whether that entry is the job's first step; the table's contents are
-            // uploaded by the graph's own copy from pinned memory on every replay
-            std::vector<int64_t> sig;
-            sig.reserve(used + (size_t)spl + 1);
-            sig.push_back((int64_t)used);
-            for (int k = 0; k < spl; ++k) sig.push_back(count[k]);
-            {
-                size_t e = 0;
-                for (int k = 0; k < spl; ++k)
-                    for (size_t r = 0; r < run.size(); ++r) {
-                        Job &j = *run[r];
-                        if (j.desc.nsteps - j.info.steps_done <= k) continue;
-                        sig.push_back(j.id * 2 + srv->table_host[e].first);
-                        ++e;
-                    }
-            }
-            if (ok && (!srv->round_graph || sig != srv->round_sig)) {
-                if (srv->round_graph) (void)hipGraphExecDestroy(srv->round_graph);
-                srv->round_graph = nullptr;
-                srv->round_sig.clear();
-                hipGraph_t g = nullptr;
-                ok = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) == hipSuccess;
-                if (ok) {
-                    bool cap = hipMemcpyAsync(srv->table_dev, srv->table_host, used * sizeof(ck::JobStep),
-                                              hipMemcpyHostToDevice, s) == hipSuccess;
-                    size_t off = 0;
-                    for (int k = 0; k < spl && cap; ++k) {
-                        if (count[k] == 0) break;
-                        ck::launch_step_multi(srv->table_dev + off, srv->table_host + off, count[k], s);
-                        off += (size_t)count[k];
-                    }
-                    cap = cap && hipGetLastError() == hipSuccess;
-                    for (size_t r = 0; r < run.size() && cap; ++r)
-                        cap = hipMemcpyAsync(&srv->status_host[run[r]->slot], ck::ctx_status_word(run[r]->ctx),
-                                             sizeof(unsigned int), hipMemcpyDeviceToHost, s) == hipSuccess;
-                    const hipError_t ce = hipStreamEndCapture(s, &g);
-                    ok = cap && ce == hipSuccess && g &&
-                         hipGraphInstantiate(&srv->round_graph, g, nullptr, nullptr, 0) == hipSuccess;
-                    if (g) (void)hipGraphDestroy(g);
-                    if (!ok) srv->round_graph = nullptr;
-                }
-                if (ok) {
-                    srv->round_sig.swap(sig);
-                    srv->graph_captures += 1;
-                }
-            } else if (ok) {
-                srv->graph_replays += 1;
-            }
-            ok = ok && hipGraphLaunch(srv->round_graph, s) == hipSuccess;
-            ok = ok && hipEventRecord(srv->gev[1], s) == hipSuccess;
-            if (!ok) {
-                for (Job *j : run) fail(srv, *j, MPM_E_HIP);
-            } else {
-                for (size_t r = 0; r < run.size(); ++r) {
-                    run[r]->in_flight = true;
-                    srv->round.emplace_back(run[r]->id, steps[r]);
-                }
-                srv->round_in_flight = true;
-            }
+    // jobs with no steps to run finish at once; the others go to their lane's next round
+    std::vector<std::vector<Job *>> run(srv->lanes.size());
+    for (auto &kv : srv->jobs) {
+        Job &j = *kv.second;
+        if (j.info.state != MPM_JOB_ACTIVE || j.in_flight) continue;
+        if (j.info.steps_done >= j.desc.nsteps) {
+            j.info.state = MPM_JOB_DONE;
+            j.info.status = MPM_OK;
+            j.info.t_done = seconds_since(srv->t0);
+            srv->active -= 1;
             moved = true;
+            continue;
         }
+        if (!srv->lanes[j.lane].in_flight) run[j.lane].push_back(&j);
+    }
+    for (size_t l = 0; l < srv->lanes.size(); ++l) {
+        if (run[l].empty()) continue;
+        // largest jobs first: each step's entries then fall into contiguous size classes
+        std::stable_sort(run[l].begin(), run[l].end(), [](const Job *a, const Job *b) { return a->desc.n > b->desc.n; });
+        start_round(srv, srv->lanes[l], run[l]);
+        moved = true;
     }
     if (progressed) *progressed = moved;
     return MPM_OK;
@@ -532,9 +562,14 @@ mpm_status mpm_server_create(const mpm_server_config *cfg, mpm_server **out) {
     srv->grouped = (cfg->flags & MPM_SERVER_GROUPED) != 0;
     if (srv->grouped) {
         const size_t entries = (size_t)cfg->max_jobs * (size_t)cfg->steps_per_launch;
-        ok = hipHostMalloc((void **)&srv->table_host, entries * sizeof(ck::JobStep), hipHostMallocDefault) == hipSuccess;
-        ok = ok && hipMalloc((void **)&srv->table_dev, entries * sizeof(ck::JobStep)) == hipSuccess;
-        for (int k = 0; ok && k < 2; ++k) ok = hipEventCreate(&srv->gev[k]) == hipSuccess;
+        srv->lanes.resize((size_t)std::min(cfg->n_streams, 4));
+        for (size_t l = 0; ok && l < srv->lanes.size(); ++l) {
+            Lane &ln = srv->lanes[l];
+            ln.stream = srv->streams[l];
+            ok = hipHostMalloc((void **)&ln.table_host, entries * sizeof(ck::JobStep), hipHostMallocDefault) == hipSuccess;
+            ok = ok && hipMalloc((void **)&ln.table_dev, entries * sizeof(ck::JobStep)) == hipSuccess;
+            for (int k = 0; ok && k < 2; ++k) ok = hipEventCreate(&ln.gev[k]) == hipSuccess;
+        }
         if (!ok) {
             (void)mpm_server_destroy(srv);
             return MPM_E_HIP;
@@ -559,11 +594,13 @@ mpm_status mpm_server_destroy(mpm_server *srv) {
     for (hipStream_t s : srv->streams) (void)hipStreamDestroy(s);
     if (srv->init_stream) (void)hipStreamDestroy(srv->init_stream);
     if (srv->status_host) (void)hipHostFree(srv->status_host);
-    if (srv->table_host) (void)hipHostFree(srv->table_host);
-    if (srv->table_dev) (void)hipFree(srv->table_dev);
-    for (hipEvent_t e : srv->gev)
-        if (e) (void)hipEventDestroy(e);
-    if (srv->round_graph) (void)hipGraphExecDestroy(srv->round_graph);
+    for (Lane &ln : srv->lanes) {
+        if (ln.table_host) (void)hipHostFree(ln.table_host);
+        if (ln.table_dev) (void)hipFree(ln.table_dev);
+        for (hipEvent_t e : ln.gev)
+            if (e) (void)hipEventDestroy(e);
+        if (ln.graph) (void)hipGraphExecDestroy(ln.graph);
+    }
     srv->arena.release();
     delete srv;
     return MPM_OK;
@@ -621,7 +658,12 @@ mpm_status mpm_server_drain(mpm_server *srv) {
         if (st != MPM_OK) return st;
         if (moved) continue;
         // nothing to do until a launch ends: block on the oldest one in flight
-        if (srv->grouped && srv->round_in_flight) (void)hipEventSynchronize(srv->gev[1]);
+        if (srv->grouped)
+            for (Lane &ln : srv->lanes)
+                if (ln.in_flight) {
+                    (void)hipEventSynchronize(ln.gev[1]);
+                    break;
+                }
         for (auto &kv : srv->jobs) {
             if (srv->grouped) break;
             Job &j = *kv.second;

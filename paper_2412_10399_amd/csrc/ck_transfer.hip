@@ -342,6 +342,30 @@ __device__ __forceinline__ void stage_compute(const DevCtx &d, const DevMaterial
     r.on = true;
 }
 
+// P2G record of a particle whose B planes carry Q itself (the state an mpm_step G2P
+// left for the next step): only the weights and base = m v - Q xi remain to form.
+__device__ __forceinline__ void stage_compute_q(const DevMaterial &M, const CellCoord &cc, const float (&v)[3],
+                                                const float (&Q)[9], Staged &r) {
+    const uint32_t code = sub_code(cc);
+    r.oct = (int)(code & 7u);
+    Weights w;
+    axis_weights(cc, w);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) r.c[a] = cc.c[a];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) r.Q[i] = Q[i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        r.xm[a] = cc.xm[a];
+        r.sp[a] = w.sp[a];
+        r.base[a] = M.mass * v[a] - (Q[3 * a] * cc.xm[0] + Q[3 * a + 1] * cc.xm[1] + Q[3 * a + 2] * cc.xm[2]);
+    }
+    r.mass = M.mass;
+    r.on = true;
+}
+
+// kCarried: the B planes of the input hold Q (and there is no carried stress).
+template <bool kCarried = false>
 __device__ __forceinline__ void stage_particle(const DevCtx &d, const PartArgs &pa, int p, int bx, int by, int bz,
                                                float dt, Staged &r) {
     r.on = false;
@@ -352,7 +376,7 @@ __device__ __forceinline__ void stage_particle(const DevCtx &d, const PartArgs &
     ld_planes(pa.in, S, kPlaneR, up, xr);
     ld_planes(pa.in, S, kPlaneV, up, v);
     ld_planes(pa.in, S, kPlaneB, up, B);
-    ld_planes(d.tau, d.tau_stride, 0, up, tau);
+    if (!kCarried) ld_planes(d.tau, d.tau_stride, 0, up, tau);
     const int mi = pa.mat_in ? (int)ld_at(pa.mat_in, up) : 0;
     const DevMaterial M = d.mats[mi < d.n_mat ? mi : 0];
     CellCoord cc;
@@ -364,7 +388,8 @@ __device__ __forceinline__ void stage_particle(const DevCtx &d, const PartArgs &
         set_status(d.counters, ST_STALE);
         return;
     }
-    stage_compute(d, M, cc, v, B, tau, dt, r);
+    if (kCarried) stage_compute_q(M, cc, v, B, r);
+    else stage_compute(d, M, cc, v, B, tau, dt, r);
 }
 
 // Upper bound of |w m| and |w (base + Q t)| over the particle's 16 nodes (w <= 1,
@@ -733,7 +758,7 @@ __device__ __forceinline__ double block_scale(float bnd, unsigned int *bmax) {
 // stages two particles per thread, takes the block's unit from their bounds, then
 // scatters them.  Otherwise an FP64 tile: every thread stages and scatters one
 // particle at a time (no unit to agree on first), and the block takes a single pass.
-template <bool kFixed>
+template <bool kFixed, bool kCarried = false>
 __device__ __forceinline__ void b_p2g(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt) {
     __shared__ int bcnt[kBins];                 // counts, then placement cursors
     __shared__ int bstart[kBins + 1];
@@ -780,11 +805,11 @@ __device__ __forceinline__ void b_p2g(const DevCtx &d, const PartArgs &pa, float
             // without mpm_invalidate) adds to the pool with float atomics instead.
             Staged st;
             st.on = false;
-            if (tid < cnt) stage_particle(d, pa, (int)ord[tid], bx, by, bz, dt, st);
+            if (tid < cnt) stage_particle<kCarried>(d, pa, (int)ord[tid], bx, by, bz, dt, st);
             for (int q = tid; q < kTileWords; q += kP2GThreads) area[q] = 0ull;
             lds_barrier();
             for (int j = tid; j < cnt; j += kP2GThreads) {
-                if (j > tid) stage_particle(d, pa, (int)ord[j], bx, by, bz, dt, st);
+                if (j > tid) stage_particle<kCarried>(d, pa, (int)ord[j], bx, by, bz, dt, st);
                 if (!st.on) continue;
                 const float cb = contribution_bound(st);
                 seen = fmaxf(seen, cb);
@@ -886,6 +911,10 @@ __device__ __forceinline__ void b_p2g(const DevCtx &d, const PartArgs &pa, float
 // CU): 0.263 ms on the sand column against 0.303 ms at three.
 __global__ void __launch_bounds__(kP2GThreads, 4) k_p2g(DevCtx d, PartArgs pa, float dt, int gp, int gt) {
     b_p2g<false>(d, pa, dt, gp, gt);
+}
+// the same on a state whose B planes carry Q (the intermediate states of mpm_step)
+__global__ void __launch_bounds__(kP2GThreads, 4) k_p2g_carried(DevCtx d, PartArgs pa, float dt, int gp, int gt) {
+    b_p2g<false, true>(d, pa, dt, gp, gt);
 }
 __global__ void __launch_bounds__(kP2GThreads, 3) k_p2g_det(DevCtx d, PartArgs pa, float dt, int gp, int gt) {
     b_p2g<true>(d, pa, dt, gp, gt);
@@ -1063,12 +1092,12 @@ struct NewState {
 __device__ __forceinline__ int g2p_finish(const DevCtx &d, const PartArgs &pa, float dt, const G2PIn &q,
                                           const DevMaterial &M, const float (&vn)[3], const float (&Bh)[9],
                                           const float (&Di)[9], uint32_t out, bool write_tau, NewState &ns,
-                                          CellCoord &cn, bool &placed, bool write_vB = true);
+                                          CellCoord &cn, bool &placed, bool write_vB = true, bool carry = false);
 
 __device__ __forceinline__ int g2p_particle(const DevCtx &d, const PartArgs &pa, float dt, const G2PIn &q,
                                             const CellCoord &cc, int bx, int by, int bz, const float *vt, uint32_t out,
                                             bool write_tau, NewState &ns, CellCoord &cn, bool &placed,
-                                            bool write_vB = true) {
+                                            bool write_vB = true, bool carry = false) {
     const DevMaterial M = d.mats[q.mat < d.n_mat ? q.mat : 0];
     Weights w;
     axis_weights(cc, w);
@@ -1134,7 +1163,7 @@ __device__ __forceinline__ int g2p_particle(const DevCtx &d, const PartArgs &pa,
     for (int a = 0; a < 3; ++a) vn[a] = cref[a] + 0.5f * vs[a];
 #pragma unroll
     for (int i = 0; i < 9; ++i) Bh[i] *= 0.5f;
-    return g2p_finish(d, pa, dt, q, M, vn, Bh, Di, out, write_tau, ns, cn, placed, write_vB);
+    return g2p_finish(d, pa, dt, q, M, vn, Bh, Di, out, write_tau, ns, cn, placed, write_vB, carry);
 }
 
 // The rest of G2P from the gathered velocity vn and Bh = B / dx (the affine sum in
@@ -1144,7 +1173,7 @@ __device__ __forceinline__ int g2p_particle(const DevCtx &d, const PartArgs &pa,
 __device__ __forceinline__ int g2p_finish_c(const DevCtx &d, const PartArgs &pa, float dt, const G2PIn &q,
                                             const DevMaterial &M, const float (&vn)[3], const float (&Bh)[9],
                                             const float (&Cc)[9], uint32_t out, bool write_tau, NewState &ns,
-                                            CellCoord &cn, bool &placed, bool write_vB = true) {
+                                            CellCoord &cn, bool &placed, bool write_vB = true, bool carry = false) {
     const long long S = pa.stride;
     int sig = -1;
     placed = false;
@@ -1177,7 +1206,36 @@ __device__ __forceinline__ int g2p_finish_c(const DevCtx &d, const PartArgs &pa,
     for (int i = 0; i < 9; ++i) probe += Fn[i] * 0.0f + Bn[i] * 0.0f;
     const bool finite = probe == 0.0f;
     if (!finite) set_status(d.counters, ST_NONFINITE);
-    if (write_vB) {
+    const bool inside = finite && cell_coord(d.geo, xn, xrn, cn);
+    if (carry) {
+        // carried form for the next P2G of the same step sequence: Q = (m B - dt V0 tau)
+        // D^-1 / dx at the new position in place of B, and no stress (the same
+        // arithmetic that P2G applies to a stored B and stress)
+        Weights w2;
+        axis_weights(cn, w2);
+        float Di2[9];
+        moment_inverse(cn, w2, Di2);
+        const float T[9] = {tau[0], tau[3], tau[4], tau[3], tau[1], tau[5], tau[4], tau[5], tau[2]};
+        const float k = dt * M.vol0;
+        float A[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) A[i] = M.mass * Bn[i] - k * T[i];
+        const float sc = d.geo.inv_dx_f;
+        float st[24];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            st[a] = xn[a];
+            st[3 + a] = vn[a];
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j2 = 0; j2 < 3; ++j2)
+                st[6 + 3 * i + j2] = sc * (A[3 * i] * Di2[j2] + A[3 * i + 1] * Di2[3 + j2] + A[3 * i + 2] * Di2[6 + j2]);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) st[15 + i] = Fn[i];
+        st_planes(pa.out, S, kPlaneX, out, st);
+    } else if (write_vB) {
         float st[24];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -1197,11 +1255,11 @@ __device__ __forceinline__ int g2p_finish_c(const DevCtx &d, const PartArgs &pa,
         st_planes(pa.out, S, kPlaneH, out, Fn);
     }
     st_planes(pa.out, S, kPlaneR, out, xrn);
-    if (write_tau) st_planes(d.tau, d.tau_stride, 0, out, tau);
+    if (write_tau && !carry) st_planes(d.tau, d.tau_stride, 0, out, tau);
     if (pa.id_out) st_at(pa.id_out, out, q.id);
     if (pa.mat_out) st_at(pa.mat_out, out, (uint8_t)q.mat);
     // next cell key for the following step
-    if (finite && cell_coord(d.geo, xn, xrn, cn)) {
+    if (inside) {
         const uint32_t key = cell_key(d.geo, cn);
         st_at(d.key, out, key);
         st_at(d.sub, out, (uint16_t)sub_code(cn));
@@ -1227,14 +1285,14 @@ __device__ __forceinline__ int g2p_finish_c(const DevCtx &d, const PartArgs &pa,
 __device__ __forceinline__ int g2p_finish(const DevCtx &d, const PartArgs &pa, float dt, const G2PIn &q,
                                           const DevMaterial &M, const float (&vn)[3], const float (&Bh)[9],
                                           const float (&Di)[9], uint32_t out, bool write_tau, NewState &ns,
-                                          CellCoord &cn, bool &placed, bool write_vB) {
+                                          CellCoord &cn, bool &placed, bool write_vB, bool carry) {
     float Cc[9];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j2 = 0; j2 < 3; ++j2)
             Cc[3 * i + j2] = Bh[3 * i] * Di[j2] + Bh[3 * i + 1] * Di[3 + j2] + Bh[3 * i + 2] * Di[6 + j2];
-    return g2p_finish_c(d, pa, dt, q, M, vn, Bh, Cc, out, write_tau, ns, cn, placed, write_vB);
+    return g2p_finish_c(d, pa, dt, q, M, vn, Bh, Cc, out, write_tau, ns, cn, placed, write_vB, carry);
 }
 
 // G2P workgroups of 128 threads (all G2P kernels): the block's tile gather at the
@@ -1244,6 +1302,8 @@ __device__ __forceinline__ int g2p_finish(const DevCtx &d, const PartArgs &pa, f
 // column; the quadratic and gradient G2P gain 9 %).
 constexpr int kG2PThreads = 128;
 
+// kCarry: the output's B planes take Q for the next P2G of the same step sequence.
+template <bool kCarry = false>
 __device__ __forceinline__ void b_g2p(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt) {
     __shared__ float vt[3 * kTileNodes];
     __shared__ int nbr[27];
@@ -1290,7 +1350,7 @@ __device__ __forceinline__ void b_g2p(const DevCtx &d, const PartArgs &pa, float
                 NewState ns;
                 CellCoord cn;
                 bool placed;
-                sig = g2p_particle(d, pa, dt, q, cc, bx, by, bz, vt, out, true, ns, cn, placed);
+                sig = g2p_particle(d, pa, dt, q, cc, bx, by, bz, vt, out, true, ns, cn, placed, true, kCarry);
             }
             wave_stamp(d, sig, E + 1);
         }
@@ -1299,6 +1359,9 @@ __device__ __forceinline__ void b_g2p(const DevCtx &d, const PartArgs &pa, float
 }
 
 __global__ void __launch_bounds__(kG2PThreads) k_g2p(DevCtx d, PartArgs pa, float dt, int gp, int gt) { b_g2p(d, pa, dt, gp, gt); }
+__global__ void __launch_bounds__(kG2PThreads) k_g2p_carry(DevCtx d, PartArgs pa, float dt, int gp, int gt) {
+    b_g2p<true>(d, pa, dt, gp, gt);
+}
 
 // one launch for many jobs: workgroup row y runs job y
 __global__ void __launch_bounds__(kG2PThreads) k_g2p_multi(const JobStep *__restrict__ jobs) {
@@ -2116,13 +2179,15 @@ void launch_stress(const DevCtx &d, const PartArgs &pa, hipStream_t s) {
     if (pa.n > 0) hipLaunchKernelGGL(k_stress, dim3((pa.n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, d, pa);
 }
 
-void launch_p2g(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, hipStream_t s) {
+void launch_p2g(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, hipStream_t s, bool carried) {
     if (d.quadratic)
         hipLaunchKernelGGL(k_p2g_quad, dim3(particle_grid(d)), dim3(kP2GThreads), 0, s, d, pa, dt, gp, gt);
     else if (d.transfer != 0)
         hipLaunchKernelGGL(k_p2g_grad, dim3(particle_grid(d)), dim3(kP2GThreads), 0, s, d, pa, dt, gp, gt);
     else if (d.det)
         hipLaunchKernelGGL(k_p2g_det, dim3(particle_grid(d)), dim3(kP2GThreads), 0, s, d, pa, dt, gp, gt);
+    else if (carried)
+        hipLaunchKernelGGL(k_p2g_carried, dim3(particle_grid(d)), dim3(kP2GThreads), 0, s, d, pa, dt, gp, gt);
     else
         hipLaunchKernelGGL(k_p2g, dim3(particle_grid(d)), dim3(kP2GThreads), 0, s, d, pa, dt, gp, gt);
 }
@@ -2136,11 +2201,13 @@ void launch_grid_update(const DevCtx &d, float dt, const float gravity[3], int g
                        gravity[0], gravity[1], gravity[2], gp, gt);
 }
 
-void launch_g2p(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, hipStream_t s) {
+void launch_g2p(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, hipStream_t s, bool carry) {
     if (d.quadratic)
         hipLaunchKernelGGL(k_g2p_quad, dim3(particle_grid(d)), dim3(kG2PThreads), 0, s, d, pa, dt, gp, gt);
     else if (d.transfer != 0)
         hipLaunchKernelGGL(k_g2p_grad, dim3(particle_grid(d)), dim3(kG2PThreads), 0, s, d, pa, dt, gp, gt);
+    else if (carry)
+        hipLaunchKernelGGL(k_g2p_carry, dim3(particle_grid(d)), dim3(kG2PThreads), 0, s, d, pa, dt, gp, gt);
     else
         hipLaunchKernelGGL(k_g2p, dim3(particle_grid(d)), dim3(kG2PThreads), 0, s, d, pa, dt, gp, gt);
 }
