@@ -39,6 +39,9 @@ STEP_GRID_BLOCK_BYTES = 2048 + 2048 + 3584 + 1536
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sand_column_4M.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2412_10399_amd", "csrc", f) for f in ("ck_transfer.hip", "ck_common.hpp")]
 KERNEL_SYMBOL = {"p2g": "k_p2g", "g2p": "k_g2p", "grid_update": "k_grid_update", "g2p2g": "k_g2p2g"}
+# inside an mpm_step sequence of the plain compact-kernel MLS path, every step's G2P but
+# the last stores the carried Q and every P2G but the first reads it
+CARRIED_SYMBOL = {"p2g": "k_p2g_carried", "g2p": "k_g2p_carry"}
 
 
 def source_digest():
@@ -453,8 +456,9 @@ def main():
                    "kernel": "quadratic_bspline_single_grid" if args.quadratic else "compact_dual_grid",
                    "transfer": args.transfer},
         "roofline": {"bound": "hbm",
-                     "kernel": KERNEL_SYMBOL[dominant] + ("_quad" if args.quadratic and dominant in ("p2g", "g2p") else
-                                                         "_grad" if transfer and dominant in ("p2g", "g2p") else ""),
+                     "kernel": (KERNEL_SYMBOL[dominant] + "_quad" if args.quadratic and dominant in ("p2g", "g2p") else
+                                KERNEL_SYMBOL[dominant] + "_grad" if transfer and dominant in ("p2g", "g2p") else
+                                CARRIED_SYMBOL.get(dominant, KERNEL_SYMBOL[dominant])),
                      "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "alg_bytes_per_launch": alg_bytes,
