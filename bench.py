@@ -39,9 +39,10 @@ STEP_GRID_BLOCK_BYTES = 2048 + 2048 + 3584 + 1536
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sand_column_4M.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2412_10399_amd", "csrc", f) for f in ("ck_transfer.hip", "ck_common.hpp")]
 KERNEL_SYMBOL = {"p2g": "k_p2g", "g2p": "k_g2p", "grid_update": "k_grid_update", "g2p2g": "k_g2p2g"}
-# inside an mpm_step sequence of the plain compact-kernel MLS path, every step's G2P but
-# the last stores the carried Q and every P2G but the first reads it
-CARRIED_SYMBOL = {"p2g": "k_p2g_carried", "g2p": "k_g2p_carry"}
+# inside an mpm_step sequence of the plain compact-kernel MLS path, every G2P but the
+# last writes the carried state (Q, packed remainder) and every P2G and G2P but the
+# first reads it: the timed steps run these two
+CARRIED_SYMBOL = {"p2g": "k_p2g_carried", "g2p": "k_g2p_cc"}
 
 
 def source_digest():

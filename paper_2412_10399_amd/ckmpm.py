@@ -510,7 +510,7 @@ class Server:
         self._inputs = {}
 
     def submit(self, cfg: mpm_config, mats: Sequence[mpm_material], state, nsteps: int, dt: float, mat=None) -> int:
-        """Queue a job; `state` is a (24, n) float32 CUDA tensor (H = F - I), `mat` an
+        """Queue a job; `state` is a (27, n) float32 CUDA tensor (`state_planes` layout), `mat` an
         optional (n,) uint8 CUDA tensor."""
         arr = (mpm_material * len(mats))(*mats)
         d = mpm_job_desc()

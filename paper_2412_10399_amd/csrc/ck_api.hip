@@ -1,6 +1,7 @@
 // C ABI of the compact-kernel MPM library (declared in include/ckmpm.h): context
 // creation and validation, launch sequencing of the step's kernels, status
 // reporting and per-phase event timing.  No allocation happens after mpm_create.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -35,7 +36,8 @@ struct mpm_ctx {
     const float *next_ready = nullptr;   // buffer whose keys and next-epoch stamps are in place
     long long next_n = -1;
     const float *p2g_done = nullptr;     // buffer the last p2g ran on
-    const float *carried = nullptr;      // buffer whose B planes hold Q (an mpm_step G2P with carry wrote it)
+    const float *carried = nullptr;      // buffer holding the carried state (an mpm_step G2P with carry wrote it)
+    bool g2p_carried = false;            // the state the last P2G read (the next G2P's input) was carried
     int grid_pool = 0, grid_table = 0;   // the grid the last p2g (or fused step) wrote: pool and page table
     int next_table = 0;                  // page table the next sort builds
     int written = -1;                    // buffer the last g2p wrote (mpm_current_buffer)
@@ -124,6 +126,13 @@ void fill_geometry(const mpm_config &c, Geometry &g) {
     g.inv_dx = 1.0 / c.dx;
     g.dx = (float)c.dx;
     g.inv_dx_f = (float)(1.0 / c.dx);
+    // packed remainder unit: 2^-9 of the FP32 ulp of the axis's largest coordinate
+    for (int a = 0; a < 3; ++a) {
+        const double m = std::max(std::fabs(c.origin[a]), std::fabs(c.origin[a] + c.n_cells[a] * c.dx));
+        const int e = m > 0.0 ? std::max(std::ilogb((float)m), -90) : -90;
+        g.r_unit[a] = std::ldexp(1.0f, e - 23 - 9);
+        g.inv_r_unit[a] = std::ldexp(1.0f, 23 + 9 - e);
+    }
     // a node i of grid G_k (k = -1, +1) sits at (i + k/4) cells (the quadratic
     // comparison kernel's single grid, stored as G-, at i cells); it is inside the
     // sticky walls when band <= its position <= n - band on every axis
@@ -225,6 +234,7 @@ mpm_status enqueue_p2g(mpm_ctx *ctx, const mpm_particles *p, double dt, hipStrea
     // keys, next-step block stamps and the stress of every particle are in place
     // when the previous mpm_g2p wrote this very buffer
     const bool ready = ctx->next_ready == pa.in && ctx->next_n == pa.n;
+    const bool carried_in = ready && ctx->carried == pa.in;
     if (ev) (void)hipEventRecord(ev[0], s);
     if (!ready) launch_flag_keys(ctx->d, pa, 1, s);
     // deterministic mode recomputes the stress from F every step, so that a run
@@ -240,7 +250,7 @@ mpm_status enqueue_p2g(mpm_ctx *ctx, const mpm_particles *p, double dt, hipStrea
     if (!physics) {
         launch_block_sort(ctx->d, s);
     } else {
-        launch_p2g(ctx->d, pa, (float)dt, t, t, s, ready && ctx->carried == pa.in);
+        launch_p2g(ctx->d, pa, (float)dt, t, t, s, carried_in);
         if (ctx->d.det) launch_det_gather(ctx->d, t, t, s);
         ctx->grid_pool = t;
         ctx->grid_table = t;
@@ -248,6 +258,7 @@ mpm_status enqueue_p2g(mpm_ctx *ctx, const mpm_particles *p, double dt, hipStrea
     if (ev) (void)hipEventRecord(ev[2], s);
     ctx->next_ready = nullptr;
     ctx->p2g_done = pa.in;
+    ctx->g2p_carried = physics && carried_in;
     ctx->carried = nullptr;
     return last_error();
 }
@@ -271,7 +282,8 @@ mpm_status enqueue_g2p(mpm_ctx *ctx, mpm_particles *p, double dt, hipStream_t s,
     if ((p->mat[0] == nullptr) != (p->mat[1] == nullptr)) return MPM_E_INVALID;
     const PartArgs pa = part_args(p, true);
     carry = carry && can_carry(ctx);
-    launch_g2p(ctx->d, pa, (float)dt, ctx->grid_pool, ctx->grid_table, s, carry);
+    launch_g2p(ctx->d, pa, (float)dt, ctx->grid_pool, ctx->grid_table, s, carry, ctx->g2p_carried);
+    ctx->g2p_carried = false;
     ctx->carried = carry ? pa.out : nullptr;
     p->current ^= 1;
     ctx->written = p->current;

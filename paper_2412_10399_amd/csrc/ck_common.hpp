@@ -58,6 +58,8 @@ struct Geometry {
     int NB[3];             // virtual blocks per axis (n/4 + 1)
     int stick_lo[2];       // per grid: a node is inside the walls when lo <= i <= hi on every axis
     int stick_hi[2][3];
+    float r_unit[3];       // unit of the packed position remainder (a power of two), see pack_remainder
+    float inv_r_unit[3];
 };
 
 struct DevCtx {
@@ -94,6 +96,25 @@ struct DevCtx {
     unsigned int *bslots;  // [2][kBoundSlots][32]: partial maxima of the contribution bound (X, then Y),
                            // one 128-byte line per slot, reduced into the counters by the bucket scan
 };
+
+// The material of a particle: a per-lane selection among the context's materials,
+// which are read with scalar loads (a uniform address), so that no vector memory
+// load -- which would wait for every load issued before it -- stands in a
+// particle's arithmetic.  Out-of-range indices take material 0.
+__device__ __forceinline__ DevMaterial material_of(const DevCtx &d, int mi) {
+    DevMaterial M = d.mats[0];
+    for (int i = 1; i < d.n_mat; ++i) {
+        const DevMaterial C = d.mats[i];
+        const bool take = mi == i;
+        M.model = take ? C.model : M.model;
+        M.mass = take ? C.mass : M.mass;
+        M.vol0 = take ? C.vol0 : M.vol0;
+        M.mu = take ? C.mu : M.mu;
+        M.lambda = take ? C.lambda : M.lambda;
+        M.dp_coef = take ? C.dp_coef : M.dp_coef;
+    }
+    return M;
+}
 
 constexpr int kStageFloats = 4 * kTileNodes;   // one particle block's tile in the deterministic staging area
 constexpr int kBoundSlots = 64;                // slots the contribution-bound maxima are spread over
@@ -243,6 +264,29 @@ __device__ __forceinline__ void advance_position(float x, float r, float d, floa
     const double s = ((double)x + (double)r) + (double)d;
     xn = (float)s;
     rn = (float)(s - (double)xn);
+}
+
+// The position remainder of the carried state inside an mpm_step sequence: each
+// FP32 remainder rounded to a multiple of its axis's unit, 2^-9 of the FP32 ulp of
+// the largest coordinate of the domain on that axis, so that |r| <= ulp(x)/2 is at
+// most 256 units, and the three stored as 10-bit signed integers in one 32-bit word
+// (bits 0-9, 10-19, 20-29).  The position x + r then keeps 2^-10 of the domain's
+// largest ulp (about 1e-10 for a unit domain) in 4 bytes instead of 12.  Every
+// reader of the word (the next P2G and G2P) takes the same FP64 sum x + r, and the
+// G2P that packs it takes the cell key from the packed value too.
+__device__ __forceinline__ uint32_t pack_remainder(const Geometry &g, const float r[3]) {
+    uint32_t w = 0u;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int q = min(max((int)rintf(r[a] * g.inv_r_unit[a]), -511), 511);
+        w |= ((uint32_t)q & 1023u) << (10 * a);
+    }
+    return w;
+}
+
+__device__ __forceinline__ void unpack_remainder(const Geometry &g, uint32_t w, float r[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) r[a] = (float)((int)(w << (22 - 10 * a)) >> 22) * g.r_unit[a];
 }
 
 // Position of a particle inside its block: the G- cell (6 bits) and the half of the
@@ -751,14 +795,17 @@ void launch_compact(const DevCtx &d, int table, hipStream_t s);
 void launch_bucket(const DevCtx &d, int n, int zero_pool, int zero_table, hipStream_t s);
 void launch_block_sort(const DevCtx &d, hipStream_t s);
 void launch_stress(const DevCtx &d, const PartArgs &pa, hipStream_t s);
-// carried: the B planes of pa.in hold Q and there is no carried stress (the state an
-// mpm_step G2P with carry left for the next step)
+// carried: the B planes of pa.in hold Q, the first remainder plane the packed remainder,
+// and there is no carried stress (the state an mpm_step G2P with carry left for the
+// next step)
 void launch_p2g(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, hipStream_t s, bool carried = false);
 void launch_grid_update(const DevCtx &d, float dt, const float gravity[3], int gp, int gt, hipStream_t s);
 void launch_det_gather(const DevCtx &d, int gp, int gt, hipStream_t s);
-// carry: store Q = (m B - dt V0 tau) D^-1 / dx in the B planes and no stress, for a P2G
-// with `carried` that follows in the same step sequence
-void launch_g2p(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, hipStream_t s, bool carry = false);
+// carry: write the carried state (Q = (m B - dt V0 tau) D^-1 / dx in the B planes and no
+// stress, the packed remainder) for a P2G with `carried` that follows in the same step
+// sequence; carried: the input is such a state
+void launch_g2p(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, hipStream_t s, bool carry = false,
+                bool carried = false);
 void launch_grid_export(const DevCtx &d, float *m, float *vec, int gp, int gt, int g0, int ng, hipStream_t s);
 void launch_block_order(const DevCtx &d, hipStream_t s);
 void launch_g2p2g(const DevCtx &d, const PartArgs &pa, float dt, int gp_in, int gt_in, int gp_out, int gt_out,

@@ -231,7 +231,7 @@ __device__ __forceinline__ void b_stress(const DevCtx &d, const PartArgs &pa) {
 #pragma unroll
         for (int a = 0; a < 9; ++a) B[a] = pa.in[(kPlaneB + a) * S + p];
         const int mi = pa.mat_in ? (int)pa.mat_in[p] : 0;
-        const DevMaterial M = d.mats[mi < d.n_mat ? mi : 0];
+        const DevMaterial M = material_of(d, mi);
         float tau[6];
         kirchhoff(M, H, tau);
 #pragma unroll
@@ -282,11 +282,17 @@ constexpr int kChunk = 2 * kP2GThreads;    // particles scattered per pass (two 
 // a pass's node sums (< kChunk * 2^40 units) must stay below 2^51 for to_fixed and the
 // conversion back through FP64 to be exact
 static_assert((double)kChunk * 1099511627776.0 < 2251799813685248.0, "fixed-point tile sums would overflow 2^51");
+// the step-global unit scatters a whole block in one pass: its node sums stay below
+// kMaxBlockParticles * 2^40 units, which must not exceed 2^51 either
+static_assert((double)kMaxBlockParticles * 1099511627776.0 <= 2251799813685248.0,
+              "fixed-point tile sums with the step-global unit would overflow 2^51");
 // Padded tile layout (64-bit words): node (x, y, z) of a grid at x + kTY y + kTZ z.
-// For any node offset, the 4 x 4 x 4 cells of a block then map x + kTY y onto 16
-// distinct residues modulo 16 (and kTZ is a multiple of 16), so the lanes of one
-// atomic spread evenly over the LDS banks.
-constexpr int kTY = 12, kTZ = 80;
+// For any node offset, the 4 x 4 x 4 cells of a block then map x + kTY y + kTZ z
+// onto every residue modulo 32 exactly twice (and modulo 16 exactly four times), so
+// the 64 lanes of one atomic whose particles lie in distinct cells spread evenly over
+// the LDS banks; among the strides with that property these give the smallest tile
+// (189 and 236 words per channel for the 125 and 216 nodes).
+constexpr int kTY = 6, kTZ = 40;
 constexpr int kTileMStride = 4 * kTZ + 5 * kTY;   // words per channel, G- ([0,4]^3)
 constexpr int kTilePStride = 5 * kTZ + 6 * kTY;   // words per channel, G+ ([0,5]^3)
 constexpr double kMagic = 6755399441055744.0;                  // 1.5 * 2^52
@@ -364,7 +370,8 @@ __device__ __forceinline__ void stage_compute_q(const DevMaterial &M, const Cell
     r.on = true;
 }
 
-// kCarried: the B planes of the input hold Q (and there is no carried stress).
+// kCarried: the B planes of the input hold Q (and there is no carried stress), and
+// the first remainder plane the packed remainder.
 template <bool kCarried = false>
 __device__ __forceinline__ void stage_particle(const DevCtx &d, const PartArgs &pa, int p, int bx, int by, int bz,
                                                float dt, Staged &r) {
@@ -373,12 +380,13 @@ __device__ __forceinline__ void stage_particle(const DevCtx &d, const PartArgs &
     const uint32_t up = (uint32_t)p;
     float x[3], xr[3], v[3], B[9], tau[6];
     ld_planes(pa.in, S, kPlaneX, up, x);
-    ld_planes(pa.in, S, kPlaneR, up, xr);
+    if (kCarried) unpack_remainder(d.geo, ld_at(reinterpret_cast<const uint32_t *>(pa.in + kPlaneR * S), up), xr);
+    else ld_planes(pa.in, S, kPlaneR, up, xr);
     ld_planes(pa.in, S, kPlaneV, up, v);
     ld_planes(pa.in, S, kPlaneB, up, B);
     if (!kCarried) ld_planes(d.tau, d.tau_stride, 0, up, tau);
     const int mi = pa.mat_in ? (int)ld_at(pa.mat_in, up) : 0;
-    const DevMaterial M = d.mats[mi < d.n_mat ? mi : 0];
+    const DevMaterial M = material_of(d, mi);
     CellCoord cc;
     if (!cell_coord(d.geo, x, xr, cc)) {
         set_status(d.counters, ST_DOMAIN);
@@ -604,19 +612,22 @@ __device__ __forceinline__ void scatter_pool(const DevCtx &d, float *pool, const
 // (dense blocks) keep the (octant, cell, index) order.
 constexpr int kLayers = 16;
 constexpr int kLayWords = 2 * kLayers * (kP2GThreads / 64) + kP2GThreads / 64;   // LDS ints of the layer tables
-// 64-bit words of the ordering buffer plus the layer table, which share a kernel's
-// LDS area with its fixed-point tile
-constexpr int kOrderWords = (kMaxBlockParticles * 4 + kLayers * kBins * 2) / 8;
+// per (layer, wave range): the ballots of its bins holding more than q particles,
+// even and odd bins (64-bit words)
+constexpr int kLayMaskWords = 2 * kLayers * (kP2GThreads / 64);
+// 64-bit words of the ordering buffer, which shares a kernel's LDS area with its
+// fixed-point tile
+constexpr int kOrderWords = kMaxBlockParticles * 4 / 8;
 
 // Orders the particles of block r (count cnt, first sorted position s) by (half-cell
 // octant, cell, index), or in the layered order when `layered`: ord[j] = particle
 // index at position j of the block, also written to the global permutation.  Uses
 // bcnt, bstart, wsum and lbuf (LDS); the layered order also uses lay (kLayWords ints)
-// and rt (kLayers * kBins 16-bit entries).
+// and lmask (kLayMaskWords 64-bit words).
 template <bool layered = false>
 __device__ __forceinline__ void order_block(const DevCtx &d, int r, int s, int cnt, int *bcnt, int *bstart, int *wsum,
                                             uint32_t *lbuf, uint32_t *ord, int *lay = nullptr,
-                                            uint16_t *rt = nullptr) {
+                                            unsigned long long *lmask = nullptr) {
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
     const uint32_t *bkt = d.bucket + (size_t)r * kMaxBlockParticles;
@@ -666,19 +677,19 @@ __device__ __forceinline__ void order_block(const DevCtx &d, int r, int s, int c
         if (tid == kP2GThreads - 1) bstart[kBins] = ex + c0 + c1;
         if (layered) {
             // largest bin of the block; layer tables when every bin fits kLayers layers:
-            // rt[q][b] = bins before b (in its wave's 128 bins) holding more than q
-            // particles, lay[q * 4 + w] = such bins in wave w's range
+            // the ballots of the wave's even and odd bins holding more than q particles
+            // (lane l holds bins 2l and 2l + 1 of the wave's 128), and lay[q * 4 + w] =
+            // the number of such bins in wave w's range
             mx = max(max(lay[2 * kLayers * 4], lay[2 * kLayers * 4 + 1]),
                      max(lay[2 * kLayers * 4 + 2], lay[2 * kLayers * 4 + 3]));
             if (mx <= kLayers) {
-                const unsigned long long lt = (1ull << lane) - 1ull;
                 for (int q = 0; q < mx; ++q) {
-                    const bool f0 = c0 > q, f1 = c1 > q;
-                    const unsigned long long m0 = __ballot(f0), m1 = __ballot(f1);
-                    const int pq = __popcll(m0 & lt) + __popcll(m1 & lt);
-                    rt[q * kBins + 2 * tid] = (uint16_t)pq;
-                    rt[q * kBins + 2 * tid + 1] = (uint16_t)(pq + (f0 ? 1 : 0));
-                    if (lane == 0) lay[q * 4 + w] = __popcll(m0) + __popcll(m1);
+                    const unsigned long long m0 = __ballot(c0 > q), m1 = __ballot(c1 > q);
+                    if (lane == 0) {
+                        lmask[2 * (q * 4 + w)] = m0;
+                        lmask[2 * (q * 4 + w) + 1] = m1;
+                        lay[q * 4 + w] = __popcll(m0) + __popcll(m1);
+                    }
                 }
             }
         }
@@ -734,8 +745,14 @@ __device__ __forceinline__ void order_block(const DevCtx &d, int r, int s, int c
         int rank = lo;
         for (int q = lo; q < hi; ++q) rank += (lbuf[q] < idx) ? 1 : 0;
         if (lay_on) {
-            const int q = rank - lo;
-            rank = lay[kLayers * 4 + q * 4 + (bin >> 7)] + rt[q * kBins + bin];
+            // within layer q and the bin's wave range: the bins before it holding more
+            // than q particles
+            const int q = rank - lo, wr = bin >> 7, l = (bin & 127) >> 1;
+            const unsigned long long m0 = lmask[2 * (q * 4 + wr)], m1 = lmask[2 * (q * 4 + wr) + 1];
+            const unsigned long long lt = (1ull << l) - 1ull;
+            int pq = __popcll(m0 & lt) + __popcll(m1 & lt);
+            if (bin & 1) pq += (int)((m0 >> l) & 1ull);
+            rank = lay[kLayers * 4 + q * 4 + wr] + pq;
         }
         ord[rank] = idx;
         st_at(d.perm, (uint32_t)(s + rank), idx);
@@ -771,8 +788,8 @@ __device__ __forceinline__ void b_p2g(const DevCtx &d, const PartArgs &pa, float
     constexpr int kAreaWords = kTileWords > kOrderWords ? kTileWords : kOrderWords;
     __shared__ unsigned long long area[kAreaWords];
     __shared__ int lay[kLayWords];
+    __shared__ unsigned long long lmask[kLayMaskWords];
     uint32_t *lbuf = reinterpret_cast<uint32_t *>(area);
-    uint16_t *rt = reinterpret_cast<uint16_t *>(lbuf + kMaxBlockParticles);   // after the ordering buffer
     unsigned long long *tile_m = area;
     unsigned long long *tile_p = area + 4 * kTileMStride;
     const int np = (int)d.counters[C_NPB];
@@ -793,7 +810,7 @@ __device__ __forceinline__ void b_p2g(const DevCtx &d, const PartArgs &pa, float
         const int s = d.pstart[r];
         const int cnt = d.pstart[r + 1] - s;
         if (cnt > kMaxBlockParticles) continue;   // reported by the bucket scan
-        order_block<true>(d, r, s, cnt, bcnt, bstart, wsum, lbuf, ord, lay, rt);
+        order_block<true>(d, r, s, cnt, bcnt, bstart, wsum, lbuf, ord, lay, lmask);
         load_neighbours(d, gt, bx, by, bz, nbr);
         lds_barrier();
 
@@ -1061,18 +1078,24 @@ __global__ void __launch_bounds__(128) k_grid_update_multi(const JobStep *__rest
 struct G2PIn {
     uint32_t p;
     float x[3], xr[3], H[9];
+    uint32_t rp;    // packed remainder of a carried input (unpacked into xr where it is used)
     int mat;
     uint32_t id;
 };
 
-__device__ __forceinline__ void g2p_load_index(const PartArgs &pa, uint32_t p, G2PIn &q) {
+// carried: the input is the carried state of an mpm_step sequence (packed remainder,
+// left in rp so that loading a particle ahead of its use does not wait for the load)
+__device__ __forceinline__ void g2p_load_index(const PartArgs &pa, uint32_t p, G2PIn &q, bool carried = false) {
     q.p = p;
     const long long S = pa.stride;
-    ld_planes(pa.in, S, kPlaneX, p, q.x);
-    ld_planes(pa.in, S, kPlaneR, p, q.xr);
-    ld_planes(pa.in, S, kPlaneH, p, q.H);
+    // the optional arrays first: the unconditional loads issued last let a later use of
+    // an earlier particle wait for fewer of the loads in flight
     q.mat = pa.mat_in ? (int)ld_at(pa.mat_in, p) : 0;
     q.id = pa.id_in ? ld_at(pa.id_in, p) : 0u;
+    ld_planes(pa.in, S, kPlaneX, p, q.x);
+    if (carried) q.rp = ld_at(reinterpret_cast<const uint32_t *>(pa.in + kPlaneR * S), p);
+    else ld_planes(pa.in, S, kPlaneR, p, q.xr);
+    ld_planes(pa.in, S, kPlaneH, p, q.H);
 }
 
 __device__ __forceinline__ void g2p_load(const DevCtx &d, const PartArgs &pa, uint32_t pos, G2PIn &q) {
@@ -1098,7 +1121,7 @@ __device__ __forceinline__ int g2p_particle(const DevCtx &d, const PartArgs &pa,
                                             const CellCoord &cc, int bx, int by, int bz, const float *vt, uint32_t out,
                                             bool write_tau, NewState &ns, CellCoord &cn, bool &placed,
                                             bool write_vB = true, bool carry = false) {
-    const DevMaterial M = d.mats[q.mat < d.n_mat ? q.mat : 0];
+    const DevMaterial M = material_of(d, q.mat);
     Weights w;
     axis_weights(cc, w);
     float Di[9];
@@ -1198,6 +1221,10 @@ __device__ __forceinline__ int g2p_finish_c(const DevCtx &d, const PartArgs &pa,
     float xn[3], xrn[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) advance_position(q.x[a], q.xr[a], dt * vn[a], xn[a], xrn[a]);
+    // the carried state keeps the packed remainder, and the new cell is that of the
+    // packed position, which the next P2G and G2P read
+    const uint32_t rpack = carry ? pack_remainder(d.geo, xrn) : 0u;
+    if (carry) unpack_remainder(d.geo, rpack, xrn);
     // x * 0 is NaN exactly when x is infinite or NaN
     float probe = 0.0f;
 #pragma unroll
@@ -1235,6 +1262,7 @@ __device__ __forceinline__ int g2p_finish_c(const DevCtx &d, const PartArgs &pa,
 #pragma unroll
         for (int i = 0; i < 9; ++i) st[15 + i] = Fn[i];
         st_planes(pa.out, S, kPlaneX, out, st);
+        st_at(reinterpret_cast<uint32_t *>(pa.out + kPlaneR * S), out, rpack);
     } else if (write_vB) {
         float st[24];
 #pragma unroll
@@ -1254,7 +1282,7 @@ __device__ __forceinline__ int g2p_finish_c(const DevCtx &d, const PartArgs &pa,
         st_planes(pa.out, S, kPlaneX, out, xn);
         st_planes(pa.out, S, kPlaneH, out, Fn);
     }
-    st_planes(pa.out, S, kPlaneR, out, xrn);
+    if (!carry) st_planes(pa.out, S, kPlaneR, out, xrn);
     if (write_tau && !carry) st_planes(d.tau, d.tau_stride, 0, out, tau);
     if (pa.id_out) st_at(pa.id_out, out, q.id);
     if (pa.mat_out) st_at(pa.mat_out, out, (uint8_t)q.mat);
@@ -1302,8 +1330,45 @@ __device__ __forceinline__ int g2p_finish(const DevCtx &d, const PartArgs &pa, f
 // column; the quadratic and gradient G2P gain 9 %).
 constexpr int kG2PThreads = 128;
 
-// kCarry: the output's B planes take Q for the next P2G of the same step sequence.
-template <bool kCarry = false>
+// One pass of the G2P particle loop over particles j0 + thread of a block: `cur` holds
+// the particle's inputs (loaded a pass before); `nxt` loads those of the next pass from
+// the index pnext (loaded a pass before), and pnext the index after that.  Lanes past
+// the end load the block's last particle again: loads on every path let the first
+// use of a particle's inputs wait for that particle's loads alone.
+template <bool kCarry, bool kCarried>
+__device__ __forceinline__ void g2p_pass(const DevCtx &d, const PartArgs &pa, float dt, const float *vt, int bx,
+                                         int by, int bz, int s, int cnt, uint32_t last, int j0, int E, G2PIn &cur,
+                                         G2PIn &nxt, uint32_t &pnext) {
+    const int j = j0 + (int)threadIdx.x;
+    const bool act = j < cnt;
+    if (kCarried) unpack_remainder(d.geo, cur.rp, cur.xr);
+    const uint32_t pn = pnext;   // the index first, then the next particle's inputs
+    pnext = ld_at(d.perm, min((uint32_t)(s + j + 2 * kG2PThreads), last));
+    g2p_load_index(pa, pn, nxt, kCarried);
+    const uint32_t out = (uint32_t)(s + j);
+    CellCoord cc;
+    bool ok = act && cell_coord(d.geo, cur.x, cur.xr, cc);
+    ok = ok && (cc.c[0] >> 2) == bx && (cc.c[1] >> 2) == by && (cc.c[2] >> 2) == bz;
+    // activation stamps of the next step (-1: none), deduplicated across the wave
+    int sig = -1;
+    if (act && !ok) {
+        set_status(d.counters, ST_STALE);
+        st_at(d.key, out, 0xffffffffu);
+    } else if (ok) {
+        NewState ns;
+        CellCoord cn;
+        bool placed;
+        sig = g2p_particle(d, pa, dt, cur, cc, bx, by, bz, vt, out, true, ns, cn, placed, true, kCarry);
+    }
+    wave_stamp(d, sig, E + 1);
+}
+
+// kCarry: the output is the carried state for the next P2G of the same step sequence
+// (Q in the B planes, the packed remainder); kCarried: so is the input.  The particle
+// loop runs two passes per trip, each reading the inputs the other loaded: the two
+// sets of registers then take turns, where one set copied into the other at the end
+// of every pass would wait for every store of the pass.
+template <bool kCarry = false, bool kCarried = false>
 __device__ __forceinline__ void b_g2p(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt) {
     __shared__ float vt[3 * kTileNodes];
     __shared__ int nbr[27];
@@ -1318,10 +1383,13 @@ __device__ __forceinline__ void b_g2p(const DevCtx &d, const PartArgs &pa, float
         block_coords(d.geo, vb, bx, by, bz);
         const int s = d.pstart[r];
         const int cnt = d.pstart[r + 1] - s;
-        if (cnt > kMaxBlockParticles) continue;
-        // the first particle's inputs load while the tile is gathered
-        G2PIn nxt;
-        if (tid < cnt) g2p_load(d, pa, (uint32_t)(s + tid), nxt);
+        if (cnt <= 0 || cnt > kMaxBlockParticles) continue;
+        // the first particle's inputs load while the tile is gathered, and the index of
+        // the one after
+        const uint32_t last = (uint32_t)(s + cnt - 1);
+        G2PIn qa, qb;
+        g2p_load_index(pa, ld_at(d.perm, min((uint32_t)(s + tid), last)), qa, kCarried);
+        uint32_t pnext = ld_at(d.perm, min((uint32_t)(s + tid + kG2PThreads), last));
         load_neighbours(d, gt, bx, by, bz, nbr);
         lds_barrier();
         for (int ni = tid; ni < kTileNodes; ni += kG2PThreads) {
@@ -1332,27 +1400,10 @@ __device__ __forceinline__ void b_g2p(const DevCtx &d, const PartArgs &pa, float
             for (int ch = 0; ch < 3; ++ch) vt[ch * kTileNodes + ni] = a >= 0 ? d.pool[gp][a + ch * 64] : 0.0f;
         }
         lds_barrier();
-        for (int j0 = 0; j0 < cnt; j0 += kG2PThreads) {   // the same trip count for every lane
-            const int j = j0 + tid;
-            const bool act = j < cnt;
-            const G2PIn q = nxt;
-            if (j + kG2PThreads < cnt) g2p_load(d, pa, (uint32_t)(s + j + kG2PThreads), nxt);   // next particle
-            const uint32_t out = (uint32_t)(s + j);
-            CellCoord cc;
-            bool ok = act && cell_coord(d.geo, q.x, q.xr, cc);
-            ok = ok && (cc.c[0] >> 2) == bx && (cc.c[1] >> 2) == by && (cc.c[2] >> 2) == bz;
-            // activation stamps of the next step (-1: none), deduplicated across the wave
-            int sig = -1;
-            if (act && !ok) {
-                set_status(d.counters, ST_STALE);
-                st_at(d.key, out, 0xffffffffu);
-            } else if (ok) {
-                NewState ns;
-                CellCoord cn;
-                bool placed;
-                sig = g2p_particle(d, pa, dt, q, cc, bx, by, bz, vt, out, true, ns, cn, placed, true, kCarry);
-            }
-            wave_stamp(d, sig, E + 1);
+        for (int j0 = 0; j0 < cnt; j0 += 2 * kG2PThreads) {   // the same trip count for every lane
+            g2p_pass<kCarry, kCarried>(d, pa, dt, vt, bx, by, bz, s, cnt, last, j0, E, qa, qb, pnext);
+            if (j0 + kG2PThreads < cnt)
+                g2p_pass<kCarry, kCarried>(d, pa, dt, vt, bx, by, bz, s, cnt, last, j0 + kG2PThreads, E, qb, qa, pnext);
         }
         lds_barrier();
     }
@@ -1361,6 +1412,12 @@ __device__ __forceinline__ void b_g2p(const DevCtx &d, const PartArgs &pa, float
 __global__ void __launch_bounds__(kG2PThreads) k_g2p(DevCtx d, PartArgs pa, float dt, int gp, int gt) { b_g2p(d, pa, dt, gp, gt); }
 __global__ void __launch_bounds__(kG2PThreads) k_g2p_carry(DevCtx d, PartArgs pa, float dt, int gp, int gt) {
     b_g2p<true>(d, pa, dt, gp, gt);
+}
+__global__ void __launch_bounds__(kG2PThreads) k_g2p_cc(DevCtx d, PartArgs pa, float dt, int gp, int gt) {
+    b_g2p<true, true>(d, pa, dt, gp, gt);
+}
+__global__ void __launch_bounds__(kG2PThreads) k_g2p_cf(DevCtx d, PartArgs pa, float dt, int gp, int gt) {
+    b_g2p<false, true>(d, pa, dt, gp, gt);
 }
 
 // one launch for many jobs: workgroup row y runs job y
@@ -1402,7 +1459,7 @@ __device__ __forceinline__ void grad_stage(const DevCtx &d, const PartArgs &pa, 
 #pragma unroll
     for (int i = 0; i < 6; ++i) tau[i] = ld_at(d.tau + i * d.tau_stride, up);
     const int mi = pa.mat_in ? (int)ld_at(pa.mat_in, up) : 0;
-    const DevMaterial M = d.mats[mi < d.n_mat ? mi : 0];
+    const DevMaterial M = material_of(d, mi);
     CellCoord cc;
     if (!cell_coord(d.geo, x, xr, cc)) {
         set_status(d.counters, ST_DOMAIN);
@@ -1514,8 +1571,8 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g_grad(DevCtx d, PartArgs pa,
     constexpr int kAreaWords = kTileWords > kOrderWords ? kTileWords : kOrderWords;
     __shared__ unsigned long long area[kAreaWords];
     __shared__ int lay[kLayWords];
+    __shared__ unsigned long long lmask[kLayMaskWords];
     uint32_t *lbuf = reinterpret_cast<uint32_t *>(area);
-    uint16_t *rt = reinterpret_cast<uint16_t *>(lbuf + kMaxBlockParticles);   // after the ordering buffer
     unsigned long long *tile_m = area;
     unsigned long long *tile_p = area + 4 * kTileMStride;
     const bool pic = d.transfer == 2;
@@ -1530,7 +1587,7 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g_grad(DevCtx d, PartArgs pa,
         const int s = d.pstart[r];
         const int cnt = d.pstart[r + 1] - s;
         if (cnt > kMaxBlockParticles) continue;
-        order_block<true>(d, r, s, cnt, bcnt, bstart, wsum, lbuf, ord, lay, rt);
+        order_block<true>(d, r, s, cnt, bcnt, bstart, wsum, lbuf, ord, lay, lmask);
         load_neighbours(d, gt, bx, by, bz, nbr);
         lds_barrier();
         for (int c0 = 0; c0 < cnt; c0 += kChunk) {
@@ -1681,7 +1738,7 @@ __global__ void __launch_bounds__(kG2PThreads) k_g2p_grad(DevCtx d, PartArgs pa,
                     Bh[i] = pic ? 0.0f : 0.5f * Bh[i];
                     Cc[i] *= 0.5f;
                 }
-                const DevMaterial M = d.mats[q.mat < d.n_mat ? q.mat : 0];
+                const DevMaterial M = material_of(d, q.mat);
                 NewState ns;
                 CellCoord cn;
                 bool placed;
@@ -1749,7 +1806,7 @@ __device__ __forceinline__ void quad_stage(const DevCtx &d, const PartArgs &pa, 
     ld_planes(pa.in, S, kPlaneB, up, B);
     ld_planes(d.tau, d.tau_stride, 0, up, tau);
     const int mi = pa.mat_in ? (int)ld_at(pa.mat_in, up) : 0;
-    const DevMaterial M = d.mats[mi < d.n_mat ? mi : 0];
+    const DevMaterial M = material_of(d, mi);
     CellCoord cc;
     if (!cell_coord(d.geo, x, xr, cc)) {
         set_status(d.counters, ST_DOMAIN);
@@ -1819,8 +1876,8 @@ __global__ void __launch_bounds__(kP2GThreads, 4) k_p2g_quad(DevCtx d, PartArgs 
     constexpr int kAreaWords = kTileWords > kOrderWords ? kTileWords : kOrderWords;
     __shared__ unsigned long long area[kAreaWords];
     __shared__ int lay[kLayWords];
+    __shared__ unsigned long long lmask[kLayMaskWords];
     uint32_t *lbuf = reinterpret_cast<uint32_t *>(area);
-    uint16_t *rt = reinterpret_cast<uint16_t *>(lbuf + kMaxBlockParticles);   // after the ordering buffer
     unsigned long long *tile = area;
     const int np = (int)d.counters[C_NPB];
     const int tid = threadIdx.x;
@@ -1833,7 +1890,7 @@ __global__ void __launch_bounds__(kP2GThreads, 4) k_p2g_quad(DevCtx d, PartArgs 
         const int s = d.pstart[r];
         const int cnt = d.pstart[r + 1] - s;
         if (cnt > kMaxBlockParticles) continue;   // reported by the bucket scan
-        order_block<true>(d, r, s, cnt, bcnt, bstart, wsum, lbuf, ord, lay, rt);
+        order_block<true>(d, r, s, cnt, bcnt, bstart, wsum, lbuf, ord, lay, lmask);
         load_neighbours(d, gt, bx, by, bz, nbr);
         lds_barrier();
         for (int c0 = 0; c0 < cnt; c0 += kChunk) {
@@ -1954,7 +2011,7 @@ __global__ void __launch_bounds__(kG2PThreads) k_g2p_quad(DevCtx d, PartArgs pa,
 #pragma unroll
                 for (int a = 0; a < 3; ++a) vn[a] = cref[a] + vs[a];
                 const float Di[9] = {4.0f, 0.0f, 0.0f, 0.0f, 4.0f, 0.0f, 0.0f, 0.0f, 4.0f};
-                const DevMaterial M = d.mats[q.mat < d.n_mat ? q.mat : 0];
+                const DevMaterial M = material_of(d, q.mat);
                 NewState ns;
                 CellCoord cn;
                 bool placed;
@@ -1975,7 +2032,7 @@ __global__ void __launch_bounds__(kP2GThreads) k_block_order(DevCtx d) {
     __shared__ uint32_t lbuf[kMaxBlockParticles];
     __shared__ uint32_t ord[kMaxBlockParticles];
     __shared__ int lay[kLayWords];
-    __shared__ uint16_t rt[kLayers * kBins];
+    __shared__ unsigned long long lmask[kLayMaskWords];
     const int np = (int)d.counters[C_NPB];
     for (int base = 0; base < np; base += gridDim.x) {
         const int r = round_block(base, np);
@@ -1983,7 +2040,7 @@ __global__ void __launch_bounds__(kP2GThreads) k_block_order(DevCtx d) {
         const int s = d.pstart[r];
         const int cnt = d.pstart[r + 1] - s;
         if (cnt > kMaxBlockParticles) continue;
-        order_block<true>(d, r, s, cnt, bcnt, bstart, wsum, lbuf, ord, lay, rt);
+        order_block<true>(d, r, s, cnt, bcnt, bstart, wsum, lbuf, ord, lay, lmask);
         lds_barrier();
     }
 }
@@ -2017,8 +2074,8 @@ __global__ void __launch_bounds__(kP2GThreads, 2) k_g2p2g(DevCtx d, PartArgs pa,
     constexpr int kAreaWords = kTileWords > kOrderWords ? kTileWords : kOrderWords;
     __shared__ unsigned long long area[kAreaWords];
     __shared__ int lay[kLayWords];
+    __shared__ unsigned long long lmask[kLayMaskWords];
     uint32_t *lbuf = reinterpret_cast<uint32_t *>(area);
-    uint16_t *rt = reinterpret_cast<uint16_t *>(lbuf + kMaxBlockParticles);   // after the ordering buffer
     double *tile_m = reinterpret_cast<double *>(area);
     double *tile_p = tile_m + 4 * kFMStride;
     const int np = (int)d.counters[C_NPB];
@@ -2033,7 +2090,7 @@ __global__ void __launch_bounds__(kP2GThreads, 2) k_g2p2g(DevCtx d, PartArgs pa,
         const int s = d.pstart[r];
         const int cnt = d.pstart[r + 1] - s;
         if (cnt > kMaxBlockParticles) continue;   // reported by the bucket scan
-        order_block<true>(d, r, s, cnt, bcnt, bstart, wsum, lbuf, ord, lay, rt);
+        order_block<true>(d, r, s, cnt, bcnt, bstart, wsum, lbuf, ord, lay, lmask);
         load_neighbours(d, gt_in, bx, by, bz, nbr_in);
         load_neighbours(d, gt_out, bx, by, bz, nbr_out, 64);
         lds_barrier();
@@ -2073,7 +2130,7 @@ __global__ void __launch_bounds__(kP2GThreads, 2) k_g2p2g(DevCtx d, PartArgs pa,
                 bool placed;
                 sig = g2p_particle(d, pa, dt, q, cc, bx, by, bz, vt, out, false, ns, cn, placed, false);
                 if (placed) {
-                    const DevMaterial M = d.mats[q.mat < d.n_mat ? q.mat : 0];
+                    const DevMaterial M = material_of(d, q.mat);
                     stage_compute(d, M, cn, ns.v, ns.B, ns.tau, dt, st);
                 }
             }
@@ -2201,13 +2258,18 @@ void launch_grid_update(const DevCtx &d, float dt, const float gravity[3], int g
                        gravity[0], gravity[1], gravity[2], gp, gt);
 }
 
-void launch_g2p(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, hipStream_t s, bool carry) {
+void launch_g2p(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, hipStream_t s, bool carry,
+                bool carried) {
     if (d.quadratic)
         hipLaunchKernelGGL(k_g2p_quad, dim3(particle_grid(d)), dim3(kG2PThreads), 0, s, d, pa, dt, gp, gt);
     else if (d.transfer != 0)
         hipLaunchKernelGGL(k_g2p_grad, dim3(particle_grid(d)), dim3(kG2PThreads), 0, s, d, pa, dt, gp, gt);
+    else if (carry && carried)
+        hipLaunchKernelGGL(k_g2p_cc, dim3(particle_grid(d)), dim3(kG2PThreads), 0, s, d, pa, dt, gp, gt);
     else if (carry)
         hipLaunchKernelGGL(k_g2p_carry, dim3(particle_grid(d)), dim3(kG2PThreads), 0, s, d, pa, dt, gp, gt);
+    else if (carried)
+        hipLaunchKernelGGL(k_g2p_cf, dim3(particle_grid(d)), dim3(kG2PThreads), 0, s, d, pa, dt, gp, gt);
     else
         hipLaunchKernelGGL(k_g2p, dim3(particle_grid(d)), dim3(kG2PThreads), 0, s, d, pa, dt, gp, gt);
 }

@@ -8,7 +8,9 @@ field, bounded by 1e-5:
     the sticky floor) and of a reduced sand column, with the checker running its
     own FP64 trajectory from the same initial state (grids compared every step);
   * the first ten steps of the full 4,194,304-particle sand column (particles
-    every step, grids after steps 1, 5 and 10).
+    every step, grids after steps 1, 5 and 10), with mpm_step's step sequence and
+    the fused G2P2G step checked against the same FP64 trajectory after steps 5
+    and 10.
 """
 import numpy as np
 import pytest
@@ -122,10 +124,15 @@ def test_reseeded_step_parity(name):
 def test_full_sand_column_ten_steps():
     """The 4,194,304-particle sand column at full size: ten phase steps against the
     checker's own FP64 trajectory from the same initial state, particle x, v, F every
-    step and grid mass, momentum and m v~ after steps 1, 5 and 10."""
+    step and grid mass, momentum and m v~ after steps 1, 5 and 10.  Beside them, from
+    the same initial state, two mpm_step calls of five steps (inside a call every G2P
+    but the last hands Q to the next P2G in place of B and the stress) and two fused
+    G2P2G calls of five steps, compared with the same trajectory after steps 5 and 10."""
     sc = scenes.sand_column()
     assert sc.n == 4194304
     run = GpuRun(sc)
+    seq = GpuRun(sc)
+    fused = GpuRun(sc, fused=True)
     st = oracle_state(dict(x=sc.x, v=sc.v, B=sc.B, F=sc.F))
     for k in range(10):
         with_grids = k + 1 in (1, 5, 10)
@@ -136,7 +143,15 @@ def test_full_sand_column_ten_steps():
             _cmp_grids("sand_column full, step %d" % (k + 1), got, g)
             del g
         _cmp_particles("sand_column full, step %d" % (k + 1), got, st, sc.dx)
+        if k + 1 in (5, 10):
+            for tag, r in (("mpm_step", seq), ("fused", fused)):
+                got = r.steps(sc.dt, 5)
+                assert got["status"] == 0, "%s step %d status %d" % (tag, k + 1, got["status"])
+                _cmp_particles("sand_column full, %s, step %d" % (tag, k + 1), got, st, sc.dx)
+        del got
     run.close()
+    seq.close()
+    fused.close()
 
 
 def test_mpm_step_equals_phase_calls():

@@ -1,6 +1,6 @@
 """The single-grid quadratic B-spline comparison kernel (MPM_FLAG_QUADRATIC) on the
 GPU against the oracle's quadratic step: one step per phase from identical input,
-ten-step trajectories against the oracle's own FP64 trajectory, and two steps of
+ten-step trajectories against the oracle's own FP64 trajectory, and ten steps of
 the full 4,194,304-particle sand column."""
 import numpy as np
 import pytest
@@ -70,16 +70,22 @@ def test_quadratic_trajectory_ten_steps(name):
     run.close()
 
 
-def test_quadratic_full_sand_column_two_steps():
+@pytest.mark.timeout(1200)
+def test_quadratic_full_sand_column_ten_steps():
+    """The full 4,194,304-particle sand column with the quadratic kernel: two
+    mpm_step calls of five steps against the checker's FP64 trajectory after steps
+    5 and 10."""
     sc = scenes.sand_column()
     run = GpuRun(sc, quadratic=True)
-    got = run.steps(sc.dt, 2)
-    run.close()
-    assert got["status"] == 0
     st = oracle_state(dict(x=sc.x, v=sc.v, B=sc.B, F=sc.F))
-    for _ in range(2):
-        _ora_step(sc, st, sc.dt, grids=False)
-    _cmp("sand column full, 2 steps", got, st)
+    for k in (5, 10):
+        got = run.steps(sc.dt, 5)
+        assert got["status"] == 0
+        for _ in range(5):
+            _ora_step(sc, st, sc.dt, grids=False)
+        _cmp("sand column full, %d steps" % k, got, st)
+        del got
+    run.close()
 
 
 def test_quadratic_rejects_fused_flag_and_reports_domain():
