@@ -97,6 +97,14 @@ struct DevCtx {
                            // one 128-byte line per slot, reduced into the counters by the bucket scan
 };
 
+// One of the context's two pools, page tables or block lists: a selection between two
+// kernel-argument pointers by a uniform index, which the compiler keeps in scalar
+// registers, where an indexed access to the argument would load the pointer from
+// memory at every use (a vector load that waits for every load and store before it).
+__device__ __forceinline__ float *pool_of(const DevCtx &d, int i) { return i ? d.pool[1] : d.pool[0]; }
+__device__ __forceinline__ int *page_of(const DevCtx &d, int i) { return i ? d.page[1] : d.page[0]; }
+__device__ __forceinline__ int *glist_of(const DevCtx &d, int i) { return i ? d.glist[1] : d.glist[0]; }
+
 // The material of a particle: a per-lane selection among the context's materials,
 // which are read with scalar loads (a uniform address), so that no vector memory
 // load -- which would wait for every load issued before it -- stands in a

@@ -106,6 +106,9 @@ __device__ __forceinline__ void wg_sum2(int &a, int &b, int *sh) {
 }
 
 constexpr int kPerThread = kCompactChunk / kThreads;   // 4 virtual blocks per thread
+// up to this many chunks (a 1,024-block chunk each; 1,024 chunks is a 1,024^3-cell
+// grid) the emitting workgroups form their own chunk offsets
+constexpr int kPrefixChunks = 1024;
 
 // Flags (stamp == E) of the kPerThread consecutive virtual blocks from `base`, both
 // stamp arrays in one 16-byte load each (every epoch's stamps are 256-byte aligned);
@@ -227,7 +230,6 @@ __device__ __forceinline__ void b_compact_scan(const DevCtx &d, int nchunks, int
         if (ng > d.max_blocks || np > d.max_blocks) set_status(d.counters, ST_CAPACITY);
         d.counters[C_NPB] = (unsigned)min(np, d.max_blocks);
         d.counters[ngb_slot(table)] = (unsigned)min(ng, d.max_blocks);
-        d.counters[C_EPOCH] += 1u;
         d.counters[C_MAXPB] = 0u;
         d.counters[C_TOTAL] = 0u;
     }
@@ -265,25 +267,69 @@ __device__ __forceinline__ int wg_excl_scan(int x, int &excl, int *sh) {
     return tot;
 }
 
-__device__ __forceinline__ void b_compact_emit(const DevCtx &d, int table) {
+// prefix: the chunks' exclusive offsets come from the chunk scan (false), or each
+// workgroup sums the counts of the chunks before its own (true; the last one then
+// writes the totals), which saves the scan's launch when there are few chunks.
+template <bool kPrefix = false>
+__device__ __forceinline__ void b_compact_emit(const DevCtx &d, int table, int nchunks = 0) {
     __shared__ int sh[8];
-    const int E = (int)d.counters[C_EPOCH];
+    __shared__ int pre[2 * (kThreads / 64)];
+    const int E = (int)d.counters[C_EPOCH] + 1;
     const int *pf = stamps(d.pflag, d.nbv, E);
     const int *gf = stamps(d.gflag, d.nbv, E);
     const long long base = (long long)blockIdx.x * kCompactChunk + threadIdx.x * kPerThread;
     int fp[kPerThread], fg[kPerThread];
     load_flags(d, pf, gf, base, E, fp, fg);
+    int cbp = 0, cbg = 0;   // counts of the chunks before this one
+    if (kPrefix) {
+        for (int c = threadIdx.x; c < (int)blockIdx.x; c += kThreads) {
+            cbp += d.chunk_p[c];
+            cbg += d.chunk_g[c];
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            cbp += __shfl_xor(cbp, off);
+            cbg += __shfl_xor(cbg, off);
+        }
+    }
     int cp = 0, cg = 0;
 #pragma unroll
     for (int k = 0; k < kPerThread; ++k) {
         cp += fp[k];
         cg += fg[k];
     }
+    if (kPrefix) {
+        const int w = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) {
+            pre[w] = cbp;
+            pre[kThreads / 64 + w] = cbg;
+        }
+    }
     int ep, eg;
     wg_excl_scan(cp, ep, sh);
-    const int gtot = wg_excl_scan(cg, eg, sh);
-    const int offp = d.chunk_p[blockIdx.x] + ep;
-    const int offg = d.chunk_g[blockIdx.x] + eg;
+    const int gtot = wg_excl_scan(cg, eg, sh);   // (the scans' barriers publish pre)
+    int offp, offg;
+    if (kPrefix) {
+        int bp = 0, bg = 0;
+#pragma unroll
+        for (int k = 0; k < kThreads / 64; ++k) {
+            bp += pre[k];
+            bg += pre[kThreads / 64 + k];
+        }
+        offp = bp + ep;
+        offg = bg + eg;
+        if ((int)blockIdx.x == nchunks - 1 && threadIdx.x == kThreads - 1) {
+            const int np = bp + ep + cp, ng = bg + eg + cg;
+            if (ng > d.max_blocks || np > d.max_blocks) set_status(d.counters, ST_CAPACITY);
+            d.counters[C_NPB] = (unsigned)min(np, d.max_blocks);
+            d.counters[ngb_slot(table)] = (unsigned)min(ng, d.max_blocks);
+            d.counters[C_MAXPB] = 0u;
+            d.counters[C_TOTAL] = 0u;
+        }
+    } else {
+        offp = d.chunk_p[blockIdx.x] + ep;
+        offg = d.chunk_g[blockIdx.x] + eg;
+    }
     int rp = offp, rg = offg;
     int ph[kPerThread];
 #pragma unroll
@@ -302,7 +348,7 @@ __device__ __forceinline__ void b_compact_emit(const DevCtx &d, int table) {
         ph[k] = -1;
         if (fg[k]) {
             if (rg < d.max_blocks) {
-                d.glist[table][rg] = v;
+                glist_of(d, table)[rg] = v;
                 ph[k] = rg;
             }
             ++rg;
@@ -310,16 +356,20 @@ __device__ __forceinline__ void b_compact_emit(const DevCtx &d, int table) {
     }
     // every virtual block gets its page entry, so the table is valid without stamps
     if (base + kPerThread <= d.nbv) {
-        *reinterpret_cast<int4 *>(d.page[table] + base) = make_int4(ph[0], ph[1], ph[2], ph[3]);
+        *reinterpret_cast<int4 *>(page_of(d, table) + base) = make_int4(ph[0], ph[1], ph[2], ph[3]);
     } else {
 #pragma unroll
         for (int k = 0; k < kPerThread; ++k)
-            if (base + k < d.nbv) d.page[table][base + k] = ph[k];
+            if (base + k < d.nbv) page_of(d, table)[base + k] = ph[k];
     }
     (void)gtot;
 }
 
-__global__ void __launch_bounds__(kThreads) k_compact_emit(DevCtx d, int table) { b_compact_emit(d, table); }
+__global__ void __launch_bounds__(kThreads) k_compact_emit(DevCtx d, int table, int nchunks) {
+    b_compact_emit<true>(d, table, nchunks);
+}
+
+__global__ void __launch_bounds__(kThreads) k_compact_emit_scanned(DevCtx d, int table) { b_compact_emit(d, table); }
 
 // one launch for many jobs: workgroup row y runs job y
 __global__ void __launch_bounds__(kThreads) k_compact_emit_multi(const JobStep *__restrict__ jobs) {
@@ -342,13 +392,13 @@ __device__ __forceinline__ void b_bucket_count(const DevCtx &d, int n, int zero_
     __shared__ int base_of[kCountTile];
     __shared__ int wmax[kThreads / 64];
     const int tid = threadIdx.x, lane = wave_lane(), w = tid >> 6;
-    const int E = (int)d.counters[C_EPOCH];
+    const int E = (int)d.counters[C_EPOCH] + 1;   // the epoch of this sort (the bucket scan ends it)
     const int *pf = stamps(d.pflag, d.nbv, E);
     const int base = blockIdx.x * kCountTile;
     // zero a share of the pool blocks handed out this step
     {
         const long long nfl = (long long)d.counters[ngb_slot(zero_table)] * (kBlockFloats / 4);
-        float4 *pool4 = reinterpret_cast<float4 *>(d.pool[zero_pool]);
+        float4 *pool4 = reinterpret_cast<float4 *>(pool_of(d, zero_pool));
         for (long long t = (long long)blockIdx.x * kThreads + tid; t < nfl; t += (long long)gridDim.x * kThreads)
             pool4[t] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
@@ -515,6 +565,9 @@ __device__ __forceinline__ void b_bucket_scan(const DevCtx &d) {
         d.pstart[np] = carry;
         d.counters[C_MAXPB] = (unsigned)m;
         d.counters[C_TOTAL] = (unsigned)carry;
+        // the sort's epoch becomes the current one (every kernel of the sort read the
+        // previous value)
+        d.counters[C_EPOCH] += 1u;
         if (m > kMaxBlockParticles) set_status(d.counters, ST_CAPACITY);
     }
     // the contribution bound for the P2G about to run: maxima of the slots the previous
@@ -560,8 +613,13 @@ void launch_clear_flags(const DevCtx &d, hipStream_t s) {
 void launch_compact(const DevCtx &d, int table, hipStream_t s) {
     const int nchunks = (int)((d.nbv + kCompactChunk - 1) / kCompactChunk);
     hipLaunchKernelGGL(k_compact_count, dim3(nchunks), dim3(kThreads), 0, s, d);
-    hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, s, d, nchunks, table);
-    hipLaunchKernelGGL(k_compact_emit, dim3(nchunks), dim3(kThreads), 0, s, d, table);
+    if (nchunks <= kPrefixChunks) {
+        // each emitting workgroup sums the chunk counts before its own
+        hipLaunchKernelGGL(k_compact_emit, dim3(nchunks), dim3(kThreads), 0, s, d, table, nchunks);
+    } else {
+        hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, s, d, nchunks, table);
+        hipLaunchKernelGGL(k_compact_emit_scanned, dim3(nchunks), dim3(kThreads), 0, s, d, table);
+    }
 }
 
 void launch_sort_multi(const JobStep *dev, const JobStep *host, int njobs, hipStream_t s) {

@@ -33,7 +33,7 @@ __device__ __forceinline__ void load_neighbours(const DevCtx &d, int table, int 
         const int x = bx + t % 3 - 1, y = by + (t / 3) % 3 - 1, z = bz + t / 9 - 1;
         int ph = -1;
         if (x >= 0 && y >= 0 && z >= 0 && x < d.geo.NB[0] && y < d.geo.NB[1] && z < d.geo.NB[2])
-            ph = d.page[table][vblock_id(d.geo, x, y, z)];
+            ph = page_of(d, table)[vblock_id(d.geo, x, y, z)];
         nbr[t] = ph;
     }
 }
@@ -834,7 +834,7 @@ __device__ __forceinline__ void b_p2g(const DevCtx &d, const PartArgs &pa, float
                     scatter_particle_unit<kTY, kTZ, kTileMStride, kTilePStride>(
                         st, st.c[0] - 4 * bx, st.c[1] - 4 * by, st.c[2] - 4 * bz, tile_m, tile_p, S);
                 else
-                    scatter_pool(d, d.pool[gp], nbr, bx, by, bz, st);
+                    scatter_pool(d, pool_of(d, gp), nbr, bx, by, bz, st);
             }
             lds_barrier();
             for (int ni = tid; ni < kTileNodes; ni += kP2GThreads) {
@@ -855,7 +855,7 @@ __device__ __forceinline__ void b_p2g(const DevCtx &d, const PartArgs &pa, float
                 }
 #pragma unroll
                 for (int ch = 0; ch < 4; ++ch)
-                    if (val[ch] != 0.0f) atomicAdd(&d.pool[gp][a + ch * 64], val[ch]);
+                    if (val[ch] != 0.0f) atomicAdd(&pool_of(d, gp)[a + ch * 64], val[ch]);
             }
             lds_barrier();
             continue;
@@ -913,7 +913,7 @@ __device__ __forceinline__ void b_p2g(const DevCtx &d, const PartArgs &pa, float
                 }
 #pragma unroll
                 for (int ch = 0; ch < 4; ++ch)
-                    if (val[ch] != 0.0f) atomicAdd(&d.pool[gp][a + ch * 64], val[ch]);
+                    if (val[ch] != 0.0f) atomicAdd(&pool_of(d, gp)[a + ch * 64], val[ch]);
             }
             lds_barrier();
         }
@@ -973,7 +973,7 @@ __device__ __forceinline__ void b_det_gather(const DevCtx &d, int gp, int gt) {
     }
     for (int b = blockIdx.x; b < ng; b += gridDim.x) {
         int bc[3];
-        block_coords(d.geo, d.glist[gt][b], bc[0], bc[1], bc[2]);
+        block_coords(d.geo, glist_of(d, gt)[b], bc[0], bc[1], bc[2]);
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         for (int oz = lo[2]; oz <= hi[2]; ++oz)
             for (int oy = lo[1]; oy <= hi[1]; ++oy)
@@ -995,7 +995,7 @@ __device__ __forceinline__ void b_det_gather(const DevCtx &d, int gp, int gt) {
 #pragma unroll
                     for (int ch = 0; ch < 4; ++ch) acc[ch] += (double)sg[ch * kTileNodes];
                 }
-        float *blk = d.pool[gp] + (size_t)b * kBlockFloats + g * 256;
+        float *blk = pool_of(d, gp) + (size_t)b * kBlockFloats + g * 256;
 #pragma unroll
         for (int ch = 0; ch < 4; ++ch) blk[ch * 64 + l] = (float)acc[ch];
     }
@@ -1030,8 +1030,8 @@ __device__ __forceinline__ void b_grid_update(const DevCtx &d, float dt, float g
         for (int k = 0; k < kGridPer; ++k) {
             const int b = b0 + k * gridDim.x;
             if (b < ng) {
-                const float *blk = d.pool[gp] + (size_t)b * kBlockFloats + g * 256;
-                vb[k] = d.glist[gt][b];
+                const float *blk = pool_of(d, gp) + (size_t)b * kBlockFloats + g * 256;
+                vb[k] = glist_of(d, gt)[b];
                 m[k] = blk[l];
                 p0[k] = blk[64 + l];
                 p1[k] = blk[128 + l];
@@ -1054,7 +1054,7 @@ __device__ __forceinline__ void b_grid_update(const DevCtx &d, float dt, float g
                 v1 = p1[k] * im + dt * g1;
                 v2 = p2[k] * im + dt * g2;
             }
-            float *blk = d.pool[gp] + (size_t)b * kBlockFloats + g * 256;
+            float *blk = pool_of(d, gp) + (size_t)b * kBlockFloats + g * 256;
             blk[64 + l] = v0;
             blk[128 + l] = v1;
             blk[192 + l] = v2;
@@ -1397,7 +1397,7 @@ __device__ __forceinline__ void b_g2p(const DevCtx &d, const PartArgs &pa, float
             tile_node(ni, bx, by, bz, g, ix, iy, iz);
             const long long a = pool_index(d, nbr, bx, by, bz, g, ix, iy, iz, 1);
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) vt[ch * kTileNodes + ni] = a >= 0 ? d.pool[gp][a + ch * 64] : 0.0f;
+            for (int ch = 0; ch < 3; ++ch) vt[ch * kTileNodes + ni] = a >= 0 ? pool_of(d, gp)[a + ch * 64] : 0.0f;
         }
         lds_barrier();
         for (int j0 = 0; j0 < cnt; j0 += 2 * kG2PThreads) {   // the same trip count for every lane
@@ -1628,7 +1628,7 @@ __global__ void __launch_bounds__(kP2GThreads) k_p2g_grad(DevCtx d, PartArgs pa,
                 }
 #pragma unroll
                 for (int ch = 0; ch < 4; ++ch)
-                    if (val[ch] != 0.0f) atomicAdd(&d.pool[gp][a + ch * 64], val[ch]);
+                    if (val[ch] != 0.0f) atomicAdd(&pool_of(d, gp)[a + ch * 64], val[ch]);
             }
             lds_barrier();
         }
@@ -1663,7 +1663,7 @@ __global__ void __launch_bounds__(kG2PThreads) k_g2p_grad(DevCtx d, PartArgs pa,
             tile_node(ni, bx, by, bz, g, ix, iy, iz);
             const long long a = pool_index(d, nbr, bx, by, bz, g, ix, iy, iz, 1);
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) vt[ch * kTileNodes + ni] = a >= 0 ? d.pool[gp][a + ch * 64] : 0.0f;
+            for (int ch = 0; ch < 3; ++ch) vt[ch * kTileNodes + ni] = a >= 0 ? pool_of(d, gp)[a + ch * 64] : 0.0f;
         }
         lds_barrier();
         for (int j0 = 0; j0 < cnt; j0 += kG2PThreads) {
@@ -1927,7 +1927,7 @@ __global__ void __launch_bounds__(kP2GThreads, 4) k_p2g_quad(DevCtx d, PartArgs 
                 }
 #pragma unroll
                 for (int ch = 0; ch < 4; ++ch)
-                    if (val[ch] != 0.0f) atomicAdd(&d.pool[gp][a + ch * 64], val[ch]);
+                    if (val[ch] != 0.0f) atomicAdd(&pool_of(d, gp)[a + ch * 64], val[ch]);
             }
             lds_barrier();
         }
@@ -1957,7 +1957,7 @@ __global__ void __launch_bounds__(kG2PThreads) k_g2p_quad(DevCtx d, PartArgs pa,
             const int ix = 4 * bx - 1 + ni % 7, iy = 4 * by - 1 + (ni / 7) % 7, iz = 4 * bz - 1 + ni / 49;
             const long long a = pool_index(d, nbr, bx, by, bz, 0, ix, iy, iz, 1);
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) vt[ch * kQNodes + ni] = a >= 0 ? d.pool[gp][a + ch * 64] : 0.0f;
+            for (int ch = 0; ch < 3; ++ch) vt[ch * kQNodes + ni] = a >= 0 ? pool_of(d, gp)[a + ch * 64] : 0.0f;
         }
         lds_barrier();
         for (int j0 = 0; j0 < cnt; j0 += kG2PThreads) {
@@ -2103,7 +2103,7 @@ __global__ void __launch_bounds__(kP2GThreads, 2) k_g2p2g(DevCtx d, PartArgs pa,
             tile_node(ni, bx, by, bz, g, ix, iy, iz);
             const long long a = pool_index(d, nbr_in, bx, by, bz, g, ix, iy, iz, 1);
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) vt[ch * kTileNodes + ni] = a >= 0 ? d.pool[gp_in][a + ch * 64] : 0.0f;
+            for (int ch = 0; ch < 3; ++ch) vt[ch * kTileNodes + ni] = a >= 0 ? pool_of(d, gp_in)[a + ch * 64] : 0.0f;
         }
         for (int q = tid; q < kTileWords; q += kP2GThreads) area[q] = 0ull;
         lds_barrier();
@@ -2140,7 +2140,7 @@ __global__ void __launch_bounds__(kP2GThreads, 2) k_g2p2g(DevCtx d, PartArgs pa,
                 if (lx >= 0 && ly >= 0 && lz >= 0 && lx <= 5 && ly <= 5 && lz <= 5)
                     scatter_particle_f64<kFTY, kFTZ, kFMStride, kFPStride>(st, lx, ly, lz, tile_m, tile_p);
                 else
-                    scatter_pool(d, d.pool[gp_out], nbr_out, bx, by, bz, st);
+                    scatter_pool(d, pool_of(d, gp_out), nbr_out, bx, by, bz, st);
             }
         }
         lds_barrier();
@@ -2173,7 +2173,7 @@ __global__ void __launch_bounds__(kP2GThreads, 2) k_g2p2g(DevCtx d, PartArgs pa,
             }
 #pragma unroll
             for (int ch = 0; ch < 4; ++ch)
-                if (val[ch] != 0.0f) atomicAdd(&d.pool[gp_out][a + ch * 64], val[ch]);
+                if (val[ch] != 0.0f) atomicAdd(&pool_of(d, gp_out)[a + ch * 64], val[ch]);
         }
         lds_barrier();
     }
@@ -2181,7 +2181,7 @@ __global__ void __launch_bounds__(kP2GThreads, 2) k_g2p2g(DevCtx d, PartArgs pa,
 
 __global__ void k_zero_pool(DevCtx d, int gp, int gt) {
     const long long nfl = (long long)d.counters[ngb_slot(gt)] * (kBlockFloats / 4);
-    float4 *pool4 = reinterpret_cast<float4 *>(d.pool[gp]);
+    float4 *pool4 = reinterpret_cast<float4 *>(pool_of(d, gp));
     for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < nfl; t += (long long)gridDim.x * blockDim.x)
         pool4[t] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
@@ -2196,9 +2196,9 @@ __global__ void k_grid_export(DevCtx d, float *m, float *vec, int gp, int gt, in
         const int ix = (int)(r % nx), iy = (int)((r / nx) % ny), iz = (int)(r / (nx * ny));
         const int v = vblock_id(d.geo, ix >> 2, iy >> 2, iz >> 2);
         float mm = 0.0f, a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
-        const int ph = d.page[gt][v];
+        const int ph = page_of(d, gt)[v];
         if (ph >= 0) {
-            const float *blk = d.pool[gp] + (size_t)ph * kBlockFloats + g * 256;
+            const float *blk = pool_of(d, gp) + (size_t)ph * kBlockFloats + g * 256;
             const int l = (iz & 3) * 16 + (iy & 3) * 4 + (ix & 3);
             mm = blk[l];
             a0 = blk[64 + l];
