@@ -180,7 +180,7 @@ int64_t device_bytes_of(const mpm_config &c) {
     auto r = [](long long bytes) { return (bytes + 256 + 255) / 256 * 256; };
     // the buffers of ctx_create, in its order
     return r(4 * np) + r(2 * np) + r(4 * np) + r(4 * nb * (long long)kMaxBlockParticles) +
-           r(2 * nb * (long long)kMaxBlockParticles) + 2 * r(8 * stamp_stride(nbv)) + 2 * r(4 * nbv) + r(4 * nbv) +
+           r(2 * nb * (long long)kMaxBlockParticles) + 2 * r(8 * stamp_stride(nbv)) + 2 * r(4 * nbv) + 2 * r(4 * nbv) +
            r(4 * nb) + r(4 * (nb + 1)) + r(4 * nb) + 2 * r(4 * nb) + r(4 * nchunks) + r(4 * nchunks) +
            2 * r(4 * nb * (long long)kBlockFloats) + r(24 * np) + r(4 * (long long)C_COUNT) + r(4 * (long long)kBoundWords) +
            (c.deterministic ? r(4 * nb * (long long)kStageFloats) : 0);
@@ -250,7 +250,7 @@ mpm_status enqueue_p2g(mpm_ctx *ctx, const mpm_particles *p, double dt, hipStrea
     if (!physics) {
         launch_block_sort(ctx->d, s);
     } else {
-        launch_p2g(ctx->d, pa, (float)dt, t, t, s, carried_in);
+        launch_p2g(ctx->d, pa, (float)dt, t, t, s, carried_in, ready);
         if (ctx->d.det) launch_det_gather(ctx->d, t, t, s);
         ctx->grid_pool = t;
         ctx->grid_table = t;
@@ -326,7 +326,8 @@ mpm_status carve_buffers(DevCtx &d, const mpm_config &cfg, Take take) {
                     take_buffer(take, &d.pflag, 2 * (size_t)stamp_stride(d.nbv)) &&
                     take_buffer(take, &d.gflag, 2 * (size_t)stamp_stride(d.nbv)) &&
                     take_buffer(take, &d.page[0], nv) && take_buffer(take, &d.page[1], nv) &&
-                    take_buffer(take, &d.prank, nv) && take_buffer(take, &d.plist, nb) &&
+                    take_buffer(take, &d.prank, nv) && take_buffer(take, &d.bchg, nv) &&
+                    take_buffer(take, &d.plist, nb) &&
                     take_buffer(take, &d.pstart, nb + 1) && take_buffer(take, &d.bcount, nb) &&
                     take_buffer(take, &d.glist[0], nb) && take_buffer(take, &d.glist[1], nb) &&
                     take_buffer(take, &d.chunk_p, nchunks) && take_buffer(take, &d.chunk_g, nchunks) &&
@@ -376,6 +377,7 @@ mpm_status ctx_create(const mpm_config *cfg, const mpm_material *mats, int32_t n
                   hipMemsetAsync(d.page[0], 0xff, nv * sizeof(int), init_stream) == hipSuccess &&
                   hipMemsetAsync(d.page[1], 0xff, nv * sizeof(int), init_stream) == hipSuccess &&
                   hipMemsetAsync(d.prank, 0xff, nv * sizeof(int), init_stream) == hipSuccess &&
+                  hipMemsetAsync(d.bchg, 0xff, nv * sizeof(int), init_stream) == hipSuccess &&
                   hipMemsetAsync(d.pstart, 0, (nb + 1) * sizeof(int), init_stream) == hipSuccess &&
                   hipMemsetAsync(d.counters, 0, C_COUNT * sizeof(unsigned int), init_stream) == hipSuccess &&
                   hipMemsetAsync(d.bslots, 0, kBoundWords * sizeof(unsigned int), init_stream) == hipSuccess;
@@ -773,6 +775,7 @@ mpm_status mpm_step_noalloc(const mpm_config *cfg, const mpm_material *mats, int
     fill_words(d.page[0], 0xffffffffu, nv, s);
     fill_words(d.page[1], 0xffffffffu, nv, s);
     fill_words(d.prank, 0xffffffffu, nv, s);
+    fill_words(d.bchg, 0xffffffffu, nv, s);
     fill_words(d.pstart, 0u, nb + 1, s);
     fill_words(d.counters, 0u, C_COUNT, s);
     fill_words(d.bslots, 0u, kBoundWords, s);

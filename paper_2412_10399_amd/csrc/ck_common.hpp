@@ -81,6 +81,8 @@ struct DevCtx {
                            // stamping the next step never disturbs readers of the current one
     int *page[2];          // two page tables: per virtual block the physical pool block, or -1
     int *prank;            // per virtual block: rank among the particle blocks
+    int *bchg;             // per virtual block: epoch of the last step whose G2P changed the set or the
+                           // (octant, cell) bins of its particles (-1: never)
     int *plist;            // particle blocks in increasing virtual id
     int *pstart;           // first sorted position of each particle block (+1 sentinel)
     int *bcount;           // particles per particle block
@@ -806,7 +808,10 @@ void launch_stress(const DevCtx &d, const PartArgs &pa, hipStream_t s);
 // carried: the B planes of pa.in hold Q, the first remainder plane the packed remainder,
 // and there is no carried stress (the state an mpm_step G2P with carry left for the
 // next step)
-void launch_p2g(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, hipStream_t s, bool carried = false);
+// reuse: the input is the state the context's previous G2P wrote, whose blocks' orders
+// the P2G may keep where that G2P changed nothing (see DevCtx::bchg)
+void launch_p2g(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, hipStream_t s, bool carried = false,
+                bool reuse = false);
 void launch_grid_update(const DevCtx &d, float dt, const float gravity[3], int gp, int gt, hipStream_t s);
 void launch_det_gather(const DevCtx &d, int gp, int gt, hipStream_t s);
 // carry: write the carried state (Q = (m B - dt V0 tau) D^-1 / dx in the B planes and no

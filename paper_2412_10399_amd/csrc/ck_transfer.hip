@@ -759,6 +759,47 @@ __device__ __forceinline__ void order_block(const DevCtx &d, int r, int s, int c
     }
 }
 
+// The block's order kept from the previous step: when the previous G2P changed neither
+// the set nor the (octant, cell) bins of the block's particles, they sit at consecutive
+// positions in the layered order of the same bins, which this step's order would
+// reproduce exactly (ranks within a bin follow the positions).  The bucket holds those
+// positions in arrival order; when they form exactly one range [lo, lo + cnt) (cnt
+// distinct positions whose extremes are cnt - 1 apart) the block order is that range
+// (ord and the global permutation are written), and otherwise nothing is written and
+// false returned, for the caller to order the block from scratch.  mm: 8 words of LDS.
+__device__ __forceinline__ bool keep_block_order(const DevCtx &d, int r, int s, int cnt, uint32_t *ord,
+                                                 unsigned int *mm) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint32_t *bkt = d.bucket + (size_t)r * kMaxBlockParticles;
+    uint32_t lo = 0xffffffffu, hi = 0u;
+    for (int j = tid; j < cnt; j += kP2GThreads) {
+        const uint32_t v = bkt[j];
+        lo = min(lo, v);
+        hi = max(hi, v);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        lo = min(lo, (uint32_t)__shfl_xor((int)lo, off));
+        hi = max(hi, (uint32_t)__shfl_xor((int)hi, off));
+    }
+    if (lane == 0) {
+        mm[w] = lo;
+        mm[kP2GThreads / 64 + w] = hi;
+    }
+    lds_barrier();
+#pragma unroll
+    for (int k = 0; k < kP2GThreads / 64; ++k) {
+        lo = min(lo, mm[k]);
+        hi = max(hi, mm[kP2GThreads / 64 + k]);
+    }
+    if (cnt <= 0 || hi - lo + 1u != (uint32_t)cnt) return false;
+    for (int j = tid; j < cnt; j += kP2GThreads) {
+        ord[j] = lo + (uint32_t)j;
+        st_at(d.perm, (uint32_t)(s + j), lo + (uint32_t)j);
+    }
+    return true;
+}
+
 // Reduces a per-thread contribution bound over the workgroup (bmax in LDS, reset by
 // the caller before the preceding barrier) and returns the fixed-point scale.
 __device__ __forceinline__ double block_scale(float bnd, unsigned int *bmax) {
@@ -775,9 +816,12 @@ __device__ __forceinline__ double block_scale(float bnd, unsigned int *bmax) {
 // stages two particles per thread, takes the block's unit from their bounds, then
 // scatters them.  Otherwise an FP64 tile: every thread stages and scatters one
 // particle at a time (no unit to agree on first), and the block takes a single pass.
+// reuse: the input is the state the context's previous G2P wrote, so that the order
+// of a block that G2P left unchanged can be kept (keep_block_order).
 template <bool kFixed, bool kCarried = false>
-__device__ __forceinline__ void b_p2g(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt) {
+__device__ __forceinline__ void b_p2g(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, bool reuse) {
     __shared__ int bcnt[kBins];                 // counts, then placement cursors
+    __shared__ unsigned int kmm[2 * (kP2GThreads / 64)];
     __shared__ int bstart[kBins + 1];
     __shared__ int wsum[kP2GThreads / 64];
     __shared__ unsigned int bmax;
@@ -793,6 +837,7 @@ __device__ __forceinline__ void b_p2g(const DevCtx &d, const PartArgs &pa, float
     unsigned long long *tile_m = area;
     unsigned long long *tile_p = area + 4 * kTileMStride;
     const int np = (int)d.counters[C_NPB];
+    const int E = (int)d.counters[C_EPOCH];
     const int tid = threadIdx.x;
     // step-global fixed-point unit (plain mode): 2^(e-39) for the contribution bound in
     // [2^e, 2^(e+1)), so that every contribution is below 2^40 units and a node's sum
@@ -810,7 +855,8 @@ __device__ __forceinline__ void b_p2g(const DevCtx &d, const PartArgs &pa, float
         const int s = d.pstart[r];
         const int cnt = d.pstart[r + 1] - s;
         if (cnt > kMaxBlockParticles) continue;   // reported by the bucket scan
-        order_block<true>(d, r, s, cnt, bcnt, bstart, wsum, lbuf, ord, lay, lmask);
+        if (!(reuse && d.bchg[vb] != E && keep_block_order(d, r, s, cnt, ord, kmm)))
+            order_block<true>(d, r, s, cnt, bcnt, bstart, wsum, lbuf, ord, lay, lmask);
         load_neighbours(d, gt, bx, by, bz, nbr);
         lds_barrier();
 
@@ -926,15 +972,16 @@ __device__ __forceinline__ void b_p2g(const DevCtx &d, const PartArgs &pa, float
 
 // Four waves per SIMD (128 VGPRs, none spilled; 40 KiB of LDS, four workgroups per
 // CU): 0.263 ms on the sand column against 0.303 ms at three.
-__global__ void __launch_bounds__(kP2GThreads, 4) k_p2g(DevCtx d, PartArgs pa, float dt, int gp, int gt) {
-    b_p2g<false>(d, pa, dt, gp, gt);
+__global__ void __launch_bounds__(kP2GThreads, 4) k_p2g(DevCtx d, PartArgs pa, float dt, int gp, int gt, int reuse) {
+    b_p2g<false>(d, pa, dt, gp, gt, reuse != 0);
 }
 // the same on a state whose B planes carry Q (the intermediate states of mpm_step)
-__global__ void __launch_bounds__(kP2GThreads, 4) k_p2g_carried(DevCtx d, PartArgs pa, float dt, int gp, int gt) {
-    b_p2g<false, true>(d, pa, dt, gp, gt);
+__global__ void __launch_bounds__(kP2GThreads, 4) k_p2g_carried(DevCtx d, PartArgs pa, float dt, int gp, int gt,
+                                                                 int reuse) {
+    b_p2g<false, true>(d, pa, dt, gp, gt, reuse != 0);
 }
-__global__ void __launch_bounds__(kP2GThreads, 3) k_p2g_det(DevCtx d, PartArgs pa, float dt, int gp, int gt) {
-    b_p2g<true>(d, pa, dt, gp, gt);
+__global__ void __launch_bounds__(kP2GThreads, 3) k_p2g_det(DevCtx d, PartArgs pa, float dt, int gp, int gt, int reuse) {
+    b_p2g<true>(d, pa, dt, gp, gt, reuse != 0);
 }
 
 // one launch for many jobs: workgroup row y runs job y (rows of deterministic-mode
@@ -942,12 +989,12 @@ __global__ void __launch_bounds__(kP2GThreads, 3) k_p2g_det(DevCtx d, PartArgs p
 __global__ void __launch_bounds__(kP2GThreads, 4) k_p2g_multi(const JobStep *__restrict__ jobs) {
     const JobStep &J = jobs[blockIdx.y];
     if (J.d.det) return;
-    b_p2g<false>(J.d, J.pa, J.dt, J.table, J.table);
+    b_p2g<false>(J.d, J.pa, J.dt, J.table, J.table, false);
 }
 __global__ void __launch_bounds__(kP2GThreads, 3) k_p2g_det_multi(const JobStep *__restrict__ jobs) {
     const JobStep &J = jobs[blockIdx.y];
     if (!J.d.det) return;
-    b_p2g<true>(J.d, J.pa, J.dt, J.table, J.table);
+    b_p2g<true>(J.d, J.pa, J.dt, J.table, J.table, false);
 }
 
 // ---------------------------------------------------------------- deterministic P2G sums
@@ -1351,14 +1398,27 @@ __device__ __forceinline__ void g2p_pass(const DevCtx &d, const PartArgs &pa, fl
     ok = ok && (cc.c[0] >> 2) == bx && (cc.c[1] >> 2) == by && (cc.c[2] >> 2) == bz;
     // activation stamps of the next step (-1: none), deduplicated across the wave
     int sig = -1;
+    // blocks whose particle set or bins change: this one when a particle leaves it or
+    // its (octant, cell) bin, and the one it enters
+    bool changed = false;
     if (act && !ok) {
         set_status(d.counters, ST_STALE);
         st_at(d.key, out, 0xffffffffu);
+        changed = true;
     } else if (ok) {
         NewState ns;
         CellCoord cn;
         bool placed;
         sig = g2p_particle(d, pa, dt, cur, cc, bx, by, bz, vt, out, true, ns, cn, placed, true, kCarry);
+        if (!placed) {
+            changed = true;
+        } else if (sig != vblock_id(d.geo, bx, by, bz) || sub_code(cn) != sub_code(cc)) {
+            changed = true;
+            d.bchg[sig] = E + 1;
+        }
+    }
+    if (__any(changed)) {
+        if (changed) d.bchg[vblock_id(d.geo, bx, by, bz)] = E + 1;
     }
     wave_stamp(d, sig, E + 1);
 }
@@ -2236,17 +2296,19 @@ void launch_stress(const DevCtx &d, const PartArgs &pa, hipStream_t s) {
     if (pa.n > 0) hipLaunchKernelGGL(k_stress, dim3((pa.n + kThreads - 1) / kThreads), dim3(kThreads), 0, s, d, pa);
 }
 
-void launch_p2g(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, hipStream_t s, bool carried) {
+void launch_p2g(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, hipStream_t s, bool carried,
+                bool reuse) {
+    const int ru = reuse ? 1 : 0;
     if (d.quadratic)
         hipLaunchKernelGGL(k_p2g_quad, dim3(particle_grid(d)), dim3(kP2GThreads), 0, s, d, pa, dt, gp, gt);
     else if (d.transfer != 0)
         hipLaunchKernelGGL(k_p2g_grad, dim3(particle_grid(d)), dim3(kP2GThreads), 0, s, d, pa, dt, gp, gt);
     else if (d.det)
-        hipLaunchKernelGGL(k_p2g_det, dim3(particle_grid(d)), dim3(kP2GThreads), 0, s, d, pa, dt, gp, gt);
+        hipLaunchKernelGGL(k_p2g_det, dim3(particle_grid(d)), dim3(kP2GThreads), 0, s, d, pa, dt, gp, gt, ru);
     else if (carried)
-        hipLaunchKernelGGL(k_p2g_carried, dim3(particle_grid(d)), dim3(kP2GThreads), 0, s, d, pa, dt, gp, gt);
+        hipLaunchKernelGGL(k_p2g_carried, dim3(particle_grid(d)), dim3(kP2GThreads), 0, s, d, pa, dt, gp, gt, ru);
     else
-        hipLaunchKernelGGL(k_p2g, dim3(particle_grid(d)), dim3(kP2GThreads), 0, s, d, pa, dt, gp, gt);
+        hipLaunchKernelGGL(k_p2g, dim3(particle_grid(d)), dim3(kP2GThreads), 0, s, d, pa, dt, gp, gt, ru);
 }
 
 void launch_det_gather(const DevCtx &d, int gp, int gt, hipStream_t s) {
