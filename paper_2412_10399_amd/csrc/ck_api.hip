@@ -181,7 +181,7 @@ int64_t device_bytes_of(const mpm_config &c) {
     // the buffers of ctx_create, in its order
     return r(4 * np) + r(2 * np) + r(4 * np) + r(4 * nb * (long long)kMaxBlockParticles) +
            r(2 * nb * (long long)kMaxBlockParticles) + 2 * r(8 * stamp_stride(nbv)) + 2 * r(4 * nbv) + 2 * r(4 * nbv) +
-           r(4 * nb) + r(4 * (nb + 1)) + r(4 * nb) + 2 * r(4 * nb) + r(4 * nchunks) + r(4 * nchunks) +
+           3 * r(4 * nb) + r(4 * (nb + 1)) + r(4 * nb) + 2 * r(4 * nb) + r(4 * nchunks) + r(4 * nchunks) +
            2 * r(4 * nb * (long long)kBlockFloats) + r(24 * np) + r(4 * (long long)C_COUNT) + r(4 * (long long)kBoundWords) +
            (c.deterministic ? r(4 * nb * (long long)kStageFloats) : 0);
 }
@@ -235,6 +235,11 @@ mpm_status enqueue_p2g(mpm_ctx *ctx, const mpm_particles *p, double dt, hipStrea
     // when the previous mpm_g2p wrote this very buffer
     const bool ready = ctx->next_ready == pa.in && ctx->next_n == pa.n;
     const bool carried_in = ready && ctx->carried == pa.in;
+    // the compact-kernel MLS G2P records the blocks it changes, so the next P2G may keep
+    // the order of the others (the quadratic and exact-gradient kernels do not; the fused
+    // step orders the first sort's blocks again from their buckets)
+    const bool keep_orders = physics && ready && !ctx->d.quadratic && ctx->d.transfer == MPM_TRANSFER_MLS &&
+                             !(ctx->cfg.flags & MPM_FLAG_FUSED_G2P2G);
     if (ev) (void)hipEventRecord(ev[0], s);
     if (!ready) launch_flag_keys(ctx->d, pa, 1, s);
     // deterministic mode recomputes the stress from F every step, so that a run
@@ -244,13 +249,13 @@ mpm_status enqueue_p2g(mpm_ctx *ctx, const mpm_particles *p, double dt, hipStrea
     if (physics && (!ready || ctx->d.det)) launch_stress(ctx->d, pa, s);
     const int t = ctx->next_table;
     launch_compact(ctx->d, t, s);
-    launch_bucket(ctx->d, pa.n, t, t, s);
+    launch_bucket(ctx->d, pa.n, t, t, s, keep_orders);
     ctx->next_table = t ^ 1;
     if (ev) (void)hipEventRecord(ev[1], s);
     if (!physics) {
         launch_block_sort(ctx->d, s);
     } else {
-        launch_p2g(ctx->d, pa, (float)dt, t, t, s, carried_in, ready);
+        launch_p2g(ctx->d, pa, (float)dt, t, t, s, carried_in, keep_orders);
         if (ctx->d.det) launch_det_gather(ctx->d, t, t, s);
         ctx->grid_pool = t;
         ctx->grid_table = t;
@@ -327,7 +332,7 @@ mpm_status carve_buffers(DevCtx &d, const mpm_config &cfg, Take take) {
                     take_buffer(take, &d.gflag, 2 * (size_t)stamp_stride(d.nbv)) &&
                     take_buffer(take, &d.page[0], nv) && take_buffer(take, &d.page[1], nv) &&
                     take_buffer(take, &d.prank, nv) && take_buffer(take, &d.bchg, nv) &&
-                    take_buffer(take, &d.plist, nb) &&
+                    take_buffer(take, &d.plist, nb) && take_buffer(take, &d.blo, nb) && take_buffer(take, &d.bhi, nb) &&
                     take_buffer(take, &d.pstart, nb + 1) && take_buffer(take, &d.bcount, nb) &&
                     take_buffer(take, &d.glist[0], nb) && take_buffer(take, &d.glist[1], nb) &&
                     take_buffer(take, &d.chunk_p, nchunks) && take_buffer(take, &d.chunk_g, nchunks) &&

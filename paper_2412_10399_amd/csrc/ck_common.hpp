@@ -83,6 +83,8 @@ struct DevCtx {
     int *prank;            // per virtual block: rank among the particle blocks
     int *bchg;             // per virtual block: epoch of the last step whose G2P changed the set or the
                            // (octant, cell) bins of its particles (-1: never)
+    uint32_t *blo, *bhi;   // per particle block whose order is kept: smallest and largest position of
+                           // its particles (the bucket is not filled for such a block)
     int *plist;            // particle blocks in increasing virtual id
     int *pstart;           // first sorted position of each particle block (+1 sentinel)
     int *bcount;           // particles per particle block
@@ -802,7 +804,9 @@ struct Allocator {
 void launch_flag_keys(const DevCtx &d, const PartArgs &pa, int epoch_offset, hipStream_t s);
 void launch_clear_flags(const DevCtx &d, hipStream_t s);
 void launch_compact(const DevCtx &d, int table, hipStream_t s);
-void launch_bucket(const DevCtx &d, int n, int zero_pool, int zero_table, hipStream_t s);
+// reuse: as for launch_p2g (blocks whose order the P2G keeps get their position range
+// instead of a filled bucket)
+void launch_bucket(const DevCtx &d, int n, int zero_pool, int zero_table, hipStream_t s, bool reuse = false);
 void launch_block_sort(const DevCtx &d, hipStream_t s);
 void launch_stress(const DevCtx &d, const PartArgs &pa, hipStream_t s);
 // carried: the B planes of pa.in hold Q, the first remainder plane the packed remainder,

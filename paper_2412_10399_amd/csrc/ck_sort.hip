@@ -340,6 +340,8 @@ __device__ __forceinline__ void b_compact_emit(const DevCtx &d, int table, int n
                 d.plist[rp] = v;
                 d.prank[v] = rp;
                 d.bcount[rp] = 0;
+                d.blo[rp] = 0xffffffffu;
+                d.bhi[rp] = 0u;
             } else {
                 d.prank[v] = -1;
             }
@@ -387,9 +389,14 @@ __global__ void __launch_bounds__(kThreads) k_compact_emit_multi(const JobStep *
 constexpr int kCountPer = 4;                       // consecutive particles per thread
 constexpr int kCountTile = kThreads * kCountPer;   // particles per workgroup
 
-__device__ __forceinline__ void b_bucket_count(const DevCtx &d, int n, int zero_pool, int zero_table) {
+// reuse: the state is the one the context's previous G2P wrote; a block that G2P
+// left unchanged keeps its order in the P2G (its particles sit at consecutive
+// positions), so its bucket is not filled: the run's first and last positions go to
+// the block's position range instead.
+__device__ __forceinline__ void b_bucket_count(const DevCtx &d, int n, int zero_pool, int zero_table, bool reuse) {
     __shared__ int rblk[kCountTile];   // particle block rank of each particle of the tile (-1: skipped)
     __shared__ int base_of[kCountTile];
+    __shared__ unsigned char kept_of[kCountTile];   // per run start: the block's order is kept
     __shared__ int wmax[kThreads / 64];
     const int tid = threadIdx.x, lane = wave_lane(), w = tid >> 6;
     const int E = (int)d.counters[C_EPOCH] + 1;   // the epoch of this sort (the bucket scan ends it)
@@ -478,13 +485,21 @@ __device__ __forceinline__ void b_bucket_count(const DevCtx &d, int n, int zero_
         const int j = tid * kCountPer + k;
         if (r[k] < 0) continue;
         const bool last = (j == kCountTile - 1) || (rblk[j + 1] != r[k]);
-        if (last) base_of[st[k]] = atomicAdd(&d.bcount[r[k]], j - st[k] + 1);
+        if (last) {
+            base_of[st[k]] = atomicAdd(&d.bcount[r[k]], j - st[k] + 1);
+            const bool keep = reuse && d.bchg[kv[k] >> 6] != E;
+            kept_of[st[k]] = keep ? 1 : 0;
+            if (keep) {
+                atomicMin(&d.blo[r[k]], (uint32_t)(base + st[k]));
+                atomicMax(&d.bhi[r[k]], (uint32_t)(base + j));
+            }
+        }
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kCountPer; ++k) {
         const int j = tid * kCountPer + k;
-        if (r[k] < 0) continue;
+        if (r[k] < 0 || kept_of[st[k]]) continue;
         const int slot = base_of[st[k]] + (j - st[k]);
         if (slot < kMaxBlockParticles) {
             d.bucket[(size_t)r[k] * kMaxBlockParticles + slot] = (uint32_t)(base + j);
@@ -493,12 +508,14 @@ __device__ __forceinline__ void b_bucket_count(const DevCtx &d, int n, int zero_
     }
 }
 
-__global__ void __launch_bounds__(kThreads) k_bucket_count(DevCtx d, int n, int zero_pool, int zero_table) { b_bucket_count(d, n, zero_pool, zero_table); }
+__global__ void __launch_bounds__(kThreads) k_bucket_count(DevCtx d, int n, int zero_pool, int zero_table, int reuse) {
+    b_bucket_count(d, n, zero_pool, zero_table, reuse != 0);
+}
 
 // one launch for many jobs: workgroup row y runs job y
 __global__ void __launch_bounds__(kThreads) k_bucket_count_multi(const JobStep *__restrict__ jobs) {
     const JobStep &J = jobs[blockIdx.y];
-    b_bucket_count(J.d, J.pa.n, J.table, J.table);
+    b_bucket_count(J.d, J.pa.n, J.table, J.table, false);
 }
 
 // Exclusive scan of the bucket sizes into the first sorted position of every
@@ -638,11 +655,11 @@ void launch_sort_multi(const JobStep *dev, const JobStep *host, int njobs, hipSt
     hipLaunchKernelGGL(k_bucket_scan_multi, dim3(1, njobs), dim3(1024), 0, s, dev);
 }
 
-void launch_bucket(const DevCtx &d, int n, int zero_pool, int zero_table, hipStream_t s) {
+void launch_bucket(const DevCtx &d, int n, int zero_pool, int zero_table, hipStream_t s, bool reuse) {
     // at least a few hundred workgroups, so that the pool clearing is spread wide
     const int tiles = (n + kCountTile - 1) / kCountTile;
     hipLaunchKernelGGL(k_bucket_count, dim3(tiles > 1024 ? tiles : 1024), dim3(kThreads), 0, s, d, n, zero_pool,
-                       zero_table);
+                       zero_table, reuse ? 1 : 0);
     hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, d);
 }
 

@@ -762,38 +762,18 @@ __device__ __forceinline__ void order_block(const DevCtx &d, int r, int s, int c
 // The block's order kept from the previous step: when the previous G2P changed neither
 // the set nor the (octant, cell) bins of the block's particles, they sit at consecutive
 // positions in the layered order of the same bins, which this step's order would
-// reproduce exactly (ranks within a bin follow the positions).  The bucket holds those
-// positions in arrival order; when they form exactly one range [lo, lo + cnt) (cnt
-// distinct positions whose extremes are cnt - 1 apart) the block order is that range
-// (ord and the global permutation are written), and otherwise nothing is written and
-// false returned, for the caller to order the block from scratch.  mm: 8 words of LDS.
-__device__ __forceinline__ bool keep_block_order(const DevCtx &d, int r, int s, int cnt, uint32_t *ord,
-                                                 unsigned int *mm) {
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const uint32_t *bkt = d.bucket + (size_t)r * kMaxBlockParticles;
-    uint32_t lo = 0xffffffffu, hi = 0u;
-    for (int j = tid; j < cnt; j += kP2GThreads) {
-        const uint32_t v = bkt[j];
-        lo = min(lo, v);
-        hi = max(hi, v);
+// reproduce exactly (ranks within a bin follow the positions).  The sort then records
+// the block's smallest and largest position instead of filling its bucket; when they
+// span exactly cnt positions the block order is that range (ord and the global
+// permutation are written).  Otherwise -- which a correct change record excludes --
+// the status reports a stale state and false is returned: the block's bucket is empty.
+__device__ __forceinline__ bool kept_block_order(const DevCtx &d, int r, int s, int cnt, uint32_t *ord) {
+    const uint32_t lo = d.blo[r], hi = d.bhi[r];
+    if (cnt <= 0 || hi < lo || hi - lo + 1u != (uint32_t)cnt) {
+        set_status(d.counters, ST_STALE);
+        return false;
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        lo = min(lo, (uint32_t)__shfl_xor((int)lo, off));
-        hi = max(hi, (uint32_t)__shfl_xor((int)hi, off));
-    }
-    if (lane == 0) {
-        mm[w] = lo;
-        mm[kP2GThreads / 64 + w] = hi;
-    }
-    lds_barrier();
-#pragma unroll
-    for (int k = 0; k < kP2GThreads / 64; ++k) {
-        lo = min(lo, mm[k]);
-        hi = max(hi, mm[kP2GThreads / 64 + k]);
-    }
-    if (cnt <= 0 || hi - lo + 1u != (uint32_t)cnt) return false;
-    for (int j = tid; j < cnt; j += kP2GThreads) {
+    for (int j = threadIdx.x; j < cnt; j += kP2GThreads) {
         ord[j] = lo + (uint32_t)j;
         st_at(d.perm, (uint32_t)(s + j), lo + (uint32_t)j);
     }
@@ -817,11 +797,10 @@ __device__ __forceinline__ double block_scale(float bnd, unsigned int *bmax) {
 // scatters them.  Otherwise an FP64 tile: every thread stages and scatters one
 // particle at a time (no unit to agree on first), and the block takes a single pass.
 // reuse: the input is the state the context's previous G2P wrote, so that the order
-// of a block that G2P left unchanged can be kept (keep_block_order).
+// of a block that G2P left unchanged is kept (kept_block_order).
 template <bool kFixed, bool kCarried = false>
 __device__ __forceinline__ void b_p2g(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt, bool reuse) {
     __shared__ int bcnt[kBins];                 // counts, then placement cursors
-    __shared__ unsigned int kmm[2 * (kP2GThreads / 64)];
     __shared__ int bstart[kBins + 1];
     __shared__ int wsum[kP2GThreads / 64];
     __shared__ unsigned int bmax;
@@ -855,8 +834,11 @@ __device__ __forceinline__ void b_p2g(const DevCtx &d, const PartArgs &pa, float
         const int s = d.pstart[r];
         const int cnt = d.pstart[r + 1] - s;
         if (cnt > kMaxBlockParticles) continue;   // reported by the bucket scan
-        if (!(reuse && d.bchg[vb] != E && keep_block_order(d, r, s, cnt, ord, kmm)))
+        if (reuse && d.bchg[vb] != E) {
+            if (!kept_block_order(d, r, s, cnt, ord)) continue;
+        } else {
             order_block<true>(d, r, s, cnt, bcnt, bstart, wsum, lbuf, ord, lay, lmask);
+        }
         load_neighbours(d, gt, bx, by, bz, nbr);
         lds_barrier();
 

@@ -77,3 +77,62 @@ def test_dense_block_keeps_octant_order():
     base = (np.array([12.0, 12.0, 12.0]) - 0.25 + 0.05) * sc.dx
     sc.x[pick] = (base + rng.random((24, 3)) * 0.4 * sc.dx).astype(np.float32)
     _check(sc, want_dense=True)
+
+
+@pytest.mark.parametrize("dense", [False, True])
+def test_kept_block_order_equals_order_from_scratch(dense):
+    """A P2G whose input the context's own G2P wrote keeps the order of every block
+    that G2P left unchanged (no particle entered, left or changed its (octant, cell)
+    bin).  Particles moving about a cell per 100 steps leave some blocks unchanged
+    each step and change others: the storage order after every step must be the one a
+    run that orders every block from scratch (the state marked as changed on the
+    host before each step) produces."""
+    sc = scenes.random_blob(23, n_cells=(32, 32, 32), lo_cells=(7.3, 8.6, 9.1), ext_cells=(11, 9, 10), F_scale=0.02,
+                            v_scale=0.3, dt=1e-3)
+    if dense:
+        rng = np.random.default_rng(6)
+        pick = rng.choice(sc.n, 24, replace=False)
+        base = (np.array([12.0, 12.0, 12.0]) - 0.25 + 0.05) * sc.dx
+        sc.x[pick] = (base + rng.random((24, 3)) * 0.4 * sc.dx).astype(np.float32)
+    kept = GpuRun(sc)
+    fresh = GpuRun(sc)
+    n_kept = n_changed = 0
+    prev = None
+    for k in range(12):
+        a = kept.steps(sc.dt, 1)
+        fresh.ck.check(fresh.ck.mpm_invalidate(fresh.ctx.h), "mpm_invalidate")
+        b = fresh.steps(sc.dt, 1)
+        assert a["status"] == 0 and b["status"] == 0
+        ra = kept.parts.read()
+        ia = ra["id"].astype(np.int64)
+        ib = fresh.parts.read()["id"].astype(np.int64)
+        assert np.array_equal(ia, ib), "step %d: %d positions differ" % (k + 1, int((ia != ib).sum()))
+        # blocks the step left unchanged (the ones whose order a following P2G keeps)
+        vb, binn = _block_bins(sc, ra["x"][np.argsort(ia)])
+        if prev is not None:
+            pvb, pbin = prev
+            moved = (vb != pvb) | (binn != pbin)
+            changed = set(np.unique(pvb[moved])) | set(np.unique(vb[moved]))
+            blocks = set(np.unique(vb))
+            n_changed += len(blocks & changed)
+            n_kept += len(blocks - changed)
+        prev = (vb, binn)
+    log("kept block order%s: 11 steps, %d blocks left unchanged by their step, %d changed" % (
+        " (dense block)" if dense else "", n_kept, n_changed))
+    assert n_kept > 0 and n_changed > 0   # both the kept and the recomputed orders ran
+    kept.close()
+    fresh.close()
+
+
+def _block_bins(sc, x):
+    """Virtual block and (octant, cell) bin of each particle (FP64, as expected_order)."""
+    X = (np.asarray(x, np.float64) - np.asarray(sc.origin, np.float64)) * (1.0 / float(sc.dx))
+    Xm = X + 0.25
+    c = np.floor(Xm).astype(np.int64)
+    up = (Xm - c) >= 0.5
+    nb = [n // 4 + 1 for n in sc.n_cells]
+    b = c >> 2
+    vb = (b[:, 2] * nb[1] + b[:, 1]) * nb[0] + b[:, 0]
+    cl = c & 3
+    octant = up[:, 0].astype(np.int64) | (up[:, 1].astype(np.int64) << 1) | (up[:, 2].astype(np.int64) << 2)
+    return vb, octant * 64 + cl[:, 2] * 16 + cl[:, 1] * 4 + cl[:, 0]
