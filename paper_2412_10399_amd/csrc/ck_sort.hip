@@ -515,7 +515,8 @@ __global__ void __launch_bounds__(kThreads) k_bucket_count(DevCtx d, int n, int 
 // one launch for many jobs: workgroup row y runs job y
 __global__ void __launch_bounds__(kThreads) k_bucket_count_multi(const JobStep *__restrict__ jobs) {
     const JobStep &J = jobs[blockIdx.y];
-    b_bucket_count(J.d, J.pa.n, J.table, J.table, false);
+    // a job's steps after its first read the state its own G2P wrote
+    b_bucket_count(J.d, J.pa.n, J.table, J.table, !J.first);
 }
 
 // Exclusive scan of the bucket sizes into the first sorted position of every

@@ -971,12 +971,12 @@ __global__ void __launch_bounds__(kP2GThreads, 3) k_p2g_det(DevCtx d, PartArgs p
 __global__ void __launch_bounds__(kP2GThreads, 4) k_p2g_multi(const JobStep *__restrict__ jobs) {
     const JobStep &J = jobs[blockIdx.y];
     if (J.d.det) return;
-    b_p2g<false>(J.d, J.pa, J.dt, J.table, J.table, false);
+    b_p2g<false>(J.d, J.pa, J.dt, J.table, J.table, !J.first);
 }
 __global__ void __launch_bounds__(kP2GThreads, 3) k_p2g_det_multi(const JobStep *__restrict__ jobs) {
     const JobStep &J = jobs[blockIdx.y];
     if (!J.d.det) return;
-    b_p2g<true>(J.d, J.pa, J.dt, J.table, J.table, false);
+    b_p2g<true>(J.d, J.pa, J.dt, J.table, J.table, !J.first);
 }
 
 // ---------------------------------------------------------------- deterministic P2G sums
