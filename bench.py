@@ -247,10 +247,25 @@ def adjoint_main(args):
     import scenes
     from paper_2412_10399_amd import ckmpm, diff
 
+    import dataclasses
+
+    import numpy as np
+
     torch.cuda.set_device(0)
     sc = scenes.diff_box()
-    target = torch.tensor(scenes.diff_target(), dtype=torch.float32, device="cuda")
-    ad = diff.AdContext(ckmpm.scene_config(sc), ckmpm.scene_materials(sc)[0])
+    target = scenes.diff_target()
+    cells = args.adjoint_cells
+    if cells != sc.n_cells[0]:
+        # the same body and target moved to the centre of a larger grid (same dx)
+        shift = (cells - sc.n_cells[0]) // 2 * sc.dx
+        sc = dataclasses.replace(sc, n_cells=(cells,) * 3, x=(sc.x + np.float32(shift)).astype(np.float32))
+        target = target + shift
+    target = torch.tensor(target, dtype=torch.float32, device="cuda")
+    nb = int(np.prod([c // 4 + 1 for c in sc.n_cells]))
+    cfg = {"auto": diff.ad_config(sc), "dense": ckmpm.scene_config(sc, max_blocks=nb),
+           "sparse": ckmpm.scene_config(sc, max_blocks=min(nb - 1, ckmpm.scene_config(sc).max_blocks))}[args.adjoint_pool]
+    pool = "dense" if cfg.max_blocks >= nb else "sparse, %d blocks per grid" % cfg.max_blocks
+    ad = diff.AdContext(cfg, ckmpm.scene_materials(sc)[0])
     s0 = torch.from_numpy(ckmpm.state_planes(sc.x, sc.v, sc.B, sc.F)).cuda()
     logE0 = torch.from_numpy(sc.logE).cuda()
     n = sc.n
@@ -276,7 +291,8 @@ def adjoint_main(args):
     out = {"metric": "differentiated particle-steps/s", "value": n * sc.steps / wall, "unit": "particle-steps/s",
            "higher_is_better": True, "n_gpus": 1, "dtype": "f32", "data": "synthetic",
            "ms_per_rollout": 1e3 * wall, "rollouts": reps,
-           "config": {"workload": "diff_box_65536", "particles": n, "grid": "64^3", "steps": sc.steps,
+           "config": {"workload": "diff_box_65536", "particles": n, "grid": "%d^3" % cells, "grids": pool,
+                      "steps": sc.steps,
                       "checkpoint_every": 8, "loss": "centre-of-mass distance squared",
                       "gradients": ["v0", "logE"]}}
     ad.close()
@@ -357,6 +373,10 @@ def main():
                     help="run one plain device copy of this size first (calibrates HBM counters under rocprofv3)")
     ap.add_argument("--serving", action="store_true", help="served-job benchmark instead of the step throughput")
     ap.add_argument("--adjoint", action="store_true", help="differentiated-rollout benchmark")
+    ap.add_argument("--adjoint-cells", type=int, default=64,
+                    help="with --adjoint: cells per axis of the grid the body is centred in")
+    ap.add_argument("--adjoint-pool", choices=("auto", "dense", "sparse"), default="auto",
+                    help="with --adjoint: dense grids, the block-sparse pool, or dense when affordable")
     ap.add_argument("--stress", action="store_true", help="30M-particle stress-scale benchmark")
     ap.add_argument("--diffusion", action="store_true", help="energy decay of the compact and quadratic kernels")
     ap.add_argument("--jobs", type=int, default=256)

@@ -14,9 +14,15 @@
  * moment matrix D_p(x_p); the compact kernel is C2, so all of them are
  * differentiable across cell faces.
  *
- * Particles keep their order (no sort).  Grids are dense FP32 arrays of both
- * staggered grids, allocated once by mpm_ad_create (about 112 B per node of the
- * (n+1)^3 lattice); the calls allocate nothing.
+ * Particles keep their order (no sort).  mpm_ad_create allocates the grids once;
+ * the calls allocate nothing.  When max_blocks covers every block of 4x4x4 nodes
+ * of the (n+1)^3 node lattice, both staggered grids are dense (about 112 B per
+ * node).  Otherwise they are block-sparse: a pool of max_blocks blocks per grid
+ * (about 7 KiB per block, plus 10 B per block of the whole lattice for the page
+ * tables); each call marks the blocks that its particles' stencils reach on each
+ * grid, gives them pool slots and sweeps those slots only.  A call whose particles
+ * reach more than max_blocks blocks on a grid reports MPM_E_CAPACITY (its results
+ * are then meaningless); later calls are unaffected.
  *
  * State and cotangent layout: 27 planes of `stride` floats, the layout of
  * mpm_particles (x[3] v[3] B[9] H[9] r[3], H = F - I, row-major 3x3, position
@@ -38,9 +44,10 @@ extern "C" {
 typedef struct mpm_ad_ctx mpm_ad_ctx; /* opaque, owned by the library */
 
 /* Context for the differentiable step.  cfg: grid, cell size, origin, gravity and
- * walls as in mpm_create (max_particles bounds n; max_blocks and flags must be as
- * mpm_create accepts; the transfer is MLS).  mat: one material, which must be
- * MPM_FIXED_COROTATED; its E is only a default (every call takes logE).
+ * walls as in mpm_create (max_particles bounds n; max_blocks, the pool capacity of
+ * each grid, and flags must be as mpm_create accepts; the transfer is MLS).
+ * mat: one material, which must be MPM_FIXED_COROTATED; its E is only a default
+ * (every call takes logE).
  * Errors: MPM_E_INVALID for a bad configuration or material, MPM_E_OOM. */
 mpm_status mpm_ad_create(const mpm_config *cfg, const mpm_material *mat, mpm_ad_ctx **out);
 mpm_status mpm_ad_destroy(mpm_ad_ctx *ctx);
@@ -49,7 +56,7 @@ mpm_status mpm_ad_destroy(mpm_ad_ctx *ctx);
  * state_out must not overlap.  Device-detected errors (a particle outside
  * (x - origin)/dx in [1/4, n - 1/4) on some axis, a non-finite result) set the
  * context's status word, read by mpm_ad_sync; such a particle adds nothing to
- * the grid. */
+ * the grid.  A pool overflow sets it too (MPM_E_CAPACITY). */
 mpm_status mpm_ad_forward(mpm_ad_ctx *ctx, int64_t n, int64_t stride, const float *state_in, const float *logE,
                           float *state_out, double dt, void *stream);
 
@@ -62,7 +69,7 @@ mpm_status mpm_ad_backward(mpm_ad_ctx *ctx, int64_t n, int64_t stride, const flo
                            const float *cot_out, float *cot_in, float *logE_cot, double dt, void *stream);
 
 /* Wait for `stream`, then return (and clear) the status word: NONFINITE before
- * DOMAIN. */
+ * DOMAIN before CAPACITY. */
 mpm_status mpm_ad_sync(mpm_ad_ctx *ctx, void *stream);
 
 #ifdef __cplusplus

@@ -1,5 +1,5 @@
-// Differentiable compact-kernel MPM step: forward step on dense grids and its
-// exact reverse mode (vector-Jacobian product), one thread per particle or node.
+// Differentiable compact-kernel MPM step: forward step on block-sparse grids and
+// its exact reverse mode (vector-Jacobian product), one thread per particle or node.
 //
 // Forward, for particle p at X = (x - origin)/dx (cell units), on grid G_k
 // (k = -1 for G-, +1 for G+, node i at i + k/4 cells), per axis a:
@@ -21,6 +21,7 @@
 #include "ck_common.hpp"
 #include "ck_ctx.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <new>
 
@@ -34,23 +35,45 @@ struct mpm_ad_ctx {
     float gravity[3];
     float nu, rho, vol0;
     int64_t max_particles = 0;
-    long long nodes = 0;      // nodes of one grid, (n+1)^3 lattice
+    int cap = 0;              // pool slots per grid (blocks of 4x4x4 nodes)
+    int nb[3] = {0, 0, 0};    // blocks per axis covering the (n+1)^3 node lattice
+    long long nbv = 0;        // nb[0] nb[1] nb[2]
+    long long nodes = 0;      // nodes of one grid: (n+1)^3 when direct, else (cap + 1) * 64
+                              // (pool slots, the last a spill slot)
     float *grid = nullptr;    // 14 planes of 2 * nodes floats, see below
+    int *page = nullptr;      // [grid][nbv]: pool slot of a block in this call, -1 if untouched
+    int *blist = nullptr;     // [grid][cap]: block of a slot
+    bool direct = false;      // max_blocks covers the lattice: dense grids, no marking
+    unsigned char *flag = nullptr;   // [grid][nbv]: touched by a particle's stencil
+    unsigned int *cnt = nullptr;     // [2]: slots taken per grid
     unsigned int *status = nullptr;
 };
 
 namespace {
 
-// planes of the dense grid buffer (each 2 * nodes floats: G- then G+)
+// Grids.  When max_blocks covers every 4x4x4-node block of the lattice (`direct`),
+// the grids are dense, node (ix, iy, iz) at (iz ny + iy) nx + ix, and the sweeps run
+// over all nodes.  Otherwise they are block-sparse: each call marks the blocks that
+// its particles' stencils touch (k_ad_mark) and gives them pool slots (k_ad_alloc);
+// the node lives at page[g][block] * 64 + ((iz & 3) * 4 + (iy & 3)) * 4 + (ix & 3),
+// and the sweeps run over the taken slots only.  Past the pool's capacity a block
+// gets the spill slot `cap` (never swept, its values meaningless) and the call
+// reports ST_CAPACITY.
+// Planes of the pool buffer (each 2 * nodes floats: G- then G+):
 enum GridPlane { GM = 0, GP = 1, GV = 4, GVB = 7, GMB = 10, GPB = 11, kGridPlanes = 14 };
 
 struct AdArgs {
     Geometry geo;
     float g[3];
     float mass, vol0, nu_mu, nu_lambda;   // mu = nu_mu E, lambda = nu_lambda E
-    int nx, ny, nz;
-    long long nodes;
+    int nx, ny;   // lattice nodes per axis (direct)
+    int nbx, nby, cap;
+    long long nbv, nodes;
     float *grid;
+    int *page, *blist;
+    int direct;
+    unsigned char *flag;
+    unsigned int *cnt;
     unsigned int *status;
     int n;
     long long stride;
@@ -58,6 +81,28 @@ struct AdArgs {
 };
 
 __device__ __forceinline__ float *plane(const AdArgs &a, int k) { return a.grid + (long long)k * 2 * a.nodes; }
+
+// Sets status bits in the context's one status word (read by mpm_ad_sync).
+__device__ __forceinline__ void ad_status(const AdArgs &a, unsigned int bits) { atomicOr(a.status, bits); }
+
+// Index of node (ix, iy, iz) of grid g in the grid planes: dense, or in the pool
+// (kSparse; the node's block was marked by this call).
+template <bool kSparse>
+__device__ __forceinline__ long long ad_index(const AdArgs &a, int g, int ix, int iy, int iz) {
+    if (!kSparse) return g * a.nodes + ((long long)iz * a.ny + iy) * a.nx + ix;
+    const long long b = ((long long)(iz >> 2) * a.nby + (iy >> 2)) * a.nbx + (ix >> 2);
+    const int slot = a.page[g * a.nbv + b];
+    return g * a.nodes + (long long)slot * 64 + (((iz & 3) * 4 + (iy & 3)) * 4 + (ix & 3));
+}
+
+// Node coordinates of local node l of pool slot `slot` of grid g (block-sparse).
+__device__ __forceinline__ void ad_coords(const AdArgs &a, int g, int slot, int l, int &ix, int &iy, int &iz) {
+    const int b = a.blist[(long long)g * a.cap + slot];
+    const int bxy = a.nbx * a.nby;
+    iz = 4 * (b / bxy) + (l >> 4);
+    iy = 4 * ((b % bxy) / a.nbx) + ((l >> 2) & 3);
+    ix = 4 * (b % a.nbx) + (l & 3);
+}
 
 // ------------------------------------------------------------ particle stencil
 struct AdStencil {
@@ -68,16 +113,22 @@ struct AdStencil {
     float Dinv[9];      // D^-1 in world units
 };
 
-// False (and nothing filled in) when the particle is outside the valid domain.
-// The position is x + r (FP32 rounding and remainder), summed in FP64.
-__device__ __forceinline__ bool ad_stencil(const AdArgs &a, const float x[3], const float r[3], AdStencil &st) {
-    constexpr float kInv2Pi = 0.15915494309189535f;
-    float X[3];
+// X = (x + r - origin) / dx (the position is x + r, FP32 rounding and remainder,
+// summed in FP64); false when the particle is outside the valid domain.
+__device__ __forceinline__ bool ad_position(const AdArgs &a, const float x[3], const float r[3], float X[3]) {
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
         X[ax] = (float)(((double)x[ax] + (double)r[ax] - a.geo.origin[ax]) * a.geo.inv_dx);
         if (!(X[ax] >= 0.25f && X[ax] < (float)a.geo.n[ax] - 0.25f)) return false;
     }
+    return true;
+}
+
+// False (and nothing filled in) when the particle is outside the valid domain.
+__device__ __forceinline__ bool ad_stencil(const AdArgs &a, const float x[3], const float r[3], AdStencil &st) {
+    constexpr float kInv2Pi = 0.15915494309189535f;
+    float X[3];
+    if (!ad_position(a, x, r, X)) return false;
 #pragma unroll
     for (int g = 0; g < 2; ++g) {
         const float k = g == 0 ? -0.25f : 0.25f;
@@ -130,10 +181,10 @@ __device__ __forceinline__ bool ad_stencil(const AdArgs &a, const float x[3], co
     return true;
 }
 
-// Node o (bits x, y, z) of grid g: dense index, weight, d = x_i - x_p (world) and
-// the gradient of the weight with respect to x_p (world).
-__device__ __forceinline__ long long ad_node(const AdArgs &a, const AdStencil &st, int g, int o, float &w, float d[3],
-                                             float gw[3]) {
+// Node o (bits x, y, z) of grid g: weight, d = x_i - x_p (world) and the gradient
+// of the weight with respect to x_p (world).
+__device__ __forceinline__ void ad_weights(const AdArgs &a, const AdStencil &st, int g, int o, float &w, float d[3],
+                                           float gw[3]) {
     const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
     const int off[3] = {ox, oy, oz};
     float wa[3], dwa[3];
@@ -147,8 +198,14 @@ __device__ __forceinline__ long long ad_node(const AdArgs &a, const AdStencil &s
     gw[0] = dwa[0] * wa[1] * wa[2];
     gw[1] = wa[0] * dwa[1] * wa[2];
     gw[2] = wa[0] * wa[1] * dwa[2];
-    const int ix = st.base[g][0] + ox, iy = st.base[g][1] + oy, iz = st.base[g][2] + oz;
-    return (long long)g * a.nodes + ((long long)iz * a.ny + iy) * a.nx + ix;
+}
+
+// The same and the node's pool index.
+template <bool kSparse>
+__device__ __forceinline__ long long ad_node(const AdArgs &a, const AdStencil &st, int g, int o, float &w, float d[3],
+                                             float gw[3]) {
+    ad_weights(a, st, g, o, w, d, gw);
+    return ad_index<kSparse>(a, g, st.base[g][0] + (o & 1), st.base[g][1] + ((o >> 1) & 1), st.base[g][2] + (o >> 2));
 }
 
 // Adds to xb the adjoint of D(x_p) for Db = dL/dD (world units):
@@ -384,7 +441,7 @@ __device__ void ad_tile_begin(bool valid, const AdStencil &st, float bnd, int nc
     __syncthreads();
 }
 
-// Adds v to channel ch of node (ix, iy, iz) of grid g (dense index id): into the tile,
+// Adds v to channel ch of node (ix, iy, iz) of grid g (pool index id): into the tile,
 // or straight into plane plane0 + ch of the grid when the tile is off.
 __device__ __forceinline__ void ad_tile_add(const AdArgs &a, const AdTile &t, int plane0, int ch, int g, int ix, int iy,
                                             int iz, long long id, float v) {
@@ -397,6 +454,7 @@ __device__ __forceinline__ void ad_tile_add(const AdArgs &a, const AdTile &t, in
 }
 
 // Called by every thread after its adds: every nonzero tile node to the grid.
+template <bool kSparse>
 __device__ void ad_tile_flush(const AdArgs &a, const AdTile &t, int plane0, int nch) {
     __syncthreads();
     if (!t.on) return;
@@ -405,16 +463,19 @@ __device__ void ad_tile_flush(const AdArgs &a, const AdTile &t, int plane0, int 
     for (int q = threadIdx.x; q < 2 * t.T; q += blockDim.x) {
         const int g = q >= t.T ? 1 : 0, r = q - g * t.T;
         const int ix = t.lo[0] + r % t.L[0], iy = t.lo[1] + (r / t.L[0]) % t.L[1], iz = t.lo[2] + r / LxLy;
-        const long long id = (long long)g * a.nodes + ((long long)iz * a.ny + iy) * a.nx + ix;
+        long long id = -1;   // looked up for a touched node only (its block is marked)
         for (int ch = 0; ch < nch; ++ch) {
             const long long v = (long long)t.w[(ch * 2 + g) * t.T + r];
-            if (v != 0) atomicAdd(&plane(a, plane0 + ch)[id], (float)((double)v * inv));
+            if (v == 0) continue;
+            if (id < 0) id = ad_index<kSparse>(a, g, ix, iy, iz);
+            atomicAdd(&plane(a, plane0 + ch)[id], (float)((double)v * inv));
         }
     }
 }
 
 // ------------------------------------------------------------ kernels
 // P2G through the workgroup's node tile (direct float atomics when it does not fit).
+template <bool kSparse>
 __global__ void __launch_bounds__(256) k_ad_p2g(AdArgs a, const float *state, const float *logE) {
     __shared__ unsigned long long tw[kAdTileWords];
     __shared__ int sh[8];
@@ -431,7 +492,7 @@ __global__ void __launch_bounds__(256) k_ad_p2g(AdArgs a, const float *state, co
         load_planes(state, a.stride, p, kPlaneR, 3, xr);
         valid = ad_stencil(a, x, xr, st);
         if (!valid) {
-            set_status(a.status, ST_DOMAIN);
+            ad_status(a, ST_DOMAIN);
         } else {
             const float E = expf(logE[p]);
             Polar P;
@@ -463,8 +524,9 @@ __global__ void __launch_bounds__(256) k_ad_p2g(AdArgs a, const float *state, co
         for (int g = 0; g < 2; ++g)
             for (int o = 0; o < 8; ++o) {
                 float w, d[3], gw[3];
-                const long long id = ad_node(a, st, g, o, w, d, gw);
+                ad_weights(a, st, g, o, w, d, gw);
                 const int ix = st.base[g][0] + (o & 1), iy = st.base[g][1] + ((o >> 1) & 1), iz = st.base[g][2] + (o >> 2);
+                const long long id = t.on ? 0 : ad_index<kSparse>(a, g, ix, iy, iz);   // the tile's flush looks it up
                 ad_tile_add(a, t, GM, 0, g, ix, iy, iz, id, w * a.mass);
 #pragma unroll
                 for (int ax = 0; ax < 3; ++ax)
@@ -472,26 +534,125 @@ __global__ void __launch_bounds__(256) k_ad_p2g(AdArgs a, const float *state, co
                                 w * (a.mass * v[ax] + Q[3 * ax] * d[0] + Q[3 * ax + 1] * d[1] + Q[3 * ax + 2] * d[2]));
             }
     }
-    ad_tile_flush(a, t, GM, 4);
+    ad_tile_flush<kSparse>(a, t, GM, 4);
 }
 
-__device__ __forceinline__ bool node_free(const AdArgs &a, long long id, int &g) {
-    g = id >= a.nodes ? 1 : 0;
-    const long long r = id - g * a.nodes;
-    const int ix = (int)(r % a.nx), iy = (int)((r / a.nx) % a.ny), iz = (int)(r / ((long long)a.nx * a.ny));
+// Marks the blocks of the nodes a valid particle's stencil reaches on both grids
+// (nodes base and base + 1 per axis, base = floor(X - k/4) as in ad_stencil).
+// Also zeroes the slot counters that k_ad_alloc then counts up.
+__global__ void __launch_bounds__(256) k_ad_mark(AdArgs a, const float *state) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p == 0) {
+        a.cnt[0] = 0u;
+        a.cnt[1] = 0u;
+    }
+    if (p >= a.n) return;
+    float x[3], xr[3], X[3];
+    load_planes(state, a.stride, p, 0, 3, x);
+    load_planes(state, a.stride, p, kPlaneR, 3, xr);
+    if (!ad_position(a, x, xr, X)) return;
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+        const float k = g == 0 ? -0.25f : 0.25f;
+        int lo[3], hi[3];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            const float Xk = X[ax] - k;
+            const int b = (int)floorf(Xk);
+            lo[ax] = b >> 2;
+            hi[ax] = (b + 1) >> 2;
+        }
+        for (int bz = lo[2]; bz <= hi[2]; ++bz)
+            for (int by = lo[1]; by <= hi[1]; ++by)
+                for (int bx = lo[0]; bx <= hi[0]; ++bx)
+                    a.flag[g * a.nbv + ((long long)bz * a.nby + by) * a.nbx + bx] = 1;
+    }
+}
+
+// One thread per block of grid blockIdx.y: a marked block takes the grid's next pool
+// slot (one counter update per wave) and is recorded in blist; its flag is cleared.
+// Every block's page entry is rewritten (-1 for an untouched one).
+__global__ void __launch_bounds__(256) k_ad_alloc(AdArgs a) {
+    const int g = blockIdx.y;
+    const long long b = blockIdx.x * 256LL + threadIdx.x;
+    const bool in = b < a.nbv;
+    const bool f = in && a.flag[g * a.nbv + b] != 0;
+    const unsigned long long m = __ballot(f);
+    if (m == 0ull) {
+        if (in) a.page[g * a.nbv + b] = -1;
+        return;
+    }
+    const int lane = threadIdx.x & 63, leader = __builtin_ctzll(m);
+    unsigned int base = 0u;
+    if (lane == leader) base = atomicAdd(&a.cnt[g], (unsigned int)__popcll(m));
+    base = __shfl(base, leader);
+    if (!in) return;
+    int slot = -1;
+    if (f) {
+        const unsigned int s = base + (unsigned int)__popcll(m & ((1ull << lane) - 1ull));
+        if (s < (unsigned int)a.cap) {
+            slot = (int)s;
+            a.blist[(long long)g * a.cap + s] = (int)b;
+        } else {
+            slot = a.cap;
+            ad_status(a, ST_CAPACITY);
+        }
+        a.flag[g * a.nbv + b] = 0;
+    }
+    a.page[g * a.nbv + b] = slot;
+}
+
+// Nodes the sweeps visit, both grids: [0, n0) on G-, then G+ (every node when
+// dense, else the nodes of the slots taken in this call).
+template <bool kSparse>
+__device__ __forceinline__ long long taken_nodes(const AdArgs &a, long long &n0) {
+    if (!kSparse) {
+        n0 = a.nodes;
+        return 2 * a.nodes;
+    }
+    const unsigned int cap = (unsigned int)a.cap;
+    const unsigned int c0 = min(a.cnt[0], cap), c1 = min(a.cnt[1], cap);
+    n0 = 64ll * c0;
+    return 64ll * (c0 + c1);
+}
+
+// Coordinates of node r of grid g in the order of taken_nodes (r < 2^32 when dense:
+// at most 2^26 blocks of 64 nodes).
+template <bool kSparse>
+__device__ __forceinline__ void taken_coords(const AdArgs &a, int g, long long r, int &ix, int &iy, int &iz) {
+    if (kSparse) {
+        ad_coords(a, g, (int)(r >> 6), (int)(r & 63), ix, iy, iz);
+    } else {
+        const unsigned int q = (unsigned int)r, nx = (unsigned int)a.nx, ny = (unsigned int)a.ny;
+        ix = (int)(q % nx);
+        iy = (int)((q / nx) % ny);
+        iz = (int)(q / (nx * ny));
+    }
+}
+
+__device__ __forceinline__ bool node_free(const AdArgs &a, int g, int ix, int iy, int iz) {
     return ix >= a.geo.stick_lo[g] && iy >= a.geo.stick_lo[g] && iz >= a.geo.stick_lo[g] &&
            ix <= a.geo.stick_hi[g][0] && iy <= a.geo.stick_hi[g][1] && iz <= a.geo.stick_hi[g][2];
 }
 
-// Grid update on the dense grids.  With zero_mp (a forward call: m and p have no
+// Grid update on the taken blocks.  With zero_mp (a forward call: m and p have no
 // later reader) m and p are zeroed after the read, ready for the next P2G.
+template <bool kSparse>
 __global__ void k_ad_grid(AdArgs a, int zero_mp) {
     float *gm = plane(a, GM);
-    for (long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x; id < 2 * a.nodes;
-         id += (long long)gridDim.x * blockDim.x) {
-        int g;
+    long long n0;
+    const long long total = taken_nodes<kSparse>(a, n0);
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int g = i >= n0 ? 1 : 0;
+        const long long r = g ? i - n0 : i, id = g * a.nodes + r;
         const float m = gm[id];
-        const bool live = m > 0.0f && node_free(a, id, g);
+        bool live = false;
+        if (m > 0.0f) {
+            int ix, iy, iz;
+            taken_coords<kSparse>(a, g, r, ix, iy, iz);
+            live = node_free(a, g, ix, iy, iz);
+        }
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
             float *pp = plane(a, GP + ax) + id;
@@ -502,6 +663,7 @@ __global__ void k_ad_grid(AdArgs a, int zero_mp) {
     }
 }
 
+template <bool kSparse>
 __global__ void __launch_bounds__(256) k_ad_g2p(AdArgs a, const float *state, float *out) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= a.n) return;
@@ -511,7 +673,7 @@ __global__ void __launch_bounds__(256) k_ad_g2p(AdArgs a, const float *state, fl
     load_planes(state, a.stride, p, 15, 9, H);
     AdStencil st;
     if (!ad_stencil(a, x, xr, st)) {
-        set_status(a.status, ST_DOMAIN);
+        ad_status(a, ST_DOMAIN);
         for (int i = 0; i < MPM_STATE_PLANES; ++i) out[i * a.stride + p] = state[i * a.stride + p];
         return;
     }
@@ -521,7 +683,7 @@ __global__ void __launch_bounds__(256) k_ad_g2p(AdArgs a, const float *state, fl
     for (int g = 0; g < 2; ++g)
         for (int o = 0; o < 8; ++o) {
             float w, d[3], gw[3];
-            const long long id = ad_node(a, st, g, o, w, d, gw);
+            const long long id = ad_node<kSparse>(a, st, g, o, w, d, gw);
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax) {
                 const float vi = plane(a, GV + ax)[id];
@@ -559,10 +721,11 @@ __global__ void __launch_bounds__(256) k_ad_g2p(AdArgs a, const float *state, fl
         out[(15 + i) * a.stride + p] = Hn[i];
         probe += Bn[i] * 0.0f + Hn[i] * 0.0f;
     }
-    if (!(probe == 0.0f)) set_status(a.status, ST_NONFINITE);
+    if (!(probe == 0.0f)) ad_status(a, ST_NONFINITE);
 }
 
 // G2P reversed: scatters dL/dv~ to the grid, writes the G2P part of dL/dx and dL/dF.
+template <bool kSparse>
 __global__ void __launch_bounds__(256) k_ad_g2p_vjp(AdArgs a, const float *state, const float *cot_out,
                                                     float *cot_in) {
     __shared__ unsigned long long tw[kAdTileWords];
@@ -584,7 +747,7 @@ __global__ void __launch_bounds__(256) k_ad_g2p_vjp(AdArgs a, const float *state
         if (!valid) {
             // the forward step left this particle unchanged; the position cotangent
             // is that of the x planes, written to the r planes as well
-            set_status(a.status, ST_DOMAIN);
+            ad_status(a, ST_DOMAIN);
             for (int i = 0; i < MPM_STATE_PLANES; ++i) cot_in[i * a.stride + p] = cot_out[i * a.stride + p];
             for (int i = 0; i < 3; ++i) cot_in[(kPlaneR + i) * a.stride + p] = xbo[i];
         }
@@ -593,7 +756,7 @@ __global__ void __launch_bounds__(256) k_ad_g2p_vjp(AdArgs a, const float *state
     if (!valid) {
         AdTile t;
         ad_tile_begin(false, st, 0.0f, 3, tw, sh, t);
-        ad_tile_flush(a, t, GVB, 3);
+        ad_tile_flush<kSparse>(a, t, GVB, 3);
         return;
     }
     // forward quantities: B' and C = B' D^-1
@@ -603,7 +766,7 @@ __global__ void __launch_bounds__(256) k_ad_g2p_vjp(AdArgs a, const float *state
     for (int g = 0; g < 2; ++g)
         for (int o = 0; o < 8; ++o) {
             float w, d[3], gw[3];
-            const long long id = ad_node(a, st, g, o, w, d, gw);
+            const long long id = ad_node<kSparse>(a, st, g, o, w, d, gw);
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax) {
                 const float vi = plane(a, GV + ax)[id];
@@ -663,7 +826,7 @@ __global__ void __launch_bounds__(256) k_ad_g2p_vjp(AdArgs a, const float *state
     for (int g = 0; g < 2; ++g)
         for (int o = 0; o < 8; ++o) {
             float w, d[3], gw[3];
-            const long long id = ad_node(a, st, g, o, w, d, gw);
+            const long long id = ad_node<kSparse>(a, st, g, o, w, d, gw);
             const int ix = st.base[g][0] + (o & 1), iy = st.base[g][1] + ((o >> 1) & 1), iz = st.base[g][2] + (o >> 2);
             float vi[3], gv[3];
 #pragma unroll
@@ -690,19 +853,28 @@ __global__ void __launch_bounds__(256) k_ad_g2p_vjp(AdArgs a, const float *state
     for (int ax = 0; ax < 3; ++ax) cot_in[ax * a.stride + p] = xb[ax];
 #pragma unroll
     for (int i = 0; i < 9; ++i) cot_in[(15 + i) * a.stride + p] = Fb[i];
-    ad_tile_flush(a, t, GVB, 3);
+    ad_tile_flush<kSparse>(a, t, GVB, 3);
 }
 
 // Grid update reversed: pb = v~b / m,  mb = -(v~b . p) / m^2 on live nodes.
 // As the last reader of m, p and v~b in a backward call, it also zeroes them for the
 // next call's scatters.
+template <bool kSparse>
 __global__ void k_ad_grid_vjp(AdArgs a) {
     float *gm = plane(a, GM);
-    for (long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x; id < 2 * a.nodes;
-         id += (long long)gridDim.x * blockDim.x) {
-        int g;
+    long long n0;
+    const long long total = taken_nodes<kSparse>(a, n0);
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int g = i >= n0 ? 1 : 0;
+        const long long r = g ? i - n0 : i, id = g * a.nodes + r;
         const float m = gm[id];
-        const bool live = m > 0.0f && node_free(a, id, g);
+        bool live = false;
+        if (m > 0.0f) {
+            int ix, iy, iz;
+            taken_coords<kSparse>(a, g, r, ix, iy, iz);
+            live = node_free(a, g, ix, iy, iz);
+        }
         float dot = 0.0f;
         const float im = live ? 1.0f / m : 0.0f;
 #pragma unroll
@@ -721,6 +893,7 @@ __global__ void k_ad_grid_vjp(AdArgs a) {
 }
 
 // P2G reversed (a gather): completes dL/dx and dL/dF, writes dL/dv, dL/dB, adds dL/dlogE.
+template <bool kSparse>
 __global__ void __launch_bounds__(256) k_ad_p2g_vjp(AdArgs a, const float *state, const float *logE, float *cot_in,
                                                     float *logE_cot) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -756,7 +929,7 @@ __global__ void __launch_bounds__(256) k_ad_p2g_vjp(AdArgs a, const float *state
     for (int g = 0; g < 2; ++g)
         for (int o = 0; o < 8; ++o) {
             float w, d[3], gw[3];
-            const long long id = ad_node(a, st, g, o, w, d, gw);
+            const long long id = ad_node<kSparse>(a, st, g, o, w, d, gw);
             float pb[3];
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax) pb[ax] = plane(a, GPB + ax)[id];
@@ -819,11 +992,19 @@ AdArgs make_args(const mpm_ad_ctx *c, int64_t n, int64_t stride, double dt) {
     a.vol0 = c->vol0;
     a.nu_mu = (float)(1.0 / (2.0 * (1.0 + c->nu)));
     a.nu_lambda = (float)(c->nu / ((1.0 + c->nu) * (1.0 - 2.0 * c->nu)));
+    a.nbx = c->nb[0];
+    a.nby = c->nb[1];
+    a.cap = c->cap;
+    a.nbv = c->nbv;
+    a.nodes = c->nodes;
     a.nx = c->geo.n[0] + 1;
     a.ny = c->geo.n[1] + 1;
-    a.nz = c->geo.n[2] + 1;
-    a.nodes = c->nodes;
     a.grid = c->grid;
+    a.page = c->page;
+    a.blist = c->blist;
+    a.direct = c->direct ? 1 : 0;
+    a.flag = c->flag;
+    a.cnt = c->cnt;
     a.status = c->status;
     a.n = (int)n;
     a.stride = stride;
@@ -836,10 +1017,44 @@ int grid_blocks(long long work) {
     return (int)(b < 8192 ? (b > 0 ? b : 1) : 8192);
 }
 
-// P2G into the (zero) m and p planes and the grid update; zero_mp for a forward call.
+// Launch size of the sweeps (all nodes, or at most the pool's 2 * cap * 64).
+int sweep_blocks(const AdArgs &a) { return grid_blocks(a.direct ? 2 * a.nodes : 2ll * a.cap * 64); }
+
+// Blocks marked and given slots (unless direct), P2G into the (zero) m and p planes,
+// the grid update;
+// zero_mp for a forward call.
 void enqueue_forward_grid(const AdArgs &a, const float *state, const float *logE, int zero_mp, hipStream_t s) {
-    if (a.n > 0) hipLaunchKernelGGL(k_ad_p2g, dim3((a.n + 255) / 256), dim3(256), 0, s, a, state, logE);
-    hipLaunchKernelGGL(k_ad_grid, dim3(grid_blocks(2 * a.nodes)), dim3(256), 0, s, a, zero_mp);
+    if (!a.direct) {
+        hipLaunchKernelGGL(k_ad_mark, dim3(a.n > 0 ? (a.n + 255) / 256 : 1), dim3(256), 0, s, a, state);
+        hipLaunchKernelGGL(k_ad_alloc, dim3((unsigned int)((a.nbv + 255) / 256), 2), dim3(256), 0, s, a);
+    }
+    const dim3 pg((a.n + 255) / 256), sg(sweep_blocks(a)), wg(256);
+    if (a.direct) {
+        if (a.n > 0) hipLaunchKernelGGL(k_ad_p2g<false>, pg, wg, 0, s, a, state, logE);
+        hipLaunchKernelGGL(k_ad_grid<false>, sg, wg, 0, s, a, zero_mp);
+    } else {
+        if (a.n > 0) hipLaunchKernelGGL(k_ad_p2g<true>, pg, wg, 0, s, a, state, logE);
+        hipLaunchKernelGGL(k_ad_grid<true>, sg, wg, 0, s, a, zero_mp);
+    }
+}
+
+void free_buffers(mpm_ad_ctx *c) {
+    void *bufs[] = {c->grid, c->page, c->blist, c->flag, c->cnt, c->status};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+}
+
+void launch_backward_scatter(const AdArgs &a, const float *state, const float *cot_out, float *cot_in, hipStream_t s) {
+    const dim3 pg((a.n + 255) / 256), wg(256);
+    if (a.direct) hipLaunchKernelGGL(k_ad_g2p_vjp<false>, pg, wg, 0, s, a, state, cot_out, cot_in);
+    else hipLaunchKernelGGL(k_ad_g2p_vjp<true>, pg, wg, 0, s, a, state, cot_out, cot_in);
+}
+
+void launch_backward_gather(const AdArgs &a, const float *state, const float *logE, float *cot_in, float *logE_cot,
+                            hipStream_t s) {
+    const dim3 pg((a.n + 255) / 256), wg(256);
+    if (a.direct) hipLaunchKernelGGL(k_ad_p2g_vjp<false>, pg, wg, 0, s, a, state, logE, cot_in, logE_cot);
+    else hipLaunchKernelGGL(k_ad_p2g_vjp<true>, pg, wg, 0, s, a, state, logE, cot_in, logE_cot);
 }
 
 mpm_status check_call(const mpm_ad_ctx *c, int64_t n, int64_t stride, const float *state, double dt) {
@@ -869,22 +1084,30 @@ mpm_status mpm_ad_create(const mpm_config *cfg, const mpm_material *mat, mpm_ad_
     c->rho = mat->rho;
     c->vol0 = mat->vol0;
     c->max_particles = cfg->max_particles;
-    c->nodes = (long long)(cfg->n_cells[0] + 1) * (cfg->n_cells[1] + 1) * (cfg->n_cells[2] + 1);
+    c->nbv = 1;
+    for (int i = 0; i < 3; ++i) {
+        c->nb[i] = cfg->n_cells[i] / 4 + 1;
+        c->nbv *= c->nb[i];
+    }
+    c->cap = (int)std::min<long long>(cfg->max_blocks, c->nbv);
+    c->direct = c->cap == c->nbv;
+    c->nodes = c->direct ? (long long)(cfg->n_cells[0] + 1) * (cfg->n_cells[1] + 1) * (cfg->n_cells[2] + 1)
+                         : (long long)(c->cap + 1) * 64;
     const size_t bytes = (size_t)kGridPlanes * 2 * c->nodes * sizeof(float);
-    if (hipMalloc(&c->grid, bytes) != hipSuccess) {
-        delete c;
-        return MPM_E_OOM;
-    }
-    // the scatter targets (m, p, v~b) start at zero; every call leaves them at zero
-    if (hipMemset(c->grid, 0, bytes) != hipSuccess) {
-        (void)hipFree(c->grid);
-        delete c;
-        return MPM_E_HIP;
-    }
-    if (hipMalloc(&c->status, sizeof(unsigned int)) != hipSuccess ||
-        hipMemset(c->status, 0, sizeof(unsigned int)) != hipSuccess) {
-        (void)hipFree(c->grid);
-        if (c->status) (void)hipFree(c->status);
+    const size_t nbv2 = 2 * (size_t)c->nbv;
+    bool ok = hipMalloc(&c->grid, bytes) == hipSuccess && hipMalloc(&c->cnt, 2 * sizeof(unsigned int)) == hipSuccess &&
+              hipMalloc(&c->status, sizeof(unsigned int)) == hipSuccess;
+    if (!c->direct)   // page tables, slot list and marks of the block-sparse pool
+        ok = ok && hipMalloc(&c->page, nbv2 * sizeof(int)) == hipSuccess &&
+             hipMalloc(&c->blist, 2 * (size_t)c->cap * sizeof(int)) == hipSuccess &&
+             hipMalloc(&c->flag, nbv2) == hipSuccess && hipMemset(c->flag, 0, nbv2) == hipSuccess;
+    // the scatter targets (m, p, v~b) start at zero and every call leaves the nodes it
+    // swept at zero; no block is marked between calls
+    ok = ok && hipMemset(c->grid, 0, bytes) == hipSuccess &&
+         hipMemset(c->cnt, 0, 2 * sizeof(unsigned int)) == hipSuccess &&
+         hipMemset(c->status, 0, sizeof(unsigned int)) == hipSuccess;
+    if (!ok) {
+        free_buffers(c);
         delete c;
         return MPM_E_OOM;
     }
@@ -896,8 +1119,7 @@ mpm_status mpm_ad_destroy(mpm_ad_ctx *c) {
     if (!c) return MPM_E_INVALID;
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
-    (void)hipFree(c->grid);
-    (void)hipFree(c->status);
+    free_buffers(c);
     delete c;
     return MPM_OK;
 }
@@ -911,7 +1133,10 @@ mpm_status mpm_ad_forward(mpm_ad_ctx *c, int64_t n, int64_t stride, const float 
     hipStream_t s = (hipStream_t)stream;
     const AdArgs a = make_args(c, n, stride, dt);
     enqueue_forward_grid(a, state_in, logE, 1, s);
-    if (n > 0) hipLaunchKernelGGL(k_ad_g2p, dim3((n + 255) / 256), dim3(256), 0, s, a, state_in, state_out);
+    if (n > 0) {
+        if (a.direct) hipLaunchKernelGGL(k_ad_g2p<false>, dim3((n + 255) / 256), dim3(256), 0, s, a, state_in, state_out);
+        else hipLaunchKernelGGL(k_ad_g2p<true>, dim3((n + 255) / 256), dim3(256), 0, s, a, state_in, state_out);
+    }
     return hipGetLastError() == hipSuccess ? MPM_OK : MPM_E_HIP;
 }
 
@@ -925,10 +1150,11 @@ mpm_status mpm_ad_backward(mpm_ad_ctx *c, int64_t n, int64_t stride, const float
     const AdArgs a = make_args(c, n, stride, dt);
     enqueue_forward_grid(a, state_in, logE, 0, s);
     if (n > 0)
-        hipLaunchKernelGGL(k_ad_g2p_vjp, dim3((n + 255) / 256), dim3(256), 0, s, a, state_in, cot_out, cot_in);
-    hipLaunchKernelGGL(k_ad_grid_vjp, dim3(grid_blocks(2 * a.nodes)), dim3(256), 0, s, a);
+        launch_backward_scatter(a, state_in, cot_out, cot_in, s);
+    if (a.direct) hipLaunchKernelGGL(k_ad_grid_vjp<false>, dim3(sweep_blocks(a)), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_ad_grid_vjp<true>, dim3(sweep_blocks(a)), dim3(256), 0, s, a);
     if (n > 0)
-        hipLaunchKernelGGL(k_ad_p2g_vjp, dim3((n + 255) / 256), dim3(256), 0, s, a, state_in, logE, cot_in, logE_cot);
+        launch_backward_gather(a, state_in, logE, cot_in, logE_cot, s);
     return hipGetLastError() == hipSuccess ? MPM_OK : MPM_E_HIP;
 }
 

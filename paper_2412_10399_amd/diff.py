@@ -35,6 +35,19 @@ class AdContext:
             pass
 
 
+def ad_config(sc, direct_budget_mib: int = 256) -> ckmpm.mpm_config:
+    """mpm_config for the differentiable step on scene sc: a pool slot for every
+    4x4x4-node block of the lattice (no per-call marking) when that costs at most
+    `direct_budget_mib` MiB of device memory (7 KiB per block), else the block-sparse
+    pool sized as for the main step."""
+    nb = 1
+    for a in range(3):
+        nb *= sc.n_cells[a] // 4 + 1
+    if nb * 7168 <= direct_budget_mib * 2 ** 20:
+        return ckmpm.scene_config(sc, max_blocks=nb)
+    return ckmpm.scene_config(sc)
+
+
 def _step(ad: AdContext, state: torch.Tensor, logE: torch.Tensor, dt: float, stream) -> torch.Tensor:
     out = torch.empty_like(state)
     n = state.shape[1]

@@ -2,8 +2,9 @@
 oracle: one forward step, one reverse-mode step with random cotangents (also with
 the particles shuffled, which takes the scatters' direct path), rollout
 gradients of the differentiation workload (65,536 particles, 64 steps, checkpoints
-every 8 steps) against the oracle's adjoint, and 32 random directional derivatives
-against central differences of the oracle's forward rollout."""
+every 8 steps) against the oracle's adjoint, 32 random directional derivatives
+against central differences of the oracle's forward rollout, and the block-sparse
+grid pool (a 256^3 grid holding only the touched blocks, pool overflow)."""
 import numpy as np
 import pytest
 
@@ -14,9 +15,14 @@ from gpu_util import TOL, log, nerr
 pytestmark = pytest.mark.gpu
 
 
-def _ctx(sc):
+def _ctx(sc, mode=None):
+    """Context for scene sc: the pool of ckmpm.scene_config (mode None), a slot for
+    every block of the lattice ("direct") or one block fewer, which makes every call
+    mark its blocks and take slots ("sparse")."""
     from paper_2412_10399_amd import ckmpm, diff
-    return diff.AdContext(ckmpm.scene_config(sc), ckmpm.scene_materials(sc)[0])
+    nb = int(np.prod([c // 4 + 1 for c in sc.n_cells]))
+    mb = {None: None, "direct": nb, "sparse": nb - 1}[mode]
+    return diff.AdContext(ckmpm.scene_config(sc, max_blocks=mb), ckmpm.scene_materials(sc)[0])
 
 
 def _state(sc, x=None, v=None, B=None, F=None):
@@ -41,12 +47,13 @@ def _fc_scene(seed, near_wall=False):
     return sc
 
 
+@pytest.mark.parametrize("mode", ["direct", "sparse"])
 @pytest.mark.parametrize("near_wall", [False, True])
-def test_forward_step_matches_oracle(near_wall):
+def test_forward_step_matches_oracle(near_wall, mode):
     import torch
     from paper_2412_10399_amd import ckmpm
     sc = _fc_scene(31, near_wall)
-    ad = _ctx(sc)
+    ad = _ctx(sc, mode)
     s0 = _state(sc)
     logE = torch.from_numpy(sc.logE).cuda()
     out = torch.empty_like(s0)
@@ -59,18 +66,19 @@ def test_forward_step_matches_oracle(near_wall):
     assert status == 0
     for k in ("x", "v", "F"):
         e = nerr(got[k], getattr(st, k))
-        log("differentiable forward step (near wall %s): %s %.2e" % (near_wall, k, e))
+        log("differentiable forward step (near wall %s, %s pool): %s %.2e" % (near_wall, mode, k, e))
         assert e <= TOL, k
     assert nerr(got["B"], st.B) <= 10 * TOL
     ad.close()
 
 
+@pytest.mark.parametrize("mode", ["direct", "sparse"])
 @pytest.mark.parametrize("near_wall", [False, True])
-def test_backward_step_matches_oracle_adjoint(near_wall):
+def test_backward_step_matches_oracle_adjoint(near_wall, mode):
     import torch
     from paper_2412_10399_amd import ckmpm
     sc = _fc_scene(32, near_wall)
-    ad = _ctx(sc)
+    ad = _ctx(sc, mode)
     n = sc.n
     rng = np.random.default_rng(3)
     cot = [rng.standard_normal((n, 3)), rng.standard_normal((n, 3)), 64 * rng.standard_normal((n, 3, 3)),
@@ -95,7 +103,7 @@ def test_backward_step_matches_oracle_adjoint(near_wall):
                logE=lcot.cpu().numpy())
     for k in ("x", "v", "B", "F", "logE"):
         e = nerr(got[k], ref[k])
-        log("reverse step (near wall %s): d/d%s %.2e" % (near_wall, k, e))
+        log("reverse step (near wall %s, %s pool): d/d%s %.2e" % (near_wall, mode, k, e))
         assert e <= 1e-4, k
     ad.close()
 
@@ -155,6 +163,159 @@ def test_shuffled_particles_take_the_direct_scatter():
         log("shuffled reverse step: d/d%s %.2e" % (k, e))
         assert e <= 1e-4, k
     ad.close()
+
+
+def _one_step_both_ways(sc, ad, cot):
+    """Forward and reverse step of scene sc on context ad: (state after, cotangents)."""
+    import torch
+    from paper_2412_10399_amd import ckmpm
+    n = sc.n
+    s0 = _state(sc)
+    logE = torch.from_numpy(sc.logE).cuda()
+    stream = torch.cuda.current_stream()
+    out = torch.empty_like(s0)
+    ckmpm.check(ckmpm.mpm_ad_forward(ad.h, n, n, s0.data_ptr(), logE.data_ptr(), out.data_ptr(), sc.dt, stream))
+    ckmpm.check(ckmpm.mpm_ad_sync(ad.h, stream))
+    cot_out = torch.from_numpy(np.concatenate([cot[0].T, cot[1].T, cot[2].reshape(n, 9).T, cot[3].reshape(n, 9).T,
+                                               np.zeros((3, n))])
+                               .astype(np.float32)).cuda().contiguous()
+    cot_in = torch.empty_like(cot_out)
+    lcot = torch.zeros(n, dtype=torch.float32, device="cuda")
+    ckmpm.check(ckmpm.mpm_ad_backward(ad.h, n, n, s0.data_ptr(), logE.data_ptr(), cot_out.data_ptr(),
+                                      cot_in.data_ptr(), lcot.data_ptr(), sc.dt, stream))
+    ckmpm.check(ckmpm.mpm_ad_sync(ad.h, stream))
+    g = cot_in.cpu().numpy().astype(np.float64)
+    grads = dict(x=g[0:3].T, v=g[3:6].T, B=g[6:15].T.reshape(n, 3, 3), F=g[15:24].T.reshape(n, 3, 3),
+                 logE=lcot.cpu().numpy())
+    return _unpack(out), grads
+
+
+def test_large_grid_holds_only_the_touched_blocks():
+    """The same body on a 16^3 grid and, moved 120 cells in, on a 256^3 grid whose
+    dense grids would take about 1.9 GB: the context takes tens of MB, and forward
+    and reverse step agree with the small grid's (positions quantised to 2^-16
+    cells, so that both grids see the same cell coordinates exactly) and with the
+    oracle."""
+    import dataclasses
+    import torch
+    from paper_2412_10399_amd import ckmpm, diff
+    sc = _fc_scene(37)
+    q = 2.0 ** 16 / sc.dx
+    sc.x = (np.round(sc.x.astype(np.float64) * q) / q).astype(np.float32)
+    shift = 120 * sc.dx
+    big = dataclasses.replace(sc, n_cells=(256, 256, 256), origin=(-shift, -shift, -shift))
+    n = sc.n
+    rng = np.random.default_rng(38)
+    cot = [rng.standard_normal((n, 3)), rng.standard_normal((n, 3)), 64 * rng.standard_normal((n, 3, 3)),
+           rng.standard_normal((n, 3, 3))]
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    ad_big = diff.AdContext(ckmpm.scene_config(big), ckmpm.scene_materials(big)[0])
+    taken = free0 - torch.cuda.mem_get_info()[0]
+    log("256^3 differentiable context: %.1f MB of device memory (dense grids: %.0f MB)"
+        % (taken / 1e6, 14 * 2 * 257 ** 3 * 4 / 1e6))
+    assert taken < 64 * 2 ** 20
+    got_big, grad_big = _one_step_both_ways(big, ad_big, cot)
+    ad_big.close()
+    ad = _ctx(sc)
+    got, grad = _one_step_both_ways(sc, ad, cot)
+    ad.close()
+    for k in ("x", "v", "B", "F"):
+        e = nerr(got_big[k], got[k])
+        log("256^3 vs 16^3 forward step: %s %.2e" % (k, e))
+        assert e <= 1e-6, k
+    for k in ("x", "v", "B", "F", "logE"):
+        e = nerr(grad_big[k], grad[k])
+        log("256^3 vs 16^3 reverse step: d/d%s %.2e" % (k, e))
+        assert e <= 1e-6, k
+    st = oracle.State(sc.x, sc.v, sc.B, sc.F, sc.mat, sc.logE)
+    status, _, _ = oracle.step(oracle.scene_config(sc), oracle.scene_materials(sc), st, sc.dt)
+    assert status == 0
+    for k in ("x", "v", "F"):
+        assert nerr(got_big[k], getattr(st, k)) <= TOL, k
+    st = oracle.State(sc.x, sc.v, sc.B, sc.F, sc.mat, sc.logE)
+    status, ref = oracle.step_vjp(oracle.scene_config(sc), oracle.scene_materials(sc), st, sc.dt, *cot)
+    assert status == 0
+    for k in ("x", "v", "B", "F", "logE"):
+        assert nerr(grad_big[k], ref[k]) <= 1e-4, k
+
+
+def test_pool_overflow_is_reported_and_the_next_call_recovers():
+    """A one-block pool per grid: a body that needs more blocks makes the call
+    report MPM_E_CAPACITY; a single particle at a block's centre (one block on each
+    grid) then steps on the same context as on one with room to spare."""
+    import torch
+    from paper_2412_10399_amd import ckmpm, diff
+    sc = _fc_scene(39)
+    ad = diff.AdContext(ckmpm.scene_config(sc, max_blocks=1), ckmpm.scene_materials(sc)[0])
+    s0 = _state(sc)
+    logE = torch.from_numpy(sc.logE).cuda()
+    out = torch.empty_like(s0)
+    stream = torch.cuda.current_stream()
+    ckmpm.check(ckmpm.mpm_ad_forward(ad.h, sc.n, sc.n, s0.data_ptr(), logE.data_ptr(), out.data_ptr(), sc.dt,
+                                     stream))
+    assert ckmpm.mpm_ad_sync(ad.h, stream) == ckmpm.MPM_E_CAPACITY
+    one = _single_particle(sc, (4 * 2 + 2.0) * sc.dx)
+    rng = np.random.default_rng(40)
+    cot = [rng.standard_normal((1, 3)), rng.standard_normal((1, 3)), 64 * rng.standard_normal((1, 3, 3)),
+           rng.standard_normal((1, 3, 3))]
+    got, grad = _one_step_both_ways(one, ad, cot)
+    ad.close()
+    roomy = _ctx(one)
+    want, want_grad = _one_step_both_ways(one, roomy, cot)
+    roomy.close()
+    for k in ("x", "v", "B", "F"):
+        assert nerr(got[k], want[k]) <= 1e-6, k
+    for k in ("x", "v", "B", "F", "logE"):
+        assert nerr(grad[k], want_grad[k]) <= 1e-6, k
+    log("one-block pool: overflow reported, single-particle step after it matches")
+
+
+def test_particle_outside_the_domain_is_reported():
+    """A particle closer than a quarter cell to the lattice's low face: forward and
+    reverse call report MPM_E_DOMAIN, the forward call passes it through unchanged
+    and the other particles match a run without it."""
+    import dataclasses
+    import torch
+    from paper_2412_10399_amd import ckmpm
+    sc = _fc_scene(41)
+    sc.x[0] = np.float32(0.1 * sc.dx)
+    ad = _ctx(sc)
+    n = sc.n
+    s0 = _state(sc)
+    logE = torch.from_numpy(sc.logE).cuda()
+    out = torch.empty_like(s0)
+    stream = torch.cuda.current_stream()
+    ckmpm.check(ckmpm.mpm_ad_forward(ad.h, n, n, s0.data_ptr(), logE.data_ptr(), out.data_ptr(), sc.dt, stream))
+    assert ckmpm.mpm_ad_sync(ad.h, stream) == ckmpm.MPM_E_DOMAIN
+    assert torch.equal(out[:, 0], s0[:, 0])
+    cot_out = torch.ones_like(s0)
+    cot_in = torch.empty_like(s0)
+    lcot = torch.zeros(n, dtype=torch.float32, device="cuda")
+    ckmpm.check(ckmpm.mpm_ad_backward(ad.h, n, n, s0.data_ptr(), logE.data_ptr(), cot_out.data_ptr(),
+                                      cot_in.data_ptr(), lcot.data_ptr(), sc.dt, stream))
+    assert ckmpm.mpm_ad_sync(ad.h, stream) == ckmpm.MPM_E_DOMAIN
+    ckmpm.check(ckmpm.mpm_ad_sync(ad.h, stream))   # the status word was cleared
+    rest = dataclasses.replace(sc, x=sc.x[1:], v=sc.v[1:], B=sc.B[1:], F=sc.F[1:], mat=sc.mat[1:], logE=sc.logE[1:])
+    s1 = _state(rest)
+    out1 = torch.empty_like(s1)
+    ckmpm.check(ckmpm.mpm_ad_forward(ad.h, n - 1, n - 1, s1.data_ptr(), logE[1:].contiguous().data_ptr(),
+                                     out1.data_ptr(), sc.dt, stream))
+    ckmpm.check(ckmpm.mpm_ad_sync(ad.h, stream))
+    got, want = _unpack(out[:, 1:].contiguous()), _unpack(out1)
+    for k in ("x", "v", "B", "F"):
+        assert nerr(got[k], want[k]) <= 1e-6, k
+    ad.close()
+    log("particle outside the domain: MPM_E_DOMAIN from forward and reverse call")
+
+
+def _single_particle(sc, pos):
+    """Scene sc cut down to its first particle, moved to `pos` on every axis."""
+    import dataclasses
+    x = np.full((1, 3), pos, np.float32)
+    one = dataclasses.replace(sc, x=x, v=sc.v[:1].copy(), B=sc.B[:1].copy(), F=sc.F[:1].copy(), mat=sc.mat[:1].copy())
+    one.logE = sc.logE[:1].copy()
+    return one
 
 
 def _gpu_rollout_grad(sc, nsteps, loss_name, target, F=None):
