@@ -31,7 +31,9 @@
  * the x planes only and writes dL/d(position) to both the x and the r planes of
  * cot_in (the position depends on x and r alike).  All pointers are device
  * memory owned by the caller; calls are stream-ordered on `stream` (a hipStream_t,
- * NULL for the default stream) and return before the work completes.
+ * NULL for the default stream) and return before the work completes.  The calls
+ * of one context share its grids: they must not overlap (issue them on one stream,
+ * or order the streams).
  */
 #ifndef CKMPM_ADJOINT_H
 #define CKMPM_ADJOINT_H
