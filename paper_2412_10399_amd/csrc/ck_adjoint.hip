@@ -752,107 +752,105 @@ __global__ void __launch_bounds__(256) k_ad_g2p_vjp(AdArgs a, const float *state
             for (int i = 0; i < 3; ++i) cot_in[(kPlaneR + i) * a.stride + p] = xbo[i];
         }
     }
-    // every thread takes part in the tile's set-up and flush; invalid lanes add nothing
-    if (!valid) {
-        AdTile t;
-        ad_tile_begin(false, st, 0.0f, 3, tw, sh, t);
-        ad_tile_flush<kSparse>(a, t, GVB, 3);
-        return;
-    }
-    // forward quantities: B' and C = B' D^-1
-    float Bn[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) Bn[i] = 0.0f;
-    for (int g = 0; g < 2; ++g)
-        for (int o = 0; o < 8; ++o) {
-            float w, d[3], gw[3];
-            const long long id = ad_node<kSparse>(a, st, g, o, w, d, gw);
-#pragma unroll
-            for (int ax = 0; ax < 3; ++ax) {
-                const float vi = plane(a, GV + ax)[id];
-#pragma unroll
-                for (int b = 0; b < 3; ++b) Bn[3 * ax + b] += 0.5f * w * vi * d[b];
-            }
-        }
-    float C[9];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-            C[3 * i + j] = Bn[3 * i] * st.Dinv[j] + Bn[3 * i + 1] * st.Dinv[3 + j] + Bn[3 * i + 2] * st.Dinv[6 + j];
-    // x' = x + dt v'  ->  xb = xb',  v'b = vb' + dt xb'
-    float xb[3], vbt[3];
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        xb[ax] = xbo[ax];
-        vbt[ax] = vbo[ax] + a.dt * xbo[ax];
-    }
-    // F' = (I + dt C) F  ->  Cb = dt Fb' F^T,  Fb = (I + dt C)^T Fb'
-    float Cb[9], Fb[9];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            float cb = 0.0f, fb = Fbo[3 * i + j];
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                cb += Fbo[3 * i + k] * (H[3 * j + k] + (j == k ? 1.0f : 0.0f));
-                fb += a.dt * C[3 * k + i] * Fbo[3 * k + j];
-            }
-            Cb[3 * i + j] = a.dt * cb;
-            Fb[3 * i + j] = fb;
-        }
-    // C = B' D^-1  ->  B'b += Cb D^-T,  (D^-1)b = B'^T Cb
-    float Bbt[9], Dib[9];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            Bbt[3 * i + j] = Bbo[3 * i + j] + Cb[3 * i] * st.Dinv[3 * j] + Cb[3 * i + 1] * st.Dinv[3 * j + 1] +
-                             Cb[3 * i + 2] * st.Dinv[3 * j + 2];
-            Dib[3 * i + j] = Bn[i] * Cb[j] + Bn[3 + i] * Cb[3 + j] + Bn[6 + i] * Cb[6 + j];
-        }
-    // |1/2 w (v'b + B'b d)| <= 1/2 (|v'b| + dx sum |B'b|)
+    // Every thread reaches the tile's set-up and flush (they hold workgroup barriers)
+    // at the same two points, whatever its particle; invalid lanes add nothing.
+    float Bn[9], C[9], xb[3], vbt[3], Fb[9], Bbt[9], Dib[9];
     float bnd = 0.0f;
+    if (valid) {
+        // forward quantities: B' and C = B' D^-1
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax)
-        bnd = fmaxf(bnd, 0.5f * (fabsf(vbt[ax]) +
-                                 a.geo.dx * (fabsf(Bbt[3 * ax]) + fabsf(Bbt[3 * ax + 1]) + fabsf(Bbt[3 * ax + 2]))));
-    AdTile t;
-    ad_tile_begin(true, st, bnd, 3, tw, sh, t);
-    // v' = 1/2 sum w v~,  B' = 1/2 sum w v~ d^T:
-    //   v~b_i += 1/2 w (v'b + B'b d),  wb = 1/2 v~ . (v'b + B'b d),  db = 1/2 w B'b^T v~,
-    //   and d = x_i - x_p moves against x_p
-    for (int g = 0; g < 2; ++g)
-        for (int o = 0; o < 8; ++o) {
-            float w, d[3], gw[3];
-            const long long id = ad_node<kSparse>(a, st, g, o, w, d, gw);
-            const int ix = st.base[g][0] + (o & 1), iy = st.base[g][1] + ((o >> 1) & 1), iz = st.base[g][2] + (o >> 2);
-            float vi[3], gv[3];
+        for (int i = 0; i < 9; ++i) Bn[i] = 0.0f;
+        for (int g = 0; g < 2; ++g)
+            for (int o = 0; o < 8; ++o) {
+                float w, d[3], gw[3];
+                const long long id = ad_node<kSparse>(a, st, g, o, w, d, gw);
 #pragma unroll
-            for (int ax = 0; ax < 3; ++ax) {
-                vi[ax] = plane(a, GV + ax)[id];
-                gv[ax] = vbt[ax] + Bbt[3 * ax] * d[0] + Bbt[3 * ax + 1] * d[1] + Bbt[3 * ax + 2] * d[2];
-            }
-            float wb = 0.0f;
+                for (int ax = 0; ax < 3; ++ax) {
+                    const float vi = plane(a, GV + ax)[id];
 #pragma unroll
-            for (int ax = 0; ax < 3; ++ax) {
-                ad_tile_add(a, t, GVB, ax, g, ix, iy, iz, id, 0.5f * w * gv[ax]);
-                wb += 0.5f * vi[ax] * gv[ax];
+                    for (int b = 0; b < 3; ++b) Bn[3 * ax + b] += 0.5f * w * vi * d[b];
+                }
             }
 #pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                const float db = 0.5f * w * (Bbt[b] * vi[0] + Bbt[3 + b] * vi[1] + Bbt[6 + b] * vi[2]);
-                xb[b] += wb * gw[b] - db;
-            }
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j)
+                C[3 * i + j] =
+                    Bn[3 * i] * st.Dinv[j] + Bn[3 * i + 1] * st.Dinv[3 + j] + Bn[3 * i + 2] * st.Dinv[6 + j];
+        // x' = x + dt v'  ->  xb = xb',  v'b = vb' + dt xb'
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            xb[ax] = xbo[ax];
+            vbt[ax] = vbo[ax] + a.dt * xbo[ax];
         }
-    float Db[9];
-    ad_inverse_vjp(st.Dinv, Dib, Db);
-    ad_moment_vjp(a, st, Db, xb);
+        // F' = (I + dt C) F  ->  Cb = dt Fb' F^T,  Fb = (I + dt C)^T Fb'
+        float Cb[9];
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) cot_in[ax * a.stride + p] = xb[ax];
+        for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int i = 0; i < 9; ++i) cot_in[(15 + i) * a.stride + p] = Fb[i];
+            for (int j = 0; j < 3; ++j) {
+                float cb = 0.0f, fb = Fbo[3 * i + j];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    cb += Fbo[3 * i + k] * (H[3 * j + k] + (j == k ? 1.0f : 0.0f));
+                    fb += a.dt * C[3 * k + i] * Fbo[3 * k + j];
+                }
+                Cb[3 * i + j] = a.dt * cb;
+                Fb[3 * i + j] = fb;
+            }
+        // C = B' D^-1  ->  B'b += Cb D^-T,  (D^-1)b = B'^T Cb
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                Bbt[3 * i + j] = Bbo[3 * i + j] + Cb[3 * i] * st.Dinv[3 * j] + Cb[3 * i + 1] * st.Dinv[3 * j + 1] +
+                                 Cb[3 * i + 2] * st.Dinv[3 * j + 2];
+                Dib[3 * i + j] = Bn[i] * Cb[j] + Bn[3 + i] * Cb[3 + j] + Bn[6 + i] * Cb[6 + j];
+            }
+        // |1/2 w (v'b + B'b d)| <= 1/2 (|v'b| + dx sum |B'b|)
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax)
+            bnd = fmaxf(bnd, 0.5f * (fabsf(vbt[ax]) + a.geo.dx * (fabsf(Bbt[3 * ax]) + fabsf(Bbt[3 * ax + 1]) +
+                                                                  fabsf(Bbt[3 * ax + 2]))));
+    }
+    AdTile t;
+    ad_tile_begin(valid, st, bnd, 3, tw, sh, t);
+    if (valid) {
+        // v' = 1/2 sum w v~,  B' = 1/2 sum w v~ d^T:
+        //   v~b_i += 1/2 w (v'b + B'b d),  wb = 1/2 v~ . (v'b + B'b d),  db = 1/2 w B'b^T v~,
+        //   and d = x_i - x_p moves against x_p
+        for (int g = 0; g < 2; ++g)
+            for (int o = 0; o < 8; ++o) {
+                float w, d[3], gw[3];
+                const long long id = ad_node<kSparse>(a, st, g, o, w, d, gw);
+                const int ix = st.base[g][0] + (o & 1), iy = st.base[g][1] + ((o >> 1) & 1),
+                          iz = st.base[g][2] + (o >> 2);
+                float vi[3], gv[3];
+#pragma unroll
+                for (int ax = 0; ax < 3; ++ax) {
+                    vi[ax] = plane(a, GV + ax)[id];
+                    gv[ax] = vbt[ax] + Bbt[3 * ax] * d[0] + Bbt[3 * ax + 1] * d[1] + Bbt[3 * ax + 2] * d[2];
+                }
+                float wb = 0.0f;
+#pragma unroll
+                for (int ax = 0; ax < 3; ++ax) {
+                    ad_tile_add(a, t, GVB, ax, g, ix, iy, iz, id, 0.5f * w * gv[ax]);
+                    wb += 0.5f * vi[ax] * gv[ax];
+                }
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    const float db = 0.5f * w * (Bbt[b] * vi[0] + Bbt[3 + b] * vi[1] + Bbt[6 + b] * vi[2]);
+                    xb[b] += wb * gw[b] - db;
+                }
+            }
+        float Db[9];
+        ad_inverse_vjp(st.Dinv, Dib, Db);
+        ad_moment_vjp(a, st, Db, xb);
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) cot_in[ax * a.stride + p] = xb[ax];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) cot_in[(15 + i) * a.stride + p] = Fb[i];
+    }
     ad_tile_flush<kSparse>(a, t, GVB, 3);
 }
 
