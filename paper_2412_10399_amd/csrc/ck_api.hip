@@ -183,7 +183,7 @@ int64_t device_bytes_of(const mpm_config &c) {
            r(2 * nb * (long long)kMaxBlockParticles) + 2 * r(8 * stamp_stride(nbv)) + 2 * r(4 * nbv) + 2 * r(4 * nbv) +
            3 * r(4 * nb) + r(4 * (nb + 1)) + r(4 * nb) + 2 * r(4 * nb) + r(4 * nchunks) + r(4 * nchunks) +
            2 * r(4 * nb * (long long)kBlockFloats) + r(24 * np) + r(4 * (long long)C_COUNT) + r(4 * (long long)kBoundWords) +
-           (c.deterministic ? r(4 * nb * (long long)kStageFloats) : 0);
+           r(4 * 27 * nb) + (c.deterministic ? r(4 * nb * (long long)kStageFloats) : 0);
 }
 
 PartArgs part_args(const mpm_particles *p, bool with_out) {
@@ -339,6 +339,7 @@ mpm_status carve_buffers(DevCtx &d, const mpm_config &cfg, Take take) {
                     take_buffer(take, &d.pool[0], nb * kBlockFloats) && take_buffer(take, &d.pool[1], nb * kBlockFloats) &&
                     take_buffer(take, &d.tau, 6 * np) && take_buffer(take, &d.counters, (size_t)C_COUNT) &&
                     take_buffer(take, &d.bslots, (size_t)kBoundWords) &&
+                    take_buffer(take, &d.nbrs, 27 * nb) &&
                     (!d.det || take_buffer(take, &d.stage, nb * (size_t)kStageFloats));
     return ok ? MPM_OK : MPM_E_OOM;
 }

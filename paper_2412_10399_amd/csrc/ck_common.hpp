@@ -86,6 +86,8 @@ struct DevCtx {
     uint32_t *blo, *bhi;   // per particle block whose order is kept: smallest and largest position of
                            // its particles (the bucket is not filled for such a block)
     int *plist;            // particle blocks in increasing virtual id
+    int *nbrs;             // per particle block: pool blocks of its 3 x 3 x 3 neighbourhood in the
+                           // step's page table (-1: none), written by P2G and read by G2P
     int *pstart;           // first sorted position of each particle block (+1 sentinel)
     int *bcount;           // particles per particle block
     int *glist[2];         // per page table: virtual id of each physical pool block

@@ -24,9 +24,9 @@ __device__ __forceinline__ void block_coords(const Geometry &g, int vb, int &bx,
 }
 
 // Physical pool block of the 27 neighbours of block (bx,by,bz) in page table
-// `table`, -1 when inactive.
+// `table`, -1 when inactive; also copied to `keep` when given.
 __device__ __forceinline__ void load_neighbours(const DevCtx &d, int table, int bx, int by, int bz, int *nbr,
-                                                int first_thread = 0) {
+                                                int first_thread = 0, int *keep = nullptr) {
     const int t = (int)threadIdx.x - first_thread;
     if (t < 0) return;
     if (t < 27) {
@@ -35,6 +35,7 @@ __device__ __forceinline__ void load_neighbours(const DevCtx &d, int table, int 
         if (x >= 0 && y >= 0 && z >= 0 && x < d.geo.NB[0] && y < d.geo.NB[1] && z < d.geo.NB[2])
             ph = page_of(d, table)[vblock_id(d.geo, x, y, z)];
         nbr[t] = ph;
+        if (keep) keep[t] = ph;
     }
 }
 
@@ -831,6 +832,10 @@ __device__ __forceinline__ void b_p2g(const DevCtx &d, const PartArgs &pa, float
         const int vb = d.plist[r];
         int bx, by, bz;
         block_coords(d.geo, vb, bx, by, bz);
+        // the neighbourhood loads while the block is ordered (the ordering's barriers
+        // publish it; the previous block's last reader passed the barrier that ends
+        // its iteration), and is kept for this step's G2P, for every block G2P visits
+        load_neighbours(d, gt, bx, by, bz, nbr, 0, d.nbrs + 27 * (size_t)r);
         const int s = d.pstart[r];
         const int cnt = d.pstart[r + 1] - s;
         if (cnt > kMaxBlockParticles) continue;   // reported by the bucket scan
@@ -839,7 +844,6 @@ __device__ __forceinline__ void b_p2g(const DevCtx &d, const PartArgs &pa, float
         } else {
             order_block<true>(d, r, s, cnt, bcnt, bstart, wsum, lbuf, ord, lay, lmask);
         }
-        load_neighbours(d, gt, bx, by, bz, nbr);
         lds_barrier();
 
         if (!kFixed) {
@@ -1409,8 +1413,10 @@ __device__ __forceinline__ void g2p_pass(const DevCtx &d, const PartArgs &pa, fl
 // (Q in the B planes, the packed remainder); kCarried: so is the input.  The particle
 // loop runs two passes per trip, each reading the inputs the other loaded: the two
 // sets of registers then take turns, where one set copied into the other at the end
-// of every pass would wait for every store of the pass.
-template <bool kCarry = false, bool kCarried = false>
+// of every pass would wait for every store of the pass.  kKept: the step's P2G was
+// b_p2g, which kept every block's neighbourhood (one load, not a page lookup that
+// waits for the block's id).
+template <bool kCarry = false, bool kCarried = false, bool kKept = false>
 __device__ __forceinline__ void b_g2p(const DevCtx &d, const PartArgs &pa, float dt, int gp, int gt) {
     __shared__ float vt[3 * kTileNodes];
     __shared__ int nbr[27];
@@ -1432,7 +1438,11 @@ __device__ __forceinline__ void b_g2p(const DevCtx &d, const PartArgs &pa, float
         G2PIn qa, qb;
         g2p_load_index(pa, ld_at(d.perm, min((uint32_t)(s + tid), last)), qa, kCarried);
         uint32_t pnext = ld_at(d.perm, min((uint32_t)(s + tid + kG2PThreads), last));
-        load_neighbours(d, gt, bx, by, bz, nbr);
+        if (kKept) {
+            if (tid < 27) nbr[tid] = d.nbrs[27 * (size_t)r + tid];
+        } else {
+            load_neighbours(d, gt, bx, by, bz, nbr);
+        }
         lds_barrier();
         for (int ni = tid; ni < kTileNodes; ni += kG2PThreads) {
             int g, ix, iy, iz;
@@ -1452,14 +1462,16 @@ __device__ __forceinline__ void b_g2p(const DevCtx &d, const PartArgs &pa, float
 }
 
 __global__ void __launch_bounds__(kG2PThreads) k_g2p(DevCtx d, PartArgs pa, float dt, int gp, int gt) { b_g2p(d, pa, dt, gp, gt); }
+// The forms inside an mpm_step sequence, whose P2G (k_p2g or k_p2g_carried) kept every
+// block's neighbourhood.
 __global__ void __launch_bounds__(kG2PThreads) k_g2p_carry(DevCtx d, PartArgs pa, float dt, int gp, int gt) {
-    b_g2p<true>(d, pa, dt, gp, gt);
+    b_g2p<true, false, true>(d, pa, dt, gp, gt);
 }
 __global__ void __launch_bounds__(kG2PThreads) k_g2p_cc(DevCtx d, PartArgs pa, float dt, int gp, int gt) {
-    b_g2p<true, true>(d, pa, dt, gp, gt);
+    b_g2p<true, true, true>(d, pa, dt, gp, gt);
 }
 __global__ void __launch_bounds__(kG2PThreads) k_g2p_cf(DevCtx d, PartArgs pa, float dt, int gp, int gt) {
-    b_g2p<false, true>(d, pa, dt, gp, gt);
+    b_g2p<false, true, true>(d, pa, dt, gp, gt);
 }
 
 // one launch for many jobs: workgroup row y runs job y
