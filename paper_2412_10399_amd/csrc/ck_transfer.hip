@@ -1474,10 +1474,11 @@ __global__ void __launch_bounds__(kG2PThreads) k_g2p_cf(DevCtx d, PartArgs pa, f
     b_g2p<false, true, true>(d, pa, dt, gp, gt);
 }
 
-// one launch for many jobs: workgroup row y runs job y
+// one launch for many jobs: workgroup row y runs job y (every job's P2G of the round,
+// plain or deterministic, was b_p2g, which kept the neighbourhoods)
 __global__ void __launch_bounds__(kG2PThreads) k_g2p_multi(const JobStep *__restrict__ jobs) {
     const JobStep &J = jobs[blockIdx.y];
-    b_g2p(J.d, J.pa, J.dt, J.table, J.table);
+    b_g2p<false, false, true>(J.d, J.pa, J.dt, J.table, J.table);
 }
 
 // ---------------------------------------------------------------- exact-gradient transfers
