@@ -188,3 +188,27 @@ def test_noalloc_step_rejects_oversized_buffers_on_host(ck):
     assert L.mpm_step_noalloc(ctypes.byref(cfg), ctypes.byref(mat), 1, ctypes.byref(p), 1e-3, 1, None,
                               None) == ck.MPM_E_INVALID
     assert L.mpm_step_noalloc(None, None, 1, None, 1e-3, 1, None, None) == ck.MPM_E_INVALID
+
+
+def test_footprint_per_grid_block(ck):
+    # Per block of max_blocks: the bucket (2048 ids, 4 B) and its sub-cell codes (2 B),
+    # the particle-block list, kept-order range (2), start and count, the two
+    # grid-block lists, the two grids (512 floats each) and the kept neighbourhood
+    # (27 pool-block indices).  With max_blocks a multiple of 64 every such buffer is
+    # a whole number of 256-byte units, so the padding cancels in the difference.
+    per_block = 2048 * 4 + 2048 * 2 + 4 + 2 * 4 + 4 + 4 + 2 * 4 + 2 * 512 * 4 + 27 * 4
+    a = ck.make_config((32, 32, 32), 1 / 32, max_particles=1000, max_blocks=64)
+    b = ck.make_config((32, 32, 32), 1 / 32, max_particles=1000, max_blocks=128)
+    assert ck.mpm_footprint(b, 1000) - ck.mpm_footprint(a, 1000) == 64 * per_block
+
+
+def test_adjoint_config_is_dense_while_affordable(ck):
+    """diff.ad_config gives every lattice block a slot (dense grids, no marking) up to
+    the memory budget, and the main step's pool size beyond it."""
+    import scenes
+    from paper_2412_10399_amd import diff
+    sc = scenes.diff_box()
+    nb = 17 ** 3
+    assert diff.ad_config(sc).max_blocks == nb
+    assert ck.scene_config(sc).max_blocks < nb          # the main step's pool would not cover it
+    assert diff.ad_config(sc, direct_budget_mib=1).max_blocks == ck.scene_config(sc).max_blocks
