@@ -1,5 +1,5 @@
-// Differentiable compact-kernel MPM step: forward step on block-sparse grids and
-// its exact reverse mode (vector-Jacobian product), one thread per particle or node.
+// Differentiable compact-kernel MPM step: forward step on dense or block-sparse grids
+// and its exact reverse mode (vector-Jacobian product), one thread per particle or node.
 //
 // Forward, for particle p at X = (x - origin)/dx (cell units), on grid G_k
 // (k = -1 for G-, +1 for G+, node i at i + k/4 cells), per axis a:
