@@ -378,7 +378,7 @@ __device__ __forceinline__ void load_planes(const float *base, long long stride,
 // ------------------------------------------------------------ workgroup node tiles
 // The two scattering kernels accumulate into a 64-bit fixed-point LDS tile over the
 // node box of their workgroup's 256 particles (both grids), then add every nonzero
-// node to the dense grid with one float atomic per channel.  Particles keep their
+// node to the grid with one float atomic per channel.  Particles keep their
 // creation order, cell by cell, so consecutive particles sit in neighbouring cells
 // and the box is small (a row of about 34 x 3 x 3 nodes for the box workload); a
 // workgroup whose box does not fit adds its contributions to the grid directly.
