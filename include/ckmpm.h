@@ -92,8 +92,8 @@ typedef struct {
     int32_t bc_band;       /* sticky: zero v~ at nodes closer than bc_band cells to a box face      */
     int64_t max_particles; /* capacity of every per-particle scratch array                          */
     int64_t max_blocks;    /* capacity of the grid block pool (blocks of 4x4x4 nodes, both grids);
-                              device memory is about 10 KiB per block (2 KiB of grid, 8 KiB of
-                              sort buckets of up to 2048 particles per block)                      */
+                              device memory is about 16 KiB per block (two 2 KiB grids, 12 KiB
+                              of sort buckets of up to 2048 particles and their sub-cell codes) */
     int32_t transfer;      /* MPM_TRANSFER_MLS, _APIC or _PIC                                       */
     int32_t flags;         /* 0, MPM_FLAG_FUSED_G2P2G or MPM_FLAG_QUADRATIC                          */
     int32_t deterministic; /* 0 or 1: bitwise reproducible steps (see below)                        */
